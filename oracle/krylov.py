@@ -1,0 +1,155 @@
+"""Plain and recycled conjugate gradients for H w = g, with the two stop tests.
+
+Recycled CG.  The paper's solver is RMINRES (Section 2.2.2, Algorithm 3): the
+correction is V_k y + U z with the Lanczos vectors kept orthogonal to C = HU,
+C^T C = I, and the coupled least-squares problem (eq. coupled) splitting into
+eq. y_solve and eq. zk_answer.  The paper defines no recycled CG; the reading
+used here is the Galerkin counterpart on the same augmented space: with
+P = I - C C^T,
+  1. r0 = g - H w0;  w0 += U C^T r0;  r0 -= C C^T r0     (as in Algorithm 3's set-up)
+  2. CG on P H restricted to range(P): every H p is projected, q - C (C^T q),
+     which is the augmented Lanczos relation (eq. arnoldi_aug_matrix) in CG form;
+  3. the recycle-space coefficient accumulates z -= alpha C^T q and the solution is
+     finished with w += U z, the CG analogue of eq. zk_answer.
+With U empty it is textbook CG (Hestenes-Stiefel), by the same code path.
+
+Stop tests (Section 4):
+  * residual: ||r_j|| <= tol ||g|| (the paper's test is absolute; here relative);
+  * hypergradient-error estimate (eq. hg-err-stop-lowrank): with Z = W V_H and mu the
+    selected Ritz generalized singular values, ||mu . (Z^T r_j)|| <= hg_tol.
+The first test at j = 0 allows zero iterations.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+OK, NOT_CONVERGED, INDEFINITE = 0, 4, 5
+
+
+def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1e-10,
+                stop: str = "resid", hg_tol: float = 0.0, max_iter: int = 10000, v_cap: int = 64,
+                check_every: int = 1, recurrence: str = "textbook", record: bool = False):
+    """Solve H w = g.  ``hvp(v)`` applies H.  Returns a dict (see keys at the end)."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    n = g.size
+    w = np.zeros(n) if w0 is None else np.array(w0, dtype=np.float64).ravel().copy()
+    s = 0 if U is None else U.shape[1]
+    r = g - hvp(w)
+    if s:
+        c0 = C.T @ r
+        w = w + U @ c0
+        r = r - C @ c0
+    gnorm = float(np.linalg.norm(g))
+    p = r.copy()
+    rho = float(r @ r)
+    zacc = np.zeros(s)
+    V = []
+    hist_res, hist_nsc = [], []
+
+    def nsc(rv):
+        return float(np.linalg.norm(mu * (Z.T @ rv)))
+
+    def met(rv, rho_v, j):
+        res = np.sqrt(max(rho_v, 0.0))
+        est = nsc(rv) if (Z is not None and mu is not None and len(mu)) else np.nan
+        if record:
+            hist_res.append(res)
+            hist_nsc.append(est)
+        if rho_v == 0.0:
+            return True
+        if j % check_every:
+            return False
+        if stop == "hgerr":
+            return est <= hg_tol
+        return res <= tol * gnorm
+
+    status = OK
+    iters = 0
+    done = met(r, rho, 0)
+    while not done and iters < max_iter:
+        if iters == 0:
+            V.append(r / np.sqrt(rho))
+        q = hvp(p)
+        e = C.T @ q if s else np.zeros(0)
+        sigma = float(p @ q)
+        if sigma <= 0.0:
+            status = INDEFINITE
+            break
+        alpha = rho / sigma
+        if recurrence == "single":
+            rq, qq, ee = float(r @ q), float(q @ q), float(e @ e)
+        w += alpha * p
+        zacc -= alpha * e
+        r -= alpha * (q - C @ e) if s else alpha * q
+        if recurrence == "single":
+            rho_new = rho - 2.0 * alpha * rq + alpha * alpha * (qq - ee)
+        else:
+            rho_new = float(r @ r)
+        iters += 1
+        done = met(r, rho_new, iters)
+        if done:
+            rho = rho_new
+            break
+        beta = rho_new / rho
+        p = r + beta * p
+        rho = rho_new
+        if len(V) < v_cap:
+            V.append(r / np.sqrt(rho))
+    if not done and status == OK:
+        status = NOT_CONVERGED
+    if s:
+        w = w + U @ zacc
+    return {"w": w, "iters": iters, "status": status, "res_norm": float(np.sqrt(max(rho, 0.0))),
+            "g_norm": gnorm, "V": np.stack(V, axis=1) if V else np.zeros((n, 0)),
+            "hist_res": hist_res, "hist_nsc": hist_nsc, "r": r, "zacc": zacc}
+
+
+def cg(hvp, g, w0=None, tol: float = 1e-10, max_iter: int = 10000, v_cap: int = 64, record: bool = False):
+    """Plain CG: the recycled solver with an empty recycle space."""
+    return recycled_cg(hvp, g, w0, tol=tol, max_iter=max_iter, v_cap=v_cap, record=record)
+
+
+def reference_solve(hvp, g, tol: float = 1e-13, max_iter: int = 100000, replace_every: int = 50):
+    """High-accuracy reference (Section 5: no recycling, tolerance 1e-13).
+
+    Cold-start CG; every ``replace_every`` iterations the recursive residual is
+    replaced by the true residual g - H w, and the run stops at the tolerance or
+    when the true residual stops decreasing over a window.
+    """
+    g = np.asarray(g, dtype=np.float64).ravel()
+    w = np.zeros_like(g)
+    r = g.copy()
+    p = r.copy()
+    rho = float(r @ r)
+    gnorm = float(np.linalg.norm(g))
+    best = np.inf
+    stall = 0
+    it = 0
+    while it < max_iter:
+        if np.sqrt(rho) <= tol * gnorm:
+            break
+        q = hvp(p)
+        alpha = rho / float(p @ q)
+        w += alpha * p
+        r -= alpha * q
+        it += 1
+        if it % replace_every == 0:
+            r = g - hvp(w)
+            tr = float(np.linalg.norm(r))
+            if tr <= tol * gnorm:
+                break
+            if tr < 0.5 * best:
+                best, stall = tr, 0
+            else:
+                stall += 1
+                if stall >= 4:
+                    break
+        rho_new = float(r @ r)
+        p = r + (rho_new / rho) * p
+        rho = rho_new
+    return w, it
+
+
+def true_hg_error(J, Hinv_r):
+    """||J H^{-1} r|| (eq. hg-error-stop), for diagnostics with dense J and H^{-1} r."""
+    return float(np.linalg.norm(J @ Hinv_r))

@@ -1,0 +1,151 @@
+"""Pins of the oracle's projected GSVD, Ritz-GSV selection, refresh and error estimate."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov, problem, recycle
+
+
+def spd(n, cond, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (Q * np.geomspace(1.0, cond, n)) @ Q.T
+
+
+@pytest.mark.parametrize("p,t", [(30, 12), (12, 12), (3, 10)])
+def test_gsvd_identities(p, t):
+    """GSVD theorem: alpha^2 + beta^2 = 1, G X = V_J diag(alpha), M X = V_H diag(beta), mu ascending."""
+    rng = np.random.default_rng(p * 100 + t)
+    G = rng.standard_normal((p, t))
+    M = spd(t, 50.0, t)
+    gs = recycle.gsvd_ps(G, M)
+    a, b, X = gs["alpha"], gs["beta"], gs["X"]
+    assert np.abs(a * a + b * b - 1.0).max() < 1e-14 * 10
+    assert np.all(np.diff(gs["mu"]) >= -1e-14)
+    assert np.abs(M @ X - gs["V_H"] * b).max() < 1e-12 * np.abs(M).max() * np.abs(X).max()
+    nz = a > 1e-14
+    assert np.abs(G @ X[:, nz] - gs["V_J"][:, nz] * a[nz]).max() < 1e-12 * np.abs(G).max() * np.abs(X).max()
+    assert np.abs(gs["V_H"].T @ gs["V_H"] - np.eye(t)).max() < 1e-13
+    VJ = gs["V_J"][:, nz]
+    assert np.abs(VJ.T @ VJ - np.eye(VJ.shape[1])).max() < 1e-10   # columns divided by small alpha
+    if p < t:
+        assert int(np.sum(gs["mu"] > 1e-10)) == p
+
+
+@pytest.mark.parametrize("p,t", [(40, 15), (15, 15), (2, 12)])
+def test_gsvd_two_routes_agree(p, t):
+    rng = np.random.default_rng(7 + p + t)
+    G = rng.standard_normal((p, t))
+    M = spd(t, 30.0, p + t)
+    a = recycle.gsvd_ps(G, M)
+    b = recycle.gsvd_via_quotient(G, M)
+    k = min(p, t)
+    ma, mb = a["mu"][-k:], b["mu"][-k:]
+    assert np.abs(ma - mb).max() <= 1e-10 * ma.max()
+    for j in range(1, k + 1):   # right vectors agree up to scale/sign
+        xa, xb = a["X"][:, -j], b["X"][:, -j]
+        ang = recycle.principal_angles(xa[:, None], xb[:, None]).max()
+        assert ang < 1e-8
+
+
+def test_gsvd_special_case_identity_J():
+    """G = I: generalized singular values are the reciprocals of the eigenvalues of M."""
+    t = 9
+    M = spd(t, 20.0, 3)
+    gs = recycle.gsvd_ps(np.eye(t), M)
+    lam = np.linalg.eigvalsh(M)
+    assert np.abs(np.sort(gs["mu"]) - np.sort(1.0 / lam)).max() < 1e-12
+
+
+def test_gsvd_special_case_full_space_is_svd_of_J_Hinv():
+    """W = I (full space): mu are the singular values of J H^{-1}."""
+    n, p = 14, 20
+    H = spd(n, 40.0, 4)
+    J = np.random.default_rng(5).standard_normal((p, n))
+    gs = recycle.gsvd_ps(J, H)
+    sv = np.linalg.svd(J @ np.linalg.inv(H), compute_uv=False)
+    assert np.abs(np.sort(gs["mu"])[::-1] - sv).max() < 1e-11 * sv.max()
+
+
+@pytest.mark.parametrize("p", [20, 3])
+def test_error_estimate_exact_on_full_space(p):
+    """Full GSVD with square W: ||mu . (V_H^T r)|| equals ||J H^{-1} r|| for any r (Section 4)."""
+    n = 16
+    H = spd(n, 25.0, 6)
+    J = np.random.default_rng(7).standard_normal((p, n))
+    gs = recycle.gsvd_ps(J, H)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        r = rng.standard_normal(n)
+        est = np.linalg.norm(gs["mu"] * (gs["V_H"].T @ r))
+        true = np.linalg.norm(J @ np.linalg.solve(H, r))
+        assert abs(est - true) <= 1e-12 * true
+
+
+def test_orthonormalize_drops_dependent_columns():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((50, 6))
+    W = np.concatenate([A, A[:, :2] @ np.array([[1.0], [2.0]]), rng.standard_normal((50, 2))], axis=1)
+    Q, kept = recycle.orthonormalize(W)
+    assert kept == [0, 1, 2, 3, 4, 5, 7, 8]
+    assert np.abs(Q.T @ Q - np.eye(8)).max() < 1e-14
+    assert recycle.principal_angles(Q, W[:, kept]).max() < 1e-12
+
+
+def test_selection_fill_rule_for_low_rank_G():
+    t, s = 12, 5
+    M = spd(t, 40.0, 10)
+    G = np.random.default_rng(11).standard_normal((2, t))
+    sel = recycle.select_rgen_large(G, M, s)
+    assert sel["rank_G"] == 2
+    assert np.all(sel["mu"][:2] > 0) and np.all(sel["mu"][2:] == 0)
+    # filled right vectors lie in null(G) and are the Ritz-S vectors of M restricted to null(G)
+    Xf = sel["X"][:, 2:]
+    assert np.abs(G @ Xf).max() < 1e-12
+    _, _, Vt = np.linalg.svd(G)
+    N = Vt[2:].T
+    lam, Q = np.linalg.eigh(N.T @ M @ N)
+    assert recycle.principal_angles(Xf, N @ Q[:, :3]).max() < 1e-10
+
+
+def tv_setup(side=12, seed=21):
+    wl = synth.custom("t", side, "tv", 6, blur_radius=2, blur_sigma=1.5, rect_min=2, rect_max=4, seed=seed)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xh = inst["xstar"].ravel() + 0.05 * synth.unit_noise(prob.n, seed + 1)
+    return wl, inst, prob, xh
+
+
+def test_refresh_invariants_and_basis_independence():
+    wl, inst, prob, xh = tv_setup()
+    th = inst["theta0"]
+    hvp = lambda v: prob.hvp(xh, th, v)
+    jac = lambda v: prob.jac_apply(xh, th, v)
+    g = xh - inst["xstar"].ravel()
+    res = krylov.cg(hvp, g, tol=1e-10, v_cap=20)
+    rs = recycle.refresh(hvp, jac, None, res["V"], s=6)
+    U, C = rs["U"], rs["C"]
+    HU = np.stack([hvp(U[:, j]) for j in range(U.shape[1])], axis=1)
+    assert np.linalg.norm(HU - C) <= 1e-12 * np.linalg.norm(C)
+    assert np.abs(C.T @ C - np.eye(C.shape[1])).max() <= 1e-14
+    # re-basing W (a rotation of the stored vectors) leaves range(U) unchanged
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((res["V"].shape[1],) * 2))
+    rs2 = recycle.refresh(hvp, jac, None, res["V"] @ Q, s=6)
+    assert recycle.principal_angles(rs["U"], rs2["U"]).max() < 1e-8
+    assert np.abs(rs["mu"] - rs2["mu"]).max() <= 1e-10 * rs["mu"].max()
+
+
+def test_recycled_sequence_reaches_same_solution_as_plain():
+    wl, inst, prob, xh = tv_setup(10, 31)
+    xs = inst["xstar"].ravel()
+    thetas = [inst["theta0"] + 0.01 * k for k in range(4)]
+    xhats = [xh + 0.001 * k * synth.unit_noise(prob.n, 40 + k) for k in range(4)]
+    plain = __import__("oracle.upper", fromlist=["x"]).solve_sequence(prob, thetas, xhats, xs, s=5,
+                                                                       recycle_on=False, tol=1e-12)
+    rec = __import__("oracle.upper", fromlist=["x"]).solve_sequence(prob, thetas, xhats, xs, s=5, tol=1e-12)
+    for a, b, th, x in zip(plain, rec, thetas, xhats):
+        Hd = prob.dense_hessian(x, th)
+        w = np.linalg.solve(Hd, x - xs)
+        kappa = np.linalg.cond(Hd)
+        for r in (a, b):
+            assert np.linalg.norm(r["w"] - w) <= kappa * 1e-12 * 10 * np.linalg.norm(w)
