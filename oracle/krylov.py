@@ -67,7 +67,8 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
     iters = 0
     done = met(r, rho, 0)
     while not done and iters < max_iter:
-        if iters == 0:
+        # V: basis of the generated Krylov space, one normalised residual per iteration run
+        if len(V) < v_cap:
             V.append(r / np.sqrt(rho))
         q = hvp(p)
         e = C.T @ q if s else np.zeros(0)
@@ -93,8 +94,6 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
         beta = rho_new / rho
         p = r + beta * p
         rho = rho_new
-        if len(V) < v_cap:
-            V.append(r / np.sqrt(rho))
     if not done and status == OK:
         status = NOT_CONVERGED
     if s:
