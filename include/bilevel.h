@@ -1,0 +1,178 @@
+/*
+ * bilevel.h -- C ABI of libbilevel_hip.so: recycled-Krylov hypergradient solves on gfx950.
+ *
+ * Method: Ehrhardt, Gazzola, Scott, "Efficient gradient-based methods for bilevel
+ * learning via recycling Krylov subspaces" (arXiv 2412.08264).
+ *
+ * Every call has C linkage, never throws and returns a bl_status.  All device arrays
+ * are owned by the caller (allocated elsewhere, passed as raw device pointers); the
+ * library never allocates device memory.  Scratch space is one caller-owned device
+ * buffer of bl_workspace_bytes() bytes.  Hyperparameters theta and the hypergradient
+ * live in host memory (p <= 512 doubles).
+ *
+ * Layout.  An image is h x w, row-major, n = h*w float64 values.  Tall matrices
+ * (U, C, Z, V) are column-major with leading dimension n: column j starts at j*n.
+ *
+ * Streams.  A context is bound to one hipStream_t; all work is stream ordered.  Calls
+ * that return host results (stats, gradients, status) synchronise that stream.
+ *
+ * Errors.  Argument and shape checks run on the host before any launch and return
+ * BL_E_ARG / BL_E_SHAPE / BL_E_WORKSPACE.  Numerical outcomes are reported after the
+ * work: BL_E_INDEFINITE when CG meets p^T H p <= 0, BL_E_NOT_CONVERGED at max_iter
+ * (the iterate is still written), BL_E_NONFINITE on NaN/Inf.  HIP failures map to
+ * BL_E_HIP (bl_last_error() gives the HIP message).
+ */
+#ifndef BILEVEL_H
+#define BILEVEL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BL_OK = 0,
+    BL_E_ARG = 1,            /* invalid argument (null pointer, bad enum, bad size)          */
+    BL_E_SHAPE = 2,          /* inconsistent sizes (e.g. s > s_max, image too small)         */
+    BL_E_WORKSPACE = 3,      /* workspace missing or smaller than bl_workspace_bytes()       */
+    BL_E_NOT_CONVERGED = 4,  /* iteration limit reached                                      */
+    BL_E_INDEFINITE = 5,     /* CG found p^T H p <= 0, or the projected matrix is not SPD    */
+    BL_E_BREAKDOWN = 6,      /* a factorisation met a zero pivot                             */
+    BL_E_RANK = 7,           /* refresh dropped dependent columns (non-fatal, s_cur reduced) */
+    BL_E_NONFINITE = 8,      /* NaN or Inf met                                               */
+    BL_E_HIP = 9             /* HIP runtime error                                            */
+} bl_status;
+
+typedef enum { BL_REG_TV = 0, BL_REG_FILTERS = 1 } bl_reg;
+typedef enum { BL_PEN_LOG = 0, BL_PEN_QUAD = 1 } bl_penalty;     /* log(1+s^2) or s^2        */
+typedef enum { BL_PREC_FP64 = 0, BL_PREC_MIXED = 1 } bl_prec;    /* mixed: FP32 HVP stencils  */
+typedef enum { BL_STOP_RESID = 0, BL_STOP_HGERR = 1 } bl_stop;
+
+/* Lower-level problem (Section 2.1 eq. bl2; Section 5 eq. ll2ex):
+ *   TV:      Phi = ||A x - y||^2 + e^{t0} sum_i sqrt(|(D x)_i|^2 + e^{2 t1}),      p = 2
+ *   filters: Phi = ||A x - y||^2 + eps/2 ||x||^2 + sum_j e^{w_j} sum_i phi((K_j x)_i),
+ *            theta = [w_1, k_1 (f*f, row-major), ..., w_N, k_N],                   p = N(1+f^2)
+ * A: same-size correlation with the normalised (2r+1)^2 Gaussian (zero outside the image);
+ * D: forward differences, zero on the last column/row; K_j: same-size zero-padded
+ * correlation with filter k_j.  Upper loss 1/2 ||x - x*||^2. */
+typedef struct {
+    int h, w;                /* image size, h, w >= 2                                         */
+    int blur_radius;         /* r in [0, 8]                                                   */
+    double blur_sigma;       /* > 0                                                           */
+    int reg;                 /* bl_reg                                                        */
+    int n_filters;           /* filters: 1..8                                                 */
+    int filter_size;         /* filters: odd, 1..7                                            */
+    double eps;              /* filters: coefficient of eps/2 ||x||^2                         */
+    int penalty;             /* filters: bl_penalty                                           */
+    int prec;                /* bl_prec                                                       */
+} bl_problem;
+
+/* Recycle state of one training sample (Section 2.2: U, C = H U with C^T C = I, and the
+ * Krylov basis V of the last solve).  All pointers are caller-owned device memory.
+ * U, C, Z: n x s_max; mu: s_max doubles; V: n x v_cap. */
+typedef struct {
+    double* U;
+    double* C;
+    double* Z;               /* Z = W V_H~ for the hypergradient-error estimate               */
+    double* mu;              /* selected Ritz generalized singular values (0 for fill slots) */
+    double* V;               /* first v_cap normalised CG residuals of the last solve         */
+    int s_max, s_cur;        /* capacity / valid columns of U, C, Z, mu (s_cur = 0: none)     */
+    int v_cap, v_cur;        /* capacity / valid columns of V                                 */
+} bl_recycle;
+
+typedef struct {
+    int stop;                /* bl_stop                                                       */
+    double tol;              /* residual test ||r|| <= tol ||g||                              */
+    double hg_tol;           /* error-estimate test ||mu . (Z^T r)|| <= hg_tol (absolute)     */
+    int max_iter;
+    int check_every;         /* iterations between host polls of the device stop flag        */
+    int rr_every;            /* residual replacement period in mixed precision (0 = off)     */
+    int store_basis;         /* store normalised residuals into rs->V                         */
+} bl_solve_opts;
+
+typedef struct {
+    int s;                   /* requested recycle dimension (<= rs->s_max)                    */
+    double rank_tol;         /* relative column-norm drop threshold for orthonormalising W   */
+} bl_recycle_opts;
+
+typedef struct {
+    int iters;
+    int status;              /* bl_status of the solve                                        */
+    int t;                   /* refresh: columns of W kept; solve: unused                     */
+    int s_cur;               /* refresh: recycle columns produced                             */
+    double res_norm;         /* final recursive residual norm                                 */
+    double res0_norm;        /* residual norm after the recycle-space projection             */
+    double g_norm;
+    double est;              /* last hypergradient-error estimate (NaN if unavailable)        */
+    double ms[4];            /* wall-clock phases (ms), filled when timing is enabled         */
+} bl_stats;
+
+typedef struct bl_ctx bl_ctx;
+
+/* Context bound to a HIP stream (hipStream_t passed as void*; NULL = default stream). */
+bl_status bl_create(bl_ctx** ctx, void* hip_stream);
+bl_status bl_destroy(bl_ctx* ctx);
+const char* bl_status_string(int status);
+const char* bl_last_error(const bl_ctx* ctx);
+int bl_num_params(const bl_problem* P);
+/* Device workspace for any call on problems of this shape with recycle capacity s_max and
+ * stored-basis capacity v_cap (t_max = s_max + v_cap columns of refresh scratch). */
+size_t bl_workspace_bytes(const bl_problem* P, int s_max, int v_cap);
+
+/* Measurement y = A x + noise * e (problem data; not on the timed path). */
+bl_status bl_forward(bl_ctx* ctx, const bl_problem* P, const double* x, const double* e, double noise,
+                     double* y, void* ws, size_t ws_bytes);
+
+/* Lower-level solve (eq. ll2): L-BFGS with history m (Section 5), Armijo backtracking,
+ * stop at ||grad Phi|| <= gtol.  x_inout: start point in, minimiser out.  out: iters in
+ * stats->iters, final gradient norm in stats->res_norm. */
+bl_status bl_lower_solve(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* y,
+                         double* x_inout, double gtol, int max_iter, int m, void* ws, size_t ws_bytes,
+                         bl_stats* out);
+
+/* Ritz-GSV refresh, outer variant (Section 3.2, eqs. gsvd, partial-gsvd, RGen-L(R)): builds
+ * W = orth([U, V]) from rs, projects M = W^T H W, G = J W at (xhat, theta), takes the s
+ * largest Ritz generalized singular values (null(G) filled by Ritz-S when rank G < s),
+ * and writes U, C = H U (C^T C = I), Z, mu and s_cur into rs.  rs->s_cur = 0 and
+ * rs->v_cur = 0 leave rs empty. */
+bl_status bl_recycle_update(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                            bl_recycle* rs, const bl_recycle_opts* opts, void* ws, size_t ws_bytes,
+                            bl_stats* out);
+
+/* Hessian solve H w = g (eq. hess_sys) by recycled CG (Galerkin counterpart of RMINRES,
+ * Section 2.2.2) with the residual or hypergradient-error test (Section 4, eq.
+ * hg-err-stop-lowrank).  rs == NULL or rs->s_cur == 0: plain CG.  w_inout: warm start in,
+ * solution out.  With opts->store_basis the normalised residuals go to rs->V. */
+bl_status bl_hessian_solve(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                           const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
+                           void* ws, size_t ws_bytes, bl_stats* out);
+
+/* Hypergradient J w = -(D_theta grad_x Phi)^T w (eq. hypgrad) into grad_host (p doubles).
+ * Filters: each filter's tap block is projected onto zero mean when project_zero_mean. */
+bl_status bl_hypergradient(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                           const double* w, double* grad_host, int project_zero_mean, void* ws, size_t ws_bytes);
+
+/* Matrix-free Hessian-vector products out[:, j] = H v[:, j], j < ncols (columns ld = n),
+ * in the problem's precision (FP32 stencil arithmetic in mixed mode, FP64 output). */
+bl_status bl_hvp(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                 const double* v, double* out, int ncols, void* ws, size_t ws_bytes);
+
+/* Gradient of the lower-level objective and its value (value to *phi_host if non-NULL). */
+bl_status bl_lower_grad(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* y,
+                        const double* x, double* grad, double* phi_host, void* ws, size_t ws_bytes);
+
+/* Time the phases of subsequent calls with HIP events (stats->ms), 0/1.  With 2, also record
+ * HIP events around every launch of the Krylov apply and update kernels (see bl_kernel_times). */
+bl_status bl_set_timing(bl_ctx* ctx, int enable);
+
+/* Per-kernel durations accumulated over solves since the last reset, iterations that ran
+ * only: out4[0] = total ms of the apply kernel (H p fused with p.q and C^T q), out4[1] =
+ * its launch count, out4[2] / out4[3] = the same for the update kernel (w, r, r.r, Z^T r).
+ * reset != 0 clears the totals after reading. */
+bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BILEVEL_H */

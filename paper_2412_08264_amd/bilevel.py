@@ -1,0 +1,252 @@
+"""ctypes binding of libbilevel_hip.so (same names as the C ABI in include/bilevel.h).
+
+Argument marshalling only: torch tensors provide device memory and the stream, every
+step of the computation runs in the library's HIP kernels.  Importing this module
+loads the library and fails loudly when it is missing or was built without GPU code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbilevel_hip.so")
+
+BL_OK, BL_E_ARG, BL_E_SHAPE, BL_E_WORKSPACE, BL_E_NOT_CONVERGED = 0, 1, 2, 3, 4
+BL_E_INDEFINITE, BL_E_BREAKDOWN, BL_E_RANK, BL_E_NONFINITE, BL_E_HIP = 5, 6, 7, 8, 9
+BL_REG_TV, BL_REG_FILTERS = 0, 1
+BL_PEN_LOG, BL_PEN_QUAD = 0, 1
+BL_PREC_FP64, BL_PREC_MIXED = 0, 1
+BL_STOP_RESID, BL_STOP_HGERR = 0, 1
+
+
+class bl_problem(C.Structure):
+    _fields_ = [("h", C.c_int), ("w", C.c_int), ("blur_radius", C.c_int), ("blur_sigma", C.c_double),
+                ("reg", C.c_int), ("n_filters", C.c_int), ("filter_size", C.c_int), ("eps", C.c_double),
+                ("penalty", C.c_int), ("prec", C.c_int)]
+
+
+class bl_recycle(C.Structure):
+    _fields_ = [("U", C.c_void_p), ("C", C.c_void_p), ("Z", C.c_void_p), ("mu", C.c_void_p), ("V", C.c_void_p),
+                ("s_max", C.c_int), ("s_cur", C.c_int), ("v_cap", C.c_int), ("v_cur", C.c_int)]
+
+
+class bl_solve_opts(C.Structure):
+    _fields_ = [("stop", C.c_int), ("tol", C.c_double), ("hg_tol", C.c_double), ("max_iter", C.c_int),
+                ("check_every", C.c_int), ("rr_every", C.c_int), ("store_basis", C.c_int)]
+
+
+class bl_recycle_opts(C.Structure):
+    _fields_ = [("s", C.c_int), ("rank_tol", C.c_double)]
+
+
+class bl_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("status", C.c_int), ("t", C.c_int), ("s_cur", C.c_int),
+                ("res_norm", C.c_double), ("res0_norm", C.c_double), ("g_norm", C.c_double), ("est", C.c_double),
+                ("ms", C.c_double * 4)]
+
+
+_P = C.POINTER
+_vp = C.c_void_p
+_SIGS = {
+    "bl_create": (C.c_int, [_P(_vp), _vp]),
+    "bl_destroy": (C.c_int, [_vp]),
+    "bl_status_string": (C.c_char_p, [C.c_int]),
+    "bl_last_error": (C.c_char_p, [_vp]),
+    "bl_num_params": (C.c_int, [_P(bl_problem)]),
+    "bl_workspace_bytes": (C.c_size_t, [_P(bl_problem), C.c_int, C.c_int]),
+    "bl_forward": (C.c_int, [_vp, _P(bl_problem), _vp, _vp, C.c_double, _vp, _vp, C.c_size_t]),
+    "bl_lower_solve": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, C.c_double, C.c_int, C.c_int,
+                                 _vp, C.c_size_t, _P(bl_stats)]),
+    "bl_recycle_update": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _P(bl_recycle),
+                                    _P(bl_recycle_opts), _vp, C.c_size_t, _P(bl_stats)]),
+    "bl_hessian_solve": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
+                                   _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
+    "bl_hypergradient": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _P(C.c_double), C.c_int,
+                                   _vp, C.c_size_t]),
+    "bl_hvp": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, C.c_int, _vp, C.c_size_t]),
+    "bl_lower_grad": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(C.c_double), _vp,
+                                C.c_size_t]),
+    "bl_set_timing": (C.c_int, [_vp, C.c_int]),
+    "bl_kernel_times": (C.c_int, [_vp, _P(C.c_double), C.c_int]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path: str = _LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load_library()
+
+
+class BLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{lib.bl_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _theta(theta) -> C.Array:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    return (C.c_double * th.size)(*th.tolist())
+
+
+def problem_from(wl, prec: str | None = None, penalty: str = "log") -> bl_problem:
+    """bl_problem of a synthetic workload recipe."""
+    prec = prec or wl.prec
+    return bl_problem(wl.h, wl.w, wl.blur_radius, wl.blur_sigma,
+                      BL_REG_TV if wl.reg == "tv" else BL_REG_FILTERS,
+                      wl.n_filters, wl.filter_size, wl.eps,
+                      BL_PEN_LOG if penalty == "log" else BL_PEN_QUAD,
+                      BL_PREC_MIXED if prec == "mixed" else BL_PREC_FP64)
+
+
+# --------------------------------------------------------------------------- same-name wrappers
+def bl_create(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ctx = C.c_void_p()
+    st = lib.bl_create(C.byref(ctx), C.c_void_p(s.cuda_stream))
+    if st != BL_OK:
+        raise BLError(st, "bl_create")
+    return ctx
+
+
+def bl_destroy(ctx) -> None:
+    lib.bl_destroy(ctx)
+
+
+def bl_workspace_bytes(P: bl_problem, s_max: int, v_cap: int) -> int:
+    return int(lib.bl_workspace_bytes(C.byref(P), s_max, v_cap))
+
+
+def bl_num_params(P: bl_problem) -> int:
+    return int(lib.bl_num_params(C.byref(P)))
+
+
+def _check(ctx, st: int, name: str, ok=(BL_OK,)) -> int:
+    if st not in ok:
+        raise BLError(st, f"{name}: {lib.bl_last_error(ctx).decode()}")
+    return st
+
+
+class Session:
+    """Context + workspace + recycle storage of one problem shape (torch tensors on one device)."""
+
+    def __init__(self, P: bl_problem, s_max: int = 0, v_cap: int = 0, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.P = P
+        self.n = P.h * P.w
+        self.p = bl_num_params(P)
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ctx = bl_create(self.stream)
+            nbytes = bl_workspace_bytes(P, s_max, v_cap)
+            if nbytes == 0:
+                raise BLError(BL_E_ARG, "bl_workspace_bytes rejected the shape")
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self.ws_ptr = self.ws.data_ptr() + off
+            self.ws_bytes = nbytes
+            f64 = dict(dtype=torch.float64, device=self.device)
+            self.U = torch.zeros((max(s_max, 1), self.n), **f64)
+            self.Cm = torch.zeros((max(s_max, 1), self.n), **f64)
+            self.Z = torch.zeros((max(s_max, 1), self.n), **f64)
+            self.mu = torch.zeros(max(s_max, 1), **f64)
+            self.V = torch.zeros((max(v_cap, 1), self.n), **f64)
+        self.rs = bl_recycle(self.U.data_ptr(), self.Cm.data_ptr(), self.Z.data_ptr(), self.mu.data_ptr(),
+                             self.V.data_ptr(), s_max, 0, v_cap, 0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            bl_destroy(self.ctx)
+            self.ctx = None
+
+    def reset(self):
+        self.rs.s_cur = 0
+        self.rs.v_cur = 0
+
+    def set_timing(self, mode: int = 1):
+        lib.bl_set_timing(self.ctx, int(mode))
+
+    def kernel_times(self, reset: bool = True):
+        """(apply ms total, apply launches, update ms total, update launches)."""
+        out = (C.c_double * 4)()
+        lib.bl_kernel_times(self.ctx, out, 1 if reset else 0)
+        return tuple(out[:])
+
+    # -- calls
+    def forward(self, x, e, noise, y):
+        _check(self.ctx, lib.bl_forward(self.ctx, C.byref(self.P), _ptr(x), _ptr(e), noise, _ptr(y),
+                                        self.ws_ptr, self.ws_bytes), "bl_forward")
+
+    def hvp(self, theta, xhat, v, out, ncols: int = 1):
+        _check(self.ctx, lib.bl_hvp(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(v), _ptr(out),
+                                    ncols, self.ws_ptr, self.ws_bytes), "bl_hvp")
+
+    def lower_grad(self, theta, y, x, grad) -> float:
+        phi = C.c_double()
+        _check(self.ctx, lib.bl_lower_grad(self.ctx, C.byref(self.P), _theta(theta), _ptr(y), _ptr(x), _ptr(grad),
+                                           C.byref(phi), self.ws_ptr, self.ws_bytes), "bl_lower_grad")
+        return phi.value
+
+    def lower_solve(self, theta, y, x, gtol=1e-8, max_iter=20000, m=10) -> bl_stats:
+        st = bl_stats()
+        _check(self.ctx, lib.bl_lower_solve(self.ctx, C.byref(self.P), _theta(theta), _ptr(y), _ptr(x), gtol,
+                                            max_iter, m, self.ws_ptr, self.ws_bytes, C.byref(st)),
+               "bl_lower_solve", ok=(BL_OK, BL_E_NOT_CONVERGED))
+        return st
+
+    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8) -> bl_stats:
+        st = bl_stats()
+        o = bl_recycle_opts(s, rank_tol)
+        _check(self.ctx, lib.bl_recycle_update(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat),
+                                               C.byref(self.rs), C.byref(o), self.ws_ptr, self.ws_bytes,
+                                               C.byref(st)), "bl_recycle_update", ok=(BL_OK, BL_E_RANK))
+        return st
+
+    def solve(self, theta, xhat, g, w, tol=1e-10, stop: str = "resid", hg_tol: float = 0.0, max_iter: int = 20000,
+              check_every: int = 1, rr_every: int = 50, store_basis: bool = True, recycle: bool = True,
+              allow=(BL_OK,)) -> bl_stats:
+        st = bl_stats()
+        o = bl_solve_opts(BL_STOP_HGERR if stop == "hgerr" else BL_STOP_RESID, tol, hg_tol, max_iter, check_every,
+                          rr_every, 1 if store_basis else 0)
+        rs = self.rs if recycle or store_basis else None
+        saved = None
+        if rs is not None and not recycle:
+            saved, rs.s_cur = rs.s_cur, 0
+        try:
+            code = lib.bl_hessian_solve(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(g), _ptr(w),
+                                        C.byref(rs) if rs is not None else None, C.byref(o), self.ws_ptr,
+                                        self.ws_bytes, C.byref(st))
+        finally:
+            if saved is not None:
+                rs.s_cur = saved
+        _check(self.ctx, code, "bl_hessian_solve", ok=allow)
+        return st
+
+    def hypergradient(self, theta, xhat, w, project: bool = True) -> np.ndarray:
+        out = (C.c_double * self.p)()
+        _check(self.ctx, lib.bl_hypergradient(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(w), out,
+                                              1 if project else 0, self.ws_ptr, self.ws_bytes), "bl_hypergradient")
+        return np.array(out[:], dtype=np.float64)

@@ -1,0 +1,616 @@
+// Stencil kernels: Hessian-vector products, the fused CG apply step, residual set-up,
+// filter-state precompute, the hypergradient map J, the lower-level gradient and A.
+#include "kernels.h"
+#include "stencil.h"
+
+namespace bl {
+
+__device__ __forceinline__ void tile_origin(const Stencil& S, int tile, int& r0, int& c0) {
+    r0 = (tile / S.tiles_x) * TH;
+    c0 = (tile % S.tiles_x) * TW;
+}
+
+// Per-block partial record of nv values; value k of this thread given by `val(k)`.
+template <typename Val>
+__device__ __forceinline__ void write_partials(double* part, int nv, double* red, Val val) {
+    for (int k = 0; k < nv; ++k) {
+        double s = block_sum(val(k), red);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * nv + k] = s;
+    }
+}
+
+// ------------------------------------------------------------------ out[:, c] = H v[:, c]
+template <typename T>
+__global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict__ xhat,
+                                            const double* __restrict__ v, double* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
+    int r0, c0;
+    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
+    const double* vc = v + (size_t)blockIdx.y * S.n;
+    stage_region<T>(lds + L.o_v, S, L, r0, c0, [&](int i) { return vc[i]; });
+    __syncthreads();
+    hvp_tile<T>(lds, S, L, xhat, r0, c0);
+    __syncthreads();
+    double* oc = out + (size_t)blockIdx.y * S.n;
+    for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
+        if (gi < S.h && gj < S.w) oc[gi * S.w + gj] = (double)lds[L.o_out + idx];
+    }
+}
+
+// ------------------------------------------------------------------ CG apply step
+// p_new = r + beta p_old (p = r on the first iteration), q = H p_new, and the block
+// partials of p.q and C^T q; the last block forms sigma, alpha = rho / sigma, e = C^T q
+// and z -= alpha e.  Optionally stores V[:, iters] = r / ||r||.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, const double* __restrict__ xhat,
+                                                 const double* __restrict__ r, const double* __restrict__ p_old,
+                                                 double* __restrict__ p_new, double* __restrict__ q,
+                                                 const double* __restrict__ C, double* __restrict__ V,
+                                                 SolveState* st, double* part, unsigned* counter) {
+    if (st->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[NWAVE];
+    __shared__ double tot[1 + S_MAX];
+    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
+    const int iters = st->iters, s = st->s;
+    const bool first = (iters == 0);
+    const double beta = first ? 0.0 : st->beta;
+    int r0, c0;
+    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
+    stage_region<T>(lds + L.o_v, S, L, r0, c0,
+                    [&](int i) { return first ? r[i] : r[i] + beta * p_old[i]; });
+    __syncthreads();
+    hvp_tile<T>(lds, S, L, xhat, r0, c0);
+    __syncthreads();
+    const bool store = st->store_basis && iters < st->v_cap;
+    const double inv_nr = store ? 1.0 / sqrt(st->rho) : 0.0;
+    // each thread owns pixels threadIdx.x and threadIdx.x + NT of the tile
+    double pv[TH * TW / NT], qv[TH * TW / NT];
+    int gid[TH * TW / NT];
+#pragma unroll
+    for (int u = 0; u < TH * TW / NT; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
+        gid[u] = -1;
+        pv[u] = 0.0;
+        qv[u] = 0.0;
+        if (gi < S.h && gj < S.w) {
+            const int i = gi * S.w + gj;
+            gid[u] = i;
+            const double ri = r[i];
+            const double pn = first ? ri : ri + beta * p_old[i];
+            const double qq = (double)lds[L.o_out + idx];
+            p_new[i] = pn;
+            q[i] = qq;
+            if (store) V[(size_t)iters * S.n + i] = ri * inv_nr;
+            pv[u] = pn;
+            qv[u] = qq;
+        }
+    }
+    const int nv = 1 + s;
+    write_partials(part, nv, red, [&](int k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < TH * TW / NT; ++u) {
+            if (gid[u] < 0) continue;
+            acc += (k == 0 ? pv[u] : C[(size_t)(k - 1) * S.n + gid[u]]) * qv[u];
+        }
+        return acc;
+    });
+    if (!last_block(counter, gridDim.x)) return;
+    reduce_partials(part, gridDim.x, nv, tot, red);
+    const double sigma = tot[0];
+    const bool bad = !(sigma > 0.0);
+    if (threadIdx.x == 0) {
+        if (bad) {
+            st->status = (sigma != sigma || fabs(sigma) == INFINITY) ? BL_E_NONFINITE : BL_E_INDEFINITE;
+            st->done = 1;
+        } else {
+            st->sigma = sigma;
+            st->alpha = st->rho / sigma;
+        }
+    }
+    if (!bad) {
+        const double alpha = st->rho / sigma;
+        for (int k = threadIdx.x; k < s; k += NT) {
+            st->e[k] = tot[1 + k];
+            st->zacc[k] -= alpha * tot[1 + k];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ residual g - H w
+// out = g - H w and block partials of C^T out (s values) and g.g; the last block stores
+// C^T out in st->c0 and ||g|| in st->gnorm.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_residual(Stencil S, const double* __restrict__ xhat,
+                                                 const double* __restrict__ w, const double* __restrict__ g,
+                                                 double* __restrict__ out, const double* __restrict__ C,
+                                                 SolveState* st, double* part, unsigned* counter) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[NWAVE];
+    __shared__ double tot[1 + S_MAX];
+    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
+    const int s = st->s;
+    int r0, c0;
+    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
+    stage_region<T>(lds + L.o_v, S, L, r0, c0, [&](int i) { return w[i]; });
+    __syncthreads();
+    hvp_tile<T>(lds, S, L, xhat, r0, c0);
+    __syncthreads();
+    double ov[TH * TW / NT], gv[TH * TW / NT];
+    int gid[TH * TW / NT];
+#pragma unroll
+    for (int u = 0; u < TH * TW / NT; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
+        gid[u] = -1;
+        ov[u] = gv[u] = 0.0;
+        if (gi < S.h && gj < S.w) {
+            const int i = gi * S.w + gj;
+            gid[u] = i;
+            gv[u] = g[i];
+            ov[u] = gv[u] - (double)lds[L.o_out + idx];
+            out[i] = ov[u];
+        }
+    }
+    const int nv = 1 + s;
+    write_partials(part, nv, red, [&](int k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < TH * TW / NT; ++u) {
+            if (gid[u] < 0) continue;
+            acc += (k == 0) ? gv[u] * gv[u] : C[(size_t)(k - 1) * S.n + gid[u]] * ov[u];
+        }
+        return acc;
+    });
+    if (!last_block(counter, gridDim.x)) return;
+    reduce_partials(part, gridDim.x, nv, tot, red);
+    if (threadIdx.x == 0) st->gnorm = sqrt(tot[0]);
+    for (int k = threadIdx.x; k < s; k += NT) st->c0[k] = tot[1 + k];
+}
+
+// ------------------------------------------------------------------ filter state
+// d1_j = phi'(K_j xhat), d2_j = phi''(K_j xhat) (FP64 maps, plus FP32 copies of d2).
+__global__ void __launch_bounds__(NT) k_filter_state(Stencil S, const double* __restrict__ xhat,
+                                                     double* __restrict__ d1, double* __restrict__ d2,
+                                                     float* __restrict__ d2f) {
+    const int i = blockIdx.x * NT + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= S.n) return;
+    const int gi = i / S.w, gj = i - gi * S.w, F = S.fs / 2;
+    const double* kj = S.taps + j * S.fs * S.fs;
+    double s = 0.0;
+    for (int a = 0; a < S.fs; ++a) {
+        const int ii = gi + a - F;
+        if (ii < 0 || ii >= S.h) continue;
+        for (int b = 0; b < S.fs; ++b) {
+            const int jj = gj + b - F;
+            if (jj < 0 || jj >= S.w) continue;
+            s += kj[a * S.fs + b] * xhat[ii * S.w + jj];
+        }
+    }
+    double p1, p2;
+    if (S.penalty == BL_PEN_LOG) {
+        const double den = 1.0 + s * s;
+        p1 = 2.0 * s / den;
+        p2 = 2.0 * (1.0 - s * s) / (den * den);
+    } else {
+        p1 = 2.0 * s;
+        p2 = 2.0;
+    }
+    const size_t o = (size_t)j * S.n + i;
+    d1[o] = p1;
+    d2[o] = p2;
+    d2f[o] = (float)p2;
+}
+
+// ------------------------------------------------------------------ J for smoothed TV
+// Column c of G (2 x ncols): [-lam sum <u/psi, D w_c>, lam gam2 sum <u/psi^3, D w_c>], u = D xhat.
+__global__ void __launch_bounds__(NT) k_jac_tv(Stencil S, const double* __restrict__ xhat,
+                                               const double* __restrict__ wv, double* __restrict__ part) {
+    __shared__ double red[NWAVE];
+    const double* w = wv + (size_t)blockIdx.y * S.n;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < S.n; i += gridDim.x * NT) {
+        const int gi = i / S.w, gj = i - gi * S.w;
+        const double a = (gj < S.w - 1) ? xhat[i + 1] - xhat[i] : 0.0;
+        const double b = (gi < S.h - 1) ? xhat[i + S.w] - xhat[i] : 0.0;
+        const double da = (gj < S.w - 1) ? w[i + 1] - w[i] : 0.0;
+        const double db = (gi < S.h - 1) ? w[i + S.w] - w[i] : 0.0;
+        const double psi2 = a * a + b * b + S.gam2;
+        const double psi = sqrt(psi2);
+        const double dot = a * da + b * db;
+        s0 += dot / psi;
+        s1 += dot / (psi2 * psi);
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        double* pr = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        pr[0] = -S.lam * s0;
+        pr[1] = S.lam * S.gam2 * s1;
+    }
+}
+
+// ------------------------------------------------------------------ J for filters
+// Column c of G (p x ncols), per block over a band of tiles:
+//   [J w]_{w_j}    = -lam_j <d1_j, K_j w>
+//   [J w]_{k_j[a]} = -lam_j (<d1_j, S_a w> + <d2_j . K_j w, S_a xhat>)
+constexpr int JF_BLOCKS = 64;
+__global__ void __launch_bounds__(NT) k_jac_filters(Stencil S, const double* __restrict__ xhat,
+                                                    const double* __restrict__ wv, const double* __restrict__ d1,
+                                                    const double* __restrict__ d2, double* __restrict__ part) {
+    const int F = S.fs / 2, fs = S.fs, f2 = fs * fs, p = S.nf * (1 + f2);
+    const int WW = TW + 2 * F, HH = TH + 2 * F;
+    __shared__ double ws[(TH + 2 * (MAX_FS / 2)) * (TW + 2 * (MAX_FS / 2))];
+    __shared__ double xs[(TH + 2 * (MAX_FS / 2)) * (TW + 2 * (MAX_FS / 2))];
+    __shared__ double kw[TH * TW], d1s[TH * TW], ts[TH * TW];
+    __shared__ double taps[MAX_NF * MAX_FS * MAX_FS];
+    __shared__ double acc_s[MAX_NF * (1 + MAX_FS * MAX_FS)];
+    __shared__ double red[NWAVE];
+    const double* w = wv + (size_t)blockIdx.y * S.n;
+    for (int k = threadIdx.x; k < S.nf * f2; k += NT) taps[k] = S.taps[k];
+    for (int k = threadIdx.x; k < p; k += NT) acc_s[k] = 0.0;
+    const int ntiles = S.tiles_x * S.tiles_y;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int r0, c0;
+        tile_origin(S, tile, r0, c0);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < HH * WW; idx += NT) {
+            const int rr = idx / WW, cc = idx - rr * WW;
+            const int gi = r0 - F + rr, gj = c0 - F + cc;
+            const bool in = gi >= 0 && gi < S.h && gj >= 0 && gj < S.w;
+            ws[idx] = in ? w[gi * S.w + gj] : 0.0;
+            xs[idx] = in ? xhat[gi * S.w + gj] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < S.nf; ++j) {
+            const double* kj = taps + j * f2;
+            for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+                const int rr = idx / TW, cc = idx - rr * TW;
+                const int gi = r0 + rr, gj = c0 + cc;
+                double kwv = 0.0, a1 = 0.0, a2 = 0.0;
+                if (gi < S.h && gj < S.w) {
+                    for (int a = 0; a < fs; ++a)
+                        for (int b = 0; b < fs; ++b) kwv += kj[a * fs + b] * ws[(rr + a) * WW + cc + b];
+                    const size_t o = (size_t)j * S.n + gi * S.w + gj;
+                    a1 = d1[o];
+                    a2 = d2[o] * kwv;
+                }
+                kw[idx] = kwv;
+                d1s[idx] = a1;
+                ts[idx] = a2;
+            }
+            __syncthreads();
+            double wsum = 0.0;
+            for (int idx = threadIdx.x; idx < TH * TW; idx += NT) wsum += d1s[idx] * kw[idx];
+            wsum = block_sum(wsum, red);
+            if (threadIdx.x == 0) acc_s[j * (1 + f2)] += wsum;
+            // taps: thread groups split the tile pixels; group sums combined in fixed order
+            const int groups = NT / f2;               // >= 5 for f <= 7
+            const int tap = threadIdx.x % f2, grp = threadIdx.x / f2;
+            double part_t = 0.0;
+            if (grp < groups) {
+                const int a = tap / fs, b = tap - a * fs;
+                for (int idx = grp; idx < TH * TW; idx += groups) {
+                    const int rr = idx / TW, cc = idx - rr * TW;
+                    const int o = (rr + a) * WW + cc + b;   // S_a with offset (a - F, b - F)
+                    part_t += d1s[idx] * ws[o] + ts[idx] * xs[o];
+                }
+            }
+            __syncthreads();
+            kw[threadIdx.x] = (grp < groups) ? part_t : 0.0;   // reuse kw as scratch (NT <= TH*TW)
+            __syncthreads();
+            if (threadIdx.x < f2) {
+                double sum = 0.0;
+                for (int gq = 0; gq < groups; ++gq) sum += kw[gq * f2 + threadIdx.x];
+                acc_s[j * (1 + f2) + 1 + threadIdx.x] += sum;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    double* pr = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * p;
+    for (int k = threadIdx.x; k < p; k += NT) {
+        const int j = k / (1 + f2);
+        pr[k] = -S.lamj[j] * acc_s[k];
+    }
+}
+
+// Sum the per-block records of J into G (p x ncols, column-major), optional zero-mean
+// projection of each filter's tap block.
+__global__ void k_jac_reduce(const double* __restrict__ part, int nblocks, int p, int ncols, double* __restrict__ G,
+                             int project, int fs2) {
+    const int c = blockIdx.x;
+    extern __shared__ double colv[];
+    for (int k = threadIdx.x; k < p; k += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += part[((size_t)c * nblocks + b) * p + k];
+        colv[k] = s;
+    }
+    __syncthreads();
+    if (project && fs2 > 0) {
+        const int nfil = p / (1 + fs2);
+        for (int j = threadIdx.x; j < nfil; j += blockDim.x) {
+            double m = 0.0;
+            for (int a = 0; a < fs2; ++a) m += colv[j * (1 + fs2) + 1 + a];
+            m /= fs2;
+            for (int a = 0; a < fs2; ++a) colv[j * (1 + fs2) + 1 + a] -= m;
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < p; k += blockDim.x) G[(size_t)c * p + k] = colv[k];
+}
+
+// ------------------------------------------------------------------ lower-level gradient
+// grad = 2 A^T (A x - y) + [TV] lam D^T(D x / psi) | [filters] eps x + sum_j lam_j K_j^T phi'(K_j x)
+// and block partials of Phi and ||grad||^2 (last block: st_out[0] = Phi, [1] = ||grad||^2).
+__global__ void __launch_bounds__(NT) k_lower_grad(Stencil S, const double* __restrict__ x,
+                                                   const double* __restrict__ y, double* __restrict__ grad,
+                                                   double* part, unsigned* counter, double* st_out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    __shared__ double red[NWAVE];
+    __shared__ double tot[2];
+    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
+    const int R = S.R, E = L.E, RW = L.RW, RH = L.RH;
+    int r0, c0;
+    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
+    double* v = lds + L.o_v;
+    stage_region<double>(v, S, L, r0, c0, [&](int i) { return x[i]; });
+    __syncthreads();
+    double* h1 = lds + L.o_h1;
+    double* t1 = lds + L.o_t1;
+    double* out = lds + L.o_out;
+    double phi_loc = 0.0;
+    const int W1 = TW + 2 * R, H1 = TH + 2 * R;
+    for (int idx = threadIdx.x; idx < RH * W1; idx += NT) {
+        const int rr = idx / W1, cc = idx - rr * W1;
+        const double* src = v + rr * RW + cc + E - 2 * R;
+        double acc = 0.0;
+        for (int b = 0; b <= 2 * R; ++b) acc += S.g[b] * src[b];
+        h1[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < H1 * W1; idx += NT) {      // residual A x - y on tile + R
+        const int rr = idx / W1, cc = idx - rr * W1;
+        const double* src = h1 + (rr + E - 2 * R) * W1 + cc;
+        double acc = 0.0;
+        for (int a = 0; a <= 2 * R; ++a) acc += S.g[a] * src[a * W1];
+        const int gi = r0 - R + rr, gj = c0 - R + cc;
+        double res = 0.0;
+        if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
+            res = acc - y[gi * S.w + gj];
+            if (rr >= R && rr < R + TH && cc >= R && cc < R + TW) phi_loc += res * res;
+        }
+        t1[idx] = res;
+    }
+    __syncthreads();
+    double* h2 = h1;
+    for (int idx = threadIdx.x; idx < H1 * TW; idx += NT) {
+        const int rr = idx / TW, cc = idx - rr * TW;
+        const double* src = t1 + rr * W1 + cc;
+        double acc = 0.0;
+        for (int b = 0; b <= 2 * R; ++b) acc += S.g[b] * src[b];
+        h2[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+        const int rr = idx / TW, cc = idx - rr * TW;
+        const double* src = h2 + rr * TW + cc;
+        double acc = 0.0;
+        for (int a = 0; a <= 2 * R; ++a) acc += S.g[a] * src[a * TW];
+        out[idx] = 2.0 * acc;
+    }
+    if (S.reg == BL_REG_TV) {
+        double* fx = lds + L.o_fx;
+        double* fy = lds + L.o_fy;
+        const int FW = TW + 1;
+        for (int idx = threadIdx.x; idx < (TH + 1) * FW; idx += NT) {
+            const int rr = idx / FW, cc = idx - rr * FW;
+            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
+            double fxv = 0.0, fyv = 0.0;
+            if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
+                const double* vc = v + (rr - 1 + E) * RW + (cc - 1 + E);
+                const double a = (gj < S.w - 1) ? vc[1] - vc[0] : 0.0;
+                const double b = (gi < S.h - 1) ? vc[RW] - vc[0] : 0.0;
+                const double psi = sqrt(a * a + b * b + S.gam2);
+                fxv = a / psi;
+                fyv = b / psi;
+                if (rr >= 1 && cc >= 1) phi_loc += S.lam * psi;
+            }
+            fx[idx] = fxv;
+            fy[idx] = fyv;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+            const int rr = idx / TW, cc = idx - rr * TW;
+            const int f = (rr + 1) * FW + (cc + 1);
+            out[idx] += S.lam * (-fx[f] + fx[f - 1] - fy[f] + fy[f - FW]);
+        }
+        __syncthreads();
+    } else {
+        const int F = L.F, fs = S.fs, TWF = TW + 2 * F, THF = TH + 2 * F;
+        double* tb = lds + L.o_t;
+        for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+            const int rr = idx / TW, cc = idx - rr * TW;
+            const double xv = v[(rr + E) * RW + (cc + E)];
+            out[idx] += S.eps * xv;
+            if (r0 + rr < S.h && c0 + cc < S.w) phi_loc += 0.5 * S.eps * xv * xv;
+        }
+        __syncthreads();
+        for (int j = 0; j < S.nf; ++j) {
+            const double* kj = S.taps + j * fs * fs;
+            const double lj = S.lamj[j];
+            for (int idx = threadIdx.x; idx < THF * TWF; idx += NT) {
+                const int rr = idx / TWF, cc = idx - rr * TWF;
+                const int gi = r0 - F + rr, gj = c0 - F + cc;
+                double val = 0.0;
+                if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
+                    const double* src = v + (rr + E - 2 * F) * RW + (cc + E - 2 * F);
+                    double sresp = 0.0;
+                    for (int a = 0; a < fs; ++a)
+                        for (int b = 0; b < fs; ++b) sresp += kj[a * fs + b] * src[a * RW + b];
+                    if (S.penalty == BL_PEN_LOG) {
+                        val = 2.0 * sresp / (1.0 + sresp * sresp);
+                        if (rr >= F && rr < F + TH && cc >= F && cc < F + TW) phi_loc += lj * log1p(sresp * sresp);
+                    } else {
+                        val = 2.0 * sresp;
+                        if (rr >= F && rr < F + TH && cc >= F && cc < F + TW) phi_loc += lj * sresp * sresp;
+                    }
+                }
+                tb[idx] = val;
+            }
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+                const int rr = idx / TW, cc = idx - rr * TW;
+                const double* src = tb + (rr + 2 * F) * TWF + (cc + 2 * F);
+                double acc = 0.0;
+                for (int a = 0; a < fs; ++a)
+                    for (int b = 0; b < fs; ++b) acc += kj[a * fs + b] * src[-a * TWF - b];
+                out[idx] += lj * acc;
+            }
+            __syncthreads();
+        }
+    }
+    double gn = 0.0;
+    for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
+        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
+        if (gi < S.h && gj < S.w) {
+            grad[gi * S.w + gj] = out[idx];
+            gn += out[idx] * out[idx];
+        }
+    }
+    const double ph = block_sum(phi_loc, red);
+    const double gg = block_sum(gn, red);
+    if (threadIdx.x == 0) {
+        part[(size_t)blockIdx.x * 2] = ph;
+        part[(size_t)blockIdx.x * 2 + 1] = gg;
+    }
+    if (!last_block(counter, gridDim.x)) return;
+    reduce_partials(part, gridDim.x, 2, tot, red);
+    if (threadIdx.x == 0) {
+        st_out[0] = tot[0];
+        st_out[1] = tot[1];
+    }
+}
+
+// ------------------------------------------------------------------ y = A x + noise e
+__global__ void __launch_bounds__(NT) k_forward(Stencil S, const double* __restrict__ x, const double* __restrict__ e,
+                                                double noise, double* __restrict__ y) {
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i >= S.n) return;
+    const int gi = i / S.w, gj = i - gi * S.w, R = S.R;
+    double acc = 0.0;
+    for (int a = -R; a <= R; ++a) {
+        const int ii = gi + a;
+        if (ii < 0 || ii >= S.h) continue;
+        double row = 0.0;
+        for (int b = -R; b <= R; ++b) {
+            const int jj = gj + b;
+            if (jj < 0 || jj >= S.w) continue;
+            row += S.g[b + R] * x[ii * S.w + jj];
+        }
+        acc += S.g[a + R] * row;
+    }
+    y[i] = acc + noise * e[i];
+}
+
+// ------------------------------------------------------------------ launchers
+// Dynamic LDS above 64 KiB (large blur radii) must be enabled per kernel.
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static inline dim3 tiles_grid(const Stencil& S, int ncols) { return dim3(S.tiles_x * S.tiles_y, ncols); }
+
+hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
+                      hipStream_t st) {
+    const size_t lds = fp32 ? tile_lds_bytes<float>(S.R, S.reg, S.fs) : tile_lds_bytes<double>(S.R, S.reg, S.fs);
+    if (fp32) {
+        allow_lds(k_hvp<float>, lds);
+        hipLaunchKernelGGL(k_hvp<float>, tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out);
+    } else {
+        allow_lds(k_hvp<double>, lds);
+        hipLaunchKernelGGL(k_hvp<double>, tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_apply(const Stencil& S, bool fp32, const double* xhat, const double* r, const double* p_old,
+                           double* p_new, double* q, const double* C, double* V, SolveState* st, double* part,
+                           unsigned* counter, hipStream_t stream) {
+    const size_t lds = fp32 ? tile_lds_bytes<float>(S.R, S.reg, S.fs) : tile_lds_bytes<double>(S.R, S.reg, S.fs);
+    if (fp32) {
+        allow_lds(k_cg_apply<float>, lds);
+        hipLaunchKernelGGL(k_cg_apply<float>, tiles_grid(S, 1), dim3(NT), lds, stream, S, xhat, r, p_old, p_new, q, C,
+                           V, st, part, counter);
+    } else {
+        allow_lds(k_cg_apply<double>, lds);
+        hipLaunchKernelGGL(k_cg_apply<double>, tiles_grid(S, 1), dim3(NT), lds, stream, S, xhat, r, p_old, p_new, q,
+                           C, V, st, part, counter);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const Stencil& S, const double* xhat, const double* w, const double* g, double* out,
+                           const double* C, SolveState* st, double* part, unsigned* counter, hipStream_t stream) {
+    allow_lds(k_residual<double>, tile_lds_bytes<double>(S.R, S.reg, S.fs));
+    hipLaunchKernelGGL(k_residual<double>, tiles_grid(S, 1), dim3(NT), tile_lds_bytes<double>(S.R, S.reg, S.fs),
+                       stream, S, xhat, w, g, out, C, st, part, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_state(const Stencil& S, const double* xhat, double* d1, double* d2, float* d2f,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(k_filter_state, dim3((S.n + NT - 1) / NT, S.nf), dim3(NT), 0, stream, S, xhat, d1, d2, d2f);
+    return hipGetLastError();
+}
+
+int jac_blocks(const Stencil& S) {
+    if (S.reg == BL_REG_TV) return (S.n + NT * 8 - 1) / (NT * 8) < 256 ? (S.n + NT * 8 - 1) / (NT * 8) : 256;
+    const int ntiles = S.tiles_x * S.tiles_y;
+    return ntiles < JF_BLOCKS ? ntiles : JF_BLOCKS;
+}
+
+hipError_t launch_jac(const Stencil& S, const double* xhat, const double* w, int ncols, const double* d1,
+                      const double* d2, double* part, double* G, int project, hipStream_t stream) {
+    const int nb = jac_blocks(S);
+    int p;
+    if (S.reg == BL_REG_TV) {
+        p = 2;
+        hipLaunchKernelGGL(k_jac_tv, dim3(nb, ncols), dim3(NT), 0, stream, S, xhat, w, part);
+    } else {
+        p = S.nf * (1 + S.fs * S.fs);
+        hipLaunchKernelGGL(k_jac_filters, dim3(nb, ncols), dim3(NT), 0, stream, S, xhat, w, d1, d2, part);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int fs2 = S.reg == BL_REG_TV ? 0 : S.fs * S.fs;
+    hipLaunchKernelGGL(k_jac_reduce, dim3(ncols), dim3(NT), p * sizeof(double), stream, part, nb, p, ncols, G, project,
+                       fs2);
+    return hipGetLastError();
+}
+
+hipError_t launch_lower_grad(const Stencil& S, const double* x, const double* y, double* grad, double* part,
+                             unsigned* counter, double* st_out, hipStream_t stream) {
+    allow_lds(k_lower_grad, tile_lds_bytes<double>(S.R, S.reg, S.fs));
+    hipLaunchKernelGGL(k_lower_grad, tiles_grid(S, 1), dim3(NT), tile_lds_bytes<double>(S.R, S.reg, S.fs), stream, S,
+                       x, y, grad, part, counter, st_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const Stencil& S, const double* x, const double* e, double noise, double* y,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_forward, dim3((S.n + NT - 1) / NT), dim3(NT), 0, stream, S, x, e, noise, y);
+    return hipGetLastError();
+}
+
+}  // namespace bl

@@ -1,0 +1,57 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared entry point,
+and answers the calls that need no GPU (sizes, parameter counts, status strings,
+argument validation before any launch)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bilevel.h")
+LIB = os.path.join(ROOT, "paper_2412_08264_amd", "libbilevel_hip.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:bl_status|size_t|int|const char\*)\s+(bl_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_2412_08264_amd import bilevel as B
+    names = declared_symbols()
+    assert len(names) >= 14
+    raw = C.CDLL(LIB)
+    for name in names:
+        assert hasattr(raw, name), name
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_sizes_and_counts():
+    from paper_2412_08264_amd import bilevel as B
+    import synth
+    P = B.problem_from(synth.WORKLOADS["tv256"])
+    assert B.bl_num_params(P) == 2
+    nb = B.bl_workspace_bytes(P, 20, 64)
+    assert nb > 65536 * 8 * 2 * 84
+    Pf = B.problem_from(synth.WORKLOADS["foe512"])
+    assert B.bl_num_params(Pf) == 400
+    assert B.bl_workspace_bytes(Pf, 30, 64) > B.bl_workspace_bytes(Pf, 10, 16)
+    assert B.bl_workspace_bytes(P, 65, 10) == 0          # s_max above the compiled limit
+    assert B.bl_workspace_bytes(P, 20, 300) == 0         # refresh width above the limit
+
+
+def test_status_strings_and_null_context():
+    from paper_2412_08264_amd import bilevel as B
+    assert B.lib.bl_status_string(B.BL_E_INDEFINITE).decode().startswith("non-positive")
+    assert B.lib.bl_status_string(99).decode() == "unknown status"
+    P = B.bl_problem(8, 8, 1, 1.0, B.BL_REG_TV, 0, 0, 0.0, 0, 0)
+    opts = B.bl_solve_opts(0, 1e-10, 0.0, 10, 1, 0, 0)
+    st = B.bl_stats()
+    th = (C.c_double * 2)(0.0, 0.0)
+    # null context is rejected before anything touches a device
+    assert B.lib.bl_hessian_solve(None, C.byref(P), th, None, None, None, None, C.byref(opts), None, 0,
+                                  C.byref(st)) == B.BL_E_ARG
+    assert B.lib.bl_destroy(None) == B.BL_E_ARG

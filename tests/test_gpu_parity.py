@@ -1,0 +1,381 @@
+"""GPU parity: every call of the C ABI against the FP64 CPU oracle on identical seeded inputs.
+
+Tolerances (FP64 mode): stencil outputs (HVP, gradients, J) 1e-13 relative; Krylov iterates
+compared at the same iteration count 1e-10 relative; refresh: generalized singular values
+1e-10 relative, selected subspaces 1e-8 radians.  Mixed mode (FP32 stencils): HVP 1e-6,
+converged solution and hypergradient 1e-6 against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov, lbfgs, problem, recycle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_08264_amd import bilevel
+    return bilevel
+
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def tv_case(h, w, seed=21, r=2, sigma=1.5, noise_x=0.05):
+    wl = synth.custom("t", h, "tv", 8, width=w, blur_radius=r, blur_sigma=sigma, rect_min=2, rect_max=6, seed=seed)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xh = inst["xstar"].ravel() + noise_x * synth.unit_noise(prob.n, seed + 1)
+    return wl, inst, prob, xh
+
+
+def foe_case(h, w, seed=31, noise_x=0.02):
+    wl = synth.custom("f", h, "filters", 8, width=w, rect_min=2, rect_max=6, seed=seed)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xh = inst["xstar"].ravel() + noise_x * synth.unit_noise(prob.n, seed + 1)
+    return wl, inst, prob, xh
+
+
+# ------------------------------------------------------------------ stencils
+@pytest.mark.parametrize("shape,r", [((37, 75), 2), ((256, 256), 4), ((5, 3), 1)])
+def test_hvp_tv(B, shape, r):
+    wl, inst, prob, xh = tv_case(*shape, r=r, sigma=1.5 + 0.25 * r)
+    th = inst["theta0"]
+    V = synth.unit_noise((3, prob.n), 5)
+    ref = np.stack([prob.hvp(xh, th, V[k]) for k in range(3)])
+    with B.Session(B.problem_from(wl)) as S:
+        out = torch.empty((3, prob.n), dtype=torch.float64, device=DEV)
+        S.hvp(th, dev(xh), dev(V), out, ncols=3)
+        assert rel(host(out), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(48, 70), (512, 512)])
+def test_hvp_filters_fp64_and_mixed(B, shape):
+    wl, inst, prob, xh = foe_case(*shape)
+    th = inst["theta0"]
+    v = synth.unit_noise(prob.n, 6)
+    ref = prob.hvp(xh, th, v)
+    with B.Session(B.problem_from(wl, prec="fp64")) as S:
+        out = torch.empty(prob.n, dtype=torch.float64, device=DEV)
+        S.hvp(th, dev(xh), dev(v), out)
+        assert rel(host(out), ref) <= 1e-13
+    with B.Session(B.problem_from(wl, prec="mixed")) as S:
+        out = torch.empty(prob.n, dtype=torch.float64, device=DEV)
+        S.hvp(th, dev(xh), dev(v), out)
+        assert rel(host(out), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("kind", ["tv", "filters"])
+def test_lower_gradient_and_objective(B, kind):
+    wl, inst, prob, xh = tv_case(40, 33) if kind == "tv" else foe_case(40, 33)
+    th = inst["theta0"]
+    y = prob.y.ravel()
+    with B.Session(B.problem_from(wl)) as S:
+        gd = torch.empty(prob.n, dtype=torch.float64, device=DEV)
+        phi = S.lower_grad(th, dev(y), dev(xh), gd)
+        assert rel(host(gd), prob.grad(xh, th)) <= 1e-13
+        assert abs(phi - prob.phi(xh, th)) <= 1e-13 * abs(prob.phi(xh, th))
+        # forward operator: y = A x* + noise e
+        yd = torch.empty(prob.n, dtype=torch.float64, device=DEV)
+        S.forward(dev(inst["xstar"]), dev(inst["e"]), wl.noise, yd)
+        assert rel(host(yd), y) <= 1e-14
+
+
+@pytest.mark.parametrize("kind", ["tv", "filters"])
+def test_hypergradient_map(B, kind):
+    wl, inst, prob, xh = tv_case(37, 41) if kind == "tv" else foe_case(37, 41)
+    th = inst["theta0"]
+    w = synth.unit_noise(prob.n, 7)
+    with B.Session(B.problem_from(wl)) as S:
+        hg = S.hypergradient(th, dev(xh), dev(w))
+        assert rel(hg, prob.jac_apply(xh, th, w)) <= 1e-12
+        if kind == "filters":
+            hg_np = S.hypergradient(th, dev(xh), dev(w), project=False)
+            assert rel(hg_np, prob.jac_apply(xh, th, w, project=False)) <= 1e-12
+
+
+# ------------------------------------------------------------------ Krylov
+def oracle_sensitivity(solve, g, seed=99):
+    """Change of the oracle's own iterate when g is perturbed by one ulp: the rounding
+    amplification of the Krylov map at this iteration count."""
+    gp = g * (1.0 + 2.0 ** -52 * synth.unit_noise(g.size, seed))
+    return rel(solve(gp), solve(g))
+
+
+def test_plain_cg_fixed_iterations_and_basis(B):
+    """Iterates agree to 1e-10 while CG keeps its vectors orthogonal (<= 25 steps here);
+    later the Krylov map amplifies rounding exponentially (the oracle's own one-ulp
+    sensitivity is measured and the GPU must stay within 100x of it)."""
+    wl, inst, prob, xh = tv_case(45, 70)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    w0 = 0.1 * synth.unit_noise(prob.n, 8)
+    hvp = lambda v: prob.hvp(xh, th, v)
+    for k in (1, 10, 25, 40):
+        ref = krylov.cg(hvp, g, w0, tol=0.0, max_iter=k, v_cap=16)
+        bound = 1e-10 if k <= 25 else max(1e-10, 100 * oracle_sensitivity(
+            lambda gg: krylov.cg(hvp, gg, w0, tol=0.0, max_iter=k)["w"], g))
+        with B.Session(B.problem_from(wl), s_max=4, v_cap=16) as S:
+            w = dev(w0)
+            st = S.solve(th, dev(xh), dev(g), w, tol=0.0, max_iter=k, allow=(B.BL_E_NOT_CONVERGED,))
+            assert st.status == B.BL_E_NOT_CONVERGED and st.iters == k
+            assert rel(host(w), ref["w"]) <= bound, (k, bound)
+            m = min(k, 16)
+            assert S.rs.v_cur == m
+            assert rel(host(S.V[:m]), ref["V"].T) <= (1e-10 if k <= 25 else 1e-8)
+            if k <= 25:
+                assert abs(st.res_norm - ref["res_norm"]) <= 1e-9 * ref["res_norm"]
+
+
+def test_plain_cg_converged(B):
+    wl, inst, prob, xh = tv_case(64, 64, seed=41)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    ref = krylov.cg(hvp, g, tol=1e-10)
+    with B.Session(B.problem_from(wl), s_max=4, v_cap=16) as S:
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        st = S.solve(th, dev(xh), dev(g), w, tol=1e-10)
+        assert abs(st.iters - ref["iters"]) <= max(2, ref["iters"] // 100)
+        wstar, _ = krylov.reference_solve(hvp, g)
+        assert rel(host(w), wstar) <= 1e-8
+        assert rel(host(w), ref["w"]) <= 1e-8
+
+
+def upload_recycle(S, rs):
+    s = rs["U"].shape[1]
+    S.U[:s] = dev(rs["U"].T)
+    S.Cm[:s] = dev(rs["C"].T)
+    S.Z[:s] = dev(rs["Z"].T)
+    S.mu[:s] = dev(rs["mu"])
+    S.rs.s_cur = s
+
+
+@pytest.mark.parametrize("stop", ["resid", "hgerr"])
+def test_recycled_cg_parity(B, stop):
+    wl, inst, prob, xh = tv_case(40, 52, seed=51)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    jac = lambda v: prob.jac_apply(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-8, v_cap=30)
+    th2 = th + 0.01
+    hvp2 = lambda v: prob.hvp(xh, th2, v)
+    # outer refresh: the recycle space is built with the Hessian of the system it serves
+    rs = recycle.refresh(hvp2, lambda v: prob.jac_apply(xh, th2, v), None, first["V"], s=8)
+    w0 = first["w"]
+    hg_tol = 1e-7 * np.linalg.norm(jac(first["w"]))
+    for k in (1, 7, 25):   # fixed iteration counts
+        ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k)
+        with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
+            upload_recycle(S, rs)
+            w = dev(w0)
+            S.solve(th2, dev(xh), dev(g), w, tol=0.0, max_iter=k, store_basis=False,
+                    allow=(B.BL_E_NOT_CONVERGED,))
+            assert rel(host(w), ref["w"]) <= 1e-10
+        if stop == "hgerr":
+            # the error estimate after k iterations
+            ref_e = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
+                                       stop="hgerr", hg_tol=0.0, record=True)
+            with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
+                upload_recycle(S, rs)
+                st = S.solve(th2, dev(xh), dev(g), dev(w0), tol=0.0, max_iter=k, stop="hgerr", hg_tol=0.0,
+                             store_basis=False, allow=(B.BL_E_NOT_CONVERGED,))
+                assert abs(st.est - ref_e["hist_nsc"][-1]) <= 1e-9 * ref_e["hist_nsc"][-1]
+    # converged: the stopping iteration of the estimate test is itself rounding-sensitive
+    # (the estimate is far from monotone), so the GPU must stop inside the spread of the
+    # oracle's own stopping iterations under one-ulp perturbations of g, and meet the test.
+    ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)
+    spread = [krylov.recycled_cg(hvp2, g * (1 + 2.0 ** -52 * synth.unit_noise(prob.n, 200 + k)), w0, rs["U"],
+                                 rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)["iters"]
+              for k in range(4)] + [ref["iters"]]
+    wstar, _ = krylov.reference_solve(hvp2, g)
+    with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
+        upload_recycle(S, rs)
+        w = dev(w0)
+        st = S.solve(th2, dev(xh), dev(g), w, tol=1e-10, stop=stop, hg_tol=hg_tol, store_basis=False)
+        lo, hi = min(spread), max(spread)
+        assert lo - max(2, hi - lo) <= st.iters <= hi + max(2, hi - lo), (st.iters, spread)
+        if stop == "hgerr":
+            assert st.est <= hg_tol
+            hg_gpu = prob.jac_apply(xh, th2, host(w))
+            hg_ora = prob.jac_apply(xh, th2, ref["w"])
+            hg_star = prob.jac_apply(xh, th2, wstar)
+            # same quality of hypergradient as the oracle's own run (within a factor 10)
+            assert rel(hg_gpu, hg_star) <= 10 * rel(hg_ora, hg_star) + 1e-12
+        else:
+            assert rel(host(w), wstar) <= 1e-8
+
+
+def test_refresh_parity(B):
+    wl, inst, prob, xh = tv_case(48, 40, seed=61)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    jac = lambda v: prob.jac_apply(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-8, v_cap=24)
+    rs0 = recycle.refresh(hvp, jac, None, first["V"], s=6)
+    # second refresh from [U, V] at a new theta
+    th2 = th + np.array([0.05, -0.03])
+    hvp2 = lambda v: prob.hvp(xh, th2, v)
+    jac2 = lambda v: prob.jac_apply(xh, th2, v)
+    second = krylov.recycled_cg(hvp2, g, first["w"], rs0["U"], rs0["C"], tol=1e-8, v_cap=24)
+    ref = recycle.refresh(hvp2, jac2, rs0["U"], second["V"], s=6)
+    with B.Session(B.problem_from(wl), s_max=6, v_cap=24) as S:
+        upload_recycle(S, rs0)
+        m = second["V"].shape[1]
+        S.V[:m] = dev(second["V"].T)
+        S.rs.v_cur = m
+        st = S.refresh(th2, dev(xh), s=6)
+        assert S.rs.s_cur == 6 and st.t == ref["t"]
+        mu = host(S.mu[:6])
+        assert np.abs(mu[:2] - ref["mu"][:2]).max() <= 1e-10 * ref["mu"][0]
+        assert np.all(mu[2:] == 0.0)
+        U = host(S.U[:6]).T
+        C = host(S.Cm[:6]).T
+        assert recycle.principal_angles(U, ref["U"]).max() <= 1e-8
+        assert np.abs(C.T @ C - np.eye(6)).max() <= 1e-13
+        HU = np.stack([hvp2(U[:, j]) for j in range(6)], axis=1)
+        assert np.linalg.norm(HU - C) <= 1e-11 * np.linalg.norm(C)
+        # GSV part of the error-estimate space
+        Z = host(S.Z[:6]).T
+        assert recycle.principal_angles(Z[:, :2], ref["Z"][:, :2]).max() <= 1e-8
+
+
+def test_refresh_parity_filters(B):
+    wl, inst, prob, xh = foe_case(40, 44, seed=71)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    jac = lambda v: prob.jac_apply(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-8, v_cap=20)
+    assert first["status"] == krylov.OK
+    ref = recycle.refresh(hvp, jac, None, first["V"], s=8)
+    with B.Session(B.problem_from(wl, prec="fp64"), s_max=8, v_cap=20) as S:
+        m = first["V"].shape[1]
+        S.V[:m] = dev(first["V"].T)
+        S.rs.v_cur = m
+        S.refresh(th, dev(xh), s=8)
+        mu = host(S.mu[:8])
+        assert np.abs(mu - ref["mu"]).max() <= 1e-10 * ref["mu"][0]
+        U = host(S.U[:8]).T
+        assert recycle.principal_angles(U, ref["U"]).max() <= 1e-8
+
+
+def test_sequence_tv32(B):
+    """Full GPU pipeline (refresh + recycled solve + hypergradient) on the 32x32 TV trajectory."""
+    from oracle import upper
+    wl = synth.WORKLOADS["tv32"]
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    thetas, xhats = upper.trajectory(prob, inst["xstar"], inst["theta0"], 6)
+    xs = inst["xstar"].ravel()
+    ref = upper.solve_sequence(prob, thetas, xhats, xs, s=wl.s, tol=wl.tol)
+    refs = [upper.hypergradient(prob, x, t, xs)[0] for t, x in zip(thetas, xhats)]
+    with B.Session(B.problem_from(wl), s_max=wl.s, v_cap=64) as S:
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        for i, (t, x) in enumerate(zip(thetas, xhats)):
+            xd, gd = dev(x), dev(x - xs)
+            if i:
+                S.refresh(t, xd, s=wl.s)
+            st = S.solve(t, xd, gd, w, tol=wl.tol)
+            hg = S.hypergradient(t, xd, w)
+            assert abs(st.iters - ref[i]["iters"]) <= 2
+            assert rel(hg, refs[i]) <= 1e-8
+            assert rel(hg, ref[i]["hg"]) <= 1e-8
+
+
+def test_lower_solve(B):
+    wl, inst, prob, xh = tv_case(24, 24, seed=81)
+    th = inst["theta0"]
+    y = prob.y.ravel()
+    xo, info = lbfgs.lbfgs(lambda v: prob.phi(v, th), lambda v: prob.grad(v, th), y, gtol=1e-8)
+    with B.Session(B.problem_from(wl)) as S:
+        x = dev(y)
+        st = S.lower_solve(th, dev(y), x, gtol=1e-8)
+        assert st.status == 0
+        assert np.linalg.norm(prob.grad(host(x), th)) <= 1.5e-8
+        assert rel(host(x), xo) <= 1e-6
+
+
+def test_mixed_precision_solve_filters(B):
+    wl, inst, prob, _ = foe_case(64, 64, seed=91)
+    th = inst["theta0"]
+    xo, _ = lbfgs.lbfgs(lambda v: prob.phi(v, th), lambda v: prob.grad(v, th), prob.y.ravel(), gtol=1e-7)
+    g = xo - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xo, th, v)
+    wref, _ = krylov.reference_solve(hvp, g)
+    hgref = prob.jac_apply(xo, th, wref)
+    with B.Session(B.problem_from(wl, prec="mixed"), s_max=8, v_cap=16) as S:
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        st = S.solve(th, dev(xo), dev(g), w, tol=1e-10, rr_every=25)
+        assert st.status == 0
+        assert rel(host(w), wref) <= 1e-6
+        assert rel(S.hypergradient(th, dev(xo), w), hgref) <= 1e-6
+
+
+# ------------------------------------------------------------------ edge cases
+def test_edge_cases(B):
+    wl, inst, prob, xh = tv_case(20, 21, seed=101)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    with B.Session(B.problem_from(wl), s_max=4, v_cap=8) as S:
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        st = S.solve(th, dev(xh), dev(g), w, max_iter=0, allow=(B.BL_E_NOT_CONVERGED,))
+        assert st.iters == 0 and st.status == B.BL_E_NOT_CONVERGED and float(w.abs().max()) == 0.0
+        # zero right-hand side converges at once
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        st = S.solve(th, dev(xh), torch.zeros_like(w), w)
+        assert st.iters == 0 and st.status == 0
+        # NaN in g is reported, not iterated on
+        gn = g.copy()
+        gn[3] = np.nan
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        st = S.solve(th, dev(xh), dev(gn), w, allow=(B.BL_E_NONFINITE,))
+        assert st.status == B.BL_E_NONFINITE
+        # refresh with nothing stored leaves the recycle space empty
+        S.reset()
+        S.refresh(th, dev(xh), s=4)
+        assert S.rs.s_cur == 0
+        # argument checks
+        with pytest.raises(B.BLError):
+            S.solve(th, dev(xh), dev(g), w, check_every=0)
+        with pytest.raises(B.BLError):
+            S.refresh(th, dev(xh), s=5)
+
+
+def test_indefinite_detected_like_oracle(B):
+    """Filters at a point with large responses: phi'' < 0 makes H indefinite; both report it."""
+    wl, inst, prob, _ = foe_case(24, 24, seed=111)
+    th = inst["theta0"].copy()
+    f2 = 49
+    for j in range(8):
+        th[j * (1 + f2)] = np.log(50.0)
+    x = 8.0 * synth.unit_noise(prob.n, 112)
+    g = synth.unit_noise(prob.n, 113)
+    ref = krylov.cg(lambda v: prob.hvp(x, th, v), g, tol=1e-12, max_iter=500)
+    assert ref["status"] == krylov.INDEFINITE
+    with B.Session(B.problem_from(wl, prec="fp64"), s_max=2, v_cap=4) as S:
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        st = S.solve(th, dev(x), dev(g), w, tol=1e-12, max_iter=500, allow=(B.BL_E_INDEFINITE,))
+        assert st.status == B.BL_E_INDEFINITE
+        assert abs(st.iters - ref["iters"]) <= 1
