@@ -51,6 +51,7 @@ def make_trajectory(S, B, wl, torch, y, xs, outer, gtol=1e-8):
     beta = 1.0
     thetas, xhats = [], []
     w = torch.zeros_like(x)
+    nl = []
     for i in range(outer):
         thetas.append(th.copy())
         xhats.append(x.clone())
@@ -67,13 +68,16 @@ def make_trajectory(S, B, wl, torch, y, xs, outer, gtol=1e-8):
             tau = beta * 0.5 ** (j - 1)
             thj = th + tau * d
             xj = xprev.clone()
-            S.lower_solve(thj, y, xj, gtol=gtol)
+            lst = S.lower_solve(thj, y, xj, gtol=gtol)
+            nl.append(lst.iters)
             c0 = upper_loss(xj, xs)
             if c0 <= c1 + 1e-4 * tau * c2:
                 th, x, c1, beta = thj, xj, c0, 2.0 * tau
                 break
             xprev = xj
-        log(f"  trajectory step {i + 1}/{outer}: loss {c1:.6e} theta {np.round(th, 4).tolist()}")
+        log(f"  trajectory step {i + 1}/{outer}: loss {c1:.6e} theta {np.round(th, 4).tolist()} "
+            f"L-BFGS iterations {nl}")
+        nl.clear()
     return thetas, xhats
 
 

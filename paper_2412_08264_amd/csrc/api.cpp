@@ -20,6 +20,8 @@ struct bl_ctx {
     SolveState* h_state = nullptr;   // pinned
     double* h_buf = nullptr;         // pinned staging (>= 4096 doubles)
     int* h_info = nullptr;           // pinned
+    SolveState* h_hdr = nullptr;     // pinned: two slots for the scalar header of in-flight chunks
+    hipEvent_t poll_ev[2] = {};
     hipEvent_t ev[6] = {};
     std::vector<hipEvent_t> kev;     // per-launch events (timing mode 2)
     double kt[4] = {0.0, 0.0, 0.0, 0.0};
@@ -57,7 +59,7 @@ bl_status check_problem(bl_ctx* c, const bl_problem* P) {
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, counters, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -71,15 +73,14 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.t_max = s_max + v_cap;
     L.nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
     const int tiles = ((P->w + TW - 1) / TW) * ((P->h + TH - 1) / TH);
-    size_t pd = (size_t)std::max(tiles, RED_BLOCKS) * (size_t)NV_RED;
+    size_t pd = (size_t)std::max(tiles, (L.n + NT - 1) / NT) * (size_t)NV_RED;
     pd = std::max(pd, (size_t)gram_chunks(L.n) * L.t_max * L.t_max);
     pd = std::max(pd, (size_t)256 * L.t_max * std::max(L.p, 2));
     pd = std::max(pd, (size_t)RED_BLOCKS * 4);
     L.part_doubles = pd;
     size_t o = 0;
     L.state = o;    o += al(sizeof(SolveState));
-    L.counters = o; o += al(64 * sizeof(unsigned));
-    L.part = o;     o += al(pd * sizeof(double));
+    L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
     L.taps = o;     o += al((size_t)(MAX_NF * MAX_FS * MAX_FS + MAX_NF + 16) * sizeof(double));
@@ -91,7 +92,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.small = o;
     o += al((6 * T2 + (size_t)L.p * L.t_max + 2 * (size_t)L.t_max * std::max(s_max, 1) + 256 +
              gsvd_scratch_doubles(L.t_max, L.p)) * sizeof(double) + 4 * L.t_max * sizeof(int));
-    L.lb = o;       o += al(((size_t)2 * (LBFGS_MMAX + 1) * L.n + 4 * LBFGS_MMAX + 64) * sizeof(double));
+    L.lb = o;       o += al(((size_t)2 * (LBFGS_MMAX + 1) * L.n + (size_t)(LBFGS_MMAX + 6) * 1024 + 64) * sizeof(double));
     L.total = o;
     return L;
 }
@@ -100,8 +101,10 @@ struct WS {
     Layout L;
     char* base;
     SolveState* st() const { return (SolveState*)(base + L.state); }
-    unsigned* ctr(int k) const { return (unsigned*)(base + L.counters) + k; }
     double* part() const { return (double*)(base + L.part); }
+    double* part_res() const { return part(); }
+    double* part_app() const { return part() + L.part_doubles; }
+    double* part_upd() const { return part() + 2 * L.part_doubles; }
     double* vec(int k) const { return (double*)(base + L.vec) + (size_t)k * L.n; }
     double* d1() const { return (double*)(base + L.maps); }
     double* d2() const { return d1() + (size_t)L.nf * L.n; }
@@ -184,11 +187,6 @@ bl_status filter_state(bl_ctx* c, const Stencil& S, const double* xhat, const WS
     return BL_OK;
 }
 
-bl_status clear_counters(bl_ctx* c, const WS& ws) {
-    HIPCHK(hipMemsetAsync(ws.ctr(0), 0, 64 * sizeof(unsigned), c->stream));
-    return BL_OK;
-}
-
 void mark(bl_ctx* c, int k) {
     if (c->timing) hipEventRecord(c->ev[k], c->stream);
 }
@@ -215,12 +213,15 @@ bl_status bl_create(bl_ctx** ctx, void* hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     if (hipHostMalloc((void**)&c->h_state, sizeof(SolveState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_buf, 8192 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_info, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_info, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_hdr, 2 * sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return BL_E_HIP;
     }
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return BL_E_HIP;
+    for (auto& e : c->poll_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return BL_E_HIP;
     *ctx = c;
     return BL_OK;
 }
@@ -231,6 +232,9 @@ bl_status bl_destroy(bl_ctx* c) {
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
     for (auto& e : c->kev) hipEventDestroy(e);
+    for (auto& e : c->poll_ev)
+        if (e) hipEventDestroy(e);
+    if (c->h_hdr) hipHostFree(c->h_hdr);
     if (c->h_state) hipHostFree(c->h_state);
     if (c->h_buf) hipHostFree(c->h_buf);
     if (c->h_info) hipHostFree(c->h_info);
@@ -316,9 +320,9 @@ bl_status bl_lower_grad(bl_ctx* c, const bl_problem* P, const double* theta, con
     TRY(check_ws(c, layout(P, 0, 0), wsp, ws_bytes, ws));
     Stencil S;
     TRY(make_stencil(c, P, theta, ws, S));
-    TRY(clear_counters(c, ws));
-    double* out = ws.lb() + 2 * (LBFGS_MMAX + 1) * (size_t)ws.L.n + 4 * LBFGS_MMAX;
-    HIPCHK(launch_lower_grad(S, x, y, grad, ws.part(), ws.ctr(0), out, c->stream));
+    double* out = ws.vec(8);
+    HIPCHK(launch_lower_grad(S, x, y, grad, ws.part(), c->stream));
+    HIPCHK(launch_finish_sum(ws.part(), tiles_of(S), 2, out, c->stream));
     if (phi_host) {
         HIPCHK(hipMemcpyAsync(c->h_buf, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -367,7 +371,6 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
     SolveState* st = ws.st();
     HIPCHK(hipMemcpyAsync(st, hs, sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
     if (s > 0) HIPCHK(hipMemcpyAsync(st->mu, rs->mu, s * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    TRY(clear_counters(c, ws));
     const double* U = s ? rs->U : nullptr;
     const double* C = s ? rs->C : nullptr;
     const double* Z = hg ? rs->Z : nullptr;
@@ -376,47 +379,81 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
     double* pb[2] = {ws.vec(1), ws.vec(2)};
     double* q = ws.vec(3);
     const bool fp32 = P->prec == BL_PREC_MIXED;
-    // r = g - H w0 (FP64), c0 = C^T r;  w += U c0;  r -= C c0;  stop test at j = 0
-    HIPCHK(launch_residual(S, xhat, w, g, r, C, st, ws.part(), ws.ctr(0), c->stream));
-    HIPCHK(launch_cg_init(n, w, r, U, C, Z, st, ws.part(), ws.ctr(1), c->stream));
+    const int tiles = tiles_of(S), nb1 = red_blocks(n);
+    double* prs = ws.part_res();
+    double* pap = ws.part_app();
+    double* pup = ws.part_upd();
+    // r = g - H w0 (FP64) with record [g.g, C^T r];  w += U c0;  r -= C c0
+    HIPCHK(launch_residual(S, xhat, w, g, r, C, s, prs, c->stream));
+    HIPCHK(launch_cg_init(n, w, r, U, C, Z, st, prs, tiles, pup, c->stream));
     mark(c, 1);
     const int rr_every = fp32 ? o->rr_every : 0;
     const bool ktime = c->timing == 2;
     std::vector<int> launched;   // iteration index of each timed launch triple
+    // Iteration j = apply(j) [stop test on r_j, p, q = H p] + update(j) [alpha, w, r].  The
+    // last index j = max_iter launches apply only: it tests r_max_iter.
     int j = 0;
-    bool done = false;
-    while (!done) {
-        const int chunk = rr_every ? std::min(POLL, rr_every - (j % rr_every)) : POLL;
-        for (int k = 0; k < chunk && j < o->max_iter; ++k, ++j) {
-            if (ktime) {
-                const size_t need = 3 * (launched.size() + 1);
-                while (c->kev.size() < need) {
-                    hipEvent_t e;
-                    HIPCHK(hipEventCreate(&e));
-                    c->kev.push_back(e);
-                }
-                HIPCHK(hipEventRecord(c->kev[3 * launched.size()], c->stream));
+    auto launch_iter = [&]() -> bl_status {
+        if (ktime) {
+            const size_t need = 3 * (launched.size() + 1);
+            while (c->kev.size() < need) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                c->kev.push_back(e);
             }
-            HIPCHK(launch_cg_apply(S, fp32, xhat, r, pb[j & 1], pb[(j + 1) & 1], q, C, V, st, ws.part(), ws.ctr(2),
-                                   c->stream));
-            if (ktime) HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 1], c->stream));
-            HIPCHK(launch_cg_update(n, w, r, pb[(j + 1) & 1], q, C, Z, st, ws.part(), ws.ctr(3), c->stream));
-            if (ktime) {
-                HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 2], c->stream));
-                launched.push_back(j);
-            }
+            HIPCHK(hipEventRecord(c->kev[3 * launched.size()], c->stream));
         }
-        HIPCHK(hipMemcpyAsync(hs, st, offsetof(SolveState, e), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        done = hs->done != 0 || j >= o->max_iter;
-        const bool at_rr = rr_every && (j % rr_every == 0 || (hs->done && hs->status == BL_OK));
-        if (at_rr && (hs->status == BL_OK)) {
-            // residual replacement in FP64: r = g - H w, z = C^T r, r -= C z; re-test
-            HIPCHK(launch_residual(S, xhat, w, g, r, C, st, ws.part(), ws.ctr(0), c->stream));
-            HIPCHK(launch_cg_replace(n, r, C, Z, st, ws.part(), ws.ctr(4), c->stream));
-            HIPCHK(hipMemcpyAsync(hs, st, offsetof(SolveState, e), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(launch_cg_apply(S, fp32, j, xhat, r, pb[j & 1], pb[(j + 1) & 1], q, C, V, st, pup, nb1, pap,
+                               c->stream));
+        if (ktime) HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 1], c->stream));
+        if (j < o->max_iter)
+            HIPCHK(launch_cg_update(n, j, w, r, pb[(j + 1) & 1], q, C, Z, st, pap, tiles, pup, c->stream));
+        if (ktime) {
+            HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 2], c->stream));
+            launched.push_back(j);
+        }
+        ++j;
+        return BL_OK;
+    };
+    const size_t hdr = offsetof(SolveState, e);
+    if (!rr_every) {
+        // Chunks of POLL iterations; the next chunk is enqueued before the host waits for the
+        // stop flag of the previous one, so the device never idles on a poll.  Iterations
+        // launched after the stop exit at once (the kernels test the device flag).
+        auto enqueue = [&](int chunk) -> bl_status {
+            for (int k = 0; k < POLL && j <= o->max_iter; ++k) TRY(launch_iter());
+            HIPCHK(hipMemcpyAsync(&c->h_hdr[chunk & 1], st, hdr, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipEventRecord(c->poll_ev[chunk & 1], c->stream));
+            return BL_OK;
+        };
+        int chunk = 0;
+        TRY(enqueue(0));
+        for (;;) {
+            const bool more = j <= o->max_iter;
+            if (more) TRY(enqueue(chunk + 1));
+            HIPCHK(hipEventSynchronize(c->poll_ev[chunk & 1]));
+            if (c->h_hdr[chunk & 1].done || !more) break;
+            ++chunk;
+        }
+    } else {
+        for (;;) {
+            const int chunk = std::min(POLL, rr_every - (j % rr_every));
+            for (int k = 0; k < chunk && j <= o->max_iter; ++k) TRY(launch_iter());
+            HIPCHK(hipMemcpyAsync(hs, st, hdr, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            done = hs->done != 0 || j >= o->max_iter;
+            const bool converged = hs->done && hs->status == BL_OK;
+            if (hs->done && !converged) break;
+            if (!converged && j % rr_every != 0 && j <= o->max_iter) continue;
+            if (!converged && j > o->max_iter) break;
+            // residual replacement in FP64: r = g - H w, z = C^T r, r -= C z; the apply step
+            // of the current index re-tests (and goes on if the true residual misses the test)
+            if (converged) j = hs->iters;
+            HIPCHK(launch_residual(S, xhat, w, g, r, C, s, prs, c->stream));
+            HIPCHK(launch_cg_replace(n, r, C, Z, st, prs, tiles, pup, c->stream));
+            TRY(launch_iter());
+            HIPCHK(hipMemcpyAsync(hs, st, hdr, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (hs->done || j > o->max_iter) break;
         }
     }
     mark(c, 2);
@@ -446,7 +483,7 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
         out->status = status;
         out->t = 0;
         out->s_cur = s;
-        out->res_norm = std::sqrt(std::max(hs->rho, 0.0));
+        out->res_norm = std::sqrt(std::max(hs->rho2[hs->iters & 1], 0.0));
         out->res0_norm = hs->res0;
         out->g_norm = hs->gnorm;
         out->est = hs->est;
@@ -614,6 +651,7 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
     Stencil S;
     TRY(make_stencil(c, P, theta, ws, S));
     const int n = P->h * P->w;
+    const int vb = vec_blocks(n);
     double* g = ws.vec(0);
     double* d = ws.vec(1);
     double* xt = ws.vec(2);
@@ -621,11 +659,14 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
     double* qv = ws.vec(4);
     double* Sh = ws.lb();
     double* Yh = Sh + (size_t)(LBFGS_MMAX + 1) * n;
-    double* dsc = Yh + (size_t)(LBFGS_MMAX + 1) * n;   // device scalars (see below)
-    double* fout = dsc + 4 * LBFGS_MMAX;               // [0] phi, [1] ||g||^2
-    TRY(clear_counters(c, ws));
+    double* dq_rec = Yh + (size_t)(LBFGS_MMAX + 1) * n;   // records of s_k . q, one per slot
+    double* dr_rec = dq_rec + (size_t)(LBFGS_MMAX + 1) * vb;
+    double* d3_rec = dr_rec + vb;                           // [s.y, s.s, y.y] records
+    double* sl_rec = d3_rec + 3 * (size_t)vb;               // g . d records
+    double* fout = sl_rec + vb;                             // host-bound scalars
     auto grad_at = [&](const double* xx, double* gg, double& f, double& gn2) -> bl_status {
-        HIPCHK(launch_lower_grad(S, xx, y, gg, ws.part(), ws.ctr(0), fout, c->stream));
+        HIPCHK(launch_lower_grad(S, xx, y, gg, ws.part(), c->stream));
+        HIPCHK(launch_finish_sum(ws.part(), tiles_of(S), 2, fout, c->stream));
         HIPCHK(hipMemcpyAsync(c->h_buf, fout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         f = c->h_buf[0];
@@ -638,34 +679,33 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
     std::vector<int> slot;   // history slots in use, oldest first
     std::vector<int> free_slots;
     for (int k = m; k >= 0; --k) free_slots.push_back(k);   // m + 1 buffers: a new pair never overwrites a kept one
-    double* dq = dsc;                  // s_k . q   (loop 1), one per slot
-    double* dr = dsc + LBFGS_MMAX + 1; // y_k . d   (loop 2)
-    double* d3 = dsc + 2 * (LBFGS_MMAX + 1);   // [s.y, s.s, y.y] of the new pair, then g.d
     int it = 0;
     double gnorm = std::sqrt(gn2);
     double gamma = 0.0;
     while (gnorm > gtol && it < max_iter) {
         if (!std::isfinite(f) || !std::isfinite(gnorm)) return c->err = "non-finite objective", BL_E_NONFINITE;
-        // two-loop recursion, coefficients kept on the device: q = g; d = H_k q
+        // two-loop recursion with the coefficients kept on the device: q = g, d = H_k q
         HIPCHK(hipMemcpyAsync(qv, g, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         const int hsz = (int)slot.size();
         for (int k = hsz - 1; k >= 0; --k) {
             const double* sk = Sh + (size_t)slot[k] * n;
             const double* yk = Yh + (size_t)slot[k] * n;
-            HIPCHK(launch_dot_to(n, sk, qv, ws.part(), ws.ctr(1), dq + slot[k], c->stream));
-            HIPCHK(launch_axpy2(n, 1.0, qv, yk, dq + slot[k], -rho[k], nullptr, 0.0, c->stream));
+            double* rec = dq_rec + (size_t)slot[k] * vb;
+            HIPCHK(launch_dots_part(n, 1, sk, qv, rec, c->stream));
+            HIPCHK(launch_axpy_red(n, 1.0, qv, yk, rec, -rho[k], nullptr, 0.0, c->stream));
         }
         const double scale0 = hsz ? gamma : 1.0 / gnorm;
-        HIPCHK(launch_axpy2(n, 0.0, d, qv, nullptr, scale0, nullptr, 0.0, c->stream));
+        HIPCHK(launch_axpy_red(n, 0.0, d, qv, nullptr, scale0, nullptr, 0.0, c->stream));
         for (int k = 0; k < hsz; ++k) {
             const double* sk = Sh + (size_t)slot[k] * n;
             const double* yk = Yh + (size_t)slot[k] * n;
-            HIPCHK(launch_dot_to(n, yk, d, ws.part(), ws.ctr(1), dr + slot[k], c->stream));
-            HIPCHK(launch_axpy2(n, 1.0, d, sk, dq + slot[k], rho[k], dr + slot[k], -rho[k], c->stream));
+            HIPCHK(launch_dots_part(n, 1, yk, d, dr_rec, c->stream));
+            HIPCHK(launch_axpy_red(n, 1.0, d, sk, dq_rec + (size_t)slot[k] * vb, rho[k], dr_rec, -rho[k], c->stream));
         }
         // direction -d; slope = -(g . d)
-        HIPCHK(launch_dot_to(n, g, d, ws.part(), ws.ctr(1), d3 + 3, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_buf, d3 + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(launch_dots_part(n, 1, g, d, sl_rec, c->stream));
+        HIPCHK(launch_finish_sum(sl_rec, vb, 1, fout + 2, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_buf, fout + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         double slope = -c->h_buf[0];
         if (!(slope < 0.0)) {   // not a descent direction: steepest descent
@@ -677,7 +717,7 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
         bool ok = false;
         for (int bt = 0; bt < 60; ++bt) {
             HIPCHK(hipMemcpyAsync(xt, x, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(launch_axpy2(n, 1.0, xt, d, nullptr, -tstep, nullptr, 0.0, c->stream));
+            HIPCHK(launch_axpy_red(n, 1.0, xt, d, nullptr, -tstep, nullptr, 0.0, c->stream));
             TRY(grad_at(xt, gt, fn, gn2n));
             if (fn <= f + 1e-4 * tstep * slope) {
                 ok = true;
@@ -693,8 +733,9 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
         double* yv = Yh + (size_t)sl * n;
         HIPCHK(launch_sub(n, xt, x, sv, c->stream));
         HIPCHK(launch_sub(n, gt, g, yv, c->stream));
-        HIPCHK(launch_dots3(n, sv, yv, ws.part(), ws.ctr(1), d3, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_buf, d3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(launch_dots_part(n, 3, sv, yv, d3_rec, c->stream));
+        HIPCHK(launch_finish_sum(d3_rec, vb, 3, fout + 3, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_buf, fout + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(x, xt, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(g, gt, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

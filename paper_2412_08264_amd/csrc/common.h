@@ -37,9 +37,14 @@ struct Stencil {
     int tiles_x, tiles_y;
 };
 
-// Scalars of one Krylov solve, resident in device memory.
+// Scalars of one Krylov solve, resident in device memory.  Every block of a kernel
+// recomputes the scalars it needs from the previous kernel's partial records (same
+// data, same order: identical values in every block); block 0 stores them here.
+// Values rewritten during a kernel that other blocks of the same kernel read are
+// double-buffered by iteration parity (rho2).
 struct SolveState {
-    double rho, sigma, alpha, beta, gnorm, tol, hg_tol, res0, est, rho_true;
+    double rho2[2];     // rho_j = r_j . r_j, slot j & 1
+    double alpha, gnorm, tol, hg_tol, res0, est, pad0[3];
     int iters, done, status, max_iter, check_every, stop, s, v_cap, v_cur, store_basis, hgerr_on, pad;
     double e[S_MAX];      // C^T q of the current iteration
     double zr[S_MAX];     // Z^T r
@@ -69,33 +74,84 @@ __device__ __forceinline__ double block_sum(double val, double* red) {
     return s;
 }
 
-// After every block has written its partial record, exactly one block (the last to
-// arrive) returns true; its threads then see all records.  Release/acquire at device
-// scope makes the records visible across XCDs.  The counter is reset for reuse.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == nblocks - 1) ? 1 : 0;
-        if (s_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Block partial record of nv values (nv <= NV_RED): value k of this thread is val(k).
+// Each wavefront reduces with shuffles, one barrier, then threads k < nv add the NWAVE
+// wave sums in fixed order and write part[blockIdx.x * nv + k].
+template <typename Val>
+__device__ __forceinline__ void block_partials(double* part, int nv, Val val) {
+    __shared__ double wred[NWAVE][NV_RED];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < nv; ++k) {
+        const double v = wave_sum(val(k));
+        if (lane == 0) wred[wave][k] = v;
     }
     __syncthreads();
-    if (s_last) __threadfence();
-    return s_last != 0;
+    for (int k = threadIdx.x; k < nv; k += NT) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWAVE; ++w) s += wred[w][k];
+        part[(size_t)blockIdx.x * nv + k] = s;
+    }
 }
 
-// In the last block: out[k] = sum over blocks b (fixed order) of part[b*nv + k], k < nv.
-// Deterministic: thread t sums blocks t, t+NT, ... in order, then a fixed tree.
-__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv, double* out, double* red) {
-    for (int k = 0; k < nv; ++k) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += NT) acc += __builtin_nontemporal_load(&part[(size_t)b * nv + k]);
-        double s = block_sum(acc, red);
-        if (threadIdx.x == 0) out[k] = s;
+// out[k] = sum over blocks of part[b*nv + k], k < nv (nv <= NT), into LDS `out` (all threads).
+// G = NT / nv threads share value k; thread (k, j) sums blocks j, j+G, ... in order and
+// the G sums are added in fixed order: the result depends only on the records, so every
+// block that reduces the same records obtains bit-identical values.
+__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv, double* out) {
+    __shared__ double tmp[NT];
+    const int G = nv >= NT ? 1 : NT / nv;
+    const int k = threadIdx.x / G, j = threadIdx.x - k * G;
+    double acc = 0.0;
+    if (k < nv)
+        for (int b = j; b < nblocks; b += G) acc += part[(size_t)b * nv + k];
+    tmp[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double s = 0.0;
+        for (int q = 0; q < G; ++q) s += tmp[threadIdx.x * G + q];
+        out[threadIdx.x] = s;
     }
     __syncthreads();
+}
+
+// Stop decision after j completed iterations from the reduced residual record (r.r and,
+// with the error estimate, Z^T r).  Order of tests: non-finite; exact zero residual; only
+// every check_every iterations: the hypergradient-error estimate ||mu . Z^T r|| <= hg_tol
+// (when enabled) or ||r|| <= tol ||g||; then the iteration limit.
+struct Decision {
+    bool done;
+    int status;
+    double est;
+};
+
+__device__ __forceinline__ Decision decide(const SolveState* st, int j, double rho, const double* zr) {
+    Decision d{false, BL_OK, NAN};
+    if (st->hgerr_on) {
+        double acc = 0.0;
+        for (int k = 0; k < st->s; ++k) {
+            const double t = st->mu[k] * zr[k];
+            acc += t * t;
+        }
+        d.est = sqrt(acc);
+    }
+    if (!(rho == rho) || fabs(rho) == INFINITY) {
+        d.done = true;
+        d.status = BL_E_NONFINITE;
+        return d;
+    }
+    bool met;
+    if (rho == 0.0) met = true;
+    else if (j % st->check_every) met = false;
+    else if (st->stop == BL_STOP_HGERR && st->hgerr_on) met = d.est <= st->hg_tol;
+    else met = sqrt(rho) <= st->tol * st->gnorm;
+    if (met) {
+        d.done = true;
+    } else if (j >= st->max_iter) {
+        d.done = true;
+        d.status = BL_E_NOT_CONVERGED;
+    }
+    return d;
 }
 
 // Map a block index to a tile index so that each XCD (blocks are dealt round-robin over

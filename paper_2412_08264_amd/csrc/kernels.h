@@ -6,45 +6,40 @@
 namespace bl {
 
 // stencil.hip
+int tiles_of(const Stencil& S);
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
                       hipStream_t st);
-hipError_t launch_cg_apply(const Stencil& S, bool fp32, const double* xhat, const double* r, const double* p_old,
-                           double* p_new, double* q, const double* C, double* V, SolveState* st, double* part,
-                           unsigned* counter, hipStream_t stream);
+hipError_t launch_cg_apply(const Stencil& S, bool fp32, int j, const double* xhat, const double* r,
+                           const double* p_old, double* p_new, double* q, const double* C, double* V, SolveState* st,
+                           const double* upd_part, int upd_nb, double* app_part, hipStream_t stream);
 hipError_t launch_residual(const Stencil& S, const double* xhat, const double* w, const double* g, double* out,
-                           const double* C, SolveState* st, double* part, unsigned* counter, hipStream_t stream);
+                           const double* C, int s, double* res_part, hipStream_t stream);
 hipError_t launch_filter_state(const Stencil& S, const double* xhat, double* d1, double* d2, float* d2f,
                                hipStream_t stream);
 int jac_blocks(const Stencil& S);
 hipError_t launch_jac(const Stencil& S, const double* xhat, const double* w, int ncols, const double* d1,
                       const double* d2, double* part, double* G, int project, hipStream_t stream);
 hipError_t launch_lower_grad(const Stencil& S, const double* x, const double* y, double* grad, double* part,
-                             unsigned* counter, double* st_out, hipStream_t stream);
+                             hipStream_t stream);
 hipError_t launch_forward(const Stencil& S, const double* x, const double* e, double noise, double* y,
                           hipStream_t stream);
 
 // krylov.hip
 int red_blocks(int n);
+int vec_blocks(int n);
 hipError_t launch_cg_init(int n, double* w, double* r, const double* U, const double* C, const double* Z,
-                          SolveState* st, double* part, unsigned* counter, hipStream_t stream);
-hipError_t launch_cg_update(int n, double* w, double* r, const double* p, const double* q, const double* C,
-                            const double* Z, SolveState* st, double* part, unsigned* counter, hipStream_t stream);
-hipError_t launch_cg_replace(int n, double* r, const double* C, const double* Z, SolveState* st, double* part,
-                             unsigned* counter, hipStream_t stream);
+                          SolveState* st, const double* res_part, int res_nb, double* upd_part, hipStream_t stream);
+hipError_t launch_cg_update(int n, int j, double* w, double* r, const double* p, const double* q, const double* C,
+                            const double* Z, SolveState* st, const double* app_part, int app_nb, double* upd_part,
+                            hipStream_t stream);
+hipError_t launch_cg_replace(int n, double* r, const double* C, const double* Z, SolveState* st,
+                             const double* res_part, int res_nb, double* upd_part, hipStream_t stream);
 hipError_t launch_cg_finish(int n, double* w, const double* U, const SolveState* st, hipStream_t stream);
-hipError_t launch_lincomb(int n, int nvec, const double* const* vecs, const double* coef, double scale, double* out,
-                          int accumulate, hipStream_t stream);
-hipError_t launch_dots(int n, int npair, const double* const* a, const double* const* b, double* part,
-                       unsigned* counter, double* dots, hipStream_t stream);
-hipError_t launch_dot_to(int n, const double* a, const double* b, double* part, unsigned* counter, double* out,
-                         hipStream_t stream);
-hipError_t launch_dots3(int n, const double* a, const double* b, double* part, unsigned* counter, double* out,
-                        hipStream_t stream);
-hipError_t launch_axpy2(int n, double beta, double* y, const double* x, const double* c1, double s1, const double* c2,
-                        double s2, hipStream_t stream);
+hipError_t launch_finish_sum(const double* part, int nb, int nv, double* out, hipStream_t stream);
+hipError_t launch_dots_part(int n, int nv, const double* a, const double* b, double* part, hipStream_t stream);
+hipError_t launch_axpy_red(int n, double beta, double* y, const double* x, const double* part1, double s1,
+                           const double* part2, double s2, hipStream_t stream);
 hipError_t launch_sub(int n, const double* a, const double* b, double* out, hipStream_t stream);
-hipError_t launch_axpy_dev(int n, const double* x, const double* d, const double* alpha, double scale, double* y,
-                           hipStream_t stream);
 
 // dense.hip
 int gram_chunks(int n);

@@ -47,6 +47,12 @@ __host__ __device__ inline TileLayout tile_layout(int R, int reg, int fs) {
     return L;
 }
 
+// Loop over a rows x cols region with a 2-D thread layout (32 columns x NT/32 rows): no
+// integer division per element and unit-stride LDS access along rows.
+#define TILE_LOOP(rows, cols, rr, cc)                                 \
+    for (int rr = (int)(threadIdx.x >> 5); rr < (rows); rr += NT / 32) \
+        for (int cc = (int)(threadIdx.x & 31); cc < (cols); cc += 32)
+
 template <typename T>
 __host__ inline size_t tile_lds_bytes(int R, int reg, int fs) {
     return (size_t)tile_layout(R, reg, fs).total * sizeof(T);
@@ -57,8 +63,8 @@ template <typename T, typename Fetch>
 __device__ __forceinline__ void stage_region(T* buf, const Stencil& S, const TileLayout& L, int r0, int c0,
                                              Fetch fetch) {
     const int rows = L.RH, cols = L.RW;
-    for (int idx = threadIdx.x; idx < rows * cols; idx += NT) {
-        const int rr = idx / cols, cc = idx - rr * cols;
+    TILE_LOOP(rows, cols, rr, cc) {
+        const int idx = rr * cols + cc;
         const int gi = r0 - L.E + rr, gj = c0 - L.E + cc;
         T v = T(0);
         if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) v = (T)fetch(gi * S.w + gj);
@@ -79,8 +85,8 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
 
     // ---- A(A v), separable
     const int W1 = TW + 2 * R;
-    for (int idx = threadIdx.x; idx < RH * W1; idx += NT) {          // rows of region 0
-        const int rr = idx / W1, cc = idx - rr * W1;
+    TILE_LOOP(RH, W1, rr, cc) {                                       // rows of region 0
+        const int idx = rr * W1 + cc;
         const T* src = v + rr * RW + cc + (E - R) - R;
         T acc = T(0);
         for (int b = 0; b <= 2 * R; ++b) acc += (T)g[b] * src[b];
@@ -88,8 +94,8 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
     }
     __syncthreads();
     const int H1 = TH + 2 * R;
-    for (int idx = threadIdx.x; idx < H1 * W1; idx += NT) {           // columns -> A v
-        const int rr = idx / W1, cc = idx - rr * W1;
+    TILE_LOOP(H1, W1, rr, cc) {                                       // columns -> A v
+        const int idx = rr * W1 + cc;
         const T* src = h1 + (rr + E - R - R) * W1 + cc;
         T acc = T(0);
         for (int a = 0; a <= 2 * R; ++a) acc += (T)g[a] * src[a * W1];
@@ -98,16 +104,16 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
     }
     __syncthreads();
     T* h2 = h1;                                                       // reuse: (TH+2R) x TW
-    for (int idx = threadIdx.x; idx < H1 * TW; idx += NT) {
-        const int rr = idx / TW, cc = idx - rr * TW;
+    TILE_LOOP(H1, TW, rr, cc) {
+        const int idx = rr * TW + cc;
         const T* src = t1 + rr * W1 + cc;
         T acc = T(0);
         for (int b = 0; b <= 2 * R; ++b) acc += (T)g[b] * src[b];
         h2[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
-        const int rr = idx / TW, cc = idx - rr * TW;
+    TILE_LOOP(TH, TW, rr, cc) {
+        const int idx = rr * TW + cc;
         const T* src = h2 + rr * TW + cc;
         T acc = T(0);
         for (int a = 0; a <= 2 * R; ++a) acc += (T)g[a] * src[a * TW];
@@ -120,16 +126,16 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         T* fx = lds + L.o_fx;              // flux on [r0-1, r0+TH) x [c0-1, c0+TW)
         T* fy = lds + L.o_fy;
         const int XW = TW + 2;
-        for (int idx = threadIdx.x; idx < (TH + 2) * XW; idx += NT) {
-            const int rr = idx / XW, cc = idx - rr * XW;
+        TILE_LOOP((TH + 2), XW, rr, cc) {
+            const int idx = rr * XW + cc;
             const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
             xs[idx] = (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) ? (T)xhat[gi * S.w + gj] : T(0);
         }
         __syncthreads();
         const T gam2 = (T)S.gam2;
         const int FW = TW + 1;
-        for (int idx = threadIdx.x; idx < (TH + 1) * FW; idx += NT) {
-            const int rr = idx / FW, cc = idx - rr * FW;
+        TILE_LOOP((TH + 1), FW, rr, cc) {
+            const int idx = rr * FW + cc;
             const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
             T fxv = T(0), fyv = T(0);
             if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
@@ -150,8 +156,8 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         }
         __syncthreads();
         const T lam = (T)S.lam;
-        for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
-            const int rr = idx / TW, cc = idx - rr * TW;
+        TILE_LOOP(TH, TW, rr, cc) {
+            const int idx = rr * TW + cc;
             const int f = (rr + 1) * FW + (cc + 1);
             const T dt = -fx[f] + fx[f - 1] - fy[f] + fy[f - FW];
             out[idx] += lam * dt;
@@ -166,15 +172,15 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         for (int k = threadIdx.x; k < ntap + S.nf; k += NT)
             taps[k] = (k < ntap) ? (T)S.taps[k] : (T)S.lamj[k - ntap];
         const T eps = (T)S.eps;
-        for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
-            const int rr = idx / TW, cc = idx - rr * TW;
+        TILE_LOOP(TH, TW, rr, cc) {
+            const int idx = rr * TW + cc;
             out[idx] += eps * v[(rr + E) * RW + (cc + E)];
         }
         __syncthreads();
         for (int j = 0; j < S.nf; ++j) {
             const T* kj = taps + j * fs * fs;
-            for (int idx = threadIdx.x; idx < THF * TWF; idx += NT) {
-                const int rr = idx / TWF, cc = idx - rr * TWF;
+            TILE_LOOP(THF, TWF, rr, cc) {
+                const int idx = rr * TWF + cc;
                 const int gi = r0 - F + rr, gj = c0 - F + cc;
                 T val = T(0);
                 if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
@@ -190,8 +196,8 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
             }
             __syncthreads();
             const T lj = taps[ntap + j];
-            for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
-                const int rr = idx / TW, cc = idx - rr * TW;
+            TILE_LOOP(TH, TW, rr, cc) {
+                const int idx = rr * TW + cc;
                 // K^T t at (rr, cc): sum_{a,b} k[a][b] t(rr - (a - F), cc - (b - F))
                 const T* src = tb + (rr + F + F) * TWF + (cc + F + F);
                 T acc = T(0);

@@ -12,11 +12,8 @@ __device__ __forceinline__ void tile_origin(const Stencil& S, int tile, int& r0,
 
 // Per-block partial record of nv values; value k of this thread given by `val(k)`.
 template <typename Val>
-__device__ __forceinline__ void write_partials(double* part, int nv, double* red, Val val) {
-    for (int k = 0; k < nv; ++k) {
-        double s = block_sum(val(k), red);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * nv + k] = s;
-    }
+__device__ __forceinline__ void write_partials(double* part, int nv, double*, Val val) {
+    block_partials(part, nv, val);
 }
 
 // ------------------------------------------------------------------ out[:, c] = H v[:, c]
@@ -41,24 +38,43 @@ __global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict_
 }
 
 // ------------------------------------------------------------------ CG apply step
-// p_new = r + beta p_old (p = r on the first iteration), q = H p_new, and the block
-// partials of p.q and C^T q; the last block forms sigma, alpha = rho / sigma, e = C^T q
-// and z -= alpha e.  Optionally stores V[:, iters] = r / ||r||.
+// Iteration j, first half.  From the residual records of the previous kernel: rho_j =
+// r_j . r_j (and Z^T r_j), the stop decision (identical in every block; block 0 stores
+// it), beta = rho_j / rho_{j-1}.  Then p_new = r + beta p_old (p = r when j = 0),
+// q = H p_new, V[:, j] = r / ||r|| while j < v_cap, and the block record [p.q, C^T q].
 template <typename T>
-__global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, const double* __restrict__ xhat,
+__global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, int j, const double* __restrict__ xhat,
                                                  const double* __restrict__ r, const double* __restrict__ p_old,
                                                  double* __restrict__ p_new, double* __restrict__ q,
                                                  const double* __restrict__ C, double* __restrict__ V,
-                                                 SolveState* st, double* part, unsigned* counter) {
+                                                 SolveState* st, const double* __restrict__ upd_part, int upd_nb,
+                                                 double* __restrict__ app_part) {
     if (st->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
-    __shared__ double red[NWAVE];
-    __shared__ double tot[1 + S_MAX];
+    __shared__ double tot[NT];
+    const int s = st->s;
+    const int nz = st->hgerr_on ? s : 0;
+    reduce_partials(upd_part, upd_nb, 1 + nz, tot);
+    const double rho = tot[0];
+    const Decision dec = decide(st, j, rho, tot + 1);
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k < nz; k += NT) st->zr[k] = tot[1 + k];
+        if (threadIdx.x == 0) {
+            st->rho2[j & 1] = rho;
+            st->est = dec.est;
+            st->iters = j;
+            if (j == 0) st->res0 = sqrt(rho);
+            if (dec.done) {
+                st->status = dec.status;
+                st->done = 1;
+            }
+        }
+    }
+    if (dec.done) return;
     const TileLayout L = tile_layout(S.R, S.reg, S.fs);
-    const int iters = st->iters, s = st->s;
-    const bool first = (iters == 0);
-    const double beta = first ? 0.0 : st->beta;
+    const bool first = (j == 0);
+    const double beta = first ? 0.0 : rho / st->rho2[(j - 1) & 1];
     int r0, c0;
     tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
     stage_region<T>(lds + L.o_v, S, L, r0, c0,
@@ -66,8 +82,8 @@ __global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, const double* __rest
     __syncthreads();
     hvp_tile<T>(lds, S, L, xhat, r0, c0);
     __syncthreads();
-    const bool store = st->store_basis && iters < st->v_cap;
-    const double inv_nr = store ? 1.0 / sqrt(st->rho) : 0.0;
+    const bool store = st->store_basis && j < st->v_cap;
+    const double inv_nr = store ? 1.0 / sqrt(rho) : 0.0;
     // each thread owns pixels threadIdx.x and threadIdx.x + NT of the tile
     double pv[TH * TW / NT], qv[TH * TW / NT];
     int gid[TH * TW / NT];
@@ -86,13 +102,12 @@ __global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, const double* __rest
             const double qq = (double)lds[L.o_out + idx];
             p_new[i] = pn;
             q[i] = qq;
-            if (store) V[(size_t)iters * S.n + i] = ri * inv_nr;
+            if (store) V[(size_t)j * S.n + i] = ri * inv_nr;
             pv[u] = pn;
             qv[u] = qq;
         }
     }
-    const int nv = 1 + s;
-    write_partials(part, nv, red, [&](int k) {
+    block_partials(app_part, 1 + s, [&](int k) {
         double acc = 0.0;
 #pragma unroll
         for (int u = 0; u < TH * TW / NT; ++u) {
@@ -101,42 +116,18 @@ __global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, const double* __rest
         }
         return acc;
     });
-    if (!last_block(counter, gridDim.x)) return;
-    reduce_partials(part, gridDim.x, nv, tot, red);
-    const double sigma = tot[0];
-    const bool bad = !(sigma > 0.0);
-    if (threadIdx.x == 0) {
-        if (bad) {
-            st->status = (sigma != sigma || fabs(sigma) == INFINITY) ? BL_E_NONFINITE : BL_E_INDEFINITE;
-            st->done = 1;
-        } else {
-            st->sigma = sigma;
-            st->alpha = st->rho / sigma;
-        }
-    }
-    if (!bad) {
-        const double alpha = st->rho / sigma;
-        for (int k = threadIdx.x; k < s; k += NT) {
-            st->e[k] = tot[1 + k];
-            st->zacc[k] -= alpha * tot[1 + k];
-        }
-    }
 }
 
 // ------------------------------------------------------------------ residual g - H w
-// out = g - H w and block partials of C^T out (s values) and g.g; the last block stores
-// C^T out in st->c0 and ||g|| in st->gnorm.
+// out = g - H w and the block record [g.g, C^T out] (s values).
 template <typename T>
 __global__ void __launch_bounds__(NT) k_residual(Stencil S, const double* __restrict__ xhat,
                                                  const double* __restrict__ w, const double* __restrict__ g,
-                                                 double* __restrict__ out, const double* __restrict__ C,
-                                                 SolveState* st, double* part, unsigned* counter) {
+                                                 double* __restrict__ out, const double* __restrict__ C, int s,
+                                                 double* __restrict__ res_part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
-    __shared__ double red[NWAVE];
-    __shared__ double tot[1 + S_MAX];
     const TileLayout L = tile_layout(S.R, S.reg, S.fs);
-    const int s = st->s;
     int r0, c0;
     tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
     stage_region<T>(lds + L.o_v, S, L, r0, c0, [&](int i) { return w[i]; });
@@ -159,8 +150,7 @@ __global__ void __launch_bounds__(NT) k_residual(Stencil S, const double* __rest
             out[i] = ov[u];
         }
     }
-    const int nv = 1 + s;
-    write_partials(part, nv, red, [&](int k) {
+    block_partials(res_part, 1 + s, [&](int k) {
         double acc = 0.0;
 #pragma unroll
         for (int u = 0; u < TH * TW / NT; ++u) {
@@ -169,10 +159,6 @@ __global__ void __launch_bounds__(NT) k_residual(Stencil S, const double* __rest
         }
         return acc;
     });
-    if (!last_block(counter, gridDim.x)) return;
-    reduce_partials(part, gridDim.x, nv, tot, red);
-    if (threadIdx.x == 0) st->gnorm = sqrt(tot[0]);
-    for (int k = threadIdx.x; k < s; k += NT) st->c0[k] = tot[1 + k];
 }
 
 // ------------------------------------------------------------------ filter state
@@ -353,11 +339,9 @@ __global__ void k_jac_reduce(const double* __restrict__ part, int nblocks, int p
 // and block partials of Phi and ||grad||^2 (last block: st_out[0] = Phi, [1] = ||grad||^2).
 __global__ void __launch_bounds__(NT) k_lower_grad(Stencil S, const double* __restrict__ x,
                                                    const double* __restrict__ y, double* __restrict__ grad,
-                                                   double* part, unsigned* counter, double* st_out) {
+                                                   double* part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
-    __shared__ double red[NWAVE];
-    __shared__ double tot[2];
     const TileLayout L = tile_layout(S.R, S.reg, S.fs);
     const int R = S.R, E = L.E, RW = L.RW, RH = L.RH;
     int r0, c0;
@@ -487,18 +471,7 @@ __global__ void __launch_bounds__(NT) k_lower_grad(Stencil S, const double* __re
             gn += out[idx] * out[idx];
         }
     }
-    const double ph = block_sum(phi_loc, red);
-    const double gg = block_sum(gn, red);
-    if (threadIdx.x == 0) {
-        part[(size_t)blockIdx.x * 2] = ph;
-        part[(size_t)blockIdx.x * 2 + 1] = gg;
-    }
-    if (!last_block(counter, gridDim.x)) return;
-    reduce_partials(part, gridDim.x, 2, tot, red);
-    if (threadIdx.x == 0) {
-        st_out[0] = tot[0];
-        st_out[1] = tot[1];
-    }
+    block_partials(part, 2, [&](int k) { return k == 0 ? phi_loc : gn; });
 }
 
 // ------------------------------------------------------------------ y = A x + noise e
@@ -530,6 +503,7 @@ static void allow_lds(K kernel, size_t bytes) {
 }
 
 static inline dim3 tiles_grid(const Stencil& S, int ncols) { return dim3(S.tiles_x * S.tiles_y, ncols); }
+int tiles_of(const Stencil& S) { return S.tiles_x * S.tiles_y; }
 
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
                       hipStream_t st) {
@@ -544,27 +518,27 @@ hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_cg_apply(const Stencil& S, bool fp32, const double* xhat, const double* r, const double* p_old,
-                           double* p_new, double* q, const double* C, double* V, SolveState* st, double* part,
-                           unsigned* counter, hipStream_t stream) {
+hipError_t launch_cg_apply(const Stencil& S, bool fp32, int j, const double* xhat, const double* r,
+                           const double* p_old, double* p_new, double* q, const double* C, double* V, SolveState* st,
+                           const double* upd_part, int upd_nb, double* app_part, hipStream_t stream) {
     const size_t lds = fp32 ? tile_lds_bytes<float>(S.R, S.reg, S.fs) : tile_lds_bytes<double>(S.R, S.reg, S.fs);
     if (fp32) {
         allow_lds(k_cg_apply<float>, lds);
-        hipLaunchKernelGGL(k_cg_apply<float>, tiles_grid(S, 1), dim3(NT), lds, stream, S, xhat, r, p_old, p_new, q, C,
-                           V, st, part, counter);
+        hipLaunchKernelGGL(k_cg_apply<float>, tiles_grid(S, 1), dim3(NT), lds, stream, S, j, xhat, r, p_old, p_new, q,
+                           C, V, st, upd_part, upd_nb, app_part);
     } else {
         allow_lds(k_cg_apply<double>, lds);
-        hipLaunchKernelGGL(k_cg_apply<double>, tiles_grid(S, 1), dim3(NT), lds, stream, S, xhat, r, p_old, p_new, q,
-                           C, V, st, part, counter);
+        hipLaunchKernelGGL(k_cg_apply<double>, tiles_grid(S, 1), dim3(NT), lds, stream, S, j, xhat, r, p_old, p_new,
+                           q, C, V, st, upd_part, upd_nb, app_part);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_residual(const Stencil& S, const double* xhat, const double* w, const double* g, double* out,
-                           const double* C, SolveState* st, double* part, unsigned* counter, hipStream_t stream) {
+                           const double* C, int s, double* res_part, hipStream_t stream) {
     allow_lds(k_residual<double>, tile_lds_bytes<double>(S.R, S.reg, S.fs));
     hipLaunchKernelGGL(k_residual<double>, tiles_grid(S, 1), dim3(NT), tile_lds_bytes<double>(S.R, S.reg, S.fs),
-                       stream, S, xhat, w, g, out, C, st, part, counter);
+                       stream, S, xhat, w, g, out, C, s, res_part);
     return hipGetLastError();
 }
 
@@ -600,10 +574,10 @@ hipError_t launch_jac(const Stencil& S, const double* xhat, const double* w, int
 }
 
 hipError_t launch_lower_grad(const Stencil& S, const double* x, const double* y, double* grad, double* part,
-                             unsigned* counter, double* st_out, hipStream_t stream) {
+                             hipStream_t stream) {
     allow_lds(k_lower_grad, tile_lds_bytes<double>(S.R, S.reg, S.fs));
     hipLaunchKernelGGL(k_lower_grad, tiles_grid(S, 1), dim3(NT), tile_lds_bytes<double>(S.R, S.reg, S.fs), stream, S,
-                       x, y, grad, part, counter, st_out);
+                       x, y, grad, part);
     return hipGetLastError();
 }
 

@@ -205,9 +205,10 @@ def test_recycled_cg_parity(B, stop):
     # (the estimate is far from monotone), so the GPU must stop inside the spread of the
     # oracle's own stopping iterations under one-ulp perturbations of g, and meet the test.
     ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)
-    spread = [krylov.recycled_cg(hvp2, g * (1 + 2.0 ** -52 * synth.unit_noise(prob.n, 200 + k)), w0, rs["U"],
-                                 rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)["iters"]
-              for k in range(4)] + [ref["iters"]]
+    runs = [krylov.recycled_cg(hvp2, g * (1 + 2.0 ** -52 * synth.unit_noise(prob.n, 200 + k)), w0, rs["U"],
+                               rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)
+            for k in range(4)] + [ref]
+    spread = [r_["iters"] for r_ in runs]
     wstar, _ = krylov.reference_solve(hvp2, g)
     with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
         upload_recycle(S, rs)
@@ -218,10 +219,10 @@ def test_recycled_cg_parity(B, stop):
         if stop == "hgerr":
             assert st.est <= hg_tol
             hg_gpu = prob.jac_apply(xh, th2, host(w))
-            hg_ora = prob.jac_apply(xh, th2, ref["w"])
             hg_star = prob.jac_apply(xh, th2, wstar)
-            # same quality of hypergradient as the oracle's own run (within a factor 10)
-            assert rel(hg_gpu, hg_star) <= 10 * rel(hg_ora, hg_star) + 1e-12
+            worst = max(rel(prob.jac_apply(xh, th2, r_["w"]), hg_star) for r_ in runs)
+            # hypergradient no worse than the oracle's own runs under one-ulp perturbations (x10)
+            assert rel(hg_gpu, hg_star) <= 10 * worst + 1e-12
         else:
             assert rel(host(w), wstar) <= 1e-8
 
