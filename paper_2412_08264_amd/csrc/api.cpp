@@ -31,6 +31,9 @@ namespace {
 
 constexpr int LBFGS_MMAX = 20;
 constexpr int POLL = 8;              // iterations launched between host polls of the stop flag
+// Consumer kernels re-reduce the producer's per-block records in every block; above this many
+// record values a one-block kernel first folds them into one record (keeps the re-reads linear).
+constexpr long REC_LIMIT = 8192;
 constexpr size_t ALIGN = 256;
 
 size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
@@ -59,7 +62,7 @@ bl_status check_problem(bl_ctx* c, const bl_problem* P) {
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -80,6 +83,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.part_doubles = pd;
     size_t o = 0;
     L.state = o;    o += al(sizeof(SolveState));
+    L.fold = o;     o += al(4 * NV_RED * sizeof(double));
     L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
@@ -105,6 +109,7 @@ struct WS {
     double* part_res() const { return part(); }
     double* part_app() const { return part() + L.part_doubles; }
     double* part_upd() const { return part() + 2 * L.part_doubles; }
+    double* part_fold(int k) const { return (double*)(base + L.fold) + k * NV_RED; }
     double* vec(int k) const { return (double*)(base + L.vec) + (size_t)k * L.n; }
     double* d1() const { return (double*)(base + L.maps); }
     double* d2() const { return d1() + (size_t)L.nf * L.n; }
@@ -383,9 +388,25 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
     double* prs = ws.part_res();
     double* pap = ws.part_app();
     double* pup = ws.part_upd();
+    // Records handed from kernel to kernel: (pointer, number of blocks), folded when large.
+    auto fold = [&](double* part, int nb, int nv, int slot, const double*& out, int& out_nb) -> bl_status {
+        if ((long)nb * nv > REC_LIMIT) {
+            HIPCHK(launch_finish_sum(part, nb, nv, ws.part_fold(slot), c->stream));
+            out = ws.part_fold(slot);
+            out_nb = 1;
+        } else {
+            out = part;
+            out_nb = nb;
+        }
+        return BL_OK;
+    };
+    const int nz = hg ? s : 0;
+    const double* rec;
+    int rec_nb;
     // r = g - H w0 (FP64) with record [g.g, C^T r];  w += U c0;  r -= C c0
     HIPCHK(launch_residual(S, xhat, w, g, r, C, s, prs, c->stream));
-    HIPCHK(launch_cg_init(n, w, r, U, C, Z, st, prs, tiles, pup, c->stream));
+    TRY(fold(prs, tiles, 1 + s, 0, rec, rec_nb));
+    HIPCHK(launch_cg_init(n, w, r, U, C, Z, st, rec, rec_nb, pup, c->stream));
     mark(c, 1);
     const int rr_every = fp32 ? o->rr_every : 0;
     const bool ktime = c->timing == 2;
@@ -403,11 +424,18 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
             }
             HIPCHK(hipEventRecord(c->kev[3 * launched.size()], c->stream));
         }
-        HIPCHK(launch_cg_apply(S, fp32, j, xhat, r, pb[j & 1], pb[(j + 1) & 1], q, C, V, st, pup, nb1, pap,
+        const double* ru;
+        int ru_nb;
+        TRY(fold(pup, nb1, 1 + nz, 1, ru, ru_nb));
+        HIPCHK(launch_cg_apply(S, fp32, j, xhat, r, pb[j & 1], pb[(j + 1) & 1], q, C, V, st, ru, ru_nb, pap,
                                c->stream));
         if (ktime) HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 1], c->stream));
-        if (j < o->max_iter)
-            HIPCHK(launch_cg_update(n, j, w, r, pb[(j + 1) & 1], q, C, Z, st, pap, tiles, pup, c->stream));
+        if (j < o->max_iter) {
+            const double* ra;
+            int ra_nb;
+            TRY(fold(pap, tiles, 1 + s, 2, ra, ra_nb));
+            HIPCHK(launch_cg_update(n, j, w, r, pb[(j + 1) & 1], q, C, Z, st, ra, ra_nb, pup, c->stream));
+        }
         if (ktime) {
             HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 2], c->stream));
             launched.push_back(j);
@@ -449,7 +477,8 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
             // of the current index re-tests (and goes on if the true residual misses the test)
             if (converged) j = hs->iters;
             HIPCHK(launch_residual(S, xhat, w, g, r, C, s, prs, c->stream));
-            HIPCHK(launch_cg_replace(n, r, C, Z, st, prs, tiles, pup, c->stream));
+            TRY(fold(prs, tiles, 1 + s, 0, rec, rec_nb));
+            HIPCHK(launch_cg_replace(n, r, C, Z, st, rec, rec_nb, pup, c->stream));
             TRY(launch_iter());
             HIPCHK(hipMemcpyAsync(hs, st, hdr, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));

@@ -9,7 +9,7 @@
 namespace bl {
 
 constexpr int TW = 32;          // stencil tile width  (pixels)
-constexpr int TH = 16;          // stencil tile height (pixels)
+constexpr int TH = 8;           // stencil tile height (pixels): one pixel per thread
 constexpr int NT = 256;         // threads per stencil / reduction block (4 wavefronts)
 constexpr int NWAVE = NT / 64;
 constexpr int S_MAX = 64;       // largest recycle dimension
@@ -81,9 +81,17 @@ template <typename Val>
 __device__ __forceinline__ void block_partials(double* part, int nv, Val val) {
     __shared__ double wred[NWAVE][NV_RED];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < nv; ++k) {
-        const double v = wave_sum(val(k));
-        if (lane == 0) wred[wave][k] = v;
+    for (int k0 = 0; k0 < nv; k0 += 8) {
+        // the values of a group of 8 (typically loads of 8 columns) are all in flight
+        // before the first shuffle reduction waits on them
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (k0 + u < nv) ? val(k0 + u) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double sum = wave_sum(v[u]);
+            if (lane == 0 && k0 + u < nv) wred[wave][k0 + u] = sum;
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nv; k += NT) {
@@ -103,8 +111,17 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
     const int G = nv >= NT ? 1 : NT / nv;
     const int k = threadIdx.x / G, j = threadIdx.x - k * G;
     double acc = 0.0;
-    if (k < nv)
-        for (int b = j; b < nblocks; b += G) acc += part[(size_t)b * nv + k];
+    if (k < nv) {
+        // eight loads in flight per round; the summation order is fixed by (nblocks, nv)
+        double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = j;
+        for (; b + 7 * G < nblocks; b += 8 * G) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a8[u] += part[(size_t)(b + u * G) * nv + k];
+        }
+        for (int u = 0; b < nblocks; b += G, ++u) a8[u & 7] += part[(size_t)b * nv + k];
+        acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+    }
     tmp[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < nv) {
@@ -152,6 +169,20 @@ __device__ __forceinline__ Decision decide(const SolveState* st, int j, double r
         d.status = BL_E_NOT_CONVERGED;
     }
     return d;
+}
+
+// sum_k M[k*n + i] * c[k], k < s, with the loads of 8 columns issued together.
+__device__ __forceinline__ double combo(const double* __restrict__ M, size_t n, int i, const double* c, int s) {
+    double acc = 0.0;
+    for (int k0 = 0; k0 < s; k0 += 8) {
+        double m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = (k0 + u < s) ? M[(size_t)(k0 + u) * n + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u < s) acc += m[u] * c[k0 + u];
+    }
+    return acc;
 }
 
 // Map a block index to a tile index so that each XCD (blocks are dealt round-robin over

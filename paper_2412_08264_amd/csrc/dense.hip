@@ -57,8 +57,8 @@ __global__ void k_sum_chunks(int nchunks, int len, const double* __restrict__ pa
 }
 
 int gram_chunks(int n) {
-    int c = (n + 4095) / 4096;
-    return c < 1 ? 1 : (c > 256 ? 256 : c);
+    int c = (n + 255) / 256;
+    return c < 1 ? 1 : (c > 512 ? 512 : c);
 }
 
 hipError_t launch_gram(int n, int t1, int t2, const double* A, const double* B, double* part, double* out,
@@ -125,6 +125,8 @@ __device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, doub
                           double* Xinv, int ldx) {
     __shared__ int s_tk, s_keep;
     __shared__ double s_d;
+    __shared__ int s_kept[256];
+    kept = s_kept;
     if (threadIdx.x == 0) s_tk = 0;
     for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) A[idx] = Gm[idx];
     __syncthreads();
@@ -171,9 +173,11 @@ __device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, doub
     if (threadIdx.x == 0) *tk_out = tk;
 }
 
+// The working matrix lives in LDS when it fits (lds != 0), else in the global scratch R.
 __global__ void __launch_bounds__(SD_NT) k_chol_drop(int t, const double* Gm, double tol, double* R, int* kept,
-                                                     int* tk_out, double* Xinv, int ldx) {
-    chol_drop(t, Gm, tol, R, kept, tk_out, Xinv, ldx);
+                                                     int* tk_out, double* Xinv, int ldx, int lds) {
+    extern __shared__ double dyn_lds[];
+    chol_drop(t, Gm, tol, lds ? dyn_lds : R, kept, tk_out, Xinv, ldx);
 }
 
 // Parallel cyclic Jacobi on a symmetric m x m matrix A (row-major, in place -> eigenvalues on
@@ -186,18 +190,32 @@ __device__ void jacobi_eigh(int m, double* A, double* V, double* cs, int* pairs,
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         // convergence: off-diagonal Frobenius norm relative to the full norm
-        if (threadIdx.x == 0) {
+        {
+            __shared__ double r_off[SD_NT / 64], r_nrm[SD_NT / 64];
             double off = 0.0, nrm = 0.0;
-            for (int i = 0; i < m; ++i)
-                for (int j = 0; j < m; ++j) {
-                    const double v = A[i * m + j];
-                    nrm += v * v;
-                    if (i != j) off += v * v;
+            for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+                const double v = A[idx];
+                nrm += v * v;
+                if (idx / m != idx % m) off += v * v;
+            }
+            off = wave_sum(off);
+            nrm = wave_sum(nrm);
+            if ((threadIdx.x & 63) == 0) {
+                r_off[threadIdx.x >> 6] = off;
+                r_nrm[threadIdx.x >> 6] = nrm;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double a = 0.0, b = 0.0;
+                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                    a += r_off[w];
+                    b += r_nrm[w];
                 }
-            s_off = off;
-            s_norm = nrm;
+                s_off = a;
+                s_norm = b;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (s_off <= 1e-30 * s_norm || s_off == 0.0) break;
         for (int rnd = 0; rnd < me - 1; ++rnd) {
             const int np = me / 2;
@@ -305,9 +323,31 @@ __device__ void chol_solve(int t, const double* L, double* x) {
 //   p >= t: eigen of S^T S = V_H diag(mu^2) V_H^T; right vectors X ~ M^{-1} V_H;
 //   p <  t: eigen of S S^T (p x p) gives mu and V_H = S^T u / mu; null(G) from Householder QR
 //           of G^T; the remaining slots take the smallest Ritz pairs of N^T M N (Ritz-S).
+// Run the symmetric Jacobi solver on (A, V) (m x m, global scratch), staging both in LDS
+// when `lds` (2 m^2 doubles fit).
+__device__ void jacobi_staged(int m, double* A, double* V, double* cs, int* pairs, int lds) {
+    extern __shared__ double dyn_lds[];
+    if (!lds) {
+        jacobi_eigh(m, A, V, cs, pairs, 40);
+        return;
+    }
+    double* LA = dyn_lds;
+    double* LV = dyn_lds + (size_t)m * m;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) LA[idx] = A[idx];
+    __syncthreads();
+    jacobi_eigh(m, LA, LV, cs, pairs, 40);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        A[idx] = LA[idx];
+        V[idx] = LV[idx];
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, const double* __restrict__ Min,
                                                        const double* __restrict__ G, double* sc, double* Xs,
-                                                       double* VHs, double* mu, int* info) {
+                                                       double* VHs, double* mu, int* info, int lds) {
+    extern __shared__ double dyn_lds[];
     __shared__ double cs[SD_NT];
     __shared__ int pairs[SD_NT];
     __shared__ int s_rank;
@@ -334,13 +374,24 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
         Ms[idx] = v;
     }
     __syncthreads();
-    if (!chol_inplace(t, L)) {
-        if (threadIdx.x == 0) {
-            info[0] = 0;
-            info[1] = 0;
-            info[2] = BL_E_INDEFINITE;
+    {
+        double* LL = lds ? dyn_lds : L;   // factor in LDS, then copy back
+        if (lds)
+            for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) LL[idx] = L[idx];
+        __syncthreads();
+        const bool spd = chol_inplace(t, LL);
+        if (lds) {
+            for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) L[idx] = LL[idx];
+            __syncthreads();
         }
-        return;
+        if (!spd) {
+            if (threadIdx.x == 0) {
+                info[0] = 0;
+                info[1] = 0;
+                info[2] = BL_E_INDEFINITE;
+            }
+            return;
+        }
     }
     // S[k, :] = (M^{-1} G[k, :]^T)^T, one row per thread
     for (int k = threadIdx.x; k < p; k += blockDim.x) {
@@ -367,7 +418,7 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
             K[idx] = v;
         }
         __syncthreads();
-        jacobi_eigh(t, K, Vv, cs, pairs, 40);
+        jacobi_staged(t, K, Vv, cs, pairs, lds);
         if (threadIdx.x == 0) {
             for (int i = 0; i < t; ++i) order[i] = i;
             for (int i = 1; i < t; ++i) {   // descending mu^2, stable
@@ -408,8 +459,8 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
             GG[idx] = w;
         }
         __syncthreads();
-        jacobi_eigh(p, K, Vv, cs, pairs, 40);
-        jacobi_eigh(p, GG, GV, cs, pairs, 40);
+        jacobi_staged(p, K, Vv, cs, pairs, lds);
+        jacobi_staged(p, GG, GV, cs, pairs, lds);
         if (threadIdx.x == 0) {
             double mx2 = 0.0;
             for (int i = 0; i < p; ++i) mx2 = fmax(mx2, GG[i * p + i]);
@@ -505,7 +556,7 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
                 B[idx] = v;
             }
             __syncthreads();
-            jacobi_eigh(nn, B, BV, cs, pairs, 40);
+            jacobi_staged(nn, B, BV, cs, pairs, lds);
             if (threadIdx.x == 0) {
                 for (int i = 0; i < nn; ++i) order[i] = i;
                 for (int i = 1; i < nn; ++i) {   // ascending Ritz values
@@ -555,15 +606,41 @@ size_t gsvd_scratch_doubles(int t, int p) {
     return T2 + PT + 2 * (T2 + P2) + 2 * P2 + PT + 6 * T2 + (t + p) + 64;
 }
 
+// Largest dynamic LDS per workgroup, queried once (falls back to 64 KiB).
+static size_t lds_limit() {
+    static size_t lim = 0;
+    if (!lim) {
+        int dev = 0, v = 0;
+        lim = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            lim = (size_t)v;
+        lim -= 16384;   // room for the kernels' static LDS
+    }
+    return lim;
+}
+
 hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int* kept, int* tk, double* Xinv,
                             int ldx, hipStream_t stream) {
-    hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(SD_NT), 0, stream, t, Gm, tol, R, kept, tk, Xinv, ldx);
+    const size_t bytes = (size_t)t * t * sizeof(double);
+    const int lds = bytes <= lds_limit() ? 1 : 0;
+    if (lds && bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)k_chol_drop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(SD_NT), lds ? bytes : 0, stream, t, Gm, tol, R, kept, tk, Xinv, ldx,
+                       lds);
     return hipGetLastError();
 }
 
 hipError_t launch_gsvd_select(int t, int p, int s, const double* M, const double* G, double* sc, double* Xs,
                               double* VHs, double* mu, int* info, hipStream_t stream) {
-    hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), 0, stream, t, p, s, M, G, sc, Xs, VHs, mu, info);
+    // Jacobi problems are at most t x t (t x t for p >= t; p x p and (t-p) x (t-p) otherwise)
+    const int m = t;
+    const size_t bytes = 2 * (size_t)m * m * sizeof(double);
+    const int lds = bytes <= lds_limit() ? 1 : 0;
+    if (lds && bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)k_gsvd_select, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), lds ? bytes : 0, stream, t, p, s, M, G, sc, Xs, VHs, mu,
+                       info, lds);
     return hipGetLastError();
 }
 

@@ -35,13 +35,8 @@ __global__ void __launch_bounds__(NT) k_cg_init(int n, double* __restrict__ w, d
     const double* c0 = tot + 1;
     const int nz = st->hgerr_on ? s : 0;
     residual_record(Z, n, nz, upd_part, [&](int i) {
-        double uc = 0.0, cc = 0.0;
-        for (int k = 0; k < s; ++k) {
-            uc += U[(size_t)k * n + i] * c0[k];
-            cc += C[(size_t)k * n + i] * c0[k];
-        }
-        w[i] += uc;
-        const double ri = r[i] - cc;
+        w[i] += combo(U, n, i, c0, s);
+        const double ri = r[i] - combo(C, n, i, c0, s);
         r[i] = ri;
         return ri;
     });
@@ -75,8 +70,7 @@ __global__ void __launch_bounds__(NT) k_cg_update(int n, int j, double* __restri
     }
     const int nz = st->hgerr_on ? s : 0;
     residual_record(Z, n, nz, upd_part, [&](int i) {
-        double ce = 0.0;
-        for (int k = 0; k < s; ++k) ce += C[(size_t)k * n + i] * e[k];
+        const double ce = combo(C, n, i, e, s);
         w[i] += alpha * p[i];
         const double ri = r[i] - alpha * (q[i] - ce);
         r[i] = ri;
@@ -103,9 +97,7 @@ __global__ void __launch_bounds__(NT) k_cg_replace(int n, double* __restrict__ r
     }
     const int nz = st->hgerr_on ? s : 0;
     residual_record(Z, n, nz, upd_part, [&](int i) {
-        double cc = 0.0;
-        for (int k = 0; k < s; ++k) cc += C[(size_t)k * n + i] * c[k];
-        const double ri = r[i] - cc;
+        const double ri = r[i] - combo(C, n, i, c, s);
         r[i] = ri;
         return ri;
     });
@@ -118,11 +110,7 @@ __global__ void __launch_bounds__(NT) k_cg_finish(int n, double* __restrict__ w,
     const int s = st->s;
     for (int k = threadIdx.x; k < s; k += NT) z[k] = st->zacc[k];
     __syncthreads();
-    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        double acc = 0.0;
-        for (int k = 0; k < s; ++k) acc += U[(size_t)k * n + i] * z[k];
-        w[i] += acc;
-    }
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) w[i] += combo(U, n, i, z, s);
 }
 
 // out[k] = sum of the records (one block).

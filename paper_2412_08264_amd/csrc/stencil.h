@@ -59,16 +59,28 @@ __host__ inline size_t tile_lds_bytes(int R, int reg, int fs) {
 }
 
 // Stage `fetch(global index)` on [r0-E, r0+TH+E) x [c0-E, c0+TW+E); zero outside the image.
+// The loads of all of a thread's elements are issued before any is stored, so the staging
+// costs one memory round trip (a block per CU has no other waves to hide latency with).
+constexpr int STAGE_MAX = ((TH + 4 * MAX_R) * (TW + 4 * MAX_R) + NT - 1) / NT;
 template <typename T, typename Fetch>
 __device__ __forceinline__ void stage_region(T* buf, const Stencil& S, const TileLayout& L, int r0, int c0,
                                              Fetch fetch) {
-    const int rows = L.RH, cols = L.RW;
-    TILE_LOOP(rows, cols, rr, cc) {
-        const int idx = rr * cols + cc;
-        const int gi = r0 - L.E + rr, gj = c0 - L.E + cc;
-        T v = T(0);
-        if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) v = (T)fetch(gi * S.w + gj);
-        buf[idx] = v;
+    const int rows = L.RH, cols = L.RW, tot = rows * cols;
+    double v[STAGE_MAX];
+#pragma unroll
+    for (int u = 0; u < STAGE_MAX; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        v[u] = 0.0;
+        if (idx < tot) {
+            const int rr = idx / cols, cc = idx - rr * cols;
+            const int gi = r0 - L.E + rr, gj = c0 - L.E + cc;
+            if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) v[u] = fetch(gi * S.w + gj);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_MAX; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        if (idx < tot) buf[idx] = (T)v[u];
     }
 }
 
