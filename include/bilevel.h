@@ -86,7 +86,7 @@ typedef struct {
     double tol;              /* residual test ||r|| <= tol ||g||                              */
     double hg_tol;           /* error-estimate test ||mu . (Z^T r)|| <= hg_tol (absolute)     */
     int max_iter;
-    int check_every;         /* iterations between host polls of the device stop flag        */
+    int check_every;         /* the stop test runs at iterations j with j % check_every == 0 */
     int rr_every;            /* residual replacement period in mixed precision (0 = off)     */
     int store_basis;         /* store normalised residuals into rs->V                         */
 } bl_solve_opts;
@@ -171,6 +171,61 @@ bl_status bl_set_timing(bl_ctx* ctx, int enable);
  * its launch count, out4[2] / out4[3] = the same for the update kernel (w, r, r.r, Z^T r).
  * reset != 0 clears the totals after reading. */
 bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
+
+/* ------------------------------------------------------------------------------------------
+ * Batched and served Hessian solves.  An engine runs up to `cap` (<= 64) recycled-CG solves
+ * of one operator class (every bl_problem field but h, w equal) side by side: each
+ * iteration is one launch of the fused apply kernel (H p with p.q and C^T q) and one of the
+ * update kernel over all running solves, whatever their sizes, recycle dimensions and
+ * iteration indices.  Every solve reduces only its own records in a fixed order, so its
+ * iterates, iteration count and status are bitwise those of the same solve run alone
+ * (bl_hessian_solve, which is a one-solve engine).  Solves are admitted and retired
+ * between steps (continuous batching).  The engine's device memory is one caller-owned
+ * workspace: fixed per-slot descriptors plus an arena from which each admitted solve takes
+ * bl_engine_slot_bytes() and to which retirement returns it.  The engine holds pinned host
+ * buffers of its own (released by bl_engine_destroy) and is used from one host thread.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct bl_engine bl_engine;
+
+/* Arena bytes one solve of problem P with s recycle columns (rs->s_cur) occupies. */
+size_t bl_engine_slot_bytes(const bl_problem* P, int s);
+/* Workspace for an engine of `cap` slots (1..64) with an arena of arena_bytes. */
+size_t bl_engine_workspace_bytes(int cap, size_t arena_bytes);
+/* Engine over the workspace ws (256-byte aligned); the arena is whatever ws_bytes leaves
+ * after the fixed part.  cls fixes the operator class; its h, w are ignored. */
+bl_status bl_engine_create(bl_ctx* ctx, const bl_problem* cls, int cap, void* ws, size_t ws_bytes,
+                           bl_engine** engine);
+bl_status bl_engine_destroy(bl_engine* engine);
+/* Admit the solve H(theta, xhat) w = g with recycle state rs (NULL or s_cur = 0: plain CG)
+ * and options opts; same arguments and meaning as bl_hessian_solve.  theta and opts are
+ * read during the call; xhat, g, w, rs and its arrays must stay valid until retirement.
+ * Set-up work (FP64 residual, projection onto C) is enqueued at once.  Returns
+ * BL_E_WORKSPACE (nothing enqueued) when no slot or no arena block of
+ * bl_engine_slot_bytes() is free: retire a completed solve and try again. */
+bl_status bl_engine_admit(bl_engine* engine, const bl_problem* P, const double* theta_host, const double* xhat,
+                          const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts, int* slot);
+/* Advance all running solves by at most max_iters iterations; with return_on_done, return
+ * as soon as one or more solves have completed.  The slots of completed solves go to
+ * done[0 .. *n_done - 1] (done holds cap ints); their w is final when the call returns. */
+bl_status bl_engine_step(bl_engine* engine, int max_iters, int return_on_done, int* done, int* n_done);
+/* Statistics of a completed solve, and the slot and its arena block freed.  Returns the
+ * solve's status (as bl_hessian_solve would); with store_basis rs->v_cur is set. */
+bl_status bl_engine_retire(bl_engine* engine, int slot, bl_stats* out);
+/* Running solves, free slots, free arena bytes and the largest free arena block. */
+bl_status bl_engine_query(const bl_engine* engine, int* running, int* free_slots, size_t* free_bytes,
+                          size_t* largest_free);
+
+/* Workspace of bl_hessian_solve_batched for nprob problems P[k] with s[k] recycle columns
+ * (s = NULL: none). */
+size_t bl_batched_workspace_bytes(int nprob, const bl_problem* P, const int* s);
+/* nprob independent solves of one operator class (P[k], theta[k], xhat[k], g[k], w[k],
+ * rs[k]; rs = NULL: plain CG for all) with shared options, advanced together (at most 64 at
+ * a time; later ones are admitted as earlier ones finish).  out[k] gets the statistics of
+ * solve k.  Returns BL_OK, or the first non-OK status of a solve. */
+bl_status bl_hessian_solve_batched(bl_ctx* ctx, int nprob, const bl_problem* P, const double* const* theta_host,
+                                   const double* const* xhat, const double* const* g, double* const* w_inout,
+                                   bl_recycle* rs, const bl_solve_opts* opts, void* ws, size_t ws_bytes,
+                                   bl_stats* out);
 
 #ifdef __cplusplus
 }

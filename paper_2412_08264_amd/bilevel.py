@@ -70,6 +70,19 @@ _SIGS = {
                                 C.c_size_t]),
     "bl_set_timing": (C.c_int, [_vp, C.c_int]),
     "bl_kernel_times": (C.c_int, [_vp, _P(C.c_double), C.c_int]),
+    "bl_engine_slot_bytes": (C.c_size_t, [_P(bl_problem), C.c_int]),
+    "bl_engine_workspace_bytes": (C.c_size_t, [C.c_int, C.c_size_t]),
+    "bl_engine_create": (C.c_int, [_vp, _P(bl_problem), C.c_int, _vp, C.c_size_t, _P(_vp)]),
+    "bl_engine_destroy": (C.c_int, [_vp]),
+    "bl_engine_admit": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
+                                  _P(bl_solve_opts), _P(C.c_int)]),
+    "bl_engine_step": (C.c_int, [_vp, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int)]),
+    "bl_engine_retire": (C.c_int, [_vp, C.c_int, _P(bl_stats)]),
+    "bl_engine_query": (C.c_int, [_vp, _P(C.c_int), _P(C.c_int), _P(C.c_size_t), _P(C.c_size_t)]),
+    "bl_batched_workspace_bytes": (C.c_size_t, [C.c_int, _P(bl_problem), _P(C.c_int)]),
+    "bl_hessian_solve_batched": (C.c_int, [_vp, C.c_int, _P(bl_problem), _P(_P(C.c_double)), _P(_vp), _P(_vp),
+                                           _P(_vp), _P(bl_recycle), _P(bl_solve_opts), _vp, C.c_size_t,
+                                           _P(bl_stats)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -158,18 +171,11 @@ class Session:
             nbytes = bl_workspace_bytes(P, s_max, v_cap)
             if nbytes == 0:
                 raise BLError(BL_E_ARG, "bl_workspace_bytes rejected the shape")
-            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-            off = (-self.ws.data_ptr()) % 256
-            self.ws_ptr = self.ws.data_ptr() + off
+            self.ws, self.ws_ptr = _aligned_workspace(nbytes, self.device)
             self.ws_bytes = nbytes
-            f64 = dict(dtype=torch.float64, device=self.device)
-            self.U = torch.zeros((max(s_max, 1), self.n), **f64)
-            self.Cm = torch.zeros((max(s_max, 1), self.n), **f64)
-            self.Z = torch.zeros((max(s_max, 1), self.n), **f64)
-            self.mu = torch.zeros(max(s_max, 1), **f64)
-            self.V = torch.zeros((max(v_cap, 1), self.n), **f64)
-        self.rs = bl_recycle(self.U.data_ptr(), self.Cm.data_ptr(), self.Z.data_ptr(), self.mu.data_ptr(),
-                             self.V.data_ptr(), s_max, 0, v_cap, 0)
+            self.rec = Recycle(self.n, s_max, v_cap, self.device)
+        self.U, self.Cm, self.Z, self.mu, self.V = self.rec.U, self.rec.Cm, self.rec.Z, self.rec.mu, self.rec.V
+        self.rs = self.rec.rs
 
     def __enter__(self):
         return self
@@ -250,3 +256,149 @@ class Session:
         _check(self.ctx, lib.bl_hypergradient(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(w), out,
                                               1 if project else 0, self.ws_ptr, self.ws_bytes), "bl_hypergradient")
         return np.array(out[:], dtype=np.float64)
+
+
+# --------------------------------------------------------------------------- recycle storage
+class Recycle:
+    """Device storage of one sample's recycle state: U, C, Z (s_max x n), mu, V (v_cap x n)."""
+
+    def __init__(self, n: int, s_max: int, v_cap: int, device):
+        import torch
+        f64 = dict(dtype=torch.float64, device=device)
+        self.n = n
+        self.U = torch.zeros((max(s_max, 1), n), **f64)
+        self.Cm = torch.zeros((max(s_max, 1), n), **f64)
+        self.Z = torch.zeros((max(s_max, 1), n), **f64)
+        self.mu = torch.zeros(max(s_max, 1), **f64)
+        self.V = torch.zeros((max(v_cap, 1), n), **f64)
+        self.rs = bl_recycle(self.U.data_ptr(), self.Cm.data_ptr(), self.Z.data_ptr(), self.mu.data_ptr(),
+                             self.V.data_ptr(), s_max, 0, v_cap, 0)
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.U, self.Cm, self.Z, self.mu, self.V))
+
+
+def solve_opts(tol=1e-10, stop: str = "resid", hg_tol: float = 0.0, max_iter: int = 20000, check_every: int = 1,
+               rr_every: int = 50, store_basis: bool = True) -> bl_solve_opts:
+    return bl_solve_opts(BL_STOP_HGERR if stop == "hgerr" else BL_STOP_RESID, tol, hg_tol, max_iter, check_every,
+                         rr_every, 1 if store_basis else 0)
+
+
+def _aligned_workspace(nbytes: int, device):
+    import torch
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return ws, ws.data_ptr() + (-ws.data_ptr()) % 256
+
+
+# --------------------------------------------------------------------------- batched / served solves
+class Engine:
+    """bl_engine: up to `cap` concurrent solves of one operator class advanced together."""
+
+    def __init__(self, cls: bl_problem, cap: int, arena_bytes: int, device=None, stream=None, ctx=None):
+        import torch
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.cls = cls
+        self.cap = cap
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self._own_ctx = ctx is None
+            self.ctx = ctx if ctx is not None else bl_create(self.stream)
+            nbytes = int(lib.bl_engine_workspace_bytes(cap, arena_bytes))
+            if nbytes == 0:
+                raise BLError(BL_E_ARG, "bl_engine_workspace_bytes rejected the capacity")
+            self.ws, self.ws_ptr = _aligned_workspace(nbytes, self.device)
+        self.handle = C.c_void_p()
+        _check(self.ctx, lib.bl_engine_create(self.ctx, C.byref(cls), cap, self.ws_ptr, nbytes,
+                                              C.byref(self.handle)), "bl_engine_create")
+        self._held = {}
+        self._done = (C.c_int * cap)()
+
+    @staticmethod
+    def slot_bytes(P: bl_problem, s: int) -> int:
+        return int(lib.bl_engine_slot_bytes(C.byref(P), s))
+
+    def admit(self, P: bl_problem, theta, xhat, g, w, rec: Recycle | None, opts: bl_solve_opts) -> int | None:
+        """Slot of the admitted solve, or None when no slot or arena block is free."""
+        slot = C.c_int(-1)
+        code = lib.bl_engine_admit(self.handle, C.byref(P), _theta(theta), _ptr(xhat), _ptr(g), _ptr(w),
+                                   C.byref(rec.rs) if rec is not None else None, C.byref(opts), C.byref(slot))
+        if code == BL_E_WORKSPACE:
+            return None
+        _check(self.ctx, code, "bl_engine_admit")
+        self._held[slot.value] = (P, xhat, g, w, rec)
+        return slot.value
+
+    def step(self, max_iters: int = 1 << 30, return_on_done: bool = True) -> list:
+        nd = C.c_int(0)
+        _check(self.ctx, lib.bl_engine_step(self.handle, max_iters, 1 if return_on_done else 0, self._done,
+                                            C.byref(nd)), "bl_engine_step")
+        return list(self._done[:nd.value])
+
+    def retire(self, slot: int) -> bl_stats:
+        st = bl_stats()
+        code = lib.bl_engine_retire(self.handle, slot, C.byref(st))
+        if code in (BL_E_ARG,):
+            _check(self.ctx, code, "bl_engine_retire")
+        self._held.pop(slot, None)
+        return st
+
+    def query(self):
+        r, f = C.c_int(), C.c_int()
+        fb, lf = C.c_size_t(), C.c_size_t()
+        _check(self.ctx, lib.bl_engine_query(self.handle, C.byref(r), C.byref(f), C.byref(fb), C.byref(lf)),
+               "bl_engine_query")
+        return r.value, f.value, fb.value, lf.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.bl_engine_destroy(self.handle)
+            self.handle = None
+        if getattr(self, "_own_ctx", False) and getattr(self, "ctx", None) is not None:
+            bl_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def hessian_solve_batched(problems, thetas, xhats, gs, ws_, recs, opts: bl_solve_opts, device=None, stream=None,
+                          ctx=None):
+    """bl_hessian_solve_batched over lists of problems / thetas / tensors (recs: list of Recycle or None).
+    Returns (status, [bl_stats])."""
+    import torch
+    k = len(problems)
+    device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    Parr = (bl_problem * k)(*problems)
+    svals = (C.c_int * k)(*[(r.rs.s_cur if r is not None else 0) for r in recs])
+    nbytes = int(lib.bl_batched_workspace_bytes(k, Parr, svals))
+    if nbytes == 0:
+        raise BLError(BL_E_ARG, "bl_batched_workspace_bytes rejected the batch")
+    with torch.cuda.device(device):
+        stream = stream if stream is not None else torch.cuda.current_stream(device)
+        own = ctx is None
+        ctx = ctx if ctx is not None else bl_create(stream)
+        ws, wsp = _aligned_workspace(nbytes, device)
+    try:
+        th = [_theta(t) for t in thetas]
+        tharr = (_P(C.c_double) * k)(*[C.cast(t, _P(C.c_double)) for t in th])
+        xa = (_vp * k)(*[_ptr(t) for t in xhats])
+        ga = (_vp * k)(*[_ptr(t) for t in gs])
+        wa = (_vp * k)(*[_ptr(t) for t in ws_])
+        any_rec = any(r is not None for r in recs)
+        empty = bl_recycle(None, None, None, None, None, 0, 0, 0, 0)
+        rsarr = (bl_recycle * k)(*[(r.rs if r is not None else empty) for r in recs]) if any_rec else None
+        out = (bl_stats * k)()
+        code = lib.bl_hessian_solve_batched(ctx, k, Parr, tharr, xa, ga, wa, rsarr, C.byref(opts), wsp, nbytes, out)
+        if code in (BL_E_ARG, BL_E_SHAPE, BL_E_WORKSPACE, BL_E_HIP):
+            _check(ctx, code, "bl_hessian_solve_batched")
+        if rsarr is not None:   # v_cur written into the array copies
+            for r, rr in zip(recs, rsarr):
+                if r is not None:
+                    r.rs.v_cur = rr.v_cur
+        return code, list(out)
+    finally:
+        if own:
+            bl_destroy(ctx)

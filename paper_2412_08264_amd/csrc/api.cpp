@@ -2,67 +2,25 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "kernels.h"
-#include "stencil.h"
+#include "host.h"
 
 using namespace bl;
-
-struct bl_ctx {
-    hipStream_t stream = nullptr;
-    std::string err;
-    int timing = 0;
-    SolveState* h_state = nullptr;   // pinned
-    double* h_buf = nullptr;         // pinned staging (>= 4096 doubles)
-    int* h_info = nullptr;           // pinned
-    SolveState* h_hdr = nullptr;     // pinned: two slots for the scalar header of in-flight chunks
-    hipEvent_t poll_ev[2] = {};
-    hipEvent_t ev[6] = {};
-    std::vector<hipEvent_t> kev;     // per-launch events (timing mode 2)
-    double kt[4] = {0.0, 0.0, 0.0, 0.0};
-};
+using namespace blh;
 
 namespace {
 
 constexpr int LBFGS_MMAX = 20;
-constexpr int POLL = 8;              // iterations launched between host polls of the stop flag
-// Consumer kernels re-reduce the producer's per-block records in every block; above this many
-// record values a one-block kernel first folds them into one record (keeps the re-reads linear).
-constexpr long REC_LIMIT = 8192;
-constexpr size_t ALIGN = 256;
-
-size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
-
-int nparams(const bl_problem* P) {
-    return P->reg == BL_REG_TV ? 2 : P->n_filters * (1 + P->filter_size * P->filter_size);
-}
-
-bl_status check_problem(bl_ctx* c, const bl_problem* P) {
-    if (!P) return c->err = "null problem", BL_E_ARG;
-    if (P->h < 2 || P->w < 2) return c->err = "image must be at least 2 x 2", BL_E_SHAPE;
-    if ((long long)P->h * P->w > (1LL << 30)) return c->err = "image too large", BL_E_SHAPE;
-    if (P->blur_radius < 0 || P->blur_radius > MAX_R) return c->err = "blur radius outside [0, 8]", BL_E_ARG;
-    if (!(P->blur_sigma > 0.0)) return c->err = "blur sigma must be positive", BL_E_ARG;
-    if (P->reg != BL_REG_TV && P->reg != BL_REG_FILTERS) return c->err = "unknown regulariser", BL_E_ARG;
-    if (P->prec != BL_PREC_FP64 && P->prec != BL_PREC_MIXED) return c->err = "unknown precision", BL_E_ARG;
-    if (P->reg == BL_REG_FILTERS) {
-        if (P->n_filters < 1 || P->n_filters > MAX_NF) return c->err = "n_filters outside [1, 8]", BL_E_ARG;
-        if (P->filter_size < 1 || P->filter_size > MAX_FS || P->filter_size % 2 == 0)
-            return c->err = "filter_size must be odd in [1, 7]", BL_E_ARG;
-        if (P->penalty != BL_PEN_LOG && P->penalty != BL_PEN_QUAD) return c->err = "unknown penalty", BL_E_ARG;
-        if (P->eps < 0.0) return c->err = "eps must be >= 0", BL_E_ARG;
-    }
-    return BL_OK;
-}
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, slots, hdr, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -83,6 +41,8 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.part_doubles = pd;
     size_t o = 0;
     L.state = o;    o += al(sizeof(SolveState));
+    L.slots = o;    o += al(sizeof(Slot));
+    L.hdr = o;      o += al(HDR_BYTES);
     L.fold = o;     o += al(4 * NV_RED * sizeof(double));
     L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
@@ -105,6 +65,8 @@ struct WS {
     Layout L;
     char* base;
     SolveState* st() const { return (SolveState*)(base + L.state); }
+    Slot* slots() const { return (Slot*)(base + L.slots); }
+    int* hdr() const { return (int*)(base + L.hdr); }
     double* part() const { return (double*)(base + L.part); }
     double* part_res() const { return part(); }
     double* part_app() const { return part() + L.part_doubles; }
@@ -132,50 +94,19 @@ bl_status check_ws(bl_ctx* c, const Layout& L, void* ws, size_t ws_bytes, WS& ou
     return BL_OK;
 }
 
-#define HIPCHK(expr)                                                                         \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess) {                                                              \
-            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
-            return BL_E_HIP;                                                                 \
-        }                                                                                    \
-    } while (0)
-
 // Stencil description at (theta); filters: taps and weights copied to the workspace.
 bl_status make_stencil(bl_ctx* c, const bl_problem* P, const double* theta, const WS& ws, Stencil& S) {
-    std::memset(&S, 0, sizeof(S));
+    class_stencil(P, S);
     S.h = P->h;
     S.w = P->w;
     S.n = P->h * P->w;
-    S.R = P->blur_radius;
-    double g[2 * MAX_R + 1], sum = 0.0;
-    for (int a = -S.R; a <= S.R; ++a) {
-        g[a + S.R] = std::exp(-(double)a * a / (2.0 * P->blur_sigma * P->blur_sigma));
-        sum += g[a + S.R];
-    }
-    for (int a = 0; a <= 2 * S.R; ++a) S.g[a] = g[a] / sum;
-    S.reg = P->reg;
     S.tiles_x = (P->w + TW - 1) / TW;
     S.tiles_y = (P->h + TH - 1) / TH;
-    if (!theta) return c->err = "null theta", BL_E_ARG;
-    if (P->reg == BL_REG_TV) {
-        S.lam = std::exp(theta[0]);
-        S.gam2 = std::exp(2.0 * theta[1]);
-        if (!std::isfinite(S.lam) || !std::isfinite(S.gam2) || S.gam2 <= 0.0)
-            return c->err = "theta gives a non-finite or zero smoothing", BL_E_ARG;
-    } else {
-        S.nf = P->n_filters;
-        S.fs = P->filter_size;
-        S.eps = P->eps;
-        S.penalty = P->penalty;
+    TRY(theta_values(c, P, theta, S.lam, S.gam2, c->h_buf));
+    if (P->reg == BL_REG_FILTERS) {
         const int f2 = S.fs * S.fs;
-        double* h = c->h_buf;
-        for (int j = 0; j < S.nf; ++j) {
-            for (int k = 0; k < f2; ++k) h[j * f2 + k] = theta[j * (1 + f2) + 1 + k];
-            h[S.nf * f2 + j] = std::exp(theta[j * (1 + f2)]);
-            if (!std::isfinite(h[S.nf * f2 + j])) return c->err = "theta gives a non-finite weight", BL_E_ARG;
-        }
-        HIPCHK(hipMemcpyAsync(ws.taps(), h, (S.nf * f2 + S.nf) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(ws.taps(), c->h_buf, (S.nf * f2 + S.nf) * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
         // the staging buffer is reused by later calls: make the copy complete
         HIPCHK(hipStreamSynchronize(c->stream));
         S.taps = ws.taps();
@@ -204,12 +135,6 @@ float elapsed(bl_ctx* c, int a, int b) {
 
 }  // namespace
 
-#define TRY(expr)                        \
-    do {                                 \
-        bl_status s_ = (expr);           \
-        if (s_ != BL_OK) return s_;      \
-    } while (0)
-
 extern "C" {
 
 bl_status bl_create(bl_ctx** ctx, void* hip_stream) {
@@ -219,7 +144,7 @@ bl_status bl_create(bl_ctx** ctx, void* hip_stream) {
     if (hipHostMalloc((void**)&c->h_state, sizeof(SolveState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_buf, 8192 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_info, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_hdr, 2 * sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_hdr, 2 * HDR_BYTES, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return BL_E_HIP;
     }
@@ -337,191 +262,51 @@ bl_status bl_lower_grad(bl_ctx* c, const bl_problem* P, const double* theta, con
 }
 
 // ---------------------------------------------------------------------------- Hessian solve
+// One solve is a one-slot batch whose scratch lives in the call's workspace.
 bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, const double* g,
                            double* w, bl_recycle* rs, const bl_solve_opts* o, void* wsp, size_t ws_bytes,
                            bl_stats* out) {
     if (!c) return BL_E_ARG;
     TRY(check_problem(c, P));
-    if (!xhat || !g || !w || !o) return c->err = "null argument", BL_E_ARG;
-    if (o->max_iter < 0 || o->check_every < 1 || o->rr_every < 0 || !(o->tol >= 0.0))
-        return c->err = "invalid solve options", BL_E_ARG;
-    if (o->stop != BL_STOP_RESID && o->stop != BL_STOP_HGERR) return c->err = "unknown stop rule", BL_E_ARG;
-    const int s = rs ? rs->s_cur : 0;
+    if (!xhat || !g || !w) return c->err = "null argument", BL_E_ARG;
+    TRY(check_solve_opts(c, o));
     const int s_max = rs ? rs->s_max : 0, v_cap = rs ? rs->v_cap : 0;
-    if (rs) {
-        if (s < 0 || s > s_max || s_max > S_MAX) return c->err = "s_cur outside [0, s_max] or s_max > 64", BL_E_SHAPE;
-        if (s > 0 && (!rs->U || !rs->C || !rs->mu)) return c->err = "null recycle arrays", BL_E_ARG;
-        if (o->store_basis && (!rs->V || v_cap < 1)) return c->err = "store_basis needs V", BL_E_ARG;
-    }
-    const bool hg = o->stop == BL_STOP_HGERR && s > 0 && rs->Z;
+    if (s_max < 0 || s_max > S_MAX || v_cap < 0) return c->err = "s_max outside [0, 64] or v_cap < 0", BL_E_SHAPE;
     WS ws;
     TRY(check_ws(c, layout(P, s_max, v_cap), wsp, ws_bytes, ws));
-    const int n = P->h * P->w;
-    Stencil S;
     mark(c, 0);
-    TRY(make_stencil(c, P, theta, ws, S));
-    TRY(filter_state(c, S, xhat, ws));
-    // device scalars
-    SolveState* hs = c->h_state;
-    std::memset(hs, 0, sizeof(SolveState));
-    hs->tol = o->tol;
-    hs->hg_tol = o->hg_tol;
-    hs->max_iter = o->max_iter;
-    hs->check_every = o->check_every;
-    hs->stop = o->stop;
-    hs->s = s;
-    hs->v_cap = (o->store_basis && rs) ? v_cap : 0;
-    hs->store_basis = (o->store_basis && rs) ? 1 : 0;
-    hs->hgerr_on = hg ? 1 : 0;
-    SolveState* st = ws.st();
-    HIPCHK(hipMemcpyAsync(st, hs, sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
-    if (s > 0) HIPCHK(hipMemcpyAsync(st->mu, rs->mu, s * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    const double* U = s ? rs->U : nullptr;
-    const double* C = s ? rs->C : nullptr;
-    const double* Z = hg ? rs->Z : nullptr;
-    double* V = (o->store_basis && rs) ? rs->V : nullptr;
-    double* r = ws.vec(0);
-    double* pb[2] = {ws.vec(1), ws.vec(2)};
-    double* q = ws.vec(3);
-    const bool fp32 = P->prec == BL_PREC_MIXED;
-    const int tiles = tiles_of(S), nb1 = red_blocks(n);
-    double* prs = ws.part_res();
-    double* pap = ws.part_app();
-    double* pup = ws.part_upd();
-    // Records handed from kernel to kernel: (pointer, number of blocks), folded when large.
-    auto fold = [&](double* part, int nb, int nv, int slot, const double*& out, int& out_nb) -> bl_status {
-        if ((long)nb * nv > REC_LIMIT) {
-            HIPCHK(launch_finish_sum(part, nb, nv, ws.part_fold(slot), c->stream));
-            out = ws.part_fold(slot);
-            out_nb = 1;
-        } else {
-            out = part;
-            out_nb = nb;
-        }
-        return BL_OK;
-    };
-    const int nz = hg ? s : 0;
-    const double* rec;
-    int rec_nb;
-    // r = g - H w0 (FP64) with record [g.g, C^T r];  w += U c0;  r -= C c0
-    HIPCHK(launch_residual(S, xhat, w, g, r, C, s, prs, c->stream));
-    TRY(fold(prs, tiles, 1 + s, 0, rec, rec_nb));
-    HIPCHK(launch_cg_init(n, w, r, U, C, Z, st, rec, rec_nb, pup, c->stream));
+    Batch B;
+    TRY(B.init(c, P, 1, ws.slots(), ws.hdr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
+    SlotBuffers buf{};
+    buf.r = ws.vec(0);
+    buf.p0 = ws.vec(1);
+    buf.p1 = ws.vec(2);
+    buf.q = ws.vec(3);
+    buf.d1 = ws.d1();
+    buf.d2 = ws.d2();
+    buf.d2f = ws.d2f();
+    buf.taps = ws.taps();
+    buf.rec_res = ws.part_res();
+    buf.rec_app = ws.part_app();
+    buf.rec_upd = ws.part_upd();
+    buf.fold = ws.part_fold(0);
+    buf.st = ws.st();
+    const SolveSpec sp{P, theta, xhat, g, w, rs, o};
+    TRY(B.admit(0, sp, buf, c->h_buf));
     mark(c, 1);
-    const int rr_every = fp32 ? o->rr_every : 0;
-    const bool ktime = c->timing == 2;
-    std::vector<int> launched;   // iteration index of each timed launch triple
-    // Iteration j = apply(j) [stop test on r_j, p, q = H p] + update(j) [alpha, w, r].  The
-    // last index j = max_iter launches apply only: it tests r_max_iter.
-    int j = 0;
-    auto launch_iter = [&]() -> bl_status {
-        if (ktime) {
-            const size_t need = 3 * (launched.size() + 1);
-            while (c->kev.size() < need) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                c->kev.push_back(e);
-            }
-            HIPCHK(hipEventRecord(c->kev[3 * launched.size()], c->stream));
-        }
-        const double* ru;
-        int ru_nb;
-        TRY(fold(pup, nb1, 1 + nz, 1, ru, ru_nb));
-        HIPCHK(launch_cg_apply(S, fp32, j, xhat, r, pb[j & 1], pb[(j + 1) & 1], q, C, V, st, ru, ru_nb, pap,
-                               c->stream));
-        if (ktime) HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 1], c->stream));
-        if (j < o->max_iter) {
-            const double* ra;
-            int ra_nb;
-            TRY(fold(pap, tiles, 1 + s, 2, ra, ra_nb));
-            HIPCHK(launch_cg_update(n, j, w, r, pb[(j + 1) & 1], q, C, Z, st, ra, ra_nb, pup, c->stream));
-        }
-        if (ktime) {
-            HIPCHK(hipEventRecord(c->kev[3 * launched.size() + 2], c->stream));
-            launched.push_back(j);
-        }
-        ++j;
-        return BL_OK;
-    };
-    const size_t hdr = offsetof(SolveState, e);
-    if (!rr_every) {
-        // Chunks of POLL iterations; the next chunk is enqueued before the host waits for the
-        // stop flag of the previous one, so the device never idles on a poll.  Iterations
-        // launched after the stop exit at once (the kernels test the device flag).
-        auto enqueue = [&](int chunk) -> bl_status {
-            for (int k = 0; k < POLL && j <= o->max_iter; ++k) TRY(launch_iter());
-            HIPCHK(hipMemcpyAsync(&c->h_hdr[chunk & 1], st, hdr, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipEventRecord(c->poll_ev[chunk & 1], c->stream));
-            return BL_OK;
-        };
-        int chunk = 0;
-        TRY(enqueue(0));
-        for (;;) {
-            const bool more = j <= o->max_iter;
-            if (more) TRY(enqueue(chunk + 1));
-            HIPCHK(hipEventSynchronize(c->poll_ev[chunk & 1]));
-            if (c->h_hdr[chunk & 1].done || !more) break;
-            ++chunk;
-        }
-    } else {
-        for (;;) {
-            const int chunk = std::min(POLL, rr_every - (j % rr_every));
-            for (int k = 0; k < chunk && j <= o->max_iter; ++k) TRY(launch_iter());
-            HIPCHK(hipMemcpyAsync(hs, st, hdr, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            const bool converged = hs->done && hs->status == BL_OK;
-            if (hs->done && !converged) break;
-            if (!converged && j % rr_every != 0 && j <= o->max_iter) continue;
-            if (!converged && j > o->max_iter) break;
-            // residual replacement in FP64: r = g - H w, z = C^T r, r -= C z; the apply step
-            // of the current index re-tests (and goes on if the true residual misses the test)
-            if (converged) j = hs->iters;
-            HIPCHK(launch_residual(S, xhat, w, g, r, C, s, prs, c->stream));
-            TRY(fold(prs, tiles, 1 + s, 0, rec, rec_nb));
-            HIPCHK(launch_cg_replace(n, r, C, Z, st, rec, rec_nb, pup, c->stream));
-            TRY(launch_iter());
-            HIPCHK(hipMemcpyAsync(hs, st, hdr, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            if (hs->done || j > o->max_iter) break;
-        }
-    }
+    std::vector<int> done;
+    TRY(B.run(INT_MAX, false, done));
     mark(c, 2);
-    if (s > 0) HIPCHK(launch_cg_finish(n, w, U, st, c->stream));
-    mark(c, 3);
-    HIPCHK(hipMemcpyAsync(hs, st, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    int status = hs->done ? hs->status : BL_E_NOT_CONVERGED;
-    if (ktime) {   // durations of launches whose iteration actually ran
-        for (size_t u = 0; u < launched.size(); ++u) {
-            if (launched[u] >= hs->iters + (status == BL_E_INDEFINITE ? 1 : 0)) break;
-            float a = 0.f, b = 0.f;
-            HIPCHK(hipEventElapsedTime(&a, c->kev[3 * u], c->kev[3 * u + 1]));
-            HIPCHK(hipEventElapsedTime(&b, c->kev[3 * u + 1], c->kev[3 * u + 2]));
-            c->kt[0] += a;
-            c->kt[1] += 1.0;
-            c->kt[2] += b;
-            c->kt[3] += 1.0;
-        }
-    }
-    if (rs && o->store_basis) {
-        int nv = hs->iters + (status == BL_E_INDEFINITE ? 1 : 0);
-        rs->v_cur = std::min(nv, v_cap);
-    }
+    bl_stats st;
+    B.stats(0, &st);
     if (out) {
-        out->iters = hs->iters;
-        out->status = status;
-        out->t = 0;
-        out->s_cur = s;
-        out->res_norm = std::sqrt(std::max(hs->rho2[hs->iters & 1], 0.0));
-        out->res0_norm = hs->res0;
-        out->g_norm = hs->gnorm;
-        out->est = hs->est;
+        *out = st;
         out->ms[0] = elapsed(c, 0, 1);
         out->ms[1] = elapsed(c, 1, 2);
-        out->ms[2] = elapsed(c, 2, 3);
-        out->ms[3] = elapsed(c, 0, 3);
+        out->ms[2] = 0.0;
+        out->ms[3] = elapsed(c, 0, 2);
     }
-    return (bl_status)status;
+    return (bl_status)st.status;
 }
 
 // ---------------------------------------------------------------------------- hypergradient

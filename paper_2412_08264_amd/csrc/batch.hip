@@ -1,0 +1,474 @@
+// Recycled-CG kernels over a batch of independent solves ("slots").
+//
+// A launch covers every active slot: block b works for slot map[b].x on its local tile or
+// pixel block map[b].y.  Slots differ in image size, recycle dimension, iteration index and
+// stop state; they share the operator class (regulariser, blur, filter size, precision).
+// No kernel synchronises its blocks: each kernel writes one partial record per block into
+// its slot's record array; the next kernel reduces the records of its slot in every block
+// (fixed order), so a slot's scalars and decisions are identical in every block and do
+// not depend on the other slots.  Block 0 of a slot stores the scalars for the host.
+#include "kernels.h"
+#include "stencil.h"
+
+namespace bl {
+
+__device__ __forceinline__ void slot_stencil(Stencil& S, const Slot& sl) {
+    S.h = sl.h;
+    S.w = sl.width;
+    S.n = sl.n;
+    S.tiles_x = sl.tiles_x;
+    S.lam = sl.lam;
+    S.gam2 = sl.gam2;
+    S.taps = sl.taps;
+    S.lamj = sl.lamj;
+    S.d2 = sl.d2;
+    S.d2f = sl.d2f;
+}
+
+__device__ __forceinline__ void slot_tile(const Slot& sl, int local, int& r0, int& c0) {
+    const int t = xcd_tile(local, sl.ntiles);
+    r0 = (t / sl.tiles_x) * TH;
+    c0 = (t % sl.tiles_x) * TW;
+}
+
+// Records a consumer reads: the producer's per-block array, or its folded record.
+__device__ __forceinline__ const double* slot_rec(const Slot& sl, int which, int& nb) {
+    if (which == 0) {
+        nb = sl.fold_res ? 1 : sl.ntiles;
+        return sl.fold_res ? sl.fold : sl.rec_res;
+    }
+    if (which == 1) {
+        nb = sl.fold_app ? 1 : sl.ntiles;
+        return sl.fold_app ? sl.fold + NV_RED : sl.rec_app;
+    }
+    nb = sl.fold_upd ? 1 : sl.npix;
+    return sl.fold_upd ? sl.fold + 2 * NV_RED : sl.rec_upd;
+}
+
+// ------------------------------------------------------------------ residual g - H w
+// r = g - H w in FP64 and the record [g.g, C^T r].  With `periodic` set (a scheduled
+// residual replacement) a slot that has already stopped is left alone.
+template <int RB>
+__global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __restrict__ slots, BatchMap M,
+                                                   int periodic) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.ntiles || (periodic && sl.st->done)) return;
+    Stencil S = base;
+    slot_stencil(S, sl);
+    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
+    int r0, c0;
+    slot_tile(sl, m.y, r0, c0);
+    const int gi = r0 + (int)threadIdx.x / TW, gj = c0 + (int)threadIdx.x % TW;
+    const bool own = gi < S.h && gj < S.w;
+    const int i = own ? gi * S.w + gj : 0;
+    const double gv = own ? sl.g[i] : 0.0;
+    stage_region<double>(lds + L.o_v, S, L, r0, c0, [&](int gidx) { return sl.w[gidx]; });
+    if (S.reg == BL_REG_TV) stage_xhat<double>(lds + L.o_x, S, sl.xhat, r0, c0);
+    __syncthreads();
+    hvp_tile<double, RB>(lds, S, L, sl.xhat, r0, c0, S.reg == BL_REG_TV);
+    __syncthreads();
+    const double ov = own ? gv - lds[L.o_out + threadIdx.x] : 0.0;
+    if (own) sl.r[i] = ov;
+    const int s = sl.s;
+    block_partials(
+        sl.rec_res, 1 + s,
+        [&](int k) {
+            if (!own) return 0.0;
+            return k == 0 ? gv * gv : sl.C[(size_t)(k - 1) * S.n + i] * ov;
+        },
+        m.y);
+}
+
+// Set-up: c0 = C^T r (records), w += U c0, r -= C c0, record [r.r, Z^T r].
+__global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, BatchMap M) {
+    __shared__ double tot[NT];
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.npix) return;
+    const int s = sl.s, nz = sl.nz, n = sl.n;
+    int nb;
+    const double* rec = slot_rec(sl, 0, nb);
+    reduce_partials(rec, nb, 1 + s, tot);
+    if (m.y == 0 && threadIdx.x == 0) sl.st->gnorm = sqrt(tot[0]);
+    const double* c0 = tot + 1;
+    const int i = m.y * NT + threadIdx.x;
+    const bool in = i < n;
+    double ri = 0.0;
+    if (in) {
+        sl.w[i] += combo(sl.U, n, i, c0, s);
+        ri = sl.r[i] - combo(sl.C, n, i, c0, s);
+        sl.r[i] = ri;
+    }
+    block_partials(
+        sl.rec_upd, 1 + nz,
+        [&](int k) -> double {
+            if (!in) return 0.0;
+            return k == 0 ? ri * ri : sl.Z[(size_t)(k - 1) * n + i] * ri;
+        },
+        m.y);
+}
+
+// Iteration j = step - j0, first half: stop test from the update records, beta, p, q = H p,
+// V store, record [p.q, C^T q].  A stopped slot's blocks leave after the record reduction
+// (its flag is read by one thread and published by the reduction's barrier: uniform per
+// block; a flag set by block 0 during this launch follows from the same decision every
+// block of the slot takes).
+constexpr int CPRE = 24;
+template <typename T, int RB>
+__global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    __shared__ double tot[NT];
+    __shared__ int sdone;
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.ntiles) return;
+    SolveState* st = sl.st;
+    const int j = step - sl.j0;
+    if (threadIdx.x == 0) sdone = st->done;
+    const int s = sl.s, nz = sl.nz;
+    int nb;
+    const double* rec = slot_rec(sl, 2, nb);
+    reduce_partials(rec, nb, 1 + nz, tot);
+    if (sdone) return;
+    const double rho_prev = j > 0 ? st->rho2[(j - 1) & 1] : 1.0;
+    const bool store_basis = st->store_basis && j < st->v_cap;
+    const double rho = tot[0];
+    const Decision dec = decide(st, j, rho, tot + 1);
+    if (m.y == 0) {
+        for (int k = threadIdx.x; k < nz; k += NT) st->zr[k] = tot[1 + k];
+        if (threadIdx.x == 0) {
+            st->rho2[j & 1] = rho;
+            st->est = dec.est;
+            st->iters = j;
+            if (j == 0) st->res0 = sqrt(rho);
+            if (dec.done) {
+                st->status = dec.status;
+                st->done = 1;
+            }
+        }
+    }
+    if (dec.done) return;
+    Stencil S = base;
+    slot_stencil(S, sl);
+    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
+    const bool first = (j == 0);
+    const double beta = first ? 0.0 : rho / rho_prev;
+    const double* __restrict__ r = sl.r;
+    const double* __restrict__ p_old = sl.p[j & 1];
+    double* __restrict__ p_new = sl.p[(j + 1) & 1];
+    int r0, c0;
+    slot_tile(sl, m.y, r0, c0);
+    const int gi = r0 + (int)threadIdx.x / TW, gj = c0 + (int)threadIdx.x % TW;
+    const bool own = gi < S.h && gj < S.w;
+    const int i = own ? gi * S.w + gj : 0;
+    const double ri = own ? r[i] : 0.0;
+    const double pi = (own && !first) ? p_old[i] : 0.0;
+    double cpre[CPRE];
+#pragma unroll
+    for (int k = 0; k < CPRE; ++k) cpre[k] = (own && k < s) ? sl.C[(size_t)k * S.n + i] : 0.0;
+    stage_region<T>(lds + L.o_v, S, L, r0, c0,
+                    [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
+    if (S.reg == BL_REG_TV) stage_xhat<T>(lds + L.o_x, S, sl.xhat, r0, c0);
+    __syncthreads();
+    hvp_tile<T, RB>(lds, S, L, sl.xhat, r0, c0, S.reg == BL_REG_TV);
+    __syncthreads();
+    const double pn = first ? ri : ri + beta * pi;
+    const double qq = own ? (double)lds[L.o_out + threadIdx.x] : 0.0;
+    if (own) {
+        p_new[i] = pn;
+        sl.q[i] = qq;
+        if (store_basis) sl.V[(size_t)j * S.n + i] = ri / sqrt(rho);
+    }
+    const double pv = own ? pn : 0.0;
+    block_partials(
+        sl.rec_app, 1 + s,
+        [&](int k) {
+            if (!own) return 0.0;
+            if (k == 0) return pv * qq;
+            const int c = k - 1;
+            double cv = 0.0;
+#pragma unroll
+            for (int u = 0; u < CPRE; ++u)
+                if (u == c) cv = cpre[u];
+            if (c >= CPRE) cv = sl.C[(size_t)c * S.n + i];
+            return cv * qq;
+        },
+        m.y);
+}
+
+// Iteration j, second half: sigma, e from the apply records; alpha = rho_j / sigma;
+// w += alpha p;  r -= alpha (q - C e);  z -= alpha e;  record [r.r, Z^T r].
+constexpr int UPRE = 24;
+__global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, int step) {
+    __shared__ double tot[NT];
+    __shared__ int sdone;
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.npix) return;
+    SolveState* st = sl.st;
+    const int j = step - sl.j0;
+    if (threadIdx.x == 0) sdone = st->done;
+    const int s = sl.s, nz = sl.nz, n = sl.n;
+    const int i = m.y * NT + threadIdx.x;
+    const bool in = i < n;
+    const double* p = sl.p[(j + 1) & 1];
+    const double wi = in ? sl.w[i] : 0.0, pi = in ? p[i] : 0.0, ri0 = in ? sl.r[i] : 0.0, qi = in ? sl.q[i] : 0.0;
+    double cpre[UPRE], zpre[UPRE];
+#pragma unroll
+    for (int k = 0; k < UPRE; ++k) {
+        cpre[k] = (in && k < s) ? sl.C[(size_t)k * n + i] : 0.0;
+        zpre[k] = (in && k < nz) ? sl.Z[(size_t)k * n + i] : 0.0;
+    }
+    int nb;
+    const double* rec = slot_rec(sl, 1, nb);
+    reduce_partials(rec, nb, 1 + s, tot);
+    if (sdone) return;
+    const double rho = st->rho2[j & 1];
+    const double sigma = tot[0];
+    if (!(sigma > 0.0)) {
+        if (m.y == 0 && threadIdx.x == 0) {
+            st->status = (sigma != sigma || fabs(sigma) == INFINITY) ? BL_E_NONFINITE : BL_E_INDEFINITE;
+            st->iters = j;
+            st->done = 1;
+        }
+        return;
+    }
+    const double alpha = rho / sigma;
+    const double* e = tot + 1;
+    if (m.y == 0) {
+        for (int k = threadIdx.x; k < s; k += NT) st->zacc[k] -= alpha * e[k];
+        if (threadIdx.x == 0) st->alpha = alpha;
+    }
+    double ce = 0.0;
+#pragma unroll
+    for (int k = 0; k < UPRE; ++k)
+        if (k < s) ce += cpre[k] * e[k];
+    for (int k = UPRE; k < s; ++k) ce += (in ? sl.C[(size_t)k * n + i] : 0.0) * e[k];
+    const double ri = ri0 - alpha * (qi - ce);
+    if (in) {
+        sl.w[i] = wi + alpha * pi;
+        sl.r[i] = ri;
+    }
+    block_partials(
+        sl.rec_upd, 1 + nz,
+        [&](int k) -> double {
+            if (!in) return 0.0;
+            if (k == 0) return ri * ri;
+            const int c = k - 1;
+            double zv = 0.0;
+#pragma unroll
+            for (int u = 0; u < UPRE; ++u)
+                if (u == c) zv = zpre[u];
+            if (c >= UPRE) zv = sl.Z[(size_t)c * n + i];
+            return zv * ri;
+        },
+        m.y);
+}
+
+// Residual replacement: r holds t = g - H w (record [g.g, C^T t]): z := C^T t,
+// r := t - C z, and the slot resumes (its next apply step re-tests the replaced residual).
+// With `periodic` set a slot that has already stopped is left alone.
+__global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots, BatchMap M, int periodic) {
+    __shared__ double tot[NT];
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.npix || (periodic && sl.st->done)) return;
+    const int s = sl.s, nz = sl.nz, n = sl.n;
+    int nb;
+    const double* rec = slot_rec(sl, 0, nb);
+    reduce_partials(rec, nb, 1 + s, tot);
+    const double* c = tot + 1;
+    if (m.y == 0) {
+        for (int k = threadIdx.x; k < s; k += NT) sl.st->zacc[k] = c[k];
+        if (threadIdx.x == 0) {
+            sl.st->done = 0;
+            sl.st->status = BL_OK;
+        }
+    }
+    const int i = m.y * NT + threadIdx.x;
+    const bool in = i < n;
+    double ri = 0.0;
+    if (in) {
+        ri = sl.r[i] - combo(sl.C, n, i, c, s);
+        sl.r[i] = ri;
+    }
+    block_partials(
+        sl.rec_upd, 1 + nz,
+        [&](int k) -> double {
+            if (!in) return 0.0;
+            return k == 0 ? ri * ri : sl.Z[(size_t)(k - 1) * n + i] * ri;
+        },
+        m.y);
+}
+
+// w += U z.
+__global__ void __launch_bounds__(NT) k_b_finish(const Slot* __restrict__ slots, BatchMap M) {
+    __shared__ double z[S_MAX];
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.npix) return;
+    const int s = sl.s;
+    for (int k = threadIdx.x; k < s; k += NT) z[k] = sl.st->zacc[k];
+    __syncthreads();
+    const int i = m.y * NT + threadIdx.x;
+    if (i < sl.n) sl.w[i] += combo(sl.U, sl.n, i, z, s);
+}
+
+// Fold the records of kind `which` (0 residual, 1 apply, 2 update): one block per listed slot.
+__global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which) {
+    __shared__ double tot[NT];
+    const Slot& sl = slots[M.slot[blockIdx.x]];
+    int nb, nv;
+    const double* rec;
+    if (which == 0) {
+        nb = sl.ntiles;
+        nv = 1 + sl.s;
+        rec = sl.rec_res;
+    } else if (which == 1) {
+        nb = sl.ntiles;
+        nv = 1 + sl.s;
+        rec = sl.rec_app;
+    } else {
+        nb = sl.npix;
+        nv = 1 + sl.nz;
+        rec = sl.rec_upd;
+    }
+    reduce_partials(rec, nb, nv, tot);
+    for (int k = threadIdx.x; k < nv; k += NT) sl.fold[which * NV_RED + k] = tot[k];
+}
+
+// Admission: descriptor `v` into slots[idx]; a zeroed SolveState with the settings of `init`
+// and the selected generalized singular values mu (s values, device; may be null when s = 0).
+__global__ void __launch_bounds__(NT) k_b_admit(Slot* __restrict__ slots, int idx, Slot v, StateInit init,
+                                                const double* __restrict__ mu) {
+    SolveState* st = v.st;
+    int* words = reinterpret_cast<int*>(st);
+    for (int k = threadIdx.x; k < (int)(sizeof(SolveState) / sizeof(int)); k += NT) words[k] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        slots[idx] = v;
+        st->tol = init.tol;
+        st->hg_tol = init.hg_tol;
+        st->max_iter = init.max_iter;
+        st->check_every = init.check_every;
+        st->stop = init.stop;
+        st->s = init.s;
+        st->v_cap = init.v_cap;
+        st->store_basis = init.store_basis;
+        st->hgerr_on = init.hgerr_on;
+    }
+    for (int k = threadIdx.x; k < init.s; k += NT) st->mu[k] = mu[k];
+}
+
+// Restart index: the slot's next apply step runs iteration j = step - j0.
+__global__ void k_b_set_j0(Slot* __restrict__ slots, int idx, int j0) {
+    if (threadIdx.x == 0) slots[idx].j0 = j0;
+}
+
+// Scalar headers of the listed slots into out[slot index * HDR_BYTES] (4-byte words).
+__global__ void __launch_bounds__(NT) k_b_headers(const Slot* __restrict__ slots, BatchMap M, int* __restrict__ out) {
+    constexpr int WPS = HDR_BYTES / 4;
+    const int t = blockIdx.x * NT + threadIdx.x;
+    const int k = t / WPS, wd = t - k * WPS;
+    if (k >= M.ns) return;
+    const int idx = M.slot[k];
+    out[(size_t)idx * WPS + wd] = reinterpret_cast<const int*>(slots[idx].st)[wd];
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename K>
+static void allow_lds_b(K kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+#define BL_RADIUS_SWITCH_B(R, CALL) \
+    switch (R) {                    \
+        case 0: CALL(0); break;     \
+        case 1: CALL(1); break;     \
+        case 2: CALL(2); break;     \
+        case 3: CALL(3); break;     \
+        case 4: CALL(4); break;     \
+        case 5: CALL(5); break;     \
+        case 6: CALL(6); break;     \
+        case 7: CALL(7); break;     \
+        default: CALL(8); break;    \
+    }
+
+static inline dim3 map_grid(const BatchMap& M) { return dim3(M.off[M.ns]); }
+
+hipError_t launch_b_residual(const Stencil& base, const Slot* slots, const BatchMap& M, int periodic,
+                             hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    const size_t lds = tile_lds_bytes<double>(base.R, base.reg, base.fs);
+#define RES_B(RB)                                                                                           \
+    allow_lds_b(k_b_residual<RB>, lds);                                                                     \
+    hipLaunchKernelGGL((k_b_residual<RB>), map_grid(M), dim3(NT), lds, stream, base, slots, M, periodic);
+    BL_RADIUS_SWITCH_B(base.R, RES_B)
+#undef RES_B
+    return hipGetLastError();
+}
+
+hipError_t launch_b_apply(const Stencil& base, bool fp32, const Slot* slots, const BatchMap& M, int step,
+                          hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    const size_t lds = fp32 ? tile_lds_bytes<float>(base.R, base.reg, base.fs)
+                            : tile_lds_bytes<double>(base.R, base.reg, base.fs);
+#define APP_B(RB)                                                                                              \
+    if (fp32) {                                                                                                \
+        allow_lds_b(k_b_apply<float, RB>, lds);                                                                \
+        hipLaunchKernelGGL((k_b_apply<float, RB>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step);  \
+    } else {                                                                                                   \
+        allow_lds_b(k_b_apply<double, RB>, lds);                                                               \
+        hipLaunchKernelGGL((k_b_apply<double, RB>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step); \
+    }
+    BL_RADIUS_SWITCH_B(base.R, APP_B)
+#undef APP_B
+    return hipGetLastError();
+}
+
+hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_init, map_grid(M), dim3(NT), 0, stream, slots, M);
+    return hipGetLastError();
+}
+hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_update, map_grid(M), dim3(NT), 0, stream, slots, M, step);
+    return hipGetLastError();
+}
+hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_replace, map_grid(M), dim3(NT), 0, stream, slots, M, periodic);
+    return hipGetLastError();
+}
+hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_finish, map_grid(M), dim3(NT), 0, stream, slots, M);
+    return hipGetLastError();
+}
+hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, hipStream_t stream) {
+    if (list.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_fold, dim3(list.ns), dim3(NT), 0, stream, slots, list, which);
+    return hipGetLastError();
+}
+hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_b_admit, dim3(1), dim3(NT), 0, stream, slots, idx, v, init, mu);
+    return hipGetLastError();
+}
+hipError_t launch_b_set_j0(Slot* slots, int idx, int j0, hipStream_t stream) {
+    hipLaunchKernelGGL(k_b_set_j0, dim3(1), dim3(64), 0, stream, slots, idx, j0);
+    return hipGetLastError();
+}
+hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, hipStream_t stream) {
+    if (list.ns == 0) return hipSuccess;
+    const int words = list.ns * (HDR_BYTES / 4);
+    hipLaunchKernelGGL(k_b_headers, dim3((words + NT - 1) / NT), dim3(NT), 0, stream, slots, list, out);
+    return hipGetLastError();
+}
+
+}  // namespace bl

@@ -53,6 +53,67 @@ struct SolveState {
     double c0[S_MAX];     // C^T r0 / scratch
 };
 
+// One independent Krylov solve inside a batched launch (device memory).  Blocks of a
+// tile-grid launch map to (slot, local tile) and blocks of a pixel-grid launch to (slot,
+// local block) through per-launch maps; each slot reduces only its own records, in the
+// same order as when it runs alone, so its results do not depend on the batch.
+struct Slot {
+    int h, width, n, tiles_x, ntiles, npix;   // image, tiles, pixel blocks (ceil(n / NT))
+    int j0;                               // global step index at which the slot started
+    int s, nz;                            // recycle columns; error-estimate columns (0: off)
+    int fold_app, fold_upd, fold_res;     // records folded by k_fold before use
+    int pad;
+    double lam, gam2;                     // TV weight e^{theta0}, smoothing e^{2 theta1}
+    const double* taps;                   // filters: taps, weights, phi'' maps
+    const double* lamj;
+    const double* d2;
+    const float* d2f;
+    const double* xhat;
+    const double* g;
+    double* w;
+    double* r;
+    double* p[2];
+    double* q;
+    const double* U;
+    const double* C;
+    const double* Z;
+    double* V;
+    SolveState* st;
+    double* rec_res;                      // records: residual (tiles), apply (tiles), update (pixel blocks)
+    double* rec_app;
+    double* rec_upd;
+    double* fold;                         // 3 folded records of NV_RED values
+};
+
+// Block-to-slot map of one batched launch, passed by value: slot k of the launch is
+// slots[slot[k]] and owns blocks off[k] .. off[k+1]-1.  In tile-grid launches every off[k]
+// is a multiple of 8, so a slot's local tile index modulo 8 is the XCD its block runs on.
+constexpr int B_MAX = 64;       // slots per batched launch
+struct BatchMap {
+    int ns;
+    int slot[B_MAX];
+    int off[B_MAX + 1];
+};
+
+// Slot and local block of block b (binary search over the offsets; uniform per block).
+__device__ __forceinline__ int2 map_block(const BatchMap& M, int b) {
+    int lo = 0, hi = M.ns;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b >= M.off[mid]) lo = mid;
+        else hi = mid;
+    }
+    return make_int2(M.slot[lo], b - M.off[lo]);
+}
+
+// Per-solve settings written into a fresh SolveState at admission.
+struct StateInit {
+    double tol, hg_tol;
+    int max_iter, check_every, stop, s, v_cap, store_basis, hgerr_on;
+};
+
+constexpr int HDR_BYTES = (int)offsetof(SolveState, e);   // scalar header polled by the host
+
 // ------------------------------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -78,7 +139,7 @@ __device__ __forceinline__ double block_sum(double val, double* red) {
 // Each wavefront reduces with shuffles, one barrier, then threads k < nv add the NWAVE
 // wave sums in fixed order and write part[blockIdx.x * nv + k].
 template <typename Val>
-__device__ __forceinline__ void block_partials(double* part, int nv, Val val) {
+__device__ __forceinline__ void block_partials(double* part, int nv, Val val, int rec_index = -1) {
     __shared__ double wred[NWAVE][NV_RED];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k0 = 0; k0 < nv; k0 += 8) {
@@ -94,11 +155,12 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val) {
         }
     }
     __syncthreads();
+    const size_t rec = rec_index < 0 ? (size_t)blockIdx.x : (size_t)rec_index;
     for (int k = threadIdx.x; k < nv; k += NT) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NWAVE; ++w) s += wred[w][k];
-        part[(size_t)blockIdx.x * nv + k] = s;
+        part[rec * nv + k] = s;
     }
 }
 

@@ -1,0 +1,725 @@
+// Batched recycled CG (host side): slot admission, block maps, chunked pipelined stepping,
+// mixed-precision residual replacement and retirement; the C-ABI engine and the batched
+// solve built on it.  Recycled CG as in Section 2.2.2 (Galerkin counterpart of RMINRES),
+// stop tests of Section 4.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <utility>
+
+#include "host.h"
+
+using namespace bl;
+
+namespace blh {
+
+int nparams(const bl_problem* P) {
+    return P->reg == BL_REG_TV ? 2 : P->n_filters * (1 + P->filter_size * P->filter_size);
+}
+
+bl_status check_problem(bl_ctx* c, const bl_problem* P) {
+    if (!P) return c->err = "null problem", BL_E_ARG;
+    if (P->h < 2 || P->w < 2) return c->err = "image must be at least 2 x 2", BL_E_SHAPE;
+    if ((long long)P->h * P->w > (1LL << 30)) return c->err = "image too large", BL_E_SHAPE;
+    if (P->blur_radius < 0 || P->blur_radius > MAX_R) return c->err = "blur radius outside [0, 8]", BL_E_ARG;
+    if (!(P->blur_sigma > 0.0)) return c->err = "blur sigma must be positive", BL_E_ARG;
+    if (P->reg != BL_REG_TV && P->reg != BL_REG_FILTERS) return c->err = "unknown regulariser", BL_E_ARG;
+    if (P->prec != BL_PREC_FP64 && P->prec != BL_PREC_MIXED) return c->err = "unknown precision", BL_E_ARG;
+    if (P->reg == BL_REG_FILTERS) {
+        if (P->n_filters < 1 || P->n_filters > MAX_NF) return c->err = "n_filters outside [1, 8]", BL_E_ARG;
+        if (P->filter_size < 1 || P->filter_size > MAX_FS || P->filter_size % 2 == 0)
+            return c->err = "filter_size must be odd in [1, 7]", BL_E_ARG;
+        if (P->penalty != BL_PEN_LOG && P->penalty != BL_PEN_QUAD) return c->err = "unknown penalty", BL_E_ARG;
+        if (P->eps < 0.0) return c->err = "eps must be >= 0", BL_E_ARG;
+    }
+    return BL_OK;
+}
+
+bl_status check_solve_opts(bl_ctx* c, const bl_solve_opts* o) {
+    if (!o) return c->err = "null solve options", BL_E_ARG;
+    if (o->max_iter < 0 || o->check_every < 1 || o->rr_every < 0 || !(o->tol >= 0.0))
+        return c->err = "invalid solve options", BL_E_ARG;
+    if (o->stop != BL_STOP_RESID && o->stop != BL_STOP_HGERR) return c->err = "unknown stop rule", BL_E_ARG;
+    return BL_OK;
+}
+
+void class_stencil(const bl_problem* P, Stencil& S) {
+    std::memset(&S, 0, sizeof(S));
+    S.R = P->blur_radius;
+    double g[2 * MAX_R + 1], sum = 0.0;
+    for (int a = -S.R; a <= S.R; ++a) {
+        g[a + S.R] = std::exp(-(double)a * a / (2.0 * P->blur_sigma * P->blur_sigma));
+        sum += g[a + S.R];
+    }
+    for (int a = 0; a <= 2 * S.R; ++a) S.g[a] = g[a] / sum;
+    S.reg = P->reg;
+    if (P->reg == BL_REG_FILTERS) {
+        S.nf = P->n_filters;
+        S.fs = P->filter_size;
+        S.eps = P->eps;
+        S.penalty = P->penalty;
+    }
+}
+
+bl_status theta_values(bl_ctx* c, const bl_problem* P, const double* theta, double& lam, double& gam2,
+                       double* taps_host) {
+    if (!theta) return c->err = "null theta", BL_E_ARG;
+    lam = gam2 = 0.0;
+    if (P->reg == BL_REG_TV) {
+        lam = std::exp(theta[0]);
+        gam2 = std::exp(2.0 * theta[1]);
+        if (!std::isfinite(lam) || !std::isfinite(gam2) || gam2 <= 0.0)
+            return c->err = "theta gives a non-finite or zero smoothing", BL_E_ARG;
+        return BL_OK;
+    }
+    const int nf = P->n_filters, f2 = P->filter_size * P->filter_size;
+    for (int j = 0; j < nf; ++j) {
+        for (int k = 0; k < f2; ++k) taps_host[j * f2 + k] = theta[j * (1 + f2) + 1 + k];
+        taps_host[nf * f2 + j] = std::exp(theta[j * (1 + f2)]);
+        if (!std::isfinite(taps_host[nf * f2 + j])) return c->err = "theta gives a non-finite weight", BL_E_ARG;
+    }
+    return BL_OK;
+}
+
+bool same_class(const bl_problem* a, const bl_problem* b) {
+    if (a->blur_radius != b->blur_radius || a->blur_sigma != b->blur_sigma || a->reg != b->reg || a->prec != b->prec)
+        return false;
+    if (a->reg == BL_REG_FILTERS)
+        return a->n_filters == b->n_filters && a->filter_size == b->filter_size && a->eps == b->eps &&
+               a->penalty == b->penalty;
+    return true;
+}
+
+static int ntiles_of(int h, int w) { return ((w + TW - 1) / TW) * ((h + TH - 1) / TH); }
+static int npix_of(long n) { return (int)((n + NT - 1) / NT); }
+
+size_t slot_bytes(const bl_problem* P, int s) {
+    const size_t n = (size_t)P->h * P->w;
+    const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
+    const size_t nt = ntiles_of(P->h, P->w), np = npix_of((long)n);
+    return 4 * al(n * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al((size_t)TAPS_MAX * 8) +
+           2 * al(nt * (1 + s) * 8) + al(np * (1 + s) * 8) + al(3 * NV_RED * 8);
+}
+
+SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
+    const size_t n = (size_t)P->h * P->w;
+    const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
+    const size_t nt = ntiles_of(P->h, P->w), np = npix_of((long)n);
+    SlotBuffers B{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + o;
+        o += al(bytes);
+        return p;
+    };
+    B.r = (double*)take(n * 8);
+    B.p0 = (double*)take(n * 8);
+    B.p1 = (double*)take(n * 8);
+    B.q = (double*)take(n * 8);
+    B.d1 = nf ? (double*)take(nf * n * 8) : nullptr;
+    B.d2 = nf ? (double*)take(nf * n * 8) : nullptr;
+    B.d2f = nf ? (float*)take(nf * n * 4) : nullptr;
+    B.taps = (double*)take((size_t)TAPS_MAX * 8);
+    B.rec_res = (double*)take(nt * (1 + s) * 8);
+    B.rec_app = (double*)take(nt * (1 + s) * 8);
+    B.rec_upd = (double*)take(np * (1 + s) * 8);
+    B.fold = (double*)take(3 * NV_RED * 8);
+    B.st = nullptr;
+    return B;
+}
+
+// ------------------------------------------------------------------------------------- Batch
+bl_status Batch::init(bl_ctx* ctx, const bl_problem* cls, int capacity, Slot* slots, int* hdr_dev, char* hdr_pinned,
+                      hipEvent_t ev0, hipEvent_t ev1) {
+    c = ctx;
+    class_stencil(cls, base);
+    fp32 = cls->prec == BL_PREC_MIXED;
+    cap = capacity;
+    d_slots = slots;
+    d_hdr = hdr_dev;
+    h_hdr = hdr_pinned;
+    poll_ev[0] = ev0;
+    poll_ev[1] = ev1;
+    S.assign(cap, Host());
+    step = 0;
+    chunk_id = 0;
+    dirty = true;
+    return BL_OK;
+}
+
+int Batch::running() const {
+    int k = 0;
+    for (const Host& h : S) k += h.running ? 1 : 0;
+    return k;
+}
+
+// Tile-grid maps give every slot a multiple of 8 blocks (the XCD-aware tile order of a slot
+// starts on XCD 0); padding blocks return at once.
+static BatchMap make_map(const std::vector<Batch::Host>& S, const std::vector<int>& idx, bool tiles) {
+    BatchMap M{};
+    M.ns = (int)idx.size();
+    int off = 0;
+    for (int k = 0; k < M.ns; ++k) {
+        const Slot& d = S[idx[k]].d;
+        M.slot[k] = idx[k];
+        M.off[k] = off;
+        off += tiles ? (d.ntiles + 7) / 8 * 8 : d.npix;
+    }
+    M.off[M.ns] = off;
+    return M;
+}
+
+bl_status Batch::rebuild() {
+    run_list.clear();
+    for (int i = 0; i < cap; ++i)
+        if (S[i].running) run_list.push_back(i);
+    tmap = make_map(S, run_list, true);
+    pmap = make_map(S, run_list, false);
+    fold_app = BatchMap{};
+    fold_upd = BatchMap{};
+    for (int i : run_list) {
+        if (S[i].d.fold_app) fold_app.slot[fold_app.ns++] = i;
+        if (S[i].d.fold_upd) fold_upd.slot[fold_upd.ns++] = i;
+    }
+    dirty = false;
+    return BL_OK;
+}
+
+bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, double* taps_stage) {
+    const bl_problem* P = sp.P;
+    const bl_solve_opts* o = sp.o;
+    bl_recycle* rs = sp.rs;
+    if (idx < 0 || idx >= cap || S[idx].used) return c->err = "slot index in use or out of range", BL_E_ARG;
+    TRY(check_problem(c, P));
+    if (!sp.xhat || !sp.g || !sp.w) return c->err = "null argument", BL_E_ARG;
+    TRY(check_solve_opts(c, o));
+    const int s = rs ? rs->s_cur : 0;
+    const int s_max = rs ? rs->s_max : 0, v_cap = rs ? rs->v_cap : 0;
+    if (rs) {
+        if (s < 0 || s > s_max || s_max > S_MAX) return c->err = "s_cur outside [0, s_max] or s_max > 64", BL_E_SHAPE;
+        if (s > 0 && (!rs->U || !rs->C || !rs->mu)) return c->err = "null recycle arrays", BL_E_ARG;
+        if (o->store_basis && (!rs->V || v_cap < 1)) return c->err = "store_basis needs V", BL_E_ARG;
+    }
+    const bool hg = o->stop == BL_STOP_HGERR && s > 0 && rs->Z;
+    const bool store = o->store_basis && rs;
+    double lam, gam2;
+    TRY(theta_values(c, P, sp.theta, lam, gam2, taps_stage));
+    const int n = P->h * P->w;
+    Slot v{};
+    v.h = P->h;
+    v.width = P->w;
+    v.n = n;
+    v.tiles_x = (P->w + TW - 1) / TW;
+    v.ntiles = ntiles_of(P->h, P->w);
+    v.npix = npix_of(n);
+    v.j0 = step;
+    v.s = s;
+    v.nz = hg ? s : 0;
+    v.fold_res = (long)v.ntiles * (1 + s) > REC_LIMIT;
+    v.fold_app = v.fold_res;
+    v.fold_upd = (long)v.npix * (1 + v.nz) > REC_LIMIT;
+    v.lam = lam;
+    v.gam2 = gam2;
+    v.xhat = sp.xhat;
+    v.g = sp.g;
+    v.w = sp.w;
+    v.r = B.r;
+    v.p[0] = B.p0;
+    v.p[1] = B.p1;
+    v.q = B.q;
+    v.U = s ? rs->U : nullptr;
+    v.C = s ? rs->C : nullptr;
+    v.Z = hg ? rs->Z : nullptr;
+    v.V = store ? rs->V : nullptr;
+    v.st = B.st;
+    v.rec_res = B.rec_res;
+    v.rec_app = B.rec_app;
+    v.rec_upd = B.rec_upd;
+    v.fold = B.fold;
+    if (P->reg == BL_REG_FILTERS) {
+        const int nf = P->n_filters, f2 = P->filter_size * P->filter_size;
+        HIPCHK(hipMemcpyAsync(B.taps, taps_stage, (size_t)(nf * f2 + nf) * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+        v.taps = B.taps;
+        v.lamj = B.taps + nf * f2;
+        v.d2 = B.d2;
+        v.d2f = B.d2f;
+        Stencil Sx = base;
+        Sx.h = P->h;
+        Sx.w = P->w;
+        Sx.n = n;
+        Sx.tiles_x = v.tiles_x;
+        Sx.tiles_y = (P->h + TH - 1) / TH;
+        Sx.taps = v.taps;
+        Sx.lamj = v.lamj;
+        Sx.d2 = v.d2;
+        Sx.d2f = v.d2f;
+        HIPCHK(launch_filter_state(Sx, sp.xhat, B.d1, B.d2, B.d2f, c->stream));
+    }
+    StateInit init{o->tol, o->hg_tol, o->max_iter, o->check_every, o->stop, s, store ? v_cap : 0, store ? 1 : 0,
+                   hg ? 1 : 0};
+    HIPCHK(launch_b_admit(d_slots, idx, v, init, s ? rs->mu : nullptr, c->stream));
+    Host& h = S[idx];
+    h = Host();
+    h.used = true;
+    h.running = true;
+    h.d = v;
+    h.max_iter = o->max_iter;
+    h.rr_every = fp32 ? o->rr_every : 0;
+    h.store_basis = store;
+    h.v_cap = v_cap;
+    h.rs = rs;
+    h.valid_from = chunk_id;
+    h.rr_js.assign(1, 0);   // the first test is on the FP64 residual of the set-up
+    // set-up: r = g - H w0 (FP64), c0 = C^T r, w += U c0, r -= C c0
+    const std::vector<int> one{idx};
+    HIPCHK(launch_b_residual(base, d_slots, make_map(S, one, true), 0, c->stream));
+    if (v.fold_res) {
+        BatchMap f{};
+        f.ns = 1;
+        f.slot[0] = idx;
+        HIPCHK(launch_b_fold(d_slots, f, 0, c->stream));
+    }
+    HIPCHK(launch_b_init(d_slots, make_map(S, one, false), c->stream));
+    dirty = true;
+    return BL_OK;
+}
+
+// Residual replacement in FP64 for the listed slots: r = g - H w, z = C^T r, r -= C z.
+bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic) {
+    HIPCHK(launch_b_residual(base, d_slots, make_map(S, idx, true), periodic, c->stream));
+    BatchMap f{};
+    for (int i : idx)
+        if (S[i].d.fold_res) f.slot[f.ns++] = i;
+    HIPCHK(launch_b_fold(d_slots, f, 0, c->stream));
+    HIPCHK(launch_b_replace(d_slots, make_map(S, idx, false), periodic, c->stream));
+    return BL_OK;
+}
+
+bl_status Batch::finish(int idx) {
+    if (S[idx].d.s > 0) HIPCHK(launch_b_finish(d_slots, make_map(S, std::vector<int>{idx}, false), c->stream));
+    return BL_OK;
+}
+
+bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::vector<int>& slots) {
+    if (dirty) TRY(rebuild());
+    slots = run_list;
+    id = chunk_id++;
+    const int buf = (int)(id & 1);
+    const bool ktime = c->timing == 2;
+    for (int k = 0; k < POLL && steps_done < max_steps; ++k) {
+        if (fp32) {   // scheduled replacements: before the test of every rr_every-th iteration
+            std::vector<int> rr;
+            for (int i : run_list) {
+                Host& h = S[i];
+                const int j = step - h.d.j0;
+                if (h.rr_every > 0 && j > 0 && j <= h.max_iter && j % h.rr_every == 0) {
+                    rr.push_back(i);
+                    h.rr_js.push_back(j);
+                }
+            }
+            if (!rr.empty()) TRY(replace_residual(rr, 1));
+        }
+        if (fold_upd.ns) HIPCHK(launch_b_fold(d_slots, fold_upd, 2, c->stream));
+        int ev = 0;
+        if (ktime) {
+            ev = 3 * (int)timed.size();
+            while ((int)c->kev.size() < ev + 3) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                c->kev.push_back(e);
+            }
+            HIPCHK(hipEventRecord(c->kev[ev], c->stream));
+        }
+        HIPCHK(launch_b_apply(base, fp32, d_slots, tmap, step, c->stream));
+        if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], c->stream));
+        if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, c->stream));
+        HIPCHK(launch_b_update(d_slots, pmap, step, c->stream));
+        if (ktime) {
+            HIPCHK(hipEventRecord(c->kev[ev + 2], c->stream));
+            Timed t;
+            t.ev = ev;
+            for (int i : run_list) t.sj.push_back(make_int2(i, step - S[i].d.j0));
+            timed.push_back(std::move(t));
+        }
+        ++step;
+        ++steps_done;
+    }
+    char* dst = h_hdr + (size_t)buf * cap * HDR_BYTES;
+    if (run_list.size() == 1) {
+        const int i = run_list[0];
+        HIPCHK(hipMemcpyAsync(dst + (size_t)i * HDR_BYTES, S[i].d.st, HDR_BYTES, hipMemcpyDeviceToHost, c->stream));
+    } else {
+        HIPCHK(launch_b_headers(d_slots, tmap, d_hdr, c->stream));
+        HIPCHK(hipMemcpyAsync(dst, d_hdr, (size_t)cap * HDR_BYTES, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipEventRecord(poll_ev[buf], c->stream));
+    return BL_OK;
+}
+
+// Read a chunk's header snapshot.  A stopped slot completes, except that in mixed precision a
+// converged slot whose last test did not follow a residual replacement is re-tested: its
+// residual is replaced in FP64 and it resumes at the iteration that stopped.
+bl_status Batch::process_chunk(long id, const std::vector<int>& slots, std::vector<int>& done) {
+    const int buf = (int)(id & 1);
+    HIPCHK(hipEventSynchronize(poll_ev[buf]));
+    const char* src = h_hdr + (size_t)buf * cap * HDR_BYTES;
+    std::vector<int> retest;
+    for (int i : slots) {
+        Host& h = S[i];
+        if (!h.running || id < h.valid_from) continue;
+        std::memcpy(&h.hdr, src + (size_t)i * HDR_BYTES, HDR_BYTES);
+        if (!h.hdr.done) continue;
+        const int jd = h.hdr.iters;
+        const bool replaced = std::find(h.rr_js.begin(), h.rr_js.end(), jd) != h.rr_js.end();
+        if (fp32 && h.hdr.status == BL_OK && !replaced) {
+            retest.push_back(i);
+        } else {
+            TRY(finish(i));
+            h.running = false;
+            h.complete = true;
+            dirty = true;
+            done.push_back(i);
+        }
+    }
+    if (!retest.empty()) {
+        for (int i : retest) {
+            Host& h = S[i];
+            h.d.j0 = step - h.hdr.iters;
+            HIPCHK(launch_b_set_j0(d_slots, i, h.d.j0, c->stream));
+            h.rr_js.assign(1, h.hdr.iters);
+            h.valid_from = chunk_id;
+        }
+        TRY(replace_residual(retest, 0));
+    }
+    return BL_OK;
+}
+
+// Kernel durations of the steps in which some slot ran a full iteration.
+void Batch::account_times() {
+    for (const Timed& t : timed) {
+        bool real = false;
+        for (const int2& p : t.sj) {
+            const Host& h = S[p.x];
+            const int bound = h.hdr.done ? h.hdr.iters + (h.hdr.status == BL_E_INDEFINITE ? 1 : 0) : h.hdr.iters + 1;
+            if (p.y < bound) real = true;
+        }
+        if (!real) continue;
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, c->kev[t.ev], c->kev[t.ev + 1]) != hipSuccess) continue;
+        if (hipEventElapsedTime(&b, c->kev[t.ev + 1], c->kev[t.ev + 2]) != hipSuccess) continue;
+        c->kt[0] += a;
+        c->kt[1] += 1.0;
+        c->kt[2] += b;
+        c->kt[3] += 1.0;
+    }
+    timed.clear();
+}
+
+bl_status Batch::run(int max_steps, bool until_any, std::vector<int>& done) {
+    std::deque<std::pair<long, std::vector<int>>> inflight;
+    int steps_done = 0;
+    bool stop = false;
+    auto can_enqueue = [&]() -> bool {
+        if (stop || steps_done >= max_steps) return false;
+        if (dirty) (void)rebuild();
+        return !run_list.empty();
+    };
+    auto enqueue = [&]() -> bl_status {
+        long id;
+        std::vector<int> slots;
+        TRY(enqueue_chunk(max_steps, steps_done, id, slots));
+        inflight.emplace_back(id, std::move(slots));
+        return BL_OK;
+    };
+    if (can_enqueue()) TRY(enqueue());
+    while (!inflight.empty()) {
+        if (can_enqueue()) TRY(enqueue());
+        const auto ch = std::move(inflight.front());
+        inflight.pop_front();
+        TRY(process_chunk(ch.first, ch.second, done));
+        if (until_any && !done.empty()) stop = true;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->timing == 2) account_times();
+    return BL_OK;
+}
+
+void Batch::stats(int idx, bl_stats* out) const {
+    const Host& h = S[idx];
+    std::memset(out, 0, sizeof(*out));
+    out->iters = h.hdr.iters;
+    out->status = h.hdr.done ? h.hdr.status : BL_E_NOT_CONVERGED;
+    out->s_cur = h.d.s;
+    out->res_norm = std::sqrt(std::max(h.hdr.rho2[h.hdr.iters & 1], 0.0));
+    out->res0_norm = h.hdr.res0;
+    out->g_norm = h.hdr.gnorm;
+    out->est = h.hdr.est;
+    if (h.rs && h.store_basis) {
+        const int nv = h.hdr.iters + (out->status == BL_E_INDEFINITE ? 1 : 0);
+        h.rs->v_cur = std::min(nv, h.v_cap);
+    }
+}
+
+void Batch::release(int idx) {
+    S[idx] = Host();
+    dirty = true;
+}
+
+}  // namespace blh
+
+using namespace blh;
+
+// ------------------------------------------------------------------------------------ engine
+struct bl_engine {
+    bl_ctx* c = nullptr;
+    bl_problem cls{};
+    int cap = 0;
+    Batch B;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::map<size_t, size_t> free_blocks;   // offset -> size
+    std::vector<std::pair<size_t, size_t>> alloc;   // per slot (offset, size)
+    SolveState* states = nullptr;
+    double* h_taps = nullptr;   // pinned [cap][TAPS_MAX]
+    char* h_hdr = nullptr;      // pinned [2][cap][HDR_BYTES]
+    hipEvent_t ev[2] = {};
+
+    bool take(size_t bytes, size_t& off) {
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second < bytes) continue;
+            off = it->first;
+            const size_t rest = it->second - bytes;
+            free_blocks.erase(it);
+            if (rest) free_blocks[off + bytes] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(size_t off, size_t bytes) {
+        auto it = free_blocks.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_blocks.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_blocks.erase(nx);
+        }
+        if (it != free_blocks.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_blocks.erase(it);
+            }
+        }
+    }
+};
+
+namespace {
+
+struct EngineLayout {
+    size_t slots, hdr, states, arena, total;
+};
+
+EngineLayout engine_layout(int cap, size_t arena_bytes) {
+    EngineLayout L{};
+    size_t o = 0;
+    L.slots = o;   o += al((size_t)cap * sizeof(Slot));
+    L.hdr = o;     o += al((size_t)cap * HDR_BYTES);
+    L.states = o;  o += al((size_t)cap * sizeof(SolveState));
+    L.arena = o;   o += al(arena_bytes);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bl_engine_slot_bytes(const bl_problem* P, int s) {
+    if (!P || s < 0 || s > S_MAX) return 0;
+    return slot_bytes(P, s);
+}
+
+size_t bl_engine_workspace_bytes(int cap, size_t arena_bytes) {
+    if (cap < 1 || cap > B_MAX) return 0;
+    return engine_layout(cap, arena_bytes).total;
+}
+
+bl_status bl_engine_create(bl_ctx* c, const bl_problem* cls, int cap, void* ws, size_t ws_bytes, bl_engine** out) {
+    if (!c) return BL_E_ARG;
+    if (!out) return c->err = "null engine handle", BL_E_ARG;
+    *out = nullptr;
+    TRY(check_problem(c, cls));
+    if (cap < 1 || cap > B_MAX) return c->err = "engine capacity outside [1, 64]", BL_E_ARG;
+    if (!ws || (uintptr_t)ws % ALIGN) return c->err = "workspace missing or not 256-byte aligned", BL_E_WORKSPACE;
+    const EngineLayout L0 = engine_layout(cap, 0);
+    if (ws_bytes < L0.total) return c->err = "workspace smaller than bl_engine_workspace_bytes(cap, 0)", BL_E_WORKSPACE;
+    const size_t arena_bytes = (ws_bytes - L0.arena) / ALIGN * ALIGN;
+    bl_engine* e = new bl_engine();
+    e->c = c;
+    e->cls = *cls;
+    e->cap = cap;
+    char* base = (char*)ws;
+    e->arena = base + L0.arena;
+    e->arena_bytes = arena_bytes;
+    if (arena_bytes) e->free_blocks[0] = arena_bytes;
+    e->alloc.assign(cap, {0, 0});
+    e->states = (SolveState*)(base + L0.states);
+    if (hipHostMalloc((void**)&e->h_taps, (size_t)cap * TAPS_MAX * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&e->h_hdr, (size_t)2 * cap * HDR_BYTES, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev[1], hipEventDisableTiming) != hipSuccess) {
+        c->err = "pinned host memory or event creation failed";
+        if (e->h_taps) hipHostFree(e->h_taps);
+        if (e->h_hdr) hipHostFree(e->h_hdr);
+        for (auto& ev : e->ev)
+            if (ev) hipEventDestroy(ev);
+        delete e;
+        return BL_E_HIP;
+    }
+    e->B.init(c, cls, cap, (Slot*)(base + L0.slots), (int*)(base + L0.hdr), e->h_hdr, e->ev[0], e->ev[1]);
+    *out = e;
+    return BL_OK;
+}
+
+bl_status bl_engine_destroy(bl_engine* e) {
+    if (!e) return BL_E_ARG;
+    hipStreamSynchronize(e->c->stream);
+    hipHostFree(e->h_taps);
+    hipHostFree(e->h_hdr);
+    for (auto& ev : e->ev) hipEventDestroy(ev);
+    delete e;
+    return BL_OK;
+}
+
+bl_status bl_engine_admit(bl_engine* e, const bl_problem* P, const double* theta, const double* xhat,
+                          const double* g, double* w, bl_recycle* rs, const bl_solve_opts* opts, int* slot) {
+    if (!e) return BL_E_ARG;
+    bl_ctx* c = e->c;
+    if (!slot) return c->err = "null slot output", BL_E_ARG;
+    *slot = -1;
+    TRY(check_problem(c, P));
+    if (!same_class(P, &e->cls)) return c->err = "problem differs from the engine's operator class", BL_E_ARG;
+    const int s = rs ? rs->s_cur : 0;
+    if (s < 0 || s > S_MAX) return c->err = "s_cur outside [0, 64]", BL_E_SHAPE;
+    int idx = -1;
+    for (int i = 0; i < e->cap; ++i)
+        if (!e->B.S[i].used) {
+            idx = i;
+            break;
+        }
+    if (idx < 0) return c->err = "engine full: no free slot", BL_E_WORKSPACE;
+    const size_t bytes = slot_bytes(P, s);
+    size_t off = 0;
+    if (!e->take(bytes, off)) return c->err = "engine full: arena has no block of the slot's size", BL_E_WORKSPACE;
+    SlotBuffers buf = carve_slot(e->arena + off, P, s);
+    buf.st = e->states + idx;
+    const SolveSpec sp{P, theta, xhat, g, w, rs, opts};
+    const bl_status st = e->B.admit(idx, sp, buf, e->h_taps + (size_t)idx * TAPS_MAX);
+    if (st != BL_OK) {
+        e->give(off, bytes);
+        return st;
+    }
+    e->alloc[idx] = {off, bytes};
+    *slot = idx;
+    return BL_OK;
+}
+
+bl_status bl_engine_step(bl_engine* e, int max_iters, int return_on_done, int* done, int* n_done) {
+    if (!e) return BL_E_ARG;
+    bl_ctx* c = e->c;
+    if (max_iters < 1 || !n_done || !done) return c->err = "invalid step arguments", BL_E_ARG;
+    std::vector<int> fin;
+    TRY(e->B.run(max_iters, return_on_done != 0, fin));
+    *n_done = (int)fin.size();
+    for (size_t k = 0; k < fin.size(); ++k) done[k] = fin[k];
+    return BL_OK;
+}
+
+bl_status bl_engine_retire(bl_engine* e, int slot, bl_stats* out) {
+    if (!e) return BL_E_ARG;
+    bl_ctx* c = e->c;
+    if (slot < 0 || slot >= e->cap || !e->B.S[slot].complete) return c->err = "slot is not complete", BL_E_ARG;
+    bl_stats tmp;
+    e->B.stats(slot, &tmp);
+    if (out) *out = tmp;
+    e->give(e->alloc[slot].first, e->alloc[slot].second);
+    e->alloc[slot] = {0, 0};
+    e->B.release(slot);
+    return (bl_status)tmp.status;
+}
+
+bl_status bl_engine_query(const bl_engine* e, int* running, int* free_slots, size_t* free_bytes,
+                          size_t* largest_free) {
+    if (!e) return BL_E_ARG;
+    int used = 0;
+    for (const auto& h : e->B.S) used += h.used ? 1 : 0;
+    size_t fb = 0, lf = 0;
+    for (const auto& kv : e->free_blocks) {
+        fb += kv.second;
+        lf = std::max(lf, kv.second);
+    }
+    if (running) *running = e->B.running();
+    if (free_slots) *free_slots = e->cap - used;
+    if (free_bytes) *free_bytes = fb;
+    if (largest_free) *largest_free = lf;
+    return BL_OK;
+}
+
+size_t bl_batched_workspace_bytes(int nprob, const bl_problem* P, const int* s) {
+    if (nprob < 1 || !P) return 0;
+    size_t arena = 0;
+    for (int k = 0; k < nprob; ++k) {
+        const int sk = s ? s[k] : 0;
+        if (sk < 0 || sk > S_MAX) return 0;
+        arena += slot_bytes(&P[k], sk);
+    }
+    return engine_layout(std::min(nprob, B_MAX), arena).total;
+}
+
+bl_status bl_hessian_solve_batched(bl_ctx* c, int nprob, const bl_problem* P, const double* const* theta,
+                                   const double* const* xhat, const double* const* g, double* const* w,
+                                   bl_recycle* rs, const bl_solve_opts* opts, void* ws, size_t ws_bytes,
+                                   bl_stats* out) {
+    if (!c) return BL_E_ARG;
+    if (nprob < 1 || !P || !theta || !xhat || !g || !w || !out) return c->err = "null or empty batch", BL_E_ARG;
+    for (int k = 0; k < nprob; ++k) {
+        TRY(check_problem(c, &P[k]));
+        if (!same_class(&P[k], &P[0])) return c->err = "batched problems differ in operator class", BL_E_ARG;
+    }
+    bl_engine* e = nullptr;
+    TRY(bl_engine_create(c, &P[0], std::min(nprob, B_MAX), ws, ws_bytes, &e));
+    struct Guard {
+        bl_engine* e;
+        ~Guard() { bl_engine_destroy(e); }
+    } guard{e};
+    std::vector<int> slot_of(std::min(nprob, B_MAX), -1);
+    bl_status first_bad = BL_OK;
+    int next = 0, left = nprob;
+    std::vector<int> done(e->cap);
+    while (left > 0) {
+        // admit in order while slots and arena space last
+        while (next < nprob) {
+            int sl;
+            const bl_status st =
+                bl_engine_admit(e, &P[next], theta[next], xhat[next], g[next], w[next], rs ? &rs[next] : nullptr, opts, &sl);
+            if (st == BL_E_WORKSPACE) break;
+            if (st != BL_OK) return st;
+            slot_of[sl] = next++;
+        }
+        if (e->B.running() == 0) return c->err = "batched workspace too small for the next problem", BL_E_WORKSPACE;
+        int nd = 0;
+        TRY(bl_engine_step(e, INT_MAX, next < nprob ? 1 : 0, done.data(), &nd));
+        for (int k = 0; k < nd; ++k) {
+            const int sl = done[k], pk = slot_of[sl];
+            const bl_status st = bl_engine_retire(e, sl, &out[pk]);
+            if (st != BL_OK && first_bad == BL_OK) first_bad = st;
+            --left;
+        }
+    }
+    return first_bad;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Host-side definitions shared by the C-ABI translation units: the context, argument
+// checks, and the batch of recycled-CG solves that every Hessian solve runs through.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+struct bl_ctx {
+    hipStream_t stream = nullptr;
+    std::string err;
+    int timing = 0;
+    bl::SolveState* h_state = nullptr;   // pinned
+    double* h_buf = nullptr;             // pinned staging (8192 doubles)
+    int* h_info = nullptr;               // pinned
+    char* h_hdr = nullptr;               // pinned: two header snapshots of a one-slot batch
+    hipEvent_t poll_ev[2] = {};
+    hipEvent_t ev[6] = {};
+    std::vector<hipEvent_t> kev;         // per-launch events (timing mode 2)
+    double kt[4] = {0.0, 0.0, 0.0, 0.0};
+};
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
+            return BL_E_HIP;                                                                 \
+        }                                                                                    \
+    } while (0)
+
+#define TRY(expr)                        \
+    do {                                 \
+        bl_status s_ = (expr);           \
+        if (s_ != BL_OK) return s_;      \
+    } while (0)
+
+namespace blh {
+
+constexpr int POLL = 8;              // iterations launched between host polls of the stop flags
+// Consumer kernels re-reduce the producer's per-block records in every block; above this many
+// record values a one-block kernel first folds them into one record (keeps the re-reads linear).
+constexpr long REC_LIMIT = 8192;
+constexpr size_t ALIGN = 256;
+constexpr int TAPS_MAX = bl::MAX_NF * bl::MAX_FS * bl::MAX_FS + bl::MAX_NF;
+
+inline size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+int nparams(const bl_problem* P);
+bl_status check_problem(bl_ctx* c, const bl_problem* P);
+bl_status check_solve_opts(bl_ctx* c, const bl_solve_opts* o);
+// Operator-class part of the stencil (blur taps, regulariser, filter shape, penalty).
+void class_stencil(const bl_problem* P, bl::Stencil& S);
+// theta-dependent scalars: TV weight and smoothing; filters: taps then weights e^{w_j}
+// into taps_host (nf*f*f + nf doubles).
+bl_status theta_values(bl_ctx* c, const bl_problem* P, const double* theta, double& lam, double& gam2,
+                       double* taps_host);
+// Problems that can share a batched launch: everything but the image size.
+bool same_class(const bl_problem* a, const bl_problem* b);
+
+// Device scratch of one solve.
+struct SlotBuffers {
+    double *r, *p0, *p1, *q;
+    double *d1, *d2;
+    float* d2f;
+    double* taps;
+    double *rec_res, *rec_app, *rec_upd, *fold;
+    bl::SolveState* st;
+};
+// Bytes of SlotBuffers (without st) for an h x w problem of this class with s recycle columns,
+// and the carving of a region of that size.
+size_t slot_bytes(const bl_problem* P, int s);
+SlotBuffers carve_slot(char* base, const bl_problem* P, int s);
+
+struct SolveSpec {
+    const bl_problem* P;
+    const double* theta;
+    const double* xhat;
+    const double* g;
+    double* w;
+    bl_recycle* rs;
+    const bl_solve_opts* o;
+};
+
+// Recycled CG over up to `cap` concurrent solves of one operator class.  Each iteration is
+// one apply launch and one update launch over all running slots; the host enqueues chunks
+// of POLL iterations and reads the slots' stop flags one chunk behind, so the device never
+// waits for the host.  A slot's arithmetic and decisions do not depend on the others.
+class Batch {
+public:
+    bl_ctx* c = nullptr;
+    bl::Stencil base{};
+    bool fp32 = false;
+    int cap = 0;
+    bl::Slot* d_slots = nullptr;   // device [cap]
+    int* d_hdr = nullptr;          // device [cap * HDR_BYTES / 4]: gathered headers
+    char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES]
+    hipEvent_t poll_ev[2] = {};
+
+    struct Host {
+        bool used = false, running = false, complete = false;
+        bl::Slot d{};
+        int max_iter = 0, rr_every = 0;
+        bool store_basis = false;
+        int v_cap = 0;
+        bl_recycle* rs = nullptr;
+        long valid_from = 0;       // first chunk whose header snapshot reflects the current run
+        std::vector<int> rr_js;    // iterations whose test follows a residual replacement
+        bl::SolveState hdr{};      // last valid header snapshot
+    };
+    std::vector<Host> S;
+    int step = 0;                  // next global step index
+    long chunk_id = 0;
+
+    bl_status init(bl_ctx* ctx, const bl_problem* cls, int capacity, bl::Slot* slots, int* hdr_dev, char* hdr_pinned,
+                   hipEvent_t ev0, hipEvent_t ev1);
+    // Validate and start solve `sp` in free slot idx with device scratch B; taps_stage is
+    // pinned host memory of TAPS_MAX doubles that stays untouched until the slot retires.
+    bl_status admit(int idx, const SolveSpec& sp, const SlotBuffers& B, double* taps_stage);
+    // Advance running slots by at most max_steps iterations, returning early once a slot
+    // completes (until_any) or none is running.  Completed slots are appended to `done`;
+    // their iterate is final when this returns.
+    bl_status run(int max_steps, bool until_any, std::vector<int>& done);
+    int running() const;
+    void stats(int idx, bl_stats* out) const;
+    void release(int idx);
+
+private:
+    bool dirty = true;
+    bl::BatchMap tmap{}, pmap{}, fold_app{}, fold_upd{};
+    std::vector<int> run_list;
+    struct Timed {
+        int ev;                    // first of 3 events
+        std::vector<int2> sj;      // (slot, iteration) pairs of the step
+    };
+    std::vector<Timed> timed;
+    bl_status rebuild();
+    bl_status replace_residual(const std::vector<int>& idx, int periodic);
+    bl_status finish(int idx);
+    bl_status enqueue_chunk(int max_steps, int& steps_done, long& id, std::vector<int>& slots);
+    bl_status process_chunk(long id, const std::vector<int>& slots, std::vector<int>& done);
+    void account_times();
+};
+
+}  // namespace blh

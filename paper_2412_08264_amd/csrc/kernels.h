@@ -9,11 +9,6 @@ namespace bl {
 int tiles_of(const Stencil& S);
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
                       hipStream_t st);
-hipError_t launch_cg_apply(const Stencil& S, bool fp32, int j, const double* xhat, const double* r,
-                           const double* p_old, double* p_new, double* q, const double* C, double* V, SolveState* st,
-                           const double* upd_part, int upd_nb, double* app_part, hipStream_t stream);
-hipError_t launch_residual(const Stencil& S, const double* xhat, const double* w, const double* g, double* out,
-                           const double* C, int s, double* res_part, hipStream_t stream);
 hipError_t launch_filter_state(const Stencil& S, const double* xhat, double* d1, double* d2, float* d2f,
                                hipStream_t stream);
 int jac_blocks(const Stencil& S);
@@ -27,19 +22,26 @@ hipError_t launch_forward(const Stencil& S, const double* x, const double* e, do
 // krylov.hip
 int red_blocks(int n);
 int vec_blocks(int n);
-hipError_t launch_cg_init(int n, double* w, double* r, const double* U, const double* C, const double* Z,
-                          SolveState* st, const double* res_part, int res_nb, double* upd_part, hipStream_t stream);
-hipError_t launch_cg_update(int n, int j, double* w, double* r, const double* p, const double* q, const double* C,
-                            const double* Z, SolveState* st, const double* app_part, int app_nb, double* upd_part,
-                            hipStream_t stream);
-hipError_t launch_cg_replace(int n, double* r, const double* C, const double* Z, SolveState* st,
-                             const double* res_part, int res_nb, double* upd_part, hipStream_t stream);
-hipError_t launch_cg_finish(int n, double* w, const double* U, const SolveState* st, hipStream_t stream);
 hipError_t launch_finish_sum(const double* part, int nb, int nv, double* out, hipStream_t stream);
 hipError_t launch_dots_part(int n, int nv, const double* a, const double* b, double* part, hipStream_t stream);
 hipError_t launch_axpy_red(int n, double beta, double* y, const double* x, const double* part1, double s1,
                            const double* part2, double s2, hipStream_t stream);
 hipError_t launch_sub(int n, const double* a, const double* b, double* out, hipStream_t stream);
+
+// batch.hip: recycled CG over a batch of slots (one launch per half-iteration)
+hipError_t launch_b_residual(const Stencil& base, const Slot* slots, const BatchMap& M, int periodic,
+                             hipStream_t stream);
+hipError_t launch_b_apply(const Stencil& base, bool fp32, const Slot* slots, const BatchMap& M, int step,
+                          hipStream_t stream);
+hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t stream);
+hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipStream_t stream);
+hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, hipStream_t stream);
+hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream);
+hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, hipStream_t stream);
+hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,
+                          hipStream_t stream);
+hipError_t launch_b_set_j0(Slot* slots, int idx, int j0, hipStream_t stream);
+hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, hipStream_t stream);
 
 // dense.hip
 int gram_chunks(int n);

@@ -84,16 +84,45 @@ __device__ __forceinline__ void stage_region(T* buf, const Stencil& S, const Til
     }
 }
 
-// Evaluate H v on the owned TH x TW tile from the staged region; result in lds[o_out].
+// Stage xhat on [r0-1, r0+TH+1) x [c0-1, c0+TW+1) (TV flux) with one batch of loads.
+constexpr int XSTAGE_MAX = ((TH + 2) * (TW + 2) + NT - 1) / NT;
 template <typename T>
+__device__ __forceinline__ void stage_xhat(T* xs, const Stencil& S, const double* __restrict__ xhat, int r0, int c0) {
+    const int XW = TW + 2, tot = (TH + 2) * XW;
+    double v[XSTAGE_MAX];
+#pragma unroll
+    for (int u = 0; u < XSTAGE_MAX; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        v[u] = 0.0;
+        if (idx < tot) {
+            const int rr = idx / XW, cc = idx - rr * XW;
+            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
+            if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) v[u] = xhat[gi * S.w + gj];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < XSTAGE_MAX; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        if (idx < tot) xs[idx] = (T)v[u];
+    }
+}
+
+// Evaluate H v on the owned TH x TW tile from the staged region; result in lds[o_out].
+// xs_staged: the TV kernels staged xhat already (stage_xhat before the barrier).
+// RB is the blur radius as a compile-time constant (the tap loops unroll fully and their LDS
+// loads issue together); LDS views are __restrict__ so passes pipeline across outputs.
+template <typename T, int RB>
 __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const double* __restrict__ xhat,
-                         int r0, int c0) {
-    const int R = S.R, E = L.E, RW = L.RW, RH = L.RH;
-    const T* v = lds + L.o_v;
-    T* h1 = lds + L.o_h1;
-    T* t1 = lds + L.o_t1;
-    T* out = lds + L.o_out;
-    const double* g = S.g;   // uniform taps, read from the kernel argument segment
+                         int r0, int c0, bool xs_staged = false) {
+    constexpr int R = RB;
+    const int E = L.E, RW = L.RW, RH = L.RH;
+    const T* __restrict__ v = lds + L.o_v;
+    T* __restrict__ h1 = lds + L.o_h1;
+    T* __restrict__ t1 = lds + L.o_t1;
+    T* __restrict__ out = lds + L.o_out;
+    T g[2 * RB + 1];
+#pragma unroll
+    for (int a = 0; a <= 2 * RB; ++a) g[a] = (T)S.g[a];
 
     // ---- A(A v), separable
     const int W1 = TW + 2 * R;
@@ -101,7 +130,7 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         const int idx = rr * W1 + cc;
         const T* src = v + rr * RW + cc + (E - R) - R;
         T acc = T(0);
-        for (int b = 0; b <= 2 * R; ++b) acc += (T)g[b] * src[b];
+        _Pragma("unroll") for (int b = 0; b <= 2 * R; ++b) acc += g[b] * src[b];
         h1[idx] = acc;
     }
     __syncthreads();
@@ -110,17 +139,17 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         const int idx = rr * W1 + cc;
         const T* src = h1 + (rr + E - R - R) * W1 + cc;
         T acc = T(0);
-        for (int a = 0; a <= 2 * R; ++a) acc += (T)g[a] * src[a * W1];
+        _Pragma("unroll") for (int a = 0; a <= 2 * R; ++a) acc += g[a] * src[a * W1];
         const int gi = r0 - R + rr, gj = c0 - R + cc;
         t1[idx] = (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) ? acc : T(0);
     }
     __syncthreads();
-    T* h2 = h1;                                                       // reuse: (TH+2R) x TW
+    T* __restrict__ h2 = h1;                                          // reuse: (TH+2R) x TW
     TILE_LOOP(H1, TW, rr, cc) {
         const int idx = rr * TW + cc;
         const T* src = t1 + rr * W1 + cc;
         T acc = T(0);
-        for (int b = 0; b <= 2 * R; ++b) acc += (T)g[b] * src[b];
+        _Pragma("unroll") for (int b = 0; b <= 2 * R; ++b) acc += g[b] * src[b];
         h2[idx] = acc;
     }
     __syncthreads();
@@ -128,7 +157,7 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         const int idx = rr * TW + cc;
         const T* src = h2 + rr * TW + cc;
         T acc = T(0);
-        for (int a = 0; a <= 2 * R; ++a) acc += (T)g[a] * src[a * TW];
+        _Pragma("unroll") for (int a = 0; a <= 2 * R; ++a) acc += g[a] * src[a * TW];
         out[idx] = T(2) * acc;
     }
 
@@ -138,12 +167,10 @@ __device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const do
         T* fx = lds + L.o_fx;              // flux on [r0-1, r0+TH) x [c0-1, c0+TW)
         T* fy = lds + L.o_fy;
         const int XW = TW + 2;
-        TILE_LOOP((TH + 2), XW, rr, cc) {
-            const int idx = rr * XW + cc;
-            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
-            xs[idx] = (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) ? (T)xhat[gi * S.w + gj] : T(0);
+        if (!xs_staged) {
+            stage_xhat<T>(xs, S, xhat, r0, c0);
+            __syncthreads();
         }
-        __syncthreads();
         const T gam2 = (T)S.gam2;
         const int FW = TW + 1;
         TILE_LOOP((TH + 1), FW, rr, cc) {

@@ -17,7 +17,7 @@ __device__ __forceinline__ void write_partials(double* part, int nv, double*, Va
 }
 
 // ------------------------------------------------------------------ out[:, c] = H v[:, c]
-template <typename T>
+template <typename T, int RB>
 __global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict__ xhat,
                                             const double* __restrict__ v, double* __restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -28,137 +28,13 @@ __global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict_
     const double* vc = v + (size_t)blockIdx.y * S.n;
     stage_region<T>(lds + L.o_v, S, L, r0, c0, [&](int i) { return vc[i]; });
     __syncthreads();
-    hvp_tile<T>(lds, S, L, xhat, r0, c0);
+    hvp_tile<T, RB>(lds, S, L, xhat, r0, c0);
     __syncthreads();
     double* oc = out + (size_t)blockIdx.y * S.n;
     for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
         const int gi = r0 + idx / TW, gj = c0 + idx % TW;
         if (gi < S.h && gj < S.w) oc[gi * S.w + gj] = (double)lds[L.o_out + idx];
     }
-}
-
-// ------------------------------------------------------------------ CG apply step
-// Iteration j, first half.  From the residual records of the previous kernel: rho_j =
-// r_j . r_j (and Z^T r_j), the stop decision (identical in every block; block 0 stores
-// it), beta = rho_j / rho_{j-1}.  Then p_new = r + beta p_old (p = r when j = 0),
-// q = H p_new, V[:, j] = r / ||r|| while j < v_cap, and the block record [p.q, C^T q].
-template <typename T>
-__global__ void __launch_bounds__(NT) k_cg_apply(Stencil S, int j, const double* __restrict__ xhat,
-                                                 const double* __restrict__ r, const double* __restrict__ p_old,
-                                                 double* __restrict__ p_new, double* __restrict__ q,
-                                                 const double* __restrict__ C, double* __restrict__ V,
-                                                 SolveState* st, const double* __restrict__ upd_part, int upd_nb,
-                                                 double* __restrict__ app_part) {
-    if (st->done) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-    __shared__ double tot[NT];
-    const int s = st->s;
-    const int nz = st->hgerr_on ? s : 0;
-    reduce_partials(upd_part, upd_nb, 1 + nz, tot);
-    const double rho = tot[0];
-    const Decision dec = decide(st, j, rho, tot + 1);
-    if (blockIdx.x == 0) {
-        for (int k = threadIdx.x; k < nz; k += NT) st->zr[k] = tot[1 + k];
-        if (threadIdx.x == 0) {
-            st->rho2[j & 1] = rho;
-            st->est = dec.est;
-            st->iters = j;
-            if (j == 0) st->res0 = sqrt(rho);
-            if (dec.done) {
-                st->status = dec.status;
-                st->done = 1;
-            }
-        }
-    }
-    if (dec.done) return;
-    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
-    const bool first = (j == 0);
-    const double beta = first ? 0.0 : rho / st->rho2[(j - 1) & 1];
-    int r0, c0;
-    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
-    stage_region<T>(lds + L.o_v, S, L, r0, c0,
-                    [&](int i) { return first ? r[i] : r[i] + beta * p_old[i]; });
-    __syncthreads();
-    hvp_tile<T>(lds, S, L, xhat, r0, c0);
-    __syncthreads();
-    const bool store = st->store_basis && j < st->v_cap;
-    const double inv_nr = store ? 1.0 / sqrt(rho) : 0.0;
-    // each thread owns pixels threadIdx.x and threadIdx.x + NT of the tile
-    double pv[TH * TW / NT], qv[TH * TW / NT];
-    int gid[TH * TW / NT];
-#pragma unroll
-    for (int u = 0; u < TH * TW / NT; ++u) {
-        const int idx = threadIdx.x + u * NT;
-        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
-        gid[u] = -1;
-        pv[u] = 0.0;
-        qv[u] = 0.0;
-        if (gi < S.h && gj < S.w) {
-            const int i = gi * S.w + gj;
-            gid[u] = i;
-            const double ri = r[i];
-            const double pn = first ? ri : ri + beta * p_old[i];
-            const double qq = (double)lds[L.o_out + idx];
-            p_new[i] = pn;
-            q[i] = qq;
-            if (store) V[(size_t)j * S.n + i] = ri * inv_nr;
-            pv[u] = pn;
-            qv[u] = qq;
-        }
-    }
-    block_partials(app_part, 1 + s, [&](int k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < TH * TW / NT; ++u) {
-            if (gid[u] < 0) continue;
-            acc += (k == 0 ? pv[u] : C[(size_t)(k - 1) * S.n + gid[u]]) * qv[u];
-        }
-        return acc;
-    });
-}
-
-// ------------------------------------------------------------------ residual g - H w
-// out = g - H w and the block record [g.g, C^T out] (s values).
-template <typename T>
-__global__ void __launch_bounds__(NT) k_residual(Stencil S, const double* __restrict__ xhat,
-                                                 const double* __restrict__ w, const double* __restrict__ g,
-                                                 double* __restrict__ out, const double* __restrict__ C, int s,
-                                                 double* __restrict__ res_part) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
-    int r0, c0;
-    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
-    stage_region<T>(lds + L.o_v, S, L, r0, c0, [&](int i) { return w[i]; });
-    __syncthreads();
-    hvp_tile<T>(lds, S, L, xhat, r0, c0);
-    __syncthreads();
-    double ov[TH * TW / NT], gv[TH * TW / NT];
-    int gid[TH * TW / NT];
-#pragma unroll
-    for (int u = 0; u < TH * TW / NT; ++u) {
-        const int idx = threadIdx.x + u * NT;
-        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
-        gid[u] = -1;
-        ov[u] = gv[u] = 0.0;
-        if (gi < S.h && gj < S.w) {
-            const int i = gi * S.w + gj;
-            gid[u] = i;
-            gv[u] = g[i];
-            ov[u] = gv[u] - (double)lds[L.o_out + idx];
-            out[i] = ov[u];
-        }
-    }
-    block_partials(res_part, 1 + s, [&](int k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < TH * TW / NT; ++u) {
-            if (gid[u] < 0) continue;
-            acc += (k == 0) ? gv[u] * gv[u] : C[(size_t)(k - 1) * S.n + gid[u]] * ov[u];
-        }
-        return acc;
-    });
 }
 
 // ------------------------------------------------------------------ filter state
@@ -505,40 +381,33 @@ static void allow_lds(K kernel, size_t bytes) {
 static inline dim3 tiles_grid(const Stencil& S, int ncols) { return dim3(S.tiles_x * S.tiles_y, ncols); }
 int tiles_of(const Stencil& S) { return S.tiles_x * S.tiles_y; }
 
+// Kernels are instantiated per blur radius (0..MAX_R) and arithmetic type.
+#define BL_RADIUS_SWITCH(R, CALL)          \
+    switch (R) {                           \
+        case 0: CALL(0); break;            \
+        case 1: CALL(1); break;            \
+        case 2: CALL(2); break;            \
+        case 3: CALL(3); break;            \
+        case 4: CALL(4); break;            \
+        case 5: CALL(5); break;            \
+        case 6: CALL(6); break;            \
+        case 7: CALL(7); break;            \
+        default: CALL(8); break;           \
+    }
+
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
                       hipStream_t st) {
     const size_t lds = fp32 ? tile_lds_bytes<float>(S.R, S.reg, S.fs) : tile_lds_bytes<double>(S.R, S.reg, S.fs);
-    if (fp32) {
-        allow_lds(k_hvp<float>, lds);
-        hipLaunchKernelGGL(k_hvp<float>, tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out);
-    } else {
-        allow_lds(k_hvp<double>, lds);
-        hipLaunchKernelGGL(k_hvp<double>, tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out);
+#define HVP_CALL(RB)                                                                                     \
+    if (fp32) {                                                                                          \
+        allow_lds(k_hvp<float, RB>, lds);                                                                \
+        hipLaunchKernelGGL((k_hvp<float, RB>), tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out);  \
+    } else {                                                                                             \
+        allow_lds(k_hvp<double, RB>, lds);                                                               \
+        hipLaunchKernelGGL((k_hvp<double, RB>), tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out); \
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_apply(const Stencil& S, bool fp32, int j, const double* xhat, const double* r,
-                           const double* p_old, double* p_new, double* q, const double* C, double* V, SolveState* st,
-                           const double* upd_part, int upd_nb, double* app_part, hipStream_t stream) {
-    const size_t lds = fp32 ? tile_lds_bytes<float>(S.R, S.reg, S.fs) : tile_lds_bytes<double>(S.R, S.reg, S.fs);
-    if (fp32) {
-        allow_lds(k_cg_apply<float>, lds);
-        hipLaunchKernelGGL(k_cg_apply<float>, tiles_grid(S, 1), dim3(NT), lds, stream, S, j, xhat, r, p_old, p_new, q,
-                           C, V, st, upd_part, upd_nb, app_part);
-    } else {
-        allow_lds(k_cg_apply<double>, lds);
-        hipLaunchKernelGGL(k_cg_apply<double>, tiles_grid(S, 1), dim3(NT), lds, stream, S, j, xhat, r, p_old, p_new,
-                           q, C, V, st, upd_part, upd_nb, app_part);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_residual(const Stencil& S, const double* xhat, const double* w, const double* g, double* out,
-                           const double* C, int s, double* res_part, hipStream_t stream) {
-    allow_lds(k_residual<double>, tile_lds_bytes<double>(S.R, S.reg, S.fs));
-    hipLaunchKernelGGL(k_residual<double>, tiles_grid(S, 1), dim3(NT), tile_lds_bytes<double>(S.R, S.reg, S.fs),
-                       stream, S, xhat, w, g, out, C, s, res_part);
+    BL_RADIUS_SWITCH(S.R, HVP_CALL)
+#undef HVP_CALL
     return hipGetLastError();
 }
 

@@ -55,3 +55,33 @@ def test_status_strings_and_null_context():
     assert B.lib.bl_hessian_solve(None, C.byref(P), th, None, None, None, None, C.byref(opts), None, 0,
                                   C.byref(st)) == B.BL_E_ARG
     assert B.lib.bl_destroy(None) == B.BL_E_ARG
+
+
+def test_engine_sizes():
+    from paper_2412_08264_amd import bilevel as B
+    import synth
+    P = B.problem_from(synth.WORKLOADS["tv256"])
+    lib = B.lib
+    s0 = lib.bl_engine_slot_bytes(C.byref(P), 0)
+    s20 = lib.bl_engine_slot_bytes(C.byref(P), 20)
+    assert s0 >= 4 * 8 * 65536 and s20 > s0
+    assert lib.bl_engine_slot_bytes(C.byref(P), 65) == 0
+    Pf = B.problem_from(synth.WORKLOADS["foe512"])
+    # filter slots hold the phi'' maps: 8 filters x (two FP64 + one FP32) maps
+    assert lib.bl_engine_slot_bytes(C.byref(Pf), 0) >= (4 + 8 * 2.5) * 8 * 512 * 512
+    assert lib.bl_engine_workspace_bytes(0, 1024) == 0 and lib.bl_engine_workspace_bytes(65, 1024) == 0
+    assert lib.bl_engine_workspace_bytes(64, 10 ** 6) >= 10 ** 6
+    arr = (B.bl_problem * 2)(P, P)
+    sv = (C.c_int * 2)(20, 0)
+    assert lib.bl_batched_workspace_bytes(2, arr, sv) >= s20 + s0
+    assert lib.bl_batched_workspace_bytes(0, arr, sv) == 0
+
+
+def test_engine_argument_checks_without_gpu():
+    from paper_2412_08264_amd import bilevel as B
+    P = B.bl_problem(8, 8, 1, 1.0, B.BL_REG_TV, 0, 0, 0.0, 0, 0)
+    eng = C.c_void_p()
+    assert B.lib.bl_engine_create(None, C.byref(P), 2, None, 0, C.byref(eng)) == B.BL_E_ARG
+    assert B.lib.bl_engine_destroy(None) == B.BL_E_ARG
+    nd = C.c_int()
+    assert B.lib.bl_engine_step(None, 1, 1, None, C.byref(nd)) == B.BL_E_ARG
