@@ -1,23 +1,28 @@
 """Benchmark: hypergradient Hessian solves/s (recycled vs plain CG) at hypergradient rel err 1e-6.
 
-Workload (default): 256x256 smoothed-TV deblurring, FP64, recycle dimension s = 20, a frozen
-sequence of 30 outer (upper-level) iterations.  Inputs are synthetic (seeded rectangles, 9x9
-Gaussian blur sigma 2.5, noise 0.01), generated on the GPU before timing: measurement y, the
-30-step gradient-descent trajectory {theta_i, x_hat_i} (L-BFGS lower solves to ||grad|| <= 1e-8)
-and reference hypergradients (plain CG to relative residual 1e-13).
+Default workload (tv256): 256x256 smoothed-TV deblurring, FP64, recycle dimension s = 20, a
+frozen sequence of 30 outer (upper-level) iterations.  Inputs are synthetic (seeded rectangles,
+9x9 Gaussian blur sigma 2.5, noise 0.01), generated on the GPU before timing: measurement y, the
+30-step gradient-descent trajectory {theta_i, x_hat_i} and reference hypergradients (plain CG to
+relative residual 1e-13).  One step = one pass of the hot path over the whole sequence: for
+every system the Ritz-GSV refresh (RGen-L(R)), the recycled CG solve with the
+hypergradient-error stop, and the hypergradient.  A solve counts towards ``value`` only if its
+hypergradient is within 1e-6 (relative) of the reference.  Plain warm-started CG and recycling
+with the residual stop are timed on the same sequence and reported beside the headline.
 
-One step = one pass of the hot path over the whole sequence: for every system, the Ritz-GSV
-refresh (RGen-L(R)), the recycled CG solve with the hypergradient-error stop, and the
-hypergradient.  A solve counts towards ``value`` only if its hypergradient is within 1e-6
-(relative) of the reference.  The same sequence is also solved with plain warm-started CG
-(residual stop) and with recycling + residual stop, reported beside the headline.
+Other workloads (``--workload``):
+  tv32     the same protocol on the 32x32 TV recipe;
+  foe512   512x512, eight 7x7 filters, mixed precision (FP32 stencils) against FP64, s = 30;
+  batch64  64 filter images of sides {128..512}, shared theta, one engine advancing all 64 solves
+           per launch; one step = one outer iteration of the whole training set;
+  serve    Poisson request stream over resident samples (TV and filters, sides 64..1024,
+           s in {10, 30, 50}) served by continuous batching; p50/p99 latency, mixed and FP64.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,12 +32,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "hypergradient Hessian solves/sec (recycled vs plain CG) at rel err 1e-6; p99 ms"
 V_CAP = 64
 RESID_TOL = 1e-10      # residual tolerance of the workload recipe (upper end of the sweep)
 # Each variant is timed at the loosest stopping threshold of its sweep for which every
 # hypergradient of the sequence is within 1e-6 of the reference (untimed selection pass).
 SWEEP_RESID = (1e-6, 1e-7, 1e-8, 1e-9, 1e-10)
 SWEEP_HG = (1e-7, 1e-8, 1e-9, 1e-10, 1e-11)   # relative to the previous hypergradient norm
+LBFGS_CAP = 1500       # L-BFGS iterations per lower solve of a trajectory (warm started)
+HBM_PEAK = 8000.0      # GB/s
 
 
 def log(*a):
@@ -44,125 +52,25 @@ def upper_loss(x, xs):
     return 0.5 * float((d * d).sum())
 
 
-LBFGS_CAP = 1500      # L-BFGS iterations per lower solve of the trajectory (warm started)
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def make_trajectory(S, B, wl, torch, y, xs, outer, gtol=1e-8):
-    """Gradient descent with backtracking on theta (frozen sequence), all on the GPU.
-
-    Lower solves stop at ||grad Phi|| <= 1e-8 or after LBFGS_CAP iterations (the smoothing
-    weight the descent reaches makes 1e-8 unreachable in reasonable time at 256x256); the
-    gradient norms reached are logged.  The Hessian systems of the sequence are SPD at any
-    point, so the frozen sequence is a valid workload either way.
-    """
-    th = np.array(synth_mod.initial_theta(wl), dtype=np.float64)
-    x = y.clone()
-    S.lower_solve(th, y, x, gtol=gtol, max_iter=LBFGS_CAP)
-    c1 = upper_loss(x, xs)
-    beta = 1.0
-    thetas, xhats = [], []
-    w = torch.zeros_like(x)
-    nl = []
-    for i in range(outer):
-        thetas.append(th.copy())
-        xhats.append(x.clone())
-        g = x - xs
-        S.reset()
-        w.zero_()
-        S.solve(th, x, g, w, tol=1e-12, store_basis=False, recycle=False, max_iter=50000,
-                allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
-        grad = S.hypergradient(th, x, w)
-        d = -grad
-        c2 = float(grad @ d)
-        xprev = x
-        for j in range(1, 31):
-            tau = beta * 0.5 ** (j - 1)
-            thj = th + tau * d
-            xj = xprev.clone()
-            lst = S.lower_solve(thj, y, xj, gtol=gtol, max_iter=LBFGS_CAP)
-            nl.append((lst.iters, float(f"{lst.res_norm:.1e}")))
-            c0 = upper_loss(xj, xs)
-            if c0 <= c1 + 1e-4 * tau * c2:
-                th, x, c1, beta = thj, xj, c0, 2.0 * tau
-                break
-            xprev = xj
-        log(f"  trajectory step {i + 1}/{outer}: loss {c1:.6e} theta {np.round(th, 4).tolist()} "
-            f"L-BFGS iterations {nl}")
-        nl.clear()
-    return thetas, xhats
-
-
-def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL):
-    """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain'; thr: the stopping
-    threshold (residual tolerance, or the error-estimate threshold relative to the previous
-    hypergradient norm).  Returns per-solve records."""
-    S.reset()
-    w = torch.zeros_like(xs)
-    prev_hg = None
-    recs = []
-    for i, (th, x) in enumerate(zip(thetas, xhats)):
-        t0 = time.perf_counter()
-        g = x - xs
-        if mode != "plain" and i > 0:
-            S.refresh(th, x, s=S.rs.s_max)
-        if mode == "rgen_hg" and S.rs.s_cur > 0 and prev_hg is not None:
-            st = S.solve(th, x, g, w, stop="hgerr", hg_tol=thr * prev_hg, tol=RESID_TOL, store_basis=True)
-        else:
-            # first system of the error-estimate variant (no recycle space yet): residual test
-            st = S.solve(th, x, g, w, tol=RESID_TOL if mode == "rgen_hg" else thr,
-                         store_basis=(mode != "plain"), recycle=(mode != "plain"))
-        hg = S.hypergradient(th, x, w)
-        t1 = time.perf_counter()
-        if lat is not None:
-            lat.append((t1 - t0) * 1e3)
-        prev_hg = float(np.linalg.norm(hg))
-        err = float(np.linalg.norm(hg - refs[i]) / np.linalg.norm(refs[i]))
-        recs.append({"iters": st.iters, "err": err, "status": st.status})
-    return recs
-
-
-def cpu_baseline(wl, seconds_budget=25.0):
-    """The CPU oracle timed on a bounded sample of the same workload (2 consecutive systems).
-
-    The oracle takes no input from the GPU path, so the sample uses stand-in points
-    x_hat = x* + 0.05 e' (e' a separate seeded normal field) and a theta path stepping
-    away from the initial value; each system is refreshed, solved by recycled CG
-    (residual stop 1e-10) and mapped to its hypergradient, as on the GPU.
-    """
-    from threadpoolctl import threadpool_info
-
-    from oracle import krylov, problem, recycle
-    inst = synth_mod.instance(wl)
-    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
-    xs = inst["xstar"].ravel()
-    xh = xs + 0.05 * synth_mod.unit_noise(prob.n, wl.seed + 77)
-    th0 = synth_mod.initial_theta(wl)
-    U = V = None
-    w = None
-    done = 0
-    t0 = time.perf_counter()
-    for i in range(2):
-        th = th0 + np.array([0.02, -0.02]) * i
-        hvp = lambda v, th=th: prob.hvp(xh, th, v)
-        jac = lambda v, th=th: prob.jac_apply(xh, th, v)
-        rs = recycle.refresh(hvp, jac, U, V, wl.s) if (U is not None or V is not None) else {"U": None, "C": None}
-        res = krylov.recycled_cg(hvp, xh - xs, w, rs["U"], rs["C"], tol=RESID_TOL, v_cap=V_CAP)
-        jac(res["w"])
-        U, V, w = rs["U"], res["V"], res["w"]
-        done += 1
-        if time.perf_counter() - t0 > seconds_budget:
-            break
-    el = time.perf_counter() - t0
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    return {"value": done / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} consecutive {wl.h}x{wl.w} TV systems (refresh + recycled CG 1e-10 + hypergradient) "
-                      f"at stand-in points x*+0.05e', numpy FP64, {el:.1f} s; host "
-                      f"{len(os.sched_getaffinity(0))} affinity cores"}
+def apply_bytes_per_pixel(reg: str, prec: str, s: int, nf: int) -> int:
+    """Algorithmic HBM bytes per pixel of one fused apply step (H p with p.q and C^T q): read
+    r and p, write p and q (FP64), read the s columns of C, and the Hessian state: x_hat for TV,
+    the nf phi'' maps for filters (FP32 in mixed precision)."""
+    b = 8 * 4 + 8 * s
+    if reg == "tv":
+        b += 8
+    else:
+        b += (4 if prec == "mixed" else 8) * nf
+    return b
 
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("stencil.h", "stencil.hip", "common.h"):
+    for f in ("stencil.h", "common.h", "batch.hip"):
         with open(os.path.join(ROOT, "paper_2412_08264_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -183,20 +91,571 @@ def measured_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-synth_mod = None
+def roofline(kernel, total_bytes, kt, workload, launches_for_traffic=None):
+    apply_ms = kt[0] / max(kt[1], 1.0)
+    achieved = total_bytes / max(kt[0] * 1e-3, 1e-30) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+            "traffic": measured_traffic(kernel, workload), "kernel": kernel, "avg_launch_us": apply_ms * 1e3,
+            "launches": int(kt[1]), "algorithmic_bytes_per_launch": total_bytes / max(kt[1], 1.0),
+            "update_avg_us": kt[2] / max(kt[3], 1.0) * 1e3}
 
 
-def kernels_only(wl, B, torch, synth):
+def base_line(args, value, el, dtype, config, **extra):
+    out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+def threads_used():
+    from threadpoolctl import threadpool_info
+    return max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+
+
+# =============================================================================== sequence workloads
+def make_trajectory(ctx, P, B, wl, torch, y, xs, theta0, outer, gtol=1e-8):
+    """Gradient descent with backtracking on theta (frozen sequence), all on the GPU.
+
+    Lower solves stop at ||grad Phi|| <= 1e-8 or after LBFGS_CAP iterations (the smoothing
+    weight the descent reaches makes 1e-8 unreachable in reasonable time at 256x256); the
+    gradient norms reached are logged.  The Hessian systems of the sequence are SPD at any
+    point, so the frozen sequence is a valid workload either way.
+    """
+    th = np.array(theta0, dtype=np.float64)
+    x = y.clone()
+    ctx.lower_solve_p(P, th, y, x, gtol=gtol, max_iter=LBFGS_CAP)
+    c1 = upper_loss(x, xs)
+    beta = 1.0
+    thetas, xhats = [], []
+    w = torch.zeros_like(x)
+    nl = []
+    for i in range(outer):
+        thetas.append(th.copy())
+        xhats.append(x.clone())
+        g = x - xs
+        w.zero_()
+        ctx.solve_p(P, None, th, x, g, w, tol=1e-12, store_basis=False, recycle=False, max_iter=50000,
+                    allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+        grad = ctx.hypergradient_p(P, th, x, w)
+        d = -grad
+        c2 = float(grad @ d)
+        xprev = x
+        for j in range(1, 31):
+            tau = beta * 0.5 ** (j - 1)
+            thj = th + tau * d
+            xj = xprev.clone()
+            lst = ctx.lower_solve_p(P, thj, y, xj, gtol=gtol, max_iter=LBFGS_CAP)
+            nl.append((lst.iters, float(f"{lst.res_norm:.1e}")))
+            c0 = upper_loss(xj, xs)
+            if c0 <= c1 + 1e-4 * tau * c2:
+                th, x, c1, beta = thj, xj, c0, 2.0 * tau
+                break
+            xprev = xj
+        log(f"  trajectory step {i + 1}/{outer}: loss {c1:.6e} L-BFGS (iterations, |grad|) {nl}")
+        nl.clear()
+    return thetas, xhats
+
+
+def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL, rr_every=50):
+    """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain'; thr: the stopping
+    threshold (residual tolerance, or the error-estimate threshold relative to the previous
+    hypergradient norm).  Returns per-solve records."""
+    S.reset()
+    w = torch.zeros_like(xs)
+    prev_hg = None
+    recs = []
+    for i, (th, x) in enumerate(zip(thetas, xhats)):
+        t0 = time.perf_counter()
+        g = x - xs
+        if mode != "plain" and i > 0:
+            S.refresh(th, x, s=S.rs.s_max)
+        if mode == "rgen_hg" and S.rs.s_cur > 0 and prev_hg is not None:
+            st = S.solve(th, x, g, w, stop="hgerr", hg_tol=thr * prev_hg, tol=RESID_TOL, store_basis=True,
+                         rr_every=rr_every)
+        else:
+            # first system of the error-estimate variant (no recycle space yet): residual test
+            st = S.solve(th, x, g, w, tol=RESID_TOL if mode == "rgen_hg" else thr,
+                         store_basis=(mode != "plain"), recycle=(mode != "plain"), rr_every=rr_every)
+        hg = S.hypergradient(th, x, w)
+        t1 = time.perf_counter()
+        if lat is not None:
+            lat.append((t1 - t0) * 1e3)
+        prev_hg = float(np.linalg.norm(hg))
+        recs.append({"iters": st.iters, "err": rel_err(hg, refs[i]), "status": st.status})
+    return recs
+
+
+def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep):
+    for thr in sweep:
+        rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr)
+        if all(r["err"] <= 1e-6 and r["status"] == 0 for r in rr):
+            return thr
+    return sweep[-1]
+
+
+def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=None):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat, thr=thr) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
+    total = sum(len(rr) for rr in recs)
+    return recs, el, ok, total
+
+
+def cpu_baseline_sequence(wl, seconds_budget=25.0):
+    """The CPU oracle timed on a bounded sample of the same workload (consecutive systems).
+
+    The oracle takes no input from the GPU path, so the sample uses stand-in points
+    x_hat = x* + 0.05 e' (e' a separate seeded normal field) and a theta path stepping
+    away from the initial value; each system is refreshed, solved by recycled CG
+    (residual stop 1e-10) and mapped to its hypergradient, as on the GPU.
+    """
+    import synth
+    from oracle import krylov, problem, recycle
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xs = inst["xstar"].ravel()
+    xh = xs + 0.05 * synth.unit_noise(prob.n, wl.seed + 77)
+    path = synth.theta_drift(wl, 3, wl.seed + 78, scale=0.01)
+    U = V = None
+    w = None
+    done = 0
+    t0 = time.perf_counter()
+    for th in path:
+        hvp = lambda v, th=th: prob.hvp(xh, th, v)
+        jac = lambda v, th=th: prob.jac_apply(xh, th, v)
+        rs = recycle.refresh(hvp, jac, U, V, wl.s) if (U is not None or V is not None) else {"U": None, "C": None}
+        res = krylov.recycled_cg(hvp, xh - xs, w, rs["U"], rs["C"], tol=RESID_TOL, v_cap=V_CAP)
+        jac(res["w"])
+        U, V, w = rs["U"], res["V"], res["w"]
+        done += 1
+        if time.perf_counter() - t0 > seconds_budget:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "solves/s", "cores": int(threads_used()), "kind": "oracle",
+            "sample": f"{done} consecutive {wl.h}x{wl.w} {wl.reg} systems (refresh + recycled CG 1e-10 + "
+                      f"hypergradient) at stand-in points x*+0.05e', numpy FP64, {el:.1f} s; host "
+                      f"{len(os.sched_getaffinity(0))} affinity cores"}
+
+
+def bench_sequence(args, B, torch, synth):
+    wl = synth.WORKLOADS[args.workload]
+    outer = args.outer or wl.outer
+    dev = torch.device("cuda:0")
+    inst = synth.instance(wl)
+    P64 = B.problem_from(wl, prec="fp64")
+    S = B.Session(P64, s_max=wl.s, v_cap=V_CAP, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs, e = t(inst["xstar"]), t(inst["e"])
+    y = torch.empty_like(xs)
+    S.forward(xs, e, wl.noise, y)
+    log(f"[bench] {args.workload}: {wl.h}x{wl.w} {wl.reg}, s={wl.s}, outer={outer}; building the trajectory")
+    tt = time.perf_counter()
+    thetas, xhats = make_trajectory(S, P64, B, wl, torch, y, xs, inst["theta0"], outer)
+    log(f"[bench] trajectory built in {time.perf_counter() - tt:.1f} s; reference hypergradients")
+    refs = []
+    w = torch.zeros_like(xs)
+    for th, x in zip(thetas, xhats):
+        w.zero_()
+        S.solve(th, x, x - xs, w, tol=1e-13, store_basis=False, recycle=False, max_iter=100000,
+                allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+        refs.append(S.hypergradient(th, x, w))
+    mixed = wl.prec == "mixed"
+    Sh = B.Session(B.problem_from(wl, prec="mixed"), s_max=wl.s, v_cap=V_CAP, device=dev) if mixed else S
+    # threshold selection (untimed): loosest setting with every hypergradient within 1e-6
+    variants = [("rgen_hg", Sh, SWEEP_HG), ("rgen_res", Sh, SWEEP_RESID), ("plain", S, SWEEP_RESID)]
+    if mixed:
+        variants.append(("rgen_hg_fp64", S, SWEEP_HG))
+    chosen = {}
+    for name, SS, sweep in variants:
+        chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, name.replace("_fp64", ""), refs, sweep)
+        log(f"[bench] {name}: threshold {chosen[name]:g}")
+    for _ in range(args.warmup):
+        run_sequence(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, thr=chosen["rgen_hg"])
+    # timed: headline (recycled + error-estimate stop), per-kernel events on the library's stream
+    Sh.set_timing(2)
+    Sh.kernel_times(reset=True)
+    lat = []
+    recs, el, ok, total = timed_passes(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, chosen["rgen_hg"],
+                                       args.steps, lat)
+    kt = Sh.kernel_times(reset=True)
+    Sh.set_timing(0)
+    value = ok / el
+    extra = {}
+    for name, SS, _ in variants[1:]:
+        mode = name.replace("_fp64", "")
+        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name])
+        rr, elm, okm, totm = timed_passes(SS, B, torch, thetas, xhats, xs, mode, refs, chosen[name], args.steps)
+        extra[name] = {"solves_per_s": okm / elm, "threshold": chosen[name],
+                       "iters_per_sequence": sum(r["iters"] for r in rr[0]),
+                       "max_rel_err": max(r["err"] for r in rr[0]), "passing": f"{okm}/{totm}"}
+    head = recs[0]
+    iters_seq = sum(r["iters"] for r in head)
+    prec = "mixed" if mixed else "fp64"
+    bpp = apply_bytes_per_pixel(wl.reg, prec, wl.s, wl.n_filters)
+    # every timed pass runs the same iterations: algorithmic bytes of all apply launches
+    total_bytes = bpp * wl.n * iters_seq * args.steps
+    kname = f"k_b_apply<{'float' if mixed else 'double'},{wl.blur_radius}>"
+    desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
+            f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
+            f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad|"
+            + (", FP32 stencils + FP64 rest with residual replacement" if mixed else ""))
+    out = base_line(args, value, el, "f32+f64" if mixed else "f64",
+                    {"workload": desc, "outer_steps": outer, "s": wl.s, "v_cap": V_CAP, "n": wl.n},
+                    passing=f"{ok}/{total}",
+                    latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                    iters_per_sequence={"rgen_hg": iters_seq, **{k: v["iters_per_sequence"] for k, v in extra.items()}},
+                    max_rel_err=max(r["err"] for r in head),
+                    speedup_vs_plain_cg=value / extra["plain"]["solves_per_s"],
+                    plain_cg=extra["plain"], rgen_resid=extra["rgen_res"],
+                    roofline=roofline(kname, total_bytes, kt, args.workload))
+    if mixed:
+        out["rgen_hg_fp64"] = extra["rgen_hg_fp64"]
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline_sequence(wl)
+    S.close()
+    if Sh is not S:
+        Sh.close()
+    return out
+
+
+# =============================================================================== batched training set
+def bench_batch(args, B, torch, synth):
+    """64 filter images, shared theta: per outer step a refresh of every image's recycle space,
+    one engine advancing all 64 recycled solves together, and the summed hypergradient."""
+    wls = synth.batch_set(args.batch, 4000, s=20)
+    T = args.outer or 4
+    dev = torch.device("cuda:0")
+    prec = args.prec
+    Ps = [B.problem_from(wl, prec=prec) for wl in wls]
+    P64 = [B.problem_from(wl, prec="fp64") for wl in wls]
+    ctx = B.Context(P64, s_max=20, v_cap=V_CAP, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs, ys, xcur = [], [], []
+    for wl, P in zip(wls, P64):
+        inst = synth.instance(wl)
+        xsk, ek = t(inst["xstar"]), t(inst["e"])
+        yk = torch.empty_like(xsk)
+        ctx.forward_p(P, xsk, ek, wl.noise, yk)
+        xs.append(xsk)
+        ys.append(yk)
+        xcur.append(yk.clone())
+    theta = synth.instance(wls[0])["theta0"].copy()   # shared theta (filters seeded alike)
+    nf, f2 = wls[0].n_filters, wls[0].filter_size ** 2
+    log(f"[bench] batch{len(wls)}: sum n = {sum(w.n for w in wls)}, {T} Adam steps to build the frozen sequence")
+    # frozen sequence: Adam (lr 1e-2) on the summed upper loss; tap updates kept zero-mean
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    thetas, xhats, refs = [], [], []
+    opts_ref = B.solve_opts(tol=1e-12, max_iter=100000, store_basis=False)
+    tt = time.perf_counter()
+    for i in range(T):
+        its = []
+        for k, P in enumerate(P64):
+            st = ctx.lower_solve_p(P, theta, ys[k], xcur[k], gtol=1e-6, max_iter=400)
+            its.append(st.iters)
+        thetas.append(theta.copy())
+        xhats.append([x.clone() for x in xcur])
+        wref = [torch.zeros_like(x) for x in xcur]
+        code, _ = B.hessian_solve_batched(P64, [theta] * len(P64), xcur, [x - s for x, s in zip(xcur, xs)], wref,
+                                          [None] * len(P64), opts_ref, device=dev, ctx=ctx.ctx)
+        hgs = [ctx.hypergradient_p(P, theta, x, w) for P, x, w in zip(P64, xcur, wref)]
+        refs.append(hgs)
+        grad = np.sum(hgs, axis=0)
+        m = 0.9 * m + 0.1 * grad
+        v = 0.999 * v + 0.001 * grad * grad
+        step = 1e-2 * (m / (1 - 0.9 ** (i + 1))) / (np.sqrt(v / (1 - 0.999 ** (i + 1))) + 1e-8)
+        for j in range(nf):
+            blk = step[j * (1 + f2) + 1:(j + 1) * (1 + f2)]
+            blk -= blk.mean()
+        theta = theta - step
+        log(f"  step {i + 1}/{T}: L-BFGS iterations max {max(its)} mean {np.mean(its):.0f}, "
+            f"|grad| {np.linalg.norm(grad):.3e} ({time.perf_counter() - tt:.1f} s)")
+    recs = [B.Recycle(w.n, 20, V_CAP, dev) for w in wls]
+    arena = int(lib_batched_bytes(B, Ps, [20] * len(Ps)) * 1.02)
+    eng = B.Engine(cap=min(len(Ps), 64), arena_bytes=arena, device=dev, ctx=ctx.ctx)
+
+    def one_pass(mode, thr, stats=None):
+        """The sequence once: mode 'rgen_hg' (refresh + error-estimate stop), 'plain' (residual)."""
+        for r in recs:
+            r.rs.s_cur = 0
+            r.rs.v_cur = 0
+        ws = [torch.zeros_like(x) for x in xs]
+        prev = [None] * len(Ps)
+        errs, iters = [], []
+        for i in range(T):
+            xh = xhats[i]
+            if mode != "plain" and i > 0:
+                for k, P in enumerate(P64):
+                    ctx.refresh_p(P, recs[k], thetas[i], xh[k], s=20)
+            slot_of = {}
+            for k, P in enumerate(Ps):
+                use_hg = mode == "rgen_hg" and recs[k].rs.s_cur > 0 and prev[k] is not None
+                o = B.solve_opts(stop="hgerr" if use_hg else "resid", hg_tol=thr * prev[k] if use_hg else 0.0,
+                                 tol=RESID_TOL if mode != "plain" else thr, store_basis=mode != "plain",
+                                 rr_every=50)
+                sl = eng.admit(P, thetas[i], xh[k], xh[k] - xs[k], ws[k], recs[k] if mode != "plain" else None, o)
+                assert sl is not None, "engine arena too small"
+                slot_of[sl] = k
+            while slot_of:
+                for sl in eng.step(return_on_done=False):
+                    k = slot_of.pop(sl)
+                    st = eng.retire(sl)
+                    iters.append(st.iters)
+                    if stats is not None:
+                        stats.append((k, st.iters))
+            hg = [ctx.hypergradient_p(P, thetas[i], xh[k], ws[k]) for k, P in enumerate(P64)]
+            for k in range(len(Ps)):
+                prev[k] = float(np.linalg.norm(hg[k]))
+                errs.append(rel_err(hg[k], refs[i][k]))
+        return errs, iters
+
+    chosen = {}
+    for mode, sweep in (("rgen_hg", SWEEP_HG), ("plain", SWEEP_RESID)):
+        chosen[mode] = sweep[-1]
+        for thr in sweep:
+            errs, _ = one_pass(mode, thr)
+            if max(errs) <= 1e-6:
+                chosen[mode] = thr
+                break
+        log(f"[bench] batch {mode}: threshold {chosen[mode]:g}")
+    for _ in range(args.warmup):
+        one_pass("rgen_hg", chosen["rgen_hg"])
+    ctx.set_timing(2)
+    ctx.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    allerr, alliters, stats = [], [], []
+    for _ in range(args.steps):
+        errs, its = one_pass("rgen_hg", chosen["rgen_hg"], stats)
+        allerr += errs
+        alliters += its
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_timing(0)
+    ok = sum(1 for e in allerr if e <= 1e-6)
+    value = ok / el
+    total_bytes = sum(apply_bytes_per_pixel("filters", prec, 20, nf) * wls[k].n * it for k, it in stats)
+    one_pass("plain", chosen["plain"])
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    perr, piters = [], []
+    for _ in range(args.steps):
+        e_, i_ = one_pass("plain", chosen["plain"])
+        perr += e_
+        piters += i_
+    torch.cuda.synchronize()
+    elp = time.perf_counter() - tp
+    okp = sum(1 for e in perr if e <= 1e-6)
+    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'},5>"
+    out = base_line(args, value, el, "f32+f64" if prec == "mixed" else "f64",
+                    {"workload": f"batch{len(wls)}: {len(wls)} filter images (8 x 7x7, blur r=5 sigma=3, noise 0.02), "
+                                 f"sides {sorted(set(w.h for w in wls))}, sum n = {sum(w.n for w in wls)}, shared theta, "
+                                 f"{T} frozen Adam steps, RGen-L(R) s=20 per image, one engine for all solves",
+                     "images": len(wls), "outer_steps": T, "s": 20, "sum_n": sum(w.n for w in wls)},
+                    passing=f"{ok}/{len(allerr)}", max_rel_err=max(allerr),
+                    iters_per_pass={"rgen_hg": sum(alliters) // args.steps, "plain": sum(piters) // args.steps},
+                    plain_cg={"solves_per_s": okp / elp, "threshold": chosen["plain"], "passing": f"{okp}/{len(perr)}"},
+                    speedup_vs_plain_cg=value / max(okp / elp, 1e-30),
+                    roofline=roofline(kname, total_bytes, kt, "batch64"))
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline_batch(wls)
+    eng.close()
+    ctx.close()
+    return out
+
+
+def lib_batched_bytes(B, Ps, s):
+    import ctypes as C
+    arr = (B.bl_problem * len(Ps))(*Ps)
+    sv = (C.c_int * len(Ps))(*s)
+    return int(B.lib.bl_batched_workspace_bytes(len(Ps), arr, sv))
+
+
+def cpu_baseline_batch(wls, seconds_budget=25.0):
+    """The oracle on images of the batch taken smallest first (stand-in points x* + 0.05 e'),
+    each a plain-start recycled CG solve (no recycle space yet) + hypergradient."""
+    import synth
+    from oracle import krylov, problem
+    order = sorted(range(len(wls)), key=lambda k: wls[k].n)
+    done, px = 0, 0
+    t0 = time.perf_counter()
+    for k in order:
+        wl = wls[k]
+        inst = synth.instance(wl)
+        prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+        xs = inst["xstar"].ravel()
+        xh = xs + 0.05 * synth.unit_noise(prob.n, wl.seed + 77)
+        th = inst["theta0"]
+        res = krylov.recycled_cg(lambda v: prob.hvp(xh, th, v), xh - xs, None, None, None, tol=RESID_TOL, v_cap=0)
+        prob.jac_apply(xh, th, res["w"])
+        done += 1
+        px += wl.n
+        if time.perf_counter() - t0 > seconds_budget:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "solves/s", "cores": int(threads_used()), "kind": "oracle",
+            "sample": f"{done} of the {len(wls)} images, smallest first ({px} pixels; the batch has "
+                      f"{sum(w.n for w in wls)}), CG 1e-10 + hypergradient at stand-in points x*+0.05e', numpy FP64, "
+                      f"{el:.1f} s; host {len(os.sched_getaffinity(0))} affinity cores"}
+
+
+# =============================================================================== served stream
+def bench_serve(args, B, torch, synth):
+    """Poisson request stream over resident samples served by continuous batching."""
+    from paper_2412_08264_amd import serve
+    dev = torch.device("cuda:0")
+    wls = synth.serve_samples(256, 5000)[: args.samples]
+    T = args.outer or 4
+    P64 = [B.problem_from(wl, prec="fp64") for wl in wls]
+    ctx = B.Context(P64, s_max=max(w.s for w in wls), v_cap=args.v_cap, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    log(f"[bench] serve: {len(wls)} samples, sum n = {sum(w.n for w in wls)}, {T} frozen outer steps each")
+    tt = time.perf_counter()
+    data = []
+    for k, (wl, P) in enumerate(zip(wls, P64)):
+        inst = synth.instance(wl)
+        xs, e = t(inst["xstar"]), t(inst["e"])
+        y = torch.empty_like(xs)
+        ctx.forward_p(P, xs, e, wl.noise, y)
+        path = synth.theta_drift(wl, T, wl.seed + 99)
+        x = y.clone()
+        xhats = []
+        for th in path:
+            ctx.lower_solve_p(P, th, y, x, gtol=1e-6, max_iter=300)
+            xhats.append(x.clone())
+        data.append((path, xhats, xs))
+    log(f"[bench] frozen steps built in {time.perf_counter() - tt:.1f} s")
+    arrivals = synth.poisson_arrivals(args.rate, args.warm_s + args.duration, len(wls), seed=5001)
+    modes = {}
+    for prec in ("mixed", "fp64"):
+        Ps = [B.problem_from(wl, prec=prec) for wl in wls]
+        arena = sum(B.Engine.slot_bytes(P, wl.s) for P, wl in zip(Ps, wls))
+        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel)
+        for k, (wl, P) in enumerate(zip(wls, Ps)):
+            path, xhats, xs = data[k]
+            srv.add_sample(serve.Sample(k, P, path, xhats, xs, wl.s, args.v_cap, dev))
+        ctx.set_timing(2)
+        ctx.kernel_times(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        srv.clock = lambda: time.perf_counter() - t0
+        i = 0
+        end = args.warm_s + args.duration
+        while True:
+            now = srv.clock()
+            while i < len(arrivals) and arrivals[i][0] <= now:
+                srv.submit(arrivals[i][1], arrivals[i][0])
+                i += 1
+            if now >= end:
+                break
+            if srv.idle():
+                if i < len(arrivals):
+                    time.sleep(max(0.0, min(arrivals[i][0] - now, 1e-3)))
+                continue
+            srv.turn()
+        backlog = len(srv.queue) + len(srv.running)
+        kt = ctx.kernel_times(reset=True)
+        ctx.set_timing(0)
+        win = [r for r in srv.completed if r.t_arrival >= args.warm_s]
+        # references for every (sample, step) served in the window: FP64 CG to 1e-12
+        refs = {}
+        for r in win:
+            key = (r.sample.key, r.step)
+            if key in refs:
+                continue
+            smp = r.sample
+            w = torch.zeros_like(smp.xstar)
+            ctx.solve_p(smp.P64, None, smp.thetas[r.step], smp.xhats[r.step], smp.xhats[r.step] - smp.xstar, w,
+                        tol=1e-12, recycle=False, store_basis=False, max_iter=100000,
+                        allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+            refs[key] = ctx.hypergradient_p(smp.P64, smp.thetas[r.step], smp.xhats[r.step], w)
+        errs = [rel_err(r.hg, refs[(r.sample.key, r.step)]) for r in win]
+        ok = sum(1 for r, e in zip(win, errs) if e <= 1e-6 and r.stats.status == 0)
+        lat = [(r.t_done - r.t_arrival) * 1e3 for r in win]
+        bpp = lambda smp: apply_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec, smp.s,
+                                                smp.P.n_filters)
+        total_bytes = sum(bpp(r.sample) * r.sample.P.h * r.sample.P.w * r.stats.iters for r in srv.completed)
+        modes[prec] = {"solves_per_s": ok / args.duration, "completed": len(win), "passing": f"{ok}/{len(win)}",
+                       "arrived": sum(1 for a in arrivals if args.warm_s <= a[0] < end),
+                       "backlog_at_end": backlog,
+                       "latency_ms": {"p50": float(np.percentile(lat, 50)) if lat else None,
+                                      "p99": float(np.percentile(lat, 99)) if lat else None},
+                       "max_rel_err": max(errs) if errs else None,
+                       "mean_iters": float(np.mean([r.stats.iters for r in win])) if win else None,
+                       "roofline": roofline("k_b_apply<*> (all classes)", total_bytes, kt, "serve")}
+        log(f"[bench] serve {prec}: {modes[prec]['solves_per_s']:.1f} solves/s, p50 "
+            f"{modes[prec]['latency_ms']['p50']} ms, p99 {modes[prec]['latency_ms']['p99']} ms, backlog {backlog}")
+        srv.close()
+    head = modes["mixed"]
+    out = base_line(args, head["solves_per_s"], args.duration * 1e3 * args.steps, "f32+f64",
+                    {"workload": f"serve: {len(wls)} resident samples (sides {sorted(set(w.h for w in wls))}, TV or "
+                                 f"8 x 7x7 filters, s in {sorted(set(w.s for w in wls))}), {T} frozen outer steps each, "
+                                 f"Poisson arrivals {args.rate:g}/s, {args.duration:g} s window after {args.warm_s:g} s, "
+                                 f"continuous batching (engine cap 64), mixed precision; FP64 beside it",
+                     "samples": len(wls), "rate_per_s": args.rate, "window_s": args.duration},
+                    latency_ms=head["latency_ms"], passing=head["passing"], mixed=head, fp64=modes["fp64"],
+                    roofline=head["roofline"])
+    out["steps"] = 1
+    out["ms_per_step"] = args.duration * 1e3
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline_serve(wls, data_steps=T)
+    ctx.close()
+    return out
+
+
+def cpu_baseline_serve(wls, data_steps, seconds_budget=25.0):
+    """The oracle serving requests serially on the smallest samples (stand-in points
+    x* + 0.05 e'): per request a recycled CG solve (refresh after the first) + hypergradient."""
+    import synth
+    from oracle import krylov, problem, recycle
+    order = sorted(range(len(wls)), key=lambda k: wls[k].n)
+    done = 0
+    t0 = time.perf_counter()
+    for k in order:
+        wl = wls[k]
+        inst = synth.instance(wl)
+        prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+        xs = inst["xstar"].ravel()
+        xh = xs + 0.05 * synth.unit_noise(prob.n, wl.seed + 77)
+        U = V = w = None
+        for th in synth.theta_drift(wl, min(data_steps, 2), wl.seed + 99):
+            hvp = lambda v, th=th: prob.hvp(xh, th, v)
+            jac = lambda v, th=th: prob.jac_apply(xh, th, v)
+            rs = recycle.refresh(hvp, jac, U, V, wl.s) if V is not None else {"U": None, "C": None}
+            res = krylov.recycled_cg(hvp, xh - xs, w, rs["U"], rs["C"], tol=RESID_TOL, v_cap=V_CAP)
+            jac(res["w"])
+            U, V, w = rs["U"], res["V"], res["w"]
+            done += 1
+        if time.perf_counter() - t0 > seconds_budget:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "solves/s", "cores": int(threads_used()), "kind": "oracle",
+            "sample": f"{done} requests served serially on the smallest samples (2 outer steps each, refresh + "
+                      f"recycled CG 1e-10 + hypergradient) at stand-in points x*+0.05e', numpy FP64, {el:.1f} s; host "
+                      f"{len(os.sched_getaffinity(0))} affinity cores"}
+
+
+# =============================================================================== kernels-only
+def kernels_only(args, B, torch, synth):
     """Short run for hardware counters: 200 plain and 200 recycled CG iterations on the
     workload's shape at a stand-in point, and one 64 MiB device-to-device copy (counter
     calibration: its FETCH_SIZE / WRITE_SIZE should read 64 MiB each)."""
+    wl = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     inst = synth.instance(wl)
     S = B.Session(B.problem_from(wl), s_max=wl.s, v_cap=V_CAP, device=dev)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
     xs = t(inst["xstar"])
     xh = xs + 0.05 * t(synth.unit_noise(wl.n, wl.seed + 77))
-    th = synth.initial_theta(wl, inst["filters"])
+    th = inst["theta0"]
     w = torch.zeros_like(xs)
     S.solve(th, xh, xh - xs, w, tol=0.0, max_iter=200, store_basis=True, allow=(B.BL_E_NOT_CONVERGED,))
     S.refresh(th, xh, s=wl.s)
@@ -211,14 +670,22 @@ def kernels_only(wl, B, torch, synth):
 
 
 def main():
-    global synth_mod
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tv256")
+    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--outer", type=int, default=0, help="override the number of outer steps")
+    ap.add_argument("--batch", type=int, default=64, help="batch64: number of images")
+    ap.add_argument("--prec", default="mixed", choices=("mixed", "fp64"), help="batch64: precision")
+    ap.add_argument("--samples", type=int, default=64, help="serve: resident samples (of the 256-sample recipe)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: measured window (s)")
+    ap.add_argument("--warm-s", dest="warm_s", type=float, default=3.0, help="serve: warm-up part of the stream (s)")
+    ap.add_argument("--hg-rel", dest="hg_rel", type=float, default=1e-9, help="serve: error-estimate threshold "
+                    "relative to the sample's previous hypergradient norm")
+    ap.add_argument("--v-cap", dest="v_cap", type=int, default=V_CAP, help="serve: stored Krylov vectors per sample")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: a few recycled-CG iterations on the workload's shape at stand-in points "
                          "x* + 0.05 e' (no trajectory) plus a 64 MiB device copy for counter calibration")
@@ -232,121 +699,16 @@ def main():
 
     import synth
     from paper_2412_08264_amd import bilevel as B
-    synth_mod = synth
-
-    wl = synth.WORKLOADS[args.workload]
-    outer = args.outer or wl.outer
+    torch.cuda.set_device(torch.device("cuda:0"))
     if args.kernels_only:
-        kernels_only(wl, B, torch, synth)
+        kernels_only(args, B, torch, synth)
         return
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    inst = synth.instance(wl)
-    P = B.problem_from(wl)
-    S = B.Session(P, s_max=wl.s, v_cap=V_CAP, device=dev)
-    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
-    xs, e = t(inst["xstar"]), t(inst["e"])
-    y = torch.empty_like(xs)
-    S.forward(xs, e, wl.noise, y)
-    log(f"[bench] {args.workload}: {wl.h}x{wl.w}, s={wl.s}, outer={outer}; building the trajectory")
-    tt = time.perf_counter()
-    thetas, xhats = make_trajectory(S, B, wl, torch, y, xs, outer)
-    log(f"[bench] trajectory built in {time.perf_counter() - tt:.1f} s; reference hypergradients")
-    refs = []
-    w = torch.zeros_like(xs)
-    for th, x in zip(thetas, xhats):
-        w.zero_()
-        S.reset()
-        S.solve(th, x, x - xs, w, tol=1e-13, store_basis=False, recycle=False, max_iter=100000,
-                allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
-        refs.append(S.hypergradient(th, x, w))
-
-    # threshold selection (untimed): loosest setting with every hypergradient within 1e-6
-    chosen = {}
-    for mode, sweep in (("rgen_hg", SWEEP_HG), ("rgen_res", SWEEP_RESID), ("plain", SWEEP_RESID)):
-        chosen[mode] = sweep[-1]
-        for thr in sweep:
-            rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr)
-            if all(r["err"] <= 1e-6 and r["status"] == 0 for r in rr):
-                chosen[mode] = thr
-                break
-        log(f"[bench] {mode}: threshold {chosen[mode]:g}")
-    # warmup
-    for _ in range(args.warmup):
-        run_sequence(S, B, torch, thetas, xhats, xs, "rgen_hg", refs, thr=chosen["rgen_hg"])
-    torch.cuda.synchronize()
-    # timed: headline (recycled + error-estimate stop), per-kernel events on the library's stream
-    S.set_timing(2)
-    S.kernel_times(reset=True)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    recs = []
-    for _ in range(args.steps):
-        recs.append(run_sequence(S, B, torch, thetas, xhats, xs, "rgen_hg", refs, lat, thr=chosen["rgen_hg"]))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kt = S.kernel_times(reset=True)
-    S.set_timing(0)
-    ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
-    total = sum(len(rr) for rr in recs)
-    value = ok / el
-    # comparison passes (timed the same way, reported beside the headline)
-    extra = {}
-    for mode in ("plain", "rgen_res"):
-        run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[mode])
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        rr = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[mode]) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        elm = time.perf_counter() - tm
-        okm = sum(1 for r1 in rr for r in r1 if r["err"] <= 1e-6 and r["status"] == 0)
-        extra[mode] = {"solves_per_s": okm / elm, "threshold": chosen[mode],
-                       "iters_per_sequence": sum(r["iters"] for r in rr[0]),
-                       "max_rel_err": max(r["err"] for r in rr[0]), "passing": f"{okm}/{sum(len(r1) for r1 in rr)}"}
-    head = recs[0]
-    n = wl.n
-    # roofline of the dominant kernel (fused H p + p.q + C^T q): algorithmic bytes per launch
-    s = wl.s
-    iters_seq = sum(r["iters"] for r in head)
-    apply_ms = kt[0] / max(kt[1], 1.0)
-    bytes_apply = (5 + s) * 8 * n          # read r, p, xhat, C (s columns); write p, q
-    achieved = bytes_apply / (apply_ms * 1e-3) / 1e9
-    traffic = measured_traffic("k_cg_apply<double>", args.workload)
-    out = {
-        "metric": "hypergradient Hessian solves/sec (recycled vs plain CG) at rel err 1e-6; p99 ms",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl.h}x{wl.w} smoothed-TV deblurring, blur r={wl.blur_radius} "
-                               f"sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
-                               f"RGen-L(R) s={s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad|",
-                   "outer_steps": outer, "s": s, "v_cap": V_CAP, "n": n},
-        "passing": f"{ok}/{total}",
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "iters_per_sequence": {"rgen_hg": iters_seq, "rgen_res": extra["rgen_res"]["iters_per_sequence"],
-                               "plain": extra["plain"]["iters_per_sequence"]},
-        "max_rel_err": max(r["err"] for r in head),
-        "speedup_vs_plain_cg": value / extra["plain"]["solves_per_s"],
-        "plain_cg": extra["plain"],
-        "rgen_resid": extra["rgen_res"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": traffic,
-                     "kernel": "k_cg_apply<double>", "avg_launch_us": apply_ms * 1e3,
-                     "launches": int(kt[1]), "update_avg_us": kt[2] / max(kt[3], 1.0) * 1e3},
-    }
-    if not args.no_cpu:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(wl)
-    S.close()
+    if args.workload == "batch64":
+        out = bench_batch(args, B, torch, synth)
+    elif args.workload == "serve":
+        out = bench_serve(args, B, torch, synth)
+    else:
+        out = bench_sequence(args, B, torch, synth)
     print(json.dumps(out), flush=True)
 
 

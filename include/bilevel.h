@@ -174,10 +174,10 @@ bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
 
 /* ------------------------------------------------------------------------------------------
  * Batched and served Hessian solves.  An engine runs up to `cap` (<= 64) recycled-CG solves
- * of one operator class (every bl_problem field but h, w equal) side by side: each
- * iteration is one launch of the fused apply kernel (H p with p.q and C^T q) and one of the
- * update kernel over all running solves, whatever their sizes, recycle dimensions and
- * iteration indices.  Every solve reduces only its own records in a fixed order, so its
+ * side by side: each iteration is one launch of the fused apply kernel (H p with p.q and
+ * C^T q) per operator class (problems equal in every bl_problem field but h, w; at most 4
+ * classes at a time) and one launch of the update kernel over all running solves, whatever
+ * their sizes, recycle dimensions and iteration indices.  Every solve reduces only its own records in a fixed order, so its
  * iterates, iteration count and status are bitwise those of the same solve run alone
  * (bl_hessian_solve, which is a one-solve engine).  Solves are admitted and retired
  * between steps (continuous batching).  The engine's device memory is one caller-owned
@@ -192,16 +192,16 @@ size_t bl_engine_slot_bytes(const bl_problem* P, int s);
 /* Workspace for an engine of `cap` slots (1..64) with an arena of arena_bytes. */
 size_t bl_engine_workspace_bytes(int cap, size_t arena_bytes);
 /* Engine over the workspace ws (256-byte aligned); the arena is whatever ws_bytes leaves
- * after the fixed part.  cls fixes the operator class; its h, w are ignored. */
-bl_status bl_engine_create(bl_ctx* ctx, const bl_problem* cls, int cap, void* ws, size_t ws_bytes,
-                           bl_engine** engine);
+ * after the fixed part. */
+bl_status bl_engine_create(bl_ctx* ctx, int cap, void* ws, size_t ws_bytes, bl_engine** engine);
 bl_status bl_engine_destroy(bl_engine* engine);
 /* Admit the solve H(theta, xhat) w = g with recycle state rs (NULL or s_cur = 0: plain CG)
  * and options opts; same arguments and meaning as bl_hessian_solve.  theta and opts are
  * read during the call; xhat, g, w, rs and its arrays must stay valid until retirement.
  * Set-up work (FP64 residual, projection onto C) is enqueued at once.  Returns
  * BL_E_WORKSPACE (nothing enqueued) when no slot or no arena block of
- * bl_engine_slot_bytes() is free: retire a completed solve and try again. */
+ * bl_engine_slot_bytes() is free: retire a completed solve and try again; BL_E_ARG when the
+ * problem would be a fifth operator class among the admitted solves. */
 bl_status bl_engine_admit(bl_engine* engine, const bl_problem* P, const double* theta_host, const double* xhat,
                           const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts, int* slot);
 /* Advance all running solves by at most max_iters iterations; with return_on_done, return
@@ -218,8 +218,8 @@ bl_status bl_engine_query(const bl_engine* engine, int* running, int* free_slots
 /* Workspace of bl_hessian_solve_batched for nprob problems P[k] with s[k] recycle columns
  * (s = NULL: none). */
 size_t bl_batched_workspace_bytes(int nprob, const bl_problem* P, const int* s);
-/* nprob independent solves of one operator class (P[k], theta[k], xhat[k], g[k], w[k],
- * rs[k]; rs = NULL: plain CG for all) with shared options, advanced together (at most 64 at
+/* nprob independent solves (P[k], theta[k], xhat[k], g[k], w[k], rs[k]; rs = NULL: plain CG
+ * for all; at most 4 operator classes) with shared options, advanced together (at most 64 at
  * a time; later ones are admitted as earlier ones finish).  out[k] gets the statistics of
  * solve k.  Returns BL_OK, or the first non-OK status of a solve. */
 bl_status bl_hessian_solve_batched(bl_ctx* ctx, int nprob, const bl_problem* P, const double* const* theta_host,

@@ -72,7 +72,7 @@ _SIGS = {
     "bl_kernel_times": (C.c_int, [_vp, _P(C.c_double), C.c_int]),
     "bl_engine_slot_bytes": (C.c_size_t, [_P(bl_problem), C.c_int]),
     "bl_engine_workspace_bytes": (C.c_size_t, [C.c_int, C.c_size_t]),
-    "bl_engine_create": (C.c_int, [_vp, _P(bl_problem), C.c_int, _vp, C.c_size_t, _P(_vp)]),
+    "bl_engine_create": (C.c_int, [_vp, C.c_int, _vp, C.c_size_t, _P(_vp)]),
     "bl_engine_destroy": (C.c_int, [_vp]),
     "bl_engine_admit": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
                                   _P(bl_solve_opts), _P(C.c_int)]),
@@ -155,27 +155,23 @@ def _check(ctx, st: int, name: str, ok=(BL_OK,)) -> int:
     return st
 
 
-class Session:
-    """Context + workspace + recycle storage of one problem shape (torch tensors on one device)."""
+class Context:
+    """Context + workspace for problems up to the given shapes; every call names its problem
+    and recycle storage explicitly (torch tensors on one device)."""
 
-    def __init__(self, P: bl_problem, s_max: int = 0, v_cap: int = 0, device=None, stream=None):
+    def __init__(self, problems, s_max: int = 0, v_cap: int = 0, device=None, stream=None):
         import torch
         self.torch = torch
-        self.P = P
-        self.n = P.h * P.w
-        self.p = bl_num_params(P)
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.ctx = bl_create(self.stream)
-            nbytes = bl_workspace_bytes(P, s_max, v_cap)
-            if nbytes == 0:
-                raise BLError(BL_E_ARG, "bl_workspace_bytes rejected the shape")
+            sizes = [bl_workspace_bytes(P, s_max, v_cap) for P in problems]
+            if not sizes or min(sizes) == 0:
+                raise BLError(BL_E_ARG, "bl_workspace_bytes rejected a shape")
+            nbytes = max(sizes)
             self.ws, self.ws_ptr = _aligned_workspace(nbytes, self.device)
             self.ws_bytes = nbytes
-            self.rec = Recycle(self.n, s_max, v_cap, self.device)
-        self.U, self.Cm, self.Z, self.mu, self.V = self.rec.U, self.rec.Cm, self.rec.Z, self.rec.mu, self.rec.V
-        self.rs = self.rec.rs
 
     def __enter__(self):
         return self
@@ -188,10 +184,6 @@ class Session:
             bl_destroy(self.ctx)
             self.ctx = None
 
-    def reset(self):
-        self.rs.s_cur = 0
-        self.rs.v_cur = 0
-
     def set_timing(self, mode: int = 1):
         lib.bl_set_timing(self.ctx, int(mode))
 
@@ -202,47 +194,47 @@ class Session:
         return tuple(out[:])
 
     # -- calls
-    def forward(self, x, e, noise, y):
-        _check(self.ctx, lib.bl_forward(self.ctx, C.byref(self.P), _ptr(x), _ptr(e), noise, _ptr(y),
+    def forward_p(self, P, x, e, noise, y):
+        _check(self.ctx, lib.bl_forward(self.ctx, C.byref(P), _ptr(x), _ptr(e), noise, _ptr(y),
                                         self.ws_ptr, self.ws_bytes), "bl_forward")
 
-    def hvp(self, theta, xhat, v, out, ncols: int = 1):
-        _check(self.ctx, lib.bl_hvp(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(v), _ptr(out),
+    def hvp_p(self, P, theta, xhat, v, out, ncols: int = 1):
+        _check(self.ctx, lib.bl_hvp(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), _ptr(v), _ptr(out),
                                     ncols, self.ws_ptr, self.ws_bytes), "bl_hvp")
 
-    def lower_grad(self, theta, y, x, grad) -> float:
+    def lower_grad_p(self, P, theta, y, x, grad) -> float:
         phi = C.c_double()
-        _check(self.ctx, lib.bl_lower_grad(self.ctx, C.byref(self.P), _theta(theta), _ptr(y), _ptr(x), _ptr(grad),
+        _check(self.ctx, lib.bl_lower_grad(self.ctx, C.byref(P), _theta(theta), _ptr(y), _ptr(x), _ptr(grad),
                                            C.byref(phi), self.ws_ptr, self.ws_bytes), "bl_lower_grad")
         return phi.value
 
-    def lower_solve(self, theta, y, x, gtol=1e-8, max_iter=20000, m=10) -> bl_stats:
+    def lower_solve_p(self, P, theta, y, x, gtol=1e-8, max_iter=20000, m=10) -> bl_stats:
         st = bl_stats()
-        _check(self.ctx, lib.bl_lower_solve(self.ctx, C.byref(self.P), _theta(theta), _ptr(y), _ptr(x), gtol,
+        _check(self.ctx, lib.bl_lower_solve(self.ctx, C.byref(P), _theta(theta), _ptr(y), _ptr(x), gtol,
                                             max_iter, m, self.ws_ptr, self.ws_bytes, C.byref(st)),
                "bl_lower_solve", ok=(BL_OK, BL_E_NOT_CONVERGED))
         return st
 
-    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8) -> bl_stats:
+    def refresh_p(self, P, rec, theta, xhat, s: int, rank_tol: float = 1e-8) -> bl_stats:
         st = bl_stats()
         o = bl_recycle_opts(s, rank_tol)
-        _check(self.ctx, lib.bl_recycle_update(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat),
-                                               C.byref(self.rs), C.byref(o), self.ws_ptr, self.ws_bytes,
+        _check(self.ctx, lib.bl_recycle_update(self.ctx, C.byref(P), _theta(theta), _ptr(xhat),
+                                               C.byref(rec.rs), C.byref(o), self.ws_ptr, self.ws_bytes,
                                                C.byref(st)), "bl_recycle_update", ok=(BL_OK, BL_E_RANK))
         return st
 
-    def solve(self, theta, xhat, g, w, tol=1e-10, stop: str = "resid", hg_tol: float = 0.0, max_iter: int = 20000,
-              check_every: int = 1, rr_every: int = 50, store_basis: bool = True, recycle: bool = True,
-              allow=(BL_OK,)) -> bl_stats:
+    def solve_p(self, P, rec, theta, xhat, g, w, tol=1e-10, stop: str = "resid", hg_tol: float = 0.0,
+                max_iter: int = 20000, check_every: int = 1, rr_every: int = 50, store_basis: bool = True,
+                recycle: bool = True, allow=(BL_OK,)) -> bl_stats:
         st = bl_stats()
         o = bl_solve_opts(BL_STOP_HGERR if stop == "hgerr" else BL_STOP_RESID, tol, hg_tol, max_iter, check_every,
                           rr_every, 1 if store_basis else 0)
-        rs = self.rs if recycle or store_basis else None
+        rs = rec.rs if rec is not None and (recycle or store_basis) else None
         saved = None
         if rs is not None and not recycle:
             saved, rs.s_cur = rs.s_cur, 0
         try:
-            code = lib.bl_hessian_solve(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(g), _ptr(w),
+            code = lib.bl_hessian_solve(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), _ptr(g), _ptr(w),
                                         C.byref(rs) if rs is not None else None, C.byref(o), self.ws_ptr,
                                         self.ws_bytes, C.byref(st))
         finally:
@@ -251,11 +243,49 @@ class Session:
         _check(self.ctx, code, "bl_hessian_solve", ok=allow)
         return st
 
-    def hypergradient(self, theta, xhat, w, project: bool = True) -> np.ndarray:
-        out = (C.c_double * self.p)()
-        _check(self.ctx, lib.bl_hypergradient(self.ctx, C.byref(self.P), _theta(theta), _ptr(xhat), _ptr(w), out,
+    def hypergradient_p(self, P, theta, xhat, w, project: bool = True) -> np.ndarray:
+        out = (C.c_double * bl_num_params(P))()
+        _check(self.ctx, lib.bl_hypergradient(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), _ptr(w), out,
                                               1 if project else 0, self.ws_ptr, self.ws_bytes), "bl_hypergradient")
         return np.array(out[:], dtype=np.float64)
+
+
+class Session(Context):
+    """Context + workspace + recycle storage of one problem shape."""
+
+    def __init__(self, P: bl_problem, s_max: int = 0, v_cap: int = 0, device=None, stream=None):
+        super().__init__([P], s_max, v_cap, device, stream)
+        self.P = P
+        self.n = P.h * P.w
+        self.p = bl_num_params(P)
+        self.rec = Recycle(self.n, s_max, v_cap, self.device)
+        self.U, self.Cm, self.Z, self.mu, self.V = self.rec.U, self.rec.Cm, self.rec.Z, self.rec.mu, self.rec.V
+        self.rs = self.rec.rs
+
+    def reset(self):
+        self.rs.s_cur = 0
+        self.rs.v_cur = 0
+
+    def forward(self, x, e, noise, y):
+        self.forward_p(self.P, x, e, noise, y)
+
+    def hvp(self, theta, xhat, v, out, ncols: int = 1):
+        self.hvp_p(self.P, theta, xhat, v, out, ncols)
+
+    def lower_grad(self, theta, y, x, grad) -> float:
+        return self.lower_grad_p(self.P, theta, y, x, grad)
+
+    def lower_solve(self, theta, y, x, gtol=1e-8, max_iter=20000, m=10) -> bl_stats:
+        return self.lower_solve_p(self.P, theta, y, x, gtol, max_iter, m)
+
+    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8) -> bl_stats:
+        return self.refresh_p(self.P, self.rec, theta, xhat, s, rank_tol)
+
+    def solve(self, theta, xhat, g, w, **kw) -> bl_stats:
+        return self.solve_p(self.P, self.rec, theta, xhat, g, w, **kw)
+
+    def hypergradient(self, theta, xhat, w, project: bool = True) -> np.ndarray:
+        return self.hypergradient_p(self.P, theta, xhat, w, project)
 
 
 # --------------------------------------------------------------------------- recycle storage
@@ -292,12 +322,11 @@ def _aligned_workspace(nbytes: int, device):
 
 # --------------------------------------------------------------------------- batched / served solves
 class Engine:
-    """bl_engine: up to `cap` concurrent solves of one operator class advanced together."""
+    """bl_engine: up to `cap` concurrent solves (up to 4 operator classes) advanced together."""
 
-    def __init__(self, cls: bl_problem, cap: int, arena_bytes: int, device=None, stream=None, ctx=None):
+    def __init__(self, cap: int, arena_bytes: int, device=None, stream=None, ctx=None):
         import torch
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.cls = cls
         self.cap = cap
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -308,8 +337,8 @@ class Engine:
                 raise BLError(BL_E_ARG, "bl_engine_workspace_bytes rejected the capacity")
             self.ws, self.ws_ptr = _aligned_workspace(nbytes, self.device)
         self.handle = C.c_void_p()
-        _check(self.ctx, lib.bl_engine_create(self.ctx, C.byref(cls), cap, self.ws_ptr, nbytes,
-                                              C.byref(self.handle)), "bl_engine_create")
+        _check(self.ctx, lib.bl_engine_create(self.ctx, cap, self.ws_ptr, nbytes, C.byref(self.handle)),
+               "bl_engine_create")
         self._held = {}
         self._done = (C.c_int * cap)()
 

@@ -47,7 +47,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
-    L.taps = o;     o += al((size_t)(MAX_NF * MAX_FS * MAX_FS + MAX_NF + 16) * sizeof(double));
+    L.taps = o;     o += al(TAPS_BYTES);
     L.W0 = o;       o += al((size_t)L.n * L.t_max * sizeof(double));
     L.W1 = o;       o += al((size_t)L.n * L.t_max * sizeof(double));
     L.Ut = o;       o += al((size_t)L.n * std::max(s_max, 1) * sizeof(double));
@@ -105,11 +105,12 @@ bl_status make_stencil(bl_ctx* c, const bl_problem* P, const double* theta, cons
     TRY(theta_values(c, P, theta, S.lam, S.gam2, c->h_buf));
     if (P->reg == BL_REG_FILTERS) {
         const int f2 = S.fs * S.fs;
-        HIPCHK(hipMemcpyAsync(ws.taps(), c->h_buf, (S.nf * f2 + S.nf) * sizeof(double), hipMemcpyHostToDevice,
-                              c->stream));
+        HIPCHK(hipMemcpyAsync(ws.taps(), c->h_buf, TAPS_MAX * sizeof(double) + (S.nf * f2 + S.nf) * sizeof(float),
+                              hipMemcpyHostToDevice, c->stream));
         // the staging buffer is reused by later calls: make the copy complete
         HIPCHK(hipStreamSynchronize(c->stream));
         S.taps = ws.taps();
+        S.tapsf = reinterpret_cast<const float*>(ws.taps() + TAPS_MAX);
         S.lamj = ws.taps() + S.nf * f2;
         S.d2 = ws.d2();
         S.d2f = ws.d2f();
@@ -276,7 +277,7 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
     TRY(check_ws(c, layout(P, s_max, v_cap), wsp, ws_bytes, ws));
     mark(c, 0);
     Batch B;
-    TRY(B.init(c, P, 1, ws.slots(), ws.hdr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
+    TRY(B.init(c, 1, ws.slots(), ws.hdr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
     SlotBuffers buf{};
     buf.r = ws.vec(0);
     buf.p0 = ws.vec(1);

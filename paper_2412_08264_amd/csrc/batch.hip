@@ -7,8 +7,10 @@
 // its slot's record array; the next kernel reduces the records of its slot in every block
 // (fixed order), so a slot's scalars and decisions are identical in every block and do
 // not depend on the other slots.  Block 0 of a slot stores the scalars for the host.
+#include <type_traits>
+
 #include "kernels.h"
-#include "stencil.h"
+#include "tile.h"
 
 namespace bl {
 
@@ -20,6 +22,7 @@ __device__ __forceinline__ void slot_stencil(Stencil& S, const Slot& sl) {
     S.lam = sl.lam;
     S.gam2 = sl.gam2;
     S.taps = sl.taps;
+    S.tapsf = sl.tapsf;
     S.lamj = sl.lamj;
     S.d2 = sl.d2;
     S.d2f = sl.d2f;
@@ -27,8 +30,25 @@ __device__ __forceinline__ void slot_stencil(Stencil& S, const Slot& sl) {
 
 __device__ __forceinline__ void slot_tile(const Slot& sl, int local, int& r0, int& c0) {
     const int t = xcd_tile(local, sl.ntiles);
-    r0 = (t / sl.tiles_x) * TH;
-    c0 = (t % sl.tiles_x) * TW;
+    r0 = (t / sl.tiles_x) * QH;
+    c0 = (t % sl.tiles_x) * QW;
+}
+
+// The thread's four pixels: rows r0 + 4 ty + k of column c0 + tx.
+struct Own {
+    int g[QR];
+    bool in[QR];
+};
+__device__ __forceinline__ Own own_pixels(int h, int w, int r0, int c0) {
+    Own o;
+    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        const int gi = r0 + QR * ty + k;
+        o.in[k] = gi < h && gj < w;
+        o.g[k] = o.in[k] ? gi * w + gj : 0;
+    }
+    return o;
 }
 
 // Records a consumer reads: the producer's per-block array, or its folded record.
@@ -48,9 +68,10 @@ __device__ __forceinline__ const double* slot_rec(const Slot& sl, int which, int
 // ------------------------------------------------------------------ residual g - H w
 // r = g - H w in FP64 and the record [g.g, C^T r].  With `periodic` set (a scheduled
 // residual replacement) a slot that has already stopped is left alone.
-template <int RB>
+template <int R, int CLS>
 __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __restrict__ slots, BatchMap M,
                                                    int periodic) {
+    using L = QLayout<double, R, CLS>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
     const int2 m = map_block(M, blockIdx.x);
@@ -58,26 +79,31 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
     if (m.y >= sl.ntiles || (periodic && sl.st->done)) return;
     Stencil S = base;
     slot_stencil(S, sl);
-    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
     int r0, c0;
     slot_tile(sl, m.y, r0, c0);
-    const int gi = r0 + (int)threadIdx.x / TW, gj = c0 + (int)threadIdx.x % TW;
-    const bool own = gi < S.h && gj < S.w;
-    const int i = own ? gi * S.w + gj : 0;
-    const double gv = own ? sl.g[i] : 0.0;
-    stage_region<double>(lds + L.o_v, S, L, r0, c0, [&](int gidx) { return sl.w[gidx]; });
-    if (S.reg == BL_REG_TV) stage_xhat<double>(lds + L.o_x, S, sl.xhat, r0, c0);
+    const Own o = own_pixels(S.h, S.w, r0, c0);
+    double gv[QR];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) gv[k] = o.in[k] ? sl.g[o.g[k]] : 0.0;
+    q_stage<double, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return sl.w[gi]; });
+    if constexpr (CLS == TC_TV) q_stage_xhat<double>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
     __syncthreads();
-    hvp_tile<double, RB>(lds, S, L, sl.xhat, r0, c0, S.reg == BL_REG_TV);
-    __syncthreads();
-    const double ov = own ? gv - lds[L.o_out + threadIdx.x] : 0.0;
-    if (own) sl.r[i] = ov;
-    const int s = sl.s;
+    double hv[QR];
+    q_hvp<double, R, CLS>(lds, S, r0, c0, hv);
+    double ov[QR];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        ov[k] = o.in[k] ? gv[k] - hv[k] : 0.0;
+        if (o.in[k]) sl.r[o.g[k]] = ov[k];
+    }
     block_partials(
-        sl.rec_res, 1 + s,
+        sl.rec_res, 1 + sl.s,
         [&](int k) {
-            if (!own) return 0.0;
-            return k == 0 ? gv * gv : sl.C[(size_t)(k - 1) * S.n + i] * ov;
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < QR; ++u)
+                if (o.in[u]) acc += k == 0 ? gv[u] * gv[u] : sl.C[(size_t)(k - 1) * S.n + o.g[u]] * ov[u];
+            return acc;
         },
         m.y);
 }
@@ -112,13 +138,17 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
 }
 
 // Iteration j = step - j0, first half: stop test from the update records, beta, p, q = H p,
-// V store, record [p.q, C^T q].  A stopped slot's blocks leave after the record reduction
-// (its flag is read by one thread and published by the reduction's barrier: uniform per
-// block; a flag set by block 0 during this launch follows from the same decision every
-// block of the slot takes).
-constexpr int CPRE = 24;
-template <typename T, int RB>
+// V store, record [p.q, C^T q].  After a residual replacement whose true residual exceeds the
+// previous recursive one the direction restarts (p = r): keeping it would let the stale
+// direction dominate (beta = rho_true / rho_rec >> 1) and stall at the accuracy of the FP32
+// operator; restarting turns the replacement into a step of iterative refinement.
+// A stopped slot's blocks leave after the record reduction (its flag is read by one thread
+// and published by the reduction's barrier: uniform per block; a flag set by block 0 during
+// this launch follows from the same decision every block of the slot takes).
+constexpr int CPRE = 8;   // columns of C per pixel loaded before the stencil
+template <typename T, int R, int CLS>
 __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
+    using L = QLayout<T, R, CLS>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     __shared__ double tot[NT];
@@ -137,6 +167,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const double rho_prev = j > 0 ? st->rho2[(j - 1) & 1] : 1.0;
     const bool store_basis = st->store_basis && j < st->v_cap;
     const double rho = tot[0];
+    const bool restart = j > 0 && st->rr_j == j && rho > rho_prev;
     const Decision dec = decide(st, j, rho, tot + 1);
     if (m.y == 0) {
         for (int k = threadIdx.x; k < nz; k += NT) st->zr[k] = tot[1 + k];
@@ -154,48 +185,66 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     if (dec.done) return;
     Stencil S = base;
     slot_stencil(S, sl);
-    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
-    const bool first = (j == 0);
+    const bool first = (j == 0) || restart;
     const double beta = first ? 0.0 : rho / rho_prev;
     const double* __restrict__ r = sl.r;
     const double* __restrict__ p_old = sl.p[j & 1];
     double* __restrict__ p_new = sl.p[(j + 1) & 1];
     int r0, c0;
     slot_tile(sl, m.y, r0, c0);
-    const int gi = r0 + (int)threadIdx.x / TW, gj = c0 + (int)threadIdx.x % TW;
-    const bool own = gi < S.h && gj < S.w;
-    const int i = own ? gi * S.w + gj : 0;
-    const double ri = own ? r[i] : 0.0;
-    const double pi = (own && !first) ? p_old[i] : 0.0;
-    double cpre[CPRE];
+    const Own o = own_pixels(S.h, S.w, r0, c0);
+    double ri[QR], pi[QR], cpre[CPRE][QR];
 #pragma unroll
-    for (int k = 0; k < CPRE; ++k) cpre[k] = (own && k < s) ? sl.C[(size_t)k * S.n + i] : 0.0;
-    stage_region<T>(lds + L.o_v, S, L, r0, c0,
-                    [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
-    if (S.reg == BL_REG_TV) stage_xhat<T>(lds + L.o_x, S, sl.xhat, r0, c0);
-    __syncthreads();
-    hvp_tile<T, RB>(lds, S, L, sl.xhat, r0, c0, S.reg == BL_REG_TV);
-    __syncthreads();
-    const double pn = first ? ri : ri + beta * pi;
-    const double qq = own ? (double)lds[L.o_out + threadIdx.x] : 0.0;
-    if (own) {
-        p_new[i] = pn;
-        sl.q[i] = qq;
-        if (store_basis) sl.V[(size_t)j * S.n + i] = ri / sqrt(rho);
+    for (int k = 0; k < QR; ++k) {
+        ri[k] = o.in[k] ? r[o.g[k]] : 0.0;
+        pi[k] = (o.in[k] && !first) ? p_old[o.g[k]] : 0.0;
     }
-    const double pv = own ? pn : 0.0;
+#pragma unroll
+    for (int c = 0; c < CPRE; ++c)
+#pragma unroll
+        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * S.n + o.g[k]] : 0.0;
+    q_stage<T, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0,
+                       [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
+    if constexpr (CLS == TC_TV) q_stage_xhat<T>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
+    __syncthreads();
+    T hv[QR];
+    q_hvp<T, R, CLS>(lds, S, r0, c0, hv);
+    double pv[QR], qq[QR];
+    const double inv = store_basis ? 1.0 / sqrt(rho) : 0.0;
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        const double pn = first ? ri[k] : ri[k] + beta * pi[k];
+        qq[k] = o.in[k] ? (double)hv[k] : 0.0;
+        pv[k] = o.in[k] ? pn : 0.0;
+        if (o.in[k]) {
+            p_new[o.g[k]] = pn;
+            sl.q[o.g[k]] = qq[k];
+            if (store_basis) sl.V[(size_t)j * S.n + o.g[k]] = ri[k] * inv;
+        }
+    }
     block_partials(
         sl.rec_app, 1 + s,
         [&](int k) {
-            if (!own) return 0.0;
-            if (k == 0) return pv * qq;
-            const int c = k - 1;
-            double cv = 0.0;
+            double acc = 0.0;
+            if (k == 0) {
 #pragma unroll
-            for (int u = 0; u < CPRE; ++u)
-                if (u == c) cv = cpre[u];
-            if (c >= CPRE) cv = sl.C[(size_t)c * S.n + i];
-            return cv * qq;
+                for (int u = 0; u < QR; ++u) acc += pv[u] * qq[u];
+                return acc;
+            }
+            const int c = k - 1;
+            if (c < CPRE) {
+#pragma unroll
+                for (int cc = 0; cc < CPRE; ++cc)
+                    if (cc == c) {
+#pragma unroll
+                        for (int u = 0; u < QR; ++u) acc += cpre[cc][u] * qq[u];
+                    }
+            } else {
+#pragma unroll
+                for (int u = 0; u < QR; ++u)
+                    if (o.in[u]) acc += sl.C[(size_t)c * S.n + o.g[u]] * qq[u];
+            }
+            return acc;
         },
         m.y);
 }
@@ -270,9 +319,10 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
 }
 
 // Residual replacement: r holds t = g - H w (record [g.g, C^T t]): z := C^T t,
-// r := t - C z, and the slot resumes (its next apply step re-tests the replaced residual).
-// With `periodic` set a slot that has already stopped is left alone.
-__global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots, BatchMap M, int periodic) {
+// r := t - C z, and the slot resumes at iteration step - j0, whose apply step re-tests the
+// replaced residual.  With `periodic` set a slot that has already stopped is left alone.
+__global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots, BatchMap M, int periodic,
+                                                  int step) {
     __shared__ double tot[NT];
     const int2 m = map_block(M, blockIdx.x);
     const Slot& sl = slots[m.x];
@@ -287,6 +337,7 @@ __global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots
         if (threadIdx.x == 0) {
             sl.st->done = 0;
             sl.st->status = BL_OK;
+            sl.st->rr_j = step - sl.j0;
         }
     }
     const int i = m.y * NT + threadIdx.x;
@@ -360,6 +411,7 @@ __global__ void __launch_bounds__(NT) k_b_admit(Slot* __restrict__ slots, int id
         st->v_cap = init.v_cap;
         st->store_basis = init.store_basis;
         st->hgerr_on = init.hgerr_on;
+        st->rr_j = -1;
     }
     for (int k = threadIdx.x; k < init.s; k += NT) st->mu[k] = mu[k];
 }
@@ -385,48 +437,35 @@ static void allow_lds_b(K kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-#define BL_RADIUS_SWITCH_B(R, CALL) \
-    switch (R) {                    \
-        case 0: CALL(0); break;     \
-        case 1: CALL(1); break;     \
-        case 2: CALL(2); break;     \
-        case 3: CALL(3); break;     \
-        case 4: CALL(4); break;     \
-        case 5: CALL(5); break;     \
-        case 6: CALL(6); break;     \
-        case 7: CALL(7); break;     \
-        default: CALL(8); break;    \
-    }
-
 static inline dim3 map_grid(const BatchMap& M) { return dim3(M.off[M.ns]); }
 
 hipError_t launch_b_residual(const Stencil& base, const Slot* slots, const BatchMap& M, int periodic,
                              hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    const size_t lds = tile_lds_bytes<double>(base.R, base.reg, base.fs);
-#define RES_B(RB)                                                                                           \
-    allow_lds_b(k_b_residual<RB>, lds);                                                                     \
-    hipLaunchKernelGGL((k_b_residual<RB>), map_grid(M), dim3(NT), lds, stream, base, slots, M, periodic);
-    BL_RADIUS_SWITCH_B(base.R, RES_B)
-#undef RES_B
+    q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
+        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
+        const size_t lds = QLayout<double, RR, CC>::bytes;
+        allow_lds_b(k_b_residual<RR, CC>, lds);
+        hipLaunchKernelGGL((k_b_residual<RR, CC>), map_grid(M), dim3(NT), lds, stream, base, slots, M, periodic);
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_b_apply(const Stencil& base, bool fp32, const Slot* slots, const BatchMap& M, int step,
                           hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    const size_t lds = fp32 ? tile_lds_bytes<float>(base.R, base.reg, base.fs)
-                            : tile_lds_bytes<double>(base.R, base.reg, base.fs);
-#define APP_B(RB)                                                                                              \
-    if (fp32) {                                                                                                \
-        allow_lds_b(k_b_apply<float, RB>, lds);                                                                \
-        hipLaunchKernelGGL((k_b_apply<float, RB>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step);  \
-    } else {                                                                                                   \
-        allow_lds_b(k_b_apply<double, RB>, lds);                                                               \
-        hipLaunchKernelGGL((k_b_apply<double, RB>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step); \
-    }
-    BL_RADIUS_SWITCH_B(base.R, APP_B)
-#undef APP_B
+    q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
+        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
+        if (fp32) {
+            const size_t lds = QLayout<float, RR, CC>::bytes;
+            allow_lds_b(k_b_apply<float, RR, CC>, lds);
+            hipLaunchKernelGGL((k_b_apply<float, RR, CC>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step);
+        } else {
+            const size_t lds = QLayout<double, RR, CC>::bytes;
+            allow_lds_b(k_b_apply<double, RR, CC>, lds);
+            hipLaunchKernelGGL((k_b_apply<double, RR, CC>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step);
+        }
+    });
     return hipGetLastError();
 }
 
@@ -440,9 +479,9 @@ hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipSt
     hipLaunchKernelGGL(k_b_update, map_grid(M), dim3(NT), 0, stream, slots, M, step);
     return hipGetLastError();
 }
-hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, hipStream_t stream) {
+hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, int step, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_replace, map_grid(M), dim3(NT), 0, stream, slots, M, periodic);
+    hipLaunchKernelGGL(k_b_replace, map_grid(M), dim3(NT), 0, stream, slots, M, periodic, step);
     return hipGetLastError();
 }
 hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream) {

@@ -30,8 +30,9 @@ struct Stencil {
     int nf, fs;                 // filters
     double eps;
     int penalty;
-    const double* taps;         // device: nf * fs * fs filter taps (row-major per filter)
-    const double* lamj;         // device: nf weights e^{w_j}
+    const double* taps;         // device: nf * fs * fs filter taps (row-major per filter), then nf weights
+    const float* tapsf;         // device: the same nf * fs * fs + nf values in FP32
+    const double* lamj;         // device: nf weights e^{w_j} (= taps + nf * fs * fs)
     const double* d2;           // device: nf maps phi''(K_j xhat), FP64
     const float* d2f;           // device: nf maps phi''(K_j xhat), FP32 (mixed precision)
     int tiles_x, tiles_y;
@@ -45,7 +46,8 @@ struct Stencil {
 struct SolveState {
     double rho2[2];     // rho_j = r_j . r_j, slot j & 1
     double alpha, gnorm, tol, hg_tol, res0, est, pad0[3];
-    int iters, done, status, max_iter, check_every, stop, s, v_cap, v_cur, store_basis, hgerr_on, pad;
+    int iters, done, status, max_iter, check_every, stop, s, v_cap, v_cur, store_basis, hgerr_on;
+    int rr_j;             // iteration whose test follows the last residual replacement (-1: none)
     double e[S_MAX];      // C^T q of the current iteration
     double zr[S_MAX];     // Z^T r
     double zacc[S_MAX];   // coefficient of U accumulated over the iterations
@@ -64,7 +66,8 @@ struct Slot {
     int fold_app, fold_upd, fold_res;     // records folded by k_fold before use
     int pad;
     double lam, gam2;                     // TV weight e^{theta0}, smoothing e^{2 theta1}
-    const double* taps;                   // filters: taps, weights, phi'' maps
+    const double* taps;                   // filters: taps (then weights), FP32 copy, weights, phi'' maps
+    const float* tapsf;
     const double* lamj;
     const double* d2;
     const float* d2f;

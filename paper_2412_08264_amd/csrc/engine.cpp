@@ -11,6 +11,7 @@
 #include <utility>
 
 #include "host.h"
+#include "tile.h"
 
 using namespace bl;
 
@@ -81,6 +82,8 @@ bl_status theta_values(bl_ctx* c, const bl_problem* P, const double* theta, doub
         taps_host[nf * f2 + j] = std::exp(theta[j * (1 + f2)]);
         if (!std::isfinite(taps_host[nf * f2 + j])) return c->err = "theta gives a non-finite weight", BL_E_ARG;
     }
+    float* tf = reinterpret_cast<float*>(taps_host + TAPS_MAX);
+    for (int k = 0; k < nf * f2 + nf; ++k) tf[k] = (float)taps_host[k];
     return BL_OK;
 }
 
@@ -93,14 +96,14 @@ bool same_class(const bl_problem* a, const bl_problem* b) {
     return true;
 }
 
-static int ntiles_of(int h, int w) { return ((w + TW - 1) / TW) * ((h + TH - 1) / TH); }
+static int ntiles_of(int h, int w) { return ((w + QW - 1) / QW) * ((h + QH - 1) / QH); }
 static int npix_of(long n) { return (int)((n + NT - 1) / NT); }
 
 size_t slot_bytes(const bl_problem* P, int s) {
     const size_t n = (size_t)P->h * P->w;
     const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
     const size_t nt = ntiles_of(P->h, P->w), np = npix_of((long)n);
-    return 4 * al(n * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al((size_t)TAPS_MAX * 8) +
+    return 4 * al(n * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al(TAPS_BYTES) +
            2 * al(nt * (1 + s) * 8) + al(np * (1 + s) * 8) + al(3 * NV_RED * 8);
 }
 
@@ -122,7 +125,7 @@ SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
     B.d1 = nf ? (double*)take(nf * n * 8) : nullptr;
     B.d2 = nf ? (double*)take(nf * n * 8) : nullptr;
     B.d2f = nf ? (float*)take(nf * n * 4) : nullptr;
-    B.taps = (double*)take((size_t)TAPS_MAX * 8);
+    B.taps = (double*)take(TAPS_BYTES);
     B.rec_res = (double*)take(nt * (1 + s) * 8);
     B.rec_app = (double*)take(nt * (1 + s) * 8);
     B.rec_upd = (double*)take(np * (1 + s) * 8);
@@ -132,11 +135,10 @@ SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
 }
 
 // ------------------------------------------------------------------------------------- Batch
-bl_status Batch::init(bl_ctx* ctx, const bl_problem* cls, int capacity, Slot* slots, int* hdr_dev, char* hdr_pinned,
-                      hipEvent_t ev0, hipEvent_t ev1) {
+bl_status Batch::init(bl_ctx* ctx, int capacity, Slot* slots, int* hdr_dev, char* hdr_pinned, hipEvent_t ev0,
+                      hipEvent_t ev1) {
     c = ctx;
-    class_stencil(cls, base);
-    fp32 = cls->prec == BL_PREC_MIXED;
+    groups.clear();
     cap = capacity;
     d_slots = slots;
     d_hdr = hdr_dev;
@@ -176,7 +178,12 @@ bl_status Batch::rebuild() {
     run_list.clear();
     for (int i = 0; i < cap; ++i)
         if (S[i].running) run_list.push_back(i);
-    tmap = make_map(S, run_list, true);
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        std::vector<int> mine;
+        for (int i : run_list)
+            if (S[i].group == gi) mine.push_back(i);
+        groups[gi].tmap = make_map(S, mine, true);
+    }
     pmap = make_map(S, run_list, false);
     fold_app = BatchMap{};
     fold_upd = BatchMap{};
@@ -205,6 +212,23 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     }
     const bool hg = o->stop == BL_STOP_HGERR && s > 0 && rs->Z;
     const bool store = o->store_basis && rs;
+    int gid = -1;
+    for (int gi = 0; gi < (int)groups.size() && gid < 0; ++gi)
+        if (same_class(&groups[gi].cls, P)) gid = gi;
+    for (int gi = 0; gi < (int)groups.size() && gid < 0; ++gi)
+        if (groups[gi].users == 0) gid = gi;   // reuse an idle class entry
+    if (gid < 0) {
+        if ((int)groups.size() >= MAX_GROUPS) return c->err = "more than 4 operator classes in one batch", BL_E_ARG;
+        groups.emplace_back();
+        gid = (int)groups.size() - 1;
+    }
+    Group& grp = groups[gid];
+    if (grp.users == 0) {
+        grp.cls = *P;
+        class_stencil(P, grp.base);
+        grp.fp32 = P->prec == BL_PREC_MIXED;
+    }
+    const Stencil& base = grp.base;
     double lam, gam2;
     TRY(theta_values(c, P, sp.theta, lam, gam2, taps_stage));
     const int n = P->h * P->w;
@@ -212,7 +236,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.h = P->h;
     v.width = P->w;
     v.n = n;
-    v.tiles_x = (P->w + TW - 1) / TW;
+    v.tiles_x = (P->w + QW - 1) / QW;
     v.ntiles = ntiles_of(P->h, P->w);
     v.npix = npix_of(n);
     v.j0 = step;
@@ -241,9 +265,10 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.fold = B.fold;
     if (P->reg == BL_REG_FILTERS) {
         const int nf = P->n_filters, f2 = P->filter_size * P->filter_size;
-        HIPCHK(hipMemcpyAsync(B.taps, taps_stage, (size_t)(nf * f2 + nf) * sizeof(double), hipMemcpyHostToDevice,
-                              c->stream));
+        HIPCHK(hipMemcpyAsync(B.taps, taps_stage, TAPS_MAX * sizeof(double) + (size_t)(nf * f2 + nf) * sizeof(float),
+                              hipMemcpyHostToDevice, c->stream));
         v.taps = B.taps;
+        v.tapsf = reinterpret_cast<const float*>(B.taps + TAPS_MAX);
         v.lamj = B.taps + nf * f2;
         v.d2 = B.d2;
         v.d2f = B.d2f;
@@ -254,6 +279,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         Sx.tiles_x = v.tiles_x;
         Sx.tiles_y = (P->h + TH - 1) / TH;
         Sx.taps = v.taps;
+        Sx.tapsf = v.tapsf;
         Sx.lamj = v.lamj;
         Sx.d2 = v.d2;
         Sx.d2f = v.d2f;
@@ -266,9 +292,11 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     h = Host();
     h.used = true;
     h.running = true;
+    h.group = gid;
+    grp.users += 1;
     h.d = v;
     h.max_iter = o->max_iter;
-    h.rr_every = fp32 ? o->rr_every : 0;
+    h.rr_every = grp.fp32 ? o->rr_every : 0;
     h.store_basis = store;
     h.v_cap = v_cap;
     h.rs = rs;
@@ -290,12 +318,18 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
 
 // Residual replacement in FP64 for the listed slots: r = g - H w, z = C^T r, r -= C z.
 bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic) {
-    HIPCHK(launch_b_residual(base, d_slots, make_map(S, idx, true), periodic, c->stream));
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        std::vector<int> mine;
+        for (int i : idx)
+            if (S[i].group == gi) mine.push_back(i);
+        if (!mine.empty())
+            HIPCHK(launch_b_residual(groups[gi].base, d_slots, make_map(S, mine, true), periodic, c->stream));
+    }
     BatchMap f{};
     for (int i : idx)
         if (S[i].d.fold_res) f.slot[f.ns++] = i;
     HIPCHK(launch_b_fold(d_slots, f, 0, c->stream));
-    HIPCHK(launch_b_replace(d_slots, make_map(S, idx, false), periodic, c->stream));
+    HIPCHK(launch_b_replace(d_slots, make_map(S, idx, false), periodic, step, c->stream));
     return BL_OK;
 }
 
@@ -311,7 +345,7 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
     const int buf = (int)(id & 1);
     const bool ktime = c->timing == 2;
     for (int k = 0; k < POLL && steps_done < max_steps; ++k) {
-        if (fp32) {   // scheduled replacements: before the test of every rr_every-th iteration
+        {   // scheduled replacements (mixed precision): before the test of every rr_every-th iteration
             std::vector<int> rr;
             for (int i : run_list) {
                 Host& h = S[i];
@@ -334,7 +368,8 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
             }
             HIPCHK(hipEventRecord(c->kev[ev], c->stream));
         }
-        HIPCHK(launch_b_apply(base, fp32, d_slots, tmap, step, c->stream));
+        for (const Group& grp : groups)
+            if (grp.tmap.ns) HIPCHK(launch_b_apply(grp.base, grp.fp32, d_slots, grp.tmap, step, c->stream));
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], c->stream));
         if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, c->stream));
         HIPCHK(launch_b_update(d_slots, pmap, step, c->stream));
@@ -353,7 +388,10 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
         const int i = run_list[0];
         HIPCHK(hipMemcpyAsync(dst + (size_t)i * HDR_BYTES, S[i].d.st, HDR_BYTES, hipMemcpyDeviceToHost, c->stream));
     } else {
-        HIPCHK(launch_b_headers(d_slots, tmap, d_hdr, c->stream));
+        BatchMap all{};
+        all.ns = (int)run_list.size();
+        for (int k = 0; k < all.ns; ++k) all.slot[k] = run_list[k];
+        HIPCHK(launch_b_headers(d_slots, all, d_hdr, c->stream));
         HIPCHK(hipMemcpyAsync(dst, d_hdr, (size_t)cap * HDR_BYTES, hipMemcpyDeviceToHost, c->stream));
     }
     HIPCHK(hipEventRecord(poll_ev[buf], c->stream));
@@ -375,7 +413,7 @@ bl_status Batch::process_chunk(long id, const std::vector<int>& slots, std::vect
         if (!h.hdr.done) continue;
         const int jd = h.hdr.iters;
         const bool replaced = std::find(h.rr_js.begin(), h.rr_js.end(), jd) != h.rr_js.end();
-        if (fp32 && h.hdr.status == BL_OK && !replaced) {
+        if (groups[h.group].fp32 && h.hdr.status == BL_OK && !replaced) {
             retest.push_back(i);
         } else {
             TRY(finish(i));
@@ -465,6 +503,7 @@ void Batch::stats(int idx, bl_stats* out) const {
 }
 
 void Batch::release(int idx) {
+    if (S[idx].group >= 0) groups[S[idx].group].users -= 1;
     S[idx] = Host();
     dirty = true;
 }
@@ -476,7 +515,6 @@ using namespace blh;
 // ------------------------------------------------------------------------------------ engine
 struct bl_engine {
     bl_ctx* c = nullptr;
-    bl_problem cls{};
     int cap = 0;
     Batch B;
     char* arena = nullptr;
@@ -484,7 +522,7 @@ struct bl_engine {
     std::map<size_t, size_t> free_blocks;   // offset -> size
     std::vector<std::pair<size_t, size_t>> alloc;   // per slot (offset, size)
     SolveState* states = nullptr;
-    double* h_taps = nullptr;   // pinned [cap][TAPS_MAX]
+    double* h_taps = nullptr;   // pinned [cap][2 * TAPS_MAX]: taps staging (doubles, then floats)
     char* h_hdr = nullptr;      // pinned [2][cap][HDR_BYTES]
     hipEvent_t ev[2] = {};
 
@@ -547,11 +585,10 @@ size_t bl_engine_workspace_bytes(int cap, size_t arena_bytes) {
     return engine_layout(cap, arena_bytes).total;
 }
 
-bl_status bl_engine_create(bl_ctx* c, const bl_problem* cls, int cap, void* ws, size_t ws_bytes, bl_engine** out) {
+bl_status bl_engine_create(bl_ctx* c, int cap, void* ws, size_t ws_bytes, bl_engine** out) {
     if (!c) return BL_E_ARG;
     if (!out) return c->err = "null engine handle", BL_E_ARG;
     *out = nullptr;
-    TRY(check_problem(c, cls));
     if (cap < 1 || cap > B_MAX) return c->err = "engine capacity outside [1, 64]", BL_E_ARG;
     if (!ws || (uintptr_t)ws % ALIGN) return c->err = "workspace missing or not 256-byte aligned", BL_E_WORKSPACE;
     const EngineLayout L0 = engine_layout(cap, 0);
@@ -559,7 +596,6 @@ bl_status bl_engine_create(bl_ctx* c, const bl_problem* cls, int cap, void* ws, 
     const size_t arena_bytes = (ws_bytes - L0.arena) / ALIGN * ALIGN;
     bl_engine* e = new bl_engine();
     e->c = c;
-    e->cls = *cls;
     e->cap = cap;
     char* base = (char*)ws;
     e->arena = base + L0.arena;
@@ -567,7 +603,7 @@ bl_status bl_engine_create(bl_ctx* c, const bl_problem* cls, int cap, void* ws, 
     if (arena_bytes) e->free_blocks[0] = arena_bytes;
     e->alloc.assign(cap, {0, 0});
     e->states = (SolveState*)(base + L0.states);
-    if (hipHostMalloc((void**)&e->h_taps, (size_t)cap * TAPS_MAX * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&e->h_taps, (size_t)cap * 2 * TAPS_MAX * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&e->h_hdr, (size_t)2 * cap * HDR_BYTES, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&e->ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&e->ev[1], hipEventDisableTiming) != hipSuccess) {
@@ -579,7 +615,7 @@ bl_status bl_engine_create(bl_ctx* c, const bl_problem* cls, int cap, void* ws, 
         delete e;
         return BL_E_HIP;
     }
-    e->B.init(c, cls, cap, (Slot*)(base + L0.slots), (int*)(base + L0.hdr), e->h_hdr, e->ev[0], e->ev[1]);
+    e->B.init(c, cap, (Slot*)(base + L0.slots), (int*)(base + L0.hdr), e->h_hdr, e->ev[0], e->ev[1]);
     *out = e;
     return BL_OK;
 }
@@ -601,7 +637,6 @@ bl_status bl_engine_admit(bl_engine* e, const bl_problem* P, const double* theta
     if (!slot) return c->err = "null slot output", BL_E_ARG;
     *slot = -1;
     TRY(check_problem(c, P));
-    if (!same_class(P, &e->cls)) return c->err = "problem differs from the engine's operator class", BL_E_ARG;
     const int s = rs ? rs->s_cur : 0;
     if (s < 0 || s > S_MAX) return c->err = "s_cur outside [0, 64]", BL_E_SHAPE;
     int idx = -1;
@@ -617,7 +652,7 @@ bl_status bl_engine_admit(bl_engine* e, const bl_problem* P, const double* theta
     SlotBuffers buf = carve_slot(e->arena + off, P, s);
     buf.st = e->states + idx;
     const SolveSpec sp{P, theta, xhat, g, w, rs, opts};
-    const bl_status st = e->B.admit(idx, sp, buf, e->h_taps + (size_t)idx * TAPS_MAX);
+    const bl_status st = e->B.admit(idx, sp, buf, e->h_taps + (size_t)idx * 2 * TAPS_MAX);
     if (st != BL_OK) {
         e->give(off, bytes);
         return st;
@@ -685,12 +720,9 @@ bl_status bl_hessian_solve_batched(bl_ctx* c, int nprob, const bl_problem* P, co
                                    bl_stats* out) {
     if (!c) return BL_E_ARG;
     if (nprob < 1 || !P || !theta || !xhat || !g || !w || !out) return c->err = "null or empty batch", BL_E_ARG;
-    for (int k = 0; k < nprob; ++k) {
-        TRY(check_problem(c, &P[k]));
-        if (!same_class(&P[k], &P[0])) return c->err = "batched problems differ in operator class", BL_E_ARG;
-    }
+    for (int k = 0; k < nprob; ++k) TRY(check_problem(c, &P[k]));
     bl_engine* e = nullptr;
-    TRY(bl_engine_create(c, &P[0], std::min(nprob, B_MAX), ws, ws_bytes, &e));
+    TRY(bl_engine_create(c, std::min(nprob, B_MAX), ws, ws_bytes, &e));
     struct Guard {
         bl_engine* e;
         ~Guard() { bl_engine_destroy(e); }

@@ -46,6 +46,8 @@ constexpr int POLL = 8;              // iterations launched between host polls o
 constexpr long REC_LIMIT = 8192;
 constexpr size_t ALIGN = 256;
 constexpr int TAPS_MAX = bl::MAX_NF * bl::MAX_FS * bl::MAX_FS + bl::MAX_NF;
+// Device and pinned staging layout of a problem's taps: TAPS_MAX doubles, then TAPS_MAX floats.
+constexpr size_t TAPS_BYTES = (size_t)TAPS_MAX * (sizeof(double) + sizeof(float));
 
 inline size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -55,7 +57,7 @@ bl_status check_solve_opts(bl_ctx* c, const bl_solve_opts* o);
 // Operator-class part of the stencil (blur taps, regulariser, filter shape, penalty).
 void class_stencil(const bl_problem* P, bl::Stencil& S);
 // theta-dependent scalars: TV weight and smoothing; filters: taps then weights e^{w_j}
-// into taps_host (nf*f*f + nf doubles).
+// into taps_host (nf*f*f + nf doubles, followed at TAPS_MAX doubles by their FP32 copies).
 bl_status theta_values(bl_ctx* c, const bl_problem* P, const double* theta, double& lam, double& gam2,
                        double* taps_host);
 // Problems that can share a batched launch: everything but the image size.
@@ -85,23 +87,34 @@ struct SolveSpec {
     const bl_solve_opts* o;
 };
 
-// Recycled CG over up to `cap` concurrent solves of one operator class.  Each iteration is
-// one apply launch and one update launch over all running slots; the host enqueues chunks
-// of POLL iterations and reads the slots' stop flags one chunk behind, so the device never
-// waits for the host.  A slot's arithmetic and decisions do not depend on the others.
+// Recycled CG over up to `cap` concurrent solves of up to MAX_GROUPS operator classes.  Each
+// iteration is one apply launch per class with running solves and one update launch over all
+// running solves; the host enqueues chunks of POLL iterations and reads the solves' stop flags
+// one chunk behind, so the device never waits for the host.  A solve's arithmetic and
+// decisions do not depend on the others.
+constexpr int MAX_GROUPS = 4;
+
 class Batch {
 public:
     bl_ctx* c = nullptr;
-    bl::Stencil base{};
-    bool fp32 = false;
     int cap = 0;
     bl::Slot* d_slots = nullptr;   // device [cap]
     int* d_hdr = nullptr;          // device [cap * HDR_BYTES / 4]: gathered headers
     char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES]
     hipEvent_t poll_ev[2] = {};
 
+    struct Group {                 // one operator class: stencil template and precision
+        bl_problem cls{};
+        bl::Stencil base{};
+        bool fp32 = false;
+        int users = 0;             // slots in use
+        bl::BatchMap tmap{};       // tile map of its running slots
+    };
+    std::vector<Group> groups;
+
     struct Host {
         bool used = false, running = false, complete = false;
+        int group = -1;
         bl::Slot d{};
         int max_iter = 0, rr_every = 0;
         bool store_basis = false;
@@ -115,8 +128,8 @@ public:
     int step = 0;                  // next global step index
     long chunk_id = 0;
 
-    bl_status init(bl_ctx* ctx, const bl_problem* cls, int capacity, bl::Slot* slots, int* hdr_dev, char* hdr_pinned,
-                   hipEvent_t ev0, hipEvent_t ev1);
+    bl_status init(bl_ctx* ctx, int capacity, bl::Slot* slots, int* hdr_dev, char* hdr_pinned, hipEvent_t ev0,
+                   hipEvent_t ev1);
     // Validate and start solve `sp` in free slot idx with device scratch B; taps_stage is
     // pinned host memory of TAPS_MAX doubles that stays untouched until the slot retires.
     bl_status admit(int idx, const SolveSpec& sp, const SlotBuffers& B, double* taps_stage);
@@ -130,7 +143,7 @@ public:
 
 private:
     bool dirty = true;
-    bl::BatchMap tmap{}, pmap{}, fold_app{}, fold_upd{};
+    bl::BatchMap pmap{}, fold_app{}, fold_upd{};
     std::vector<int> run_list;
     struct Timed {
         int ev;                    // first of 3 events

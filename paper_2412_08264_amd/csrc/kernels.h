@@ -35,7 +35,7 @@ hipError_t launch_b_apply(const Stencil& base, bool fp32, const Slot* slots, con
                           hipStream_t stream);
 hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t stream);
 hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipStream_t stream);
-hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, hipStream_t stream);
+hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, int step, hipStream_t stream);
 hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream);
 hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, hipStream_t stream);
 hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,

@@ -107,146 +107,4 @@ __device__ __forceinline__ void stage_xhat(T* xs, const Stencil& S, const double
     }
 }
 
-// Evaluate H v on the owned TH x TW tile from the staged region; result in lds[o_out].
-// xs_staged: the TV kernels staged xhat already (stage_xhat before the barrier).
-// RB is the blur radius as a compile-time constant (the tap loops unroll fully and their LDS
-// loads issue together); LDS views are __restrict__ so passes pipeline across outputs.
-template <typename T, int RB>
-__device__ void hvp_tile(T* lds, const Stencil& S, const TileLayout& L, const double* __restrict__ xhat,
-                         int r0, int c0, bool xs_staged = false) {
-    constexpr int R = RB;
-    const int E = L.E, RW = L.RW, RH = L.RH;
-    const T* __restrict__ v = lds + L.o_v;
-    T* __restrict__ h1 = lds + L.o_h1;
-    T* __restrict__ t1 = lds + L.o_t1;
-    T* __restrict__ out = lds + L.o_out;
-    T g[2 * RB + 1];
-#pragma unroll
-    for (int a = 0; a <= 2 * RB; ++a) g[a] = (T)S.g[a];
-
-    // ---- A(A v), separable
-    const int W1 = TW + 2 * R;
-    TILE_LOOP(RH, W1, rr, cc) {                                       // rows of region 0
-        const int idx = rr * W1 + cc;
-        const T* src = v + rr * RW + cc + (E - R) - R;
-        T acc = T(0);
-        _Pragma("unroll") for (int b = 0; b <= 2 * R; ++b) acc += g[b] * src[b];
-        h1[idx] = acc;
-    }
-    __syncthreads();
-    const int H1 = TH + 2 * R;
-    TILE_LOOP(H1, W1, rr, cc) {                                       // columns -> A v
-        const int idx = rr * W1 + cc;
-        const T* src = h1 + (rr + E - R - R) * W1 + cc;
-        T acc = T(0);
-        _Pragma("unroll") for (int a = 0; a <= 2 * R; ++a) acc += g[a] * src[a * W1];
-        const int gi = r0 - R + rr, gj = c0 - R + cc;
-        t1[idx] = (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) ? acc : T(0);
-    }
-    __syncthreads();
-    T* __restrict__ h2 = h1;                                          // reuse: (TH+2R) x TW
-    TILE_LOOP(H1, TW, rr, cc) {
-        const int idx = rr * TW + cc;
-        const T* src = t1 + rr * W1 + cc;
-        T acc = T(0);
-        _Pragma("unroll") for (int b = 0; b <= 2 * R; ++b) acc += g[b] * src[b];
-        h2[idx] = acc;
-    }
-    __syncthreads();
-    TILE_LOOP(TH, TW, rr, cc) {
-        const int idx = rr * TW + cc;
-        const T* src = h2 + rr * TW + cc;
-        T acc = T(0);
-        _Pragma("unroll") for (int a = 0; a <= 2 * R; ++a) acc += g[a] * src[a * TW];
-        out[idx] = T(2) * acc;
-    }
-
-    if (S.reg == BL_REG_TV) {
-        // ---- lambda D^T (B D v)
-        T* xs = lds + L.o_x;               // xhat on [r0-1, r0+TH+1) x [c0-1, c0+TW+1)
-        T* fx = lds + L.o_fx;              // flux on [r0-1, r0+TH) x [c0-1, c0+TW)
-        T* fy = lds + L.o_fy;
-        const int XW = TW + 2;
-        if (!xs_staged) {
-            stage_xhat<T>(xs, S, xhat, r0, c0);
-            __syncthreads();
-        }
-        const T gam2 = (T)S.gam2;
-        const int FW = TW + 1;
-        TILE_LOOP((TH + 1), FW, rr, cc) {
-            const int idx = rr * FW + cc;
-            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
-            T fxv = T(0), fyv = T(0);
-            if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
-                const T xc = xs[rr * XW + cc];
-                const T a = (gj < S.w - 1) ? xs[rr * XW + cc + 1] - xc : T(0);
-                const T b = (gi < S.h - 1) ? xs[(rr + 1) * XW + cc] - xc : T(0);
-                const T* vc = v + (rr - 1 + E) * RW + (cc - 1 + E);
-                const T da = (gj < S.w - 1) ? vc[1] - vc[0] : T(0);
-                const T db = (gi < S.h - 1) ? vc[RW] - vc[0] : T(0);
-                const T psi2 = a * a + b * b + gam2;
-                const T psi = sqrt(psi2);
-                const T ip3 = T(1) / (psi2 * psi);
-                fxv = ((b * b + gam2) * da - a * b * db) * ip3;
-                fyv = ((a * a + gam2) * db - a * b * da) * ip3;
-            }
-            fx[idx] = fxv;
-            fy[idx] = fyv;
-        }
-        __syncthreads();
-        const T lam = (T)S.lam;
-        TILE_LOOP(TH, TW, rr, cc) {
-            const int idx = rr * TW + cc;
-            const int f = (rr + 1) * FW + (cc + 1);
-            const T dt = -fx[f] + fx[f - 1] - fy[f] + fy[f - FW];
-            out[idx] += lam * dt;
-        }
-        __syncthreads();
-    } else {
-        // ---- eps v + sum_j lambda_j K_j^T (phi''_j . K_j v)
-        const int F = L.F, fs = S.fs, TWF = TW + 2 * F, THF = TH + 2 * F;
-        T* tb = lds + L.o_t;
-        T* taps = lds + L.o_taps;
-        const int ntap = S.nf * fs * fs;
-        for (int k = threadIdx.x; k < ntap + S.nf; k += NT)
-            taps[k] = (k < ntap) ? (T)S.taps[k] : (T)S.lamj[k - ntap];
-        const T eps = (T)S.eps;
-        TILE_LOOP(TH, TW, rr, cc) {
-            const int idx = rr * TW + cc;
-            out[idx] += eps * v[(rr + E) * RW + (cc + E)];
-        }
-        __syncthreads();
-        for (int j = 0; j < S.nf; ++j) {
-            const T* kj = taps + j * fs * fs;
-            TILE_LOOP(THF, TWF, rr, cc) {
-                const int idx = rr * TWF + cc;
-                const int gi = r0 - F + rr, gj = c0 - F + cc;
-                T val = T(0);
-                if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) {
-                    const T* src = v + (rr + E - F - F) * RW + (cc + E - F - F);
-                    T acc = T(0);
-                    for (int a = 0; a < fs; ++a)
-                        for (int b = 0; b < fs; ++b) acc += kj[a * fs + b] * src[a * RW + b];
-                    const size_t gidx = (size_t)j * S.n + (size_t)gi * S.w + gj;
-                    const T d2 = (sizeof(T) == 4) ? (T)S.d2f[gidx] : (T)S.d2[gidx];
-                    val = d2 * acc;
-                }
-                tb[idx] = val;
-            }
-            __syncthreads();
-            const T lj = taps[ntap + j];
-            TILE_LOOP(TH, TW, rr, cc) {
-                const int idx = rr * TW + cc;
-                // K^T t at (rr, cc): sum_{a,b} k[a][b] t(rr - (a - F), cc - (b - F))
-                const T* src = tb + (rr + F + F) * TWF + (cc + F + F);
-                T acc = T(0);
-                for (int a = 0; a < fs; ++a)
-                    for (int b = 0; b < fs; ++b) acc += kj[a * fs + b] * src[-a * TWF - b];
-                out[idx] += lj * acc;
-            }
-            __syncthreads();
-        }
-    }
-}
-
 }  // namespace bl

@@ -2,6 +2,7 @@
 // filter-state precompute, the hypergradient map J, the lower-level gradient and A.
 #include "kernels.h"
 #include "stencil.h"
+#include "tile.h"
 
 namespace bl {
 
@@ -17,23 +18,28 @@ __device__ __forceinline__ void write_partials(double* part, int nv, double*, Va
 }
 
 // ------------------------------------------------------------------ out[:, c] = H v[:, c]
-template <typename T, int RB>
+// One 32 x 32 tile of one column per block (grid: tiles x columns).
+template <typename T, int R, int CLS>
 __global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict__ xhat,
                                             const double* __restrict__ v, double* __restrict__ out) {
+    using L = QLayout<T, R, CLS>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
-    const TileLayout L = tile_layout(S.R, S.reg, S.fs);
-    int r0, c0;
-    tile_origin(S, xcd_tile(blockIdx.x, gridDim.x), r0, c0);
+    const int qtx = (S.w + QW - 1) / QW;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r0 = (t / qtx) * QH, c0 = (t % qtx) * QW;
     const double* vc = v + (size_t)blockIdx.y * S.n;
-    stage_region<T>(lds + L.o_v, S, L, r0, c0, [&](int i) { return vc[i]; });
+    q_stage<T, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0, [&](int i) { return vc[i]; });
+    if constexpr (CLS == TC_TV) q_stage_xhat<T>(lds + L::o_x, S.h, S.w, xhat, r0, c0);
     __syncthreads();
-    hvp_tile<T, RB>(lds, S, L, xhat, r0, c0);
-    __syncthreads();
+    T hv[QR];
+    q_hvp<T, R, CLS>(lds, S, r0, c0, hv);
     double* oc = out + (size_t)blockIdx.y * S.n;
-    for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
-        const int gi = r0 + idx / TW, gj = c0 + idx % TW;
-        if (gi < S.h && gj < S.w) oc[gi * S.w + gj] = (double)lds[L.o_out + idx];
+    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        const int gi = r0 + QR * ty + k;
+        if (gi < S.h && gj < S.w) oc[gi * S.w + gj] = (double)hv[k];
     }
 }
 
@@ -382,32 +388,21 @@ static inline dim3 tiles_grid(const Stencil& S, int ncols) { return dim3(S.tiles
 int tiles_of(const Stencil& S) { return S.tiles_x * S.tiles_y; }
 
 // Kernels are instantiated per blur radius (0..MAX_R) and arithmetic type.
-#define BL_RADIUS_SWITCH(R, CALL)          \
-    switch (R) {                           \
-        case 0: CALL(0); break;            \
-        case 1: CALL(1); break;            \
-        case 2: CALL(2); break;            \
-        case 3: CALL(3); break;            \
-        case 4: CALL(4); break;            \
-        case 5: CALL(5); break;            \
-        case 6: CALL(6); break;            \
-        case 7: CALL(7); break;            \
-        default: CALL(8); break;           \
-    }
-
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
                       hipStream_t st) {
-    const size_t lds = fp32 ? tile_lds_bytes<float>(S.R, S.reg, S.fs) : tile_lds_bytes<double>(S.R, S.reg, S.fs);
-#define HVP_CALL(RB)                                                                                     \
-    if (fp32) {                                                                                          \
-        allow_lds(k_hvp<float, RB>, lds);                                                                \
-        hipLaunchKernelGGL((k_hvp<float, RB>), tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out);  \
-    } else {                                                                                             \
-        allow_lds(k_hvp<double, RB>, lds);                                                               \
-        hipLaunchKernelGGL((k_hvp<double, RB>), tiles_grid(S, ncols), dim3(NT), lds, st, S, xhat, v, out); \
-    }
-    BL_RADIUS_SWITCH(S.R, HVP_CALL)
-#undef HVP_CALL
+    const dim3 grid(((S.w + QW - 1) / QW) * ((S.h + QH - 1) / QH), ncols);
+    q_dispatch(S.R, tile_class(S.reg, S.fs), [&](auto rc, auto cc) {
+        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
+        if (fp32) {
+            const size_t lds = QLayout<float, RR, CC>::bytes;
+            allow_lds(k_hvp<float, RR, CC>, lds);
+            hipLaunchKernelGGL((k_hvp<float, RR, CC>), grid, dim3(NT), lds, st, S, xhat, v, out);
+        } else {
+            const size_t lds = QLayout<double, RR, CC>::bytes;
+            allow_lds(k_hvp<double, RR, CC>, lds);
+            hipLaunchKernelGGL((k_hvp<double, RR, CC>), grid, dim3(NT), lds, st, S, xhat, v, out);
+        }
+    });
     return hipGetLastError();
 }
 

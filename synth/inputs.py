@@ -139,3 +139,67 @@ def custom(name: str, side: int, reg: str, s: int, width: int | None = None, **k
     outer = base.pop("outer", 8)
     return Workload(name, side, side if width is None else width, base.pop("rect_min"), base.pop("rect_max"), base.pop("blur_radius"),
                     base.pop("blur_sigma"), base.pop("noise"), seed, reg, s, base.pop("tol"), outer, **base)
+
+
+def batch_set(count: int = 64, seed: int = 4000, s: int = 20) -> list[Workload]:
+    """Batched training set: ``count`` images whose sides are uniform over {128, ..., 512}
+    (drawn with ``seed``), rectangles 8-20, the filter family's blur (11x11, sigma 3), noise 0.02
+    and its eight 7x7 filters (shared theta: one filter seed for all), recycle dimension s.
+    Image k draws its rectangles and noise with seed ``seed + 1 + k``."""
+    sides = batch_sides(count, seed)
+    return [custom(f"batch{k}", side, "filters", s, seed=seed + 1 + k, prec="mixed")
+            for k, side in enumerate(sides)]
+
+
+SERVE_SIDES = (64, 128, 256, 512, 1024)
+SERVE_S = (10, 30, 50)
+
+
+def serve_samples(count: int = 256, seed: int = 5000) -> list[Workload]:
+    """Resident training samples of the served stream: side uniform over SERVE_SIDES, TV (the
+    256x256 family's blur and noise) or eight 7x7 filters (the 512x512 family's) with equal
+    probability, recycle dimension uniform over SERVE_S.  Sample k draws its image with seed
+    ``seed + 1 + k``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        side = int(rng.choice(np.array(SERVE_SIDES)))
+        reg = "tv" if rng.random() < 0.5 else "filters"
+        s = int(rng.choice(np.array(SERVE_S)))
+        out.append(custom(f"serve{k}", side, reg, s, seed=seed + 1 + k))
+    return out
+
+
+def poisson_arrivals(rate: float, duration: float, count: int, seed: int = 5001) -> list[tuple[float, int]]:
+    """Arrival times (seconds) of a Poisson stream of the given rate over ``duration`` seconds,
+    each naming a sample drawn uniformly from ``count``."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            return out
+        out.append((t, int(rng.integers(count))))
+
+
+def theta_drift(wl: Workload, steps: int, seed: int, scale: float = 0.02) -> list[np.ndarray]:
+    """A frozen outer-step path of hyperparameters for a served sample: theta_0 (the recipe's
+    initial value) followed by steps - 1 increments of a seeded normal direction scaled to
+    ``scale`` times the norm of theta_0 (filters: the tap increments are made zero-mean per
+    filter, as the filter parameterisation requires)."""
+    filters = None
+    if wl.reg == "filters":
+        filters = zero_mean_filters(wl.n_filters, wl.filter_size, np.random.default_rng(wl.filter_seed))
+    th = initial_theta(wl, filters)
+    rng = np.random.default_rng(seed)
+    path = [th.copy()]
+    for _ in range(steps - 1):
+        d = rng.standard_normal(th.shape)
+        if wl.reg == "filters":
+            f2 = wl.filter_size ** 2
+            for j in range(wl.n_filters):
+                blk = d[j * (1 + f2) + 1:(j + 1) * (1 + f2)]
+                blk -= blk.mean()
+        th = th + scale * np.linalg.norm(path[0]) / np.linalg.norm(d) * d
+        path.append(th.copy())
+    return path

@@ -81,7 +81,7 @@ def test_engine_argument_checks_without_gpu():
     from paper_2412_08264_amd import bilevel as B
     P = B.bl_problem(8, 8, 1, 1.0, B.BL_REG_TV, 0, 0, 0.0, 0, 0)
     eng = C.c_void_p()
-    assert B.lib.bl_engine_create(None, C.byref(P), 2, None, 0, C.byref(eng)) == B.BL_E_ARG
+    assert B.lib.bl_engine_create(None, 2, None, 0, C.byref(eng)) == B.BL_E_ARG
     assert B.lib.bl_engine_destroy(None) == B.BL_E_ARG
     nd = C.c_int()
     assert B.lib.bl_engine_step(None, 1, 1, None, C.byref(nd)) == B.BL_E_ARG

@@ -132,7 +132,7 @@ def test_engine_continuous_admission_bitwise(B, kind, prec):
         ref.append((w, st, basis, c["rec"].rs.v_cur))
     sizes = [B.Engine.slot_bytes(c["P"], c["rec"].rs.s_cur if c["rec"] else 0) for c in cases]
     arena = max(sizes[0] + sizes[1], sizes[2])     # the first two fit together, never all three
-    eng = B.Engine(cases[0]["P"], cap=3, arena_bytes=arena)
+    eng = B.Engine(cap=3, arena_bytes=arena)
     try:
         ws = [c["w0"].clone() for c in cases]
         slots = {}
@@ -175,19 +175,34 @@ def test_engine_continuous_admission_bitwise(B, kind, prec):
             assert torch.equal(c["rec"].V[:vcur], basis)
 
 
-def test_engine_rejects_other_class_and_bad_slots(B):
-    c = make_case(B, "tv", 32, 32, 0, 401)
-    other = B.bl_problem(32, 32, 3, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)   # different blur radius
-    with B.Engine(c["P"], cap=1, arena_bytes=B.Engine.slot_bytes(c["P"], 0)) as eng:
-        w = c["w0"].clone()
+def test_engine_mixes_operator_classes(B):
+    """TV and filter solves in FP64 and mixed precision share one engine (one apply launch per
+    class, one update launch for all) and each equals its solo run bitwise; a fifth class is
+    refused while four are admitted."""
+    cases = [make_case(B, "tv", 36, 44, 5, 401), make_case(B, "filters", 40, 36, 4, 402),
+             make_case(B, "filters", 32, 48, 6, 403, prec="mixed"), make_case(B, "tv", 50, 30, 0, 404, prec="mixed")]
+    kw = dict(tol=1e-9, rr_every=8, store_basis=False)
+    ref = [solo(B, c, **kw) for c in cases]
+    fifth = B.bl_problem(32, 32, 3, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)   # another blur radius
+    arena = sum(B.Engine.slot_bytes(c["P"], c["rec"].rs.s_cur if c["rec"] else 0) for c in cases) + \
+        B.Engine.slot_bytes(fifth, 0)
+    with B.Engine(cap=5, arena_bytes=arena) as eng:
+        ws = [c["w0"].clone() for c in cases]
+        slots = {}
+        for k, c in enumerate(cases):
+            sl = eng.admit(c["P"], c["th"], c["xh"], c["g"], ws[k], c["rec"], B.solve_opts(**kw))
+            slots[sl] = k
+        w5 = torch.zeros(32 * 32, dtype=torch.float64, device=DEV)
         with pytest.raises(B.BLError):
-            eng.admit(other, c["th"], c["xh"], c["g"], w, None, B.solve_opts())
+            eng.admit(fifth, np.zeros(2), w5, w5, w5, None, B.solve_opts())
         with pytest.raises(B.BLError):
-            eng.retire(0)                        # nothing admitted
-        sl = eng.admit(c["P"], c["th"], c["xh"], c["g"], w, None, B.solve_opts(tol=1e-9, store_basis=False))
-        assert sl == 0
-        assert eng.step(return_on_done=True) == [0]
-        st = eng.retire(0)
-        assert st.status == B.BL_OK
-        w2, st2 = solo(B, c, tol=1e-9, store_basis=False)
-        assert torch.equal(w, w2) and st.iters == st2.iters
+            eng.retire(4)                        # nothing there
+        stats = {}
+        while slots:
+            for sl in eng.step():
+                stats[slots.pop(sl)] = eng.retire(sl)
+    for k in range(len(cases)):
+        w_ref, st_ref = ref[k]
+        assert st_ref.status == B.BL_OK
+        assert same(stats[k], st_ref), k
+        assert torch.equal(ws[k], w_ref)

@@ -56,7 +56,7 @@ def foe_case(h, w, seed=31, noise_x=0.02):
 
 
 # ------------------------------------------------------------------ stencils
-@pytest.mark.parametrize("shape,r", [((37, 75), 2), ((256, 256), 4), ((5, 3), 1)])
+@pytest.mark.parametrize("shape,r", [((37, 75), 2), ((256, 256), 4), ((5, 3), 1), ((70, 90), 8), ((33, 64), 0)])
 def test_hvp_tv(B, shape, r):
     wl, inst, prob, xh = tv_case(*shape, r=r, sigma=1.5 + 0.25 * r)
     th = inst["theta0"]
@@ -82,6 +82,24 @@ def test_hvp_filters_fp64_and_mixed(B, shape):
         out = torch.empty(prob.n, dtype=torch.float64, device=DEV)
         S.hvp(th, dev(xh), dev(v), out)
         assert rel(host(out), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("fs,r", [(5, 3), (3, 8), (1, 0), (7, 1)])
+def test_hvp_filters_other_sizes_and_radii(B, fs, r):
+    """Filter sizes other than 7x7 take the run-time-size path; radii 0..8 change the halo."""
+    wl = synth.custom("f", 45, "filters", 4, width=67, rect_min=2, rect_max=6, seed=41, filter_size=fs,
+                      blur_radius=r, blur_sigma=2.0)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xh = inst["xstar"].ravel() + 0.02 * synth.unit_noise(prob.n, 42)
+    th = inst["theta0"]
+    V = synth.unit_noise((2, prob.n), 43)
+    ref = np.stack([prob.hvp(xh, th, V[k]) for k in range(2)])
+    for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
+        with B.Session(B.problem_from(wl, prec=prec)) as S:
+            out = torch.empty((2, prob.n), dtype=torch.float64, device=DEV)
+            S.hvp(th, dev(xh), dev(V), out, ncols=2)
+            assert rel(host(out), ref) <= tol, prec
 
 
 @pytest.mark.parametrize("kind", ["tv", "filters"])
