@@ -644,10 +644,53 @@ def cpu_baseline_serve(wls, data_steps, seconds_budget=25.0):
 
 
 # =============================================================================== kernels-only
+def kernels_only_batch(args, B, torch, synth):
+    """batch64 shapes at stand-in points x* + 0.05 e': 100 plain iterations of all images in one
+    engine (basis stored), a refresh of every image, 100 recycled iterations, then the copy."""
+    dev = torch.device("cuda:0")
+    wls = synth.batch_set(args.batch, 4000, s=20)
+    Ps = [B.problem_from(wl, prec=args.prec) for wl in wls]
+    P64 = [B.problem_from(wl, prec="fp64") for wl in wls]
+    ctx = B.Context(P64, s_max=20, v_cap=V_CAP, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs, xh, recs = [], [], []
+    for wl in wls:
+        inst = synth.instance(wl)
+        xs.append(t(inst["xstar"]))
+        xh.append(xs[-1] + 0.05 * t(synth.unit_noise(wl.n, wl.seed + 77)))
+        recs.append(B.Recycle(wl.n, 20, V_CAP, dev))
+    th = synth.instance(wls[0])["theta0"]
+    eng = B.Engine(cap=len(Ps), arena_bytes=int(lib_batched_bytes(B, Ps, [20] * len(Ps)) * 1.02), device=dev,
+                   ctx=ctx.ctx)
+    for phase in range(2):
+        ws = [torch.zeros_like(x) for x in xs]
+        if phase == 1:
+            for k, P in enumerate(P64):
+                ctx.refresh_p(P, recs[k], th, xh[k], s=20)
+        slots = set()
+        for k, P in enumerate(Ps):
+            o = B.solve_opts(tol=0.0, max_iter=100, store_basis=phase == 0)
+            slots.add(eng.admit(P, th, xh[k], xh[k] - xs[k], ws[k], recs[k], o))
+        while slots:
+            for sl in eng.step(return_on_done=False):
+                eng.retire(sl)
+                slots.discard(sl)
+    a = torch.empty(8 * 1024 * 1024, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    eng.close()
+    ctx.close()
+    print(json.dumps({"kernels_only": True, "workload": "batch64", "copy_bytes": a.numel() * 8}))
+
+
 def kernels_only(args, B, torch, synth):
     """Short run for hardware counters: 200 plain and 200 recycled CG iterations on the
     workload's shape at a stand-in point, and one 64 MiB device-to-device copy (counter
     calibration: its FETCH_SIZE / WRITE_SIZE should read 64 MiB each)."""
+    if args.workload == "batch64":
+        kernels_only_batch(args, B, torch, synth)
+        return
     wl = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     inst = synth.instance(wl)

@@ -168,16 +168,18 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
 }
 
 // out[k] = sum over blocks of part[b*nv + k], k < nv (nv <= NT), into LDS `out` (all threads).
-// G = NT / nv threads share value k; thread (k, j) sums blocks j, j+G, ... in order and
-// the G sums are added in fixed order: the result depends only on the records, so every
-// block that reduces the same records obtains bit-identical values.
+// G threads share value k (G the largest power of two with G * nv <= NT): thread (k, j) sums
+// blocks j, j+G, ... (eight loads in flight), then the G partial sums are combined by an
+// xor butterfly (within a wave; across the waves of a group in wave order).  The order depends
+// only on (nblocks, nv), so every block that reduces the same records obtains bit-identical
+// values, and no thread adds more than nblocks / G + log2(G) terms in sequence.
 __device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv, double* out) {
-    __shared__ double tmp[NT];
-    const int G = nv >= NT ? 1 : NT / nv;
-    const int k = threadIdx.x / G, j = threadIdx.x - k * G;
+    __shared__ double wsum[NWAVE];
+    int G = 1;
+    while (G * 2 * nv <= NT) G *= 2;
+    const int k = threadIdx.x / G, j = threadIdx.x & (G - 1);
     double acc = 0.0;
     if (k < nv) {
-        // eight loads in flight per round; the summation order is fixed by (nblocks, nv)
         double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int b = j;
         for (; b + 7 * G < nblocks; b += 8 * G) {
@@ -187,12 +189,19 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
         for (int u = 0; b < nblocks; b += G, ++u) a8[u & 7] += part[(size_t)b * nv + k];
         acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     }
-    tmp[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x < nv) {
-        double s = 0.0;
-        for (int q = 0; q < G; ++q) s += tmp[threadIdx.x * G + q];
-        out[threadIdx.x] = s;
+    const int span = G < 64 ? G : 64;
+    for (int off = span >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (G <= 64) {
+        if (j == 0 && k < nv) out[k] = acc;
+    } else {
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if ((int)threadIdx.x < nv) {
+            const int wpg = G / 64;
+            double s = 0.0;
+            for (int q = 0; q < wpg; ++q) s += wsum[threadIdx.x * wpg + q];
+            out[threadIdx.x] = s;
+        }
     }
     __syncthreads();
 }

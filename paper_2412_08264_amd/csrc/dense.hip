@@ -1,6 +1,9 @@
 // Dense kernels of the recycle-space refresh: tall-skinny Gram products, tall x small
-// products, and single-workgroup small dense algebra (Cholesky with column drop,
-// parallel cyclic Jacobi, projected GSVD and Ritz-GSV selection).
+// products, and single-workgroup small dense algebra (Cholesky with column drop, a
+// symmetric eigensolver (Householder tridiagonalisation, bisection, inverse iteration),
+// projected GSVD and Ritz-GSV selection).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace bl {
@@ -180,98 +183,283 @@ __global__ void __launch_bounds__(SD_NT) k_chol_drop(int t, const double* Gm, do
     chol_drop(t, Gm, tol, lds ? dyn_lds : R, kept, tk_out, Xinv, ldx);
 }
 
-// Parallel cyclic Jacobi on a symmetric m x m matrix A (row-major, in place -> eigenvalues on
-// the diagonal), eigenvectors accumulated in V (row-major, V[i*m + k] = component i of
-// vector k).  Round-robin pairing; m is padded to even with a decoupled index.
-__device__ void jacobi_eigh(int m, double* A, double* V, double* cs, int* pairs, int max_sweeps) {
-    const int me = (m + 1) & ~1;      // even count; index m (if padded) is a dummy
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
-    __shared__ double s_off, s_norm;
+// ------------------------------------------------------------------ symmetric eigensolver
+constexpr int EIG_MAX = 256;        // largest order
+constexpr int KC = 32;              // rows of G M^{-1} staged per chunk of S^T S
+
+// 1 / a from the hardware reciprocal refined by one Newton step (relative error ~1e-16); used
+// where a correctly rounded quotient is not needed (Sturm counts, inverse-iteration solves).
+__device__ __forceinline__ double fast_rcp(double a) {
+    const double r = __builtin_amdgcn_rcp(a);
+    return r * fma(-a, r, 2.0);
+}
+
+// Block-wide sum (SD_NT threads); the result is valid in every thread.
+__device__ __forceinline__ double sd_sum(double v, double* red) {
+    v = wave_sum(v);
+    if (SD_NT == 64) return v;
     __syncthreads();
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // convergence: off-diagonal Frobenius norm relative to the full norm
-        {
-            __shared__ double r_off[SD_NT / 64], r_nrm[SD_NT / 64];
-            double off = 0.0, nrm = 0.0;
-            for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-                const double v = A[idx];
-                nrm += v * v;
-                if (idx / m != idx % m) off += v * v;
-            }
-            off = wave_sum(off);
-            nrm = wave_sum(nrm);
-            if ((threadIdx.x & 63) == 0) {
-                r_off[threadIdx.x >> 6] = off;
-                r_nrm[threadIdx.x >> 6] = nrm;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double a = 0.0, b = 0.0;
-                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-                    a += r_off[w];
-                    b += r_nrm[w];
-                }
-                s_off = a;
-                s_norm = b;
-            }
-            __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < SD_NT / 64; ++k) s += red[k];
+    return s;
+}
+
+// Householder tridiagonalisation of a symmetric m x m matrix A (row-major, full storage):
+// A <- H_{m-3} ... H_0 A H_0 ... H_{m-3} with H_k = I - tau_k v_k v_k^T acting on indices
+// k+1 .. m-1 and mapping column k below the diagonal to a multiple of e_1.  Output: the
+// diagonal d and subdiagonal e (e[i] couples i and i+1, e[m-1] = 0); v_k is kept in column k
+// of A below the diagonal and tau_k in tau.
+__device__ void tridiag(int m, double* A, double* d, double* e, double* tau, double* vv, double* pw, double* red) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int k = 0; k + 2 < m; ++k) {
+        const int n2 = m - k - 1;
+        double sg = 0.0;
+        for (int i = tid; i < n2; i += bs) {
+            const double xi = A[(size_t)(k + 1 + i) * m + k];
+            vv[i] = xi;
+            if (i >= 1) sg += xi * xi;
         }
-        if (s_off <= 1e-30 * s_norm || s_off == 0.0) break;
-        for (int rnd = 0; rnd < me - 1; ++rnd) {
-            const int np = me / 2;
-            for (int k = threadIdx.x; k < np; k += blockDim.x) {
-                int a, b;
-                if (k == 0) {
-                    a = 0;
-                    b = (rnd % (me - 1)) + 1;
-                } else {
-                    a = ((k + rnd) % (me - 1)) + 1;
-                    b = ((me - 1 - k + rnd) % (me - 1)) + 1;
+        const double sig = sd_sum(sg, red);
+        const double x0 = A[(size_t)(k + 1) * m + k];
+        const double nrm = sqrt(x0 * x0 + sig);
+        // v = x - alpha e_1, alpha = -sign(x0) |x|:  v^T v = 2 |x| (|x| + |x0|), tau = 2 / v^T v
+        const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0.0 ? -nrm : nrm);
+        const double t = nrm == 0.0 ? 0.0 : 1.0 / (nrm * (nrm + fabs(x0)));
+        __syncthreads();
+        if (tid == 0) {
+            vv[0] = x0 - alpha;
+            e[k] = alpha;
+            tau[k] = t;
+        }
+        __syncthreads();
+        if (t != 0.0) {
+            // p = tau A' v, K = tau/2 p.v, w = p - K v, A' -= v w^T + w v^T
+            double pv = 0.0;
+            for (int i = tid; i < n2; i += bs) {
+                // row i of A' read as column i (A' symmetric): consecutive threads, consecutive banks
+                const double* col = A + (size_t)(k + 1) * m + (k + 1 + i);
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int j = 0;
+                for (; j + 3 < n2; j += 4) {
+                    a0 += col[(size_t)j * m] * vv[j];
+                    a1 += col[(size_t)(j + 1) * m] * vv[j + 1];
+                    a2 += col[(size_t)(j + 2) * m] * vv[j + 2];
+                    a3 += col[(size_t)(j + 3) * m] * vv[j + 3];
                 }
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                pairs[2 * k] = p;
-                pairs[2 * k + 1] = q;
-                double c = 1.0, s = 0.0;
-                if (q < m) {
-                    const double apq = A[p * m + q];
-                    if (apq != 0.0) {
-                        const double tau = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
-                    }
-                }
-                cs[2 * k] = c;
-                cs[2 * k + 1] = s;
+                for (; j < n2; ++j) a0 += col[(size_t)j * m] * vv[j];
+                const double pi = t * ((a0 + a1) + (a2 + a3));
+                pw[i] = pi;
+                pv += pi * vv[i];
             }
+            const double K = 0.5 * t * sd_sum(pv, red);
             __syncthreads();
-            // rows: A <- J^T A
-            for (int idx = threadIdx.x; idx < np * m; idx += blockDim.x) {
-                const int k = idx / m, j = idx - k * m;
-                const int p = pairs[2 * k], q = pairs[2 * k + 1];
-                if (q >= m) continue;
-                const double c = cs[2 * k], s = cs[2 * k + 1];
-                const double ap = A[p * m + j], aq = A[q * m + j];
-                A[p * m + j] = c * ap - s * aq;
-                A[q * m + j] = s * ap + c * aq;
+            for (int i = tid; i < n2; i += bs) pw[i] -= K * vv[i];
+            __syncthreads();
+            for (int idx = tid; idx < n2 * n2; idx += bs) {
+                const int r = idx / n2, c = idx - r * n2;
+                A[(size_t)(k + 1 + r) * m + (k + 1 + c)] -= vv[r] * pw[c] + pw[r] * vv[c];
             }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int idx = threadIdx.x; idx < np * m; idx += blockDim.x) {
-                const int k = idx / m, i = idx - k * m;
-                const int p = pairs[2 * k], q = pairs[2 * k + 1];
-                if (q >= m) continue;
-                const double c = cs[2 * k], s = cs[2 * k + 1];
-                const double ap = A[i * m + p], aq = A[i * m + q];
-                A[i * m + p] = c * ap - s * aq;
-                A[i * m + q] = s * ap + c * aq;
-                const double vp = V[i * m + p], vq = V[i * m + q];
-                V[i * m + p] = c * vp - s * vq;
-                V[i * m + q] = s * vp + c * vq;
+        }
+        for (int i = tid; i < n2; i += bs) A[(size_t)(k + 1 + i) * m + k] = vv[i];
+        __syncthreads();
+    }
+    for (int j = tid; j < m; j += bs) d[j] = A[(size_t)j * m + j];
+    if (tid == 0) {
+        if (m >= 2) e[m - 2] = A[(size_t)(m - 1) * m + (m - 2)];
+        e[m - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// Eigenvalues of the symmetric tridiagonal (d, e), e2[i] = e[i]^2, by bisection on Sturm
+// counts (the number of negative pivots of the LDL^T factorisation of T - x I equals the
+// number of eigenvalues below x), one thread per eigenvalue: lam[k] = k-th smallest.
+__device__ void tri_bisect(int m, const double* d, const double* e2, double glo, double ghi, double pivmin,
+                           double* lam) {
+    for (int k = threadIdx.x; k < m; k += blockDim.x) {
+        double lo = glo, hi = ghi;
+        for (int it = 0; it < 96; ++it) {
+            const double x = 0.5 * (lo + hi);
+            if (!(x > lo && x < hi)) break;   // adjacent doubles: converged
+            int cnt = 0;
+            double q = d[0] - x;
+            for (int i = 0;;) {
+                if (fabs(q) < pivmin) q = -pivmin;
+                cnt += q < 0.0;
+                if (++i >= m) break;
+                q = (d[i] - x) - e2[i - 1] * fast_rcp(q);
             }
-            __syncthreads();
+            if (cnt > k) hi = x;
+            else lo = x;
+        }
+        lam[k] = 0.5 * (lo + hi);
+    }
+}
+
+// One eigenvector of the tridiagonal (d, e) for the eigenvalue approximation lam by inverse
+// iteration: (T - lam I) = P L U with partial pivoting (U with two superdiagonals), three
+// solves from a fixed start vector, each followed by Gram-Schmidt against the `nprev`
+// vectors prev (earlier members of a cluster of close eigenvalues) and scaling.  Vectors and
+// factors are strided by `ld` (element i at [i * ld]) so that the threads of a block, each
+// with its own column, access consecutive LDS words.  z: the unit-norm result; w: 4 strided
+// arrays (u0^{-1}, u1, u2, multipliers) at w + k * wst; piv: pivot flags (stride ld).
+__device__ void tri_invit(int m, const double* d, const double* e, double lam, double tiny, const double* prev,
+                          int nprev, double* z, double* w, size_t wst, unsigned char* piv, int ld, int seed) {
+    double* iu0 = w;
+    double* u1 = w + wst;
+    double* u2 = w + 2 * wst;
+    double* ml = w + 3 * wst;
+    double a = d[0] - lam, c = m > 1 ? e[0] : 0.0;
+    for (int i = 0; i + 1 < m; ++i) {
+        const double b = e[i], an = d[i + 1] - lam, cn = i + 2 < m ? e[i + 1] : 0.0;
+        const size_t o = (size_t)i * ld;
+        if (fabs(a) >= fabs(b)) {
+            const double aa = a != 0.0 ? a : tiny;
+            const double ia = fast_rcp(aa);
+            iu0[o] = ia;
+            u1[o] = c;
+            u2[o] = 0.0;
+            ml[o] = b * ia;
+            piv[o] = 0;
+            a = an - ml[o] * c;
+            c = cn;
+        } else {
+            const double mli = a * fast_rcp(b);
+            iu0[o] = fast_rcp(b);
+            u1[o] = an;
+            u2[o] = cn;
+            ml[o] = mli;
+            piv[o] = 1;
+            a = c - mli * an;
+            c = -mli * cn;
         }
     }
+    iu0[(size_t)(m - 1) * ld] = fast_rcp(a != 0.0 ? a : tiny);
+    for (int i = 0; i < m; ++i) z[(size_t)i * ld] = 1.0 + 0.25 * (double)(((i + 1) * 7919 + seed * 104729) % 101) / 101.0;
+    for (int it = 0; it < 3; ++it) {
+        double zi = z[0];
+        for (int i = 0; i + 1 < m; ++i) {   // y = L^{-1} P z  (zi carries the running element i)
+            double zn = z[(size_t)(i + 1) * ld];
+            if (piv[(size_t)i * ld]) {
+                const double tmp = zi;
+                zi = zn;
+                zn = tmp;
+            }
+            z[(size_t)i * ld] = zi;
+            zi = zn - ml[(size_t)i * ld] * zi;
+        }
+        z[(size_t)(m - 1) * ld] = zi;
+        double x1 = 0.0, x2 = 0.0;   // x[i + 1], x[i + 2]
+        for (int i = m - 1; i >= 0; --i) {   // U x = y
+            const size_t o = (size_t)i * ld;
+            const double v = (z[o] - u1[o] * x1 - u2[o] * x2) * iu0[o];
+            z[o] = v;
+            x2 = x1;
+            x1 = v;
+        }
+        for (int j = 0; j < nprev; ++j) {   // orthogonalise within the cluster
+            const double* pj = prev + j;
+            double dt = 0.0;
+            for (int i = 0; i < m; ++i) dt += pj[(size_t)i * ld] * z[(size_t)i * ld];
+            for (int i = 0; i < m; ++i) z[(size_t)i * ld] -= dt * pj[(size_t)i * ld];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += z[(size_t)i * ld] * z[(size_t)i * ld];
+        const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+        for (int i = 0; i < m; ++i) z[(size_t)i * ld] *= inv;
+    }
+}
+
+// Symmetric eigenproblem of the m x m matrix A (row-major, destroyed): all eigenvalues in
+// ascending order to lam, the eigenvectors of eigenvalues lo .. hi-1 to the columns of Z
+// (Z[(k - lo) * m + i] = component i).  Householder tridiagonalisation (in LDS when m^2
+// doubles fit), eigenvalues by parallel bisection, vectors by inverse iteration (eigenvalues
+// closer than 1e-7 of the spectrum's width are treated as a cluster, their vectors computed
+// in sequence and orthogonalised), and the reflectors applied to the few vectors wanted.
+// scr: (hi - lo) * 4 m + m doubles of scratch.
+__device__ void eig_range(int m, double* A, int lo, int hi, double* lam, double* Z, double* scr, int ldsd) {
+    __shared__ double d[EIG_MAX], e[EIG_MAX], e2[EIG_MAX], tau[EIG_MAX], vv[EIG_MAX], pw[EIG_MAX],
+        red[SD_NT / 64];
+    __shared__ double s_lo, s_hi, s_piv, s_gap;
+    __shared__ int cstart[EIG_MAX];
+    extern __shared__ double dyn_lds[];
+    const bool in_lds = m * m <= ldsd;
+    double* LA = in_lds ? dyn_lds : A;
+    if (in_lds) {
+        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) LA[idx] = A[idx];
+        __syncthreads();
+    }
+    tridiag(m, LA, d, e, tau, vv, pw, red);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) e2[i] = e[i] * e[i];
+    if (threadIdx.x == 0) {   // Gershgorin interval
+        double gl = d[0], gh = d[0], me2 = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
+            gl = fmin(gl, d[i] - r);
+            gh = fmax(gh, d[i] + r);
+            if (i + 1 < m) me2 = fmax(me2, e[i] * e[i]);
+        }
+        const double w = fmax(gh - gl, fmax(fabs(gl), fabs(gh)));
+        s_lo = gl - 1e-14 * w - 1e-300;
+        s_hi = gh + 1e-14 * w + 1e-300;
+        s_piv = 2.3e-308 * fmax(1.0, me2);
+        s_gap = 1e-7 * w;
+    }
+    __syncthreads();
+    tri_bisect(m, d, e2, s_lo, s_hi, s_piv, lam);
+    __syncthreads();
+    const int nw = hi - lo;
+    if (threadIdx.x == 0) {   // clusters among the wanted eigenvalues
+        for (int k = 0; k < nw; ++k) cstart[k] = (k == 0 || lam[lo + k] - lam[lo + k - 1] > s_gap) ? 1 : 0;
+    }
+    __syncthreads();
+    const double tiny = 2.3e-16 * fmax(fabs(s_lo), fabs(s_hi));
+    // vectors and inverse-iteration factors: in LDS after LA when they fit (element i of
+    // vector k at zs[i * nw + k]), else in the global scratch
+    const size_t need = (size_t)5 * m * nw + ((size_t)m * nw + 7) / 8;
+    const bool v_lds = in_lds && (size_t)m * m + need <= (size_t)ldsd;
+    double* zs = v_lds ? dyn_lds + (size_t)m * m : scr;
+    double* ws = zs + (size_t)m * nw;
+    unsigned char* pv = reinterpret_cast<unsigned char*>(ws + (size_t)4 * m * nw);
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) {
+        if (!cstart[k]) continue;
+        int len = 1;
+        while (k + len < nw && !cstart[k + len]) ++len;
+        for (int j = 0; j < len; ++j)
+            tri_invit(m, d, e, lam[lo + k + j], tiny, zs + k, j, zs + k + j, ws + k + j, (size_t)m * nw,
+                      pv + k + j, nw, lo + k + j);
+    }
+    __syncthreads();
+    // back to the original basis: z <- H_0 H_1 ... H_{m-3} z
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) {
+        double* z = zs + k;
+        for (int r = m - 3; r >= 0; --r) {
+            const double tr = tau[r];
+            if (tr == 0.0) continue;
+            const double* hv = LA + (size_t)(r + 1) * m + r;   // v_r[i] at hv[i * m]
+            const int len = m - r - 1;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int i = 0;
+            for (; i + 3 < len; i += 4) {
+                a0 += hv[(size_t)i * m] * z[(size_t)(r + 1 + i) * nw];
+                a1 += hv[(size_t)(i + 1) * m] * z[(size_t)(r + 2 + i) * nw];
+                a2 += hv[(size_t)(i + 2) * m] * z[(size_t)(r + 3 + i) * nw];
+                a3 += hv[(size_t)(i + 3) * m] * z[(size_t)(r + 4 + i) * nw];
+            }
+            for (; i < len; ++i) a0 += hv[(size_t)i * m] * z[(size_t)(r + 1 + i) * nw];
+            const double dt = tr * ((a0 + a1) + (a2 + a3));
+            for (i = 0; i < len; ++i) z[(size_t)(r + 1 + i) * nw] -= dt * hv[(size_t)i * m];
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nw * m; idx += blockDim.x) {
+        const int k = idx / m, i = idx - k * m;
+        Z[(size_t)k * m + i] = zs[(size_t)i * nw + k];
+    }
+    __syncthreads();
 }
 
 // Cholesky M = L L^T in place (lower, column-major ld t).  Returns false if not SPD.
@@ -302,71 +490,95 @@ __device__ bool chol_inplace(int t, double* L) {
     return true;
 }
 
-// x <- M^{-1} x with M = L L^T (single thread, one right-hand side of length t).
-__device__ void chol_solve(int t, const double* L, double* x) {
-    for (int i = 0; i < t; ++i) {
-        double v = x[i];
-        for (int k = 0; k < i; ++k) v -= L[(size_t)k * t + i] * x[k];
-        x[i] = v / L[(size_t)i * t + i];
+// X[:, c] <- M^{-1} X[:, c], c < ncols, with M = L L^T (L lower, column-major ld t); column c
+// starts at X + c * ldc with element stride incx.  L is staged in LDS when it fits; the
+// columns are solved in groups held in LDS (element i of group column c at xs[i * gn + c]),
+// one column per thread.
+__device__ void solve_cols(int t, const double* L, double* X, int ncols, size_t ldc, size_t incx, int ldsd) {
+    extern __shared__ double dyn_lds[];
+    const bool l_in = t * t + t <= ldsd;
+    const double* LL = L;
+    if (l_in) {
+        for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) dyn_lds[idx] = L[idx];
+        LL = dyn_lds;
     }
-    for (int i = t - 1; i >= 0; --i) {
-        double v = x[i];
-        for (int k = i + 1; k < t; ++k) v -= L[(size_t)i * t + k] * x[k];
-        x[i] = v / L[(size_t)i * t + i];
+    double* xs = l_in ? dyn_lds + (size_t)t * t : dyn_lds;
+    const int avail = ldsd - (l_in ? t * t : 0);
+    int group = avail / t;
+    if (group > (int)blockDim.x) group = blockDim.x;
+    for (int c0 = 0; c0 < ncols; c0 += group) {
+        const int gn = (ncols - c0) < group ? (ncols - c0) : group;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < gn * t; idx += blockDim.x) {
+            const int c = idx / t, i = idx - c * t;
+            xs[i * gn + c] = X[(size_t)(c0 + c) * ldc + (size_t)i * incx];
+        }
+        __syncthreads();
+        const int c = threadIdx.x;
+        if (c < gn) {
+            for (int i = 0; i < t; ++i) {   // L y = x
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = 0;
+                for (; k + 3 < i; k += 4) {
+                    a0 += LL[(size_t)k * t + i] * xs[k * gn + c];
+                    a1 += LL[(size_t)(k + 1) * t + i] * xs[(k + 1) * gn + c];
+                    a2 += LL[(size_t)(k + 2) * t + i] * xs[(k + 2) * gn + c];
+                    a3 += LL[(size_t)(k + 3) * t + i] * xs[(k + 3) * gn + c];
+                }
+                for (; k < i; ++k) a0 += LL[(size_t)k * t + i] * xs[k * gn + c];
+                xs[i * gn + c] = (xs[i * gn + c] - ((a0 + a1) + (a2 + a3))) / LL[(size_t)i * t + i];
+            }
+            for (int i = t - 1; i >= 0; --i) {   // L^T x = y
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = i + 1;
+                for (; k + 3 < t; k += 4) {
+                    a0 += LL[(size_t)i * t + k] * xs[k * gn + c];
+                    a1 += LL[(size_t)i * t + k + 1] * xs[(k + 1) * gn + c];
+                    a2 += LL[(size_t)i * t + k + 2] * xs[(k + 2) * gn + c];
+                    a3 += LL[(size_t)i * t + k + 3] * xs[(k + 3) * gn + c];
+                }
+                for (; k < t; ++k) a0 += LL[(size_t)i * t + k] * xs[k * gn + c];
+                xs[i * gn + c] = (xs[i * gn + c] - ((a0 + a1) + (a2 + a3))) / LL[(size_t)i * t + i];
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < gn * t; idx += blockDim.x) {
+            const int cc = idx / t, i = idx - cc * t;
+            X[(size_t)(c0 + cc) * ldc + (size_t)i * incx] = xs[i * gn + cc];
+        }
     }
+    __syncthreads();
 }
 
 // Projected GSVD of (G, M) (p x t and t x t) and RGen-L(R) selection of s_eff = min(s, t)
 // columns.  Output: Xs (t x s_eff, unit columns), VHs (t x s_eff, zero for filled slots),
-// mu (s_eff), info = {s_eff, rank_G, status}.  Scratch: sc (see sizes in the host).
+// mu (s_eff), info = {s_eff, rank_G, status}.  Scratch: sc (gsvd_scratch_doubles).
 // Route: Cholesky M = L L^T;  S = G M^{-1};
 //   p >= t: eigen of S^T S = V_H diag(mu^2) V_H^T; right vectors X ~ M^{-1} V_H;
-//   p <  t: eigen of S S^T (p x p) gives mu and V_H = S^T u / mu; null(G) from Householder QR
-//           of G^T; the remaining slots take the smallest Ritz pairs of N^T M N (Ritz-S).
-// Run the symmetric Jacobi solver on (A, V) (m x m, global scratch), staging both in LDS
-// when `lds` (2 m^2 doubles fit).
-__device__ void jacobi_staged(int m, double* A, double* V, double* cs, int* pairs, int lds) {
-    extern __shared__ double dyn_lds[];
-    if (!lds) {
-        jacobi_eigh(m, A, V, cs, pairs, 40);
-        return;
-    }
-    double* LA = dyn_lds;
-    double* LV = dyn_lds + (size_t)m * m;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) LA[idx] = A[idx];
-    __syncthreads();
-    jacobi_eigh(m, LA, LV, cs, pairs, 40);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-        A[idx] = LA[idx];
-        V[idx] = LV[idx];
-    }
-    __syncthreads();
-}
-
+//   p <  t: eigen of S S^T (p x p) gives mu and V_H = S^T u / mu; null(G) from the Householder
+//           QR G^T = Q R: the remaining slots take the smallest Ritz pairs of N^T M N with
+//           N = Q[:, p:], formed as the trailing block of Q^T M Q (Ritz-S).
 __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, const double* __restrict__ Min,
                                                        const double* __restrict__ G, double* sc, double* Xs,
-                                                       double* VHs, double* mu, int* info, int lds) {
+                                                       double* VHs, double* mu, int* info, int ldsd) {
     extern __shared__ double dyn_lds[];
-    __shared__ double cs[SD_NT];
-    __shared__ int pairs[SD_NT];
     __shared__ int s_rank;
     __shared__ double s_beta[64];
+    __shared__ double red[SD_NT / 64];
+    __shared__ double vv[EIG_MAX], pw[EIG_MAX];
     const int s_eff = s < t ? s : t;
-    const size_t T2 = (size_t)t * t, P2 = (size_t)p * p, PT = (size_t)p * t;
+    const size_t T2 = (size_t)t * t, P2 = (size_t)p * p, PT = (size_t)p * t, KM = T2 > P2 ? T2 : P2;
     double* L = sc;                 // t*t   Cholesky factor of sym(M)
     double* S = L + T2;             // p*t   G M^{-1}, column-major ld p
-    double* K = S + PT;             // t*t or p*p   S^T S  |  S S^T
-    double* Vv = K + T2 + P2;       // t*t or p*p   eigenvectors of K
-    double* GG = Vv + T2 + P2;      // p*p   G G^T
+    double* K = S + PT;             // S^T S (t*t) | S S^T (p*p)
+    double* Vv = K + KM;            // eigenvectors of K
+    double* GG = Vv + KM;           // p*p   G G^T
     double* GV = GG + P2;           // p*p
     double* Hv = GV + P2;           // t*p   Householder vectors of G^T
-    double* Nb = Hv + PT;           // t*t   basis of null(G)
-    double* Ms = Nb + T2;           // t*t   sym(M)
-    double* MN = Ms + T2;           // t*t   M N
-    double* B = MN + T2;            // t*t   N^T M N
-    double* BV = B + T2;            // t*t
-    int* order = reinterpret_cast<int*>(BV + T2);   // t + p ints
+    double* Ms = Hv + PT;           // t*t   sym(M), then Q^T M Q
+    double* BV = Ms + T2;           // (t-p)^2 eigenvectors of N^T M N
+    double* lamv = BV + T2;         // eigenvalues (t + p)
+    double* esc = lamv + t + p;     // eigensolver scratch: 5 t^2 + t
     for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
         const int j = idx / t, i = idx - j * t;
         const double v = 0.5 * (Min[(size_t)j * t + i] + Min[(size_t)i * t + j]);
@@ -375,12 +587,14 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
     }
     __syncthreads();
     {
-        double* LL = lds ? dyn_lds : L;   // factor in LDS, then copy back
-        if (lds)
+        const bool in_lds = (int)T2 <= ldsd;
+        double* LL = in_lds ? dyn_lds : L;
+        if (in_lds) {
             for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) LL[idx] = L[idx];
-        __syncthreads();
+            __syncthreads();
+        }
         const bool spd = chol_inplace(t, LL);
-        if (lds) {
+        if (in_lds) {
             for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) L[idx] = LL[idx];
             __syncthreads();
         }
@@ -393,60 +607,91 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
             return;
         }
     }
-    // S[k, :] = (M^{-1} G[k, :]^T)^T, one row per thread
-    for (int k = threadIdx.x; k < p; k += blockDim.x) {
-        double* row = S + k;   // stride p
-        for (int j = 0; j < t; ++j) row[(size_t)j * p] = G[(size_t)j * p + k];
-        for (int i = 0; i < t; ++i) {
-            double v = row[(size_t)i * p];
-            for (int q = 0; q < i; ++q) v -= L[(size_t)q * t + i] * row[(size_t)q * p];
-            row[(size_t)i * p] = v / L[(size_t)i * t + i];
-        }
-        for (int i = t - 1; i >= 0; --i) {
-            double v = row[(size_t)i * p];
-            for (int q = i + 1; q < t; ++q) v -= L[(size_t)i * t + q] * row[(size_t)q * p];
-            row[(size_t)i * p] = v / L[(size_t)i * t + i];
-        }
+    // p < t: S[k, :] = (M^{-1} G[k, :]^T)^T
+    if (p < t) {
+        for (int idx = threadIdx.x; idx < p * t; idx += blockDim.x) S[idx] = G[idx];
+        __syncthreads();
+        solve_cols(t, L, S, p, 1, p, ldsd);
     }
-    __syncthreads();
     int rankG;
+    bool ok = true;
     if (p >= t) {
-        for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
-            const int i = idx / t, j = idx - i * t;
-            double v = 0.0;
-            for (int k = 0; k < p; ++k) v += S[(size_t)i * p + k] * S[(size_t)j * p + k];
-            K[idx] = v;
-        }
-        __syncthreads();
-        jacobi_staged(t, K, Vv, cs, pairs, lds);
-        if (threadIdx.x == 0) {
-            for (int i = 0; i < t; ++i) order[i] = i;
-            for (int i = 1; i < t; ++i) {   // descending mu^2, stable
-                const int oi = order[i];
-                const double vi = K[oi * t + oi];
-                int j = i - 1;
-                while (j >= 0 && K[order[j] * t + order[j]] < vi) {
-                    order[j + 1] = order[j];
-                    --j;
+        // K = S^T S = M^{-1} (G^T G) M^{-1}.  G^T G from chunks of KC rows of G staged in LDS
+        // (2 x 2 output blocks per thread, at most 8 blocks per thread per pass over G)
+        constexpr int BPT = 8;
+        const int tb = (t + 1) / 2, nblk = tb * tb;
+        double* Sc = dyn_lds;   // KC x t, row k of the chunk at Sc[k * t]
+        for (int g0 = 0; g0 < nblk; g0 += BPT * SD_NT) {
+            double acc[BPT][4];
+#pragma unroll
+            for (int u = 0; u < BPT; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[u][q] = 0.0;
+            for (int k0 = 0; k0 < p; k0 += KC) {
+                const int kn = (p - k0) < KC ? (p - k0) : KC;
+                __syncthreads();
+                for (int idx = threadIdx.x; idx < kn * t; idx += blockDim.x) {
+                    const int j = idx / kn, k = idx - j * kn;
+                    Sc[k * t + j] = G[(size_t)j * p + k0 + k];
                 }
-                order[j + 1] = oi;
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < BPT; ++u) {
+                    const int b = g0 + threadIdx.x + u * SD_NT;
+                    if (b < nblk) {
+                        const int bi = 2 * (b / tb), bj = 2 * (b % tb);
+                        const bool i1 = bi + 1 < t, j1 = bj + 1 < t;
+                        for (int k = 0; k < kn; ++k) {
+                            const double* sr = Sc + k * t;
+                            const double a0 = sr[bi], a1 = i1 ? sr[bi + 1] : 0.0;
+                            const double b0 = sr[bj], b1 = j1 ? sr[bj + 1] : 0.0;
+                            acc[u][0] += a0 * b0;
+                            acc[u][1] += a0 * b1;
+                            acc[u][2] += a1 * b0;
+                            acc[u][3] += a1 * b1;
+                        }
+                    }
+                }
             }
-            s_rank = t;
+#pragma unroll
+            for (int u = 0; u < BPT; ++u) {
+                const int b = g0 + threadIdx.x + u * SD_NT;
+                if (b < nblk) {
+                    const int bi = 2 * (b / tb), bj = 2 * (b % tb);
+                    K[(size_t)bi * t + bj] = acc[u][0];
+                    if (bj + 1 < t) K[(size_t)bi * t + bj + 1] = acc[u][1];
+                    if (bi + 1 < t) K[(size_t)(bi + 1) * t + bj] = acc[u][2];
+                    if (bi + 1 < t && bj + 1 < t) K[(size_t)(bi + 1) * t + bj + 1] = acc[u][3];
+                }
+            }
         }
         __syncthreads();
-        rankG = s_rank;
+        solve_cols(t, L, K, t, t, 1, ldsd);   // Y = M^{-1} G^T G (columns of Y at K + c t)
+        solve_cols(t, L, K, t, 1, t, ldsd);   // K = M^{-1} Y^T (columns of Y^T: rows of Y)
+        for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {   // symmetrise
+            const int i = idx / t, j = idx - i * t;
+            if (i < j) {
+                const double v = 0.5 * (K[idx] + K[(size_t)j * t + i]);
+                K[idx] = v;
+                K[(size_t)j * t + i] = v;
+            }
+        }
+        __syncthreads();
+        // all eigenvalues of K (ascending), vectors of the s_eff largest
+        eig_range(t, K, t - s_eff, t, lamv, Vv, esc, ldsd);
+        rankG = t;
+        for (int idx = threadIdx.x; idx < s_eff * t; idx += blockDim.x) {
+            const int c = idx / t, i = idx - c * t;
+            const double v = Vv[(size_t)(s_eff - 1 - c) * t + i];   // c-th largest
+            VHs[(size_t)c * t + i] = v;
+            Xs[(size_t)c * t + i] = v;
+        }
         for (int c = threadIdx.x; c < s_eff; c += blockDim.x) {
-            const int o = order[c];
-            const double lam = K[o * t + o];
+            const double lam = lamv[t - 1 - c];
             mu[c] = lam > 0.0 ? sqrt(lam) : 0.0;
-            double* x = Xs + (size_t)c * t;
-            for (int i = 0; i < t; ++i) {
-                VHs[(size_t)c * t + i] = Vv[i * t + o];
-                x[i] = Vv[i * t + o];
-            }
-            chol_solve(t, L, x);
         }
         __syncthreads();
+        solve_cols(t, L, Xs, s_eff, t, 1, ldsd);
     } else {
         for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
             const int i = idx / p, j = idx - i * p;
@@ -459,40 +704,29 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
             GG[idx] = w;
         }
         __syncthreads();
-        jacobi_staged(p, K, Vv, cs, pairs, lds);
-        jacobi_staged(p, GG, GV, cs, pairs, lds);
+        double* lamg = lamv + t;
+        eig_range(p, GG, 0, 0, lamg, GV, esc, ldsd);   // singular values of G (squared)
+        eig_range(p, K, 0, p, lamv, Vv, esc, ldsd);    // S S^T: all pairs, ascending
         if (threadIdx.x == 0) {
-            double mx2 = 0.0;
-            for (int i = 0; i < p; ++i) mx2 = fmax(mx2, GG[i * p + i]);
+            const double mx2 = fmax(lamg[p - 1], 0.0);
             int r = 0;
             for (int i = 0; i < p; ++i)
-                if (GG[i * p + i] > 1e-16 * mx2) ++r;   // singular values of G above 1e-8 of the largest
+                if (lamg[i] > 1e-16 * mx2) ++r;   // singular values of G above 1e-8 of the largest
             s_rank = r;
-            for (int i = 0; i < p; ++i) order[i] = i;
-            for (int i = 1; i < p; ++i) {
-                const int oi = order[i];
-                const double vi = K[oi * p + oi];
-                int j = i - 1;
-                while (j >= 0 && K[order[j] * p + order[j]] < vi) {
-                    order[j + 1] = order[j];
-                    --j;
-                }
-                order[j + 1] = oi;
-            }
         }
         __syncthreads();
         rankG = s_rank;
         const int kg = s_eff < rankG ? s_eff : rankG;
         for (int c = threadIdx.x; c < kg; c += blockDim.x) {
-            const int o = order[c];
-            const double lam = K[o * p + o];
+            const int o = p - 1 - c;   // c-th largest
+            const double lam = lamv[o];
             mu[c] = lam > 0.0 ? sqrt(lam) : 0.0;
             double* vh = VHs + (size_t)c * t;
             double* x = Xs + (size_t)c * t;
             double nrm = 0.0;
             for (int i = 0; i < t; ++i) {
                 double v = 0.0;
-                for (int k = 0; k < p; ++k) v += S[(size_t)i * p + k] * Vv[k * p + o];
+                for (int k = 0; k < p; ++k) v += S[(size_t)i * p + k] * Vv[(size_t)o * p + k];
                 vh[i] = v;
                 nrm += v * v;
             }
@@ -501,9 +735,9 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
                 vh[i] /= nrm;
                 x[i] = vh[i];
             }
-            chol_solve(t, L, x);
         }
         __syncthreads();
+        solve_cols(t, L, Xs, kg, t, 1, ldsd);
         const int nfill = s_eff - kg;
         if (nfill > 0 && p <= 64) {
             const int nn = t - p;
@@ -531,56 +765,61 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
                 }
             }
             __syncthreads();
-            for (int c = threadIdx.x; c < nn; c += blockDim.x) {   // N = Q[:, p:]
-                double* col = Nb + (size_t)c * t;
-                for (int i = 0; i < t; ++i) col[i] = (i == p + c) ? 1.0 : 0.0;
-                for (int j = p - 1; j >= 0; --j) {
-                    const double* v = Hv + (size_t)j * t;
-                    double d = 0.0;
-                    for (int i = j; i < t; ++i) d += v[i] * col[i];
-                    for (int i = j; i < t; ++i) col[i] -= s_beta[j] * d * v[i];
+            // Q^T M Q = H_{p-1} ... H_0 M H_0 ... H_{p-1}; its trailing block is N^T M N
+            {
+                const bool in_lds = (int)T2 <= ldsd;
+                double* MM = in_lds ? dyn_lds : Ms;   // row-major (M symmetric)
+                if (in_lds) {
+                    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) MM[idx] = Ms[idx];
+                    __syncthreads();
                 }
-            }
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < t * nn; idx += blockDim.x) {
-                const int c = idx / t, i = idx - c * t;
-                double v = 0.0;
-                for (int k = 0; k < t; ++k) v += Ms[(size_t)k * t + i] * Nb[(size_t)c * t + k];
-                MN[idx] = v;
-            }
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < nn * nn; idx += blockDim.x) {
-                const int i = idx / nn, j = idx - i * nn;
-                double v = 0.0;
-                for (int k = 0; k < t; ++k) v += Nb[(size_t)i * t + k] * MN[(size_t)j * t + k];
-                B[idx] = v;
-            }
-            __syncthreads();
-            jacobi_staged(nn, B, BV, cs, pairs, lds);
-            if (threadIdx.x == 0) {
-                for (int i = 0; i < nn; ++i) order[i] = i;
-                for (int i = 1; i < nn; ++i) {   // ascending Ritz values
-                    const int oi = order[i];
-                    const double vi = B[oi * nn + oi];
-                    int j = i - 1;
-                    while (j >= 0 && B[order[j] * nn + order[j]] > vi) {
-                        order[j + 1] = order[j];
-                        --j;
+                const int tid = threadIdx.x, bs = blockDim.x;
+                for (int j = 0; j < p; ++j) {
+                    const double beta = s_beta[j];
+                    if (beta == 0.0) continue;
+                    for (int i = tid; i < t; i += bs) vv[i] = Hv[(size_t)j * t + i];
+                    __syncthreads();
+                    double pv = 0.0;
+                    for (int i = tid; i < t; i += bs) {
+                        const double* row = MM + (size_t)i * t;
+                        double acc = 0.0;
+                        for (int q = 0; q < t; ++q) acc += row[q] * vv[q];
+                        const double pi = beta * acc;
+                        pw[i] = pi;
+                        pv += pi * vv[i];
                     }
-                    order[j + 1] = oi;
+                    const double Kc = 0.5 * beta * sd_sum(pv, red);
+                    __syncthreads();
+                    for (int i = tid; i < t; i += bs) pw[i] -= Kc * vv[i];
+                    __syncthreads();
+                    for (int idx = tid; idx < t * t; idx += bs) {
+                        const int r = idx / t, c = idx - r * t;
+                        MM[idx] -= vv[r] * pw[c] + pw[r] * vv[c];
+                    }
+                    __syncthreads();
                 }
+                // B = trailing nn x nn block, into K (row-major)
+                for (int idx = threadIdx.x; idx < nn * nn; idx += blockDim.x) {
+                    const int r = idx / nn, c = idx - r * nn;
+                    K[idx] = MM[(size_t)(p + r) * t + (p + c)];
+                }
+                __syncthreads();
             }
-            __syncthreads();
+            eig_range(nn, K, 0, nfill, lamv, BV, esc, ldsd);   // the nfill smallest Ritz pairs
+            // fill vectors x = N y = Q [0; y]: apply H_{p-1}, ..., H_0 to [0; y]
             for (int f = threadIdx.x; f < nfill; f += blockDim.x) {
                 const int c = kg + f;
-                const int o = order[f];
                 mu[c] = 0.0;
                 double* x = Xs + (size_t)c * t;
                 for (int i = 0; i < t; ++i) {
-                    double v = 0.0;
-                    for (int k = 0; k < nn; ++k) v += Nb[(size_t)k * t + i] * BV[k * nn + o];
-                    x[i] = v;
+                    x[i] = i < p ? 0.0 : BV[(size_t)f * nn + (i - p)];
                     VHs[(size_t)c * t + i] = 0.0;
+                }
+                for (int j = p - 1; j >= 0; --j) {
+                    const double* v = Hv + (size_t)j * t;
+                    double d = 0.0;
+                    for (int i = j; i < t; ++i) d += v[i] * x[i];
+                    for (int i = j; i < t; ++i) x[i] -= s_beta[j] * d * v[i];
                 }
             }
             __syncthreads();
@@ -597,13 +836,14 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
     if (threadIdx.x == 0) {
         info[0] = s_eff;
         info[1] = rankG;
-        info[2] = BL_OK;
+        info[2] = ok ? BL_OK : BL_E_BREAKDOWN;
     }
 }
 
 size_t gsvd_scratch_doubles(int t, int p) {
-    const size_t T2 = (size_t)t * t, P2 = (size_t)p * p, PT = (size_t)p * t;
-    return T2 + PT + 2 * (T2 + P2) + 2 * P2 + PT + 6 * T2 + (t + p) + 64;
+    const size_t T2 = (size_t)t * t, P2 = (size_t)p * p, PT = (size_t)p * t, KM = T2 > P2 ? T2 : P2;
+    const size_t m = t > p ? t : p;
+    return T2 + PT + 2 * KM + 2 * P2 + PT + 2 * T2 + (t + p) + 5 * m * m + m + 64;
 }
 
 // Largest dynamic LDS per workgroup, queried once (falls back to 64 KiB).
@@ -615,7 +855,7 @@ static size_t lds_limit() {
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
             lim = (size_t)v;
-        lim -= 16384;   // room for the kernels' static LDS
+        lim -= 24576;   // room for the kernels' static LDS (k_gsvd_select: about 18 KiB)
     }
     return lim;
 }
@@ -633,14 +873,14 @@ hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int*
 
 hipError_t launch_gsvd_select(int t, int p, int s, const double* M, const double* G, double* sc, double* Xs,
                               double* VHs, double* mu, int* info, hipStream_t stream) {
-    // Jacobi problems are at most t x t (t x t for p >= t; p x p and (t-p) x (t-p) otherwise)
-    const int m = t;
-    const size_t bytes = 2 * (size_t)m * m * sizeof(double);
-    const int lds = bytes <= lds_limit() ? 1 : 0;
-    if (lds && bytes > 65536)
+    // dynamic LDS: the eigensolver's matrix plus its vectors, the solves' factor plus columns;
+    // at least the S^T S chunk
+    const size_t want = std::max((size_t)3 * t * t + (size_t)6 * t * t, (size_t)KC * t) * sizeof(double);
+    const size_t bytes = std::min(want, lds_limit()) / sizeof(double) * sizeof(double);
+    if (bytes > 65536)
         (void)hipFuncSetAttribute((const void*)k_gsvd_select, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), lds ? bytes : 0, stream, t, p, s, M, G, sc, Xs, VHs, mu,
-                       info, lds);
+    hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), bytes, stream, t, p, s, M, G, sc, Xs, VHs, mu, info,
+                       (int)(bytes / sizeof(double)));
     return hipGetLastError();
 }
 
