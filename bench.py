@@ -70,7 +70,7 @@ def apply_bytes_per_pixel(reg: str, prec: str, s: int, nf: int) -> int:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("stencil.h", "common.h", "batch.hip"):
+    for f in ("tile.h", "common.h", "batch.hip"):
         with open(os.path.join(ROOT, "paper_2412_08264_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -91,12 +91,17 @@ def measured_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def roofline(kernel, total_bytes, kt, workload, launches_for_traffic=None):
+KT_SAMPLE = 8   # the library records kernel events on one Krylov step in eight
+
+
+def roofline(kernel, bytes_per_launch, kt, workload):
+    """Achieved HBM rate of the apply kernel: algorithmic bytes per launch over its mean duration,
+    the duration from HIP events the library records around sampled launches of the timed run."""
     apply_ms = kt[0] / max(kt[1], 1.0)
-    achieved = total_bytes / max(kt[0] * 1e-3, 1e-30) / 1e9
+    achieved = bytes_per_launch / max(apply_ms * 1e-3, 1e-30) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s", "frac": achieved / HBM_PEAK,
             "traffic": measured_traffic(kernel, workload), "kernel": kernel, "avg_launch_us": apply_ms * 1e3,
-            "launches": int(kt[1]), "algorithmic_bytes_per_launch": total_bytes / max(kt[1], 1.0),
+            "timed_launches": int(kt[1]), "algorithmic_bytes_per_launch": bytes_per_launch,
             "update_avg_us": kt[2] / max(kt[3], 1.0) * 1e3}
 
 
@@ -296,9 +301,7 @@ def bench_sequence(args, B, torch, synth):
     iters_seq = sum(r["iters"] for r in head)
     prec = "mixed" if mixed else "fp64"
     bpp = apply_bytes_per_pixel(wl.reg, prec, wl.s, wl.n_filters)
-    # every timed pass runs the same iterations: algorithmic bytes of all apply launches
-    total_bytes = bpp * wl.n * iters_seq * args.steps
-    kname = f"k_b_apply<{'float' if mixed else 'double'},{wl.blur_radius}>"
+    kname = f"k_b_apply<{'float' if mixed else 'double'}, {wl.blur_radius}, {0 if wl.reg == 'tv' else 1}>"
     desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
             f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
             f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad|"
@@ -311,7 +314,7 @@ def bench_sequence(args, B, torch, synth):
                     max_rel_err=max(r["err"] for r in head),
                     speedup_vs_plain_cg=value / extra["plain"]["solves_per_s"],
                     plain_cg=extra["plain"], rgen_resid=extra["rgen_res"],
-                    roofline=roofline(kname, total_bytes, kt, args.workload))
+                    roofline=roofline(kname, bpp * wl.n, kt, args.workload))
     if mixed:
         out["rgen_hg_fp64"] = extra["rgen_hg_fp64"]
     if not args.no_cpu:
@@ -378,6 +381,8 @@ def bench_batch(args, B, torch, synth):
     recs = [B.Recycle(w.n, 20, V_CAP, dev) for w in wls]
     arena = int(lib_batched_bytes(B, Ps, [20] * len(Ps)) * 1.02)
     eng = B.Engine(cap=min(len(Ps), 64), arena_bytes=arena, device=dev, ctx=ctx.ctx)
+    # refreshes and hypergradients of the images run concurrently on a pool of contexts
+    pool = B.ContextPool(P64, 20, V_CAP, args.workers, dev)
 
     def one_pass(mode, thr, stats=None):
         """The sequence once: mode 'rgen_hg' (refresh + error-estimate stop), 'plain' (residual)."""
@@ -390,8 +395,8 @@ def bench_batch(args, B, torch, synth):
         for i in range(T):
             xh = xhats[i]
             if mode != "plain" and i > 0:
-                for k, P in enumerate(P64):
-                    ctx.refresh_p(P, recs[k], thetas[i], xh[k], s=20)
+                pool.map(lambda c, k: c.refresh_p(P64[k], recs[k], thetas[i], xh[k], s=20),
+                         [(k,) for k in range(len(P64))])
             slot_of = {}
             for k, P in enumerate(Ps):
                 use_hg = mode == "rgen_hg" and recs[k].rs.s_cur > 0 and prev[k] is not None
@@ -408,7 +413,8 @@ def bench_batch(args, B, torch, synth):
                     iters.append(st.iters)
                     if stats is not None:
                         stats.append((k, st.iters))
-            hg = [ctx.hypergradient_p(P, thetas[i], xh[k], ws[k]) for k, P in enumerate(P64)]
+            hg = pool.map(lambda c, k: c.hypergradient_p(P64[k], thetas[i], xh[k], ws[k]),
+                          [(k,) for k in range(len(P64))])
             for k in range(len(Ps)):
                 prev[k] = float(np.linalg.norm(hg[k]))
                 errs.append(rel_err(hg[k], refs[i][k]))
@@ -441,6 +447,7 @@ def bench_batch(args, B, torch, synth):
     ok = sum(1 for e in allerr if e <= 1e-6)
     value = ok / el
     total_bytes = sum(apply_bytes_per_pixel("filters", prec, 20, nf) * wls[k].n * it for k, it in stats)
+    launches = max(kt[1] * KT_SAMPLE, 1.0)   # apply launches of the timed passes (sampled 1 in 8)
     one_pass("plain", chosen["plain"])
     torch.cuda.synchronize()
     tp = time.perf_counter()
@@ -452,7 +459,7 @@ def bench_batch(args, B, torch, synth):
     torch.cuda.synchronize()
     elp = time.perf_counter() - tp
     okp = sum(1 for e in perr if e <= 1e-6)
-    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'},5>"
+    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'}, 5, 1>"
     out = base_line(args, value, el, "f32+f64" if prec == "mixed" else "f64",
                     {"workload": f"batch{len(wls)}: {len(wls)} filter images (8 x 7x7, blur r=5 sigma=3, noise 0.02), "
                                  f"sides {sorted(set(w.h for w in wls))}, sum n = {sum(w.n for w in wls)}, shared theta, "
@@ -462,11 +469,12 @@ def bench_batch(args, B, torch, synth):
                     iters_per_pass={"rgen_hg": sum(alliters) // args.steps, "plain": sum(piters) // args.steps},
                     plain_cg={"solves_per_s": okp / elp, "threshold": chosen["plain"], "passing": f"{okp}/{len(perr)}"},
                     speedup_vs_plain_cg=value / max(okp / elp, 1e-30),
-                    roofline=roofline(kname, total_bytes, kt, "batch64"))
+                    roofline=roofline(kname, total_bytes / launches, kt, "batch64"))
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline_batch(wls)
     eng.close()
+    pool.close()
     ctx.close()
     return out
 
@@ -533,11 +541,12 @@ def bench_serve(args, B, torch, synth):
         data.append((path, xhats, xs))
     log(f"[bench] frozen steps built in {time.perf_counter() - tt:.1f} s")
     arrivals = synth.poisson_arrivals(args.rate, args.warm_s + args.duration, len(wls), seed=5001)
+    pool = B.ContextPool(P64, max(w.s for w in wls), args.v_cap, args.workers, dev)
     modes = {}
     for prec in ("mixed", "fp64"):
         Ps = [B.problem_from(wl, prec=prec) for wl in wls]
         arena = sum(B.Engine.slot_bytes(P, wl.s) for P, wl in zip(Ps, wls))
-        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel)
+        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, pool=pool)
         for k, (wl, P) in enumerate(zip(wls, Ps)):
             path, xhats, xs = data[k]
             srv.add_sample(serve.Sample(k, P, path, xhats, xs, wl.s, args.v_cap, dev))
@@ -560,7 +569,7 @@ def bench_serve(args, B, torch, synth):
                     time.sleep(max(0.0, min(arrivals[i][0] - now, 1e-3)))
                 continue
             srv.turn()
-        backlog = len(srv.queue) + len(srv.running)
+        backlog = len(srv.queue) + len(srv.preparing) + len(srv.ready) + len(srv.running) + len(srv.finishing)
         kt = ctx.kernel_times(reset=True)
         ctx.set_timing(0)
         win = [r for r in srv.completed if r.t_arrival >= args.warm_s]
@@ -582,6 +591,7 @@ def bench_serve(args, B, torch, synth):
         bpp = lambda smp: apply_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec, smp.s,
                                                 smp.P.n_filters)
         total_bytes = sum(bpp(r.sample) * r.sample.P.h * r.sample.P.w * r.stats.iters for r in srv.completed)
+        launches = max(kt[1] * KT_SAMPLE, 1.0)
         modes[prec] = {"solves_per_s": ok / args.duration, "completed": len(win), "passing": f"{ok}/{len(win)}",
                        "arrived": sum(1 for a in arrivals if args.warm_s <= a[0] < end),
                        "backlog_at_end": backlog,
@@ -589,7 +599,7 @@ def bench_serve(args, B, torch, synth):
                                       "p99": float(np.percentile(lat, 99)) if lat else None},
                        "max_rel_err": max(errs) if errs else None,
                        "mean_iters": float(np.mean([r.stats.iters for r in win])) if win else None,
-                       "roofline": roofline("k_b_apply<*> (all classes)", total_bytes, kt, "serve")}
+                       "roofline": roofline("k_b_apply<*> (all classes)", total_bytes / launches, kt, "serve")}
         log(f"[bench] serve {prec}: {modes[prec]['solves_per_s']:.1f} solves/s, p50 "
             f"{modes[prec]['latency_ms']['p50']} ms, p99 {modes[prec]['latency_ms']['p99']} ms, backlog {backlog}")
         srv.close()
@@ -607,6 +617,7 @@ def bench_serve(args, B, torch, synth):
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline_serve(wls, data_steps=T)
+    pool.close()
     ctx.close()
     return out
 
@@ -722,6 +733,8 @@ def main():
     ap.add_argument("--outer", type=int, default=0, help="override the number of outer steps")
     ap.add_argument("--batch", type=int, default=64, help="batch64: number of images")
     ap.add_argument("--prec", default="mixed", choices=("mixed", "fp64"), help="batch64: precision")
+    ap.add_argument("--workers", type=int, default=8, help="batch64 / serve: contexts (streams) for refreshes "
+                    "and hypergradients running beside the engine")
     ap.add_argument("--samples", type=int, default=64, help="serve: resident samples (of the 256-sample recipe)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured window (s)")

@@ -163,12 +163,13 @@ bl_status bl_lower_grad(bl_ctx* ctx, const bl_problem* P, const double* theta_ho
                         const double* x, double* grad, double* phi_host, void* ws, size_t ws_bytes);
 
 /* Time the phases of subsequent calls with HIP events (stats->ms), 0/1.  With 2, also record
- * HIP events around every launch of the Krylov apply and update kernels (see bl_kernel_times). */
+ * HIP events around the apply and update launches of every eighth Krylov step (see
+ * bl_kernel_times); sampling keeps the events' own cost out of the run they measure. */
 bl_status bl_set_timing(bl_ctx* ctx, int enable);
 
 /* Per-kernel durations accumulated over solves since the last reset, iterations that ran
- * only: out4[0] = total ms of the apply kernel (H p fused with p.q and C^T q), out4[1] =
- * its launch count, out4[2] / out4[3] = the same for the update kernel (w, r, r.r, Z^T r).
+ * only, over the sampled steps: out4[0] = total ms of the apply launches (H p fused with p.q
+ * and C^T q), out4[1] = their count, out4[2] / out4[3] = the same for the update kernel.
  * reset != 0 clears the totals after reading. */
 bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
 

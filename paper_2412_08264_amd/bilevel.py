@@ -431,3 +431,47 @@ def hessian_solve_batched(problems, thetas, xhats, gs, ws_, recs, opts: bl_solve
     finally:
         if own:
             bl_destroy(ctx)
+
+
+class ContextPool:
+    """Several contexts, each with its own HIP stream (default priority) and workspace, driven by
+    as many host threads: independent per-sample calls (refreshes, hypergradients, lower solves)
+    run concurrently on the GPU.  Every call synchronises its own stream before it returns, so a
+    result is complete when its future is."""
+
+    def __init__(self, problems, s_max: int, v_cap: int, workers: int, device=None):
+        import queue
+        from concurrent.futures import ThreadPoolExecutor
+
+        import torch
+        device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ctxs = [Context(problems, s_max, v_cap, device, stream=torch.cuda.Stream(device)) for _ in range(workers)]
+        self._free = queue.Queue()
+        for c in self.ctxs:
+            self._free.put(c)
+        self._ex = ThreadPoolExecutor(max_workers=workers)
+
+    def submit(self, fn, *args):
+        """fn(context, *args) on a free context; returns a future."""
+        def run():
+            c = self._free.get()
+            try:
+                return fn(c, *args)
+            finally:
+                self._free.put(c)
+        return self._ex.submit(run)
+
+    def map(self, fn, arg_tuples) -> list:
+        futs = [self.submit(fn, *a) for a in arg_tuples]
+        return [f.result() for f in futs]
+
+    def close(self):
+        self._ex.shutdown(wait=True)
+        for c in self.ctxs:
+            c.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
 // A stopped slot's blocks leave after the record reduction (its flag is read by one thread
 // and published by the reduction's barrier: uniform per block; a flag set by block 0 during
 // this launch follows from the same decision every block of the slot takes).
-constexpr int CPRE = 8;   // columns of C per pixel loaded before the stencil
+constexpr int CPRE = 8;   // columns of C per pixel loaded before the (short) TV stencil
 template <typename T, int R, int CLS>
 __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
     using L = QLayout<T, R, CLS>;
@@ -193,14 +193,17 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     int r0, c0;
     slot_tile(sl, m.y, r0, c0);
     const Own o = own_pixels(S.h, S.w, r0, c0);
-    double ri[QR], pi[QR], cpre[CPRE][QR];
+    // the filter stencil is long enough to hide the C loads issued after it, and the registers
+    // of a prefetch would cost occupancy there
+    constexpr int CP = CLS == TC_TV ? CPRE : 1;
+    double ri[QR], pi[QR], cpre[CP][QR];
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
         ri[k] = o.in[k] ? r[o.g[k]] : 0.0;
         pi[k] = (o.in[k] && !first) ? p_old[o.g[k]] : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < CPRE; ++c)
+    for (int c = 0; c < CP; ++c)
 #pragma unroll
         for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * S.n + o.g[k]] : 0.0;
     q_stage<T, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0,
@@ -232,9 +235,9 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
                 return acc;
             }
             const int c = k - 1;
-            if (c < CPRE) {
+            if (c < CP) {
 #pragma unroll
-                for (int cc = 0; cc < CPRE; ++cc)
+                for (int cc = 0; cc < CP; ++cc)
                     if (cc == c) {
 #pragma unroll
                         for (int u = 0; u < QR; ++u) acc += cpre[cc][u] * qq[u];

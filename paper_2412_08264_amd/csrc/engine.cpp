@@ -343,8 +343,9 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
     slots = run_list;
     id = chunk_id++;
     const int buf = (int)(id & 1);
-    const bool ktime = c->timing == 2;
     for (int k = 0; k < POLL && steps_done < max_steps; ++k) {
+        // per-kernel events on one step in KT_SAMPLE: the events themselves cost time
+        const bool ktime = c->timing == 2 && step % KT_SAMPLE == 0;
         {   // scheduled replacements (mixed precision): before the test of every rr_every-th iteration
             std::vector<int> rr;
             for (int i : run_list) {
@@ -363,7 +364,7 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
             ev = 3 * (int)timed.size();
             while ((int)c->kev.size() < ev + 3) {
                 hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
+                HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                 c->kev.push_back(e);
             }
             HIPCHK(hipEventRecord(c->kev[ev], c->stream));

@@ -41,6 +41,7 @@ struct bl_ctx {
 namespace blh {
 
 constexpr int POLL = 8;              // iterations launched between host polls of the stop flags
+constexpr int KT_SAMPLE = 8;         // timing mode 2: kernel events on every KT_SAMPLE-th step
 // Consumer kernels re-reduce the producer's per-block records in every block; above this many
 // record values a one-block kernel first folds them into one record (keeps the re-reads linear).
 constexpr long REC_LIMIT = 8192;

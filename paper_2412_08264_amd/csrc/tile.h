@@ -244,22 +244,34 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
             constexpr int FS = 7, F = 3, F2 = 49;
             for (int j0 = 0; j0 < nf; j0 += NFG) {
                 __syncthreads();   // the previous readers of the tb space are done
-                // t_j = lambda_j phi''_j (K_j v) on THF x TWF, strips of 2 rows
+                // t_j = lambda_j phi''_j (K_j v) on THF x TWF, strips of 2 rows; the phi'' values of
+                // the next strip are loaded while the current one is computed
                 constexpr int NS = (G::THF + 1) / 2;
-                for (int q = threadIdx.x; q < NS * G::TWF; q += NT) {
+                auto load_d2 = [&](int q, T (&dst)[NFG][2]) {
                     const int sidx = q / G::TWF, cc = q - sidx * G::TWF, rb = 2 * sidx;
-                    T d2v[NFG][2];
                     const int gj = c0 - F + cc;
 #pragma unroll
                     for (int k = 0; k < 2; ++k) {
                         const int gi = r0 - F + rb + k;
-                        const bool in = rb + k < G::THF && gi >= 0 && gi < h && gj >= 0 && gj < w;
+                        const bool in = q < NS * G::TWF && rb + k < G::THF && gi >= 0 && gi < h && gj >= 0 && gj < w;
 #pragma unroll
                         for (int jj = 0; jj < NFG; ++jj)
-                            d2v[jj][k] = (in && j0 + jj < nf)
+                            dst[jj][k] = (in && j0 + jj < nf)
                                              ? d2_at<T>(S, (size_t)(j0 + jj) * S.n + (size_t)gi * w + gj)
                                              : T(0);
                     }
+                };
+                T d2n[NFG][2];
+                load_d2(threadIdx.x, d2n);
+                for (int q = threadIdx.x; q < NS * G::TWF; q += NT) {
+                    const int sidx = q / G::TWF, cc = q - sidx * G::TWF, rb = 2 * sidx;
+                    T d2v[NFG][2];
+#pragma unroll
+                    for (int jj = 0; jj < NFG; ++jj) {
+                        d2v[jj][0] = d2n[jj][0];
+                        d2v[jj][1] = d2n[jj][1];
+                    }
+                    load_d2(q + NT, d2n);
                     T win[2 + FS - 1][FS];
 #pragma unroll
                     for (int u = 0; u < 2 + FS - 1; ++u)

@@ -44,7 +44,7 @@ class Sample:
 
 
 class Request:
-    __slots__ = ("sample", "t_arrival", "step", "t_start", "t_done", "slot", "hg", "stats", "g")
+    __slots__ = ("sample", "t_arrival", "step", "t_start", "t_done", "slot", "hg", "stats", "g", "fut", "opts")
 
     def __init__(self, sample, t_arrival):
         self.sample = sample
@@ -55,13 +55,17 @@ class Request:
         self.hg = None
         self.stats = None
         self.g = None
+        self.fut = None
+        self.opts = None
 
 
 class Server:
-    """Continuous-batching server over resident samples (one context, one engine, one stream)."""
+    """Continuous-batching server over resident samples: one engine (on the context's stream)
+    for the solves; refreshes and hypergradients on `pool` (a ContextPool: other streams,
+    other host threads) so that they overlap the engine's iterations, or inline without one."""
 
     def __init__(self, ctx: B.Context, cap: int, arena_bytes: int, hg_rel: float = 1e-9, tol: float = 1e-10,
-                 rr_every: int = 50, iters_per_turn: int = 16, clock=time.perf_counter):
+                 rr_every: int = 50, iters_per_turn: int = 16, clock=time.perf_counter, pool=None):
         self.ctx = ctx
         self.engine = B.Engine(cap=cap, arena_bytes=arena_bytes, device=ctx.device, ctx=ctx.ctx)
         self.hg_rel = hg_rel
@@ -69,9 +73,13 @@ class Server:
         self.rr_every = rr_every
         self.iters_per_turn = iters_per_turn
         self.clock = clock
+        self.pool = pool
         self.samples = {}
-        self.queue = collections.deque()
-        self.running = {}
+        self.queue = collections.deque()   # arrived, not started
+        self.preparing = []                # refresh submitted
+        self.ready = collections.deque()   # refreshed, waiting for engine room
+        self.running = {}                  # slot -> request
+        self.finishing = []                # hypergradient submitted
         self.completed = []
 
     def add_sample(self, sample: Sample):
@@ -83,71 +91,98 @@ class Server:
     def submit(self, key, t_arrival: float):
         self.queue.append(Request(self.samples[key], t_arrival))
 
-    def _start(self, req: Request) -> bool:
-        """Refresh and admit; False (nothing changed) when the engine has no room."""
+    def _run(self, fn, *args):
+        if self.pool is None:
+            fn(self.ctx, *args)
+            return None
+        return self.pool.submit(fn, *args)
+
+    # ---- stages
+    def _prepare(self, req: Request):
+        """Refresh the sample's recycle space for its next outer step (an empty space at the
+        start of a pass over the sample's steps) and fix the solve options."""
         smp = req.sample
         step = smp.step % len(smp.thetas)
-        if step == 0:   # a new pass over the sample's outer steps starts from an empty space
+        req.step = step
+        if step == 0:
             smp.rec.rs.s_cur = 0
             smp.rec.rs.v_cur = 0
             smp.prev_hg = None
             smp.w.zero_()
-        need = B.Engine.slot_bytes(smp.P, smp.s if step > 0 else 0)
-        _, free_slots, _, largest = self.engine.query()
-        if free_slots == 0 or largest < need:
-            return False
-        th, xh = smp.thetas[step], smp.xhats[step]
+        req.t_start = self.clock()
         if step > 0:
-            self.ctx.refresh_p(smp.P64, smp.rec, th, xh, s=smp.s)
+            req.fut = self._run(lambda c, P, rec, th, xh, s: c.refresh_p(P, rec, th, xh, s=s),
+                                smp.P64, smp.rec, smp.thetas[step], smp.xhats[step], smp.s)
+
+    def _admit(self, req: Request) -> bool:
+        smp = req.sample
         use_hg = smp.rec.rs.s_cur > 0 and smp.prev_hg is not None
         opts = B.solve_opts(stop="hgerr" if use_hg else "resid", hg_tol=self.hg_rel * smp.prev_hg if use_hg else 0.0,
                             tol=self.tol, store_basis=True, rr_every=self.rr_every)
+        xh = smp.xhats[req.step]
         req.g = xh - smp.xstar
-        slot = self.engine.admit(smp.P, th, xh, req.g, smp.w, smp.rec, opts)
-        if slot is None:   # the refresh changed s_cur: retry later
+        slot = self.engine.admit(smp.P, smp.thetas[req.step], xh, req.g, smp.w, smp.rec, opts)
+        if slot is None:
             return False
-        req.step = step
         req.slot = slot
-        req.t_start = self.clock()
-        smp.busy = True
         self.running[slot] = req
         return True
 
-    def admit_waiting(self):
-        """Start queued requests whose sample is idle, in arrival order, as far as room allows."""
+    def _complete(self, req: Request):
+        smp = req.sample
+        req.t_done = self.clock()
+        smp.prev_hg = float(np.linalg.norm(req.hg))
+        smp.step += 1
+        smp.busy = False
+        self.completed.append(req)
+
+    def turn(self):
+        """Start refreshes of queued requests whose sample is idle; admit refreshed ones while the
+        engine has room; advance the engine a few iterations; finish completed solves."""
+        out = []
         blocked = set()
         for req in list(self.queue):
             smp = req.sample
             if smp.busy or smp.key in blocked:
                 blocked.add(smp.key)
                 continue
-            if not self._start(req):
-                blocked.add(smp.key)
-                continue
             self.queue.remove(req)
-
-    def turn(self):
-        """Admit what fits, advance the engine a few iterations, finish completed requests."""
-        self.admit_waiting()
-        if not self.running:
-            return []
-        done = self.engine.step(max_iters=self.iters_per_turn, return_on_done=True)
-        out = []
-        for slot in done:
-            req = self.running.pop(slot)
-            req.stats = self.engine.retire(slot)
-            smp = req.sample
-            req.hg = self.ctx.hypergradient_p(smp.P64, smp.thetas[req.step], smp.xhats[req.step], smp.w)
-            req.t_done = self.clock()
-            smp.prev_hg = float(np.linalg.norm(req.hg))
-            smp.step += 1
-            smp.busy = False
-            out.append(req)
-        self.completed += out
+            smp.busy = True
+            self._prepare(req)
+            self.preparing.append(req)
+        for req in list(self.preparing):
+            if req.fut is None or req.fut.done():
+                if req.fut is not None:
+                    req.fut.result()
+                self.preparing.remove(req)
+                self.ready.append(req)
+        while self.ready:
+            if not self._admit(self.ready[0]):
+                break
+            self.ready.popleft()
+        if self.running:
+            for slot in self.engine.step(max_iters=self.iters_per_turn, return_on_done=True):
+                req = self.running.pop(slot)
+                req.stats = self.engine.retire(slot)
+                smp = req.sample
+                if self.pool is None:
+                    req.hg = self.ctx.hypergradient_p(smp.P64, smp.thetas[req.step], smp.xhats[req.step], smp.w)
+                    self._complete(req)
+                    out.append(req)
+                else:
+                    req.fut = self.pool.submit(lambda c, P, th, xh, w: c.hypergradient_p(P, th, xh, w),
+                                               smp.P64, smp.thetas[req.step], smp.xhats[req.step], smp.w)
+                    self.finishing.append(req)
+        for req in list(self.finishing):
+            if req.fut.done():
+                req.hg = req.fut.result()
+                self.finishing.remove(req)
+                self._complete(req)
+                out.append(req)
         return out
 
     def idle(self) -> bool:
-        return not self.running and not self.queue
+        return not (self.queue or self.preparing or self.ready or self.running or self.finishing)
 
     def close(self):
         self.engine.close()

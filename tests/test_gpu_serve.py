@@ -47,11 +47,11 @@ def build(B, ctx, specs, T):
     return out
 
 
-def serve_all(B, ctx, data, order, prec):
+def serve_all(B, ctx, data, order, prec, pool=None):
     from paper_2412_08264_amd import serve
     Ps = [B.problem_from(wl, prec=prec) for wl, *_ in data]
     arena = sum(B.Engine.slot_bytes(P, wl.s) for P, (wl, *_) in zip(Ps, data))
-    srv = serve.Server(ctx, cap=8, arena_bytes=arena, hg_rel=1e-10, iters_per_turn=8)
+    srv = serve.Server(ctx, cap=8, arena_bytes=arena, hg_rel=1e-10, iters_per_turn=8, pool=pool)
     keys = sorted(set(order))
     for k in keys:
         wl, path, xhats, xs, _ = data[k]
@@ -79,7 +79,9 @@ def test_served_results_same_alone_and_in_mix(B, prec):
     try:
         data = build(B, ctx, specs, T)
         order = [k for _ in range(T) for k in range(len(specs))]      # interleaved arrivals
-        mix = serve_all(B, ctx, data, order, prec)
+        # in the mix, refreshes and hypergradients run on other streams and host threads
+        with B.ContextPool(P64s, 6, 32, 3, torch.device(DEV)) as pool:
+            mix = serve_all(B, ctx, data, order, prec, pool)
         assert len(mix) == len(specs) * T
         for k in range(len(specs)):
             alone = serve_all(B, ctx, data, [k] * T, prec)
