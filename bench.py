@@ -105,6 +105,22 @@ def roofline(kernel, bytes_per_launch, kt, workload):
             "update_avg_us": kt[2] / max(kt[3], 1.0) * 1e3}
 
 
+def autotune_tiles(ctx, B, items, iters=100):
+    """Tile heights from the library's autotuner, one run per (operator class, size class):
+    items are (P, theta, xhat, s).  Returns {label: {"rows": r, "us_per_iter": [8, 16, 32 rows]}}."""
+    out = {}
+    for P, th, xh, s in items:
+        lg = int(np.floor(np.log2(P.h * P.w)))
+        label = (f"{'tv' if P.reg == B.BL_REG_TV else 'filters'} r{P.blur_radius} "
+                 f"{'mixed' if P.prec == B.BL_PREC_MIXED else 'fp64'} n~2^{lg}")
+        if label in out:
+            continue
+        rows, us = ctx.autotune_tiles(P, th, xh, s, iters)
+        out[label] = {"rows": rows, "us_per_iter": [round(u, 2) for u in us]}
+        log(f"[bench] autotune {label}: {rows} rows ({', '.join(f'{u:.1f}' for u in us)} us/iteration)")
+    return out
+
+
 def base_line(args, value, el, dtype, config, **extra):
     out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
@@ -270,6 +286,7 @@ def bench_sequence(args, B, torch, synth):
         refs.append(S.hypergradient(th, x, w))
     mixed = wl.prec == "mixed"
     Sh = B.Session(B.problem_from(wl, prec="mixed"), s_max=wl.s, v_cap=V_CAP, device=dev) if mixed else S
+    tiles = autotune_tiles(S, B, [(Sh.P, thetas[0], xhats[0], wl.s), (S.P, thetas[0], xhats[0], wl.s)])
     # threshold selection (untimed): loosest setting with every hypergradient within 1e-6
     variants = [("rgen_hg", Sh, SWEEP_HG), ("rgen_res", Sh, SWEEP_RESID), ("plain", S, SWEEP_RESID)]
     if mixed:
@@ -301,13 +318,14 @@ def bench_sequence(args, B, torch, synth):
     iters_seq = sum(r["iters"] for r in head)
     prec = "mixed" if mixed else "fp64"
     bpp = apply_bytes_per_pixel(wl.reg, prec, wl.s, wl.n_filters)
-    kname = f"k_b_apply<{'float' if mixed else 'double'}, {wl.blur_radius}, {0 if wl.reg == 'tv' else 1}>"
+    kname = (f"k_b_apply<{'float' if mixed else 'double'}, {wl.blur_radius}, {0 if wl.reg == 'tv' else 1}, "
+             f"{B.bl_tile_rows(Sh.P) // 8}>")
     desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
             f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
             f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad|"
             + (", FP32 stencils + FP64 rest with residual replacement" if mixed else ""))
     out = base_line(args, value, el, "f32+f64" if mixed else "f64",
-                    {"workload": desc, "outer_steps": outer, "s": wl.s, "v_cap": V_CAP, "n": wl.n},
+                    {"workload": desc, "outer_steps": outer, "s": wl.s, "v_cap": V_CAP, "n": wl.n, "tiles": tiles},
                     passing=f"{ok}/{total}",
                     latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                     iters_per_sequence={"rgen_hg": iters_seq, **{k: v["iters_per_sequence"] for k, v in extra.items()}},
@@ -429,6 +447,21 @@ def bench_batch(args, B, torch, synth):
                 chosen[mode] = thr
                 break
         log(f"[bench] batch {mode}: threshold {chosen[mode]:g}")
+    # tile heights: the whole batch shares the chip, so the autotuner times whole passes, one
+    # per height for every image (untimed)
+    search = {}
+    for rows in (8, 16, 32):
+        for P in Ps:
+            B.bl_tile_rows_set(P, rows)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        one_pass("rgen_hg", chosen["rgen_hg"])
+        torch.cuda.synchronize()
+        search[rows] = (time.perf_counter() - ts) * 1e3
+    best_rows = min(search, key=search.get)
+    for P in Ps:
+        B.bl_tile_rows_set(P, best_rows)
+    log(f"[bench] batch tile heights: {best_rows} rows (ms per pass {search})")
     for _ in range(args.warmup):
         one_pass("rgen_hg", chosen["rgen_hg"])
     ctx.set_timing(2)
@@ -459,12 +492,13 @@ def bench_batch(args, B, torch, synth):
     torch.cuda.synchronize()
     elp = time.perf_counter() - tp
     okp = sum(1 for e in perr if e <= 1e-6)
-    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'}, 5, 1>"
+    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'}, 5, 1, {best_rows // 8}>"
     out = base_line(args, value, el, "f32+f64" if prec == "mixed" else "f64",
                     {"workload": f"batch{len(wls)}: {len(wls)} filter images (8 x 7x7, blur r=5 sigma=3, noise 0.02), "
                                  f"sides {sorted(set(w.h for w in wls))}, sum n = {sum(w.n for w in wls)}, shared theta, "
                                  f"{T} frozen Adam steps, RGen-L(R) s=20 per image, one engine for all solves",
-                     "images": len(wls), "outer_steps": T, "s": 20, "sum_n": sum(w.n for w in wls)},
+                     "images": len(wls), "outer_steps": T, "s": 20, "sum_n": sum(w.n for w in wls),
+                     "tiles": {"rows": best_rows, "ms_per_pass": {str(k): round(v, 2) for k, v in search.items()}}},
                     passing=f"{ok}/{len(allerr)}", max_rel_err=max(allerr),
                     iters_per_pass={"rgen_hg": sum(alliters) // args.steps, "plain": sum(piters) // args.steps},
                     plain_cg={"solves_per_s": okp / elp, "threshold": chosen["plain"], "passing": f"{okp}/{len(perr)}"},
@@ -543,8 +577,11 @@ def bench_serve(args, B, torch, synth):
     arrivals = synth.poisson_arrivals(args.rate, args.warm_s + args.duration, len(wls), seed=5001)
     pool = B.ContextPool(P64, max(w.s for w in wls), args.v_cap, args.workers, dev)
     modes = {}
+    tiles = {}
     for prec in ("mixed", "fp64"):
         Ps = [B.problem_from(wl, prec=prec) for wl in wls]
+        tiles.update(autotune_tiles(ctx, B, [(P, data[k][0][0], data[k][1][0], wl.s)
+                                             for k, (P, wl) in enumerate(zip(Ps, wls))]))
         arena = sum(B.Engine.slot_bytes(P, wl.s) for P, wl in zip(Ps, wls))
         srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, pool=pool)
         for k, (wl, P) in enumerate(zip(wls, Ps)):
@@ -609,7 +646,7 @@ def bench_serve(args, B, torch, synth):
                                  f"8 x 7x7 filters, s in {sorted(set(w.s for w in wls))}), {T} frozen outer steps each, "
                                  f"Poisson arrivals {args.rate:g}/s, {args.duration:g} s window after {args.warm_s:g} s, "
                                  f"continuous batching (engine cap 64), mixed precision; FP64 beside it",
-                     "samples": len(wls), "rate_per_s": args.rate, "window_s": args.duration},
+                     "samples": len(wls), "rate_per_s": args.rate, "window_s": args.duration, "tiles": tiles},
                     latency_ms=head["latency_ms"], passing=head["passing"], mixed=head, fp64=modes["fp64"],
                     roofline=head["roofline"])
     out["steps"] = 1
@@ -661,6 +698,8 @@ def kernels_only_batch(args, B, torch, synth):
     dev = torch.device("cuda:0")
     wls = synth.batch_set(args.batch, 4000, s=20)
     Ps = [B.problem_from(wl, prec=args.prec) for wl in wls]
+    for P in Ps:
+        B.bl_tile_rows_set(P, args.rows or 32)
     P64 = [B.problem_from(wl, prec="fp64") for wl in wls]
     ctx = B.Context(P64, s_max=20, v_cap=V_CAP, device=dev)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
@@ -710,6 +749,10 @@ def kernels_only(args, B, torch, synth):
     xs = t(inst["xstar"])
     xh = xs + 0.05 * t(synth.unit_noise(wl.n, wl.seed + 77))
     th = inst["theta0"]
+    if args.rows:
+        B.bl_tile_rows_set(S.P, args.rows)
+    else:
+        autotune_tiles(S, B, [(S.P, th, xh, wl.s)])
     w = torch.zeros_like(xs)
     S.solve(th, xh, xh - xs, w, tol=0.0, max_iter=200, store_basis=True, allow=(B.BL_E_NOT_CONVERGED,))
     S.refresh(th, xh, s=wl.s)
@@ -720,7 +763,8 @@ def kernels_only(args, B, torch, synth):
     b.copy_(a)
     torch.cuda.synchronize()
     S.close()
-    print(json.dumps({"kernels_only": True, "workload": wl.name, "copy_bytes": a.numel() * 8}))
+    print(json.dumps({"kernels_only": True, "workload": wl.name, "copy_bytes": a.numel() * 8,
+                      "rows": B.bl_tile_rows(S.P)}))
 
 
 def main():
@@ -742,6 +786,8 @@ def main():
     ap.add_argument("--hg-rel", dest="hg_rel", type=float, default=1e-9, help="serve: error-estimate threshold "
                     "relative to the sample's previous hypergradient norm")
     ap.add_argument("--v-cap", dest="v_cap", type=int, default=V_CAP, help="serve: stored Krylov vectors per sample")
+    ap.add_argument("--rows", type=int, default=0, choices=(0, 8, 16, 32),
+                    help="kernels-only: tile height of the solves (0: autotune)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: a few recycled-CG iterations on the workload's shape at stand-in points "
                          "x* + 0.05 e' (no trajectory) plus a 64 MiB device copy for counter calibration")

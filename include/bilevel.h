@@ -176,11 +176,12 @@ bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
 /* ------------------------------------------------------------------------------------------
  * Batched and served Hessian solves.  An engine runs up to `cap` (<= 64) recycled-CG solves
  * side by side: each iteration is one launch of the fused apply kernel (H p with p.q and
- * C^T q) per operator class (problems equal in every bl_problem field but h, w; at most 4
- * classes at a time) and one launch of the update kernel over all running solves, whatever
- * their sizes, recycle dimensions and iteration indices.  Every solve reduces only its own records in a fixed order, so its
- * iterates, iteration count and status are bitwise those of the same solve run alone
- * (bl_hessian_solve, which is a one-solve engine).  Solves are admitted and retired
+ * C^T q) per group of solves with the same operator class (problems equal in every
+ * bl_problem field but h, w) and tile height (bl_tile_rows; at most 8 groups at a time), and
+ * one launch of the update kernel over all running solves, whatever their sizes, recycle
+ * dimensions and iteration indices.  Every solve reduces only its own records in a fixed
+ * order, so its iterates, iteration count and status are bitwise those of the same solve
+ * run alone (bl_hessian_solve, which is a one-solve engine) with the same tile height.  Solves are admitted and retired
  * between steps (continuous batching).  The engine's device memory is one caller-owned
  * workspace: fixed per-slot descriptors plus an arena from which each admitted solve takes
  * bl_engine_slot_bytes() and to which retirement returns it.  The engine holds pinned host
@@ -202,7 +203,7 @@ bl_status bl_engine_destroy(bl_engine* engine);
  * Set-up work (FP64 residual, projection onto C) is enqueued at once.  Returns
  * BL_E_WORKSPACE (nothing enqueued) when no slot or no arena block of
  * bl_engine_slot_bytes() is free: retire a completed solve and try again; BL_E_ARG when the
- * problem would be a fifth operator class among the admitted solves. */
+ * problem would open a ninth (operator class, tile height) group among the admitted solves. */
 bl_status bl_engine_admit(bl_engine* engine, const bl_problem* P, const double* theta_host, const double* xhat,
                           const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts, int* slot);
 /* Advance all running solves by at most max_iters iterations; with return_on_done, return
@@ -220,13 +221,38 @@ bl_status bl_engine_query(const bl_engine* engine, int* running, int* free_slots
  * (s = NULL: none). */
 size_t bl_batched_workspace_bytes(int nprob, const bl_problem* P, const int* s);
 /* nprob independent solves (P[k], theta[k], xhat[k], g[k], w[k], rs[k]; rs = NULL: plain CG
- * for all; at most 4 operator classes) with shared options, advanced together (at most 64 at
+ * for all; at most 8 (operator class, tile height) groups) with shared options, advanced together (at most 64 at
  * a time; later ones are admitted as earlier ones finish).  out[k] gets the statistics of
  * solve k.  Returns BL_OK, or the first non-OK status of a solve. */
 bl_status bl_hessian_solve_batched(bl_ctx* ctx, int nprob, const bl_problem* P, const double* const* theta_host,
                                    const double* const* xhat, const double* const* g, double* const* w_inout,
                                    bl_recycle* rs, const bl_solve_opts* opts, void* ws, size_t ws_bytes,
                                    bl_stats* out);
+
+/* ------------------------------------------------------------------------------------------
+ * Tile shapes.  The fused apply and residual kernels of the Hessian solves work on tiles of
+ * 32 columns and 8, 16 or 32 rows: tall tiles reuse more of each staged value, short tiles
+ * give small images more blocks.  The height a solve uses is looked up in a process-wide
+ * table keyed by the operator class (regulariser, blur radius, filter count and size,
+ * precision) and the size class floor(log2(h*w)); without an entry it is the tallest tile
+ * that still gives the image at least 256 tiles (one per compute unit), else 8 rows.  A
+ * solve keeps the height it was admitted with; the table is read under a lock.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Set (rows = 8, 16 or 32) or clear (rows = 0) the table entry of P's class and size class.
+ * BL_E_ARG for another value. */
+bl_status bl_tile_rows_set(const bl_problem* P, int rows);
+/* The tile height solves of P use now (table entry or default); 0 for an invalid problem. */
+int bl_tile_rows(const bl_problem* P);
+/* Autotuner: time `iters` iterations of a recycled-CG solve of P at (theta_host, xhat) with
+ * s (0..64) recycle columns at each tile height, store the fastest in the table and return
+ * it in *best_rows; us_per_iter[0..2] (may be NULL) get the mean microseconds per iteration
+ * at 8, 16 and 32 rows.  The recycle columns are zero, which leaves the arithmetic that of
+ * plain CG while every projection is still read, and the stop test is disabled, so every
+ * height runs exactly `iters` (1..100000) iterations.  Allocates and frees its own device
+ * memory; synchronous on the context's stream. */
+bl_status bl_autotune_tiles(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat, int s,
+                            int iters, double* us_per_iter, int* best_rows);
 
 #ifdef __cplusplus
 }

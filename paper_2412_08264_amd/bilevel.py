@@ -83,6 +83,10 @@ _SIGS = {
     "bl_hessian_solve_batched": (C.c_int, [_vp, C.c_int, _P(bl_problem), _P(_P(C.c_double)), _P(_vp), _P(_vp),
                                            _P(_vp), _P(bl_recycle), _P(bl_solve_opts), _vp, C.c_size_t,
                                            _P(bl_stats)]),
+    "bl_tile_rows_set": (C.c_int, [_P(bl_problem), C.c_int]),
+    "bl_tile_rows": (C.c_int, [_P(bl_problem)]),
+    "bl_autotune_tiles": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, C.c_int, C.c_int, _P(C.c_double),
+                                    _P(C.c_int)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -155,6 +159,17 @@ def _check(ctx, st: int, name: str, ok=(BL_OK,)) -> int:
     return st
 
 
+def bl_tile_rows_set(P: bl_problem, rows: int) -> None:
+    """Tile height (8, 16, 32; 0 clears) of the solves of P's operator class and size class."""
+    st = lib.bl_tile_rows_set(C.byref(P), int(rows))
+    if st != BL_OK:
+        raise BLError(st, "bl_tile_rows_set")
+
+
+def bl_tile_rows(P: bl_problem) -> int:
+    return int(lib.bl_tile_rows(C.byref(P)))
+
+
 class Context:
     """Context + workspace for problems up to the given shapes; every call names its problem
     and recycle storage explicitly (torch tensors on one device)."""
@@ -192,6 +207,15 @@ class Context:
         out = (C.c_double * 4)()
         lib.bl_kernel_times(self.ctx, out, 1 if reset else 0)
         return tuple(out[:])
+
+    def autotune_tiles(self, P, theta, xhat, s: int, iters: int = 100):
+        """Time every tile height on a solve of P at (theta, xhat) and keep the fastest for P's
+        operator class and size class.  Returns (rows, microseconds per iteration at 8/16/32)."""
+        us = (C.c_double * 3)()
+        best = C.c_int()
+        _check(self.ctx, lib.bl_autotune_tiles(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), int(s), int(iters),
+                                               us, C.byref(best)), "bl_autotune_tiles")
+        return best.value, tuple(us[:])
 
     # -- calls
     def forward_p(self, P, x, e, noise, y):
@@ -322,7 +346,8 @@ def _aligned_workspace(nbytes: int, device):
 
 # --------------------------------------------------------------------------- batched / served solves
 class Engine:
-    """bl_engine: up to `cap` concurrent solves (up to 4 operator classes) advanced together."""
+    """bl_engine: up to `cap` concurrent solves (up to 8 operator class / tile height groups) advanced
+    together."""
 
     def __init__(self, cap: int, arena_bytes: int, device=None, stream=None, ctx=None):
         import torch

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "host.h"
+#include "tile.h"
 
 using namespace bl;
 using namespace blh;
@@ -308,6 +309,96 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
         out->ms[3] = elapsed(c, 0, 2);
     }
     return (bl_status)st.status;
+}
+
+// ------------------------------------------------------------------------------ tile heights
+bl_status bl_tile_rows_set(const bl_problem* P, int rows) {
+    bl_ctx tmp;
+    if (check_problem(&tmp, P) != BL_OK) return BL_E_ARG;
+    if (rows != 0 && !valid_rows(rows)) return BL_E_ARG;
+    set_tile_rows(P, rows);
+    return BL_OK;
+}
+
+int bl_tile_rows(const bl_problem* P) {
+    bl_ctx tmp;
+    if (check_problem(&tmp, P) != BL_OK) return 0;
+    return tile_rows(P);
+}
+
+// Each height runs a short warm-up solve, then `iters` timed iterations of a solve whose
+// recycle columns are zero (C^T q = 0, C e = 0: plain CG arithmetic, recycled memory traffic)
+// with the stop test disabled (tol = 0).
+bl_status bl_autotune_tiles(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, int s,
+                            int iters, double* us_per_iter, int* best_rows) {
+    if (!c) return BL_E_ARG;
+    TRY(check_problem(c, P));
+    if (!theta || !xhat || !best_rows) return c->err = "null argument", BL_E_ARG;
+    if (s < 0 || s > S_MAX) return c->err = "s outside [0, 64]", BL_E_SHAPE;
+    if (iters < 1 || iters > 100000) return c->err = "iters outside [1, 100000]", BL_E_ARG;
+    const size_t n = (size_t)P->h * P->w, sc = (size_t)std::max(s, 1);
+    const size_t wsb = bl_workspace_bytes(P, s, 0);
+    const size_t o_g = al(wsb), o_w = o_g + al(n * 8), o_u = o_w + al(n * 8), o_c = o_u + al(n * sc * 8),
+                 o_z = o_c + al(n * sc * 8), o_mu = o_z + al(n * sc * 8), total = o_mu + al(sc * 8);
+    char* mem = nullptr;
+    HIPCHK(hipMalloc(&mem, total));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bl_status rc = BL_OK;
+    double us[3] = {0.0, 0.0, 0.0};
+    const int heights[3] = {QTY, 2 * QTY, 4 * QTY};
+    auto body = [&]() -> bl_status {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipMemsetAsync(mem + o_u, 0, o_mu + al(sc * 8) - o_u, c->stream));
+        HIPCHK(hipMemcpyAsync(mem + o_g, xhat, n * 8, hipMemcpyDeviceToDevice, c->stream));
+        bl_recycle rs{};
+        rs.U = (double*)(mem + o_u);
+        rs.C = (double*)(mem + o_c);
+        rs.Z = (double*)(mem + o_z);
+        rs.mu = (double*)(mem + o_mu);
+        rs.s_max = s;
+        rs.s_cur = s;
+        bl_solve_opts o{};
+        o.stop = BL_STOP_RESID;
+        o.tol = 0.0;
+        o.check_every = 1;
+        o.rr_every = 50;
+        for (int k = 0; k < 3; ++k) {
+            c->force_rows = heights[k];
+            for (int pass = 0; pass < 2; ++pass) {
+                o.max_iter = pass == 0 ? std::min(iters, 16) : iters;
+                HIPCHK(hipMemsetAsync(mem + o_w, 0, n * 8, c->stream));
+                if (pass == 1) HIPCHK(hipEventRecord(e0, c->stream));
+                bl_stats st{};
+                const bl_status r = bl_hessian_solve(c, P, theta, xhat, (const double*)(mem + o_g),
+                                                     (double*)(mem + o_w), s ? &rs : nullptr, &o, mem, wsb, &st);
+                if (r == BL_E_HIP || r == BL_E_ARG || r == BL_E_SHAPE || r == BL_E_WORKSPACE) return r;
+                if (pass == 1) {
+                    HIPCHK(hipEventRecord(e1, c->stream));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    us[k] = 1e3 * ms / std::max(st.iters, 1);
+                }
+            }
+        }
+        return BL_OK;
+    };
+    rc = body();
+    c->force_rows = 0;
+    (void)hipStreamSynchronize(c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(mem);
+    if (rc != BL_OK) return rc;
+    int best = 0;
+    for (int k = 1; k < 3; ++k)
+        if (us[k] < us[best]) best = k;
+    set_tile_rows(P, heights[best]);
+    *best_rows = heights[best];
+    if (us_per_iter)
+        for (int k = 0; k < 3; ++k) us_per_iter[k] = us[k];
+    return BL_OK;
 }
 
 // ---------------------------------------------------------------------------- hypergradient

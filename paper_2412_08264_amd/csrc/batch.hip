@@ -7,106 +7,9 @@
 // its slot's record array; the next kernel reduces the records of its slot in every block
 // (fixed order), so a slot's scalars and decisions are identical in every block and do
 // not depend on the other slots.  Block 0 of a slot stores the scalars for the host.
-#include <type_traits>
-
-#include "kernels.h"
-#include "tile.h"
+#include "batch_tile.h"
 
 namespace bl {
-
-__device__ __forceinline__ void slot_stencil(Stencil& S, const Slot& sl) {
-    S.h = sl.h;
-    S.w = sl.width;
-    S.n = sl.n;
-    S.tiles_x = sl.tiles_x;
-    S.lam = sl.lam;
-    S.gam2 = sl.gam2;
-    S.taps = sl.taps;
-    S.tapsf = sl.tapsf;
-    S.lamj = sl.lamj;
-    S.d2 = sl.d2;
-    S.d2f = sl.d2f;
-}
-
-__device__ __forceinline__ void slot_tile(const Slot& sl, int local, int& r0, int& c0) {
-    const int t = xcd_tile(local, sl.ntiles);
-    r0 = (t / sl.tiles_x) * QH;
-    c0 = (t % sl.tiles_x) * QW;
-}
-
-// The thread's four pixels: rows r0 + 4 ty + k of column c0 + tx.
-struct Own {
-    int g[QR];
-    bool in[QR];
-};
-__device__ __forceinline__ Own own_pixels(int h, int w, int r0, int c0) {
-    Own o;
-    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
-#pragma unroll
-    for (int k = 0; k < QR; ++k) {
-        const int gi = r0 + QR * ty + k;
-        o.in[k] = gi < h && gj < w;
-        o.g[k] = o.in[k] ? gi * w + gj : 0;
-    }
-    return o;
-}
-
-// Records a consumer reads: the producer's per-block array, or its folded record.
-__device__ __forceinline__ const double* slot_rec(const Slot& sl, int which, int& nb) {
-    if (which == 0) {
-        nb = sl.fold_res ? 1 : sl.ntiles;
-        return sl.fold_res ? sl.fold : sl.rec_res;
-    }
-    if (which == 1) {
-        nb = sl.fold_app ? 1 : sl.ntiles;
-        return sl.fold_app ? sl.fold + NV_RED : sl.rec_app;
-    }
-    nb = sl.fold_upd ? 1 : sl.npix;
-    return sl.fold_upd ? sl.fold + 2 * NV_RED : sl.rec_upd;
-}
-
-// ------------------------------------------------------------------ residual g - H w
-// r = g - H w in FP64 and the record [g.g, C^T r].  With `periodic` set (a scheduled
-// residual replacement) a slot that has already stopped is left alone.
-template <int R, int CLS>
-__global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __restrict__ slots, BatchMap M,
-                                                   int periodic) {
-    using L = QLayout<double, R, CLS>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* lds = reinterpret_cast<double*>(smem_raw);
-    const int2 m = map_block(M, blockIdx.x);
-    const Slot& sl = slots[m.x];
-    if (m.y >= sl.ntiles || (periodic && sl.st->done)) return;
-    Stencil S = base;
-    slot_stencil(S, sl);
-    int r0, c0;
-    slot_tile(sl, m.y, r0, c0);
-    const Own o = own_pixels(S.h, S.w, r0, c0);
-    double gv[QR];
-#pragma unroll
-    for (int k = 0; k < QR; ++k) gv[k] = o.in[k] ? sl.g[o.g[k]] : 0.0;
-    q_stage<double, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return sl.w[gi]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<double>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
-    __syncthreads();
-    double hv[QR];
-    q_hvp<double, R, CLS>(lds, S, r0, c0, hv);
-    double ov[QR];
-#pragma unroll
-    for (int k = 0; k < QR; ++k) {
-        ov[k] = o.in[k] ? gv[k] - hv[k] : 0.0;
-        if (o.in[k]) sl.r[o.g[k]] = ov[k];
-    }
-    block_partials(
-        sl.rec_res, 1 + sl.s,
-        [&](int k) {
-            double acc = 0.0;
-#pragma unroll
-            for (int u = 0; u < QR; ++u)
-                if (o.in[u]) acc += k == 0 ? gv[u] * gv[u] : sl.C[(size_t)(k - 1) * S.n + o.g[u]] * ov[u];
-            return acc;
-        },
-        m.y);
-}
 
 // Set-up: c0 = C^T r (records), w += U c0, r -= C c0, record [r.r, Z^T r].
 __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, BatchMap M) {
@@ -133,121 +36,6 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
         [&](int k) -> double {
             if (!in) return 0.0;
             return k == 0 ? ri * ri : sl.Z[(size_t)(k - 1) * n + i] * ri;
-        },
-        m.y);
-}
-
-// Iteration j = step - j0, first half: stop test from the update records, beta, p, q = H p,
-// V store, record [p.q, C^T q].  After a residual replacement whose true residual exceeds the
-// previous recursive one the direction restarts (p = r): keeping it would let the stale
-// direction dominate (beta = rho_true / rho_rec >> 1) and stall at the accuracy of the FP32
-// operator; restarting turns the replacement into a step of iterative refinement.
-// A stopped slot's blocks leave after the record reduction (its flag is read by one thread
-// and published by the reduction's barrier: uniform per block; a flag set by block 0 during
-// this launch follows from the same decision every block of the slot takes).
-constexpr int CPRE = 8;   // columns of C per pixel loaded before the (short) TV stencil
-template <typename T, int R, int CLS>
-__global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
-    using L = QLayout<T, R, CLS>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-    __shared__ double tot[NT];
-    __shared__ int sdone;
-    const int2 m = map_block(M, blockIdx.x);
-    const Slot& sl = slots[m.x];
-    if (m.y >= sl.ntiles) return;
-    SolveState* st = sl.st;
-    const int j = step - sl.j0;
-    if (threadIdx.x == 0) sdone = st->done;
-    const int s = sl.s, nz = sl.nz;
-    int nb;
-    const double* rec = slot_rec(sl, 2, nb);
-    reduce_partials(rec, nb, 1 + nz, tot);
-    if (sdone) return;
-    const double rho_prev = j > 0 ? st->rho2[(j - 1) & 1] : 1.0;
-    const bool store_basis = st->store_basis && j < st->v_cap;
-    const double rho = tot[0];
-    const bool restart = j > 0 && st->rr_j == j && rho > rho_prev;
-    const Decision dec = decide(st, j, rho, tot + 1);
-    if (m.y == 0) {
-        for (int k = threadIdx.x; k < nz; k += NT) st->zr[k] = tot[1 + k];
-        if (threadIdx.x == 0) {
-            st->rho2[j & 1] = rho;
-            st->est = dec.est;
-            st->iters = j;
-            if (j == 0) st->res0 = sqrt(rho);
-            if (dec.done) {
-                st->status = dec.status;
-                st->done = 1;
-            }
-        }
-    }
-    if (dec.done) return;
-    Stencil S = base;
-    slot_stencil(S, sl);
-    const bool first = (j == 0) || restart;
-    const double beta = first ? 0.0 : rho / rho_prev;
-    const double* __restrict__ r = sl.r;
-    const double* __restrict__ p_old = sl.p[j & 1];
-    double* __restrict__ p_new = sl.p[(j + 1) & 1];
-    int r0, c0;
-    slot_tile(sl, m.y, r0, c0);
-    const Own o = own_pixels(S.h, S.w, r0, c0);
-    // the filter stencil is long enough to hide the C loads issued after it, and the registers
-    // of a prefetch would cost occupancy there
-    constexpr int CP = CLS == TC_TV ? CPRE : 1;
-    double ri[QR], pi[QR], cpre[CP][QR];
-#pragma unroll
-    for (int k = 0; k < QR; ++k) {
-        ri[k] = o.in[k] ? r[o.g[k]] : 0.0;
-        pi[k] = (o.in[k] && !first) ? p_old[o.g[k]] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < CP; ++c)
-#pragma unroll
-        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * S.n + o.g[k]] : 0.0;
-    q_stage<T, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0,
-                       [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<T>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
-    __syncthreads();
-    T hv[QR];
-    q_hvp<T, R, CLS>(lds, S, r0, c0, hv);
-    double pv[QR], qq[QR];
-    const double inv = store_basis ? 1.0 / sqrt(rho) : 0.0;
-#pragma unroll
-    for (int k = 0; k < QR; ++k) {
-        const double pn = first ? ri[k] : ri[k] + beta * pi[k];
-        qq[k] = o.in[k] ? (double)hv[k] : 0.0;
-        pv[k] = o.in[k] ? pn : 0.0;
-        if (o.in[k]) {
-            p_new[o.g[k]] = pn;
-            sl.q[o.g[k]] = qq[k];
-            if (store_basis) sl.V[(size_t)j * S.n + o.g[k]] = ri[k] * inv;
-        }
-    }
-    block_partials(
-        sl.rec_app, 1 + s,
-        [&](int k) {
-            double acc = 0.0;
-            if (k == 0) {
-#pragma unroll
-                for (int u = 0; u < QR; ++u) acc += pv[u] * qq[u];
-                return acc;
-            }
-            const int c = k - 1;
-            if (c < CP) {
-#pragma unroll
-                for (int cc = 0; cc < CP; ++cc)
-                    if (cc == c) {
-#pragma unroll
-                        for (int u = 0; u < QR; ++u) acc += cpre[cc][u] * qq[u];
-                    }
-            } else {
-#pragma unroll
-                for (int u = 0; u < QR; ++u)
-                    if (o.in[u]) acc += sl.C[(size_t)c * S.n + o.g[u]] * qq[u];
-            }
-            return acc;
         },
         m.y);
 }
@@ -434,42 +222,26 @@ __global__ void __launch_bounds__(NT) k_b_headers(const Slot* __restrict__ slots
     out[(size_t)idx * WPS + wd] = reinterpret_cast<const int*>(slots[idx].st)[wd];
 }
 
-// ------------------------------------------------------------------ launchers
-template <typename K>
-static void allow_lds_b(K kernel, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-static inline dim3 map_grid(const BatchMap& M) { return dim3(M.off[M.ns]); }
-
-hipError_t launch_b_residual(const Stencil& base, const Slot* slots, const BatchMap& M, int periodic,
+hipError_t launch_b_residual(const Stencil& base, int rows, const Slot* slots, const BatchMap& M, int periodic,
                              hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
-        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
-        const size_t lds = QLayout<double, RR, CC>::bytes;
-        allow_lds_b(k_b_residual<RR, CC>, lds);
-        hipLaunchKernelGGL((k_b_residual<RR, CC>), map_grid(M), dim3(NT), lds, stream, base, slots, M, periodic);
-    });
-    return hipGetLastError();
+    switch (rows) {
+        case QTY * 1: return launch_b_residual_q<1>(base, slots, M, periodic, stream);
+        case QTY * 2: return launch_b_residual_q<2>(base, slots, M, periodic, stream);
+        case QTY * 4: return launch_b_residual_q<4>(base, slots, M, periodic, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_b_apply(const Stencil& base, bool fp32, const Slot* slots, const BatchMap& M, int step,
+hipError_t launch_b_apply(const Stencil& base, int rows, bool fp32, const Slot* slots, const BatchMap& M, int step,
                           hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
-        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
-        if (fp32) {
-            const size_t lds = QLayout<float, RR, CC>::bytes;
-            allow_lds_b(k_b_apply<float, RR, CC>, lds);
-            hipLaunchKernelGGL((k_b_apply<float, RR, CC>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step);
-        } else {
-            const size_t lds = QLayout<double, RR, CC>::bytes;
-            allow_lds_b(k_b_apply<double, RR, CC>, lds);
-            hipLaunchKernelGGL((k_b_apply<double, RR, CC>), map_grid(M), dim3(NT), lds, stream, base, slots, M, step);
-        }
-    });
-    return hipGetLastError();
+    switch (rows) {
+        case QTY * 1: return launch_b_apply_q<1>(base, fp32, slots, M, step, stream);
+        case QTY * 2: return launch_b_apply_q<2>(base, fp32, slots, M, step, stream);
+        case QTY * 4: return launch_b_apply_q<4>(base, fp32, slots, M, step, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t stream) {

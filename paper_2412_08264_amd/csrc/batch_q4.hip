@@ -1,0 +1,9 @@
+// Batched residual and apply kernels on tiles of 32 x 32 pixels.
+#include "batch_tile.h"
+
+namespace bl {
+
+template hipError_t launch_b_residual_q<4>(const Stencil&, const Slot*, const BatchMap&, int, hipStream_t);
+template hipError_t launch_b_apply_q<4>(const Stencil&, bool, const Slot*, const BatchMap&, int, hipStream_t);
+
+}  // namespace bl

@@ -64,7 +64,7 @@ struct Slot {
     int j0;                               // global step index at which the slot started
     int s, nz;                            // recycle columns; error-estimate columns (0: off)
     int fold_app, fold_upd, fold_res;     // records folded by k_fold before use
-    int pad;
+    int rows;                             // tile height of the Hessian-vector launches
     double lam, gam2;                     // TV weight e^{theta0}, smoothing e^{2 theta1}
     const double* taps;                   // filters: taps (then weights), FP32 copy, weights, phi'' maps
     const float* tapsf;

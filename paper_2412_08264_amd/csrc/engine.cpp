@@ -8,6 +8,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "host.h"
@@ -96,13 +98,61 @@ bool same_class(const bl_problem* a, const bl_problem* b) {
     return true;
 }
 
-static int ntiles_of(int h, int w) { return ((w + QW - 1) / QW) * ((h + QH - 1) / QH); }
+static int ntiles_of(int h, int w, int rows) { return ((w + QW - 1) / QW) * ((h + rows - 1) / rows); }
 static int npix_of(long n) { return (int)((n + NT - 1) / NT); }
 
+// ------------------------------------------------------------------------------ tile heights
+// Rows per tile of the recycled-CG Hessian-vector kernels: a process-wide table keyed by the
+// operator class and the size class floor(log2 n), filled by the autotuner (or by the caller
+// from a stored table); without an entry the tallest tile that still gives the image at least
+// one block per compute unit, else the shortest.  A solve keeps the height it was admitted
+// with; solves of different heights run in different launches.
+namespace {
+using TileKey = std::tuple<int, int, int, int, int, int>;   // reg, radius, filters, size, prec, log2 n
+std::mutex tile_mu;
+std::map<TileKey, int> tile_table;
+constexpr int FILL_BLOCKS = 256;
+
+int log2_floor(long n) {
+    int k = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++k;
+    }
+    return k;
+}
+TileKey tile_key(const bl_problem* P) {
+    const bool f = P->reg == BL_REG_FILTERS;
+    return TileKey(P->reg, P->blur_radius, f ? P->n_filters : 0, f ? P->filter_size : 0, P->prec,
+                   log2_floor((long)P->h * P->w));
+}
+}  // namespace
+
+bool valid_rows(int rows) { return rows == QTY || rows == 2 * QTY || rows == 4 * QTY; }
+
+int default_rows(const bl_problem* P) {
+    for (int rows = 4 * QTY; rows > QTY; rows /= 2)
+        if (ntiles_of(P->h, P->w, rows) >= FILL_BLOCKS) return rows;
+    return QTY;
+}
+
+int tile_rows(const bl_problem* P) {
+    std::lock_guard<std::mutex> lk(tile_mu);
+    const auto it = tile_table.find(tile_key(P));
+    return it == tile_table.end() ? default_rows(P) : it->second;
+}
+
+void set_tile_rows(const bl_problem* P, int rows) {
+    std::lock_guard<std::mutex> lk(tile_mu);
+    if (rows == 0) tile_table.erase(tile_key(P));
+    else tile_table[tile_key(P)] = rows;
+}
+
+// Records are sized for the shortest tiles (the most tiles), whatever height a solve uses.
 size_t slot_bytes(const bl_problem* P, int s) {
     const size_t n = (size_t)P->h * P->w;
     const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
-    const size_t nt = ntiles_of(P->h, P->w), np = npix_of((long)n);
+    const size_t nt = ntiles_of(P->h, P->w, QTY), np = npix_of((long)n);
     return 4 * al(n * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al(TAPS_BYTES) +
            2 * al(nt * (1 + s) * 8) + al(np * (1 + s) * 8) + al(3 * NV_RED * 8);
 }
@@ -110,7 +160,7 @@ size_t slot_bytes(const bl_problem* P, int s) {
 SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
     const size_t n = (size_t)P->h * P->w;
     const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
-    const size_t nt = ntiles_of(P->h, P->w), np = npix_of((long)n);
+    const size_t nt = ntiles_of(P->h, P->w, QTY), np = npix_of((long)n);
     SlotBuffers B{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -212,13 +262,15 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     }
     const bool hg = o->stop == BL_STOP_HGERR && s > 0 && rs->Z;
     const bool store = o->store_basis && rs;
+    const int rows = c->force_rows ? c->force_rows : tile_rows(P);
     int gid = -1;
     for (int gi = 0; gi < (int)groups.size() && gid < 0; ++gi)
-        if (same_class(&groups[gi].cls, P)) gid = gi;
+        if (groups[gi].users > 0 && same_class(&groups[gi].cls, P) && groups[gi].rows == rows) gid = gi;
     for (int gi = 0; gi < (int)groups.size() && gid < 0; ++gi)
-        if (groups[gi].users == 0) gid = gi;   // reuse an idle class entry
+        if (groups[gi].users == 0) gid = gi;   // reuse an idle entry
     if (gid < 0) {
-        if ((int)groups.size() >= MAX_GROUPS) return c->err = "more than 4 operator classes in one batch", BL_E_ARG;
+        if ((int)groups.size() >= MAX_GROUPS)
+            return c->err = "more than 8 (operator class, tile height) groups in one batch", BL_E_ARG;
         groups.emplace_back();
         gid = (int)groups.size() - 1;
     }
@@ -227,6 +279,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         grp.cls = *P;
         class_stencil(P, grp.base);
         grp.fp32 = P->prec == BL_PREC_MIXED;
+        grp.rows = rows;
     }
     const Stencil& base = grp.base;
     double lam, gam2;
@@ -237,7 +290,8 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.width = P->w;
     v.n = n;
     v.tiles_x = (P->w + QW - 1) / QW;
-    v.ntiles = ntiles_of(P->h, P->w);
+    v.ntiles = ntiles_of(P->h, P->w, rows);
+    v.rows = rows;
     v.npix = npix_of(n);
     v.j0 = step;
     v.s = s;
@@ -304,7 +358,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     h.rr_js.assign(1, 0);   // the first test is on the FP64 residual of the set-up
     // set-up: r = g - H w0 (FP64), c0 = C^T r, w += U c0, r -= C c0
     const std::vector<int> one{idx};
-    HIPCHK(launch_b_residual(base, d_slots, make_map(S, one, true), 0, c->stream));
+    HIPCHK(launch_b_residual(base, rows, d_slots, make_map(S, one, true), 0, c->stream));
     if (v.fold_res) {
         BatchMap f{};
         f.ns = 1;
@@ -323,7 +377,8 @@ bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic) {
         for (int i : idx)
             if (S[i].group == gi) mine.push_back(i);
         if (!mine.empty())
-            HIPCHK(launch_b_residual(groups[gi].base, d_slots, make_map(S, mine, true), periodic, c->stream));
+            HIPCHK(launch_b_residual(groups[gi].base, groups[gi].rows, d_slots, make_map(S, mine, true), periodic,
+                                     c->stream));
     }
     BatchMap f{};
     for (int i : idx)
@@ -370,7 +425,8 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
             HIPCHK(hipEventRecord(c->kev[ev], c->stream));
         }
         for (const Group& grp : groups)
-            if (grp.tmap.ns) HIPCHK(launch_b_apply(grp.base, grp.fp32, d_slots, grp.tmap, step, c->stream));
+            if (grp.tmap.ns)
+                HIPCHK(launch_b_apply(grp.base, grp.rows, grp.fp32, d_slots, grp.tmap, step, c->stream));
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], c->stream));
         if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, c->stream));
         HIPCHK(launch_b_update(d_slots, pmap, step, c->stream));

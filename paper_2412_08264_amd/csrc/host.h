@@ -13,6 +13,7 @@ struct bl_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int timing = 0;
+    int force_rows = 0;                  // autotuner: tile height of the solves it times (0: table)
     bl::SolveState* h_state = nullptr;   // pinned
     double* h_buf = nullptr;             // pinned staging (8192 doubles)
     int* h_info = nullptr;               // pinned
@@ -63,6 +64,12 @@ bl_status theta_values(bl_ctx* c, const bl_problem* P, const double* theta, doub
                        double* taps_host);
 // Problems that can share a batched launch: everything but the image size.
 bool same_class(const bl_problem* a, const bl_problem* b);
+// Tile height (rows) of the recycled-CG Hessian-vector kernels for P: the table entry of P's
+// class and size class, else the block-count default.
+bool valid_rows(int rows);
+int default_rows(const bl_problem* P);
+int tile_rows(const bl_problem* P);
+void set_tile_rows(const bl_problem* P, int rows);
 
 // Device scratch of one solve.
 struct SlotBuffers {
@@ -93,7 +100,7 @@ struct SolveSpec {
 // running solves; the host enqueues chunks of POLL iterations and reads the solves' stop flags
 // one chunk behind, so the device never waits for the host.  A solve's arithmetic and
 // decisions do not depend on the others.
-constexpr int MAX_GROUPS = 4;
+constexpr int MAX_GROUPS = 8;
 
 class Batch {
 public:
@@ -104,10 +111,11 @@ public:
     char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES]
     hipEvent_t poll_ev[2] = {};
 
-    struct Group {                 // one operator class: stencil template and precision
+    struct Group {                 // one operator class and tile height: stencil template, precision
         bl_problem cls{};
         bl::Stencil base{};
         bool fp32 = false;
+        int rows = 0;
         int users = 0;             // slots in use
         bl::BatchMap tmap{};       // tile map of its running slots
     };

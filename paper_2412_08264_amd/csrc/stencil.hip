@@ -22,18 +22,19 @@ __device__ __forceinline__ void write_partials(double* part, int nv, double*, Va
 template <typename T, int R, int CLS>
 __global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict__ xhat,
                                             const double* __restrict__ v, double* __restrict__ out) {
-    using L = QLayout<T, R, CLS>;
+    constexpr int QR = Q_DEFAULT, QH = QTY * QR;
+    using L = QLayout<T, R, CLS, QR>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int qtx = (S.w + QW - 1) / QW;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = (t / qtx) * QH, c0 = (t % qtx) * QW;
     const double* vc = v + (size_t)blockIdx.y * S.n;
-    q_stage<T, R, CLS>(lds + L::o_v, S.h, S.w, r0, c0, [&](int i) { return vc[i]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<T>(lds + L::o_x, S.h, S.w, xhat, r0, c0);
+    q_stage<T, R, CLS, QR>(lds + L::o_v, S.h, S.w, r0, c0, [&](int i) { return vc[i]; });
+    if constexpr (CLS == TC_TV) q_stage_xhat<T, QR>(lds + L::o_x, S.h, S.w, xhat, r0, c0);
     __syncthreads();
     T hv[QR];
-    q_hvp<T, R, CLS>(lds, S, r0, c0, hv);
+    q_hvp<T, R, CLS, QR>(lds, S, r0, c0, hv);
     double* oc = out + (size_t)blockIdx.y * S.n;
     const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
 #pragma unroll
@@ -390,15 +391,15 @@ int tiles_of(const Stencil& S) { return S.tiles_x * S.tiles_y; }
 // Kernels are instantiated per blur radius (0..MAX_R) and arithmetic type.
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
                       hipStream_t st) {
-    const dim3 grid(((S.w + QW - 1) / QW) * ((S.h + QH - 1) / QH), ncols);
+    const dim3 grid(((S.w + QW - 1) / QW) * ((S.h + QTY * Q_DEFAULT - 1) / (QTY * Q_DEFAULT)), ncols);
     q_dispatch(S.R, tile_class(S.reg, S.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
         if (fp32) {
-            const size_t lds = QLayout<float, RR, CC>::bytes;
+            const size_t lds = QLayout<float, RR, CC, Q_DEFAULT>::bytes;
             allow_lds(k_hvp<float, RR, CC>, lds);
             hipLaunchKernelGGL((k_hvp<float, RR, CC>), grid, dim3(NT), lds, st, S, xhat, v, out);
         } else {
-            const size_t lds = QLayout<double, RR, CC>::bytes;
+            const size_t lds = QLayout<double, RR, CC, Q_DEFAULT>::bytes;
             allow_lds(k_hvp<double, RR, CC>, lds);
             hipLaunchKernelGGL((k_hvp<double, RR, CC>), grid, dim3(NT), lds, st, S, xhat, v, out);
         }

@@ -1,4 +1,4 @@
-// Hessian-vector product on 32 x 32 pixel tiles (256 threads, 4 pixels per thread).
+// Hessian-vector product on 32 x (8 Q) pixel tiles (256 threads, Q = 1, 2 or 4 pixels per thread).
 //
 // The Hessian of the lower-level objective (Section 2.1; TV and filter regularisers of
 // Section 5):  H v = 2 A^T A v + lambda D^T (B(x) D v)            (smoothed TV)
@@ -6,8 +6,11 @@
 // with A the normalised (2R+1)^2 Gaussian correlation (zero outside the image, A^T = A).
 //
 // A block stages v on its tile plus a halo of E = max(2R, 2F, 1) pixels into LDS once and
-// evaluates every term from there.  Thread (tx, ty) owns column tx and rows 4 ty .. 4 ty + 3
-// of the tile; the result of those four pixels is returned in registers.  Passes along
+// evaluates every term from there.  Thread (tx, ty) owns column tx and rows Q ty .. Q ty + Q - 1
+// of the tile; the result of those Q pixels is returned in registers.  Taller tiles share
+// more halo and register windows per staged value; shorter ones give small images more
+// blocks (the rows per tile of each operator class and image size come from a timing
+// autotuner, with a block-count rule as the default).  Passes along
 // columns work on strips of consecutive rows held in registers, so every LDS value loaded
 // serves several outputs; the filter correlation loads each input window once and applies
 // all filters to it; filter taps are uniform (scalar) loads.
@@ -20,15 +23,16 @@
 namespace bl {
 
 constexpr int QW = 32;                  // tile columns
-constexpr int QH = 32;                  // tile rows
-constexpr int QR = QH * QW / NT;        // rows owned per thread (4)
+constexpr int QTY = NT / QW;            // thread rows of a block (8); a tile has QTY * Q rows
+constexpr int Q_DEFAULT = 4;            // rows per thread of the stand-alone HVP kernel (32 x 32 tiles)
 
 enum TileClass { TC_TV = 0, TC_F7 = 1, TC_FG = 2 };   // TV; filters 7x7; filters of another size
 
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-template <int R, int CLS>
+template <int R, int CLS, int Q>
 struct QGeo {
+    static constexpr int QH = QTY * Q;                       // tile rows
     static constexpr int F = CLS == TC_TV ? 0 : 3;           // largest filter half-size
     static constexpr int E = cmax(cmax(2 * R, 2 * F), 1);    // halo of the staged region
     static constexpr int RW = QW + 2 * E, RH = QH + 2 * E;   // staged region
@@ -42,9 +46,9 @@ struct QGeo {
     static constexpr int N_FL = (QH + 1) * (QW + 1);         // TV: flux grid
 };
 
-template <typename T, int R, int CLS>
+template <typename T, int R, int CLS, int Q>
 struct QLayout {
-    using G = QGeo<R, CLS>;
+    using G = QGeo<R, CLS, Q>;
     static constexpr int NFG = CLS == TC_TV ? 1 : (sizeof(T) == 8 ? 4 : 8);   // filters per LDS pass
     static constexpr int o_v = 0;
     static constexpr int o_h = o_v + G::N_V;
@@ -63,9 +67,9 @@ __host__ __device__ inline int tile_class(int reg, int fs) {
 
 // Stage fetch(global index) on the region [r0-E, r0+QH+E) x [c0-E, c0+QW+E), zero outside
 // the image; all of a thread's loads are issued before the first store.
-template <typename T, int R, int CLS, typename Fetch>
+template <typename T, int R, int CLS, int Q, typename Fetch>
 __device__ __forceinline__ void q_stage(T* buf, int h, int w, int r0, int c0, Fetch fetch) {
-    using G = QGeo<R, CLS>;
+    using G = QGeo<R, CLS, Q>;
     constexpr int NST = (G::N_V + NT - 1) / NT;
     double val[NST];
 #pragma unroll
@@ -86,9 +90,9 @@ __device__ __forceinline__ void q_stage(T* buf, int h, int w, int r0, int c0, Fe
 }
 
 // TV: stage xhat on [r0-1, r0+QH+1) x [c0-1, c0+QW+1).
-template <typename T>
+template <typename T, int Q>
 __device__ __forceinline__ void q_stage_xhat(T* xs, int h, int w, const double* __restrict__ xhat, int r0, int c0) {
-    constexpr int XW = QW + 2, TOT = (QH + 2) * XW, NST = (TOT + NT - 1) / NT;
+    constexpr int XW = QW + 2, TOT = (QTY * Q + 2) * XW, NST = (TOT + NT - 1) / NT;
     double val[NST];
 #pragma unroll
     for (int u = 0; u < NST; ++u) {
@@ -122,12 +126,13 @@ __device__ __forceinline__ double d2_at<double>(const Stencil& S, size_t gidx) {
 template <>
 __device__ __forceinline__ float d2_at<float>(const Stencil& S, size_t gidx) { return S.d2f[gidx]; }
 
-// H v at the thread's four pixels (rows r0 + 4 ty + k, column c0 + tx) from the staged region
+// H v at the thread's Q pixels (rows r0 + Q ty + k, column c0 + tx) from the staged region
 // (and, for TV, the staged xhat), into out[].  Ends with a barrier after its last LDS read.
-template <typename T, int R, int CLS>
-__device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, T out[QR]) {
-    using G = QGeo<R, CLS>;
-    using L = QLayout<T, R, CLS>;
+template <typename T, int R, int CLS, int Q>
+__device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, T out[Q]) {
+    using G = QGeo<R, CLS, Q>;
+    using L = QLayout<T, R, CLS, Q>;
+    constexpr int QR = Q;
     const T* __restrict__ v = lds + L::o_v;
     T* __restrict__ hb = lds + L::o_h;
     T* __restrict__ t1 = lds + L::o_t1;

@@ -85,3 +85,32 @@ def test_engine_argument_checks_without_gpu():
     assert B.lib.bl_engine_destroy(None) == B.BL_E_ARG
     nd = C.c_int()
     assert B.lib.bl_engine_step(None, 1, 1, None, C.byref(nd)) == B.BL_E_ARG
+
+
+def test_tile_height_table_without_gpu():
+    """Default tile height: the tallest of 32/16/8 rows that gives the image >= 256 tiles of 32
+    columns, else 8; table entries override it per operator class and size class (log2 n)."""
+    from paper_2412_08264_amd import bilevel as B
+    mk = lambda h, w, reg=B.BL_REG_TV, prec=0: B.bl_problem(h, w, 4, 2.5, reg, 8 if reg else 0, 7 if reg else 0,
+                                                            0.0, 0, prec)
+    tiles = lambda h, w, rows: -(-w // 32) * -(-h // rows)
+    for h, w in [(256, 256), (512, 512), (384, 384), (128, 128), (1024, 1024), (64, 64), (3, 2000)]:
+        want = next((r for r in (32, 16) if tiles(h, w, r) >= 256), 8)
+        assert B.bl_tile_rows(mk(h, w)) == want, (h, w)
+    P, Pq = mk(256, 256), mk(200, 300)          # n = 65536 and 60000: size classes 16 and 15
+    Pf = mk(256, 256, B.BL_REG_FILTERS)
+    B.bl_tile_rows_set(P, 32)
+    try:
+        assert B.bl_tile_rows(P) == 32 and B.bl_tile_rows(mk(300, 250)) == 32   # same size class
+        assert B.bl_tile_rows(Pq) == B.bl_tile_rows(mk(200, 300, prec=1)) == 8  # other classes
+        assert B.bl_tile_rows(Pf) == 8
+        with pytest.raises(B.BLError):
+            B.bl_tile_rows_set(P, 24)
+        with pytest.raises(B.BLError):
+            B.bl_tile_rows_set(B.bl_problem(1, 1, 0, 1.0, 0, 0, 0, 0.0, 0, 0), 8)
+    finally:
+        B.bl_tile_rows_set(P, 0)
+    assert B.bl_tile_rows(P) == 8
+    assert B.lib.bl_tile_rows(None) == 0
+    nul = C.c_int()
+    assert B.lib.bl_autotune_tiles(None, C.byref(P), None, None, 0, 10, None, C.byref(nul)) == B.BL_E_ARG

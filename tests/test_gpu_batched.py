@@ -176,31 +176,42 @@ def test_engine_continuous_admission_bitwise(B, kind, prec):
 
 
 def test_engine_mixes_operator_classes(B):
-    """TV and filter solves in FP64 and mixed precision share one engine (one apply launch per
-    class, one update launch for all) and each equals its solo run bitwise; a fifth class is
-    refused while four are admitted."""
+    """TV and filter solves in FP64 and mixed precision, each class at two tile heights, share
+    one engine (one apply launch per (class, height) group, one update launch for all) and each
+    equals its solo run bitwise; a ninth group is refused while eight are admitted."""
     cases = [make_case(B, "tv", 36, 44, 5, 401), make_case(B, "filters", 40, 36, 4, 402),
-             make_case(B, "filters", 32, 48, 6, 403, prec="mixed"), make_case(B, "tv", 50, 30, 0, 404, prec="mixed")]
+             make_case(B, "filters", 32, 48, 6, 403, prec="mixed"), make_case(B, "tv", 50, 30, 0, 404, prec="mixed"),
+             make_case(B, "tv", 64, 70, 3, 405), make_case(B, "filters", 70, 66, 2, 406),
+             make_case(B, "filters", 66, 72, 5, 407, prec="mixed"), make_case(B, "tv", 72, 64, 4, 408, prec="mixed")]
+    # the first four (size class 10 or 11) on 8-row tiles, the last four (size class 12) on 32
+    heights = [8, 8, 8, 8, 32, 32, 32, 32]
     kw = dict(tol=1e-9, rr_every=8, store_basis=False)
-    ref = [solo(B, c, **kw) for c in cases]
-    fifth = B.bl_problem(32, 32, 3, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)   # another blur radius
-    arena = sum(B.Engine.slot_bytes(c["P"], c["rec"].rs.s_cur if c["rec"] else 0) for c in cases) + \
-        B.Engine.slot_bytes(fifth, 0)
-    with B.Engine(cap=5, arena_bytes=arena) as eng:
-        ws = [c["w0"].clone() for c in cases]
-        slots = {}
-        for k, c in enumerate(cases):
-            sl = eng.admit(c["P"], c["th"], c["xh"], c["g"], ws[k], c["rec"], B.solve_opts(**kw))
-            slots[sl] = k
-        w5 = torch.zeros(32 * 32, dtype=torch.float64, device=DEV)
-        with pytest.raises(B.BLError):
-            eng.admit(fifth, np.zeros(2), w5, w5, w5, None, B.solve_opts())
-        with pytest.raises(B.BLError):
-            eng.retire(4)                        # nothing there
-        stats = {}
-        while slots:
-            for sl in eng.step():
-                stats[slots.pop(sl)] = eng.retire(sl)
+    extra = B.bl_problem(32, 32, 3, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)   # another blur radius
+    try:
+        for c, rows in zip(cases, heights):
+            B.bl_tile_rows_set(c["P"], rows)
+        assert [B.bl_tile_rows(c["P"]) for c in cases] == heights
+        ref = [solo(B, c, **kw) for c in cases]
+        arena = sum(B.Engine.slot_bytes(c["P"], c["rec"].rs.s_cur if c["rec"] else 0) for c in cases) + \
+            B.Engine.slot_bytes(extra, 0)
+        with B.Engine(cap=9, arena_bytes=arena) as eng:
+            ws = [c["w0"].clone() for c in cases]
+            slots = {}
+            for k, c in enumerate(cases):
+                sl = eng.admit(c["P"], c["th"], c["xh"], c["g"], ws[k], c["rec"], B.solve_opts(**kw))
+                slots[sl] = k
+            w9 = torch.zeros(32 * 32, dtype=torch.float64, device=DEV)
+            with pytest.raises(B.BLError):
+                eng.admit(extra, np.zeros(2), w9, w9, w9, None, B.solve_opts())
+            with pytest.raises(B.BLError):
+                eng.retire(8)                        # nothing there
+            stats = {}
+            while slots:
+                for sl in eng.step():
+                    stats[slots.pop(sl)] = eng.retire(sl)
+    finally:
+        for c in cases:
+            B.bl_tile_rows_set(c["P"], 0)
     for k in range(len(cases)):
         w_ref, st_ref = ref[k]
         assert st_ref.status == B.BL_OK

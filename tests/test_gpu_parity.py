@@ -245,6 +245,40 @@ def test_recycled_cg_parity(B, stop):
             assert rel(host(w), wstar) <= 1e-8
 
 
+@pytest.mark.parametrize("kind,prec", [("tv", "fp64"), ("filters", "fp64"), ("tv", "mixed")])
+def test_recycled_cg_every_tile_height(B, kind, prec):
+    """The fused apply/residual kernels at 8, 16 and 32 rows per tile (70 x 90: ragged tiles in
+    both directions at every height) against the oracle's recycled CG after a fixed number of
+    iterations (FP64: 1e-10) and, in mixed precision, converged (1e-6 against the exact w)."""
+    wl, inst, prob, xh = (tv_case(70, 90, seed=55) if kind == "tv" else foe_case(70, 90, seed=56))
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-6, v_cap=24)
+    rs = recycle.refresh(hvp, lambda v: prob.jac_apply(xh, th, v), None, first["V"], s=6)
+    P = B.problem_from(wl, prec=prec)
+    k = 12
+    ref = krylov.recycled_cg(hvp, g, None, rs["U"], rs["C"], tol=0.0, max_iter=k)
+    wstar, _ = krylov.reference_solve(hvp, g)
+    try:
+        for rows in (8, 16, 32):
+            B.bl_tile_rows_set(P, rows)
+            assert B.bl_tile_rows(P) == rows
+            with B.Session(P, s_max=6, v_cap=24) as S:
+                upload_recycle(S, rs)
+                w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+                if prec == "fp64":
+                    S.solve(th, dev(xh), dev(g), w, tol=0.0, max_iter=k, store_basis=False,
+                            allow=(B.BL_E_NOT_CONVERGED,))
+                    assert rel(host(w), ref["w"]) <= 1e-10, rows
+                else:
+                    st = S.solve(th, dev(xh), dev(g), w, tol=1e-9, store_basis=False, rr_every=10)
+                    assert st.status == B.BL_OK
+                    assert rel(host(w), wstar) <= 1e-6, rows
+    finally:
+        B.bl_tile_rows_set(P, 0)
+
+
 def test_refresh_parity(B):
     wl, inst, prob, xh = tv_case(48, 40, seed=61)
     th = inst["theta0"]
