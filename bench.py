@@ -70,7 +70,7 @@ def apply_bytes_per_pixel(reg: str, prec: str, s: int, nf: int) -> int:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("tile.h", "common.h", "batch.hip"):
+    for f in ("tile.h", "common.h", "batch_tile.h"):
         with open(os.path.join(ROOT, "paper_2412_08264_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -286,7 +286,12 @@ def bench_sequence(args, B, torch, synth):
         refs.append(S.hypergradient(th, x, w))
     mixed = wl.prec == "mixed"
     Sh = B.Session(B.problem_from(wl, prec="mixed"), s_max=wl.s, v_cap=V_CAP, device=dev) if mixed else S
-    tiles = autotune_tiles(S, B, [(Sh.P, thetas[0], xhats[0], wl.s), (S.P, thetas[0], xhats[0], wl.s)])
+    if args.rows:   # a fixed tile height (profiling runs repeat the height a timed run chose)
+        for PP in (Sh.P, S.P):
+            B.bl_tile_rows_set(PP, args.rows)
+        tiles = {"fixed": args.rows}
+    else:
+        tiles = autotune_tiles(S, B, [(Sh.P, thetas[0], xhats[0], wl.s), (S.P, thetas[0], xhats[0], wl.s)])
     # threshold selection (untimed): loosest setting with every hypergradient within 1e-6
     variants = [("rgen_hg", Sh, SWEEP_HG), ("rgen_res", Sh, SWEEP_RESID), ("plain", S, SWEEP_RESID)]
     if mixed:
@@ -319,7 +324,7 @@ def bench_sequence(args, B, torch, synth):
     prec = "mixed" if mixed else "fp64"
     bpp = apply_bytes_per_pixel(wl.reg, prec, wl.s, wl.n_filters)
     kname = (f"k_b_apply<{'float' if mixed else 'double'}, {wl.blur_radius}, {0 if wl.reg == 'tv' else 1}, "
-             f"{B.bl_tile_rows(Sh.P) // 8}>")
+             f"{B.bl_tile_rows(Sh.P) // 8}, true>")
     desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
             f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
             f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad|"
@@ -492,7 +497,7 @@ def bench_batch(args, B, torch, synth):
     torch.cuda.synchronize()
     elp = time.perf_counter() - tp
     okp = sum(1 for e in perr if e <= 1e-6)
-    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'}, 5, 1, {best_rows // 8}>"
+    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'}, 5, 1, {best_rows // 8}, true>"
     out = base_line(args, value, el, "f32+f64" if prec == "mixed" else "f64",
                     {"workload": f"batch{len(wls)}: {len(wls)} filter images (8 x 7x7, blur r=5 sigma=3, noise 0.02), "
                                  f"sides {sorted(set(w.h for w in wls))}, sum n = {sum(w.n for w in wls)}, shared theta, "
@@ -787,7 +792,7 @@ def main():
                     "relative to the sample's previous hypergradient norm")
     ap.add_argument("--v-cap", dest="v_cap", type=int, default=V_CAP, help="serve: stored Krylov vectors per sample")
     ap.add_argument("--rows", type=int, default=0, choices=(0, 8, 16, 32),
-                    help="kernels-only: tile height of the solves (0: autotune)")
+                    help="tile height of the solves (0: autotune; kernels-only batch64: 0 means 32)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: a few recycled-CG iterations on the workload's shape at stand-in points "
                          "x* + 0.05 e' (no trajectory) plus a 64 MiB device copy for counter calibration")

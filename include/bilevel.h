@@ -177,7 +177,8 @@ bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
  * Batched and served Hessian solves.  An engine runs up to `cap` (<= 64) recycled-CG solves
  * side by side: each iteration is one launch of the fused apply kernel (H p with p.q and
  * C^T q) per group of solves with the same operator class (problems equal in every
- * bl_problem field but h, w) and tile height (bl_tile_rows; at most 8 groups at a time), and
+ * bl_problem field but h, w), tile height (bl_tile_rows) and recycling (s_cur > 0 or not; at
+ * most 16 groups at a time), and
  * one launch of the update kernel over all running solves, whatever their sizes, recycle
  * dimensions and iteration indices.  Every solve reduces only its own records in a fixed
  * order, so its iterates, iteration count and status are bitwise those of the same solve
@@ -203,7 +204,8 @@ bl_status bl_engine_destroy(bl_engine* engine);
  * Set-up work (FP64 residual, projection onto C) is enqueued at once.  Returns
  * BL_E_WORKSPACE (nothing enqueued) when no slot or no arena block of
  * bl_engine_slot_bytes() is free: retire a completed solve and try again; BL_E_ARG when the
- * problem would open a ninth (operator class, tile height) group among the admitted solves. */
+ * problem would open a 17th (operator class, tile height, recycling) group among the admitted
+ * solves. */
 bl_status bl_engine_admit(bl_engine* engine, const bl_problem* P, const double* theta_host, const double* xhat,
                           const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts, int* slot);
 /* Advance all running solves by at most max_iters iterations; with return_on_done, return
@@ -221,9 +223,10 @@ bl_status bl_engine_query(const bl_engine* engine, int* running, int* free_slots
  * (s = NULL: none). */
 size_t bl_batched_workspace_bytes(int nprob, const bl_problem* P, const int* s);
 /* nprob independent solves (P[k], theta[k], xhat[k], g[k], w[k], rs[k]; rs = NULL: plain CG
- * for all; at most 8 (operator class, tile height) groups) with shared options, advanced together (at most 64 at
- * a time; later ones are admitted as earlier ones finish).  out[k] gets the statistics of
- * solve k.  Returns BL_OK, or the first non-OK status of a solve. */
+ * for all; at most 16 (operator class, tile height, recycling) groups) with shared options,
+ * advanced together (at most 64 at a time; later ones are admitted as earlier ones finish).
+ * out[k] gets the statistics of solve k.  Returns BL_OK, or the first non-OK status of a
+ * solve. */
 bl_status bl_hessian_solve_batched(bl_ctx* ctx, int nprob, const bl_problem* P, const double* const* theta_host,
                                    const double* const* xhat, const double* const* g, double* const* w_inout,
                                    bl_recycle* rs, const bl_solve_opts* opts, void* ws, size_t ws_bytes,

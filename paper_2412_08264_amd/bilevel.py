@@ -346,8 +346,8 @@ def _aligned_workspace(nbytes: int, device):
 
 # --------------------------------------------------------------------------- batched / served solves
 class Engine:
-    """bl_engine: up to `cap` concurrent solves (up to 8 operator class / tile height groups) advanced
-    together."""
+    """bl_engine: up to `cap` concurrent solves (up to 16 groups of operator class, tile height and
+    recycling) advanced together."""
 
     def __init__(self, cap: int, arena_bytes: int, device=None, stream=None, ctx=None):
         import torch

@@ -222,24 +222,24 @@ __global__ void __launch_bounds__(NT) k_b_headers(const Slot* __restrict__ slots
     out[(size_t)idx * WPS + wd] = reinterpret_cast<const int*>(slots[idx].st)[wd];
 }
 
-hipError_t launch_b_residual(const Stencil& base, int rows, const Slot* slots, const BatchMap& M, int periodic,
-                             hipStream_t stream) {
+hipError_t launch_b_residual(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M,
+                             int periodic, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
     switch (rows) {
-        case QTY * 1: return launch_b_residual_q<1>(base, slots, M, periodic, stream);
-        case QTY * 2: return launch_b_residual_q<2>(base, slots, M, periodic, stream);
-        case QTY * 4: return launch_b_residual_q<4>(base, slots, M, periodic, stream);
+        case QTY * 1: return launch_b_residual_q<1>(base, rec, slots, M, periodic, stream);
+        case QTY * 2: return launch_b_residual_q<2>(base, rec, slots, M, periodic, stream);
+        case QTY * 4: return launch_b_residual_q<4>(base, rec, slots, M, periodic, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_b_apply(const Stencil& base, int rows, bool fp32, const Slot* slots, const BatchMap& M, int step,
-                          hipStream_t stream) {
+hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
+                          int step, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
     switch (rows) {
-        case QTY * 1: return launch_b_apply_q<1>(base, fp32, slots, M, step, stream);
-        case QTY * 2: return launch_b_apply_q<2>(base, fp32, slots, M, step, stream);
-        case QTY * 4: return launch_b_apply_q<4>(base, fp32, slots, M, step, stream);
+        case QTY * 1: return launch_b_apply_q<1>(base, rec, fp32, slots, M, step, stream);
+        case QTY * 2: return launch_b_apply_q<2>(base, rec, fp32, slots, M, step, stream);
+        case QTY * 4: return launch_b_apply_q<4>(base, rec, fp32, slots, M, step, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,6 +1,8 @@
 // Tile-grid kernels of the batched recycled CG (residual and apply), templated on the rows
-// per thread Q of the Hessian-vector tile (tiles of 32 x 8Q pixels), with the device helpers
-// the batch kernels share.  Each tile height is instantiated in a translation unit of its own.
+// per thread Q of the Hessian-vector tile (tiles of 32 x 8Q pixels) and on whether the solves
+// of the launch have a recycle space (REC; plain CG launches carry no projection code), with
+// the device helpers the batch kernels share.  Each tile height is instantiated in a
+// translation unit of its own.
 #pragma once
 
 #include <type_traits>
@@ -67,7 +69,7 @@ __device__ __forceinline__ const double* slot_rec(const Slot& sl, int which, int
 // ------------------------------------------------------------------ residual g - H w
 // r = g - H w in FP64 and the record [g.g, C^T r].  With `periodic` set (a scheduled
 // residual replacement) a slot that has already stopped is left alone.
-template <int R, int CLS, int Q>
+template <int R, int CLS, int Q, bool REC>
 __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __restrict__ slots, BatchMap M,
                                                    int periodic) {
     using L = QLayout<double, R, CLS, Q>;
@@ -97,7 +99,7 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
         if (o.in[k]) sl.r[o.g[k]] = ov[k];
     }
     block_partials(
-        sl.rec_res, 1 + sl.s,
+        sl.rec_res, REC ? 1 + sl.s : 1,
         [&](int k) {
             double acc = 0.0;
 #pragma unroll
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
 // and published by the reduction's barrier: uniform per block; a flag set by block 0 during
 // this launch follows from the same decision every block of the slot takes).
 constexpr int CPRE = 8;   // columns of C per pixel loaded before the (short) TV stencil
-template <typename T, int R, int CLS, int Q>
+template <typename T, int R, int CLS, int Q, bool REC>
 __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
     using L = QLayout<T, R, CLS, Q>;
     constexpr int QR = Q;
@@ -131,7 +133,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     SolveState* st = sl.st;
     const int j = step - sl.j0;
     if (threadIdx.x == 0) sdone = st->done;
-    const int s = sl.s, nz = sl.nz;
+    const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     int nb;
     const double* rec = slot_rec(sl, 2, nb);
     reduce_partials(rec, nb, 1 + nz, tot);
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const Own<Q> o = own_pixels<Q>(S.h, S.w, r0, c0);
     // the filter stencil is long enough to hide the C loads issued after it, and the registers
     // of a prefetch would cost occupancy there
-    constexpr int CP = CLS == TC_TV ? CPRE : 1;
+    constexpr int CP = !REC ? 1 : (CLS == TC_TV ? CPRE : 1);
     double ri[QR], pi[QR], cpre[CP][QR];
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
@@ -232,36 +234,40 @@ static void allow_lds_b(K kernel, size_t bytes) {
 static inline dim3 map_grid(const BatchMap& M) { return dim3(M.off[M.ns]); }
 
 template <int Q>
-hipError_t launch_b_residual_q(const Stencil& base, const Slot* slots, const BatchMap& M, int periodic,
+hipError_t launch_b_residual_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, int periodic,
                                hipStream_t stream) {
     q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
         const size_t lds = QLayout<double, RR, CC, Q>::bytes;
-        allow_lds_b(k_b_residual<RR, CC, Q>, lds);
-        hipLaunchKernelGGL((k_b_residual<RR, CC, Q>), map_grid(M), dim3(NT), lds, stream, base, slots, M, periodic);
+        auto go = [&](auto kern) {
+            allow_lds_b(kern, lds);
+            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, periodic);
+        };
+        if (rec) go(k_b_residual<RR, CC, Q, true>);
+        else go(k_b_residual<RR, CC, Q, false>);
     });
     return hipGetLastError();
 }
 
 template <int Q>
-hipError_t launch_b_apply_q(const Stencil& base, bool fp32, const Slot* slots, const BatchMap& M, int step,
+hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot* slots, const BatchMap& M, int step,
                             hipStream_t stream) {
     q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
+        auto go = [&](auto kern, size_t lds) {
+            allow_lds_b(kern, lds);
+            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, step);
+        };
+        constexpr size_t l32 = QLayout<float, RR, CC, Q>::bytes, l64 = QLayout<double, RR, CC, Q>::bytes;
         if (fp32) {
-            const size_t lds = QLayout<float, RR, CC, Q>::bytes;
-            allow_lds_b(k_b_apply<float, RR, CC, Q>, lds);
-            hipLaunchKernelGGL((k_b_apply<float, RR, CC, Q>), map_grid(M), dim3(NT), lds, stream, base, slots, M,
-                               step);
+            if (rec) go(k_b_apply<float, RR, CC, Q, true>, l32);
+            else go(k_b_apply<float, RR, CC, Q, false>, l32);
         } else {
-            const size_t lds = QLayout<double, RR, CC, Q>::bytes;
-            allow_lds_b(k_b_apply<double, RR, CC, Q>, lds);
-            hipLaunchKernelGGL((k_b_apply<double, RR, CC, Q>), map_grid(M), dim3(NT), lds, stream, base, slots, M,
-                               step);
+            if (rec) go(k_b_apply<double, RR, CC, Q, true>, l64);
+            else go(k_b_apply<double, RR, CC, Q, false>, l64);
         }
     });
     return hipGetLastError();
 }
-
 
 }  // namespace bl

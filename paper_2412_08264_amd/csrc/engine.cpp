@@ -265,12 +265,14 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     const int rows = c->force_rows ? c->force_rows : tile_rows(P);
     int gid = -1;
     for (int gi = 0; gi < (int)groups.size() && gid < 0; ++gi)
-        if (groups[gi].users > 0 && same_class(&groups[gi].cls, P) && groups[gi].rows == rows) gid = gi;
+        if (groups[gi].users > 0 && same_class(&groups[gi].cls, P) && groups[gi].rows == rows &&
+            groups[gi].rec == (s > 0))
+            gid = gi;
     for (int gi = 0; gi < (int)groups.size() && gid < 0; ++gi)
         if (groups[gi].users == 0) gid = gi;   // reuse an idle entry
     if (gid < 0) {
         if ((int)groups.size() >= MAX_GROUPS)
-            return c->err = "more than 8 (operator class, tile height) groups in one batch", BL_E_ARG;
+            return c->err = "more than 16 (operator class, tile height, recycling) groups in one batch", BL_E_ARG;
         groups.emplace_back();
         gid = (int)groups.size() - 1;
     }
@@ -280,6 +282,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         class_stencil(P, grp.base);
         grp.fp32 = P->prec == BL_PREC_MIXED;
         grp.rows = rows;
+        grp.rec = s > 0;
     }
     const Stencil& base = grp.base;
     double lam, gam2;
@@ -358,7 +361,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     h.rr_js.assign(1, 0);   // the first test is on the FP64 residual of the set-up
     // set-up: r = g - H w0 (FP64), c0 = C^T r, w += U c0, r -= C c0
     const std::vector<int> one{idx};
-    HIPCHK(launch_b_residual(base, rows, d_slots, make_map(S, one, true), 0, c->stream));
+    HIPCHK(launch_b_residual(base, rows, s > 0, d_slots, make_map(S, one, true), 0, c->stream));
     if (v.fold_res) {
         BatchMap f{};
         f.ns = 1;
@@ -377,7 +380,8 @@ bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic) {
         for (int i : idx)
             if (S[i].group == gi) mine.push_back(i);
         if (!mine.empty())
-            HIPCHK(launch_b_residual(groups[gi].base, groups[gi].rows, d_slots, make_map(S, mine, true), periodic,
+            HIPCHK(launch_b_residual(groups[gi].base, groups[gi].rows, groups[gi].rec, d_slots, make_map(S, mine, true),
+                                     periodic,
                                      c->stream));
     }
     BatchMap f{};
@@ -426,7 +430,7 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
         }
         for (const Group& grp : groups)
             if (grp.tmap.ns)
-                HIPCHK(launch_b_apply(grp.base, grp.rows, grp.fp32, d_slots, grp.tmap, step, c->stream));
+                HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, step, c->stream));
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], c->stream));
         if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, c->stream));
         HIPCHK(launch_b_update(d_slots, pmap, step, c->stream));

@@ -95,12 +95,13 @@ struct SolveSpec {
     const bl_solve_opts* o;
 };
 
-// Recycled CG over up to `cap` concurrent solves of up to MAX_GROUPS operator classes.  Each
-// iteration is one apply launch per class with running solves and one update launch over all
+// Recycled CG over up to `cap` concurrent solves in up to MAX_GROUPS groups (operator class,
+// tile height, with or without a recycle space).  Each iteration is one apply launch per group
+// with running solves and one update launch over all
 // running solves; the host enqueues chunks of POLL iterations and reads the solves' stop flags
 // one chunk behind, so the device never waits for the host.  A solve's arithmetic and
 // decisions do not depend on the others.
-constexpr int MAX_GROUPS = 8;
+constexpr int MAX_GROUPS = 16;
 
 class Batch {
 public:
@@ -111,11 +112,12 @@ public:
     char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES]
     hipEvent_t poll_ev[2] = {};
 
-    struct Group {                 // one operator class and tile height: stencil template, precision
+    struct Group {                 // operator class, tile height, recycling: stencil template, precision
         bl_problem cls{};
         bl::Stencil base{};
         bool fp32 = false;
         int rows = 0;
+        bool rec = false;          // solves with a recycle space (projection code) or plain CG
         int users = 0;             // slots in use
         bl::BatchMap tmap{};       // tile map of its running slots
     };

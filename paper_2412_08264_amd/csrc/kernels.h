@@ -30,20 +30,21 @@ hipError_t launch_sub(int n, const double* a, const double* b, double* out, hipS
 
 // batch.hip: recycled CG over a batch of slots (one launch per half-iteration).  The tile-grid
 // kernels take the tile height in rows (8, 16 or 32); batch_q{1,2,4}.hip instantiate them.
-hipError_t launch_b_residual(const Stencil& base, int rows, const Slot* slots, const BatchMap& M, int periodic,
-                             hipStream_t stream);
-hipError_t launch_b_apply(const Stencil& base, int rows, bool fp32, const Slot* slots, const BatchMap& M, int step,
-                          hipStream_t stream);
+// `rec`: the slots of the launch have recycle spaces (all of them, or none).
+hipError_t launch_b_residual(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M,
+                             int periodic, hipStream_t stream);
+hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
+                          int step, hipStream_t stream);
 template <int Q>
-hipError_t launch_b_residual_q(const Stencil& base, const Slot* slots, const BatchMap& M, int periodic,
+hipError_t launch_b_residual_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, int periodic,
                                hipStream_t stream);
 template <int Q>
-hipError_t launch_b_apply_q(const Stencil& base, bool fp32, const Slot* slots, const BatchMap& M, int step,
+hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot* slots, const BatchMap& M, int step,
                             hipStream_t stream);
-#define BL_TILE_EXTERN(Q)                                                                                  \
-    extern template hipError_t launch_b_residual_q<Q>(const Stencil&, const Slot*, const BatchMap&, int,    \
-                                                      hipStream_t);                                         \
-    extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, const Slot*, const BatchMap&, int, \
+#define BL_TILE_EXTERN(Q)                                                                                        \
+    extern template hipError_t launch_b_residual_q<Q>(const Stencil&, bool, const Slot*, const BatchMap&, int,    \
+                                                      hipStream_t);                                               \
+    extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, bool, const Slot*, const BatchMap&, int, \
                                                    hipStream_t);
 BL_TILE_EXTERN(1)
 BL_TILE_EXTERN(2)

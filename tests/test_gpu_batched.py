@@ -176,15 +176,18 @@ def test_engine_continuous_admission_bitwise(B, kind, prec):
 
 
 def test_engine_mixes_operator_classes(B):
-    """TV and filter solves in FP64 and mixed precision, each class at two tile heights, share
-    one engine (one apply launch per (class, height) group, one update launch for all) and each
-    equals its solo run bitwise; a ninth group is refused while eight are admitted."""
-    cases = [make_case(B, "tv", 36, 44, 5, 401), make_case(B, "filters", 40, 36, 4, 402),
-             make_case(B, "filters", 32, 48, 6, 403, prec="mixed"), make_case(B, "tv", 50, 30, 0, 404, prec="mixed"),
-             make_case(B, "tv", 64, 70, 3, 405), make_case(B, "filters", 70, 66, 2, 406),
-             make_case(B, "filters", 66, 72, 5, 407, prec="mixed"), make_case(B, "tv", 72, 64, 4, 408, prec="mixed")]
-    # the first four (size class 10 or 11) on 8-row tiles, the last four (size class 12) on 32
-    heights = [8, 8, 8, 8, 32, 32, 32, 32]
+    """TV and filter solves in FP64 and mixed precision, each class at two tile heights, with
+    and without recycle spaces, share one engine (one apply launch per (class, height,
+    recycling) group, one update launch for all) and each equals its solo run bitwise; a 17th
+    group is refused while sixteen are admitted."""
+    base = [("tv", 36, 44, "fp64"), ("filters", 40, 36, "fp64"), ("filters", 32, 48, "mixed"),
+            ("tv", 50, 30, "mixed"), ("tv", 64, 70, "fp64"), ("filters", 70, 66, "fp64"),
+            ("filters", 66, 72, "mixed"), ("tv", 72, 64, "mixed")]
+    # each shape once with a recycle space (s = 2..5) and once without (s = 0)
+    cases = [make_case(B, kind, h, w, s, 401 + 2 * k + (s == 0), prec=prec)
+             for k, (kind, h, w, prec) in enumerate(base) for s in (2 + k % 4, 0)]
+    # the first eight (size class 10) on 8-row tiles, the last eight (size class 12) on 32
+    heights = [8] * 8 + [32] * 8
     kw = dict(tol=1e-9, rr_every=8, store_basis=False)
     extra = B.bl_problem(32, 32, 3, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)   # another blur radius
     try:
@@ -194,7 +197,7 @@ def test_engine_mixes_operator_classes(B):
         ref = [solo(B, c, **kw) for c in cases]
         arena = sum(B.Engine.slot_bytes(c["P"], c["rec"].rs.s_cur if c["rec"] else 0) for c in cases) + \
             B.Engine.slot_bytes(extra, 0)
-        with B.Engine(cap=9, arena_bytes=arena) as eng:
+        with B.Engine(cap=17, arena_bytes=arena) as eng:
             ws = [c["w0"].clone() for c in cases]
             slots = {}
             for k, c in enumerate(cases):
@@ -204,7 +207,7 @@ def test_engine_mixes_operator_classes(B):
             with pytest.raises(B.BLError):
                 eng.admit(extra, np.zeros(2), w9, w9, w9, None, B.solve_opts())
             with pytest.raises(B.BLError):
-                eng.retire(8)                        # nothing there
+                eng.retire(16)                       # nothing there
             stats = {}
             while slots:
                 for sl in eng.step():
