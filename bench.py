@@ -178,10 +178,13 @@ def make_trajectory(ctx, P, B, wl, torch, y, xs, theta0, outer, gtol=1e-8):
     return thetas, xhats
 
 
-def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL, rr_every=50):
+def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL, rr_every=50,
+                 first_tol=RESID_TOL):
     """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain'; thr: the stopping
     threshold (residual tolerance, or the error-estimate threshold relative to the previous
-    hypergradient norm).  Returns per-solve records."""
+    hypergradient norm); first_tol: residual tolerance of the error-estimate variant's first
+    system, which has no recycle space yet (the plain variant's threshold).  Returns per-solve
+    records."""
     S.reset()
     w = torch.zeros_like(xs)
     prev_hg = None
@@ -196,7 +199,7 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
                          rr_every=rr_every)
         else:
             # first system of the error-estimate variant (no recycle space yet): residual test
-            st = S.solve(th, x, g, w, tol=RESID_TOL if mode == "rgen_hg" else thr,
+            st = S.solve(th, x, g, w, tol=first_tol if mode == "rgen_hg" else thr,
                          store_basis=(mode != "plain"), recycle=(mode != "plain"), rr_every=rr_every)
         hg = S.hypergradient(th, x, w)
         t1 = time.perf_counter()
@@ -207,18 +210,19 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
     return recs
 
 
-def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep):
+def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep, first_tol=RESID_TOL):
     for thr in sweep:
-        rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr)
+        rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr, first_tol=first_tol)
         if all(r["err"] <= 1e-6 and r["status"] == 0 for r in rr):
             return thr
     return sweep[-1]
 
 
-def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=None):
+def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=None, first_tol=RESID_TOL):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat, thr=thr) for _ in range(steps)]
+    recs = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat, thr=thr, first_tol=first_tol)
+            for _ in range(steps)]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
@@ -297,25 +301,29 @@ def bench_sequence(args, B, torch, synth):
     if mixed:
         variants.append(("rgen_hg_fp64", S, SWEEP_HG))
     chosen = {}
-    for name, SS, sweep in variants:
-        chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, name.replace("_fp64", ""), refs, sweep)
+    # plain first: its threshold is also the first-system tolerance of the estimate variants
+    for name, SS, sweep in [variants[2]] + [v for v in variants if v[0] != "plain"]:
+        chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, name.replace("_fp64", ""), refs, sweep,
+                                        first_tol=chosen.get("plain", RESID_TOL))
         log(f"[bench] {name}: threshold {chosen[name]:g}")
+    ftol = chosen["plain"]
     for _ in range(args.warmup):
-        run_sequence(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, thr=chosen["rgen_hg"])
+        run_sequence(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, thr=chosen["rgen_hg"], first_tol=ftol)
     # timed: headline (recycled + error-estimate stop), per-kernel events on the library's stream
     Sh.set_timing(2)
     Sh.kernel_times(reset=True)
     lat = []
     recs, el, ok, total = timed_passes(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, chosen["rgen_hg"],
-                                       args.steps, lat)
+                                       args.steps, lat, first_tol=ftol)
     kt = Sh.kernel_times(reset=True)
     Sh.set_timing(0)
     value = ok / el
     extra = {}
     for name, SS, _ in variants[1:]:
         mode = name.replace("_fp64", "")
-        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name])
-        rr, elm, okm, totm = timed_passes(SS, B, torch, thetas, xhats, xs, mode, refs, chosen[name], args.steps)
+        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name], first_tol=ftol)
+        rr, elm, okm, totm = timed_passes(SS, B, torch, thetas, xhats, xs, mode, refs, chosen[name], args.steps,
+                                          first_tol=ftol)
         extra[name] = {"solves_per_s": okm / elm, "threshold": chosen[name],
                        "iters_per_sequence": sum(r["iters"] for r in rr[0]),
                        "max_rel_err": max(r["err"] for r in rr[0]), "passing": f"{okm}/{totm}"}
@@ -327,7 +335,8 @@ def bench_sequence(args, B, torch, synth):
              f"{B.bl_tile_rows(Sh.P) // 8}, true>")
     desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
             f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
-            f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad|"
+            f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad| (first system: "
+            f"residual {ftol:g}, as plain CG)"
             + (", FP32 stencils + FP64 rest with residual replacement" if mixed else ""))
     out = base_line(args, value, el, "f32+f64" if mixed else "f64",
                     {"workload": desc, "outer_steps": outer, "s": wl.s, "v_cap": V_CAP, "n": wl.n, "tiles": tiles},
@@ -407,24 +416,35 @@ def bench_batch(args, B, torch, synth):
     # refreshes and hypergradients of the images run concurrently on a pool of contexts
     pool = B.ContextPool(P64, 20, V_CAP, args.workers, dev)
 
-    def one_pass(mode, thr, stats=None):
-        """The sequence once: mode 'rgen_hg' (refresh + error-estimate stop), 'plain' (residual)."""
+    phase_ms = {"refresh": 0.0, "solve": 0.0, "hypergradient": 0.0}
+
+    def one_pass(mode, thr, stats=None, first_tol=RESID_TOL, phases=None):
+        """The sequence once: mode 'rgen_hg' (refresh + error-estimate stop; first step: residual
+        stop at first_tol, as plain CG), 'plain' (residual stop at thr)."""
         for r in recs:
             r.rs.s_cur = 0
             r.rs.v_cur = 0
         ws = [torch.zeros_like(x) for x in xs]
         prev = [None] * len(Ps)
         errs, iters = [], []
+
+        def mark(name, t0):
+            if phases is not None:
+                torch.cuda.synchronize()
+                phases[name] += (time.perf_counter() - t0) * 1e3
+            return time.perf_counter()
         for i in range(T):
             xh = xhats[i]
+            tp = time.perf_counter()
             if mode != "plain" and i > 0:
                 pool.map(lambda c, k: c.refresh_p(P64[k], recs[k], thetas[i], xh[k], s=20),
                          [(k,) for k in range(len(P64))])
+            tp = mark("refresh", tp)
             slot_of = {}
             for k, P in enumerate(Ps):
                 use_hg = mode == "rgen_hg" and recs[k].rs.s_cur > 0 and prev[k] is not None
                 o = B.solve_opts(stop="hgerr" if use_hg else "resid", hg_tol=thr * prev[k] if use_hg else 0.0,
-                                 tol=RESID_TOL if mode != "plain" else thr, store_basis=mode != "plain",
+                                 tol=first_tol if mode != "plain" else thr, store_basis=mode != "plain",
                                  rr_every=50)
                 sl = eng.admit(P, thetas[i], xh[k], xh[k] - xs[k], ws[k], recs[k] if mode != "plain" else None, o)
                 assert sl is not None, "engine arena too small"
@@ -436,22 +456,25 @@ def bench_batch(args, B, torch, synth):
                     iters.append(st.iters)
                     if stats is not None:
                         stats.append((k, st.iters))
+            tp = mark("solve", tp)
             hg = pool.map(lambda c, k: c.hypergradient_p(P64[k], thetas[i], xh[k], ws[k]),
                           [(k,) for k in range(len(P64))])
+            mark("hypergradient", tp)
             for k in range(len(Ps)):
                 prev[k] = float(np.linalg.norm(hg[k]))
                 errs.append(rel_err(hg[k], refs[i][k]))
         return errs, iters
 
     chosen = {}
-    for mode, sweep in (("rgen_hg", SWEEP_HG), ("plain", SWEEP_RESID)):
+    for mode, sweep in (("plain", SWEEP_RESID), ("rgen_hg", SWEEP_HG)):
         chosen[mode] = sweep[-1]
         for thr in sweep:
-            errs, _ = one_pass(mode, thr)
+            errs, _ = one_pass(mode, thr, first_tol=chosen.get("plain", RESID_TOL))
             if max(errs) <= 1e-6:
                 chosen[mode] = thr
                 break
         log(f"[bench] batch {mode}: threshold {chosen[mode]:g}")
+    ftol = chosen["plain"]
     # tile heights: the whole batch shares the chip, so the autotuner times whole passes, one
     # per height for every image (untimed)
     search = {}
@@ -460,7 +483,7 @@ def bench_batch(args, B, torch, synth):
             B.bl_tile_rows_set(P, rows)
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        one_pass("rgen_hg", chosen["rgen_hg"])
+        one_pass("rgen_hg", chosen["rgen_hg"], first_tol=ftol)
         torch.cuda.synchronize()
         search[rows] = (time.perf_counter() - ts) * 1e3
     best_rows = min(search, key=search.get)
@@ -468,14 +491,15 @@ def bench_batch(args, B, torch, synth):
         B.bl_tile_rows_set(P, best_rows)
     log(f"[bench] batch tile heights: {best_rows} rows (ms per pass {search})")
     for _ in range(args.warmup):
-        one_pass("rgen_hg", chosen["rgen_hg"])
+        one_pass("rgen_hg", chosen["rgen_hg"], first_tol=ftol)
+    one_pass("rgen_hg", chosen["rgen_hg"], first_tol=ftol, phases=phase_ms)   # phase split (untimed)
     ctx.set_timing(2)
     ctx.kernel_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     allerr, alliters, stats = [], [], []
     for _ in range(args.steps):
-        errs, its = one_pass("rgen_hg", chosen["rgen_hg"], stats)
+        errs, its = one_pass("rgen_hg", chosen["rgen_hg"], stats, first_tol=ftol)
         allerr += errs
         alliters += its
     torch.cuda.synchronize()
@@ -508,6 +532,7 @@ def bench_batch(args, B, torch, synth):
                     iters_per_pass={"rgen_hg": sum(alliters) // args.steps, "plain": sum(piters) // args.steps},
                     plain_cg={"solves_per_s": okp / elp, "threshold": chosen["plain"], "passing": f"{okp}/{len(perr)}"},
                     speedup_vs_plain_cg=value / max(okp / elp, 1e-30),
+                    phase_ms_per_pass={k: round(v, 1) for k, v in phase_ms.items()},
                     roofline=roofline(kname, total_bytes / launches, kt, "batch64"))
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")

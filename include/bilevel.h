@@ -86,7 +86,8 @@ typedef struct {
     double tol;              /* residual test ||r|| <= tol ||g||                              */
     double hg_tol;           /* error-estimate test ||mu . (Z^T r)|| <= hg_tol (absolute)     */
     int max_iter;
-    int check_every;         /* the stop test runs at iterations j with j % check_every == 0 */
+    int check_every;         /* the stop test runs at iterations j with j % check_every == 0; */
+                             /* the estimate's Z^T r is formed on those iterations only      */
     int rr_every;            /* residual replacement period in mixed precision (0 = off)     */
     int store_basis;         /* store normalised residuals into rs->V                         */
 } bl_solve_opts;
@@ -104,7 +105,7 @@ typedef struct {
     double res_norm;         /* final recursive residual norm                                 */
     double res0_norm;        /* residual norm after the recycle-space projection             */
     double g_norm;
-    double est;              /* last hypergradient-error estimate (NaN if unavailable)        */
+    double est;              /* estimate at the last tested iteration (NaN if unavailable)    */
     double ms[4];            /* wall-clock phases (ms), filled when timing is enabled         */
 } bl_stats;
 

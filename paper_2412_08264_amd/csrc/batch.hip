@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
         sl.r[i] = ri;
     }
     block_partials(
-        sl.rec_upd, 1 + nz,
+        sl.rec_upd, 1 + zr_width(sl.st, nz, 0),
         [&](int k) -> double {
             if (!in) return 0.0;
             return k == 0 ? ri * ri : sl.Z[(size_t)(k - 1) * n + i] * ri;
@@ -41,7 +41,8 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
 }
 
 // Iteration j, second half: sigma, e from the apply records; alpha = rho_j / sigma;
-// w += alpha p;  r -= alpha (q - C e);  z -= alpha e;  record [r.r, Z^T r].
+// w += alpha p;  r -= alpha (q - C e);  z -= alpha e;  record [r.r, Z^T r] (Z^T r only when
+// the test of iteration j + 1 evaluates the error estimate).
 constexpr int UPRE = 24;
 __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, int step) {
     __shared__ double tot[NT];
@@ -52,17 +53,17 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     SolveState* st = sl.st;
     const int j = step - sl.j0;
     if (threadIdx.x == 0) sdone = st->done;
-    const int s = sl.s, nz = sl.nz, n = sl.n;
+    const int s = sl.s, n = sl.n;
     const int i = m.y * NT + threadIdx.x;
     const bool in = i < n;
     const double* p = sl.p[(j + 1) & 1];
     const double wi = in ? sl.w[i] : 0.0, pi = in ? p[i] : 0.0, ri0 = in ? sl.r[i] : 0.0, qi = in ? sl.q[i] : 0.0;
     double cpre[UPRE], zpre[UPRE];
 #pragma unroll
-    for (int k = 0; k < UPRE; ++k) {
-        cpre[k] = (in && k < s) ? sl.C[(size_t)k * n + i] : 0.0;
-        zpre[k] = (in && k < nz) ? sl.Z[(size_t)k * n + i] : 0.0;
-    }
+    for (int k = 0; k < UPRE; ++k) cpre[k] = (in && k < s) ? sl.C[(size_t)k * n + i] : 0.0;
+    const int zw = zr_width(st, sl.nz, j + 1);
+#pragma unroll
+    for (int k = 0; k < UPRE; ++k) zpre[k] = (in && k < zw) ? sl.Z[(size_t)k * n + i] : 0.0;
     int nb;
     const double* rec = slot_rec(sl, 1, nb);
     reduce_partials(rec, nb, 1 + s, tot);
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
         sl.r[i] = ri;
     }
     block_partials(
-        sl.rec_upd, 1 + nz,
+        sl.rec_upd, 1 + zw,
         [&](int k) -> double {
             if (!in) return 0.0;
             if (k == 0) return ri * ri;
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots
         sl.r[i] = ri;
     }
     block_partials(
-        sl.rec_upd, 1 + nz,
+        sl.rec_upd, 1 + zr_width(sl.st, nz, step - sl.j0),
         [&](int k) -> double {
             if (!in) return 0.0;
             return k == 0 ? ri * ri : sl.Z[(size_t)(k - 1) * n + i] * ri;
@@ -160,8 +161,9 @@ __global__ void __launch_bounds__(NT) k_b_finish(const Slot* __restrict__ slots,
     if (i < sl.n) sl.w[i] += combo(sl.U, sl.n, i, z, s);
 }
 
-// Fold the records of kind `which` (0 residual, 1 apply, 2 update): one block per listed slot.
-__global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which) {
+// Fold the records of kind `which` (0 residual, 1 apply, 2 update, read by the test of step
+// `step`): one block per listed slot.
+__global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which, int step) {
     __shared__ double tot[NT];
     const Slot& sl = slots[M.slot[blockIdx.x]];
     int nb, nv;
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, B
         rec = sl.rec_app;
     } else {
         nb = sl.npix;
-        nv = 1 + sl.nz;
+        nv = 1 + zr_width(sl.st, sl.nz, step - sl.j0);
         rec = sl.rec_upd;
     }
     reduce_partials(rec, nb, nv, tot);
@@ -264,9 +266,9 @@ hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t str
     hipLaunchKernelGGL(k_b_finish, map_grid(M), dim3(NT), 0, stream, slots, M);
     return hipGetLastError();
 }
-hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, hipStream_t stream) {
+hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, int step, hipStream_t stream) {
     if (list.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_fold, dim3(list.ns), dim3(NT), 0, stream, slots, list, which);
+    hipLaunchKernelGGL(k_b_fold, dim3(list.ns), dim3(NT), 0, stream, slots, list, which, step);
     return hipGetLastError();
 }
 hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,

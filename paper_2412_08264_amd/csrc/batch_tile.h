@@ -136,18 +136,19 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     int nb;
     const double* rec = slot_rec(sl, 2, nb);
-    reduce_partials(rec, nb, 1 + nz, tot);
+    const int zw = REC ? zr_width(st, nz, j) : 0;
+    reduce_partials(rec, nb, 1 + zw, tot);
     if (sdone) return;
     const double rho_prev = j > 0 ? st->rho2[(j - 1) & 1] : 1.0;
     const bool store_basis = st->store_basis && j < st->v_cap;
     const double rho = tot[0];
     const bool restart = j > 0 && st->rr_j == j && rho > rho_prev;
-    const Decision dec = decide(st, j, rho, tot + 1);
+    const Decision dec = decide(st, j, rho, tot + 1, zw > 0);
     if (m.y == 0) {
-        for (int k = threadIdx.x; k < nz; k += NT) st->zr[k] = tot[1 + k];
+        for (int k = threadIdx.x; k < zw; k += NT) st->zr[k] = tot[1 + k];
         if (threadIdx.x == 0) {
             st->rho2[j & 1] = rho;
-            st->est = dec.est;
+            if (zw) st->est = dec.est;
             st->iters = j;
             if (j == 0) st->res0 = sqrt(rho);
             if (dec.done) {

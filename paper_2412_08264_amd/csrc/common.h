@@ -206,8 +206,15 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
     __syncthreads();
 }
 
+// Width of the residual record that the test of iteration j reads: r.r, and Z^T r (nz values)
+// only when that test evaluates the error estimate (every check_every-th iteration), so the
+// columns of Z are read on tested iterations only.
+__device__ __forceinline__ int zr_width(const SolveState* st, int nz, int j) {
+    return (nz > 0 && j % st->check_every == 0) ? nz : 0;
+}
+
 // Stop decision after j completed iterations from the reduced residual record (r.r and,
-// with the error estimate, Z^T r).  Order of tests: non-finite; exact zero residual; only
+// when the record holds it, Z^T r).  Order of tests: non-finite; exact zero residual; only
 // every check_every iterations: the hypergradient-error estimate ||mu . Z^T r|| <= hg_tol
 // (when enabled) or ||r|| <= tol ||g||; then the iteration limit.
 struct Decision {
@@ -216,9 +223,9 @@ struct Decision {
     double est;
 };
 
-__device__ __forceinline__ Decision decide(const SolveState* st, int j, double rho, const double* zr) {
+__device__ __forceinline__ Decision decide(const SolveState* st, int j, double rho, const double* zr, bool have_zr) {
     Decision d{false, BL_OK, NAN};
-    if (st->hgerr_on) {
+    if (st->hgerr_on && have_zr) {
         double acc = 0.0;
         for (int k = 0; k < st->s; ++k) {
             const double t = st->mu[k] * zr[k];

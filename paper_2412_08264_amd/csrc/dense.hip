@@ -51,12 +51,32 @@ __global__ void __launch_bounds__(NT) k_gram(int n, int t1, int t2, const double
         }
 }
 
-__global__ void k_sum_chunks(int nchunks, int len, const double* __restrict__ part, double* __restrict__ out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= len) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * len + k];
-    out[k] = s;
+// out[k] = sum over chunks c of part[c * len + k].  A block handles 16 consecutive outputs with
+// 16 thread groups; group g sums chunks g, g + 16, ... (8 loads in flight), then the 16 group
+// sums are added in group order (a fixed order: deterministic).
+constexpr int SC_OUT = 16;
+__global__ void __launch_bounds__(NT) k_sum_chunks(int nchunks, int len, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+    __shared__ double gs[NT / SC_OUT][SC_OUT];
+    const int o = threadIdx.x % SC_OUT, g = threadIdx.x / SC_OUT;
+    const int k = blockIdx.x * SC_OUT + o;
+    constexpr int NG = NT / SC_OUT;
+    double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (k < len) {
+        int c = g;
+        for (; c + 7 * NG < nchunks; c += 8 * NG) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a8[u] += part[(size_t)(c + u * NG) * len + k];
+        }
+        for (int u = 0; c < nchunks; c += NG, ++u) a8[u & 7] += part[(size_t)c * len + k];
+    }
+    gs[g][o] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+    __syncthreads();
+    if (g == 0 && k < len) {
+        double sum = 0.0;
+        for (int q = 0; q < NG; ++q) sum += gs[q][o];
+        out[k] = sum;
+    }
 }
 
 int gram_chunks(int n) {
@@ -73,38 +93,69 @@ hipError_t launch_gram(int n, int t1, int t2, const double* A, const double* B, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int len = t1 * t2;
-    hipLaunchKernelGGL(k_sum_chunks, dim3((len + 255) / 256), dim3(256), 0, stream, nch, len, part, out);
+    hipLaunchKernelGGL(k_sum_chunks, dim3((len + SC_OUT - 1) / SC_OUT), dim3(NT), 0, stream, nch, len, part, out);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ Out = A X (tall x small)
-// A: n x t (ld n); X: t x k (ld ldx); Out: n x k (ld n).  One row per thread, 16 outputs
-// at a time, X staged in LDS.
-constexpr int GT_K = 16;
+// A: n x t (ld n); X: t x k (ld ldx); Out: n x k (ld n).  A dense contraction, so it runs on the
+// FP64 matrix cores (16 x 16 x 4 products): each wave owns 16 rows of Out and up to 128 of its
+// columns (8 accumulator tiles), reads its 16 rows of A once per 128 columns, and takes the
+// rows of X from LDS, staged 32 at a time.  Lane l holds A[row0 + l % 16][t0 + l / 16] and
+// X[t0 + l / 16][c + l % 16]; element r of its accumulator tile is Out[row0 + l / 16 + 4 r][c + l % 16],
+// r = 0..3 (the FP64 output layout, checked on the device).
+constexpr int GM_COLS = 128;
+constexpr int GM_TROWS = 32;
 constexpr int GT_TMAX = 256;
+typedef double gm_acc __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(NT) k_gemm_tall(int n, int t, int k, const double* __restrict__ A,
                                                   const double* __restrict__ X, int ldx, double* __restrict__ Out) {
-    __shared__ double Xs[GT_TMAX * GT_K];
-    const int i = blockIdx.x * NT + threadIdx.x;
-    for (int k0 = 0; k0 < k; k0 += GT_K) {
-        const int kk = min(GT_K, k - k0);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < t * GT_K; idx += NT) {
-            const int j = idx / GT_K, c = idx - j * GT_K;
-            Xs[idx] = (c < kk) ? X[(size_t)(k0 + c) * ldx + j] : 0.0;
-        }
-        __syncthreads();
-        if (i < n) {
-            double acc[GT_K];
+    __shared__ double Xs[GM_TROWS][GM_COLS + 2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int row0 = (blockIdx.x * NWAVE + wave) * 16;
+    const int arow = row0 + li;
+    for (int c0 = 0; c0 < k; c0 += GM_COLS) {
+        const int kc = min(GM_COLS, k - c0);
+        const int ntile = (kc + 15) / 16;
+        gm_acc acc[GM_COLS / 16];
 #pragma unroll
-            for (int c = 0; c < GT_K; ++c) acc[c] = 0.0;
-            for (int j = 0; j < t; ++j) {
-                const double a = A[(size_t)j * n + i];
+        for (int q = 0; q < GM_COLS / 16; ++q) acc[q] = gm_acc{0.0, 0.0, 0.0, 0.0};
+        for (int t0 = 0; t0 < t; t0 += GM_TROWS) {
+            const int tr = min(GM_TROWS, t - t0);
+            // this chunk's 32 rows of A for the wave's 16 rows (8 loads in flight per lane)
+            double av[GM_TROWS / 4];
 #pragma unroll
-                for (int c = 0; c < GT_K; ++c) acc[c] += a * Xs[j * GT_K + c];
+            for (int u = 0; u < GM_TROWS / 4; ++u) {
+                const int tt = 4 * u + lk;
+                av[u] = (tt < tr && arow < n) ? A[(size_t)(t0 + tt) * n + arow] : 0.0;
             }
-            for (int c = 0; c < kk; ++c) Out[(size_t)(k0 + c) * n + i] = acc[c];
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < GM_TROWS * GM_COLS; idx += NT) {
+                const int c = idx / GM_TROWS, r = idx - c * GM_TROWS;
+                Xs[r][c] = (r < tr && c < kc) ? X[(size_t)(c0 + c) * ldx + t0 + r] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GM_TROWS / 4; ++u) {
+                if (4 * u >= tr) break;
+#pragma unroll
+                for (int q = 0; q < GM_COLS / 16; ++q)
+                    if (q < ntile)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], Xs[4 * u + lk][16 * q + li], acc[q], 0, 0,
+                                                                       0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < GM_COLS / 16; ++q) {
+            const int col = c0 + 16 * q + li;
+            if (q >= ntile || col >= k) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + lk + 4 * r;
+                if (row < n) Out[(size_t)col * n + row] = acc[q][r];
+            }
         }
     }
 }
@@ -112,7 +163,10 @@ __global__ void __launch_bounds__(NT) k_gemm_tall(int n, int t, int k, const dou
 hipError_t launch_gemm_tall(int n, int t, int k, const double* A, const double* X, int ldx, double* Out,
                             hipStream_t stream) {
     if (t > GT_TMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm_tall, dim3((n + NT - 1) / NT), dim3(NT), 0, stream, n, t, k, A, X, ldx, Out);
+    if (n <= 0 || k <= 0) return hipSuccess;
+    const int rows_per_block = 16 * NWAVE;
+    hipLaunchKernelGGL(k_gemm_tall, dim3((n + rows_per_block - 1) / rows_per_block), dim3(NT), 0, stream, n, t, k, A,
+                       X, ldx, Out);
     return hipGetLastError();
 }
 

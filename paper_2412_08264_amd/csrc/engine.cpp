@@ -366,7 +366,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         BatchMap f{};
         f.ns = 1;
         f.slot[0] = idx;
-        HIPCHK(launch_b_fold(d_slots, f, 0, c->stream));
+        HIPCHK(launch_b_fold(d_slots, f, 0, step, c->stream));
     }
     HIPCHK(launch_b_init(d_slots, make_map(S, one, false), c->stream));
     dirty = true;
@@ -387,7 +387,7 @@ bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic) {
     BatchMap f{};
     for (int i : idx)
         if (S[i].d.fold_res) f.slot[f.ns++] = i;
-    HIPCHK(launch_b_fold(d_slots, f, 0, c->stream));
+    HIPCHK(launch_b_fold(d_slots, f, 0, step, c->stream));
     HIPCHK(launch_b_replace(d_slots, make_map(S, idx, false), periodic, step, c->stream));
     return BL_OK;
 }
@@ -417,7 +417,7 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
             }
             if (!rr.empty()) TRY(replace_residual(rr, 1));
         }
-        if (fold_upd.ns) HIPCHK(launch_b_fold(d_slots, fold_upd, 2, c->stream));
+        if (fold_upd.ns) HIPCHK(launch_b_fold(d_slots, fold_upd, 2, step, c->stream));
         int ev = 0;
         if (ktime) {
             ev = 3 * (int)timed.size();
@@ -432,7 +432,7 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
             if (grp.tmap.ns)
                 HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, step, c->stream));
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], c->stream));
-        if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, c->stream));
+        if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, step, c->stream));
         HIPCHK(launch_b_update(d_slots, pmap, step, c->stream));
         if (ktime) {
             HIPCHK(hipEventRecord(c->kev[ev + 2], c->stream));

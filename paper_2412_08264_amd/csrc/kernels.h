@@ -54,7 +54,7 @@ hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t strea
 hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipStream_t stream);
 hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, int step, hipStream_t stream);
 hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream);
-hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, hipStream_t stream);
+hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, int step, hipStream_t stream);
 hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,
                           hipStream_t stream);
 hipError_t launch_b_set_j0(Slot* slots, int idx, int j0, hipStream_t stream);

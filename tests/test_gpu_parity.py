@@ -245,6 +245,45 @@ def test_recycled_cg_parity(B, stop):
             assert rel(host(w), wstar) <= 1e-8
 
 
+def test_error_estimate_on_tested_iterations_only(B):
+    """check_every = 4 with the error-estimate stop: Z^T r is formed only for tested iterations;
+    the estimate reported after k iterations is the oracle's at the last multiple of 4, and a
+    converged solve stops on a multiple of 4 within the oracle's one-ulp spread."""
+    wl, inst, prob, xh = tv_case(44, 60, seed=57)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    jac = lambda v: prob.jac_apply(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-8, v_cap=30)
+    th2 = th + 0.01
+    hvp2 = lambda v: prob.hvp(xh, th2, v)
+    rs = recycle.refresh(hvp2, lambda v: prob.jac_apply(xh, th2, v), None, first["V"], s=8)
+    w0 = first["w"]
+    for k in (8, 10, 13):
+        ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
+                                 stop="hgerr", hg_tol=0.0, record=True)
+        with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
+            upload_recycle(S, rs)
+            w = dev(w0)
+            st = S.solve(th2, dev(xh), dev(g), w, tol=0.0, max_iter=k, stop="hgerr", hg_tol=0.0, check_every=4,
+                         store_basis=False, allow=(B.BL_E_NOT_CONVERGED,))
+            want = ref["hist_nsc"][(k // 4) * 4]
+            assert abs(st.est - want) <= 1e-9 * want, (k, st.est, want)
+            assert rel(host(w), ref["w"]) <= 1e-10
+    hg_tol = 1e-7 * np.linalg.norm(jac(first["w"]))
+    runs = [krylov.recycled_cg(hvp2, g * (1 + 2.0 ** -52 * synth.unit_noise(prob.n, 300 + k)), w0, rs["U"], rs["C"],
+                               rs["Z"], rs["mu"], tol=1e-10, stop="hgerr", hg_tol=hg_tol, check_every=4)
+            for k in range(4)]
+    spread = [r_["iters"] for r_ in runs]
+    with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
+        upload_recycle(S, rs)
+        w = dev(w0)
+        st = S.solve(th2, dev(xh), dev(g), w, tol=1e-10, stop="hgerr", hg_tol=hg_tol, check_every=4,
+                     store_basis=False)
+        assert st.iters % 4 == 0 and st.est <= hg_tol
+        assert min(spread) - 4 <= st.iters <= max(spread) + 4, (st.iters, spread)
+
+
 @pytest.mark.parametrize("kind,prec", [("tv", "fp64"), ("filters", "fp64"), ("tv", "mixed")])
 def test_recycled_cg_every_tile_height(B, kind, prec):
     """The fused apply/residual kernels at 8, 16 and 32 rows per tile (70 x 90: ragged tiles in
