@@ -179,7 +179,7 @@ def make_trajectory(ctx, P, B, wl, torch, y, xs, theta0, outer, gtol=1e-8):
 
 
 def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL, rr_every=50,
-                 first_tol=RESID_TOL):
+                 first_tol=RESID_TOL, check_every=1):
     """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain'; thr: the stopping
     threshold (residual tolerance, or the error-estimate threshold relative to the previous
     hypergradient norm); first_tol: residual tolerance of the error-estimate variant's first
@@ -196,7 +196,7 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
             S.refresh(th, x, s=S.rs.s_max)
         if mode == "rgen_hg" and S.rs.s_cur > 0 and prev_hg is not None:
             st = S.solve(th, x, g, w, stop="hgerr", hg_tol=thr * prev_hg, tol=RESID_TOL, store_basis=True,
-                         rr_every=rr_every)
+                         rr_every=rr_every, check_every=check_every)
         else:
             # first system of the error-estimate variant (no recycle space yet): residual test
             st = S.solve(th, x, g, w, tol=first_tol if mode == "rgen_hg" else thr,
@@ -210,19 +210,21 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
     return recs
 
 
-def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep, first_tol=RESID_TOL):
+def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep, first_tol=RESID_TOL, check_every=1):
     for thr in sweep:
-        rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr, first_tol=first_tol)
+        rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr, first_tol=first_tol,
+                          check_every=check_every)
         if all(r["err"] <= 1e-6 and r["status"] == 0 for r in rr):
             return thr
     return sweep[-1]
 
 
-def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=None, first_tol=RESID_TOL):
+def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=None, first_tol=RESID_TOL,
+                 check_every=1):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat, thr=thr, first_tol=first_tol)
-            for _ in range(steps)]
+    recs = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat, thr=thr, first_tol=first_tol,
+                         check_every=check_every) for _ in range(steps)]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
@@ -304,26 +306,28 @@ def bench_sequence(args, B, torch, synth):
     # plain first: its threshold is also the first-system tolerance of the estimate variants
     for name, SS, sweep in [variants[2]] + [v for v in variants if v[0] != "plain"]:
         chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, name.replace("_fp64", ""), refs, sweep,
-                                        first_tol=chosen.get("plain", RESID_TOL))
+                                        first_tol=chosen.get("plain", RESID_TOL), check_every=args.check_every)
         log(f"[bench] {name}: threshold {chosen[name]:g}")
     ftol = chosen["plain"]
     for _ in range(args.warmup):
-        run_sequence(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, thr=chosen["rgen_hg"], first_tol=ftol)
+        run_sequence(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, thr=chosen["rgen_hg"], first_tol=ftol,
+                     check_every=args.check_every)
     # timed: headline (recycled + error-estimate stop), per-kernel events on the library's stream
     Sh.set_timing(2)
     Sh.kernel_times(reset=True)
     lat = []
     recs, el, ok, total = timed_passes(Sh, B, torch, thetas, xhats, xs, "rgen_hg", refs, chosen["rgen_hg"],
-                                       args.steps, lat, first_tol=ftol)
+                                       args.steps, lat, first_tol=ftol, check_every=args.check_every)
     kt = Sh.kernel_times(reset=True)
     Sh.set_timing(0)
     value = ok / el
     extra = {}
     for name, SS, _ in variants[1:]:
         mode = name.replace("_fp64", "")
-        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name], first_tol=ftol)
+        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name], first_tol=ftol,
+                     check_every=args.check_every)
         rr, elm, okm, totm = timed_passes(SS, B, torch, thetas, xhats, xs, mode, refs, chosen[name], args.steps,
-                                          first_tol=ftol)
+                                          first_tol=ftol, check_every=args.check_every)
         extra[name] = {"solves_per_s": okm / elm, "threshold": chosen[name],
                        "iters_per_sequence": sum(r["iters"] for r in rr[0]),
                        "max_rel_err": max(r["err"] for r in rr[0]), "passing": f"{okm}/{totm}"}
@@ -335,7 +339,8 @@ def bench_sequence(args, B, torch, synth):
              f"{B.bl_tile_rows(Sh.P) // 8}, true>")
     desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
             f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
-            f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad| (first system: "
+            f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad| tested every "
+            f"{args.check_every} iterations (first system: "
             f"residual {ftol:g}, as plain CG)"
             + (", FP32 stencils + FP64 rest with residual replacement" if mixed else ""))
     out = base_line(args, value, el, "f32+f64" if mixed else "f64",
@@ -445,7 +450,7 @@ def bench_batch(args, B, torch, synth):
                 use_hg = mode == "rgen_hg" and recs[k].rs.s_cur > 0 and prev[k] is not None
                 o = B.solve_opts(stop="hgerr" if use_hg else "resid", hg_tol=thr * prev[k] if use_hg else 0.0,
                                  tol=first_tol if mode != "plain" else thr, store_basis=mode != "plain",
-                                 rr_every=50)
+                                 rr_every=50, check_every=args.check_every if use_hg else 1)
                 sl = eng.admit(P, thetas[i], xh[k], xh[k] - xs[k], ws[k], recs[k] if mode != "plain" else None, o)
                 assert sl is not None, "engine arena too small"
                 slot_of[sl] = k
@@ -613,7 +618,8 @@ def bench_serve(args, B, torch, synth):
         tiles.update(autotune_tiles(ctx, B, [(P, data[k][0][0], data[k][1][0], wl.s)
                                              for k, (P, wl) in enumerate(zip(Ps, wls))]))
         arena = sum(B.Engine.slot_bytes(P, wl.s) for P, wl in zip(Ps, wls))
-        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, pool=pool)
+        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, pool=pool,
+                           check_every=args.check_every)
         for k, (wl, P) in enumerate(zip(wls, Ps)):
             path, xhats, xs = data[k]
             srv.add_sample(serve.Sample(k, P, path, xhats, xs, wl.s, args.v_cap, dev))
@@ -816,6 +822,8 @@ def main():
     ap.add_argument("--hg-rel", dest="hg_rel", type=float, default=1e-9, help="serve: error-estimate threshold "
                     "relative to the sample's previous hypergradient norm")
     ap.add_argument("--v-cap", dest="v_cap", type=int, default=V_CAP, help="serve: stored Krylov vectors per sample")
+    ap.add_argument("--check-every", dest="check_every", type=int, default=8,
+                    help="iterations between error-estimate tests (Z^T r is formed on tested iterations only)")
     ap.add_argument("--rows", type=int, default=0, choices=(0, 8, 16, 32),
                     help="tile height of the solves (0: autotune; kernels-only batch64: 0 means 32)")
     ap.add_argument("--kernels-only", action="store_true",

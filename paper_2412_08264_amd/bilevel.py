@@ -10,6 +10,9 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: the library's HIP runtime dependency (libamdhip64.so.7) then resolves to the
+# runtime torch has loaded, so the process holds one HIP runtime whatever the import order
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbilevel_hip.so")
 

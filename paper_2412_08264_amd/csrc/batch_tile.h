@@ -118,11 +118,25 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
 // A stopped slot's blocks leave after the record reduction (its flag is read by one thread
 // and published by the reduction's barrier: uniform per block; a flag set by block 0 during
 // this launch follows from the same decision every block of the slot takes).
-constexpr int CPRE = 8;   // columns of C per pixel loaded before the (short) TV stencil
+// TV on short tiles (8 or 16 rows, the small images, where latency decides): the loads that
+// do not depend on the scalars of this iteration (the thread's r, p and columns of C, the halo
+// of r and p, x_hat) are issued before the record reduction, so their latency overlaps it; the
+// stencil input r + beta p is formed from registers afterwards.  The
+// filter stencil is long enough to hide loads issued after it, and the registers of a
+// prefetch would cost occupancy there.
+template <int CLS, int Q, bool REC>
+__host__ __device__ constexpr int c_prefetch() {
+    return !REC ? 1 : (CLS != TC_TV ? 1 : (Q == 1 ? 24 : (Q == 2 ? 12 : 8)));
+}
+
 template <typename T, int R, int CLS, int Q, bool REC>
 __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
     using L = QLayout<T, R, CLS, Q>;
+    using G = QGeo<R, CLS, Q>;
     constexpr int QR = Q;
+    constexpr bool EARLY = CLS == TC_TV && Q < 4;   // (tall tiles: registers would cost occupancy)
+    constexpr int CP = c_prefetch<CLS, Q, REC>();
+    constexpr int NST = EARLY ? (G::N_V + NT - 1) / NT : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     __shared__ double tot[NT];
@@ -134,6 +148,40 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const int j = step - sl.j0;
     if (threadIdx.x == 0) sdone = st->done;
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
+    const int h = sl.h, w = sl.width, n = sl.n;
+    const double* __restrict__ r = sl.r;
+    const double* __restrict__ p_old = sl.p[j & 1];
+    double* __restrict__ p_new = sl.p[(j + 1) & 1];
+    int r0, c0;
+    slot_tile<Q>(sl, m.y, r0, c0);
+    const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
+    // p_old is read whatever the iteration and selected away below when the direction restarts
+    double ri[QR], pr[QR], cpre[CP][QR], hr[NST], hp[NST];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        ri[k] = o.in[k] ? r[o.g[k]] : 0.0;
+        pr[k] = o.in[k] ? p_old[o.g[k]] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+#pragma unroll
+        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * n + o.g[k]] : 0.0;
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            hr[u] = hp[u] = 0.0;
+            if (idx < G::N_V) {
+                const int rr = idx / G::RW, cc = idx - rr * G::RW;
+                const int gi = r0 - G::E + rr, gj = c0 - G::E + cc;
+                if (gi >= 0 && gi < h && gj >= 0 && gj < w) {
+                    hr[u] = r[gi * w + gj];
+                    hp[u] = p_old[gi * w + gj];
+                }
+            }
+        }
+        q_stage_xhat<T, Q>(lds + L::o_x, h, w, sl.xhat, r0, c0);
+    }
     int nb;
     const double* rec = slot_rec(sl, 2, nb);
     const int zw = REC ? zr_width(st, nz, j) : 0;
@@ -162,28 +210,21 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     slot_stencil(S, sl);
     const bool first = (j == 0) || restart;
     const double beta = first ? 0.0 : rho / rho_prev;
-    const double* __restrict__ r = sl.r;
-    const double* __restrict__ p_old = sl.p[j & 1];
-    double* __restrict__ p_new = sl.p[(j + 1) & 1];
-    int r0, c0;
-    slot_tile<Q>(sl, m.y, r0, c0);
-    const Own<Q> o = own_pixels<Q>(S.h, S.w, r0, c0);
-    // the filter stencil is long enough to hide the C loads issued after it, and the registers
-    // of a prefetch would cost occupancy there
-    constexpr int CP = !REC ? 1 : (CLS == TC_TV ? CPRE : 1);
-    double ri[QR], pi[QR], cpre[CP][QR];
+    double pi[QR];
 #pragma unroll
-    for (int k = 0; k < QR; ++k) {
-        ri[k] = o.in[k] ? r[o.g[k]] : 0.0;
-        pi[k] = (o.in[k] && !first) ? p_old[o.g[k]] : 0.0;
+    for (int k = 0; k < QR; ++k) pi[k] = first ? 0.0 : pr[k];
+    if constexpr (EARLY) {
+        T* v = lds + L::o_v;
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            if (idx < G::N_V) v[idx] = (T)(first ? hr[u] : hr[u] + beta * hp[u]);
+        }
+    } else {
+        q_stage<T, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0,
+                              [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
+        if constexpr (CLS == TC_TV) q_stage_xhat<T, Q>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
     }
-#pragma unroll
-    for (int c = 0; c < CP; ++c)
-#pragma unroll
-        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * S.n + o.g[k]] : 0.0;
-    q_stage<T, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0,
-                          [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<T, Q>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
     __syncthreads();
     T hv[QR];
     q_hvp<T, R, CLS, Q>(lds, S, r0, c0, hv);

@@ -175,19 +175,28 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
 // values, and no thread adds more than nblocks / G + log2(G) terms in sequence.
 __device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv, double* out) {
     __shared__ double wsum[NWAVE];
+    constexpr int U = 8;
     int G = 1;
     while (G * 2 * nv <= NT) G *= 2;
     const int k = threadIdx.x / G, j = threadIdx.x & (G - 1);
     double acc = 0.0;
     if (k < nv) {
-        double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int b = j;
-        for (; b + 7 * G < nblocks; b += 8 * G) {
+        double a[U];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a8[u] += part[(size_t)(b + u * G) * nv + k];
+        for (int u = 0; u < U; ++u) a[u] = 0.0;
+        int b = j;
+        for (; b + (U - 1) * G < nblocks; b += U * G) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] += part[(size_t)(b + u * G) * nv + k];
         }
-        for (int u = 0; b < nblocks; b += G, ++u) a8[u & 7] += part[(size_t)b * nv + k];
-        acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b + u * G < nblocks) a[u] += part[(size_t)(b + u * G) * nv + k];
+#pragma unroll
+        for (int w2 = U / 2; w2 > 0; w2 >>= 1)
+#pragma unroll
+            for (int u = 0; u < w2; ++u) a[u] += a[u + w2];
+        acc = a[0];
     }
     const int span = G < 64 ? G : 64;
     for (int off = span >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);

@@ -65,12 +65,14 @@ class Server:
     other host threads) so that they overlap the engine's iterations, or inline without one."""
 
     def __init__(self, ctx: B.Context, cap: int, arena_bytes: int, hg_rel: float = 1e-9, tol: float = 1e-10,
-                 rr_every: int = 50, iters_per_turn: int = 16, clock=time.perf_counter, pool=None):
+                 rr_every: int = 50, iters_per_turn: int = 16, clock=time.perf_counter, pool=None,
+                 check_every: int = 1):
         self.ctx = ctx
         self.engine = B.Engine(cap=cap, arena_bytes=arena_bytes, device=ctx.device, ctx=ctx.ctx)
         self.hg_rel = hg_rel
         self.tol = tol
         self.rr_every = rr_every
+        self.check_every = check_every
         self.iters_per_turn = iters_per_turn
         self.clock = clock
         self.pool = pool
@@ -118,7 +120,8 @@ class Server:
         smp = req.sample
         use_hg = smp.rec.rs.s_cur > 0 and smp.prev_hg is not None
         opts = B.solve_opts(stop="hgerr" if use_hg else "resid", hg_tol=self.hg_rel * smp.prev_hg if use_hg else 0.0,
-                            tol=self.tol, store_basis=True, rr_every=self.rr_every)
+                            tol=self.tol, store_basis=True, rr_every=self.rr_every,
+                            check_every=self.check_every if use_hg else 1)
         xh = smp.xhats[req.step]
         req.g = xh - smp.xstar
         slot = self.engine.admit(smp.P, smp.thetas[req.step], xh, req.g, smp.w, smp.rec, opts)
