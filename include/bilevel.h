@@ -163,9 +163,21 @@ bl_status bl_hvp(bl_ctx* ctx, const bl_problem* P, const double* theta_host, con
 bl_status bl_lower_grad(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* y,
                         const double* x, double* grad, double* phi_host, void* ws, size_t ws_bytes);
 
+/* Graph replay of the Krylov iterations, 1 (default) / 0.  The iterations of a solve run in
+ * chunks of 8 (apply and update launches, scheduled residual replacements, the gather of the
+ * stop flags).  A chunk whose launch sequence has occurred before since the set of running
+ * solves last changed is captured once (on a private stream of the context) and replayed with
+ * hipGraphLaunch on the context's stream; the kernels take their iteration index from a device
+ * counter, so the replays need no new arguments.  Results are bitwise those of direct launches.
+ * If a capture fails, the batch falls back to direct launches. */
+bl_status bl_set_graphs(bl_ctx* ctx, int enable);
+/* Chunks captured into graphs and chunk replays on this context since it was created. */
+bl_status bl_graph_counts(const bl_ctx* ctx, long long* captured, long long* replayed);
+
 /* Time the phases of subsequent calls with HIP events (stats->ms), 0/1.  With 2, also record
  * HIP events around the apply and update launches of every eighth Krylov step (see
- * bl_kernel_times); sampling keeps the events' own cost out of the run they measure. */
+ * bl_kernel_times; with graph replay on, every step of every eighth chunk, which then runs
+ * directly); sampling keeps the events' own cost out of the run they measure. */
 bl_status bl_set_timing(bl_ctx* ctx, int enable);
 
 /* Per-kernel durations accumulated over solves since the last reset, iterations that ran

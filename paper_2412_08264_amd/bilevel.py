@@ -72,6 +72,8 @@ _SIGS = {
     "bl_lower_grad": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(C.c_double), _vp,
                                 C.c_size_t]),
     "bl_set_timing": (C.c_int, [_vp, C.c_int]),
+    "bl_set_graphs": (C.c_int, [_vp, C.c_int]),
+    "bl_graph_counts": (C.c_int, [_vp, _P(C.c_longlong), _P(C.c_longlong)]),
     "bl_kernel_times": (C.c_int, [_vp, _P(C.c_double), C.c_int]),
     "bl_engine_slot_bytes": (C.c_size_t, [_P(bl_problem), C.c_int]),
     "bl_engine_workspace_bytes": (C.c_size_t, [C.c_int, C.c_size_t]),
@@ -204,6 +206,16 @@ class Context:
 
     def set_timing(self, mode: int = 1):
         lib.bl_set_timing(self.ctx, int(mode))
+
+    def set_graphs(self, enable: bool = True):
+        """Replay repeated chunks of Krylov iterations from captured HIP graphs (default on)."""
+        lib.bl_set_graphs(self.ctx, 1 if enable else 0)
+
+    def graph_counts(self):
+        """(chunks captured, chunk replays) on this context."""
+        cap, rep = C.c_longlong(), C.c_longlong()
+        lib.bl_graph_counts(self.ctx, C.byref(cap), C.byref(rep))
+        return cap.value, rep.value
 
     def kernel_times(self, reset: bool = True):
         """(apply ms total, apply launches, update ms total, update launches)."""

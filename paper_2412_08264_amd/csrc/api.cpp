@@ -21,7 +21,7 @@ constexpr int LBFGS_MMAX = 20;
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, slots, hdr, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, slots, hdr, ctr, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -44,6 +44,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.state = o;    o += al(sizeof(SolveState));
     L.slots = o;    o += al(sizeof(Slot));
     L.hdr = o;      o += al(HDR_BYTES);
+    L.ctr = o;      o += al(sizeof(int));
     L.fold = o;     o += al(4 * NV_RED * sizeof(double));
     L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
@@ -68,6 +69,7 @@ struct WS {
     SolveState* st() const { return (SolveState*)(base + L.state); }
     Slot* slots() const { return (Slot*)(base + L.slots); }
     int* hdr() const { return (int*)(base + L.hdr); }
+    int* ctr() const { return (int*)(base + L.ctr); }
     double* part() const { return (double*)(base + L.part); }
     double* part_res() const { return part(); }
     double* part_app() const { return part() + L.part_doubles; }
@@ -161,6 +163,7 @@ bl_status bl_create(bl_ctx** ctx, void* hip_stream) {
 bl_status bl_destroy(bl_ctx* c) {
     if (!c) return BL_E_ARG;
     hipStreamSynchronize(c->stream);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
     for (auto& e : c->kev) hipEventDestroy(e);
@@ -197,6 +200,19 @@ int bl_num_params(const bl_problem* P) { return P ? nparams(P) : -1; }
 size_t bl_workspace_bytes(const bl_problem* P, int s_max, int v_cap) {
     if (!P || s_max < 0 || v_cap < 0 || s_max > S_MAX || s_max + v_cap > 256) return 0;
     return layout(P, s_max, v_cap).total;
+}
+
+bl_status bl_set_graphs(bl_ctx* c, int enable) {
+    if (!c) return BL_E_ARG;
+    c->graphs = enable ? 1 : 0;
+    return BL_OK;
+}
+
+bl_status bl_graph_counts(const bl_ctx* c, long long* captured, long long* replayed) {
+    if (!c) return BL_E_ARG;
+    if (captured) *captured = c->graph_captures;
+    if (replayed) *replayed = c->graph_replays;
+    return BL_OK;
 }
 
 bl_status bl_set_timing(bl_ctx* c, int enable) {
@@ -278,7 +294,7 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
     TRY(check_ws(c, layout(P, s_max, v_cap), wsp, ws_bytes, ws));
     mark(c, 0);
     Batch B;
-    TRY(B.init(c, 1, ws.slots(), ws.hdr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
+    TRY(B.init(c, 1, ws.slots(), ws.hdr(), ws.ctr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
     SlotBuffers buf{};
     buf.r = ws.vec(0);
     buf.p0 = ws.vec(1);

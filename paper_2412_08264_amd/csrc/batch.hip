@@ -44,14 +44,14 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
 // w += alpha p;  r -= alpha (q - C e);  z -= alpha e;  record [r.r, Z^T r] (Z^T r only when
 // the test of iteration j + 1 evaluates the error estimate).
 constexpr int UPRE = 24;
-__global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, int step) {
+__global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, StepRef sr) {
     __shared__ double tot[NT];
     __shared__ int sdone;
     const int2 m = map_block(M, blockIdx.x);
     const Slot& sl = slots[m.x];
     if (m.y >= sl.npix) return;
     SolveState* st = sl.st;
-    const int j = step - sl.j0;
+    const int j = step_of(sr) - sl.j0;
     if (threadIdx.x == 0) sdone = st->done;
     const int s = sl.s, n = sl.n;
     const int i = m.y * NT + threadIdx.x;
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
 // r := t - C z, and the slot resumes at iteration step - j0, whose apply step re-tests the
 // replaced residual.  With `periodic` set a slot that has already stopped is left alone.
 __global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots, BatchMap M, int periodic,
-                                                  int step) {
+                                                  StepRef sr) {
     __shared__ double tot[NT];
     const int2 m = map_block(M, blockIdx.x);
     const Slot& sl = slots[m.x];
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots
         if (threadIdx.x == 0) {
             sl.st->done = 0;
             sl.st->status = BL_OK;
-            sl.st->rr_j = step - sl.j0;
+            sl.st->rr_j = step_of(sr) - sl.j0;
         }
     }
     const int i = m.y * NT + threadIdx.x;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots
         sl.r[i] = ri;
     }
     block_partials(
-        sl.rec_upd, 1 + zr_width(sl.st, nz, step - sl.j0),
+        sl.rec_upd, 1 + zr_width(sl.st, nz, step_of(sr) - sl.j0),
         [&](int k) -> double {
             if (!in) return 0.0;
             return k == 0 ? ri * ri : sl.Z[(size_t)(k - 1) * n + i] * ri;
@@ -162,8 +162,8 @@ __global__ void __launch_bounds__(NT) k_b_finish(const Slot* __restrict__ slots,
 }
 
 // Fold the records of kind `which` (0 residual, 1 apply, 2 update, read by the test of step
-// `step`): one block per listed slot.
-__global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which, int step) {
+// sr): one block per listed slot.
+__global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which, StepRef sr) {
     __shared__ double tot[NT];
     const Slot& sl = slots[M.slot[blockIdx.x]];
     int nb, nv;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, B
         rec = sl.rec_app;
     } else {
         nb = sl.npix;
-        nv = 1 + zr_width(sl.st, sl.nz, step - sl.j0);
+        nv = 1 + zr_width(sl.st, sl.nz, step_of(sr) - sl.j0);
         rec = sl.rec_upd;
     }
     reduce_partials(rec, nb, nv, tot);
@@ -214,10 +214,13 @@ __global__ void k_b_set_j0(Slot* __restrict__ slots, int idx, int j0) {
     if (threadIdx.x == 0) slots[idx].j0 = j0;
 }
 
-// Scalar headers of the listed slots into out[slot index * HDR_BYTES] (4-byte words).
-__global__ void __launch_bounds__(NT) k_b_headers(const Slot* __restrict__ slots, BatchMap M, int* __restrict__ out) {
+// Scalar headers of the listed slots into out[slot index * HDR_BYTES] (4-byte words), and the
+// step counter advanced past the chunk (adv steps; no other block of this kernel reads it).
+__global__ void __launch_bounds__(NT) k_b_headers(const Slot* __restrict__ slots, BatchMap M, int* __restrict__ out,
+                                                  int* __restrict__ ctr, int adv) {
     constexpr int WPS = HDR_BYTES / 4;
     const int t = blockIdx.x * NT + threadIdx.x;
+    if (t == 0) ctr[0] += adv;
     const int k = t / WPS, wd = t - k * WPS;
     if (k >= M.ns) return;
     const int idx = M.slot[k];
@@ -236,12 +239,12 @@ hipError_t launch_b_residual(const Stencil& base, int rows, bool rec, const Slot
 }
 
 hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
-                          int step, hipStream_t stream) {
+                          StepRef sr, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
     switch (rows) {
-        case QTY * 1: return launch_b_apply_q<1>(base, rec, fp32, slots, M, step, stream);
-        case QTY * 2: return launch_b_apply_q<2>(base, rec, fp32, slots, M, step, stream);
-        case QTY * 4: return launch_b_apply_q<4>(base, rec, fp32, slots, M, step, stream);
+        case QTY * 1: return launch_b_apply_q<1>(base, rec, fp32, slots, M, sr, stream);
+        case QTY * 2: return launch_b_apply_q<2>(base, rec, fp32, slots, M, sr, stream);
+        case QTY * 4: return launch_b_apply_q<4>(base, rec, fp32, slots, M, sr, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -251,14 +254,14 @@ hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t strea
     hipLaunchKernelGGL(k_b_init, map_grid(M), dim3(NT), 0, stream, slots, M);
     return hipGetLastError();
 }
-hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipStream_t stream) {
+hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_update, map_grid(M), dim3(NT), 0, stream, slots, M, step);
+    hipLaunchKernelGGL(k_b_update, map_grid(M), dim3(NT), 0, stream, slots, M, sr);
     return hipGetLastError();
 }
-hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, int step, hipStream_t stream) {
+hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, StepRef sr, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_replace, map_grid(M), dim3(NT), 0, stream, slots, M, periodic, step);
+    hipLaunchKernelGGL(k_b_replace, map_grid(M), dim3(NT), 0, stream, slots, M, periodic, sr);
     return hipGetLastError();
 }
 hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream) {
@@ -266,9 +269,9 @@ hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t str
     hipLaunchKernelGGL(k_b_finish, map_grid(M), dim3(NT), 0, stream, slots, M);
     return hipGetLastError();
 }
-hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, int step, hipStream_t stream) {
+hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, StepRef sr, hipStream_t stream) {
     if (list.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_fold, dim3(list.ns), dim3(NT), 0, stream, slots, list, which, step);
+    hipLaunchKernelGGL(k_b_fold, dim3(list.ns), dim3(NT), 0, stream, slots, list, which, sr);
     return hipGetLastError();
 }
 hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,
@@ -280,10 +283,11 @@ hipError_t launch_b_set_j0(Slot* slots, int idx, int j0, hipStream_t stream) {
     hipLaunchKernelGGL(k_b_set_j0, dim3(1), dim3(64), 0, stream, slots, idx, j0);
     return hipGetLastError();
 }
-hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, hipStream_t stream) {
-    if (list.ns == 0) return hipSuccess;
+hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, int* ctr, int adv,
+                            hipStream_t stream) {
     const int words = list.ns * (HDR_BYTES / 4);
-    hipLaunchKernelGGL(k_b_headers, dim3((words + NT - 1) / NT), dim3(NT), 0, stream, slots, list, out);
+    hipLaunchKernelGGL(k_b_headers, dim3(words > 0 ? (words + NT - 1) / NT : 1), dim3(NT), 0, stream, slots, list, out,
+                       ctr, adv);
     return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@
 namespace bl {
 
 template hipError_t launch_b_residual_q<1>(const Stencil&, bool, const Slot*, const BatchMap&, int, hipStream_t);
-template hipError_t launch_b_apply_q<1>(const Stencil&, bool, bool, const Slot*, const BatchMap&, int,
+template hipError_t launch_b_apply_q<1>(const Stencil&, bool, bool, const Slot*, const BatchMap&, StepRef,
                                              hipStream_t);
 
 }  // namespace bl

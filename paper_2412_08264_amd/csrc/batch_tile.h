@@ -130,7 +130,8 @@ __host__ __device__ constexpr int c_prefetch() {
 }
 
 template <typename T, int R, int CLS, int Q, bool REC>
-__global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M, int step) {
+__global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __restrict__ slots, BatchMap M,
+                                                StepRef sr) {
     using L = QLayout<T, R, CLS, Q>;
     using G = QGeo<R, CLS, Q>;
     constexpr int QR = Q;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const Slot& sl = slots[m.x];
     if (m.y >= sl.ntiles) return;
     SolveState* st = sl.st;
-    const int j = step - sl.j0;
+    const int j = step_of(sr) - sl.j0;
     if (threadIdx.x == 0) sdone = st->done;
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     const int h = sl.h, w = sl.width, n = sl.n;
@@ -188,7 +189,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     reduce_partials(rec, nb, 1 + zw, tot);
     if (sdone) return;
     const double rho_prev = j > 0 ? st->rho2[(j - 1) & 1] : 1.0;
-    const bool store_basis = st->store_basis && j < st->v_cap;
+    const bool store_basis = st->store_basis && j >= 0 && j < st->v_cap;
     const double rho = tot[0];
     const bool restart = j > 0 && st->rr_j == j && rho > rho_prev;
     const Decision dec = decide(st, j, rho, tot + 1, zw > 0);
@@ -292,13 +293,13 @@ hipError_t launch_b_residual_q(const Stencil& base, bool rec, const Slot* slots,
 }
 
 template <int Q>
-hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot* slots, const BatchMap& M, int step,
-                            hipStream_t stream) {
+hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
+                            StepRef sr, hipStream_t stream) {
     q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
         auto go = [&](auto kern, size_t lds) {
             allow_lds_b(kern, lds);
-            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, step);
+            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, sr);
         };
         constexpr size_t l32 = QLayout<float, RR, CC, Q>::bytes, l64 = QLayout<double, RR, CC, Q>::bytes;
         if (fp32) {

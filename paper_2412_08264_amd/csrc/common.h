@@ -109,6 +109,15 @@ __device__ __forceinline__ int2 map_block(const BatchMap& M, int b) {
     return make_int2(M.slot[lo], b - M.off[lo]);
 }
 
+// Global step index of a launch: a device counter, advanced by the header kernel at the end of
+// each chunk of iterations, plus the launch's position in its chunk.  A chunk's launches then
+// take the same arguments every time, so a captured chunk can be replayed as a graph.
+struct StepRef {
+    const int* ctr;
+    int k;
+};
+__device__ __forceinline__ int step_of(const StepRef& sr) { return sr.ctr[0] + sr.k; }
+
 // Per-solve settings written into a fresh SolveState at admission.
 struct StateInit {
     double tol, hg_tol;

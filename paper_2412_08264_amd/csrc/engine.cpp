@@ -185,13 +185,22 @@ SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
 }
 
 // ------------------------------------------------------------------------------------- Batch
-bl_status Batch::init(bl_ctx* ctx, int capacity, Slot* slots, int* hdr_dev, char* hdr_pinned, hipEvent_t ev0,
-                      hipEvent_t ev1) {
+Batch::~Batch() {
+    if ((graph_cache.empty() && retired.empty()) || !c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : graph_cache) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraphExec_t ex : retired) (void)hipGraphExecDestroy(ex);
+}
+
+bl_status Batch::init(bl_ctx* ctx, int capacity, Slot* slots, int* hdr_dev, int* ctr_dev, char* hdr_pinned,
+                      hipEvent_t ev0, hipEvent_t ev1) {
     c = ctx;
     groups.clear();
     cap = capacity;
     d_slots = slots;
     d_hdr = hdr_dev;
+    d_ctr = ctr_dev;
+    HIPCHK(hipMemsetAsync(d_ctr, 0, sizeof(int), c->stream));
     h_hdr = hdr_pinned;
     poll_ev[0] = ev0;
     poll_ev[1] = ev1;
@@ -224,7 +233,16 @@ static BatchMap make_map(const std::vector<Batch::Host>& S, const std::vector<in
     return M;
 }
 
+// Outdated graphs wait in `retired` until run() has drained the stream.
+void Batch::drop_graphs() {
+    for (auto& kv : graph_cache) retired.push_back(kv.second);
+    graph_cache.clear();
+    seen.clear();
+}
+
 bl_status Batch::rebuild() {
+    ++gen;
+    drop_graphs();
     run_list.clear();
     for (int i = 0; i < cap; ++i)
         if (S[i].running) run_list.push_back(i);
@@ -366,29 +384,29 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         BatchMap f{};
         f.ns = 1;
         f.slot[0] = idx;
-        HIPCHK(launch_b_fold(d_slots, f, 0, step, c->stream));
+        HIPCHK(launch_b_fold(d_slots, f, 0, StepRef{d_ctr, 0}, c->stream));
     }
     HIPCHK(launch_b_init(d_slots, make_map(S, one, false), c->stream));
     dirty = true;
     return BL_OK;
 }
 
-// Residual replacement in FP64 for the listed slots: r = g - H w, z = C^T r, r -= C z.
-bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic) {
+// Residual replacement in FP64 for the listed slots: r = g - H w, z = C^T r, r -= C z, launched
+// on stream ls at position k of the current chunk (k = 0 between chunks).
+bl_status Batch::replace_residual(const std::vector<int>& idx, int periodic, int k, hipStream_t ls) {
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
         std::vector<int> mine;
         for (int i : idx)
             if (S[i].group == gi) mine.push_back(i);
         if (!mine.empty())
             HIPCHK(launch_b_residual(groups[gi].base, groups[gi].rows, groups[gi].rec, d_slots, make_map(S, mine, true),
-                                     periodic,
-                                     c->stream));
+                                     periodic, ls));
     }
     BatchMap f{};
     for (int i : idx)
         if (S[i].d.fold_res) f.slot[f.ns++] = i;
-    HIPCHK(launch_b_fold(d_slots, f, 0, step, c->stream));
-    HIPCHK(launch_b_replace(d_slots, make_map(S, idx, false), periodic, step, c->stream));
+    HIPCHK(launch_b_fold(d_slots, f, 0, StepRef{d_ctr, k}, ls));
+    HIPCHK(launch_b_replace(d_slots, make_map(S, idx, false), periodic, StepRef{d_ctr, k}, ls));
     return BL_OK;
 }
 
@@ -397,27 +415,19 @@ bl_status Batch::finish(int idx) {
     return BL_OK;
 }
 
-bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::vector<int>& slots) {
-    if (dirty) TRY(rebuild());
-    slots = run_list;
-    id = chunk_id++;
-    const int buf = (int)(id & 1);
-    for (int k = 0; k < POLL && steps_done < max_steps; ++k) {
-        // per-kernel events on one step in KT_SAMPLE: the events themselves cost time
-        const bool ktime = c->timing == 2 && step % KT_SAMPLE == 0;
-        {   // scheduled replacements (mixed precision): before the test of every rr_every-th iteration
-            std::vector<int> rr;
-            for (int i : run_list) {
-                Host& h = S[i];
-                const int j = step - h.d.j0;
-                if (h.rr_every > 0 && j > 0 && j <= h.max_iter && j % h.rr_every == 0) {
-                    rr.push_back(i);
-                    h.rr_js.push_back(j);
-                }
-            }
-            if (!rr.empty()) TRY(replace_residual(rr, 1));
-        }
-        if (fold_upd.ns) HIPCHK(launch_b_fold(d_slots, fold_upd, 2, step, c->stream));
+// The launches of one chunk of nsteps iterations on stream ls: scheduled replacements, record
+// folds, one apply launch per group and one update launch per iteration, then the header
+// gather (which advances the step counter) and its copy to pinned buffer buf.  With time_all
+// (timing mode 2) HIP events bracket the apply and update launches of every iteration; without
+// graphs, those of every KT_SAMPLE-th step.  No host-side state changes here, so the same
+// sequence can be captured.
+bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipStream_t ls,
+                              bool time_all) {
+    for (int k = 0; k < nsteps; ++k) {
+        const StepRef sr{d_ctr, k};
+        const bool ktime = c->timing == 2 && (time_all || (!c->graphs && (step + k) % KT_SAMPLE == 0));
+        if (!rr[k].empty()) TRY(replace_residual(rr[k], 1, k, ls));
+        if (fold_upd.ns) HIPCHK(launch_b_fold(d_slots, fold_upd, 2, sr, ls));
         int ev = 0;
         if (ktime) {
             ev = 3 * (int)timed.size();
@@ -426,35 +436,116 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
                 HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                 c->kev.push_back(e);
             }
-            HIPCHK(hipEventRecord(c->kev[ev], c->stream));
+            HIPCHK(hipEventRecord(c->kev[ev], ls));
         }
         for (const Group& grp : groups)
-            if (grp.tmap.ns)
-                HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, step, c->stream));
-        if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], c->stream));
-        if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, step, c->stream));
-        HIPCHK(launch_b_update(d_slots, pmap, step, c->stream));
+            if (grp.tmap.ns) HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, sr, ls));
+        if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], ls));
+        if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, sr, ls));
+        HIPCHK(launch_b_update(d_slots, pmap, sr, ls));
         if (ktime) {
-            HIPCHK(hipEventRecord(c->kev[ev + 2], c->stream));
+            HIPCHK(hipEventRecord(c->kev[ev + 2], ls));
             Timed t;
             t.ev = ev;
-            for (int i : run_list) t.sj.push_back(make_int2(i, step - S[i].d.j0));
+            for (int i : run_list) t.sj.push_back(make_int2(i, step + k - S[i].d.j0));
             timed.push_back(std::move(t));
         }
-        ++step;
-        ++steps_done;
     }
-    char* dst = h_hdr + (size_t)buf * cap * HDR_BYTES;
-    if (run_list.size() == 1) {
-        const int i = run_list[0];
-        HIPCHK(hipMemcpyAsync(dst + (size_t)i * HDR_BYTES, S[i].d.st, HDR_BYTES, hipMemcpyDeviceToHost, c->stream));
-    } else {
-        BatchMap all{};
-        all.ns = (int)run_list.size();
-        for (int k = 0; k < all.ns; ++k) all.slot[k] = run_list[k];
-        HIPCHK(launch_b_headers(d_slots, all, d_hdr, c->stream));
-        HIPCHK(hipMemcpyAsync(dst, d_hdr, (size_t)cap * HDR_BYTES, hipMemcpyDeviceToHost, c->stream));
+    BatchMap all{};
+    all.ns = (int)run_list.size();
+    for (int k = 0; k < all.ns; ++k) all.slot[k] = run_list[k];
+    HIPCHK(launch_b_headers(d_slots, all, d_hdr, d_ctr, nsteps, ls));
+    HIPCHK(hipMemcpyAsync(h_hdr + (size_t)buf * cap * HDR_BYTES, d_hdr, (size_t)cap * HDR_BYTES, hipMemcpyDeviceToHost,
+                          ls));
+    return BL_OK;
+}
+
+// Capture a chunk on the context's private stream (nothing runs) into an executable graph.  On
+// failure the stage and HIP error are left in the context's error string.
+bl_status Batch::capture(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipGraphExec_t& ex) {
+    ex = nullptr;
+    auto fail = [&](const char* stage, hipError_t e) {
+        c->err = std::string("graph capture (") + stage + "): " + hipGetErrorString(e);
+        (void)hipGetLastError();
+        return BL_E_HIP;
+    };
+    if (!c->cap_stream) {
+        const hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            c->cap_stream = nullptr;
+            return fail("stream", e);
+        }
     }
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return fail("begin", e);
+    const bl_status st = launch_chunk(nsteps, buf, rr, c->cap_stream, false);
+    const std::string launch_err = st == BL_OK ? std::string() : c->err;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != BL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        c->err = "graph capture (launch): " + launch_err;
+        (void)hipGetLastError();
+        return BL_E_HIP;
+    }
+    if (e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail("end", e);
+    }
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ex = nullptr;
+        return fail("instantiate", e);
+    }
+    return BL_OK;
+}
+
+bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::vector<int>& slots) {
+    if (dirty) TRY(rebuild());
+    slots = run_list;
+    id = chunk_id++;
+    const int buf = (int)(id & 1);
+    const int nsteps = std::min(POLL, max_steps - steps_done);
+    // scheduled replacements (mixed precision): before the test of every rr_every-th iteration
+    std::vector<std::vector<int>> rr(nsteps);
+    for (int k = 0; k < nsteps; ++k)
+        for (int i : run_list) {
+            Host& h = S[i];
+            const int j = step + k - h.d.j0;
+            if (h.rr_every > 0 && j > 0 && j <= h.max_iter && j % h.rr_every == 0) {
+                rr[k].push_back(i);
+                h.rr_js.push_back(j);
+            }
+        }
+    // timing mode 2 with graphs: every KT_SAMPLE-th chunk runs directly, with events on each step
+    const bool sampled = c->timing == 2 && c->graphs && id % KT_SAMPLE == 0;
+    bool launched = false;
+    if (c->graphs && !graphs_off && !sampled) {
+        GraphKey key(gen, nsteps, buf, rr);
+        auto it = graph_cache.find(key);
+        if (it == graph_cache.end()) {
+            if (seen.count(key)) {
+                hipGraphExec_t ex = nullptr;
+                if (capture(nsteps, buf, rr, ex) == BL_OK) {
+                    it = graph_cache.emplace(key, ex).first;
+                    ++c->graph_captures;
+                } else {
+                    graphs_off = true;
+                }
+            } else {
+                seen.insert(key);
+            }
+        }
+        if (it != graph_cache.end()) {
+            HIPCHK(hipGraphLaunch(it->second, c->stream));
+            ++c->graph_replays;
+            launched = true;
+        }
+    }
+    if (!launched) TRY(launch_chunk(nsteps, buf, rr, c->stream, sampled));
+    step += nsteps;
+    steps_done += nsteps;
     HIPCHK(hipEventRecord(poll_ev[buf], c->stream));
     return BL_OK;
 }
@@ -492,7 +583,7 @@ bl_status Batch::process_chunk(long id, const std::vector<int>& slots, std::vect
             h.rr_js.assign(1, h.hdr.iters);
             h.valid_from = chunk_id;
         }
-        TRY(replace_residual(retest, 0));
+        TRY(replace_residual(retest, 0, 0, c->stream));
     }
     return BL_OK;
 }
@@ -543,6 +634,8 @@ bl_status Batch::run(int max_steps, bool until_any, std::vector<int>& done) {
         if (until_any && !done.empty()) stop = true;
     }
     HIPCHK(hipStreamSynchronize(c->stream));
+    for (hipGraphExec_t ex : retired) (void)hipGraphExecDestroy(ex);
+    retired.clear();
     if (c->timing == 2) account_times();
     return BL_OK;
 }
@@ -618,7 +711,7 @@ struct bl_engine {
 namespace {
 
 struct EngineLayout {
-    size_t slots, hdr, states, arena, total;
+    size_t slots, hdr, ctr, states, arena, total;
 };
 
 EngineLayout engine_layout(int cap, size_t arena_bytes) {
@@ -626,6 +719,7 @@ EngineLayout engine_layout(int cap, size_t arena_bytes) {
     size_t o = 0;
     L.slots = o;   o += al((size_t)cap * sizeof(Slot));
     L.hdr = o;     o += al((size_t)cap * HDR_BYTES);
+    L.ctr = o;     o += al(sizeof(int));
     L.states = o;  o += al((size_t)cap * sizeof(SolveState));
     L.arena = o;   o += al(arena_bytes);
     L.total = o;
@@ -676,7 +770,14 @@ bl_status bl_engine_create(bl_ctx* c, int cap, void* ws, size_t ws_bytes, bl_eng
         delete e;
         return BL_E_HIP;
     }
-    e->B.init(c, cap, (Slot*)(base + L0.slots), (int*)(base + L0.hdr), e->h_hdr, e->ev[0], e->ev[1]);
+    if (e->B.init(c, cap, (Slot*)(base + L0.slots), (int*)(base + L0.hdr), (int*)(base + L0.ctr), e->h_hdr, e->ev[0],
+                  e->ev[1]) != BL_OK) {
+        hipHostFree(e->h_taps);
+        hipHostFree(e->h_hdr);
+        for (auto& ev : e->ev) hipEventDestroy(ev);
+        delete e;
+        return BL_E_HIP;
+    }
     *out = e;
     return BL_OK;
 }

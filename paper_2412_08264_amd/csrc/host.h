@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -13,6 +16,9 @@ struct bl_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int timing = 0;
+    int graphs = 1;                      // replay repeated chunks of iterations from captured graphs
+    hipStream_t cap_stream = nullptr;    // private stream graphs are captured on (created on first use)
+    long graph_captures = 0, graph_replays = 0;
     int force_rows = 0;                  // autotuner: tile height of the solves it times (0: table)
     bl::SolveState* h_state = nullptr;   // pinned
     double* h_buf = nullptr;             // pinned staging (8192 doubles)
@@ -109,6 +115,7 @@ public:
     int cap = 0;
     bl::Slot* d_slots = nullptr;   // device [cap]
     int* d_hdr = nullptr;          // device [cap * HDR_BYTES / 4]: gathered headers
+    int* d_ctr = nullptr;          // device step counter (equals `step` at chunk boundaries)
     char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES]
     hipEvent_t poll_ev[2] = {};
 
@@ -139,8 +146,12 @@ public:
     int step = 0;                  // next global step index
     long chunk_id = 0;
 
-    bl_status init(bl_ctx* ctx, int capacity, bl::Slot* slots, int* hdr_dev, char* hdr_pinned, hipEvent_t ev0,
-                   hipEvent_t ev1);
+    Batch() = default;
+    Batch(const Batch&) = delete;
+    Batch& operator=(const Batch&) = delete;
+    ~Batch();
+    bl_status init(bl_ctx* ctx, int capacity, bl::Slot* slots, int* hdr_dev, int* ctr_dev, char* hdr_pinned,
+                   hipEvent_t ev0, hipEvent_t ev1);
     // Validate and start solve `sp` in free slot idx with device scratch B; taps_stage is
     // pinned host memory of TAPS_MAX doubles that stays untouched until the slot retires.
     bl_status admit(int idx, const SolveSpec& sp, const SlotBuffers& B, double* taps_stage);
@@ -161,9 +172,23 @@ private:
         std::vector<int2> sj;      // (slot, iteration) pairs of the step
     };
     std::vector<Timed> timed;
+    // Captured chunks, keyed by the slot-set generation, the chunk length, the header buffer and
+    // the scheduled replacements of each position; a chunk is captured the second time its key
+    // occurs and replayed after that.  Graphs of an outdated generation are destroyed once the
+    // stream has drained.
+    using GraphKey = std::tuple<long, int, int, std::vector<std::vector<int>>>;
+    std::map<GraphKey, hipGraphExec_t> graph_cache;
+    std::set<GraphKey> seen;
+    std::vector<hipGraphExec_t> retired;
+    long gen = 0;
+    bool graphs_off = false;       // a capture failed: launch directly from then on
     bl_status rebuild();
-    bl_status replace_residual(const std::vector<int>& idx, int periodic);
+    bl_status replace_residual(const std::vector<int>& idx, int periodic, int k, hipStream_t ls);
     bl_status finish(int idx);
+    bl_status launch_chunk(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipStream_t ls,
+                           bool time_all);
+    bl_status capture(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipGraphExec_t& ex);
+    void drop_graphs();
     bl_status enqueue_chunk(int max_steps, int& steps_done, long& id, std::vector<int>& slots);
     bl_status process_chunk(long id, const std::vector<int>& slots, std::vector<int>& done);
     void account_times();

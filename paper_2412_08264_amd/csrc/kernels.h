@@ -34,31 +34,32 @@ hipError_t launch_sub(int n, const double* a, const double* b, double* out, hipS
 hipError_t launch_b_residual(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M,
                              int periodic, hipStream_t stream);
 hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
-                          int step, hipStream_t stream);
+                          StepRef sr, hipStream_t stream);
 template <int Q>
 hipError_t launch_b_residual_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, int periodic,
                                hipStream_t stream);
 template <int Q>
-hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot* slots, const BatchMap& M, int step,
-                            hipStream_t stream);
+hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
+                            StepRef sr, hipStream_t stream);
 #define BL_TILE_EXTERN(Q)                                                                                        \
     extern template hipError_t launch_b_residual_q<Q>(const Stencil&, bool, const Slot*, const BatchMap&, int,    \
                                                       hipStream_t);                                               \
-    extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, bool, const Slot*, const BatchMap&, int, \
-                                                   hipStream_t);
+    extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, bool, const Slot*, const BatchMap&,      \
+                                                   StepRef, hipStream_t);
 BL_TILE_EXTERN(1)
 BL_TILE_EXTERN(2)
 BL_TILE_EXTERN(4)
 #undef BL_TILE_EXTERN
 hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t stream);
-hipError_t launch_b_update(const Slot* slots, const BatchMap& M, int step, hipStream_t stream);
-hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, int step, hipStream_t stream);
+hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, hipStream_t stream);
+hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, StepRef sr, hipStream_t stream);
 hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream);
-hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, int step, hipStream_t stream);
+hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, StepRef sr, hipStream_t stream);
 hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,
                           hipStream_t stream);
 hipError_t launch_b_set_j0(Slot* slots, int idx, int j0, hipStream_t stream);
-hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, hipStream_t stream);
+hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, int* ctr, int adv,
+                            hipStream_t stream);
 
 // dense.hip
 int gram_chunks(int n);

@@ -220,3 +220,58 @@ def test_engine_mixes_operator_classes(B):
         assert st_ref.status == B.BL_OK
         assert same(stats[k], st_ref), k
         assert torch.equal(ws[k], w_ref)
+
+
+def test_graph_replay_bitwise_equals_direct_launches(B):
+    """Repeated chunks of iterations replayed from captured graphs give bitwise the iterates,
+    counts and statuses of direct launches: a long FP64 TV solve (error-estimate stop tested
+    every 4 iterations), a mixed-precision filter solve (scheduled residual replacements every
+    16 iterations, i.e. every other chunk, and the final re-test change the chunks' launch
+    sequences), a plain solve, and a batch of three with continuous admission; the replay path
+    is taken (the context's counters)."""
+    cases = [make_case(B, "tv", 64, 72, 6, 701), make_case(B, "filters", 48, 40, 4, 702, prec="mixed"),
+             make_case(B, "tv", 40, 36, 0, 703)]
+    kws = [dict(tol=1e-11, stop="hgerr", hg_tol=0.0, check_every=4, max_iter=300, store_basis=True),
+           dict(tol=1e-12, rr_every=16, store_basis=False), dict(tol=1e-12, store_basis=False)]
+    for c, kw in zip(cases, kws):
+        S = c["S"]
+        cap0, rep0 = S.graph_counts()
+        w_g, st_g = solo(B, c, **kw)
+        cap1, rep1 = S.graph_counts()
+        S.set_graphs(False)
+        try:
+            w_d, st_d = solo(B, c, **kw)
+        finally:
+            S.set_graphs(True)
+        assert S.graph_counts() == (cap1, rep1)
+        assert rep1 - rep0 >= 3 and cap1 > cap0, (cap0, rep0, cap1, rep1, st_g.iters, st_g.status, st_d.iters,
+                                                  B.lib.bl_last_error(S.ctx).decode())
+        assert same(st_g, st_d) and st_g.iters == st_d.iters
+        assert torch.equal(w_g, w_d)
+        if c["rec"] is not None and kw.get("store_basis"):
+            assert c["rec"].rs.v_cur > 0
+    # engine: graphs on and off over the same admissions
+    outs = []
+    for graphs in (True, False):
+        ctx = B.Context([c["P"] for c in cases], s_max=6, v_cap=24)
+        ctx.set_graphs(graphs)
+        arena = sum(B.Engine.slot_bytes(c["P"], c["rec"].rs.s_cur if c["rec"] else 0) for c in cases)
+        ws = [c["w0"].clone() for c in cases]
+        with B.Engine(cap=2, arena_bytes=arena, ctx=ctx.ctx) as eng:
+            pending, slots, stats = list(range(3)), {}, {}
+            while pending or slots:
+                while pending:
+                    k = pending[0]
+                    sl = eng.admit(cases[k]["P"], cases[k]["th"], cases[k]["xh"], cases[k]["g"], ws[k],
+                                   cases[k]["rec"], B.solve_opts(tol=1e-11, store_basis=False))
+                    if sl is None:
+                        break
+                    slots[sl] = pending.pop(0)
+                for sl in eng.step(max_iters=24):
+                    stats[slots.pop(sl)] = eng.retire(sl)
+        outs.append((ws, stats, ctx.graph_counts()))
+        ctx.close()
+    (wg, sg, cg), (wd, sd, _) = outs
+    assert cg[1] > 0
+    for k in range(3):
+        assert same(sg[k], sd[k]) and torch.equal(wg[k], wd[k]), k
