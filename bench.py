@@ -618,7 +618,7 @@ def bench_serve(args, B, torch, synth):
         tiles.update(autotune_tiles(ctx, B, [(P, data[k][0][0], data[k][1][0], wl.s)
                                              for k, (P, wl) in enumerate(zip(Ps, wls))]))
         arena = sum(B.Engine.slot_bytes(P, wl.s) for P, wl in zip(Ps, wls))
-        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, pool=pool,
+        srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, tol=args.serve_tol, pool=pool,
                            check_every=args.check_every)
         for k, (wl, P) in enumerate(zip(wls, Ps)):
             path, xhats, xs = data[k]
@@ -661,6 +661,10 @@ def bench_serve(args, B, torch, synth):
         errs = [rel_err(r.hg, refs[(r.sample.key, r.step)]) for r in win]
         ok = sum(1 for r, e in zip(win, errs) if e <= 1e-6 and r.stats.status == 0)
         lat = [(r.t_done - r.t_arrival) * 1e3 for r in win]
+        stage = lambda a, b: float(np.mean([(getattr(r, b) - getattr(r, a)) * 1e3 for r in win])) if win else None
+        stages = {"queue": stage("t_arrival", "t_start"), "refresh": stage("t_start", "t_ready"),
+                  "wait_engine": stage("t_ready", "t_admit"), "solve": stage("t_admit", "t_solved"),
+                  "hypergradient": stage("t_solved", "t_done")}
         bpp = lambda smp: apply_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec, smp.s,
                                                 smp.P.n_filters)
         total_bytes = sum(bpp(r.sample) * r.sample.P.h * r.sample.P.w * r.stats.iters for r in srv.completed)
@@ -672,6 +676,7 @@ def bench_serve(args, B, torch, synth):
                                       "p99": float(np.percentile(lat, 99)) if lat else None},
                        "max_rel_err": max(errs) if errs else None,
                        "mean_iters": float(np.mean([r.stats.iters for r in win])) if win else None,
+                       "mean_stage_ms": {k: (round(v, 2) if v is not None else None) for k, v in stages.items()},
                        "roofline": roofline("k_b_apply<*> (all classes)", total_bytes / launches, kt, "serve")}
         log(f"[bench] serve {prec}: {modes[prec]['solves_per_s']:.1f} solves/s, p50 "
             f"{modes[prec]['latency_ms']['p50']} ms, p99 {modes[prec]['latency_ms']['p99']} ms, backlog {backlog}")
@@ -681,7 +686,9 @@ def bench_serve(args, B, torch, synth):
                     {"workload": f"serve: {len(wls)} resident samples (sides {sorted(set(w.h for w in wls))}, TV or "
                                  f"8 x 7x7 filters, s in {sorted(set(w.s for w in wls))}), {T} frozen outer steps each, "
                                  f"Poisson arrivals {args.rate:g}/s, {args.duration:g} s window after {args.warm_s:g} s, "
-                                 f"continuous batching (engine cap 64), mixed precision; FP64 beside it",
+                                 f"continuous batching (engine cap 64), error-estimate stop {args.hg_rel:g} x previous "
+                                 f"|grad| tested every {args.check_every} iterations, residual stop {args.serve_tol:g} "
+                                 f"without a recycle space, mixed precision; FP64 beside it",
                      "samples": len(wls), "rate_per_s": args.rate, "window_s": args.duration, "tiles": tiles},
                     latency_ms=head["latency_ms"], passing=head["passing"], mixed=head, fp64=modes["fp64"],
                     roofline=head["roofline"])
@@ -822,6 +829,8 @@ def main():
     ap.add_argument("--hg-rel", dest="hg_rel", type=float, default=1e-9, help="serve: error-estimate threshold "
                     "relative to the sample's previous hypergradient norm")
     ap.add_argument("--v-cap", dest="v_cap", type=int, default=V_CAP, help="serve: stored Krylov vectors per sample")
+    ap.add_argument("--serve-tol", dest="serve_tol", type=float, default=1e-8,
+                    help="serve: residual tolerance of solves without a recycle space (first step of a pass)")
     ap.add_argument("--check-every", dest="check_every", type=int, default=8,
                     help="iterations between error-estimate tests (Z^T r is formed on tested iterations only)")
     ap.add_argument("--rows", type=int, default=0, choices=(0, 8, 16, 32),

@@ -108,86 +108,148 @@ __global__ void __launch_bounds__(NT) k_jac_tv(Stencil S, const double* __restri
 }
 
 // ------------------------------------------------------------------ J for filters
-// Column c of G (p x ncols), per block over a band of tiles:
-//   [J w]_{w_j}    = -lam_j <d1_j, K_j w>
-//   [J w]_{k_j[a]} = -lam_j (<d1_j, S_a w> + <d2_j . K_j w, S_a xhat>)
+// Column c of G = J W (p x ncols), per block over a band of 8 x 32 tiles:
+//   [J w]_{w_j}      = -lam_j <d1_j, K_j w>
+//   [J w]_{k_j[a,b]} = -lam_j (<d1_j, S_ab w> + <d2_j . K_j w, S_ab xhat>)
+// (S_ab: shift by (a - F, b - F), zero outside the image).  Per tile, each thread forms K_j w
+// at one pixel for every filter from one window of w (the taps are uniform loads) and stores
+// d1_j and t_j = d2_j . K_j w; then items (j, a, r) (filter, tap row, tile row) sweep the 32
+// columns of row r with sliding windows of w and xhat held in registers, accumulating the FS
+// tap sums of both terms.  The accumulators stay in registers across the block's tiles and are
+// summed over the 8 tile rows (8 adjacent lanes) by shuffles at the end, in a fixed order.
 constexpr int JF_BLOCKS = 64;
+template <int FS>
 __global__ void __launch_bounds__(NT) k_jac_filters(Stencil S, const double* __restrict__ xhat,
                                                     const double* __restrict__ wv, const double* __restrict__ d1,
                                                     const double* __restrict__ d2, double* __restrict__ part) {
-    const int F = S.fs / 2, fs = S.fs, f2 = fs * fs, p = S.nf * (1 + f2);
-    const int WW = TW + 2 * F, HH = TH + 2 * F;
-    __shared__ double ws[(TH + 2 * (MAX_FS / 2)) * (TW + 2 * (MAX_FS / 2))];
-    __shared__ double xs[(TH + 2 * (MAX_FS / 2)) * (TW + 2 * (MAX_FS / 2))];
-    __shared__ double kw[TH * TW], d1s[TH * TW], ts[TH * TW];
-    __shared__ double taps[MAX_NF * MAX_FS * MAX_FS];
-    __shared__ double acc_s[MAX_NF * (1 + MAX_FS * MAX_FS)];
-    __shared__ double red[NWAVE];
-    const double* w = wv + (size_t)blockIdx.y * S.n;
-    for (int k = threadIdx.x; k < S.nf * f2; k += NT) taps[k] = S.taps[k];
-    for (int k = threadIdx.x; k < p; k += NT) acc_s[k] = 0.0;
+    constexpr int F = FS / 2, F2 = FS * FS;
+    constexpr int WW = TW + 2 * F, HH = TH + 2 * F;
+    constexpr int NITEM = MAX_NF * FS * TH;
+    constexpr int IPT = (NITEM + NT - 1) / NT;
+    __shared__ double ws[HH * WW], xs[HH * WW];
+    __shared__ double d1s[MAX_NF][TH * TW], tss[MAX_NF][TH * TW];
+    __shared__ double acc_s[MAX_NF * (1 + F2)];
+    __shared__ double wred[NWAVE][MAX_NF];
+    const int nf = S.nf, p = nf * (1 + F2);
+    const size_t n = (size_t)S.n;
+    const double* __restrict__ w = wv + (size_t)blockIdx.y * n;
+    const double* __restrict__ tp = S.taps;
+    double A1[IPT][FS], A2[IPT][FS], wacc[MAX_NF];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u)
+#pragma unroll
+        for (int b = 0; b < FS; ++b) A1[u][b] = A2[u][b] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAX_NF; ++j) wacc[j] = 0.0;
+    const int pr_ = threadIdx.x / TW, pc = threadIdx.x % TW;   // the thread's pixel of a tile
     const int ntiles = S.tiles_x * S.tiles_y;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         int r0, c0;
         tile_origin(S, tile, r0, c0);
-        __syncthreads();
+        __syncthreads();   // the previous tile's sweep is done with the LDS arrays
         for (int idx = threadIdx.x; idx < HH * WW; idx += NT) {
             const int rr = idx / WW, cc = idx - rr * WW;
             const int gi = r0 - F + rr, gj = c0 - F + cc;
             const bool in = gi >= 0 && gi < S.h && gj >= 0 && gj < S.w;
-            ws[idx] = in ? w[gi * S.w + gj] : 0.0;
-            xs[idx] = in ? xhat[gi * S.w + gj] : 0.0;
+            ws[idx] = in ? w[(size_t)gi * S.w + gj] : 0.0;
+            xs[idx] = in ? xhat[(size_t)gi * S.w + gj] : 0.0;
         }
         __syncthreads();
-        for (int j = 0; j < S.nf; ++j) {
-            const double* kj = taps + j * f2;
-            for (int idx = threadIdx.x; idx < TH * TW; idx += NT) {
-                const int rr = idx / TW, cc = idx - rr * TW;
-                const int gi = r0 + rr, gj = c0 + cc;
-                double kwv = 0.0, a1 = 0.0, a2 = 0.0;
-                if (gi < S.h && gj < S.w) {
-                    for (int a = 0; a < fs; ++a)
-                        for (int b = 0; b < fs; ++b) kwv += kj[a * fs + b] * ws[(rr + a) * WW + cc + b];
-                    const size_t o = (size_t)j * S.n + gi * S.w + gj;
-                    a1 = d1[o];
-                    a2 = d2[o] * kwv;
-                }
-                kw[idx] = kwv;
-                d1s[idx] = a1;
-                ts[idx] = a2;
-            }
-            __syncthreads();
-            double wsum = 0.0;
-            for (int idx = threadIdx.x; idx < TH * TW; idx += NT) wsum += d1s[idx] * kw[idx];
-            wsum = block_sum(wsum, red);
-            if (threadIdx.x == 0) acc_s[j * (1 + f2)] += wsum;
-            // taps: thread groups split the tile pixels; group sums combined in fixed order
-            const int groups = NT / f2;               // >= 5 for f <= 7
-            const int tap = threadIdx.x % f2, grp = threadIdx.x / f2;
-            double part_t = 0.0;
-            if (grp < groups) {
-                const int a = tap / fs, b = tap - a * fs;
-                for (int idx = grp; idx < TH * TW; idx += groups) {
-                    const int rr = idx / TW, cc = idx - rr * TW;
-                    const int o = (rr + a) * WW + cc + b;   // S_a with offset (a - F, b - F)
-                    part_t += d1s[idx] * ws[o] + ts[idx] * xs[o];
+        {
+            const int gi = r0 + pr_, gj = c0 + pc;
+            const bool in = gi < S.h && gj < S.w;
+            double kw[MAX_NF];
+#pragma unroll
+            for (int j = 0; j < MAX_NF; ++j) kw[j] = 0.0;
+#pragma unroll
+            for (int a = 0; a < FS; ++a) {
+                double win[FS];
+#pragma unroll
+                for (int b = 0; b < FS; ++b) win[b] = ws[(pr_ + a) * WW + pc + b];
+#pragma unroll
+                for (int j = 0; j < MAX_NF; ++j) {
+                    if (j >= nf) break;
+#pragma unroll
+                    for (int b = 0; b < FS; ++b) kw[j] += tp[j * F2 + a * FS + b] * win[b];
                 }
             }
-            __syncthreads();
-            kw[threadIdx.x] = (grp < groups) ? part_t : 0.0;   // reuse kw as scratch (NT <= TH*TW)
-            __syncthreads();
-            if (threadIdx.x < f2) {
-                double sum = 0.0;
-                for (int gq = 0; gq < groups; ++gq) sum += kw[gq * f2 + threadIdx.x];
-                acc_s[j * (1 + f2) + 1 + threadIdx.x] += sum;
+            const size_t o = in ? (size_t)gi * S.w + gj : 0;
+#pragma unroll
+            for (int j = 0; j < MAX_NF; ++j) {
+                if (j >= nf) break;
+                const double a1 = in ? d1[(size_t)j * n + o] : 0.0;
+                const double a2 = in ? d2[(size_t)j * n + o] : 0.0;
+                d1s[j][threadIdx.x] = a1;
+                tss[j][threadIdx.x] = a2 * kw[j];
+                wacc[j] += a1 * kw[j];
             }
-            __syncthreads();
         }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int item = threadIdx.x + u * NT;
+            const int r = item % TH, ja = item / TH, a = ja % FS, j = ja / FS;
+            if (j < nf) {
+                const double* wrow = ws + (r + a) * WW;
+                const double* xrow = xs + (r + a) * WW;
+                const double* drow = d1s[j] + r * TW;
+                const double* trow = tss[j] + r * TW;
+                double wwin[FS], xwin[FS];
+#pragma unroll
+                for (int b = 0; b + 1 < FS; ++b) {
+                    wwin[b] = wrow[b];
+                    xwin[b] = xrow[b];
+                }
+#pragma unroll
+                for (int c = 0; c < TW; ++c) {
+                    wwin[FS - 1] = wrow[c + FS - 1];
+                    xwin[FS - 1] = xrow[c + FS - 1];
+                    const double dd = drow[c], tt = trow[c];
+#pragma unroll
+                    for (int b = 0; b < FS; ++b) {
+                        A1[u][b] += dd * wwin[b];
+                        A2[u][b] += tt * xwin[b];
+                    }
+#pragma unroll
+                    for (int b = 0; b + 1 < FS; ++b) {
+                        wwin[b] = wwin[b + 1];
+                        xwin[b] = xwin[b + 1];
+                    }
+                }
+            }
+        }
+    }
+    // weight terms: block sums of wacc_j
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < MAX_NF; ++j) {
+        const double v = wave_sum(wacc[j]);
+        if (lane == 0) wred[wave][j] = v;
+    }
+    // tap terms: both terms, then the 8 tile rows (lanes 8g .. 8g + 7 share (j, a))
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        const int item = threadIdx.x + u * NT;
+        const int r = item % TH, ja = item / TH, a = ja % FS, j = ja / FS;
+#pragma unroll
+        for (int b = 0; b < FS; ++b) {
+            double v = A1[u][b] + A2[u][b];
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 4, 64);
+            if (r == 0 && j < nf) acc_s[j * (1 + F2) + 1 + a * FS + b] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nf) {
+        double v = 0.0;
+        for (int q = 0; q < NWAVE; ++q) v += wred[q][threadIdx.x];
+        acc_s[threadIdx.x * (1 + F2)] = v;
     }
     __syncthreads();
     double* pr = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * p;
     for (int k = threadIdx.x; k < p; k += NT) {
-        const int j = k / (1 + f2);
+        const int j = k / (1 + F2);
         pr[k] = -S.lamj[j] * acc_s[k];
     }
 }
@@ -428,7 +490,14 @@ hipError_t launch_jac(const Stencil& S, const double* xhat, const double* w, int
         hipLaunchKernelGGL(k_jac_tv, dim3(nb, ncols), dim3(NT), 0, stream, S, xhat, w, part);
     } else {
         p = S.nf * (1 + S.fs * S.fs);
-        hipLaunchKernelGGL(k_jac_filters, dim3(nb, ncols), dim3(NT), 0, stream, S, xhat, w, d1, d2, part);
+        const dim3 grid(nb, ncols);
+        switch (S.fs) {
+            case 1: hipLaunchKernelGGL(k_jac_filters<1>, grid, dim3(NT), 0, stream, S, xhat, w, d1, d2, part); break;
+            case 3: hipLaunchKernelGGL(k_jac_filters<3>, grid, dim3(NT), 0, stream, S, xhat, w, d1, d2, part); break;
+            case 5: hipLaunchKernelGGL(k_jac_filters<5>, grid, dim3(NT), 0, stream, S, xhat, w, d1, d2, part); break;
+            case 7: hipLaunchKernelGGL(k_jac_filters<7>, grid, dim3(NT), 0, stream, S, xhat, w, d1, d2, part); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -44,13 +44,14 @@ class Sample:
 
 
 class Request:
-    __slots__ = ("sample", "t_arrival", "step", "t_start", "t_done", "slot", "hg", "stats", "g", "fut", "opts")
+    __slots__ = ("sample", "t_arrival", "step", "t_start", "t_ready", "t_admit", "t_solved", "t_done", "slot", "hg",
+                 "stats", "g", "fut", "opts")
 
     def __init__(self, sample, t_arrival):
         self.sample = sample
         self.t_arrival = t_arrival
         self.step = -1
-        self.t_start = self.t_done = None
+        self.t_start = self.t_ready = self.t_admit = self.t_solved = self.t_done = None
         self.slot = None
         self.hg = None
         self.stats = None
@@ -128,6 +129,7 @@ class Server:
         if slot is None:
             return False
         req.slot = slot
+        req.t_admit = self.clock()
         self.running[slot] = req
         return True
 
@@ -158,6 +160,7 @@ class Server:
                 if req.fut is not None:
                     req.fut.result()
                 self.preparing.remove(req)
+                req.t_ready = self.clock()
                 self.ready.append(req)
         while self.ready:
             if not self._admit(self.ready[0]):
@@ -166,6 +169,7 @@ class Server:
         if self.running:
             for slot in self.engine.step(max_iters=self.iters_per_turn, return_on_done=True):
                 req = self.running.pop(slot)
+                req.t_solved = self.clock()
                 req.stats = self.engine.retire(slot)
                 smp = req.sample
                 if self.pool is None:

@@ -131,6 +131,23 @@ def test_hypergradient_map(B, kind):
             assert rel(hg_np, prob.jac_apply(xh, th, w, project=False)) <= 1e-12
 
 
+@pytest.mark.parametrize("fs,nf", [(1, 3), (3, 8), (5, 5), (7, 2)])
+def test_hypergradient_map_filter_sizes(B, fs, nf):
+    """J w for every filter size and for filter counts below the maximum, on a ragged image
+    (45 x 67: partial tiles in both directions), projected and unprojected."""
+    wl = synth.custom("f", 45, "filters", 4, width=67, rect_min=2, rect_max=6, seed=44, filter_size=fs,
+                      n_filters=nf)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xh = inst["xstar"].ravel() + 0.02 * synth.unit_noise(prob.n, 45)
+    th = inst["theta0"]
+    w = synth.unit_noise(prob.n, 46)
+    with B.Session(B.problem_from(wl)) as S:
+        for project in (True, False):
+            hg = S.hypergradient(th, dev(xh), dev(w), project=project)
+            assert rel(hg, prob.jac_apply(xh, th, w, project=project)) <= 1e-12, project
+
+
 # ------------------------------------------------------------------ Krylov
 def oracle_sensitivity(solve, g, seed=99):
     """Change of the oracle's own iterate when g is perturbed by one ulp: the rounding
