@@ -121,12 +121,12 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
 // TV on short tiles (8 or 16 rows, the small images, where latency decides): the loads that
 // do not depend on the scalars of this iteration (the thread's r, p and columns of C, the halo
 // of r and p, x_hat) are issued before the record reduction, so their latency overlaps it; the
-// stencil input r + beta p is formed from registers afterwards.  The
-// filter stencil is long enough to hide loads issued after it, and the registers of a
-// prefetch would cost occupancy there.
+// stencil input r + beta p is formed from registers afterwards.  Filters: the first columns
+// of C (about 20 values per thread) are loaded before the stencil, whose arithmetic then
+// hides them (measured: 7-13% per iteration over loading them after the stencil).
 template <int CLS, int Q, bool REC>
 __host__ __device__ constexpr int c_prefetch() {
-    return !REC ? 1 : (CLS != TC_TV ? 1 : (Q == 1 ? 24 : (Q == 2 ? 12 : 8)));
+    return !REC ? 1 : (CLS != TC_TV ? (Q == 1 ? 20 : (Q == 2 ? 10 : 5)) : (Q == 1 ? 24 : (Q == 2 ? 12 : 8)));
 }
 
 template <typename T, int R, int CLS, int Q, bool REC>
