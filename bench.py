@@ -483,7 +483,7 @@ def bench_batch(args, B, torch, synth):
     # tile heights: the whole batch shares the chip, so the autotuner times whole passes, one
     # per height for every image (untimed)
     search = {}
-    for rows in (8, 16, 32):
+    for rows in ((args.rows,) if args.rows else (8, 16, 32)):
         for P in Ps:
             B.bl_tile_rows_set(P, rows)
         torch.cuda.synchronize()
@@ -609,11 +609,14 @@ def bench_serve(args, B, torch, synth):
             xhats.append(x.clone())
         data.append((path, xhats, xs))
     log(f"[bench] frozen steps built in {time.perf_counter() - tt:.1f} s")
-    arrivals = synth.poisson_arrivals(args.rate, args.warm_s + args.duration, len(wls), seed=5001)
     pool = B.ContextPool(P64, max(w.s for w in wls), args.v_cap, args.workers, dev)
     modes = {}
     tiles = {}
-    for prec in ("mixed", "fp64"):
+    # the offered rate in both precisions, then (mixed) a rate below the measured capacity, where
+    # latency is service time rather than queueing
+    runs = [("mixed", args.rate), ("fp64", args.rate)] + ([("mixed", args.rate2)] if args.rate2 > 0 else [])
+    for prec, rate in runs:
+        arrivals = synth.poisson_arrivals(rate, args.warm_s + args.duration, len(wls), seed=5001)
         Ps = [B.problem_from(wl, prec=prec) for wl in wls]
         tiles.update(autotune_tiles(ctx, B, [(P, data[k][0][0], data[k][1][0], wl.s)
                                              for k, (P, wl) in enumerate(zip(Ps, wls))]))
@@ -643,6 +646,9 @@ def bench_serve(args, B, torch, synth):
                 continue
             srv.turn()
         backlog = len(srv.queue) + len(srv.preparing) + len(srv.ready) + len(srv.running) + len(srv.finishing)
+        for req in srv.preparing + srv.finishing:   # drain the pool before the next run
+            if req.fut is not None:
+                req.fut.result()
         kt = ctx.kernel_times(reset=True)
         ctx.set_timing(0)
         win = [r for r in srv.completed if r.t_arrival >= args.warm_s]
@@ -669,7 +675,9 @@ def bench_serve(args, B, torch, synth):
                                                 smp.P.n_filters)
         total_bytes = sum(bpp(r.sample) * r.sample.P.h * r.sample.P.w * r.stats.iters for r in srv.completed)
         launches = max(kt[1] * KT_SAMPLE, 1.0)
-        modes[prec] = {"solves_per_s": ok / args.duration, "completed": len(win), "passing": f"{ok}/{len(win)}",
+        key = prec if rate == args.rate else f"{prec}_at_{rate:g}_per_s"
+        modes[key] = {"rate_per_s": rate, "solves_per_s": ok / args.duration, "completed": len(win),
+                       "passing": f"{ok}/{len(win)}",
                        "arrived": sum(1 for a in arrivals if args.warm_s <= a[0] < end),
                        "backlog_at_end": backlog,
                        "latency_ms": {"p50": float(np.percentile(lat, 50)) if lat else None,
@@ -678,8 +686,8 @@ def bench_serve(args, B, torch, synth):
                        "mean_iters": float(np.mean([r.stats.iters for r in win])) if win else None,
                        "mean_stage_ms": {k: (round(v, 2) if v is not None else None) for k, v in stages.items()},
                        "roofline": roofline("k_b_apply<*> (all classes)", total_bytes / launches, kt, "serve")}
-        log(f"[bench] serve {prec}: {modes[prec]['solves_per_s']:.1f} solves/s, p50 "
-            f"{modes[prec]['latency_ms']['p50']} ms, p99 {modes[prec]['latency_ms']['p99']} ms, backlog {backlog}")
+        log(f"[bench] serve {key}: {modes[key]['solves_per_s']:.1f} solves/s, p50 "
+            f"{modes[key]['latency_ms']['p50']} ms, p99 {modes[key]['latency_ms']['p99']} ms, backlog {backlog}")
         srv.close()
     head = modes["mixed"]
     out = base_line(args, head["solves_per_s"], args.duration * 1e3 * args.steps, "f32+f64",
@@ -691,7 +699,7 @@ def bench_serve(args, B, torch, synth):
                                  f"without a recycle space, mixed precision; FP64 beside it",
                      "samples": len(wls), "rate_per_s": args.rate, "window_s": args.duration, "tiles": tiles},
                     latency_ms=head["latency_ms"], passing=head["passing"], mixed=head, fp64=modes["fp64"],
-                    roofline=head["roofline"])
+                    roofline=head["roofline"], **{k: v for k, v in modes.items() if k not in ("mixed", "fp64")})
     out["steps"] = 1
     out["ms_per_step"] = args.duration * 1e3
     if not args.no_cpu:
@@ -824,6 +832,8 @@ def main():
                     "and hypergradients running beside the engine")
     ap.add_argument("--samples", type=int, default=64, help="serve: resident samples (of the 256-sample recipe)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--rate2", type=float, default=40.0,
+                    help="serve: second, sub-capacity arrival rate (mixed precision; 0: skip)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured window (s)")
     ap.add_argument("--warm-s", dest="warm_s", type=float, default=3.0, help="serve: warm-up part of the stream (s)")
     ap.add_argument("--hg-rel", dest="hg_rel", type=float, default=1e-9, help="serve: error-estimate threshold "
