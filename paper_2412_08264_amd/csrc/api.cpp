@@ -255,7 +255,7 @@ bl_status bl_hvp(bl_ctx* c, const bl_problem* P, const double* theta, const doub
     Stencil S;
     TRY(make_stencil(c, P, theta, ws, S));
     TRY(filter_state(c, S, xhat, ws));
-    HIPCHK(launch_hvp(S, P->prec == BL_PREC_MIXED, xhat, v, out, ncols, c->stream));
+    HIPCHK(launch_hvp(S, P->prec == BL_PREC_MIXED, xhat, v, out, ncols, tile_rows(P), c->stream));
     return BL_OK;
 }
 
@@ -507,7 +507,8 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     HIPCHK(launch_gemm_tall(n, t1, t, W1, Xinv, t1, W0, c->stream));   // W (orthonormal) in W0
     mark(c, 1);
     // Y = H W (FP64), M = W^T Y, G = J W
-    HIPCHK(launch_hvp(S, false, xhat, W0, W1, t, c->stream));
+    // t columns give any tile height enough blocks: the tallest (measured fastest for this product)
+    HIPCHK(launch_hvp(S, false, xhat, W0, W1, t, 4 * QTY, c->stream));
     HIPCHK(launch_gram(n, t, t, W0, W1, ws.part(), M, c->stream));
     HIPCHK(launch_jac(S, xhat, W0, t, ws.d1(), ws.d2(), ws.part(), Gj, 1, c->stream));
     mark(c, 2);

@@ -1,4 +1,5 @@
-// Batched residual and apply kernels on tiles of 32 x 8 pixels.
+// Batched residual and apply kernels, and the stand-alone Hessian-vector product, on tiles of
+// 32 x 8 pixels.
 #include "batch_tile.h"
 
 namespace bl {
@@ -6,5 +7,7 @@ namespace bl {
 template hipError_t launch_b_residual_q<1>(const Stencil&, bool, const Slot*, const BatchMap&, int, hipStream_t);
 template hipError_t launch_b_apply_q<1>(const Stencil&, bool, bool, const Slot*, const BatchMap&, StepRef,
                                              hipStream_t);
+template hipError_t launch_hvp_q<1>(const Stencil&, bool, const double*, const double*, double*, int,
+                                          hipStream_t);
 
 }  // namespace bl

@@ -269,6 +269,34 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
         m.y);
 }
 
+// ------------------------------------------------------------------ out[:, c] = H v[:, c]
+// One 32 x 8Q tile of one column per block (grid: tiles x columns): the refresh's Y = H W and
+// the stand-alone product of the ABI.
+template <typename T, int R, int CLS, int Q>
+__global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict__ xhat,
+                                            const double* __restrict__ v, double* __restrict__ out) {
+    constexpr int QH = QTY * Q;
+    using L = QLayout<T, R, CLS, Q>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int qtx = (S.w + QW - 1) / QW;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r0 = (t / qtx) * QH, c0 = (t % qtx) * QW;
+    const double* vc = v + (size_t)blockIdx.y * S.n;
+    q_stage<T, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0, [&](int i) { return vc[i]; });
+    if constexpr (CLS == TC_TV) q_stage_xhat<T, Q>(lds + L::o_x, S.h, S.w, xhat, r0, c0);
+    __syncthreads();
+    T hv[Q];
+    q_hvp<T, R, CLS, Q>(lds, S, r0, c0, hv);
+    double* oc = out + (size_t)blockIdx.y * S.n;
+    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int gi = r0 + Q * ty + k;
+        if (gi < S.h && gj < S.w) oc[gi * S.w + gj] = (double)hv[k];
+    }
+}
+
 template <typename K>
 static void allow_lds_b(K kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -308,6 +336,25 @@ hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot
         } else {
             if (rec) go(k_b_apply<double, RR, CC, Q, true>, l64);
             else go(k_b_apply<double, RR, CC, Q, false>, l64);
+        }
+    });
+    return hipGetLastError();
+}
+
+template <int Q>
+hipError_t launch_hvp_q(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
+                        hipStream_t st) {
+    const dim3 grid(((S.w + QW - 1) / QW) * ((S.h + QTY * Q - 1) / (QTY * Q)), ncols);
+    q_dispatch(S.R, tile_class(S.reg, S.fs), [&](auto rc, auto cc) {
+        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
+        if (fp32) {
+            const size_t lds = QLayout<float, RR, CC, Q>::bytes;
+            allow_lds_b(k_hvp<float, RR, CC, Q>, lds);
+            hipLaunchKernelGGL((k_hvp<float, RR, CC, Q>), grid, dim3(NT), lds, st, S, xhat, v, out);
+        } else {
+            const size_t lds = QLayout<double, RR, CC, Q>::bytes;
+            allow_lds_b(k_hvp<double, RR, CC, Q>, lds);
+            hipLaunchKernelGGL((k_hvp<double, RR, CC, Q>), grid, dim3(NT), lds, st, S, xhat, v, out);
         }
     });
     return hipGetLastError();

@@ -7,8 +7,12 @@ namespace bl {
 
 // stencil.hip
 int tiles_of(const Stencil& S);
+// H v for ncols columns on tiles of `rows` (8, 16 or 32) rows; batch_q{1,2,4}.hip instantiate it.
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
-                      hipStream_t st);
+                      int rows, hipStream_t st);
+template <int Q>
+hipError_t launch_hvp_q(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
+                        hipStream_t st);
 hipError_t launch_filter_state(const Stencil& S, const double* xhat, double* d1, double* d2, float* d2f,
                                hipStream_t stream);
 int jac_blocks(const Stencil& S);
@@ -46,6 +50,13 @@ hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot
                                                       hipStream_t);                                               \
     extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, bool, const Slot*, const BatchMap&,      \
                                                    StepRef, hipStream_t);
+#define BL_HVP_EXTERN(Q)                                                                                   \
+    extern template hipError_t launch_hvp_q<Q>(const Stencil&, bool, const double*, const double*, double*, int, \
+                                               hipStream_t);
+BL_HVP_EXTERN(1)
+BL_HVP_EXTERN(2)
+BL_HVP_EXTERN(4)
+#undef BL_HVP_EXTERN
 BL_TILE_EXTERN(1)
 BL_TILE_EXTERN(2)
 BL_TILE_EXTERN(4)

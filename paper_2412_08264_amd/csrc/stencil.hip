@@ -17,33 +17,6 @@ __device__ __forceinline__ void write_partials(double* part, int nv, double*, Va
     block_partials(part, nv, val);
 }
 
-// ------------------------------------------------------------------ out[:, c] = H v[:, c]
-// One 32 x 32 tile of one column per block (grid: tiles x columns).
-template <typename T, int R, int CLS>
-__global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict__ xhat,
-                                            const double* __restrict__ v, double* __restrict__ out) {
-    constexpr int QR = Q_DEFAULT, QH = QTY * QR;
-    using L = QLayout<T, R, CLS, QR>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-    const int qtx = (S.w + QW - 1) / QW;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int r0 = (t / qtx) * QH, c0 = (t % qtx) * QW;
-    const double* vc = v + (size_t)blockIdx.y * S.n;
-    q_stage<T, R, CLS, QR>(lds + L::o_v, S.h, S.w, r0, c0, [&](int i) { return vc[i]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<T, QR>(lds + L::o_x, S.h, S.w, xhat, r0, c0);
-    __syncthreads();
-    T hv[QR];
-    q_hvp<T, R, CLS, QR>(lds, S, r0, c0, hv);
-    double* oc = out + (size_t)blockIdx.y * S.n;
-    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
-#pragma unroll
-    for (int k = 0; k < QR; ++k) {
-        const int gi = r0 + QR * ty + k;
-        if (gi < S.h && gj < S.w) oc[gi * S.w + gj] = (double)hv[k];
-    }
-}
-
 // ------------------------------------------------------------------ filter state
 // d1_j = phi'(K_j xhat), d2_j = phi''(K_j xhat) (FP64 maps, plus FP32 copies of d2).
 __global__ void __launch_bounds__(NT) k_filter_state(Stencil S, const double* __restrict__ xhat,
@@ -452,21 +425,13 @@ int tiles_of(const Stencil& S) { return S.tiles_x * S.tiles_y; }
 
 // Kernels are instantiated per blur radius (0..MAX_R) and arithmetic type.
 hipError_t launch_hvp(const Stencil& S, bool fp32, const double* xhat, const double* v, double* out, int ncols,
-                      hipStream_t st) {
-    const dim3 grid(((S.w + QW - 1) / QW) * ((S.h + QTY * Q_DEFAULT - 1) / (QTY * Q_DEFAULT)), ncols);
-    q_dispatch(S.R, tile_class(S.reg, S.fs), [&](auto rc, auto cc) {
-        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
-        if (fp32) {
-            const size_t lds = QLayout<float, RR, CC, Q_DEFAULT>::bytes;
-            allow_lds(k_hvp<float, RR, CC>, lds);
-            hipLaunchKernelGGL((k_hvp<float, RR, CC>), grid, dim3(NT), lds, st, S, xhat, v, out);
-        } else {
-            const size_t lds = QLayout<double, RR, CC, Q_DEFAULT>::bytes;
-            allow_lds(k_hvp<double, RR, CC>, lds);
-            hipLaunchKernelGGL((k_hvp<double, RR, CC>), grid, dim3(NT), lds, st, S, xhat, v, out);
-        }
-    });
-    return hipGetLastError();
+                      int rows, hipStream_t st) {
+    switch (rows) {
+        case QTY * 1: return launch_hvp_q<1>(S, fp32, xhat, v, out, ncols, st);
+        case QTY * 2: return launch_hvp_q<2>(S, fp32, xhat, v, out, ncols, st);
+        case QTY * 4: return launch_hvp_q<4>(S, fp32, xhat, v, out, ncols, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_filter_state(const Stencil& S, const double* xhat, double* d1, double* d2, float* d2f,

@@ -24,7 +24,6 @@ namespace bl {
 
 constexpr int QW = 32;                  // tile columns
 constexpr int QTY = NT / QW;            // thread rows of a block (8); a tile has QTY * Q rows
-constexpr int Q_DEFAULT = 4;            // rows per thread of the stand-alone HVP kernel (32 x 32 tiles)
 
 enum TileClass { TC_TV = 0, TC_F7 = 1, TC_FG = 2 };   // TV; filters 7x7; filters of another size
 

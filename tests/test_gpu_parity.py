@@ -84,6 +84,27 @@ def test_hvp_filters_fp64_and_mixed(B, shape):
         assert rel(host(out), ref) <= 1e-6
 
 
+@pytest.mark.parametrize("kind", ["tv", "filters"])
+def test_hvp_every_tile_height(B, kind):
+    """The stand-alone product on 8-, 16- and 32-row tiles (the height of P's table entry),
+    three columns, a ragged 61 x 83 image."""
+    wl, inst, prob, xh = tv_case(61, 83, seed=71) if kind == "tv" else foe_case(61, 83, seed=72)
+    th = inst["theta0"]
+    V = synth.unit_noise((3, prob.n), 73)
+    ref = np.stack([prob.hvp(xh, th, V[k]) for k in range(3)])
+    for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
+        P = B.problem_from(wl, prec=prec)
+        try:
+            for rows in (8, 16, 32):
+                B.bl_tile_rows_set(P, rows)
+                with B.Session(P) as S:
+                    out = torch.empty((3, prob.n), dtype=torch.float64, device=DEV)
+                    S.hvp(th, dev(xh), dev(V), out, ncols=3)
+                    assert rel(host(out), ref) <= tol, (prec, rows)
+        finally:
+            B.bl_tile_rows_set(P, 0)
+
+
 @pytest.mark.parametrize("fs,r", [(5, 3), (3, 8), (1, 0), (7, 1)])
 def test_hvp_filters_other_sizes_and_radii(B, fs, r):
     """Filter sizes other than 7x7 take the run-time-size path; radii 0..8 change the halo."""
