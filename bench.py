@@ -354,6 +354,9 @@ def bench_sequence(args, B, torch, synth):
                     roofline=roofline(kname, bpp * wl.n, kt, args.workload))
     if mixed:
         out["rgen_hg_fp64"] = extra["rgen_hg_fp64"]
+    if not args.no_micro and args.workload == "tv256":
+        log("[bench] HBM microbenchmark (4096 x 4096)")
+        out["hbm_micro"] = hbm_micro(args, B, torch, synth)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline_sequence(wl)
@@ -742,6 +745,59 @@ def cpu_baseline_serve(wls, data_steps, seconds_budget=25.0):
                       f"{len(os.sched_getaffinity(0))} affinity cores"}
 
 
+# =============================================================================== HBM microbenchmark
+def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=64):
+    """HBM rate of the iteration kernels where the working set is far above the 256 MB Infinity
+    Cache: a 4096 x 4096 TV problem (16.8 M pixels, FP64) solved for a fixed number of iterations
+    (stop test off) with s recycle columns that are zero (plain-CG arithmetic with every projection
+    read and written as in a recycled solve), then without a recycle space.  Apply and update
+    durations come from the library's sampled HIP events; rates use algorithmic bytes."""
+    wl = synth.custom("tv4096", side, "tv", s, blur_radius=4, blur_sigma=2.5, rect_min=8, rect_max=20, seed=6001)
+    inst = synth.instance(wl)
+    dev = torch.device("cuda:0")
+    n = wl.n
+    P = B.problem_from(wl, prec="fp64")
+    S = B.Session(P, s_max=s, v_cap=0, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs = t(inst["xstar"])
+    xh = xs + 0.05 * t(synth.unit_noise(n, 6002))
+    g = xh - xs
+    th = inst["theta0"]
+    if args.rows:
+        B.bl_tile_rows_set(P, args.rows)
+        tuned = None
+    else:
+        tuned = S.autotune_tiles(P, th, xh, s, 24)[1]
+    out = {"workload": f"{side}x{side} smoothed-TV (r=4), FP64, {iters} iterations, s={s} zero recycle columns "
+                       f"(recycled) or none (plain), residual stop off; tile height {B.bl_tile_rows(P)} rows",
+           "n": n, "autotune_us_per_iter": [round(u, 1) for u in tuned] if tuned else None}
+    for name, sc in (("recycled", s), ("plain", 0)):
+        S.rs.s_cur = sc
+        w = torch.zeros_like(xs)
+        S.solve(th, xh, g, w, tol=0.0, max_iter=16, store_basis=False, recycle=sc > 0, allow=(B.BL_E_NOT_CONVERGED,))
+        S.set_timing(2)
+        S.kernel_times(reset=True)
+        w.zero_()
+        S.solve(th, xh, g, w, tol=0.0, max_iter=iters, store_basis=False, recycle=sc > 0,
+                allow=(B.BL_E_NOT_CONVERGED,))
+        kt = S.kernel_times(reset=True)
+        S.set_timing(0)
+        a_us = kt[0] / max(kt[1], 1.0) * 1e3
+        u_us = kt[2] / max(kt[3], 1.0) * 1e3
+        a_bytes = 8 * (5 + sc) * n
+        u_bytes = 8 * (6 + sc) * n
+        out[name] = {"apply": {"kernel": f"k_b_apply<double, 4, 0, {B.bl_tile_rows(P) // 8}, {'true' if sc else 'false'}>",
+                               "avg_us": round(a_us, 2), "algorithmic_bytes": a_bytes,
+                               "GBps": round(a_bytes / (a_us * 1e3), 1),
+                               "frac": round(a_bytes / (a_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[1])},
+                     "update": {"kernel": "k_b_update", "avg_us": round(u_us, 2), "algorithmic_bytes": u_bytes,
+                                "GBps": round(u_bytes / (u_us * 1e3), 1),
+                                "frac": round(u_bytes / (u_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[3])}}
+    S.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 # =============================================================================== kernels-only
 def kernels_only_batch(args, B, torch, synth):
     """batch64 shapes at stand-in points x* + 0.05 e': 100 plain iterations of all images in one
@@ -825,6 +881,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve"))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-micro", dest="no_micro", action="store_true",
+                    help="skip the 4096 x 4096 HBM microbenchmark of the default workload")
+    ap.add_argument("--micro-only", dest="micro_only", action="store_true",
+                    help="run only the 4096 x 4096 HBM microbenchmark (profiling aid)")
     ap.add_argument("--outer", type=int, default=0, help="override the number of outer steps")
     ap.add_argument("--batch", type=int, default=64, help="batch64: number of images")
     ap.add_argument("--prec", default="mixed", choices=("mixed", "fp64"), help="batch64: precision")
@@ -851,7 +911,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-sample solves are "
-              "independent and would shard one sample per GPU, see the design notes.", file=sys.stderr)
+              "independent: several GPUs would each hold and solve their own samples.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -861,6 +921,9 @@ def main():
     torch.cuda.set_device(torch.device("cuda:0"))
     if args.kernels_only:
         kernels_only(args, B, torch, synth)
+        return
+    if args.micro_only:
+        print(json.dumps({"hbm_micro": hbm_micro(args, B, torch, synth)}), flush=True)
         return
     if args.workload == "batch64":
         out = bench_batch(args, B, torch, synth)

@@ -45,7 +45,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.slots = o;    o += al(sizeof(Slot));
     L.hdr = o;      o += al(HDR_BYTES);
     L.ctr = o;      o += al(sizeof(int));
-    L.fold = o;     o += al(4 * NV_RED * sizeof(double));
+    L.fold = o;     o += al((size_t)3 * FOLD_BLOCKS * NV_RED * sizeof(double));
     L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
@@ -74,7 +74,7 @@ struct WS {
     double* part_res() const { return part(); }
     double* part_app() const { return part() + L.part_doubles; }
     double* part_upd() const { return part() + 2 * L.part_doubles; }
-    double* part_fold(int k) const { return (double*)(base + L.fold) + k * NV_RED; }
+    double* part_fold(int k) const { return (double*)(base + L.fold) + (size_t)k * FOLD_BLOCKS * NV_RED; }
     double* vec(int k) const { return (double*)(base + L.vec) + (size_t)k * L.n; }
     double* d1() const { return (double*)(base + L.maps); }
     double* d2() const { return d1() + (size_t)L.nf * L.n; }

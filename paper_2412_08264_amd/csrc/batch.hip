@@ -162,10 +162,13 @@ __global__ void __launch_bounds__(NT) k_b_finish(const Slot* __restrict__ slots,
 }
 
 // Fold the records of kind `which` (0 residual, 1 apply, 2 update, read by the test of step
-// sr): one block per listed slot.
+// sr): FOLD_BLOCKS blocks per listed slot; block f reduces the records f * nb / FOLD_BLOCKS ..
+// (f + 1) * nb / FOLD_BLOCKS - 1 (in order) into folded record f, and consumers then reduce the
+// FOLD_BLOCKS folded records (two levels, fixed order: deterministic).
 __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which, StepRef sr) {
     __shared__ double tot[NT];
-    const Slot& sl = slots[M.slot[blockIdx.x]];
+    const Slot& sl = slots[M.slot[blockIdx.x / FOLD_BLOCKS]];
+    const int f = blockIdx.x % FOLD_BLOCKS;
     int nb, nv;
     const double* rec;
     if (which == 0) {
@@ -181,8 +184,10 @@ __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, B
         nv = 1 + zr_width(sl.st, sl.nz, step_of(sr) - sl.j0);
         rec = sl.rec_upd;
     }
-    reduce_partials(rec, nb, nv, tot);
-    for (int k = threadIdx.x; k < nv; k += NT) sl.fold[which * NV_RED + k] = tot[k];
+    const int b0 = (int)((long)f * nb / FOLD_BLOCKS), b1 = (int)((long)(f + 1) * nb / FOLD_BLOCKS);
+    reduce_partials(rec + (size_t)b0 * nv, b1 - b0, nv, tot);
+    double* out = sl.fold + (size_t)which * FOLD_BLOCKS * NV_RED + (size_t)f * nv;
+    for (int k = threadIdx.x; k < nv; k += NT) out[k] = tot[k];
 }
 
 // Admission: descriptor `v` into slots[idx]; a zeroed SolveState with the settings of `init`
@@ -271,7 +276,7 @@ hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t str
 }
 hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, StepRef sr, hipStream_t stream) {
     if (list.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_fold, dim3(list.ns), dim3(NT), 0, stream, slots, list, which, sr);
+    hipLaunchKernelGGL(k_b_fold, dim3(list.ns * FOLD_BLOCKS), dim3(NT), 0, stream, slots, list, which, sr);
     return hipGetLastError();
 }
 hipError_t launch_b_admit(Slot* slots, int idx, const Slot& v, const StateInit& init, const double* mu,

@@ -55,15 +55,15 @@ __device__ __forceinline__ Own<Q> own_pixels(int h, int w, int r0, int c0) {
 // Records a consumer reads: the producer's per-block array, or its folded record.
 __device__ __forceinline__ const double* slot_rec(const Slot& sl, int which, int& nb) {
     if (which == 0) {
-        nb = sl.fold_res ? 1 : sl.ntiles;
+        nb = sl.fold_res ? FOLD_BLOCKS : sl.ntiles;
         return sl.fold_res ? sl.fold : sl.rec_res;
     }
     if (which == 1) {
-        nb = sl.fold_app ? 1 : sl.ntiles;
-        return sl.fold_app ? sl.fold + NV_RED : sl.rec_app;
+        nb = sl.fold_app ? FOLD_BLOCKS : sl.ntiles;
+        return sl.fold_app ? sl.fold + FOLD_BLOCKS * NV_RED : sl.rec_app;
     }
-    nb = sl.fold_upd ? 1 : sl.npix;
-    return sl.fold_upd ? sl.fold + 2 * NV_RED : sl.rec_upd;
+    nb = sl.fold_upd ? FOLD_BLOCKS : sl.npix;
+    return sl.fold_upd ? sl.fold + 2 * FOLD_BLOCKS * NV_RED : sl.rec_upd;
 }
 
 // ------------------------------------------------------------------ residual g - H w

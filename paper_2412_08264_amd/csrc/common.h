@@ -18,6 +18,7 @@ constexpr int MAX_NF = 8;       // largest number of filters
 constexpr int MAX_FS = 7;       // largest filter size
 constexpr int RED_BLOCKS = 512; // blocks of 1-D reduction kernels
 constexpr int NV_RED = 2 + 2 * S_MAX;   // widest per-block partial record
+constexpr int FOLD_BLOCKS = 128;        // blocks (and folded records) per slot of a record fold
 
 // Stencil description passed by value to kernels.
 struct Stencil {
@@ -85,7 +86,7 @@ struct Slot {
     double* rec_res;                      // records: residual (tiles), apply (tiles), update (pixel blocks)
     double* rec_app;
     double* rec_upd;
-    double* fold;                         // 3 folded records of NV_RED values
+    double* fold;                         // folded records: 3 kinds x FOLD_BLOCKS records of NV_RED values
 };
 
 // Block-to-slot map of one batched launch, passed by value: slot k of the launch is

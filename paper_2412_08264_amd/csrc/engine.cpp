@@ -154,7 +154,7 @@ size_t slot_bytes(const bl_problem* P, int s) {
     const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
     const size_t nt = ntiles_of(P->h, P->w, QTY), np = npix_of((long)n);
     return 4 * al(n * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al(TAPS_BYTES) +
-           2 * al(nt * (1 + s) * 8) + al(np * (1 + s) * 8) + al(3 * NV_RED * 8);
+           2 * al(nt * (1 + s) * 8) + al(np * (1 + s) * 8) + al((size_t)3 * FOLD_BLOCKS * NV_RED * 8);
 }
 
 SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
@@ -179,7 +179,7 @@ SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
     B.rec_res = (double*)take(nt * (1 + s) * 8);
     B.rec_app = (double*)take(nt * (1 + s) * 8);
     B.rec_upd = (double*)take(np * (1 + s) * 8);
-    B.fold = (double*)take(3 * NV_RED * 8);
+    B.fold = (double*)take((size_t)3 * FOLD_BLOCKS * NV_RED * 8);
     B.st = nullptr;
     return B;
 }

@@ -50,7 +50,8 @@ namespace blh {
 constexpr int POLL = 8;              // iterations launched between host polls of the stop flags
 constexpr int KT_SAMPLE = 8;         // timing mode 2: kernel events on every KT_SAMPLE-th step
 // Consumer kernels re-reduce the producer's per-block records in every block; above this many
-// record values a one-block kernel first folds them into one record (keeps the re-reads linear).
+// record values a fold kernel (FOLD_BLOCKS blocks per solve) first reduces them to FOLD_BLOCKS
+// records, so the consumers' re-reads stay bounded whatever the image size.
 constexpr long REC_LIMIT = 8192;
 constexpr size_t ALIGN = 256;
 constexpr int TAPS_MAX = bl::MAX_NF * bl::MAX_FS * bl::MAX_FS + bl::MAX_NF;

@@ -322,6 +322,36 @@ def test_error_estimate_on_tested_iterations_only(B):
         assert min(spread) - 4 <= st.iters <= max(spread) + 4, (st.iters, spread)
 
 
+def test_recycled_cg_folded_records(B):
+    """A 384 x 384 solve with s = 20 has more record values per kernel than the consumers reduce
+    directly (576 tiles x 21 values), so every record kind goes through the multi-block fold:
+    iterates and the error estimate against the oracle after a fixed number of iterations."""
+    wl, inst, prob, xh = tv_case(384, 384, seed=58)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-4, v_cap=30)
+    rs = recycle.refresh(hvp, lambda v: prob.jac_apply(xh, th, v), None, first["V"], s=20)
+    s_eff = rs["U"].shape[1]
+    k = 9
+    ref = krylov.recycled_cg(hvp, g, None, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
+                             stop="hgerr", hg_tol=0.0, record=True)
+    P = B.problem_from(wl)
+    try:
+        B.bl_tile_rows_set(P, 8)
+        with B.Session(P, s_max=20, v_cap=30) as S:
+            upload_recycle(S, rs)
+            w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+            st = S.solve(th, dev(xh), dev(g), w, tol=0.0, max_iter=k, stop="hgerr", hg_tol=0.0, check_every=4,
+                         store_basis=False, allow=(B.BL_E_NOT_CONVERGED,))
+            assert 576 * (1 + s_eff) > 8192
+            assert rel(host(w), ref["w"]) <= 1e-10
+            want = ref["hist_nsc"][8]
+            assert abs(st.est - want) <= 1e-9 * want
+    finally:
+        B.bl_tile_rows_set(P, 0)
+
+
 @pytest.mark.parametrize("kind,prec", [("tv", "fp64"), ("filters", "fp64"), ("tv", "mixed")])
 def test_recycled_cg_every_tile_height(B, kind, prec):
     """The fused apply/residual kernels at 8, 16 and 32 rows per tile (70 x 90: ragged tiles in
