@@ -129,11 +129,32 @@ constexpr int HDR_BYTES = (int)offsetof(SolveState, e);   // scalar header polle
 
 // ------------------------------------------------------------------------------------ reductions
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// A double moved across lanes by a DPP control (two 32-bit moves; every lane of a row takes
+// part, so the row and bank masks are full).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of G consecutive lanes (G a power of two, 1..64); every lane of a
+// group ends with the same value.  Lanes pair within quads (DPP quad permutations), then
+// mirror within half rows and rows of 16 (each partner already holds the other half's sum),
+// then across rows with LDS permutes.  Additions are commutative, so partners compute
+// identical sums; the pattern is fixed, so the result is deterministic.
+__device__ __forceinline__ double group_sum(double v, int G) {
+    if (G >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    if (G >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    if (G >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+    if (G >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+    if (G >= 32) v += __shfl_xor(v, 16, 64);
+    if (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
+
+__device__ __forceinline__ double wave_sum(double v) { return group_sum(v, 64); }
 
 // Sum `val` over the block; result valid in every thread.  `red` has NWAVE doubles.
 __device__ __forceinline__ double block_sum(double val, double* red) {
@@ -163,8 +184,9 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
         for (int u = 0; u < 8; ++u) v[u] = (k0 + u < nv) ? val(k0 + u) : 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
+            if (k0 + u >= nv) break;   // uniform: no reduction of the padding values
             const double sum = wave_sum(v[u]);
-            if (lane == 0 && k0 + u < nv) wred[wave][k0 + u] = sum;
+            if (lane == 0) wred[wave][k0 + u] = sum;
         }
     }
     __syncthreads();
@@ -179,8 +201,8 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
 
 // out[k] = sum over blocks of part[b*nv + k], k < nv (nv <= NT), into LDS `out` (all threads).
 // G threads share value k (G the largest power of two with G * nv <= NT): thread (k, j) sums
-// blocks j, j+G, ... (eight loads in flight), then the G partial sums are combined by an
-// xor butterfly (within a wave; across the waves of a group in wave order).  The order depends
+// blocks j, j+G, ... (eight loads in flight), then the G partial sums are combined by a group
+// sum (within a wave; across the waves of a group in wave order).  The order depends
 // only on (nblocks, nv), so every block that reduces the same records obtains bit-identical
 // values, and no thread adds more than nblocks / G + log2(G) terms in sequence.
 __device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv, double* out) {
@@ -208,8 +230,7 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
             for (int u = 0; u < w2; ++u) a[u] += a[u + w2];
         acc = a[0];
     }
-    const int span = G < 64 ? G : 64;
-    for (int off = span >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    acc = group_sum(acc, G < 64 ? G : 64);
     if (G <= 64) {
         if (j == 0 && k < nv) out[k] = acc;
     } else {

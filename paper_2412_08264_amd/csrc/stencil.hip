@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(NT) k_jac_tv(Stencil S, const double* __restri
 // d1_j and t_j = d2_j . K_j w; then items (j, a, r) (filter, tap row, tile row) sweep the 32
 // columns of row r with sliding windows of w and xhat held in registers, accumulating the FS
 // tap sums of both terms.  The accumulators stay in registers across the block's tiles and are
-// summed over the 8 tile rows (8 adjacent lanes) by shuffles at the end, in a fixed order.
+// summed over the 8 tile rows (8 adjacent lanes) by a group sum at the end, in a fixed order.
 constexpr int JF_BLOCKS = 64;
 template <int FS>
 __global__ void __launch_bounds__(NT) k_jac_filters(Stencil S, const double* __restrict__ xhat,
@@ -206,10 +206,7 @@ __global__ void __launch_bounds__(NT) k_jac_filters(Stencil S, const double* __r
         const int r = item % TH, ja = item / TH, a = ja % FS, j = ja / FS;
 #pragma unroll
         for (int b = 0; b < FS; ++b) {
-            double v = A1[u][b] + A2[u][b];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
+            const double v = group_sum(A1[u][b] + A2[u][b], 8);
             if (r == 0 && j < nf) acc_s[j * (1 + F2) + 1 + a * FS + b] = v;
         }
     }
