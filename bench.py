@@ -37,8 +37,8 @@ V_CAP = 64
 RESID_TOL = 1e-10      # residual tolerance of the workload recipe (upper end of the sweep)
 # Each variant is timed at the loosest stopping threshold of its sweep for which every
 # hypergradient of the sequence is within 1e-6 of the reference (untimed selection pass).
-SWEEP_RESID = (1e-6, 1e-7, 1e-8, 1e-9, 1e-10)
-SWEEP_HG = (1e-7, 1e-8, 1e-9, 1e-10, 1e-11)   # relative to the previous hypergradient norm
+SWEEP_RESID = (1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10)
+SWEEP_HG = (1e-7, 3e-8, 1e-8, 3e-9, 1e-9, 3e-10, 1e-10, 1e-11)   # relative to the previous hypergradient norm
 LBFGS_CAP = 1500       # L-BFGS iterations per lower solve of a trajectory (warm started)
 HBM_PEAK = 8000.0      # GB/s
 

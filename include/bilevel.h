@@ -155,7 +155,8 @@ bl_status bl_hypergradient(bl_ctx* ctx, const bl_problem* P, const double* theta
                            const double* w, double* grad_host, int project_zero_mean, void* ws, size_t ws_bytes);
 
 /* Matrix-free Hessian-vector products out[:, j] = H v[:, j], j < ncols (columns ld = n),
- * in the problem's precision (FP32 stencil arithmetic in mixed mode, FP64 output). */
+ * in the problem's precision (FP32 stencil arithmetic in mixed mode, FP64 output), on tiles
+ * of bl_tile_rows(P) rows. */
 bl_status bl_hvp(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
                  const double* v, double* out, int ncols, void* ws, size_t ws_bytes);
 
