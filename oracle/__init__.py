@@ -14,6 +14,7 @@ Modules
   problem  lower-level objectives (smoothed TV, fields-of-experts filters): Phi, grad, HVP, J
   lbfgs    L-BFGS lower-level solver
   krylov   plain CG, recycled CG (Galerkin counterpart of RMINRES), stop tests, reference solve
+  rminres  RMINRES (Algorithm 3) with the explicit residual of Appendix A, stop tests
   recycle  orthonormalisation, projected GSVD (two routes), Ritz-GSV selection, refresh
   upper    gradient descent with backtracking (frozen-trajectory generator)
 """
