@@ -180,11 +180,14 @@ def make_trajectory(ctx, P, B, wl, torch, y, xs, theta0, outer, gtol=1e-8):
 
 def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL, rr_every=50,
                  first_tol=RESID_TOL, check_every=1):
-    """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain'; thr: the stopping
+    """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain' (recycled CG, or CG)
+    | 'rminres_hg' | 'minres' (RMINRES with the error-estimate stop, or MINRES); thr: the stopping
     threshold (residual tolerance, or the error-estimate threshold relative to the previous
     hypergradient norm); first_tol: residual tolerance of the error-estimate variant's first
-    system, which has no recycle space yet (the plain variant's threshold).  Returns per-solve
-    records."""
+    system, which has no recycle space yet (the threshold of the variant without recycling).
+    Returns per-solve records."""
+    method = "rminres" if mode in ("rminres_hg", "minres") else "cg"
+    kind = {"rminres_hg": "rgen_hg", "minres": "plain"}.get(mode, mode)
     S.reset()
     w = torch.zeros_like(xs)
     prev_hg = None
@@ -192,15 +195,16 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
     for i, (th, x) in enumerate(zip(thetas, xhats)):
         t0 = time.perf_counter()
         g = x - xs
-        if mode != "plain" and i > 0:
+        if kind != "plain" and i > 0:
             S.refresh(th, x, s=S.rs.s_max)
-        if mode == "rgen_hg" and S.rs.s_cur > 0 and prev_hg is not None:
+        if kind == "rgen_hg" and S.rs.s_cur > 0 and prev_hg is not None:
             st = S.solve(th, x, g, w, stop="hgerr", hg_tol=thr * prev_hg, tol=RESID_TOL, store_basis=True,
-                         rr_every=rr_every, check_every=check_every)
+                         rr_every=rr_every, check_every=check_every, method=method)
         else:
             # first system of the error-estimate variant (no recycle space yet): residual test
-            st = S.solve(th, x, g, w, tol=first_tol if mode == "rgen_hg" else thr,
-                         store_basis=(mode != "plain"), recycle=(mode != "plain"), rr_every=rr_every)
+            st = S.solve(th, x, g, w, tol=first_tol if kind == "rgen_hg" else thr,
+                         store_basis=(kind != "plain"), recycle=(kind != "plain"), rr_every=rr_every,
+                         method=method)
         hg = S.hypergradient(th, x, w)
         t1 = time.perf_counter()
         if lat is not None:
@@ -302,11 +306,17 @@ def bench_sequence(args, B, torch, synth):
     variants = [("rgen_hg", Sh, SWEEP_HG), ("rgen_res", Sh, SWEEP_RESID), ("plain", S, SWEEP_RESID)]
     if mixed:
         variants.append(("rgen_hg_fp64", S, SWEEP_HG))
+    # the paper's own solver (FP64): RMINRES with the error-estimate stop, and MINRES
+    variants += [("minres", S, SWEEP_RESID), ("rminres_hg", S, SWEEP_HG)]
     chosen = {}
-    # plain first: its threshold is also the first-system tolerance of the estimate variants
-    for name, SS, sweep in [variants[2]] + [v for v in variants if v[0] != "plain"]:
+    # variants without recycling first: their thresholds are the first-system tolerances of
+    # the estimate variants of the same solver
+    first_of = lambda name: chosen.get("minres" if name == "rminres_hg" else "plain", RESID_TOL)
+    order = [v for v in variants if v[0] in ("plain", "minres")] + [v for v in variants
+                                                                    if v[0] not in ("plain", "minres")]
+    for name, SS, sweep in order:
         chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, name.replace("_fp64", ""), refs, sweep,
-                                        first_tol=chosen.get("plain", RESID_TOL), check_every=args.check_every)
+                                        first_tol=first_of(name), check_every=args.check_every)
         log(f"[bench] {name}: threshold {chosen[name]:g}")
     ftol = chosen["plain"]
     for _ in range(args.warmup):
@@ -324,10 +334,10 @@ def bench_sequence(args, B, torch, synth):
     extra = {}
     for name, SS, _ in variants[1:]:
         mode = name.replace("_fp64", "")
-        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name], first_tol=ftol,
+        run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name], first_tol=first_of(name),
                      check_every=args.check_every)
         rr, elm, okm, totm = timed_passes(SS, B, torch, thetas, xhats, xs, mode, refs, chosen[name], args.steps,
-                                          first_tol=ftol, check_every=args.check_every)
+                                          first_tol=first_of(name), check_every=args.check_every)
         extra[name] = {"solves_per_s": okm / elm, "threshold": chosen[name],
                        "iters_per_sequence": sum(r["iters"] for r in rr[0]),
                        "max_rel_err": max(r["err"] for r in rr[0]), "passing": f"{okm}/{totm}"}
@@ -354,6 +364,8 @@ def bench_sequence(args, B, torch, synth):
                     roofline=roofline(kname, bpp * wl.n, kt, args.workload))
     if mixed:
         out["rgen_hg_fp64"] = extra["rgen_hg_fp64"]
+    out["rminres"] = extra["rminres_hg"]
+    out["minres"] = extra["minres"]
     if not args.no_micro and args.workload == "tv256":
         log("[bench] HBM microbenchmark (4096 x 4096)")
         out["hbm_micro"] = hbm_micro(args, B, torch, synth)

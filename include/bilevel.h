@@ -149,6 +149,27 @@ bl_status bl_hessian_solve(bl_ctx* ctx, const bl_problem* P, const double* theta
                            const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
                            void* ws, size_t ws_bytes, bl_stats* out);
 
+/* Hessian solve H w = g by RMINRES (Section 2.2.2, Algorithm 3): the correction V_k y + U z
+ * minimising ||g - H w|| over w0 + range(U) + K_k((I - C C^T) H, r0) (eq. coupled), with the
+ * Lanczos vectors kept orthogonal to C = H U (eq. arnoldi_aug_matrix).  H may be indefinite.
+ * Same arguments as bl_hessian_solve; differences:
+ *   * FP64 only (a problem with prec = BL_PREC_MIXED is refused with BL_E_ARG; rr_every is
+ *     ignored);
+ *   * the residual test is |zeta_j| <= tol ||g||, |zeta_j| the residual norm that MINRES's QR
+ *     factors give; the error-estimate test forms Z^T r_j from the explicit residual kept by
+ *     the recurrence of Appendix A's residual (in a one-vector form); both run on iterates j
+ *     with j % check_every == 0;
+ *   * with store_basis the normalised Lanczos vectors v_1, v_2, ... go to rs->V
+ *     (rs->v_cur = min(iters, v_cap));
+ *   * BL_E_BREAKDOWN if a Givens rotation meets a zero column (the iterate of the last test is
+ *     kept); BL_E_INDEFINITE is never returned.
+ * stats: res_norm = |zeta| at the returned iterate, res0_norm = ||r0|| after the projection.
+ * Tiles of 32 x 8 pixels; no graph replay: two launches per step from the host, with a poll of
+ * the stop flag every 8 steps. */
+bl_status bl_hessian_solve_rminres(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                                   const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
+                                   void* ws, size_t ws_bytes, bl_stats* out);
+
 /* Hypergradient J w = -(D_theta grad_x Phi)^T w (eq. hypgrad) into grad_host (p doubles).
  * Filters: each filter's tap block is projected onto zero mean when project_zero_mean. */
 bl_status bl_hypergradient(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,

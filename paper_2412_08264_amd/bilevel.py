@@ -66,6 +66,8 @@ _SIGS = {
                                     _P(bl_recycle_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hessian_solve": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
                                    _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
+    "bl_hessian_solve_rminres": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
+                                           _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hypergradient": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _P(C.c_double), C.c_int,
                                    _vp, C.c_size_t]),
     "bl_hvp": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, C.c_int, _vp, C.c_size_t]),
@@ -264,7 +266,12 @@ class Context:
 
     def solve_p(self, P, rec, theta, xhat, g, w, tol=1e-10, stop: str = "resid", hg_tol: float = 0.0,
                 max_iter: int = 20000, check_every: int = 1, rr_every: int = 50, store_basis: bool = True,
-                recycle: bool = True, allow=(BL_OK,)) -> bl_stats:
+                recycle: bool = True, allow=(BL_OK,), method: str = "cg") -> bl_stats:
+        """Hessian solve by recycled CG (``method="cg"``) or RMINRES (``method="rminres"``)."""
+        if method not in ("cg", "rminres"):
+            raise ValueError(f"unknown method {method!r}")
+        fn, name = ((lib.bl_hessian_solve, "bl_hessian_solve") if method == "cg"
+                    else (lib.bl_hessian_solve_rminres, "bl_hessian_solve_rminres"))
         st = bl_stats()
         o = bl_solve_opts(BL_STOP_HGERR if stop == "hgerr" else BL_STOP_RESID, tol, hg_tol, max_iter, check_every,
                           rr_every, 1 if store_basis else 0)
@@ -273,13 +280,12 @@ class Context:
         if rs is not None and not recycle:
             saved, rs.s_cur = rs.s_cur, 0
         try:
-            code = lib.bl_hessian_solve(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), _ptr(g), _ptr(w),
-                                        C.byref(rs) if rs is not None else None, C.byref(o), self.ws_ptr,
-                                        self.ws_bytes, C.byref(st))
+            code = fn(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), _ptr(g), _ptr(w),
+                      C.byref(rs) if rs is not None else None, C.byref(o), self.ws_ptr, self.ws_bytes, C.byref(st))
         finally:
             if saved is not None:
                 rs.s_cur = saved
-        _check(self.ctx, code, "bl_hessian_solve", ok=allow)
+        _check(self.ctx, code, name, ok=allow)
         return st
 
     def hypergradient_p(self, P, theta, xhat, w, project: bool = True) -> np.ndarray:

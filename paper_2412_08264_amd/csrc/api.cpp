@@ -21,7 +21,7 @@ constexpr int LBFGS_MMAX = 20;
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, slots, hdr, ctr, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, mstate, slots, hdr, ctr, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -42,6 +42,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.part_doubles = pd;
     size_t o = 0;
     L.state = o;    o += al(sizeof(SolveState));
+    L.mstate = o;   o += al(sizeof(MinresState));
     L.slots = o;    o += al(sizeof(Slot));
     L.hdr = o;      o += al(HDR_BYTES);
     L.ctr = o;      o += al(sizeof(int));
@@ -67,6 +68,7 @@ struct WS {
     Layout L;
     char* base;
     SolveState* st() const { return (SolveState*)(base + L.state); }
+    MinresState* mst() const { return (MinresState*)(base + L.mstate); }
     Slot* slots() const { return (Slot*)(base + L.slots); }
     int* hdr() const { return (int*)(base + L.hdr); }
     int* ctr() const { return (int*)(base + L.ctr); }
@@ -325,6 +327,107 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
         out->ms[3] = elapsed(c, 0, 2);
     }
     return (bl_status)st.status;
+}
+
+// ------------------------------------------------------------------------------ RMINRES
+// One solve, launched step by step: the set-up, then an apply and an update launch per Lanczos
+// step, with a record fold before a consumer whenever the records exceed REC_LIMIT values, and
+// a poll of the stop flag every POLL steps.  The test of iterate j runs in the apply launch of
+// step j + 2, so at most max_iter + 2 steps are launched.
+bl_status bl_hessian_solve_rminres(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat,
+                                   const double* g, double* w, bl_recycle* rs, const bl_solve_opts* o, void* wsp,
+                                   size_t ws_bytes, bl_stats* out) {
+    if (!c) return BL_E_ARG;
+    TRY(check_problem(c, P));
+    if (!xhat || !g || !w) return c->err = "null argument", BL_E_ARG;
+    TRY(check_solve_opts(c, o));
+    if (P->prec != BL_PREC_FP64) return c->err = "RMINRES runs in FP64 only", BL_E_ARG;
+    const int s = rs ? rs->s_cur : 0, s_max = rs ? rs->s_max : 0, v_cap = rs ? rs->v_cap : 0;
+    if (s_max < 0 || s_max > S_MAX || v_cap < 0) return c->err = "s_max outside [0, 64] or v_cap < 0", BL_E_SHAPE;
+    if (rs) {
+        if (s < 0 || s > s_max) return c->err = "s_cur outside [0, s_max]", BL_E_SHAPE;
+        if (s > 0 && (!rs->U || !rs->C || !rs->mu)) return c->err = "null recycle arrays", BL_E_ARG;
+        if (o->store_basis && (!rs->V || v_cap < 1)) return c->err = "store_basis needs V", BL_E_ARG;
+    }
+    WS ws;
+    TRY(check_ws(c, layout(P, s_max, v_cap), wsp, ws_bytes, ws));
+    mark(c, 0);
+    Stencil S;
+    TRY(make_stencil(c, P, theta, ws, S));
+    TRY(filter_state(c, S, xhat, ws));
+    const bool hg = o->stop == BL_STOP_HGERR && s > 0 && rs->Z;
+    const bool store = o->store_basis && rs;
+    const int n = P->h * P->w;
+    MinresArgs a{};
+    a.xhat = xhat;
+    a.g = g;
+    a.w = w;
+    a.r = ws.vec(0);
+    a.q = ws.vec(1);
+    for (int k = 0; k < 3; ++k) a.u[k] = ws.vec(2 + k);
+    for (int k = 0; k < 2; ++k) a.m[k] = ws.vec(5 + k);
+    a.U = s ? rs->U : nullptr;
+    a.C = s ? rs->C : nullptr;
+    a.Z = hg ? rs->Z : nullptr;
+    a.V = store ? rs->V : nullptr;
+    a.st = ws.mst();
+    a.rec_res = ws.part_res();
+    a.rec_app = ws.part_app();
+    a.rec_upd = ws.part_upd();
+    a.fold = ws.part_fold(0);
+    a.n = n;
+    a.ntiles = ((P->w + QW - 1) / QW) * ((P->h + QTY - 1) / QTY);
+    a.npix = (n + NT - 1) / NT;
+    a.s = s;
+    a.nz = hg ? s : 0;
+    const MinresInit in{o->tol, o->hg_tol, o->max_iter, o->check_every, o->stop, s, a.nz, hg ? 1 : 0,
+                        store ? 1 : 0, v_cap, s ? rs->mu : nullptr};
+    HIPCHK(launch_m_residual(S, a, c->stream));
+    const bool fold_res = (long)a.ntiles * (1 + s) > REC_LIMIT;
+    if (fold_res) HIPCHK(launch_m_fold(a.rec_res, a.ntiles, 1 + s, a.fold, c->stream));
+    HIPCHK(launch_m_init(a, in, fold_res, c->stream));
+    mark(c, 1);
+    const bool fold_app = (long)a.ntiles * (1 + s) > REC_LIMIT;
+    int nvb = 1 + a.nz;   // the set-up's record: iterate 0 is always tested
+    bool decided = false;
+    const long kmax = (long)o->max_iter + 2;
+    for (long k = 1; k <= kmax && !decided; ++k) {
+        const bool fold_upd = (long)a.npix * nvb > REC_LIMIT;
+        if (fold_upd) HIPCHK(launch_m_fold(a.rec_upd, a.npix, nvb, a.fold, c->stream));
+        HIPCHK(launch_m_apply(S, a, (int)k, nvb, fold_upd, c->stream));
+        if (fold_app) HIPCHK(launch_m_fold(a.rec_app, a.ntiles, 1 + s, a.fold, c->stream));
+        const int zr = (k >= 2 && a.nz > 0 && (k - 1) % o->check_every == 0) ? a.nz : 0;
+        HIPCHK(launch_m_update(a, (int)k, zr, fold_app, c->stream));
+        nvb = 1 + zr;
+        if (k % POLL == 0 || k == kmax) {
+            HIPCHK(hipMemcpyAsync(c->h_info, a.st, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            decided = c->h_info[0] != 0;
+        }
+    }
+    if (!decided) return c->err = "RMINRES ended without a stop decision", BL_E_HIP;
+    if (s) HIPCHK(launch_m_finish(a, c->stream));
+    mark(c, 2);
+    static_assert(sizeof(MinresState) <= 8192 * sizeof(double), "state exceeds the staging buffer");
+    HIPCHK(hipMemcpyAsync(c->h_buf, a.st, sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    MinresState hs;
+    std::memcpy(&hs, c->h_buf, sizeof(MinresState));
+    if (store) rs->v_cur = std::min(hs.iters, v_cap);
+    if (out) {
+        *out = bl_stats{};
+        out->iters = hs.iters;
+        out->status = hs.status;
+        out->s_cur = s;
+        out->res_norm = hs.res;
+        out->res0_norm = hs.res0;
+        out->g_norm = hs.gnorm;
+        out->est = hs.est;
+        out->ms[0] = elapsed(c, 0, 1);
+        out->ms[1] = elapsed(c, 1, 2);
+        out->ms[3] = elapsed(c, 0, 2);
+    }
+    return (bl_status)hs.status;
 }
 
 // ------------------------------------------------------------------------------ tile heights

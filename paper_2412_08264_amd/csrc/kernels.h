@@ -72,6 +72,52 @@ hipError_t launch_b_set_j0(Slot* slots, int idx, int j0, hipStream_t stream);
 hipError_t launch_b_headers(const Slot* slots, const BatchMap& list, int* out, int* ctr, int adv,
                             hipStream_t stream);
 
+// rminres.hip: RMINRES (Algorithm 3) on 32 x 8 tiles, FP64, one solve.
+// Scalars of the solve; slot k & 3 of a recurrence array holds step k's value.  Kernels read
+// values of earlier steps and block 0 writes the current step's, so no block reads a slot
+// that another block of the same launch writes.
+struct MinresState {
+    int done, status, iters, v_cur;     // header polled by the host
+    double res, res0, est, gnorm;
+    double tol, hg_tol;
+    int max_iter, check_every, stop, s, nz, hgerr_on, store, v_cap;
+    double beta[4], alpha[4], c[4], sn[4], zeta[4], gam[4], del[4], epst[4];
+    double e[4][S_MAX];       // C^T H v_k
+    double mh[4][S_MAX];      // b~_k in the coordinates of U (b~_k = U mh_k)
+    double zacc[S_MAX];       // sum over steps of c_k zeta_{k-1} mh_k
+    double mu[S_MAX];
+};
+struct MinresInit {
+    double tol, hg_tol;
+    int max_iter, check_every, stop, s, nz, hgerr_on, store, v_cap;
+    const double* mu;         // device, s values (may be null when s = 0)
+};
+struct MinresArgs {
+    const double* xhat;
+    const double* g;
+    double* w;
+    double* r;
+    double* q;
+    double* u[3];             // unnormalised Lanczos vectors: u_k = beta_k v_k in u[k % 3]
+    double* m[2];             // v~_k in m[k & 1]
+    const double* U;
+    const double* C;
+    const double* Z;
+    double* V;                // stored Lanczos vectors (store != 0)
+    MinresState* st;
+    double* rec_res;          // records of the residual launch (tiles x (1 + s))
+    double* rec_app;          // records of the apply launch (tiles x (1 + s))
+    double* rec_upd;          // records of the set-up and update launches (pixel blocks x (1 + nz))
+    double* fold;             // FOLD_BLOCKS folded records of NV_RED values
+    int n, ntiles, npix, s, nz;
+};
+hipError_t launch_m_residual(const Stencil& S, const MinresArgs& a, hipStream_t stream);
+hipError_t launch_m_init(const MinresArgs& a, const MinresInit& in, bool fold, hipStream_t stream);
+hipError_t launch_m_apply(const Stencil& S, const MinresArgs& a, int k, int nvb, bool fold, hipStream_t stream);
+hipError_t launch_m_update(const MinresArgs& a, int k, int nvb, bool fold, hipStream_t stream);
+hipError_t launch_m_finish(const MinresArgs& a, hipStream_t stream);
+hipError_t launch_m_fold(const double* rec, int nb, int nv, double* out, hipStream_t stream);
+
 // dense.hip
 int gram_chunks(int n);
 hipError_t launch_gram(int n, int t1, int t2, const double* A, const double* B, double* part, double* out,
