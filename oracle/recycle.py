@@ -21,6 +21,10 @@ Readings taken where the paper is silent:
     C~ = C R (diag R > 0), U = U~ R^{-1} (Section 2.2.2).
   * Z = W V_H (selected columns; zero for filled slots) and mu feed the
     hypergradient-error estimate ||mu . (Z^T r)|| of eq. hg-err-stop-lowrank.
+  * Other selections of Table 2 on the same projected matrices (:func:`select`): Ritz and
+    harmonic Ritz vectors of sizes S, L, M, and the L, R, M sides of RGen-L.  Readings: size M
+    keeps ceil(s/2) smallest and floor(s/2) largest values; the left vector of each right vector
+    x is v = M x / ||M x|| (the GSVD's M x = beta v fixes its sign), and side M is x/||x|| + v.
 """
 from __future__ import annotations
 
@@ -115,6 +119,78 @@ def select_rgen_large(G: np.ndarray, M: np.ndarray, s: int) -> dict:
     return {"X": X, "V_H": VH, "mu": mu, "rank_G": rG}
 
 
+# Selections of Table 2 built here: vector type and size (S: the s smallest values, L: the s
+# largest, M: ceil(s/2) smallest and floor(s/2) largest), and for RGen-L the side (R: right
+# vectors W X, L: left vectors W V_H, M: their normalised sum).
+SELECTIONS = ("rgen-l-r", "rgen-l-l", "rgen-l-m", "ritz-s", "ritz-l", "ritz-m", "hritz-s", "hritz-l", "hritz-m")
+
+
+def size_pick(t: int, s: int, size: str) -> list:
+    """Positions, in a list of t values sorted ascending, of the s values a size rule keeps:
+    smallest first for S, largest first for L, and for M the smallest ceil(s/2) (ascending)
+    followed by the largest floor(s/2) (descending)."""
+    s = min(s, t)
+    if size == "s":
+        return list(range(s))
+    if size == "l":
+        return list(range(t - 1, t - 1 - s, -1))
+    lo = (s + 1) // 2
+    return list(range(lo)) + list(range(t - 1, t - 1 - (s - lo), -1))
+
+
+def select_ritz(M: np.ndarray, s: int, size: str) -> dict:
+    """Ritz vectors (eq. ritz-matrix-decomp): eigenvectors of W^T H W (W orthonormal), chosen by
+    their Ritz values."""
+    lam, Q = np.linalg.eigh(M)
+    idx = size_pick(M.shape[0], s, size)
+    k = len(idx)
+    return {"X": Q[:, idx], "V_H": np.zeros((M.shape[0], k)), "mu": np.zeros(k), "rank_G": 0,
+            "values": lam[idx]}
+
+
+def select_hritz(M: np.ndarray, YtY: np.ndarray, s: int, size: str) -> dict:
+    """Harmonic Ritz vectors (eq. harmonic-ritz): (HW)^T HW rho = theta (HW)^T W rho, with
+    (HW)^T W = W^T H W = M.  Solved as the symmetric-definite problem M rho = nu (Y^T Y) rho
+    (Y = H W of full column rank), theta = 1 / nu, and chosen by theta."""
+    import scipy.linalg
+    nu, R = scipy.linalg.eigh(M, YtY)
+    theta = 1.0 / nu
+    order = np.argsort(theta, kind="stable")
+    idx = [order[j] for j in size_pick(M.shape[0], s, size)]
+    k = len(idx)
+    return {"X": R[:, idx], "V_H": np.zeros((M.shape[0], k)), "mu": np.zeros(k), "rank_G": 0,
+            "values": theta[idx]}
+
+
+def rgen_side(M: np.ndarray, sel: dict, side: str) -> dict:
+    """Side of the RGen-L vectors.  The GSVD ties each left vector to its right one,
+    M x_i = beta_i v_i with beta_i > 0, so v = M x / ||M x|| fixes its sign; this holds for the
+    filled slots (mu = 0, beta = 1) too.  Side L takes v, side M the normalised x + v; Z and mu
+    stay those of the GSVD."""
+    if side == "r":
+        return sel
+    X = sel["X"] / np.linalg.norm(sel["X"], axis=0, keepdims=True)
+    Vl = M @ X
+    Vl = Vl / np.linalg.norm(Vl, axis=0, keepdims=True)
+    out = dict(sel)
+    out["X"] = Vl if side == "l" else X + Vl
+    return out
+
+
+def select(G, M, YtY, s: int, rule: str) -> dict:
+    """Dispatch a selection rule of SELECTIONS."""
+    kind, size, *rest = rule.split("-")
+    if kind == "rgen":
+        if size != "l":
+            raise ValueError(f"RGen sizes other than L are not built: {rule}")
+        return rgen_side(M, select_rgen_large(G, M, s), rest[0])
+    if kind == "ritz":
+        return select_ritz(M, s, size)
+    if kind == "hritz":
+        return select_hritz(M, YtY, s, size)
+    raise ValueError(f"unknown selection {rule}")
+
+
 def build_from_selection(W: np.ndarray, Y: np.ndarray, sel: dict) -> dict:
     """U~ = W X~, C~ = Y X~ (= H U~), thin QR C~ = C R, U = U~ R^{-1}, Z = W V_H~."""
     X = sel["X"] / np.linalg.norm(sel["X"], axis=0, keepdims=True)
@@ -129,8 +205,10 @@ def build_from_selection(W: np.ndarray, Y: np.ndarray, sel: dict) -> dict:
     return {"U": U, "C": Qc, "Z": W @ sel["V_H"], "mu": sel["mu"].copy()}
 
 
-def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL) -> dict:
-    """Outer RGen-L(R) refresh.  ``hvp(v)``/``jac_apply(v)`` use the new (x_hat, theta)."""
+def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL, select_rule: str = "rgen-l-r") -> dict:
+    """Outer refresh (RGen-L(R) by default; any rule of SELECTIONS).  ``hvp(v)``/``jac_apply(v)``
+    use the new (x_hat, theta).  Selections other than RGen leave mu = 0 and Z = 0: the
+    error-estimate test is then undefined and solves use the residual test."""
     blocks = [B for B in (U_prev, V_prev) if B is not None and B.shape[1] > 0]
     if not blocks or s <= 0:
         return {"U": None, "C": None, "Z": None, "mu": None, "t": 0, "rank_G": 0}
@@ -138,8 +216,10 @@ def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL) 
     t = W.shape[1]
     Y = np.stack([hvp(W[:, c]) for c in range(t)], axis=1)
     M = 0.5 * (W.T @ Y + Y.T @ W)
-    G = np.stack([jac_apply(W[:, c]) for c in range(t)], axis=1)
-    sel = select_rgen_large(G, M, s)
+    rgen = select_rule.startswith("rgen")
+    G = np.stack([jac_apply(W[:, c]) for c in range(t)], axis=1) if rgen else None
+    YtY = Y.T @ Y if select_rule.startswith("hritz") else None
+    sel = select(G, M, YtY, s, select_rule)
     out = build_from_selection(W, Y, sel)
     out.update({"t": t, "rank_G": sel["rank_G"], "W": W, "M": M, "G": G, "Y": Y, "sel": sel,
                 "dropped": len(np.concatenate(blocks, axis=1).T) - len(kept)})
