@@ -92,9 +92,27 @@ typedef struct {
     int store_basis;         /* store normalised residuals into rs->V                         */
 } bl_solve_opts;
 
+/* Recycle-space selections (Table 2) on the projected matrices of the refresh, W orthonormal:
+ *   RGEN_L_R / _L / _M: the s largest Ritz generalized singular values of (J W, W^T H W)
+ *     (Section 3.2), right vectors W X, left vectors W V_H, or their sum (each left vector taken
+ *     as v = W^T H W x / ||W^T H W x||, x unit; side M is x + v), with Z and mu for the
+ *     error-estimate test;
+ *   RITZ_S / _L / _M: Ritz vectors (eq. ritz-matrix-decomp) of the smallest, the largest, or
+ *     ceil(s/2) smallest and floor(s/2) largest Ritz values;
+ *   HRITZ_S / _L / _M: harmonic Ritz vectors (eq. harmonic-ritz) chosen likewise by the harmonic
+ *     Ritz values.
+ * Ritz and harmonic Ritz selections need no J and write mu = 0 and Z = 0: the error-estimate
+ * test is then undefined (its estimate is 0), so solves after them use the residual test. */
+typedef enum {
+    BL_SEL_RGEN_L_R = 0, BL_SEL_RGEN_L_L = 1, BL_SEL_RGEN_L_M = 2,
+    BL_SEL_RITZ_S = 3, BL_SEL_RITZ_L = 4, BL_SEL_RITZ_M = 5,
+    BL_SEL_HRITZ_S = 6, BL_SEL_HRITZ_L = 7, BL_SEL_HRITZ_M = 8
+} bl_select;
+
 typedef struct {
     int s;                   /* requested recycle dimension (<= rs->s_max)                    */
     double rank_tol;         /* relative column-norm drop threshold for orthonormalising W   */
+    int select;              /* bl_select (0: RGen-L(R))                                       */
 } bl_recycle_opts;
 
 typedef struct {
@@ -136,7 +154,9 @@ bl_status bl_lower_solve(bl_ctx* ctx, const bl_problem* P, const double* theta_h
  * W = orth([U, V]) from rs, projects M = W^T H W, G = J W at (xhat, theta), takes the s
  * largest Ritz generalized singular values (null(G) filled by Ritz-S when rank G < s),
  * and writes U, C = H U (C^T C = I), Z, mu and s_cur into rs.  rs->s_cur = 0 and
- * rs->v_cur = 0 leave rs empty. */
+ * rs->v_cur = 0 leave rs empty.  opts->select picks another rule of bl_select on the same
+ * projected matrices (Ritz and harmonic Ritz selections also work for indefinite H, where
+ * RGen's Cholesky of W^T H W fails with BL_E_INDEFINITE). */
 bl_status bl_recycle_update(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
                             bl_recycle* rs, const bl_recycle_opts* opts, void* ws, size_t ws_bytes,
                             bl_stats* out);

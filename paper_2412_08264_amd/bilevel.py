@@ -41,7 +41,12 @@ class bl_solve_opts(C.Structure):
 
 
 class bl_recycle_opts(C.Structure):
-    _fields_ = [("s", C.c_int), ("rank_tol", C.c_double)]
+    _fields_ = [("s", C.c_int), ("rank_tol", C.c_double), ("select", C.c_int)]
+
+
+# selection rules of bl_select, by name
+SELECTIONS = {"rgen-l-r": 0, "rgen-l-l": 1, "rgen-l-m": 2, "ritz-s": 3, "ritz-l": 4, "ritz-m": 5,
+              "hritz-s": 6, "hritz-l": 7, "hritz-m": 8}
 
 
 class bl_stats(C.Structure):
@@ -256,9 +261,9 @@ class Context:
                "bl_lower_solve", ok=(BL_OK, BL_E_NOT_CONVERGED))
         return st
 
-    def refresh_p(self, P, rec, theta, xhat, s: int, rank_tol: float = 1e-8) -> bl_stats:
+    def refresh_p(self, P, rec, theta, xhat, s: int, rank_tol: float = 1e-8, select: str = "rgen-l-r") -> bl_stats:
         st = bl_stats()
-        o = bl_recycle_opts(s, rank_tol)
+        o = bl_recycle_opts(s, rank_tol, SELECTIONS[select])
         _check(self.ctx, lib.bl_recycle_update(self.ctx, C.byref(P), _theta(theta), _ptr(xhat),
                                                C.byref(rec.rs), C.byref(o), self.ws_ptr, self.ws_bytes,
                                                C.byref(st)), "bl_recycle_update", ok=(BL_OK, BL_E_RANK))
@@ -323,8 +328,8 @@ class Session(Context):
     def lower_solve(self, theta, y, x, gtol=1e-8, max_iter=20000, m=10) -> bl_stats:
         return self.lower_solve_p(self.P, theta, y, x, gtol, max_iter, m)
 
-    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8) -> bl_stats:
-        return self.refresh_p(self.P, self.rec, theta, xhat, s, rank_tol)
+    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8, select: str = "rgen-l-r") -> bl_stats:
+        return self.refresh_p(self.P, self.rec, theta, xhat, s, rank_tol, select)
 
     def solve(self, theta, xhat, g, w, **kw) -> bl_stats:
         return self.solve_p(self.P, self.rec, theta, xhat, g, w, **kw)

@@ -555,6 +555,8 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     if (!rs->U || !rs->C || !rs->Z || !rs->mu || (rs->v_cap > 0 && !rs->V))
         return c->err = "null recycle arrays", BL_E_ARG;
     if (!(o->rank_tol > 0.0 && o->rank_tol < 1.0)) return c->err = "rank_tol outside (0, 1)", BL_E_ARG;
+    if (o->select < BL_SEL_RGEN_L_R || o->select > BL_SEL_HRITZ_M) return c->err = "unknown selection", BL_E_ARG;
+    const bool rgen = o->select <= BL_SEL_RGEN_L_M;
     WS ws;
     TRY(check_ws(c, layout(P, rs->s_max, rs->v_cap), wsp, ws_bytes, ws));
     const int n = P->h * P->w, p = nparams(P);
@@ -613,15 +615,26 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     // t columns give any tile height enough blocks: the tallest (measured fastest for this product)
     HIPCHK(launch_hvp(S, false, xhat, W0, W1, t, 4 * QTY, c->stream));
     HIPCHK(launch_gram(n, t, t, W0, W1, ws.part(), M, c->stream));
-    HIPCHK(launch_jac(S, xhat, W0, t, ws.d1(), ws.d2(), ws.part(), Gj, 1, c->stream));
+    if (rgen) HIPCHK(launch_jac(S, xhat, W0, t, ws.d1(), ws.d2(), ws.part(), Gj, 1, c->stream));
     mark(c, 2);
-    HIPCHK(launch_gsvd_select(t, p, o->s, M, Gj, gsc, Xs, VHs, mu_tmp, info, c->stream));
+    if (rgen) {
+        HIPCHK(launch_gsvd_select(t, p, o->s, M, Gj, gsc, Xs, VHs, mu_tmp, info, c->stream));
+        if (o->select != BL_SEL_RGEN_L_R)
+            HIPCHK(launch_rgen_side(t, o->select == BL_SEL_RGEN_L_L ? 1 : 2, M, Xs, info, c->stream));
+    } else {
+        // Ritz values of W^T H W, or harmonic Ritz values from (H W)^T (H W) = Y^T Y
+        const int kind = o->select >= BL_SEL_HRITZ_S ? 1 : 0;
+        const int size = (o->select - (kind ? BL_SEL_HRITZ_S : BL_SEL_RITZ_S));
+        if (kind) HIPCHK(launch_gram(n, t, t, W1, W1, ws.part(), Gram, c->stream));
+        HIPCHK(launch_ritz_select(t, o->s, kind, size, M, Gram, gsc, Xs, VHs, mu_tmp, info, c->stream));
+    }
     HIPCHK(hipMemcpyAsync(c->h_info, info, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     const int s_eff = c->h_info[0], rankG = c->h_info[1], gst = c->h_info[2];
     if (gst != BL_OK) {
         rs->s_cur = 0;
-        c->err = "projected Hessian W^T H W is not positive definite";
+        c->err = rgen ? "projected Hessian W^T H W is not positive definite"
+                      : "(H W)^T (H W) is not positive definite";
         return (bl_status)gst;
     }
     // U~ = W X~, C~ = Y X~, Z = W V_H~

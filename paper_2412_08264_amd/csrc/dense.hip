@@ -894,6 +894,140 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
     }
 }
 
+// Ritz (eq. ritz-matrix-decomp) or harmonic Ritz (eq. harmonic-ritz) selection of
+// s_eff = min(s, t) vectors from the projected matrices (t x t, column-major; W orthonormal):
+//   kind 0: eigenpairs of sym(M), chosen by the Ritz values;
+//   kind 1: sym(M) rho = nu (Y^T Y) rho with Y^T Y = L L^T: eigenpairs (nu, z) of
+//           K = L^{-1} sym(M) L^{-T}, rho = L^{-T} z, chosen by theta = 1 / nu.
+// size 0 (S): the s_eff smallest values, ascending; 1 (L): the largest, descending; 2 (M):
+// ceil(s_eff / 2) smallest, then floor(s_eff / 2) largest.  Output: Xs (t x s_eff, unit
+// columns), VHs = 0 and mu = 0 (no error estimate), info = {s_eff, 0, status}.
+__global__ void __launch_bounds__(SD_NT) k_ritz_select(int t, int s, int kind, int size, const double* __restrict__ Min,
+                                                       const double* __restrict__ YtY, double* sc, double* Xs,
+                                                       double* VHs, double* mu, int* info, int ldsd) {
+    __shared__ int order[EIG_MAX];
+    __shared__ int pick[EIG_MAX];
+    __shared__ double val[EIG_MAX];
+    const int s_eff = s < t ? s : t;
+    const size_t T2 = (size_t)t * t;
+    double* A = sc;           // sym(M), then K
+    double* L = A + T2;       // Cholesky factor of Y^T Y
+    double* Bm = L + T2;      // L^{-1} sym(M)
+    double* Z = Bm + T2;      // eigenvectors, vector k at Z[k * t]
+    double* lam = Z + T2;     // t eigenvalues, ascending
+    double* esc = lam + t;    // eigensolver scratch (4 t^2 + t)
+    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+        const int j = idx / t, i = idx - j * t;
+        A[idx] = 0.5 * (Min[(size_t)j * t + i] + Min[(size_t)i * t + j]);
+        if (kind == 1) L[idx] = 0.5 * (YtY[(size_t)j * t + i] + YtY[(size_t)i * t + j]);
+    }
+    __syncthreads();
+    if (kind == 1) {
+        if (!chol_inplace(t, L)) {
+            if (threadIdx.x == 0) {
+                info[0] = 0;
+                info[1] = 0;
+                info[2] = BL_E_BREAKDOWN;
+            }
+            return;
+        }
+        // Bm = L^{-1} A, one column per thread
+        for (int c = threadIdx.x; c < t; c += blockDim.x)
+            for (int i = 0; i < t; ++i) {
+                double acc = A[(size_t)c * t + i];
+                for (int k = 0; k < i; ++k) acc -= L[(size_t)k * t + i] * Bm[(size_t)c * t + k];
+                Bm[(size_t)c * t + i] = acc / L[(size_t)i * t + i];
+            }
+        __syncthreads();
+        // K = L^{-1} Bm^T (A symmetric), into Z, then symmetrised into A
+        for (int c = threadIdx.x; c < t; c += blockDim.x)
+            for (int i = 0; i < t; ++i) {
+                double acc = Bm[(size_t)i * t + c];
+                for (int k = 0; k < i; ++k) acc -= L[(size_t)k * t + i] * Z[(size_t)c * t + k];
+                Z[(size_t)c * t + i] = acc / L[(size_t)i * t + i];
+            }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+            const int j = idx / t, i = idx - j * t;
+            A[idx] = 0.5 * (Z[(size_t)j * t + i] + Z[(size_t)i * t + j]);
+        }
+        __syncthreads();
+    }
+    eig_range(t, A, 0, t, lam, Z, esc, ldsd);
+    if (threadIdx.x == 0) {
+        // values and their ascending order (insertion sort; t <= EIG_MAX)
+        for (int k = 0; k < t; ++k) {
+            val[k] = kind == 0 ? lam[k] : 1.0 / lam[k];
+            order[k] = k;
+        }
+        for (int k = 1; k < t; ++k) {
+            const int o = order[k];
+            int q = k - 1;
+            while (q >= 0 && val[order[q]] > val[o]) {
+                order[q + 1] = order[q];
+                --q;
+            }
+            order[q + 1] = o;
+        }
+        const int lo = size == 0 ? s_eff : (size == 1 ? 0 : (s_eff + 1) / 2);
+        for (int j = 0; j < lo; ++j) pick[j] = order[j];
+        for (int j = lo; j < s_eff; ++j) pick[j] = order[t - 1 - (j - lo)];
+    }
+    __syncthreads();
+    // vectors: z (Ritz) or rho = L^{-T} z (harmonic Ritz), unit columns; one column per thread
+    for (int j = threadIdx.x; j < s_eff; j += blockDim.x) {
+        const double* z = Z + (size_t)pick[j] * t;
+        double* x = Xs + (size_t)j * t;
+        if (kind == 0) {
+            for (int i = 0; i < t; ++i) x[i] = z[i];
+        } else {
+            for (int i = t - 1; i >= 0; --i) {
+                double acc = z[i];
+                for (int k = i + 1; k < t; ++k) acc -= L[(size_t)i * t + k] * x[k];
+                x[i] = acc / L[(size_t)i * t + i];
+            }
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < t; ++i) nrm += x[i] * x[i];
+        const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+        for (int i = 0; i < t; ++i) {
+            x[i] *= inv;
+            VHs[(size_t)j * t + i] = 0.0;
+        }
+        mu[j] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        info[0] = s_eff;
+        info[1] = 0;
+        info[2] = BL_OK;
+    }
+}
+
+// Side of the RGen-L vectors: Xs holds the unit right vectors x of the info[0] selected
+// columns; the left vector is v = sym(M) x / ||sym(M) x|| (the GSVD's M x = beta v with
+// beta > 0).  side 1 (L): x <- v; side 2 (M): x <- x + v.
+__global__ void __launch_bounds__(SD_NT) k_rgen_side(int t, int side, const double* __restrict__ Min, double* Xs,
+                                                     const int* __restrict__ info) {
+    __shared__ double xv[EIG_MAX], vv[EIG_MAX], red[SD_NT / 64];
+    const int s_eff = info[0];
+    for (int j = 0; j < s_eff; ++j) {
+        double* x = Xs + (size_t)j * t;
+        for (int i = threadIdx.x; i < t; i += blockDim.x) xv[i] = x[i];
+        __syncthreads();
+        double part = 0.0;
+        for (int i = threadIdx.x; i < t; i += blockDim.x) {
+            double acc = 0.0;
+            for (int k = 0; k < t; ++k) acc += 0.5 * (Min[(size_t)k * t + i] + Min[(size_t)i * t + k]) * xv[k];
+            vv[i] = acc;
+            part += acc * acc;
+        }
+        const double nrm = sqrt(sd_sum(part, red));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int i = threadIdx.x; i < t; i += blockDim.x) x[i] = side == 1 ? vv[i] * inv : xv[i] + vv[i] * inv;
+        __syncthreads();
+    }
+}
+
 size_t gsvd_scratch_doubles(int t, int p) {
     const size_t T2 = (size_t)t * t, P2 = (size_t)p * p, PT = (size_t)p * t, KM = T2 > P2 ? T2 : P2;
     const size_t m = t > p ? t : p;
@@ -935,6 +1069,22 @@ hipError_t launch_gsvd_select(int t, int p, int s, const double* M, const double
         (void)hipFuncSetAttribute((const void*)k_gsvd_select, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), bytes, stream, t, p, s, M, G, sc, Xs, VHs, mu, info,
                        (int)(bytes / sizeof(double)));
+    return hipGetLastError();
+}
+
+hipError_t launch_ritz_select(int t, int s, int kind, int size, const double* M, const double* YtY, double* sc,
+                              double* Xs, double* VHs, double* mu, int* info, hipStream_t stream) {
+    const size_t want = (size_t)6 * t * t * sizeof(double);
+    const size_t bytes = std::min(want, lds_limit()) / sizeof(double) * sizeof(double);
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)k_ritz_select, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k_ritz_select, dim3(1), dim3(SD_NT), bytes, stream, t, s, kind, size, M, YtY, sc, Xs, VHs, mu,
+                       info, (int)(bytes / sizeof(double)));
+    return hipGetLastError();
+}
+
+hipError_t launch_rgen_side(int t, int side, const double* M, double* Xs, const int* info, hipStream_t stream) {
+    hipLaunchKernelGGL(k_rgen_side, dim3(1), dim3(SD_NT), 0, stream, t, side, M, Xs, info);
     return hipGetLastError();
 }
 

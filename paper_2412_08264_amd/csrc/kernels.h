@@ -129,5 +129,11 @@ hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int*
 size_t gsvd_scratch_doubles(int t, int p);
 hipError_t launch_gsvd_select(int t, int p, int s, const double* M, const double* G, double* sc, double* Xs,
                               double* VHs, double* mu, int* info, hipStream_t stream);
+// Ritz (kind 0) or harmonic Ritz (kind 1) selection, size 0 / 1 / 2 = S / L / M; scratch as
+// gsvd_scratch_doubles.
+hipError_t launch_ritz_select(int t, int s, int kind, int size, const double* M, const double* YtY, double* sc,
+                              double* Xs, double* VHs, double* mu, int* info, hipStream_t stream);
+// Left (side 1) or mixed (side 2) RGen vectors from the right ones in Xs.
+hipError_t launch_rgen_side(int t, int side, const double* M, double* Xs, const int* info, hipStream_t stream);
 
 }  // namespace bl
