@@ -7,8 +7,9 @@ frozen sequence of 30 outer (upper-level) iterations.  Inputs are synthetic (see
 relative residual 1e-13).  One step = one pass of the hot path over the whole sequence: for
 every system the Ritz-GSV refresh (RGen-L(R)), the recycled CG solve with the
 hypergradient-error stop, and the hypergradient.  A solve counts towards ``value`` only if its
-hypergradient is within 1e-6 (relative) of the reference.  Plain warm-started CG and recycling
-with the residual stop are timed on the same sequence and reported beside the headline.
+hypergradient is within 1e-6 (relative) of the reference.  Plain warm-started CG, recycling
+with the residual stop, RMINRES with the error-estimate stop and MINRES (the paper's solver)
+are timed on the same sequence and reported beside the headline.
 
 Other workloads (``--workload``):
   tv32     the same protocol on the 32x32 TV recipe;
@@ -16,7 +17,9 @@ Other workloads (``--workload``):
   batch64  64 filter images of sides {128..512}, shared theta, one engine advancing all 64 solves
            per launch; one step = one outer iteration of the whole training set;
   serve    Poisson request stream over resident samples (TV and filters, sides 64..1024,
-           s in {10, 30, 50}) served by continuous batching; p50/p99 latency, mixed and FP64.
+           s in {10, 30, 50}) served by continuous batching; p50/p99 latency, mixed and FP64;
+  selections  the tv256 sequence refreshed by every selection rule of Table 2 (Ritz, harmonic
+           Ritz, sides of RGen-L), recycled CG with the residual stop.
 """
 from __future__ import annotations
 
@@ -270,6 +273,76 @@ def cpu_baseline_sequence(wl, seconds_budget=25.0):
             "sample": f"{done} consecutive {wl.h}x{wl.w} {wl.reg} systems (refresh + recycled CG 1e-10 + "
                       f"hypergradient) at stand-in points x*+0.05e', numpy FP64, {el:.1f} s; host "
                       f"{len(os.sched_getaffinity(0))} affinity cores"}
+
+
+def bench_selections(args, B, torch, synth):
+    """tv256 with every recycle-space selection of Table 2: recycled CG with the residual stop,
+    each rule at the loosest threshold of SWEEP_RESID that keeps every hypergradient within 1e-6;
+    reports solves/s, iterations per pass and the mean refresh time of each rule."""
+    wl = synth.WORKLOADS["tv256"]
+    outer = args.outer or wl.outer
+    dev = torch.device("cuda:0")
+    inst = synth.instance(wl)
+    P64 = B.problem_from(wl, prec="fp64")
+    S = B.Session(P64, s_max=wl.s, v_cap=V_CAP, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs, e = t(inst["xstar"]), t(inst["e"])
+    y = torch.empty_like(xs)
+    S.forward(xs, e, wl.noise, y)
+    thetas, xhats = make_trajectory(S, P64, B, wl, torch, y, xs, inst["theta0"], outer)
+    refs = []
+    w = torch.zeros_like(xs)
+    for th, x in zip(thetas, xhats):
+        w.zero_()
+        S.solve(th, x, x - xs, w, tol=1e-13, store_basis=False, recycle=False, max_iter=100000,
+                allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+        refs.append(S.hypergradient(th, x, w))
+    tiles = autotune_tiles(S, B, [(S.P, thetas[0], xhats[0], wl.s)])
+
+    def one_pass(rule, thr, refresh_ms=None):
+        S.reset()
+        w = torch.zeros_like(xs)
+        recs = []
+        for i, (th, x) in enumerate(zip(thetas, xhats)):
+            if i > 0:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.refresh(th, x, s=wl.s, select=rule)
+                torch.cuda.synchronize()
+                if refresh_ms is not None:
+                    refresh_ms.append((time.perf_counter() - t0) * 1e3)
+            st = S.solve(th, x, x - xs, w, tol=thr, store_basis=True)
+            hg = S.hypergradient(th, x, w)
+            recs.append({"iters": st.iters, "err": rel_err(hg, refs[i]), "status": st.status})
+        return recs
+
+    out_rules = {}
+    for rule in B.SELECTIONS:
+        thr = SWEEP_RESID[-1]
+        for cand in SWEEP_RESID:
+            rr = one_pass(rule, cand)
+            if all(r["err"] <= 1e-6 and r["status"] == 0 for r in rr):
+                thr = cand
+                break
+        one_pass(rule, thr)
+        ref_ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = [one_pass(rule, thr, ref_ms) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
+        total = sum(len(rr) for rr in recs)
+        out_rules[rule] = {"solves_per_s": ok / el, "threshold": thr, "iters_per_sequence": sum(r["iters"] for r in recs[0]),
+                           "refresh_ms": float(np.mean(ref_ms)), "passing": f"{ok}/{total}",
+                           "max_rel_err": max(r["err"] for r in recs[0])}
+        log(f"[bench] {rule}: {out_rules[rule]}")
+    head = out_rules["rgen-l-r"]
+    desc = (f"selections: tv256 ({wl.h}x{wl.w} smoothed-TV, s={wl.s}, {outer} frozen outer steps), recycled CG "
+            f"with the residual stop after a refresh by each rule of Table 2")
+    return base_line(args, head["solves_per_s"], 0.0, "f64", {"workload": desc, "outer_steps": outer, "s": wl.s,
+                                                              "tiles": tiles},
+                     selections=out_rules)
 
 
 def bench_sequence(args, B, torch, synth):
@@ -891,7 +964,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve"))
+    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve", "selections"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", dest="no_micro", action="store_true",
                     help="skip the 4096 x 4096 HBM microbenchmark of the default workload")
@@ -941,6 +1014,8 @@ def main():
         out = bench_batch(args, B, torch, synth)
     elif args.workload == "serve":
         out = bench_serve(args, B, torch, synth)
+    elif args.workload == "selections":
+        out = bench_selections(args, B, torch, synth)
     else:
         out = bench_sequence(args, B, torch, synth)
     print(json.dumps(out), flush=True)
