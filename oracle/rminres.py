@@ -34,8 +34,11 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 4, 6
 
 
 def rminres(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1e-10, stop: str = "resid",
-            hg_tol: float = 0.0, max_iter: int = 10000, check_every: int = 1, record: bool = False):
-    """Solve H w = g by RMINRES.  ``hvp(v)`` applies H.  Returns a dict (keys at the end)."""
+            hg_tol: float = 0.0, max_iter: int = 10000, check_every: int = 1, record: bool = False,
+            v_cap: int = 64):
+    """Solve H w = g by RMINRES.  ``hvp(v)`` applies H.  Returns a dict (keys at the end); "V"
+    holds the Lanczos vectors v_1 .. v_m of the steps taken (m <= v_cap), a basis of the Krylov
+    space K_m((I - C C^T) H, r0) for the next refresh."""
     g = np.asarray(g, dtype=np.float64).ravel()
     n = g.size
     w = np.zeros(n) if w0 is None else np.array(w0, dtype=np.float64).ravel().copy()
@@ -75,9 +78,12 @@ def rminres(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1e-10
 
     status = OK
     iters = 0
+    Vs = []
     done = met(r, abs(zeta), 0)
     while not done and iters < max_iter:
         k = iters + 1
+        if len(Vs) < v_cap:
+            Vs.append(v)
         # new Lanczos vector, orthogonal to C
         Hv = hvp(v)
         e = C.T @ Hv if s else np.zeros(0)
@@ -118,4 +124,5 @@ def rminres(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1e-10
     if not done and status == OK:
         status = NOT_CONVERGED
     return {"w": w, "iters": iters, "status": status, "res_norm": abs(zeta), "g_norm": gnorm, "r": r,
-            "hist_res": hist_res, "hist_nsc": hist_nsc}
+            "hist_res": hist_res, "hist_nsc": hist_nsc,
+            "V": np.stack(Vs, axis=1) if Vs else np.zeros((n, 0))}
