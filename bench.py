@@ -19,7 +19,9 @@ Other workloads (``--workload``):
   serve    Poisson request stream over resident samples (TV and filters, sides 64..1024,
            s in {10, 30, 50}) served by continuous batching; p50/p99 latency, mixed and FP64;
   selections  the tv256 sequence refreshed by every selection rule of Table 2 (Ritz, harmonic
-           Ritz, sides of RGen-L), recycled CG with the residual stop.
+           Ritz, sides of RGen-L), recycled CG with the residual stop;
+  train    tv256 trained end to end (not a frozen sequence) with recycled CG, RMINRES and plain
+           CG hypergradients; wall time per outer iteration and its split.
 """
 from __future__ import annotations
 
@@ -343,6 +345,42 @@ def bench_selections(args, B, torch, synth):
     return base_line(args, head["solves_per_s"], 0.0, "f64", {"workload": desc, "outer_steps": outer, "s": wl.s,
                                                               "tiles": tiles},
                      selections=out_rules)
+
+
+def bench_train(args, B, torch, synth):
+    """tv256 trained end to end (Algorithm 2 with Algorithm 1's backtracking, `outer` steps from
+    theta0): hypergradients by recycled CG with RGen-L(R) and the error-estimate stop, by RMINRES
+    likewise, and by plain CG; reports the wall time split into lower-level solves, refreshes,
+    Hessian solves and hypergradients, and the final upper loss."""
+    from paper_2412_08264_amd import train as T
+    wl = synth.WORKLOADS["tv256"]
+    outer = args.outer or 10
+    dev = torch.device("cuda:0")
+    inst = synth.instance(wl)
+    P64 = B.problem_from(wl, prec="fp64")
+    S = B.Session(P64, s_max=wl.s, v_cap=V_CAP, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs, e = t(inst["xstar"]), t(inst["e"])
+    y = torch.empty_like(xs)
+    S.forward(xs, e, wl.noise, y)
+    autotune_tiles(S, B, [(S.P, inst["theta0"], y, wl.s)])
+    runs = {}
+    for name, kw in (("recycled_cg", dict(s=wl.s, solver="cg", stop="hgerr")),
+                     ("rminres", dict(s=wl.s, solver="rminres", stop="hgerr")),
+                     ("plain_cg", dict(s=0, solver="cg", stop="resid"))):
+        t0 = time.perf_counter()
+        hist = T.train(S, y, xs, inst["theta0"], outer, tol=1e-8, hg_rel=1e-8, check_every=args.check_every,
+                       lbfgs_iters=LBFGS_CAP, **kw)
+        el = time.perf_counter() - t0
+        runs[name] = {"seconds": el, "outer_per_s": outer / el, "final_loss": hist["loss"][-1],
+                      "hessian_iters": sum(hist["iters"]), "lbfgs_iters": sum(hist["lbfgs_iters"]),
+                      "split_s": {k: round(v, 3) for k, v in hist["seconds"].items()}}
+        log(f"[bench] train {name}: {runs[name]}")
+    desc = (f"train: tv256 ({wl.h}x{wl.w} smoothed-TV) trained end to end for {outer} outer steps from theta0, "
+            f"s={wl.s}, error-estimate stop 1e-8 x previous |grad| (first system and plain CG: residual 1e-8)")
+    head = runs["recycled_cg"]
+    return base_line(args, head["outer_per_s"], head["seconds"], "f64", {"workload": desc, "outer_steps": outer},
+                     unit_note="outer iterations per second", train=runs)
 
 
 def bench_sequence(args, B, torch, synth):
@@ -964,7 +1002,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve", "selections"))
+    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve", "selections", "train"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", dest="no_micro", action="store_true",
                     help="skip the 4096 x 4096 HBM microbenchmark of the default workload")
@@ -1016,6 +1054,8 @@ def main():
         out = bench_serve(args, B, torch, synth)
     elif args.workload == "selections":
         out = bench_selections(args, B, torch, synth)
+    elif args.workload == "train":
+        out = bench_train(args, B, torch, synth)
     else:
         out = bench_sequence(args, B, torch, synth)
     print(json.dumps(out), flush=True)
