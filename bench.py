@@ -966,8 +966,9 @@ def kernels_only_batch(args, B, torch, synth):
 
 def kernels_only(args, B, torch, synth):
     """Short run for hardware counters: 200 plain and 200 recycled CG iterations on the
-    workload's shape at a stand-in point, and one 64 MiB device-to-device copy (counter
-    calibration: its FETCH_SIZE / WRITE_SIZE should read 64 MiB each)."""
+    workload's shape at a stand-in point, then 200 RMINRES steps with the same recycle space and
+    200 without (FP64 problems), and one 64 MiB device-to-device copy (counter calibration: its
+    FETCH_SIZE / WRITE_SIZE should read 64 MiB each)."""
     if args.workload == "batch64":
         kernels_only_batch(args, B, torch, synth)
         return
@@ -988,6 +989,11 @@ def kernels_only(args, B, torch, synth):
     S.refresh(th, xh, s=wl.s)
     w.zero_()
     S.solve(th, xh, xh - xs, w, tol=0.0, max_iter=200, store_basis=False, allow=(B.BL_E_NOT_CONVERGED,))
+    if wl.prec == "fp64":
+        for rec in (True, False):
+            w.zero_()
+            S.solve(th, xh, xh - xs, w, tol=0.0, max_iter=200, store_basis=False, recycle=rec, method="rminres",
+                    allow=(B.BL_E_NOT_CONVERGED,))
     a = torch.empty(8 * 1024 * 1024, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
     b.copy_(a)

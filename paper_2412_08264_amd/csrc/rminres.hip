@@ -157,9 +157,16 @@ __global__ void __launch_bounds__(NT) k_m_init(MinresArgs a, MinresInit in, int 
 // ------------------------------------------------------------------ apply, step k
 // `nvb` values per record of the previous launch (1, or 1 + nz when iterate k - 2 is tested;
 // 1 + nz at k = 1); `fold`: those records were folded.
+// Loads that do not depend on this step's scalars are issued before the record reduction: the
+// columns of C at the thread's pixel (the first MCP), x_hat, and for TV the staged region of u_k
+// (the stencil input v_k = u_k / beta_k is formed from registers once beta_k is known).
+constexpr int MCP = 24;
 template <int R, int CLS>
 __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, int nvb, int fold) {
     using L = QLayout<double, R, CLS, 1>;
+    using G = QGeo<R, CLS, 1>;
+    constexpr bool EARLY = CLS == TC_TV;
+    constexpr int NST = EARLY ? (G::N_V + NT - 1) / NT : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
     __shared__ double tot[NT];
@@ -170,8 +177,24 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
     tile_origin(S, r0, c0);
     const Own<1> o = own_pixels<1>(S.h, S.w, r0, c0);
     const double* __restrict__ uk = a.u[k % 3];
-    // x_hat does not depend on this step's scalars: staged before the reduction
-    if constexpr (CLS == TC_TV) q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+    const int n = S.n, s = a.s;
+    double cpre[MCP], hu[NST];
+#pragma unroll
+    for (int c = 0; c < MCP; ++c) cpre[c] = (o.in[0] && c < s) ? a.C[(size_t)c * n + o.g[0]] : 0.0;
+    const double uown = o.in[0] ? uk[o.g[0]] : 0.0;
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            hu[u] = 0.0;
+            if (idx < G::N_V) {
+                const int rr = idx / G::RW, cc = idx - rr * G::RW;
+                const int gi = r0 - G::E + rr, gj = c0 - G::E + cc;
+                if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) hu[u] = uk[gi * S.w + gj];
+            }
+        }
+        q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+    }
     reduce_partials(fold ? a.fold : a.rec_upd, fold ? FOLD_BLOCKS : a.npix, nvb, tot);
     if (sdone) return;
     const double bk = sqrt(tot[0]);
@@ -227,20 +250,37 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
         }
     }
     // v_k = u_k / beta_k and q = H v_k
-    auto vfetch = [&](int gi) { return bk > 0.0 ? uk[gi] / bk : 0.0; };
-    q_stage<double, R, CLS, 1>(lds + L::o_v, S.h, S.w, r0, c0, vfetch);
+    auto vof = [&](double uv) { return bk > 0.0 ? uv / bk : 0.0; };
+    if constexpr (EARLY) {
+        double* v = lds + L::o_v;
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            if (idx < G::N_V) v[idx] = vof(hu[u]);
+        }
+    } else {
+        q_stage<double, R, CLS, 1>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return vof(uk[gi]); });
+        q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+    }
     __syncthreads();
     double hv[1];
     q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv);
-    const double vi = o.in[0] ? vfetch(o.g[0]) : 0.0;
+    const double vi = o.in[0] ? vof(uown) : 0.0;
     const double qi = o.in[0] ? hv[0] : 0.0;
     if (o.in[0]) {
         a.q[o.g[0]] = qi;
-        if (st->store && k - 1 < st->v_cap) a.V[(size_t)(k - 1) * S.n + o.g[0]] = vi;
+        if (st->store && k - 1 < st->v_cap) a.V[(size_t)(k - 1) * n + o.g[0]] = vi;
     }
-    block_partials(a.rec_app, 1 + a.s, [&](int kk) -> double {
+    block_partials(a.rec_app, 1 + s, [&](int kk) -> double {
         if (!o.in[0]) return 0.0;
-        return kk == 0 ? vi * qi : a.C[(size_t)(kk - 1) * S.n + o.g[0]] * qi;
+        if (kk == 0) return vi * qi;
+        const int c = kk - 1;
+        double cv = 0.0;
+#pragma unroll
+        for (int u = 0; u < MCP; ++u)
+            if (u == c) cv = cpre[u];
+        if (c >= MCP) cv = a.C[(size_t)c * n + o.g[0]];
+        return cv * qi;
     });
 }
 
@@ -270,11 +310,30 @@ __global__ void __launch_bounds__(NT) k_m_update(MinresArgs a, int k, int zr, in
     double cpre[MPRE];
 #pragma unroll
     for (int c = 0; c < MPRE; ++c) cpre[c] = (in && c < s) ? a.C[(size_t)c * n + i] : 0.0;
+    // scalars of earlier launches (this step's beta and the rotation of column k - 1 come from
+    // the apply launch): read before the reduction
+    const int km = k - 1;
+    const double bk = st->beta[k & 3], bk1 = st->beta[km & 3];
+    double ck = 0.0, sk = 0.0, zk = 0.0, gam = 0.0, del = 0.0, ept = 1.0, zkm = 0.0;
+    if (k >= 2) {
+        ck = st->c[km & 3];
+        sk = st->sn[km & 3];
+        zk = st->zeta[km & 3];
+        gam = st->gam[km & 3];
+        del = st->del[km & 3];
+        ept = st->epst[km & 3];
+        zkm = st->zeta[(km - 1) & 3];
+    }
+    const bool lead0 = blockIdx.x == 0;
+    // block 0 carries the recycle-space coordinates: e_{k-1} and mh of the two steps before
+    const bool mine = lead0 && k >= 2 && (int)threadIdx.x < s;
+    const double e_km = mine ? st->e[km & 3][threadIdx.x] : 0.0;
+    const double mh1 = mine ? st->mh[(km - 1) & 3][threadIdx.x] : 0.0;
+    const double mh2 = mine ? st->mh[(km - 2) & 3][threadIdx.x] : 0.0;
     reduce_partials(fold ? a.fold : a.rec_app, fold ? FOLD_BLOCKS : a.ntiles, 1 + s, tot);
     if (sdone) return;
     const double alpha = tot[0];
     const double* e = tot + 1;
-    const double bk = st->beta[k & 3], bk1 = st->beta[(k - 1) & 3];
     const double vk = bk > 0.0 ? uk / bk : 0.0;
     const double vk1 = bk1 > 0.0 ? uk1 / bk1 : 0.0;
     double ce = 0.0;
@@ -284,14 +343,10 @@ __global__ void __launch_bounds__(NT) k_m_update(MinresArgs a, int k, int zr, in
     for (int c = MPRE; c < s; ++c) ce += (in ? a.C[(size_t)c * n + i] : 0.0) * e[c];
     const double un = (qi - ce) - alpha * vk - bk * vk1;
     if (in) a.u[(k + 1) % 3][i] = un;
-    const bool lead0 = blockIdx.x == 0;
     double rn = ri;
     if (k >= 2) {
         // solution update of step k - 1 with its rotation
-        const int km = k - 1;
-        const double ck = st->c[km & 3], sk = st->sn[km & 3], zk = st->zeta[km & 3];
-        const double gam = st->gam[km & 3], del = st->del[km & 3], ept = st->epst[km & 3];
-        const double tau = ck * st->zeta[(km - 1) & 3];
+        const double tau = ck * zkm;
         const double mn = (vk1 - gam * mB - del * mA) / ept;
         rn = sk * sk * ri + ck * zk * vk;
         if (in) {
@@ -299,12 +354,10 @@ __global__ void __launch_bounds__(NT) k_m_update(MinresArgs a, int k, int zr, in
             a.w[i] = wi + tau * mn;
             a.r[i] = rn;
         }
-        if (lead0) {
-            for (int t = threadIdx.x; t < s; t += NT) {
-                const double mh = (st->e[km & 3][t] - gam * st->mh[(km - 2) & 3][t] - del * st->mh[(km - 1) & 3][t]) / ept;
-                st->mh[km & 3][t] = mh;
-                st->zacc[t] += tau * mh;
-            }
+        if (mine) {
+            const double mh = (e_km - gam * mh2 - del * mh1) / ept;
+            st->mh[km & 3][threadIdx.x] = mh;
+            st->zacc[threadIdx.x] += tau * mh;
         }
     }
     if (lead0) {
