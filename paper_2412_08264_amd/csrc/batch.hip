@@ -66,9 +66,13 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     for (int k = 0; k < UPRE; ++k) zpre[k] = (in && k < zw) ? sl.Z[(size_t)k * n + i] : 0.0;
     int nb;
     const double* rec = slot_rec(sl, 1, nb);
+    // scalars of earlier launches, read before the reduction: rho_j (the apply of this
+    // iteration) and, in block 0, the recycle coefficient accumulated so far
+    const double rho = uni(st->rho2[j & 1]);
+    const bool acc_mine = m.y == 0 && (int)threadIdx.x < s;
+    const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
     reduce_partials(rec, nb, 1 + s, tot);
     if (sdone) return;
-    const double rho = st->rho2[j & 1];
     const double sigma = tot[0];
     if (!(sigma > 0.0)) {
         if (m.y == 0 && threadIdx.x == 0) {
@@ -80,10 +84,8 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     }
     const double alpha = rho / sigma;
     const double* e = tot + 1;
-    if (m.y == 0) {
-        for (int k = threadIdx.x; k < s; k += NT) st->zacc[k] -= alpha * e[k];
-        if (threadIdx.x == 0) st->alpha = alpha;
-    }
+    if (acc_mine) st->zacc[threadIdx.x] = zacc0 - alpha * e[threadIdx.x];
+    if (m.y == 0 && threadIdx.x == 0) st->alpha = alpha;
     double ce = 0.0;
 #pragma unroll
     for (int k = 0; k < UPRE; ++k)

@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
 // hides them (measured: 7-13% per iteration over loading them after the stencil).
 template <int CLS, int Q, bool REC>
 __host__ __device__ constexpr int c_prefetch() {
-    return !REC ? 1 : (CLS != TC_TV ? (Q == 1 ? 20 : (Q == 2 ? 10 : 5)) : (Q == 1 ? 24 : (Q == 2 ? 12 : 8)));
+    return !REC ? 1 : (CLS != TC_TV ? (Q == 1 ? 20 : (Q == 2 ? 10 : 5)) : (Q == 1 ? 24 : (Q == 2 ? 10 : 8)));
 }
 
 template <typename T, int R, int CLS, int Q, bool REC>
@@ -186,13 +186,17 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     int nb;
     const double* rec = slot_rec(sl, 2, nb);
     const int zw = REC ? zr_width(st, nz, j) : 0;
+    // scalars written by earlier launches, read before the reduction so that nothing after it
+    // waits on them
+    const TestSettings ts = test_settings(st);
+    const double rho_prev = j > 0 ? uni(st->rho2[(j - 1) & 1]) : 1.0;
+    const bool store_basis = uni(st->store_basis) && j >= 0 && j < uni(st->v_cap);
+    const int rr_j = uni(st->rr_j);
     reduce_partials(rec, nb, 1 + zw, tot);
     if (sdone) return;
-    const double rho_prev = j > 0 ? st->rho2[(j - 1) & 1] : 1.0;
-    const bool store_basis = st->store_basis && j >= 0 && j < st->v_cap;
     const double rho = tot[0];
-    const bool restart = j > 0 && st->rr_j == j && rho > rho_prev;
-    const Decision dec = decide(st, j, rho, tot + 1, zw > 0);
+    const bool restart = j > 0 && rr_j == j && rho > rho_prev;
+    const Decision dec = decide(st, ts, j, rho, tot + 1, zw > 0);
     if (m.y == 0) {
         for (int k = threadIdx.x; k < zw; k += NT) st->zr[k] = tot[1 + k];
         if (threadIdx.x == 0) {

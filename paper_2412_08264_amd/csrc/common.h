@@ -263,11 +263,33 @@ struct Decision {
     double est;
 };
 
-__device__ __forceinline__ Decision decide(const SolveState* st, int j, double rho, const double* zr, bool have_zr) {
+// A value every lane of the wave holds (loaded from one address), moved to a scalar register,
+// so that keeping it across a long stretch of code costs no vector registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The settings the test reads, loaded once: a kernel can issue these loads before its record
+// reduction, so the decision does not wait on them afterwards.
+struct TestSettings {
+    double tol, hg_tol, gnorm;
+    int check_every, stop, hgerr_on, s, max_iter;
+};
+__device__ __forceinline__ TestSettings test_settings(const SolveState* st) {
+    return TestSettings{uni(st->tol),         uni(st->hg_tol), uni(st->gnorm), uni(st->check_every),
+                        uni(st->stop),        uni(st->hgerr_on), uni(st->s),   uni(st->max_iter)};
+}
+
+__device__ __forceinline__ Decision decide(const SolveState* st, const TestSettings& ts, int j, double rho,
+                                           const double* zr, bool have_zr) {
     Decision d{false, BL_OK, NAN};
-    if (st->hgerr_on && have_zr) {
+    if (ts.hgerr_on && have_zr) {
         double acc = 0.0;
-        for (int k = 0; k < st->s; ++k) {
+        for (int k = 0; k < ts.s; ++k) {
             const double t = st->mu[k] * zr[k];
             acc += t * t;
         }
@@ -280,12 +302,12 @@ __device__ __forceinline__ Decision decide(const SolveState* st, int j, double r
     }
     bool met;
     if (rho == 0.0) met = true;
-    else if (j % st->check_every) met = false;
-    else if (st->stop == BL_STOP_HGERR && st->hgerr_on) met = d.est <= st->hg_tol;
-    else met = sqrt(rho) <= st->tol * st->gnorm;
+    else if (j % ts.check_every) met = false;
+    else if (ts.stop == BL_STOP_HGERR && ts.hgerr_on) met = d.est <= ts.hg_tol;
+    else met = sqrt(rho) <= ts.tol * ts.gnorm;
     if (met) {
         d.done = true;
-    } else if (j >= st->max_iter) {
+    } else if (j >= ts.max_iter) {
         d.done = true;
         d.status = BL_E_NOT_CONVERGED;
     }
