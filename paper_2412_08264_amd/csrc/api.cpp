@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "host.h"
@@ -695,14 +696,10 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
     double* d = ws.vec(1);
     double* xt = ws.vec(2);
     double* gt = ws.vec(3);
-    double* qv = ws.vec(4);
     double* Sh = ws.lb();
     double* Yh = Sh + (size_t)(LBFGS_MMAX + 1) * n;
-    double* dq_rec = Yh + (size_t)(LBFGS_MMAX + 1) * n;   // records of s_k . q, one per slot
-    double* dr_rec = dq_rec + (size_t)(LBFGS_MMAX + 1) * vb;
-    double* d3_rec = dr_rec + vb;                           // [s.y, s.s, y.y] records
-    double* sl_rec = d3_rec + 3 * (size_t)vb;               // g . d records
-    double* fout = sl_rec + vb;                             // host-bound scalars
+    double* md_rec = Yh + (size_t)(LBFGS_MMAX + 1) * n;   // multi-dot records: VL_MAX per block
+    double* fout = md_rec + (size_t)VL_MAX * vb;           // host-bound scalars
     auto grad_at = [&](const double* xx, double* gg, double& f, double& gn2) -> bl_status {
         HIPCHK(launch_lower_grad(S, xx, y, gg, ws.part(), c->stream));
         HIPCHK(launch_finish_sum(ws.part(), tiles_of(S), 2, fout, c->stream));
@@ -712,41 +709,85 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
         gn2 = c->h_buf[1];
         return BL_OK;
     };
+    // dots a_i . b_i of a list of pairs, VL_MAX per pass, into host memory
+    auto dots = [&](const std::vector<std::pair<const double*, const double*>>& pr, double* hout) -> bl_status {
+        const int k = (int)pr.size();
+        for (int c0 = 0; c0 < k; c0 += VL_MAX) {
+            VecPairs vp{};
+            vp.k = std::min(VL_MAX, k - c0);
+            for (int i = 0; i < vp.k; ++i) {
+                vp.a[i] = pr[c0 + i].first;
+                vp.b[i] = pr[c0 + i].second;
+            }
+            HIPCHK(launch_multidot(n, vp, md_rec, c->stream));
+            HIPCHK(launch_finish_sum(md_rec, vb, vp.k, fout + 2 + c0, c->stream));
+        }
+        HIPCHK(hipMemcpyAsync(c->h_buf, fout + 2, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::memcpy(hout, c->h_buf, k * sizeof(double));
+        return BL_OK;
+    };
     double f, gn2;
     TRY(grad_at(x, g, f, gn2));
-    std::vector<double> rho;
-    std::vector<int> slot;   // history slots in use, oldest first
+    // History of kept pairs, oldest first (device buffers of m + 1 slots, so a new pair never
+    // overwrites a kept one), with the small matrices of the compact representation
+    // (Byrd, Nocedal, Schnabel 1994): SY[i][j] = s_i . y_j and YY[i][j] = y_i . y_j.
+    constexpr int MM = LBFGS_MMAX + 1;
+    std::vector<int> slot;
     std::vector<int> free_slots;
-    for (int k = m; k >= 0; --k) free_slots.push_back(k);   // m + 1 buffers: a new pair never overwrites a kept one
+    for (int k = m; k >= 0; --k) free_slots.push_back(k);
+    std::vector<double> SY(MM * MM, 0.0), YY(MM * MM, 0.0);
+    std::vector<double> av(2 * MM), uv(MM), pv(MM), wv(MM), nd(3 * MM + 3);
     int it = 0;
     double gnorm = std::sqrt(gn2);
     double gamma = 0.0;
     while (gnorm > gtol && it < max_iter) {
         if (!std::isfinite(f) || !std::isfinite(gnorm)) return c->err = "non-finite objective", BL_E_NONFINITE;
-        // two-loop recursion with the coefficients kept on the device: q = g, d = H_k q
-        HIPCHK(hipMemcpyAsync(qv, g, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        // d = H_k g in the compact form: with a = S^T g, b = Y^T g, R the upper triangle of
+        // S^T Y and D its diagonal, u = R^{-1} a, p = R^{-T} ((D + gamma Y^T Y) u - gamma b),
+        // d = gamma g + S p - gamma Y u.  One pass for the 2h dots, one for the combination.
         const int hsz = (int)slot.size();
-        for (int k = hsz - 1; k >= 0; --k) {
-            const double* sk = Sh + (size_t)slot[k] * n;
-            const double* yk = Yh + (size_t)slot[k] * n;
-            double* rec = dq_rec + (size_t)slot[k] * vb;
-            HIPCHK(launch_dots_part(n, 1, sk, qv, rec, c->stream));
-            HIPCHK(launch_axpy_red(n, 1.0, qv, yk, rec, -rho[k], nullptr, 0.0, c->stream));
-        }
-        const double scale0 = hsz ? gamma : 1.0 / gnorm;
-        HIPCHK(launch_axpy_red(n, 0.0, d, qv, nullptr, scale0, nullptr, 0.0, c->stream));
-        for (int k = 0; k < hsz; ++k) {
-            const double* sk = Sh + (size_t)slot[k] * n;
-            const double* yk = Yh + (size_t)slot[k] * n;
-            HIPCHK(launch_dots_part(n, 1, yk, d, dr_rec, c->stream));
-            HIPCHK(launch_axpy_red(n, 1.0, d, sk, dq_rec + (size_t)slot[k] * vb, rho[k], dr_rec, -rho[k], c->stream));
+        double gd;
+        if (hsz == 0) {
+            VecComb vc{};
+            HIPCHK(launch_lincomb(n, 1.0 / gnorm, g, vc, d, c->stream));
+            gd = gnorm;
+        } else {
+            std::vector<std::pair<const double*, const double*>> pr;
+            for (int i = 0; i < hsz; ++i) pr.push_back({Sh + (size_t)slot[i] * n, g});
+            for (int i = 0; i < hsz; ++i) pr.push_back({Yh + (size_t)slot[i] * n, g});
+            TRY(dots(pr, av.data()));
+            const double* A = av.data();
+            const double* Bv = av.data() + hsz;
+            for (int i = hsz - 1; i >= 0; --i) {
+                double acc = A[i];
+                for (int j = i + 1; j < hsz; ++j) acc -= SY[i * MM + j] * uv[j];
+                uv[i] = acc / SY[i * MM + i];
+            }
+            for (int i = 0; i < hsz; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < hsz; ++j) acc += YY[i * MM + j] * uv[j];
+                wv[i] = SY[i * MM + i] * uv[i] + gamma * acc - gamma * Bv[i];
+            }
+            for (int i = 0; i < hsz; ++i) {
+                double acc = wv[i];
+                for (int j = 0; j < i; ++j) acc -= SY[j * MM + i] * pv[j];
+                pv[i] = acc / SY[i * MM + i];
+            }
+            VecComb vc{};
+            vc.k = 2 * hsz;
+            gd = gamma * gn2;
+            for (int i = 0; i < hsz; ++i) {
+                vc.c[i] = pv[i];
+                vc.v[i] = Sh + (size_t)slot[i] * n;
+                vc.c[hsz + i] = -gamma * uv[i];
+                vc.v[hsz + i] = Yh + (size_t)slot[i] * n;
+                gd += pv[i] * A[i] - gamma * uv[i] * Bv[i];
+            }
+            HIPCHK(launch_lincomb(n, gamma, g, vc, d, c->stream));
         }
         // direction -d; slope = -(g . d)
-        HIPCHK(launch_dots_part(n, 1, g, d, sl_rec, c->stream));
-        HIPCHK(launch_finish_sum(sl_rec, vb, 1, fout + 2, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_buf, fout + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        double slope = -c->h_buf[0];
+        double slope = -gd;
         if (!(slope < 0.0)) {   // not a descent direction: steepest descent
             HIPCHK(hipMemcpyAsync(d, g, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
             slope = -gnorm * gnorm;
@@ -765,33 +806,56 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
             tstep *= 0.5;
         }
         if (!ok) break;
-        // new pair s = xt - x, y = gt - g
+        // new pair s = xt - x, y = gt - g, and its dots with itself and the kept pairs
         const int sl = free_slots.back();
         free_slots.pop_back();
         double* sv = Sh + (size_t)sl * n;
         double* yv = Yh + (size_t)sl * n;
         HIPCHK(launch_sub(n, xt, x, sv, c->stream));
         HIPCHK(launch_sub(n, gt, g, yv, c->stream));
-        HIPCHK(launch_dots_part(n, 3, sv, yv, d3_rec, c->stream));
-        HIPCHK(launch_finish_sum(d3_rec, vb, 3, fout + 3, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_buf, fout + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        {
+            std::vector<std::pair<const double*, const double*>> pr;
+            pr.push_back({sv, yv});
+            pr.push_back({sv, sv});
+            pr.push_back({yv, yv});
+            for (int j = 0; j < hsz; ++j) {
+                const double* sj = Sh + (size_t)slot[j] * n;
+                const double* yj = Yh + (size_t)slot[j] * n;
+                pr.push_back({sv, yj});
+                pr.push_back({sj, yv});
+                pr.push_back({yv, yj});
+            }
+            TRY(dots(pr, nd.data()));
+        }
         HIPCHK(hipMemcpyAsync(x, xt, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(g, gt, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        const double sy = c->h_buf[0], ss = c->h_buf[1], yy = c->h_buf[2];
+        const double sy = nd[0], ss = nd[1], yy = nd[2];
         if (sy > 1e-12 * std::sqrt(ss) * std::sqrt(yy)) {
+            const int q = hsz;   // position of the new pair
+            for (int j = 0; j < hsz; ++j) {
+                SY[q * MM + j] = nd[3 + 3 * j];       // s_new . y_j
+                SY[j * MM + q] = nd[3 + 3 * j + 1];   // s_j . y_new
+                YY[q * MM + j] = YY[j * MM + q] = nd[3 + 3 * j + 2];
+            }
+            SY[q * MM + q] = sy;
+            YY[q * MM + q] = yy;
             slot.push_back(sl);
-            rho.push_back(1.0 / sy);
             gamma = sy / yy;
-            if ((int)slot.size() > m) {
+            if ((int)slot.size() > m) {   // drop the oldest pair: shift the matrices
                 free_slots.push_back(slot.front());
                 slot.erase(slot.begin());
-                rho.erase(rho.begin());
+                const int h2 = (int)slot.size();
+                for (int i = 0; i < h2; ++i)
+                    for (int j = 0; j < h2; ++j) {
+                        SY[i * MM + j] = SY[(i + 1) * MM + j + 1];
+                        YY[i * MM + j] = YY[(i + 1) * MM + j + 1];
+                    }
             }
         } else {
             free_slots.push_back(sl);
         }
         f = fn;
+        gn2 = gn2n;
         gnorm = std::sqrt(gn2n);
         ++it;
     }

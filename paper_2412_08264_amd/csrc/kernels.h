@@ -24,6 +24,21 @@ hipError_t launch_forward(const Stencil& S, const double* x, const double* e, do
                           hipStream_t stream);
 
 // krylov.hip
+// Up to VL_MAX dot products in one pass, and a linear combination of up to VC_MAX vectors.
+constexpr int VL_MAX = 24;
+constexpr int VC_MAX = 40;
+struct VecPairs {
+    int k;
+    const double* a[VL_MAX];
+    const double* b[VL_MAX];
+};
+struct VecComb {
+    int k;
+    double c[VC_MAX];
+    const double* v[VC_MAX];
+};
+hipError_t launch_multidot(int n, const VecPairs& vp, double* part, hipStream_t stream);
+hipError_t launch_lincomb(int n, double c0, const double* x0, const VecComb& vc, double* out, hipStream_t stream);
 int red_blocks(int n);
 int vec_blocks(int n);
 hipError_t launch_finish_sum(const double* part, int nb, int nv, double* out, hipStream_t stream);

@@ -54,6 +54,35 @@ __global__ void __launch_bounds__(NT) k_sub(int n, const double* __restrict__ a,
     for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) out[i] = a[i] - b[i];
 }
 
+// Dots a_i . b_i of up to VL_MAX vector pairs in one pass (records: one per block, k values).
+__global__ void __launch_bounds__(NT) k_multidot(int n, VecPairs vp, double* __restrict__ part) {
+    double acc[VL_MAX];
+#pragma unroll
+    for (int i = 0; i < VL_MAX; ++i) acc[i] = 0.0;
+    for (int p = blockIdx.x * NT + threadIdx.x; p < n; p += gridDim.x * NT) {
+#pragma unroll
+        for (int i = 0; i < VL_MAX; ++i)
+            if (i < vp.k) acc[i] += vp.a[i][p] * vp.b[i][p];
+    }
+    block_partials(part, vp.k, [&](int i) {
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < VL_MAX; ++u)
+            if (u == i) v = acc[u];
+        return v;
+    });
+}
+
+// out = c0 x0 + sum_i c_i v_i (i < k).
+__global__ void __launch_bounds__(NT) k_lincomb(int n, double c0, const double* __restrict__ x0, VecComb vc,
+                                                double* __restrict__ out) {
+    for (int p = blockIdx.x * NT + threadIdx.x; p < n; p += gridDim.x * NT) {
+        double acc = c0 * x0[p];
+        for (int i = 0; i < vc.k; ++i) acc += vc.c[i] * vc.v[i][p];
+        out[p] = acc;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 // One pixel per thread (the residual-record kernels rely on it).
 int red_blocks(int n) { return (n + NT - 1) / NT; }
@@ -75,6 +104,14 @@ hipError_t launch_axpy_red(int n, double beta, double* y, const double* x, const
                            const double* part2, double s2, hipStream_t stream) {
     hipLaunchKernelGGL(k_axpy_red, dim3(vec_blocks(n)), dim3(NT), 0, stream, n, beta, y, x, part1, s1, part2, s2,
                        vec_blocks(n));
+    return hipGetLastError();
+}
+hipError_t launch_multidot(int n, const VecPairs& vp, double* part, hipStream_t stream) {
+    hipLaunchKernelGGL(k_multidot, dim3(vec_blocks(n)), dim3(NT), 0, stream, n, vp, part);
+    return hipGetLastError();
+}
+hipError_t launch_lincomb(int n, double c0, const double* x0, const VecComb& vc, double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_lincomb, dim3(vec_blocks(n)), dim3(NT), 0, stream, n, c0, x0, vc, out);
     return hipGetLastError();
 }
 hipError_t launch_sub(int n, const double* a, const double* b, double* out, hipStream_t stream) {
