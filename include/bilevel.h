@@ -185,7 +185,8 @@ bl_status bl_hessian_solve(bl_ctx* ctx, const bl_problem* P, const double* theta
  *     kept); BL_E_INDEFINITE is never returned.
  * stats: res_norm = |zeta| at the returned iterate, res0_norm = ||r0|| after the projection.
  * Tiles of 32 x 8 pixels; no graph replay: two launches per step from the host, with a poll of
- * the stop flag every 8 steps. */
+ * the stop flag every 8 steps (double-buffered: the device runs the next 8 steps while the host
+ * reads the flag of the previous ones). */
 bl_status bl_hessian_solve_rminres(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
                                    const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
                                    void* ws, size_t ws_bytes, bl_stats* out);

@@ -392,6 +392,10 @@ bl_status bl_hessian_solve_rminres(bl_ctx* c, const bl_problem* P, const double*
     int nvb = 1 + a.nz;   // the set-up's record: iterate 0 is always tested
     bool decided = false;
     const long kmax = (long)o->max_iter + 2;
+    // Stop-flag polls: after every POLL steps the header goes to one of two pinned snapshots,
+    // marked by an event; the host then waits for the previous snapshot only, so the device
+    // runs the next chunk meanwhile.  Launches after the stop return after their reduction.
+    int pending = -1, npoll = 0;
     for (long k = 1; k <= kmax && !decided; ++k) {
         const bool fold_upd = (long)a.npix * nvb > REC_LIMIT;
         if (fold_upd) HIPCHK(launch_m_fold(a.rec_upd, a.npix, nvb, a.fold, c->stream));
@@ -401,10 +405,19 @@ bl_status bl_hessian_solve_rminres(bl_ctx* c, const bl_problem* P, const double*
         HIPCHK(launch_m_update(a, (int)k, zr, fold_app, c->stream));
         nvb = 1 + zr;
         if (k % POLL == 0 || k == kmax) {
-            HIPCHK(hipMemcpyAsync(c->h_info, a.st, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            decided = c->h_info[0] != 0;
+            const int buf = npoll++ & 1;
+            HIPCHK(hipMemcpyAsync(c->h_info + 4 * buf, a.st, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipEventRecord(c->poll_ev[buf], c->stream));
+            if (pending >= 0) {
+                HIPCHK(hipEventSynchronize(c->poll_ev[pending]));
+                decided = c->h_info[4 * pending] != 0;
+            }
+            pending = buf;
         }
+    }
+    if (!decided && pending >= 0) {   // the snapshot taken after the last launched step
+        HIPCHK(hipEventSynchronize(c->poll_ev[pending]));
+        decided = c->h_info[4 * pending] != 0;
     }
     if (!decided) return c->err = "RMINRES ended without a stop decision", BL_E_HIP;
     if (s) HIPCHK(launch_m_finish(a, c->stream));
