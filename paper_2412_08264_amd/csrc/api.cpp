@@ -750,26 +750,27 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
     std::vector<int> free_slots;
     for (int k = m; k >= 0; --k) free_slots.push_back(k);
     std::vector<double> SY(MM * MM, 0.0), YY(MM * MM, 0.0);
-    std::vector<double> av(2 * MM), uv(MM), pv(MM), wv(MM), nd(3 * MM + 3);
+    std::vector<double> av(2 * MM), uv(MM), pv(MM), wv(MM), nd(5 * MM + 3);
+    // the iterate and its gradient alternate between the caller's x (and g) and xt (and gt)
+    double* xc = x;
+    double* xn = xt;
+    double* gc = g;
+    double* gn = gt;
     int it = 0;
     double gnorm = std::sqrt(gn2);
     double gamma = 0.0;
     while (gnorm > gtol && it < max_iter) {
         if (!std::isfinite(f) || !std::isfinite(gnorm)) return c->err = "non-finite objective", BL_E_NONFINITE;
-        // d = H_k g in the compact form: with a = S^T g, b = Y^T g, R the upper triangle of
-        // S^T Y and D its diagonal, u = R^{-1} a, p = R^{-T} ((D + gamma Y^T Y) u - gamma b),
-        // d = gamma g + S p - gamma Y u.  One pass for the 2h dots, one for the combination.
+        // d = H_k g in the compact form: with a = S^T g, b = Y^T g (av, from the previous
+        // iteration's dot pass), R the upper triangle of S^T Y and D its diagonal,
+        // u = R^{-1} a, p = R^{-T} ((D + gamma Y^T Y) u - gamma b), d = gamma g + S p - gamma Y u.
         const int hsz = (int)slot.size();
         double gd;
         if (hsz == 0) {
             VecComb vc{};
-            HIPCHK(launch_lincomb(n, 1.0 / gnorm, g, vc, d, c->stream));
+            HIPCHK(launch_lincomb(n, 1.0 / gnorm, gc, vc, d, c->stream));
             gd = gnorm;
         } else {
-            std::vector<std::pair<const double*, const double*>> pr;
-            for (int i = 0; i < hsz; ++i) pr.push_back({Sh + (size_t)slot[i] * n, g});
-            for (int i = 0; i < hsz; ++i) pr.push_back({Yh + (size_t)slot[i] * n, g});
-            TRY(dots(pr, av.data()));
             const double* A = av.data();
             const double* Bv = av.data() + hsz;
             for (int i = hsz - 1; i >= 0; --i) {
@@ -797,21 +798,24 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
                 vc.v[hsz + i] = Yh + (size_t)slot[i] * n;
                 gd += pv[i] * A[i] - gamma * uv[i] * Bv[i];
             }
-            HIPCHK(launch_lincomb(n, gamma, g, vc, d, c->stream));
+            HIPCHK(launch_lincomb(n, gamma, gc, vc, d, c->stream));
         }
         // direction -d; slope = -(g . d)
         double slope = -gd;
         if (!(slope < 0.0)) {   // not a descent direction: steepest descent
-            HIPCHK(hipMemcpyAsync(d, g, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(d, gc, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
             slope = -gnorm * gnorm;
         }
         // backtracking Armijo on x - t d
         double tstep = 1.0, fn = 0.0, gn2n = 0.0;
         bool ok = false;
         for (int bt = 0; bt < 60; ++bt) {
-            HIPCHK(hipMemcpyAsync(xt, x, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(launch_axpy_red(n, 1.0, xt, d, nullptr, -tstep, nullptr, 0.0, c->stream));
-            TRY(grad_at(xt, gt, fn, gn2n));
+            VecComb step{};
+            step.k = 1;
+            step.c[0] = -tstep;
+            step.v[0] = d;
+            HIPCHK(launch_lincomb(n, 1.0, xc, step, xn, c->stream));
+            TRY(grad_at(xn, gn, fn, gn2n));
             if (fn <= f + 1e-4 * tstep * slope) {
                 ok = true;
                 break;
@@ -819,13 +823,15 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
             tstep *= 0.5;
         }
         if (!ok) break;
-        // new pair s = xt - x, y = gt - g, and its dots with itself and the kept pairs
+        // new pair s = x_new - x, y = g_new - g; one dot pass for its products with itself and
+        // the kept pairs and for the next direction's S^T g_new, Y^T g_new (kept pairs and the
+        // new one: whether the new pair is kept is decided from these dots)
         const int sl = free_slots.back();
         free_slots.pop_back();
         double* sv = Sh + (size_t)sl * n;
         double* yv = Yh + (size_t)sl * n;
-        HIPCHK(launch_sub(n, xt, x, sv, c->stream));
-        HIPCHK(launch_sub(n, gt, g, yv, c->stream));
+        HIPCHK(launch_sub(n, xn, xc, sv, c->stream));
+        HIPCHK(launch_sub(n, gn, gc, yv, c->stream));
         {
             std::vector<std::pair<const double*, const double*>> pr;
             pr.push_back({sv, yv});
@@ -838,11 +844,19 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
                 pr.push_back({sj, yv});
                 pr.push_back({yv, yj});
             }
+            for (int j = 0; j < hsz; ++j) pr.push_back({Sh + (size_t)slot[j] * n, gn});
+            pr.push_back({sv, gn});
+            for (int j = 0; j < hsz; ++j) pr.push_back({Yh + (size_t)slot[j] * n, gn});
+            pr.push_back({yv, gn});
             TRY(dots(pr, nd.data()));
         }
-        HIPCHK(hipMemcpyAsync(x, xt, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(g, gt, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        const double* sg = nd.data() + 3 + 3 * hsz;   // S^T g_new (kept pairs, then the new one)
+        const double* yg = sg + hsz + 1;                // Y^T g_new
+        std::swap(xc, xn);
+        std::swap(gc, gn);
         const double sy = nd[0], ss = nd[1], yy = nd[2];
+        int first = 0;   // first kept pair after this update (1 when the oldest is dropped)
+        int hk = hsz;    // pairs kept after this update
         if (sy > 1e-12 * std::sqrt(ss) * std::sqrt(yy)) {
             const int q = hsz;   // position of the new pair
             for (int j = 0; j < hsz; ++j) {
@@ -854,6 +868,7 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
             YY[q * MM + q] = yy;
             slot.push_back(sl);
             gamma = sy / yy;
+            hk = hsz + 1;
             if ((int)slot.size() > m) {   // drop the oldest pair: shift the matrices
                 free_slots.push_back(slot.front());
                 slot.erase(slot.begin());
@@ -863,15 +878,23 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
                         SY[i * MM + j] = SY[(i + 1) * MM + j + 1];
                         YY[i * MM + j] = YY[(i + 1) * MM + j + 1];
                     }
+                first = 1;
+                hk = h2;
             }
         } else {
             free_slots.push_back(sl);
+        }
+        // a = S^T g and b = Y^T g over the pairs now kept (in their order)
+        for (int i = 0; i < hk; ++i) {
+            av[i] = sg[first + i];
+            av[hk + i] = yg[first + i];
         }
         f = fn;
         gn2 = gn2n;
         gnorm = std::sqrt(gn2n);
         ++it;
     }
+    if (xc != x) HIPCHK(hipMemcpyAsync(x, xc, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (out) {
         std::memset(out, 0, sizeof(*out));
