@@ -123,6 +123,9 @@ def select_rgen_large(G: np.ndarray, M: np.ndarray, s: int) -> dict:
 # largest, M: ceil(s/2) smallest and floor(s/2) largest), and for RGen-L the side (R: right
 # vectors W X, L: left vectors W V_H, M: their normalised sum).
 SELECTIONS = ("rgen-l-r", "rgen-l-l", "rgen-l-m", "ritz-s", "ritz-l", "ritz-m", "hritz-s", "hritz-l", "hritz-m")
+# RGen of sizes S and M: only where J W has full column rank (p >= t), so that every generalized
+# singular value is positive and "the smallest" is defined without ties among zeros.
+SELECTIONS_FULL_RANK = ("rgen-s-r", "rgen-s-l", "rgen-s-m", "rgen-m-r", "rgen-m-l", "rgen-m-m")
 
 
 def size_pick(t: int, s: int, size: str) -> list:
@@ -177,13 +180,24 @@ def rgen_side(M: np.ndarray, sel: dict, side: str) -> dict:
     return out
 
 
+def select_rgen_size(G: np.ndarray, M: np.ndarray, s: int, size: str) -> dict:
+    """RGen of size S or M (Table 2): the smallest, or ceil(s/2) smallest and floor(s/2) largest,
+    generalized singular values of (G, M); needs rank G = t."""
+    t = M.shape[0]
+    rG = g_rank(G)
+    if rG < t:
+        raise ValueError("RGen sizes S and M need J W of full column rank")
+    gs = gsvd_ps(G, M)   # ascending mu
+    idx = size_pick(t, s, size)
+    return {"X": gs["X"][:, idx], "V_H": gs["V_H"][:, idx], "mu": gs["mu"][idx], "rank_G": rG}
+
+
 def select(G, M, YtY, s: int, rule: str) -> dict:
-    """Dispatch a selection rule of SELECTIONS."""
+    """Dispatch a selection rule of SELECTIONS or SELECTIONS_FULL_RANK."""
     kind, size, *rest = rule.split("-")
     if kind == "rgen":
-        if size != "l":
-            raise ValueError(f"RGen sizes other than L are not built: {rule}")
-        return rgen_side(M, select_rgen_large(G, M, s), rest[0])
+        sel = select_rgen_large(G, M, s) if size == "l" else select_rgen_size(G, M, s, size)
+        return rgen_side(M, sel, rest[0])
     if kind == "ritz":
         return select_ritz(M, s, size)
     if kind == "hritz":

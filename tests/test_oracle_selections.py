@@ -124,3 +124,37 @@ def test_refresh_invariants_every_rule(rule):
     assert np.linalg.norm(H @ U - C) <= 1e-11 * np.linalg.norm(C)
     if not rule.startswith("rgen"):
         assert np.all(out["mu"] == 0.0) and np.all(out["Z"] == 0.0)
+
+
+@pytest.mark.parametrize("rule", recycle.SELECTIONS_FULL_RANK)
+def test_rgen_small_and_mixed_sizes(rule):
+    """p >= t: the chosen generalized singular values are the smallest (S) or both ends (M) of
+    the full GSVD spectrum, and the chosen pairs still diagonalise the projected Hessian."""
+    n, t, p, s = 50, 8, 12, 4
+    H, _ = sym_known(n, np.geomspace(1.0, 40.0, n), 11)
+    rng = np.random.default_rng(12)
+    W, _ = np.linalg.qr(rng.standard_normal((n, t)))
+    J = rng.standard_normal((p, n))
+    M = W.T @ H @ W
+    G = J @ W
+    sel = recycle.select(G, M, None, s, rule)
+    # generalized singular values: sigma(G M^{-1}) (eq. gritz-decomp), all t positive here
+    allmu = np.sort(np.linalg.svd(G @ np.linalg.inv(M), compute_uv=False))
+    size = rule.split("-")[1]
+    want = allmu[recycle.size_pick(t, s, size)]
+    assert np.allclose(np.sort(sel["mu"]), np.sort(want), rtol=1e-10)
+    right = recycle.select(G, M, None, s, rule[:-1] + "r")
+    Xr = right["X"] / np.linalg.norm(right["X"], axis=0)
+    left = recycle.select(G, M, None, s, rule[:-1] + "l")
+    D = (W @ left["X"]).T @ H @ (W @ Xr)
+    assert np.abs(D - np.diag(np.diag(D))).max() <= 1e-12 * np.abs(np.diag(D)).max()
+    assert np.all(np.diag(D) > 0)
+
+
+def test_rgen_small_needs_full_rank():
+    n, t = 40, 10
+    H, _ = sym_known(n, np.geomspace(1.0, 20.0, n), 13)
+    W, _ = np.linalg.qr(np.random.default_rng(14).standard_normal((n, t)))
+    G = np.random.default_rng(15).standard_normal((3, n)) @ W     # p = 3 < t
+    with pytest.raises(ValueError):
+        recycle.select(G, W.T @ H @ W, None, 4, "rgen-s-r")
