@@ -101,12 +101,17 @@ typedef struct {
  *     ceil(s/2) smallest and floor(s/2) largest Ritz values;
  *   HRITZ_S / _L / _M: harmonic Ritz vectors (eq. harmonic-ritz) chosen likewise by the harmonic
  *     Ritz values.
+ *   RGEN_S_* / RGEN_M_*: the s smallest, or ceil(s/2) smallest and floor(s/2) largest, Ritz
+ *     generalized singular values, sides as above; only where p >= t (J W of full column rank,
+ *     so that no generalized singular value is zero), else BL_E_ARG.
  * Ritz and harmonic Ritz selections need no J and write mu = 0 and Z = 0: the error-estimate
  * test is then undefined (its estimate is 0), so solves after them use the residual test. */
 typedef enum {
     BL_SEL_RGEN_L_R = 0, BL_SEL_RGEN_L_L = 1, BL_SEL_RGEN_L_M = 2,
     BL_SEL_RITZ_S = 3, BL_SEL_RITZ_L = 4, BL_SEL_RITZ_M = 5,
-    BL_SEL_HRITZ_S = 6, BL_SEL_HRITZ_L = 7, BL_SEL_HRITZ_M = 8
+    BL_SEL_HRITZ_S = 6, BL_SEL_HRITZ_L = 7, BL_SEL_HRITZ_M = 8,
+    BL_SEL_RGEN_S_R = 9, BL_SEL_RGEN_S_L = 10, BL_SEL_RGEN_S_M = 11,
+    BL_SEL_RGEN_M_R = 12, BL_SEL_RGEN_M_L = 13, BL_SEL_RGEN_M_M = 14
 } bl_select;
 
 typedef struct {

@@ -46,7 +46,8 @@ class bl_recycle_opts(C.Structure):
 
 # selection rules of bl_select, by name
 SELECTIONS = {"rgen-l-r": 0, "rgen-l-l": 1, "rgen-l-m": 2, "ritz-s": 3, "ritz-l": 4, "ritz-m": 5,
-              "hritz-s": 6, "hritz-l": 7, "hritz-m": 8}
+              "hritz-s": 6, "hritz-l": 7, "hritz-m": 8,
+              "rgen-s-r": 9, "rgen-s-l": 10, "rgen-s-m": 11, "rgen-m-r": 12, "rgen-m-l": 13, "rgen-m-m": 14}
 
 
 class bl_stats(C.Structure):

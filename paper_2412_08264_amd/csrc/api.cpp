@@ -569,8 +569,17 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     if (!rs->U || !rs->C || !rs->Z || !rs->mu || (rs->v_cap > 0 && !rs->V))
         return c->err = "null recycle arrays", BL_E_ARG;
     if (!(o->rank_tol > 0.0 && o->rank_tol < 1.0)) return c->err = "rank_tol outside (0, 1)", BL_E_ARG;
-    if (o->select < BL_SEL_RGEN_L_R || o->select > BL_SEL_HRITZ_M) return c->err = "unknown selection", BL_E_ARG;
-    const bool rgen = o->select <= BL_SEL_RGEN_L_M;
+    if (o->select < BL_SEL_RGEN_L_R || o->select > BL_SEL_RGEN_M_M) return c->err = "unknown selection", BL_E_ARG;
+    const bool rgen = o->select <= BL_SEL_RGEN_L_M || o->select >= BL_SEL_RGEN_S_R;
+    // RGen: size 0 / 1 / 2 (largest / smallest / both ends), side 0 / 1 / 2 (right / left / sum)
+    int gsize = 0, side = 0;
+    if (o->select <= BL_SEL_RGEN_L_M) {
+        side = o->select - BL_SEL_RGEN_L_R;
+    } else if (o->select >= BL_SEL_RGEN_S_R) {
+        const int q = o->select - BL_SEL_RGEN_S_R;
+        gsize = 1 + q / 3;
+        side = q % 3;
+    }
     WS ws;
     TRY(check_ws(c, layout(P, rs->s_max, rs->v_cap), wsp, ws_bytes, ws));
     const int n = P->h * P->w, p = nparams(P);
@@ -632,9 +641,12 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     if (rgen) HIPCHK(launch_jac(S, xhat, W0, t, ws.d1(), ws.d2(), ws.part(), Gj, 1, c->stream));
     mark(c, 2);
     if (rgen) {
-        HIPCHK(launch_gsvd_select(t, p, o->s, M, Gj, gsc, Xs, VHs, mu_tmp, info, c->stream));
-        if (o->select != BL_SEL_RGEN_L_R)
-            HIPCHK(launch_rgen_side(t, o->select == BL_SEL_RGEN_L_L ? 1 : 2, M, Xs, info, c->stream));
+        if (gsize != 0 && p < t) {
+            rs->s_cur = 0;
+            return c->err = "RGen sizes S and M need p >= t (J W of full column rank)", BL_E_ARG;
+        }
+        HIPCHK(launch_gsvd_select(t, p, o->s, gsize, M, Gj, gsc, Xs, VHs, mu_tmp, info, c->stream));
+        if (side != 0) HIPCHK(launch_rgen_side(t, side, M, Xs, info, c->stream));
     } else {
         // Ritz values of W^T H W, or harmonic Ritz values from (H W)^T (H W) = Y^T Y
         const int kind = o->select >= BL_SEL_HRITZ_S ? 1 : 0;

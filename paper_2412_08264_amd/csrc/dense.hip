@@ -604,7 +604,8 @@ __device__ void solve_cols(int t, const double* L, double* X, int ncols, size_t 
     __syncthreads();
 }
 
-// Projected GSVD of (G, M) (p x t and t x t) and RGen-L(R) selection of s_eff = min(s, t)
+// Projected GSVD of (G, M) (p x t and t x t) and RGen selection of s_eff = min(s, t)
+// (`size`: the largest, RGen-L; with p >= t also the smallest or both ends, RGen-S / RGen-M)
 // columns.  Output: Xs (t x s_eff, unit columns), VHs (t x s_eff, zero for filled slots),
 // mu (s_eff), info = {s_eff, rank_G, status}.  Scratch: sc (gsvd_scratch_doubles).
 // Route: Cholesky M = L L^T;  S = G M^{-1};
@@ -612,7 +613,7 @@ __device__ void solve_cols(int t, const double* L, double* X, int ncols, size_t 
 //   p <  t: eigen of S S^T (p x p) gives mu and V_H = S^T u / mu; null(G) from the Householder
 //           QR G^T = Q R: the remaining slots take the smallest Ritz pairs of N^T M N with
 //           N = Q[:, p:], formed as the trailing block of Q^T M Q (Ritz-S).
-__global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, const double* __restrict__ Min,
+__global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int size, const double* __restrict__ Min,
                                                        const double* __restrict__ G, double* sc, double* Xs,
                                                        double* VHs, double* mu, int* info, int ldsd) {
     extern __shared__ double dyn_lds[];
@@ -731,17 +732,24 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, cons
             }
         }
         __syncthreads();
-        // all eigenvalues of K (ascending), vectors of the s_eff largest
-        eig_range(t, K, t - s_eff, t, lamv, Vv, esc, ldsd);
+        // all eigenvalues of K (ascending); vectors of the chosen ones: size 0 (L) the s_eff
+        // largest (largest first), 1 (S) the s_eff smallest (ascending), 2 (M) ceil(s_eff / 2)
+        // smallest then floor(s_eff / 2) largest
+        const int lo_e = size == 0 ? t - s_eff : 0, hi_e = size == 1 ? s_eff : t;
+        const int nlo = (s_eff + 1) / 2;
+        eig_range(t, K, lo_e, hi_e, lamv, Vv, esc, ldsd);
         rankG = t;
+        auto eig_of = [&](int c) {   // eigen index of output column c
+            return size == 0 ? t - 1 - c : (size == 1 ? c : (c < nlo ? c : t - 1 - (c - nlo)));
+        };
         for (int idx = threadIdx.x; idx < s_eff * t; idx += blockDim.x) {
             const int c = idx / t, i = idx - c * t;
-            const double v = Vv[(size_t)(s_eff - 1 - c) * t + i];   // c-th largest
+            const double v = Vv[(size_t)(eig_of(c) - lo_e) * t + i];
             VHs[(size_t)c * t + i] = v;
             Xs[(size_t)c * t + i] = v;
         }
         for (int c = threadIdx.x; c < s_eff; c += blockDim.x) {
-            const double lam = lamv[t - 1 - c];
+            const double lam = lamv[eig_of(c)];
             mu[c] = lam > 0.0 ? sqrt(lam) : 0.0;
         }
         __syncthreads();
@@ -1059,16 +1067,16 @@ hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int*
     return hipGetLastError();
 }
 
-hipError_t launch_gsvd_select(int t, int p, int s, const double* M, const double* G, double* sc, double* Xs,
-                              double* VHs, double* mu, int* info, hipStream_t stream) {
+hipError_t launch_gsvd_select(int t, int p, int s, int size, const double* M, const double* G, double* sc,
+                              double* Xs, double* VHs, double* mu, int* info, hipStream_t stream) {
     // dynamic LDS: the eigensolver's matrix plus its vectors, the solves' factor plus columns;
     // at least the S^T S chunk
     const size_t want = std::max((size_t)3 * t * t + (size_t)6 * t * t, (size_t)KC * t) * sizeof(double);
     const size_t bytes = std::min(want, lds_limit()) / sizeof(double) * sizeof(double);
     if (bytes > 65536)
         (void)hipFuncSetAttribute((const void*)k_gsvd_select, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), bytes, stream, t, p, s, M, G, sc, Xs, VHs, mu, info,
-                       (int)(bytes / sizeof(double)));
+    hipLaunchKernelGGL(k_gsvd_select, dim3(1), dim3(SD_NT), bytes, stream, t, p, s, size, M, G, sc, Xs, VHs, mu,
+                       info, (int)(bytes / sizeof(double)));
     return hipGetLastError();
 }
 

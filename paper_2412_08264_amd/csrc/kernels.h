@@ -142,8 +142,10 @@ hipError_t launch_gemm_tall(int n, int t, int k, const double* A, const double* 
 hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int* kept, int* tk, double* Xinv,
                             int ldx, hipStream_t stream);
 size_t gsvd_scratch_doubles(int t, int p);
-hipError_t launch_gsvd_select(int t, int p, int s, const double* M, const double* G, double* sc, double* Xs,
-                              double* VHs, double* mu, int* info, hipStream_t stream);
+// size 0 / 1 / 2: the s largest / smallest / both ends of the generalized singular values
+// (sizes 1 and 2 only with p >= t, checked by the caller).
+hipError_t launch_gsvd_select(int t, int p, int s, int size, const double* M, const double* G, double* sc,
+                              double* Xs, double* VHs, double* mu, int* info, hipStream_t stream);
 // Ritz (kind 0) or harmonic Ritz (kind 1) selection, size 0 / 1 / 2 = S / L / M; scratch as
 // gsvd_scratch_doubles.
 hipError_t launch_ritz_select(int t, int s, int kind, int size, const double* M, const double* YtY, double* sc,

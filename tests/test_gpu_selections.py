@@ -105,3 +105,37 @@ def test_indefinite_selection_then_rminres(B, rule):
                      allow=(B.BL_E_NOT_CONVERGED,))
         assert st.iters == k
         assert rel(host(w), ref_s["w"]) <= 1e-8
+
+
+@pytest.mark.parametrize("rule", list(recycle.SELECTIONS_FULL_RANK))
+def test_refresh_rgen_small_and_mixed_filters(B, rule):
+    """Filters (p = 400 >= t): RGen of sizes S and M, every side, against the oracle."""
+    wl = synth.custom("f", 40, "filters", 8, width=44, rect_min=2, rect_max=6, seed=71)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xh = inst["xstar"].ravel() + 0.02 * synth.unit_noise(prob.n, 72)
+    th = inst["theta0"]
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    first = krylov.cg(hvp, g, tol=1e-8, v_cap=20)
+    ref = recycle.refresh(hvp, lambda v: prob.jac_apply(xh, th, v), None, first["V"], s=8, select_rule=rule)
+    with B.Session(B.problem_from(wl, prec="fp64"), s_max=8, v_cap=20) as S:
+        m = first["V"].shape[1]
+        S.V[:m] = dev(first["V"].T)
+        S.rs.v_cur = m
+        S.refresh(th, dev(xh), s=8, select=rule)
+        assert S.rs.s_cur == 8
+        mu = host(S.mu[:8])
+        assert np.abs(np.sort(mu) - np.sort(ref["mu"])).max() <= 1e-9 * ref["mu"].max()
+        U = host(S.U[:8]).T
+        assert recycle.principal_angles(U, ref["U"]).max() <= 1e-8, rule
+
+
+def test_rgen_small_refused_for_tv(B, tv_basis):
+    wl, prob, xh, th, V = tv_basis
+    with B.Session(B.problem_from(wl), s_max=6, v_cap=24) as S:
+        m = V.shape[1]
+        S.V[:m] = dev(V.T)
+        S.rs.v_cur = m
+        with pytest.raises(B.BLError):
+            S.refresh(th, dev(xh), s=6, select="rgen-s-r")
