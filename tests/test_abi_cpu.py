@@ -55,6 +55,20 @@ def test_status_strings_and_null_context():
     assert B.lib.bl_hessian_solve(None, C.byref(P), th, None, None, None, None, C.byref(opts), None, 0,
                                   C.byref(st)) == B.BL_E_ARG
     assert B.lib.bl_destroy(None) == B.BL_E_ARG
+    assert B.lib.bl_hessian_solve_rminres(None, C.byref(P), th, None, None, None, None, C.byref(opts), None, 0,
+                                          C.byref(st)) == B.BL_E_ARG
+    ro = B.bl_recycle_opts(4, 1e-8, 0)
+    assert B.lib.bl_recycle_update(None, C.byref(P), th, None, None, C.byref(ro), None, 0, C.byref(st)) == B.BL_E_ARG
+
+
+def test_selection_codes_match_header():
+    """The binding's selection names map to the codes bl_select declares, in Table 2's order."""
+    from paper_2412_08264_amd import bilevel as B
+    text = open(HEADER).read()
+    codes = {m.group(1).lower().replace("_", "-"): int(m.group(2))
+             for m in re.finditer(r"BL_SEL_(\w+)\s*=\s*(\d+)", text)}
+    assert codes == B.SELECTIONS
+    assert len(set(codes.values())) == 15
 
 
 def test_engine_sizes():
