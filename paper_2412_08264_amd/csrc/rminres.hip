@@ -160,11 +160,12 @@ __global__ void __launch_bounds__(NT) k_m_init(MinresArgs a, MinresInit in, int 
 // Loads that do not depend on this step's scalars are issued before the record reduction: the
 // columns of C at the thread's pixel (the first MCP), x_hat, and for TV the staged region of u_k
 // (the stencil input v_k = u_k / beta_k is formed from registers once beta_k is known).
-constexpr int MCP = 24;
-template <int R, int CLS>
+// REC: the solve has a recycle space (s > 0); without one no registers hold columns of C.
+template <int R, int CLS, bool REC>
 __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, int nvb, int fold) {
     using L = QLayout<double, R, CLS, 1>;
     using G = QGeo<R, CLS, 1>;
+    constexpr int MCP = REC ? 24 : 1;
     constexpr bool EARLY = CLS == TC_TV;
     constexpr int NST = EARLY ? (G::N_V + NT - 1) / NT : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -177,7 +178,7 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
     tile_origin(S, r0, c0);
     const Own<1> o = own_pixels<1>(S.h, S.w, r0, c0);
     const double* __restrict__ uk = a.u[k % 3];
-    const int n = S.n, s = a.s;
+    const int n = S.n, s = REC ? a.s : 0;
     double cpre[MCP], hu[NST];
 #pragma unroll
     for (int c = 0; c < MCP; ++c) cpre[c] = (o.in[0] && c < s) ? a.C[(size_t)c * n + o.g[0]] : 0.0;
@@ -287,13 +288,14 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
 // ------------------------------------------------------------------ update, step k
 // `zr` values of Z^T r_{k-1} go into this launch's record (0 or nz); `fold`: the apply records
 // were folded.
-constexpr int MPRE = 24;
+template <bool REC>
 __global__ void __launch_bounds__(NT) k_m_update(MinresArgs a, int k, int zr, int fold) {
+    constexpr int MPRE = REC ? 24 : 1;
     __shared__ double tot[NT];
     __shared__ int sdone;
     MinresState* st = a.st;
     if (threadIdx.x == 0) sdone = st->done;
-    const int s = a.s, n = a.n;
+    const int s = REC ? a.s : 0, n = a.n;
     const int i = blockIdx.x * NT + threadIdx.x;
     const bool in = i < n;
     // loads that do not depend on this step's scalars, issued before the reduction
@@ -411,14 +413,19 @@ hipError_t launch_m_apply(const Stencil& S, const MinresArgs& a, int k, int nvb,
     q_dispatch(S.R, tile_class(S.reg, S.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
         const size_t lds = QLayout<double, RR, CC, 1>::bytes;
-        allow_lds_b(k_m_apply<RR, CC>, lds);
-        hipLaunchKernelGGL((k_m_apply<RR, CC>), dim3(a.ntiles), dim3(NT), lds, stream, S, a, k, nvb, (int)fold);
+        auto go = [&](auto kern) {
+            allow_lds_b(kern, lds);
+            hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(NT), lds, stream, S, a, k, nvb, (int)fold);
+        };
+        if (a.s > 0) go(k_m_apply<RR, CC, true>);
+        else go(k_m_apply<RR, CC, false>);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_m_update(const MinresArgs& a, int k, int zr, bool fold, hipStream_t stream) {
-    hipLaunchKernelGGL(k_m_update, dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
+    if (a.s > 0) hipLaunchKernelGGL(k_m_update<true>, dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
+    else hipLaunchKernelGGL(k_m_update<false>, dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
     return hipGetLastError();
 }
 
