@@ -43,8 +43,11 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
 // Iteration j, second half: sigma, e from the apply records; alpha = rho_j / sigma;
 // w += alpha p;  r -= alpha (q - C e);  z -= alpha e;  record [r.r, Z^T r] (Z^T r only when
 // the test of iteration j + 1 evaluates the error estimate).
-constexpr int UPRE = 24;
+// REC: some slot of the launch has a recycle space; without one (plain CG only) no registers
+// hold columns of C or Z.  A slot with s = 0 computes the same values either way.
+template <bool REC>
 __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, StepRef sr) {
+    constexpr int UPRE = REC ? 24 : 1;
     __shared__ double tot[NT];
     __shared__ int sdone;
     const int2 m = map_block(M, blockIdx.x);
@@ -53,7 +56,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     SolveState* st = sl.st;
     const int j = step_of(sr) - sl.j0;
     if (threadIdx.x == 0) sdone = st->done;
-    const int s = sl.s, n = sl.n;
+    const int s = REC ? sl.s : 0, n = sl.n;
     const int i = m.y * NT + threadIdx.x;
     const bool in = i < n;
     const double* p = sl.p[(j + 1) & 1];
@@ -61,7 +64,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     double cpre[UPRE], zpre[UPRE];
 #pragma unroll
     for (int k = 0; k < UPRE; ++k) cpre[k] = (in && k < s) ? sl.C[(size_t)k * n + i] : 0.0;
-    const int zw = zr_width(st, sl.nz, j + 1);
+    const int zw = REC ? zr_width(st, sl.nz, j + 1) : 0;
 #pragma unroll
     for (int k = 0; k < UPRE; ++k) zpre[k] = (in && k < zw) ? sl.Z[(size_t)k * n + i] : 0.0;
     int nb;
@@ -261,9 +264,12 @@ hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t strea
     hipLaunchKernelGGL(k_b_init, map_grid(M), dim3(NT), 0, stream, slots, M);
     return hipGetLastError();
 }
-hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, hipStream_t stream) {
+hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, bool rec, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_update, map_grid(M), dim3(NT), 0, stream, slots, M, sr);
+    if (rec)
+        hipLaunchKernelGGL(k_b_update<true>, map_grid(M), dim3(NT), 0, stream, slots, M, sr);
+    else
+        hipLaunchKernelGGL(k_b_update<false>, map_grid(M), dim3(NT), 0, stream, slots, M, sr);
     return hipGetLastError();
 }
 hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, StepRef sr, hipStream_t stream) {

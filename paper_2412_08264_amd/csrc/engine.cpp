@@ -423,6 +423,8 @@ bl_status Batch::finish(int idx) {
 // sequence can be captured.
 bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipStream_t ls,
                               bool time_all) {
+    bool any_rec = false;
+    for (const Group& grp : groups) any_rec |= grp.rec && grp.tmap.ns > 0;
     for (int k = 0; k < nsteps; ++k) {
         const StepRef sr{d_ctr, k};
         const bool ktime = c->timing == 2 && (time_all || (!c->graphs && (step + k) % KT_SAMPLE == 0));
@@ -442,7 +444,7 @@ bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector
             if (grp.tmap.ns) HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, sr, ls));
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], ls));
         if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, sr, ls));
-        HIPCHK(launch_b_update(d_slots, pmap, sr, ls));
+        HIPCHK(launch_b_update(d_slots, pmap, sr, any_rec, ls));
         if (ktime) {
             HIPCHK(hipEventRecord(c->kev[ev + 2], ls));
             Timed t;

@@ -77,7 +77,7 @@ BL_TILE_EXTERN(2)
 BL_TILE_EXTERN(4)
 #undef BL_TILE_EXTERN
 hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t stream);
-hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, hipStream_t stream);
+hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, bool rec, hipStream_t stream);
 hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, StepRef sr, hipStream_t stream);
 hipError_t launch_b_finish(const Slot* slots, const BatchMap& M, hipStream_t stream);
 hipError_t launch_b_fold(const Slot* slots, const BatchMap& list, int which, StepRef sr, hipStream_t stream);
