@@ -179,7 +179,9 @@ def test_engine_mixes_operator_classes(B):
     """TV and filter solves in FP64 and mixed precision, each class at two tile heights, with
     and without recycle spaces, share one engine (one apply launch per (class, height,
     recycling) group, one update launch for all) and each equals its solo run bitwise; a 17th
-    group is refused while sixteen are admitted."""
+    group is refused while sixteen are admitted.  The shared update launch is the variant with
+    recycle-space registers while any recycled solve runs; a plain solve's solo run uses the
+    variant without them, so the bitwise match also covers the two variants' agreement."""
     base = [("tv", 36, 44, "fp64"), ("filters", 40, 36, "fp64"), ("filters", 32, 48, "mixed"),
             ("tv", 50, 30, "mixed"), ("tv", 64, 70, "fp64"), ("filters", 70, 66, "fp64"),
             ("filters", 66, 72, "mixed"), ("tv", 72, 64, "mixed")]
