@@ -716,7 +716,7 @@ bl_status bl_lower_solve(bl_ctx* c, const bl_problem* P, const double* theta, co
     Stencil S;
     TRY(make_stencil(c, P, theta, ws, S));
     const int n = P->h * P->w;
-    const int vb = vec_blocks(n);
+    const int vb = wide_blocks(n);   // records of the multi-dot pass (at most 1024)
     double* g = ws.vec(0);
     double* d = ws.vec(1);
     double* xt = ws.vec(2);

@@ -41,6 +41,7 @@ hipError_t launch_multidot(int n, const VecPairs& vp, double* part, hipStream_t 
 hipError_t launch_lincomb(int n, double c0, const double* x0, const VecComb& vc, double* out, hipStream_t stream);
 int red_blocks(int n);
 int vec_blocks(int n);
+int wide_blocks(int n);   // blocks of launch_multidot / launch_lincomb (records: one per block)
 hipError_t launch_finish_sum(const double* part, int nb, int nv, double* out, hipStream_t stream);
 hipError_t launch_dots_part(int n, int nv, const double* a, const double* b, double* part, hipStream_t stream);
 hipError_t launch_axpy_red(int n, double beta, double* y, const double* x, const double* part1, double s1,

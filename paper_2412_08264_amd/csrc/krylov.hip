@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(NT) k_lincomb(int n, double c0, const double* 
                                                 double* __restrict__ out) {
     for (int p = blockIdx.x * NT + threadIdx.x; p < n; p += gridDim.x * NT) {
         double acc = c0 * x0[p];
+#pragma unroll 8
         for (int i = 0; i < vc.k; ++i) acc += vc.c[i] * vc.v[i][p];
         out[p] = acc;
     }
@@ -89,6 +90,13 @@ int red_blocks(int n) { return (n + NT - 1) / NT; }
 // Blocks of the grid-stride vector kernels.
 int vec_blocks(int n) {
     const int b = (n + NT * 4 - 1) / (NT * 4);
+    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+// Blocks of the many-vector kernels (multi-dot, linear combination): one pixel per thread up to
+// 1024 blocks, so that a 256 x 256 image spreads over every compute unit.
+int wide_blocks(int n) {
+    const int b = red_blocks(n);
     return b < 1 ? 1 : (b > 1024 ? 1024 : b);
 }
 
@@ -107,11 +115,11 @@ hipError_t launch_axpy_red(int n, double beta, double* y, const double* x, const
     return hipGetLastError();
 }
 hipError_t launch_multidot(int n, const VecPairs& vp, double* part, hipStream_t stream) {
-    hipLaunchKernelGGL(k_multidot, dim3(vec_blocks(n)), dim3(NT), 0, stream, n, vp, part);
+    hipLaunchKernelGGL(k_multidot, dim3(wide_blocks(n)), dim3(NT), 0, stream, n, vp, part);
     return hipGetLastError();
 }
 hipError_t launch_lincomb(int n, double c0, const double* x0, const VecComb& vc, double* out, hipStream_t stream) {
-    hipLaunchKernelGGL(k_lincomb, dim3(vec_blocks(n)), dim3(NT), 0, stream, n, c0, x0, vc, out);
+    hipLaunchKernelGGL(k_lincomb, dim3(wide_blocks(n)), dim3(NT), 0, stream, n, c0, x0, vc, out);
     return hipGetLastError();
 }
 hipError_t launch_sub(int n, const double* a, const double* b, double* out, hipStream_t stream) {
