@@ -464,8 +464,11 @@ def test_sequence_tv32(B):
             assert rel(hg, ref[i]["hg"]) <= 1e-8
 
 
-def test_lower_solve(B):
-    wl, inst, prob, xh = tv_case(24, 24, seed=81)
+@pytest.mark.parametrize("h,w", [(24, 24), (40, 52)])
+def test_lower_solve(B, h, w):
+    """L-BFGS on the GPU against the oracle's: 576 pixels (three vector blocks, the last a
+    quarter full) and 2080 (nine, ragged)."""
+    wl, inst, prob, xh = tv_case(h, w, seed=81)
     th = inst["theta0"]
     y = prob.y.ravel()
     xo, info = lbfgs.lbfgs(lambda v: prob.phi(v, th), lambda v: prob.grad(v, th), y, gtol=1e-8)
