@@ -177,20 +177,24 @@ constexpr int SD_NT = 512;
 // column order: the pivot of column j is its diagonal after the updates from the kept
 // columns before it (= squared norm of column j after projection); j is dropped when
 // pivot_j <= tol^2 Gm_jj.  Writes Xinv (t x tk, ld ldx) with W Xinv = orthonormal basis of
-// the kept columns (rows of dropped columns zero) and *tk_out = tk.  Scratch: A (t*t), kept (t).
-__device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, double* A, int* kept, int* tk_out,
+// the kept columns (rows of dropped columns zero) and *tk_out = tk.  Scratch: A (t*t); X (t*t,
+// optional, in LDS) holds Xinv while its columns are solved, so that the solve's reads of
+// values it has just written stay on chip.  Gm's diagonal is staged in LDS once: the serial
+// pivot test of every column reads it.
+__device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, double* A, double* X, int* tk_out,
                           double* Xinv, int ldx) {
     __shared__ int s_tk, s_keep;
     __shared__ double s_d;
-    __shared__ int s_kept[256];
-    kept = s_kept;
+    __shared__ int kept[256];
+    __shared__ double gdiag[256];
     if (threadIdx.x == 0) s_tk = 0;
     for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) A[idx] = Gm[idx];
+    for (int j = threadIdx.x; j < t; j += blockDim.x) gdiag[j] = Gm[(size_t)j * t + j];
     __syncthreads();
     for (int j = 0; j < t; ++j) {
         if (threadIdx.x == 0) {
             const double piv = A[(size_t)j * t + j];
-            const double gjj = Gm[(size_t)j * t + j];
+            const double gjj = gdiag[j];
             s_keep = (gjj > 0.0 && piv > tol * tol * gjj) ? 1 : 0;
             s_d = s_keep ? sqrt(piv) : 1.0;
             if (s_keep) {
@@ -214,11 +218,13 @@ __device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, doub
         __syncthreads();
     }
     const int tk = s_tk;
-    for (int idx = threadIdx.x; idx < t * tk; idx += blockDim.x) Xinv[(size_t)(idx / t) * ldx + idx % t] = 0.0;
+    double* xb = X ? X : Xinv;
+    const int ldb = X ? t : ldx;
+    for (int idx = threadIdx.x; idx < t * tk; idx += blockDim.x) xb[(size_t)(idx / t) * ldb + idx % t] = 0.0;
     __syncthreads();
     // R (kept rows/cols) upper triangular: Rk[k][l] = A[kept_l * t + kept_k] (k < l), diag A[kept_k*t+kept_k]
     for (int mcol = threadIdx.x; mcol < tk; mcol += blockDim.x) {
-        double* x = Xinv + (size_t)mcol * ldx;
+        double* x = xb + (size_t)mcol * ldb;
         for (int k = mcol; k >= 0; --k) {
             const int ck = kept[k];
             double v = (k == mcol) ? 1.0 : 0.0;
@@ -227,14 +233,19 @@ __device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, doub
         }
     }
     __syncthreads();
+    if (X) {
+        for (int idx = threadIdx.x; idx < t * tk; idx += blockDim.x) Xinv[(size_t)(idx / t) * ldx + idx % t] = X[idx];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) *tk_out = tk;
 }
 
-// The working matrix lives in LDS when it fits (lds != 0), else in the global scratch R.
-__global__ void __launch_bounds__(SD_NT) k_chol_drop(int t, const double* Gm, double tol, double* R, int* kept,
-                                                     int* tk_out, double* Xinv, int ldx, int lds) {
+// The working matrix lives in LDS when it fits (lds >= 1), else in the global scratch R; with
+// lds = 2 the inverse factor is solved in LDS too.
+__global__ void __launch_bounds__(SD_NT) k_chol_drop(int t, const double* Gm, double tol, double* R, int* tk_out,
+                                                     double* Xinv, int ldx, int lds) {
     extern __shared__ double dyn_lds[];
-    chol_drop(t, Gm, tol, lds ? dyn_lds : R, kept, tk_out, Xinv, ldx);
+    chol_drop(t, Gm, tol, lds ? dyn_lds : R, lds == 2 ? dyn_lds + (size_t)t * t : nullptr, tk_out, Xinv, ldx);
 }
 
 // ------------------------------------------------------------------ symmetric eigensolver
@@ -1058,12 +1069,14 @@ static size_t lds_limit() {
 
 hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int* kept, int* tk, double* Xinv,
                             int ldx, hipStream_t stream) {
-    const size_t bytes = (size_t)t * t * sizeof(double);
-    const int lds = bytes <= lds_limit() ? 1 : 0;
-    if (lds && bytes > 65536)
+    (void)kept;   // the kept-column list lives in LDS
+    if (t < 0 || t > 256) return hipErrorInvalidValue;   // LDS lists of 256 columns
+    const size_t one = (size_t)t * t * sizeof(double);
+    const int lds = 2 * one <= lds_limit() ? 2 : (one <= lds_limit() ? 1 : 0);
+    const size_t bytes = lds * one;
+    if (bytes > 65536)
         (void)hipFuncSetAttribute((const void*)k_chol_drop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(SD_NT), lds ? bytes : 0, stream, t, Gm, tol, R, kept, tk, Xinv, ldx,
-                       lds);
+    hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(SD_NT), bytes, stream, t, Gm, tol, R, tk, Xinv, ldx, lds);
     return hipGetLastError();
 }
 
