@@ -790,23 +790,30 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
         __syncthreads();
         rankG = s_rank;
         const int kg = s_eff < rankG ? s_eff : rankG;
+        // v_H = S^T u / |S^T u| for the kg largest pairs (c-th largest: o = p - 1 - c), one
+        // element per thread, then a block sum per column for its norm
         for (int c = threadIdx.x; c < kg; c += blockDim.x) {
-            const int o = p - 1 - c;   // c-th largest
-            const double lam = lamv[o];
+            const double lam = lamv[p - 1 - c];
             mu[c] = lam > 0.0 ? sqrt(lam) : 0.0;
-            double* vh = VHs + (size_t)c * t;
-            double* x = Xs + (size_t)c * t;
-            double nrm = 0.0;
-            for (int i = 0; i < t; ++i) {
-                double v = 0.0;
-                for (int k = 0; k < p; ++k) v += S[(size_t)i * p + k] * Vv[(size_t)o * p + k];
-                vh[i] = v;
-                nrm += v * v;
+        }
+        for (int idx = threadIdx.x; idx < kg * t; idx += blockDim.x) {
+            const int c = idx / t, i = idx - c * t, o = p - 1 - c;
+            double v = 0.0;
+            for (int k = 0; k < p; ++k) v += S[(size_t)i * p + k] * Vv[(size_t)o * p + k];
+            VHs[(size_t)c * t + i] = v;
+        }
+        __syncthreads();
+        for (int c = 0; c < kg; ++c) {
+            double part = 0.0;
+            for (int i = threadIdx.x; i < t; i += blockDim.x) {
+                const double v = VHs[(size_t)c * t + i];
+                part += v * v;
             }
-            nrm = sqrt(nrm);
-            for (int i = 0; i < t; ++i) {
-                vh[i] /= nrm;
-                x[i] = vh[i];
+            const double nrm = sqrt(sd_sum(part, red));
+            for (int i = threadIdx.x; i < t; i += blockDim.x) {
+                const double v = VHs[(size_t)c * t + i] / nrm;
+                VHs[(size_t)c * t + i] = v;
+                Xs[(size_t)c * t + i] = v;
             }
         }
         __syncthreads();
@@ -879,23 +886,32 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
                 __syncthreads();
             }
             eig_range(nn, K, 0, nfill, lamv, BV, esc, ldsd);   // the nfill smallest Ritz pairs
-            // fill vectors x = N y = Q [0; y]: apply H_{p-1}, ..., H_0 to [0; y]
-            for (int f = threadIdx.x; f < nfill; f += blockDim.x) {
-                const int c = kg + f;
-                mu[c] = 0.0;
-                double* x = Xs + (size_t)c * t;
-                for (int i = 0; i < t; ++i) {
-                    x[i] = i < p ? 0.0 : BV[(size_t)f * nn + (i - p)];
-                    VHs[(size_t)c * t + i] = 0.0;
-                }
-                for (int j = p - 1; j >= 0; --j) {
-                    const double* v = Hv + (size_t)j * t;
-                    double d = 0.0;
-                    for (int i = j; i < t; ++i) d += v[i] * x[i];
-                    for (int i = j; i < t; ++i) x[i] -= s_beta[j] * d * v[i];
-                }
+            // fill vectors x = N y = Q [0; y]: apply H_{p-1}, ..., H_0 to [0; y] (element-parallel;
+            // the dot v_j . x_f of each reflection is one wave's sum, kept in pw[f])
+            for (int f = threadIdx.x; f < nfill; f += blockDim.x) mu[kg + f] = 0.0;
+            for (int idx = threadIdx.x; idx < nfill * t; idx += blockDim.x) {
+                const int f = idx / t, i = idx - f * t;
+                Xs[(size_t)(kg + f) * t + i] = i < p ? 0.0 : BV[(size_t)f * nn + (i - p)];
+                VHs[(size_t)(kg + f) * t + i] = 0.0;
             }
             __syncthreads();
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+            for (int j = p - 1; j >= 0; --j) {
+                const double* v = Hv + (size_t)j * t;
+                for (int f = wave; f < nfill; f += nwave) {
+                    const double* x = Xs + (size_t)(kg + f) * t;
+                    double a = 0.0;
+                    for (int i = j + lane; i < t; i += 64) a += v[i] * x[i];
+                    a = wave_sum(a);
+                    if (lane == 0) pw[f] = a;
+                }
+                __syncthreads();
+                for (int idx = threadIdx.x; idx < nfill * t; idx += blockDim.x) {
+                    const int f = idx / t, i = idx - f * t;
+                    if (i >= j) Xs[(size_t)(kg + f) * t + i] -= s_beta[j] * pw[f] * v[i];
+                }
+                __syncthreads();
+            }
         }
     }
     for (int c = threadIdx.x; c < s_eff; c += blockDim.x) {   // unit columns of X~
