@@ -988,7 +988,12 @@ __global__ void __launch_bounds__(SD_NT) k_ritz_select(int t, int s, int kind, i
         }
         __syncthreads();
     }
-    eig_range(t, A, 0, t, lam, Z, esc, ldsd);
+    // Ritz S / L need only the s_eff vectors at one end (Ritz values ascend with the
+    // eigenvalues); fewer vectors also let the eigensolver keep them in LDS.  Harmonic Ritz
+    // and size M take all t.
+    const int lo_e = (kind == 0 && size == 1) ? t - s_eff : 0;
+    const int hi_e = (kind == 0 && size == 0) ? s_eff : t;
+    eig_range(t, A, lo_e, hi_e, lam, Z, esc, ldsd);
     if (threadIdx.x == 0) {
         // values and their ascending order (insertion sort; t <= EIG_MAX)
         for (int k = 0; k < t; ++k) {
@@ -1007,11 +1012,13 @@ __global__ void __launch_bounds__(SD_NT) k_ritz_select(int t, int s, int kind, i
         const int lo = size == 0 ? s_eff : (size == 1 ? 0 : (s_eff + 1) / 2);
         for (int j = 0; j < lo; ++j) pick[j] = order[j];
         for (int j = lo; j < s_eff; ++j) pick[j] = order[t - 1 - (j - lo)];
+        if (hi_e - lo_e < t)   // one end only: by eigen index, within the computed range
+            for (int j = 0; j < s_eff; ++j) pick[j] = size == 0 ? j : t - 1 - j;
     }
     __syncthreads();
     // vectors: z (Ritz) or rho = L^{-T} z (harmonic Ritz), unit columns; one column per thread
     for (int j = threadIdx.x; j < s_eff; j += blockDim.x) {
-        const double* z = Z + (size_t)pick[j] * t;
+        const double* z = Z + (size_t)(pick[j] - lo_e) * t;
         double* x = Xs + (size_t)j * t;
         if (kind == 0) {
             for (int i = 0; i < t; ++i) x[i] = z[i];
