@@ -211,3 +211,45 @@ def test_zero_mean_projection():
     assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
     taps = a.reshape(prob.N, -1)[:, 1:]
     assert np.abs(taps.sum(axis=1)).max() < 1e-13
+
+
+def _lbfgs_min(prob, th, x0, gtol):
+    return lbfgs.lbfgs(lambda v: prob.phi(v, th), lambda v: prob.grad(v, th), x0, gtol=gtol)
+
+
+@pytest.mark.parametrize("kind,side", [("tv", 8), ("tv", 16), ("log", 8), ("log", 16)])
+def test_lbfgs_reaches_the_minimiser(kind, side):
+    """L-BFGS (Section 5: history 10, gradient-norm stop) returns a point within ||grad|| / lambda_min(H)
+    of the minimiser, the minimiser being found independently by Newton's method to ||grad|| < 1e-12."""
+    if kind == "tv":
+        wl, inst, prob = tv_case(side, side, seed=30 + side)
+        th = inst["theta0"]
+    else:
+        wl, inst, prob, th = foe_case(side, side, seed=40 + side)
+    gtol = 1e-8
+    x, info = _lbfgs_min(prob, th, prob.y.ravel(), gtol)
+    assert info["converged"] and info["iters"] > 0
+    gn = float(np.linalg.norm(prob.grad(x, th)))
+    assert gn <= gtol
+    xn = lbfgs.newton_polish(lambda v: prob.grad(v, th), lambda v: prob.dense_hessian(v, th), x, steps=6)
+    assert np.linalg.norm(prob.grad(xn, th)) < 1e-12
+    lam_min = float(np.linalg.eigvalsh(prob.dense_hessian(xn, th)).min())
+    assert lam_min > 0.0
+    assert np.linalg.norm(x - xn) <= 1.5 * gn / lam_min + 1e-14
+
+
+def test_lbfgs_quadratic_penalty_closed_form():
+    """phi = s^2: the lower-level minimiser is one linear solve; L-BFGS must land on it."""
+    wl, inst, prob, th = foe_case(penalty="quad", seed=12)
+    Am = ops.dense_correlation(prob.h, prob.w, prob.kernel)
+    lam, ks = prob.unpack(th)
+    Hm = 2 * Am.T @ Am + prob.eps * np.eye(prob.n)
+    for j in range(prob.N):
+        Km = ops.dense_correlation(prob.h, prob.w, ks[j])
+        Hm = Hm + 2 * lam[j] * Km.T @ Km
+    x_cf = np.linalg.solve(Hm, 2 * Am.T @ prob.y.ravel())
+    gtol = 1e-9
+    x, info = _lbfgs_min(prob, th, prob.y.ravel(), gtol)
+    assert info["converged"]
+    lam_min = float(np.linalg.eigvalsh(Hm).min())
+    assert np.linalg.norm(x - x_cf) <= 1.5 * gtol / lam_min

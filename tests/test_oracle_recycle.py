@@ -149,3 +149,22 @@ def test_recycled_sequence_reaches_same_solution_as_plain():
         kappa = np.linalg.cond(Hd)
         for r in (a, b):
             assert np.linalg.norm(r["w"] - w) <= kappa * 1e-12 * 10 * np.linalg.norm(w)
+
+
+@pytest.mark.parametrize("p,t,s", [(30, 12, 5), (12, 12, 12), (400, 20, 7)])
+def test_rgen_large_picks_largest_quotient_singular_values(p, t, s):
+    """p >= t (filter regulariser): RGen-L keeps the s largest generalized singular values of (G, M),
+    i.e. the s largest singular values of G M^{-1} (eq. gritz-decomp); its right vectors X span
+    M^{-1} V_top and its left vectors V_H span V_top, V_top the matching right singular vectors."""
+    rng = np.random.default_rng(p + 3 * t + s)
+    G = rng.standard_normal((p, t))
+    M = spd(t, 60.0, p + t)
+    sel = recycle.select_rgen_large(G, M, s)
+    S = G @ np.linalg.inv(M)
+    _, sig, Vt = np.linalg.svd(S)
+    assert sel["rank_G"] == t
+    assert np.all(np.diff(sel["mu"]) <= 0.0)
+    assert np.abs(sel["mu"] - sig[:s]).max() <= 1e-10 * sig[0]
+    Vtop = Vt[:s].T
+    assert recycle.principal_angles(sel["V_H"], Vtop).max() < 1e-8
+    assert recycle.principal_angles(sel["X"], np.linalg.solve(M, Vtop)).max() < 1e-8
