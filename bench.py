@@ -914,7 +914,7 @@ def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=64):
                                "avg_us": round(a_us, 2), "algorithmic_bytes": a_bytes,
                                "GBps": round(a_bytes / (a_us * 1e3), 1),
                                "frac": round(a_bytes / (a_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[1])},
-                     "update": {"kernel": f"k_b_update<{'true' if sc else 'false'}>", "avg_us": round(u_us, 2), "algorithmic_bytes": u_bytes,
+                     "update": {"kernel": f"k_b_update<{'true, false' if sc else 'false, false'}>", "avg_us": round(u_us, 2), "algorithmic_bytes": u_bytes,
                                 "GBps": round(u_bytes / (u_us * 1e3), 1),
                                 "frac": round(u_bytes / (u_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[3])}}
     S.close()

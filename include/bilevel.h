@@ -144,6 +144,17 @@ int bl_num_params(const bl_problem* P);
  * stored-basis capacity v_cap (t_max = s_max + v_cap columns of refresh scratch). */
 size_t bl_workspace_bytes(const bl_problem* P, int s_max, int v_cap);
 
+/* Recycle storage of one training sample (the U, C = H U of Section 2.2.2 with Z, mu and the
+ * stored basis V of Section 3.1) as one caller-owned device buffer: bl_recycle_bytes gives its
+ * size for capacities s_max (0..64) and v_cap (s_max + v_cap <= 256), 0 for an invalid shape;
+ * bl_recycle_init carves base (256-byte aligned, at least that many bytes) into U, C, Z
+ * (n x s_max each), mu (s_max doubles) and V (n x v_cap; NULL when v_cap = 0), in that order,
+ * each array starting on a 256-byte boundary, and sets s_cur = v_cur = 0.  Host-only: no device
+ * access, the buffer's contents are not touched.  BL_E_ARG (null pointer), BL_E_SHAPE (bad
+ * capacities or problem), BL_E_WORKSPACE (buffer too small or misaligned). */
+size_t bl_recycle_bytes(const bl_problem* P, int s_max, int v_cap);
+bl_status bl_recycle_init(const bl_problem* P, int s_max, int v_cap, void* base, size_t bytes, bl_recycle* rs);
+
 /* Measurement y = A x + noise * e (problem data; not on the timed path). */
 bl_status bl_forward(bl_ctx* ctx, const bl_problem* P, const double* x, const double* e, double noise,
                      double* y, void* ws, size_t ws_bytes);
@@ -308,15 +319,31 @@ bl_status bl_hessian_solve_batched(bl_ctx* ctx, int nprob, const bl_problem* P, 
 bl_status bl_tile_rows_set(const bl_problem* P, int rows);
 /* The tile height solves of P use now (table entry or default); 0 for an invalid problem. */
 int bl_tile_rows(const bl_problem* P);
-/* Autotuner: time `iters` iterations of a recycled-CG solve of P at (theta_host, xhat) with
- * s (0..64) recycle columns at each tile height, store the fastest in the table and return
- * it in *best_rows; us_per_iter[0..2] (may be NULL) get the mean microseconds per iteration
- * at 8, 16 and 32 rows.  The recycle columns are zero, which leaves the arithmetic that of
- * plain CG while every projection is still read, and the stop test is disabled, so every
- * height runs exactly `iters` (1..100000) iterations.  Allocates and frees its own device
- * memory; synchronous on the context's stream. */
-bl_status bl_autotune_tiles(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat, int s,
-                            int iters, double* us_per_iter, int* best_rows);
+/* Scratch of bl_autotune for P with s (0..64) recycle columns; 0 for an invalid shape. */
+size_t bl_autotune_workspace_bytes(const bl_problem* P, int s);
+/* Tile-height autotuner with a persistent cache.
+ *   cache_path != NULL and the file holds an entry for P's operator class and size class: the
+ *     stored height goes into the table and *best_rows; nothing is timed, no device work,
+ *     theta_host, xhat, iters and ws may be NULL / 0; us_per_iter (may be NULL) gets zeros.
+ *   otherwise: times `iters` (1..100000) iterations of a recycled-CG solve of P at
+ *     (theta_host, xhat) with s recycle columns at each height (8, 16, 32 rows), stores the
+ *     fastest in the table, returns it in *best_rows and the mean microseconds per iteration in
+ *     us_per_iter[0..2]; with cache_path the entry is then added to (or replaced in) the file,
+ *     which is rewritten whole through a temporary file next to it and a rename.  The recycle
+ *     columns are zero (the arithmetic of plain CG with every projection still read) and the
+ *     stop test is off, so each height runs exactly `iters` iterations.  Scratch: the caller's
+ *     ws of bl_autotune_workspace_bytes(P, s) bytes (256-byte aligned); synchronous on the
+ *     context's stream.
+ * Cache file: text, one entry per line "reg radius n_filters filter_size prec log2n rows us8
+ * us16 us32", '#' lines are comments.  A file that exists but does not parse, or cannot be
+ * written, gives BL_E_ARG (bl_last_error names the line) and is left unchanged. */
+bl_status bl_autotune(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat, int s,
+                      int iters, const char* cache_path, void* ws, size_t ws_bytes, int* best_rows,
+                      double* us_per_iter);
+/* Load every entry of a tile cache file written by bl_autotune into the table (host only, no
+ * context, no device work); *entries (may be NULL) gets their number.  BL_E_ARG when the file
+ * is missing or does not parse; then the table is unchanged. */
+bl_status bl_tile_cache_load(const char* cache_path, int* entries);
 
 #ifdef __cplusplus
 }

@@ -98,8 +98,12 @@ _SIGS = {
                                            _P(bl_stats)]),
     "bl_tile_rows_set": (C.c_int, [_P(bl_problem), C.c_int]),
     "bl_tile_rows": (C.c_int, [_P(bl_problem)]),
-    "bl_autotune_tiles": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, C.c_int, C.c_int, _P(C.c_double),
-                                    _P(C.c_int)]),
+    "bl_autotune_workspace_bytes": (C.c_size_t, [_P(bl_problem), C.c_int]),
+    "bl_autotune": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, C.c_int, C.c_int, C.c_char_p, _vp,
+                              C.c_size_t, _P(C.c_int), _P(C.c_double)]),
+    "bl_tile_cache_load": (C.c_int, [C.c_char_p, _P(C.c_int)]),
+    "bl_recycle_bytes": (C.c_size_t, [_P(bl_problem), C.c_int, C.c_int]),
+    "bl_recycle_init": (C.c_int, [_P(bl_problem), C.c_int, C.c_int, _vp, C.c_size_t, _P(bl_recycle)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -183,6 +187,15 @@ def bl_tile_rows(P: bl_problem) -> int:
     return int(lib.bl_tile_rows(C.byref(P)))
 
 
+def bl_tile_cache_load(path: str) -> int:
+    """Entries of a tile cache file (written by bl_autotune) into the tile table; their count."""
+    k = C.c_int(0)
+    st = lib.bl_tile_cache_load(path.encode(), C.byref(k))
+    if st != BL_OK:
+        raise BLError(st, f"bl_tile_cache_load({path})")
+    return k.value
+
+
 class Context:
     """Context + workspace for problems up to the given shapes; every call names its problem
     and recycle storage explicitly (torch tensors on one device)."""
@@ -231,13 +244,22 @@ class Context:
         lib.bl_kernel_times(self.ctx, out, 1 if reset else 0)
         return tuple(out[:])
 
-    def autotune_tiles(self, P, theta, xhat, s: int, iters: int = 100):
-        """Time every tile height on a solve of P at (theta, xhat) and keep the fastest for P's
-        operator class and size class.  Returns (rows, microseconds per iteration at 8/16/32)."""
+    def autotune_tiles(self, P, theta, xhat, s: int, iters: int = 100, cache_path: str | None = None):
+        """bl_autotune: time every tile height on a solve of P at (theta, xhat) and keep the fastest
+        for P's operator class and size class (or take the stored height from cache_path, and store
+        a new result there).  Returns (rows, microseconds per iteration at 8/16/32; zeros when the
+        height came from the cache)."""
         us = (C.c_double * 3)()
         best = C.c_int()
-        _check(self.ctx, lib.bl_autotune_tiles(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), int(s), int(iters),
-                                               us, C.byref(best)), "bl_autotune_tiles")
+        nbytes = int(lib.bl_autotune_workspace_bytes(C.byref(P), int(s)))
+        if nbytes == 0:
+            raise BLError(BL_E_ARG, "bl_autotune_workspace_bytes rejected the shape")
+        with self.torch.cuda.device(self.device):
+            ws, wsp = _aligned_workspace(nbytes, self.device)
+        path = cache_path.encode() if cache_path is not None else None
+        _check(self.ctx, lib.bl_autotune(self.ctx, C.byref(P), _theta(theta), _ptr(xhat), int(s), int(iters), path,
+                                         wsp, nbytes, C.byref(best), us), "bl_autotune")
+        del ws
         return best.value, tuple(us[:])
 
     # -- calls
@@ -309,7 +331,7 @@ class Session(Context):
         self.P = P
         self.n = P.h * P.w
         self.p = bl_num_params(P)
-        self.rec = Recycle(self.n, s_max, v_cap, self.device)
+        self.rec = Recycle(self.n, s_max, v_cap, self.device, P)
         self.U, self.Cm, self.Z, self.mu, self.V = self.rec.U, self.rec.Cm, self.rec.Z, self.rec.mu, self.rec.V
         self.rs = self.rec.rs
 
@@ -341,22 +363,38 @@ class Session(Context):
 
 # --------------------------------------------------------------------------- recycle storage
 class Recycle:
-    """Device storage of one sample's recycle state: U, C, Z (s_max x n), mu, V (v_cap x n)."""
+    """Device storage of one sample's recycle state, one buffer of bl_recycle_bytes() carved by
+    bl_recycle_init: U, C, Z (s_max x n), mu, V (v_cap x n), exposed as tensor views."""
 
-    def __init__(self, n: int, s_max: int, v_cap: int, device):
+    def __init__(self, n: int, s_max: int, v_cap: int, device, P: bl_problem | None = None):
         import torch
-        f64 = dict(dtype=torch.float64, device=device)
+        if P is None:   # the layout depends on n only: any valid problem of n pixels
+            if n % 2:
+                raise ValueError("Recycle: pass the problem P for an odd pixel count")
+            P = bl_problem(2, n // 2, 0, 1.0, BL_REG_TV, 0, 0, 0.0, BL_PEN_LOG, BL_PREC_FP64)
+        elif P.h * P.w != n:
+            raise ValueError("Recycle: n differs from P.h * P.w")
         self.n = n
-        self.U = torch.zeros((max(s_max, 1), n), **f64)
-        self.Cm = torch.zeros((max(s_max, 1), n), **f64)
-        self.Z = torch.zeros((max(s_max, 1), n), **f64)
-        self.mu = torch.zeros(max(s_max, 1), **f64)
-        self.V = torch.zeros((max(v_cap, 1), n), **f64)
-        self.rs = bl_recycle(self.U.data_ptr(), self.Cm.data_ptr(), self.Z.data_ptr(), self.mu.data_ptr(),
-                             self.V.data_ptr(), s_max, 0, v_cap, 0)
+        nbytes = int(lib.bl_recycle_bytes(C.byref(P), int(s_max), int(v_cap)))
+        if nbytes == 0:
+            raise BLError(BL_E_SHAPE, f"bl_recycle_bytes rejected s_max={s_max}, v_cap={v_cap}")
+        self.buf, base = _aligned_workspace(nbytes, device)
+        self.rs = bl_recycle()
+        st = lib.bl_recycle_init(C.byref(P), int(s_max), int(v_cap), base, nbytes, C.byref(self.rs))
+        if st != BL_OK:
+            raise BLError(st, "bl_recycle_init")
+        self.buf.zero_()
+        off = lambda p: (p or base) - self.buf.data_ptr()
+        view = lambda p, rows: self.buf[off(p):off(p) + 8 * rows * n].view(torch.float64).view(rows, n)
+        self.U = view(self.rs.U, s_max)
+        self.Cm = view(self.rs.C, s_max)
+        self.Z = view(self.rs.Z, s_max)
+        self.mu = self.buf[off(self.rs.mu):off(self.rs.mu) + 8 * s_max].view(torch.float64)
+        self.V = view(self.rs.V, v_cap) if v_cap > 0 else self.buf[:0].view(torch.float64).view(0, n)
+        self._nbytes = nbytes
 
     def nbytes(self) -> int:
-        return sum(t.numel() * t.element_size() for t in (self.U, self.Cm, self.Z, self.mu, self.V))
+        return self._nbytes
 
 
 def solve_opts(tol=1e-10, stop: str = "resid", hg_tol: float = 0.0, max_iter: int = 20000, check_every: int = 1,

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -27,7 +28,9 @@ struct Layout {
     int n, p, s_max, v_cap, t_max, nf;
 };
 
-Layout layout(const bl_problem* P, int s_max, int v_cap) {
+// solve_only: the part a Hessian solve uses (state, records, vectors, filter maps and taps);
+// the refresh and lower-level scratch after it has size zero.
+Layout layout(const bl_problem* P, int s_max, int v_cap, bool solve_only = false) {
     Layout L{};
     L.n = P->h * P->w;
     L.p = nparams(P);
@@ -52,6 +55,11 @@ Layout layout(const bl_problem* P, int s_max, int v_cap) {
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
     L.taps = o;     o += al(TAPS_BYTES);
+    if (solve_only) {
+        L.W0 = L.W1 = L.Ut = L.Ct = L.small = L.lb = o;
+        L.total = o;
+        return L;
+    }
     L.W0 = o;       o += al((size_t)L.n * L.t_max * sizeof(double));
     L.W1 = o;       o += al((size_t)L.n * L.t_max * sizeof(double));
     L.Ut = o;       o += al((size_t)L.n * std::max(s_max, 1) * sizeof(double));
@@ -283,18 +291,10 @@ bl_status bl_lower_grad(bl_ctx* c, const bl_problem* P, const double* theta, con
 }
 
 // ---------------------------------------------------------------------------- Hessian solve
-// One solve is a one-slot batch whose scratch lives in the call's workspace.
-bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, const double* g,
-                           double* w, bl_recycle* rs, const bl_solve_opts* o, void* wsp, size_t ws_bytes,
-                           bl_stats* out) {
-    if (!c) return BL_E_ARG;
-    TRY(check_problem(c, P));
-    if (!xhat || !g || !w) return c->err = "null argument", BL_E_ARG;
-    TRY(check_solve_opts(c, o));
-    const int s_max = rs ? rs->s_max : 0, v_cap = rs ? rs->v_cap : 0;
-    if (s_max < 0 || s_max > S_MAX || v_cap < 0) return c->err = "s_max outside [0, 64] or v_cap < 0", BL_E_SHAPE;
-    WS ws;
-    TRY(check_ws(c, layout(P, s_max, v_cap), wsp, ws_bytes, ws));
+namespace {
+// One solve is a one-slot batch whose scratch lives in ws (checked by the caller).
+bl_status solve_in(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, const double* g,
+                   double* w, bl_recycle* rs, const bl_solve_opts* o, const WS& ws, bl_stats* out) {
     mark(c, 0);
     Batch B;
     TRY(B.init(c, 1, ws.slots(), ws.hdr(), ws.ctr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
@@ -328,6 +328,28 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
         out->ms[3] = elapsed(c, 0, 2);
     }
     return (bl_status)st.status;
+}
+
+bl_status solve_args(bl_ctx* c, const bl_problem* P, const double* xhat, const double* g, double* w,
+                     const bl_recycle* rs, const bl_solve_opts* o) {
+    if (!c) return BL_E_ARG;
+    TRY(check_problem(c, P));
+    if (!xhat || !g || !w) return c->err = "null argument", BL_E_ARG;
+    TRY(check_solve_opts(c, o));
+    const int s_max = rs ? rs->s_max : 0, v_cap = rs ? rs->v_cap : 0;
+    if (s_max < 0 || s_max > S_MAX || v_cap < 0) return c->err = "s_max outside [0, 64] or v_cap < 0", BL_E_SHAPE;
+    return BL_OK;
+}
+
+}  // namespace
+
+bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, const double* g,
+                           double* w, bl_recycle* rs, const bl_solve_opts* o, void* wsp, size_t ws_bytes,
+                           bl_stats* out) {
+    TRY(solve_args(c, P, xhat, g, w, rs, o));
+    WS ws;
+    TRY(check_ws(c, layout(P, rs ? rs->s_max : 0, rs ? rs->v_cap : 0), wsp, ws_bytes, ws));
+    return solve_in(c, P, theta, xhat, g, w, rs, o, ws, out);
 }
 
 // ------------------------------------------------------------------------------ RMINRES
@@ -459,36 +481,44 @@ int bl_tile_rows(const bl_problem* P) {
     return tile_rows(P);
 }
 
+// Autotuner scratch inside the caller's workspace: the solve workspace (s recycle columns, no
+// stored basis), then g, w, and the zero recycle columns U, C, Z with mu.
+namespace {
+struct TuneLayout {
+    size_t solve, g, w, u, c, z, mu, total;
+};
+TuneLayout tune_layout(const bl_problem* P, int s) {
+    TuneLayout T{};
+    const size_t n = (size_t)P->h * P->w, sc = (size_t)std::max(s, 1);
+    T.solve = bl_workspace_bytes(P, s, 0);
+    T.g = al(T.solve);
+    T.w = T.g + al(n * 8);
+    T.u = T.w + al(n * 8);
+    T.c = T.u + al(n * sc * 8);
+    T.z = T.c + al(n * sc * 8);
+    T.mu = T.z + al(n * sc * 8);
+    T.total = T.mu + al(sc * 8);
+    return T;
+}
+
 // Each height runs a short warm-up solve, then `iters` timed iterations of a solve whose
 // recycle columns are zero (C^T q = 0, C e = 0: plain CG arithmetic, recycled memory traffic)
 // with the stop test disabled (tol = 0).
-bl_status bl_autotune_tiles(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, int s,
-                            int iters, double* us_per_iter, int* best_rows) {
-    if (!c) return BL_E_ARG;
-    TRY(check_problem(c, P));
-    if (!theta || !xhat || !best_rows) return c->err = "null argument", BL_E_ARG;
-    if (s < 0 || s > S_MAX) return c->err = "s outside [0, 64]", BL_E_SHAPE;
-    if (iters < 1 || iters > 100000) return c->err = "iters outside [1, 100000]", BL_E_ARG;
+bl_status autotune_time(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, int s, int iters,
+                        char* mem, const TuneLayout& T, double us[3]) {
     const size_t n = (size_t)P->h * P->w, sc = (size_t)std::max(s, 1);
-    const size_t wsb = bl_workspace_bytes(P, s, 0);
-    const size_t o_g = al(wsb), o_w = o_g + al(n * 8), o_u = o_w + al(n * 8), o_c = o_u + al(n * sc * 8),
-                 o_z = o_c + al(n * sc * 8), o_mu = o_z + al(n * sc * 8), total = o_mu + al(sc * 8);
-    char* mem = nullptr;
-    HIPCHK(hipMalloc(&mem, total));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    bl_status rc = BL_OK;
-    double us[3] = {0.0, 0.0, 0.0};
     const int heights[3] = {QTY, 2 * QTY, 4 * QTY};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     auto body = [&]() -> bl_status {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        HIPCHK(hipMemsetAsync(mem + o_u, 0, o_mu + al(sc * 8) - o_u, c->stream));
-        HIPCHK(hipMemcpyAsync(mem + o_g, xhat, n * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemsetAsync(mem + T.u, 0, T.mu + al(sc * 8) - T.u, c->stream));
+        HIPCHK(hipMemcpyAsync(mem + T.g, xhat, n * 8, hipMemcpyDeviceToDevice, c->stream));
         bl_recycle rs{};
-        rs.U = (double*)(mem + o_u);
-        rs.C = (double*)(mem + o_c);
-        rs.Z = (double*)(mem + o_z);
-        rs.mu = (double*)(mem + o_mu);
+        rs.U = (double*)(mem + T.u);
+        rs.C = (double*)(mem + T.c);
+        rs.Z = (double*)(mem + T.z);
+        rs.mu = (double*)(mem + T.mu);
         rs.s_max = s;
         rs.s_cur = s;
         bl_solve_opts o{};
@@ -500,11 +530,11 @@ bl_status bl_autotune_tiles(bl_ctx* c, const bl_problem* P, const double* theta,
             c->force_rows = heights[k];
             for (int pass = 0; pass < 2; ++pass) {
                 o.max_iter = pass == 0 ? std::min(iters, 16) : iters;
-                HIPCHK(hipMemsetAsync(mem + o_w, 0, n * 8, c->stream));
+                HIPCHK(hipMemsetAsync(mem + T.w, 0, n * 8, c->stream));
                 if (pass == 1) HIPCHK(hipEventRecord(e0, c->stream));
                 bl_stats st{};
-                const bl_status r = bl_hessian_solve(c, P, theta, xhat, (const double*)(mem + o_g),
-                                                     (double*)(mem + o_w), s ? &rs : nullptr, &o, mem, wsb, &st);
+                const bl_status r = bl_hessian_solve(c, P, theta, xhat, (const double*)(mem + T.g),
+                                                     (double*)(mem + T.w), s ? &rs : nullptr, &o, mem, T.solve, &st);
                 if (r == BL_E_HIP || r == BL_E_ARG || r == BL_E_SHAPE || r == BL_E_WORKSPACE) return r;
                 if (pass == 1) {
                     HIPCHK(hipEventRecord(e1, c->stream));
@@ -517,13 +547,48 @@ bl_status bl_autotune_tiles(bl_ctx* c, const bl_problem* P, const double* theta,
         }
         return BL_OK;
     };
-    rc = body();
+    const bl_status rc = body();
     c->force_rows = 0;
     (void)hipStreamSynchronize(c->stream);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(mem);
-    if (rc != BL_OK) return rc;
+    return rc;
+}
+}  // namespace
+
+size_t bl_autotune_workspace_bytes(const bl_problem* P, int s) {
+    bl_ctx tmp;
+    if (!P || check_problem(&tmp, P) != BL_OK || s < 0 || s > S_MAX) return 0;
+    return tune_layout(P, s).total;
+}
+
+bl_status bl_autotune(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, int s, int iters,
+                      const char* cache_path, void* wsp, size_t ws_bytes, int* best_rows, double* us_per_iter) {
+    if (!c) return BL_E_ARG;
+    TRY(check_problem(c, P));
+    if (!best_rows) return c->err = "null best_rows", BL_E_ARG;
+    if (s < 0 || s > S_MAX) return c->err = "s outside [0, 64]", BL_E_SHAPE;
+    if (us_per_iter)
+        for (int k = 0; k < 3; ++k) us_per_iter[k] = 0.0;
+    if (cache_path) {
+        int rows = 0;
+        bool found = false;
+        if (!tile_cache_lookup(cache_path, P, rows, found, c->err)) return BL_E_ARG;
+        if (found) {   // a stored result: no timing, no device work
+            set_tile_rows(P, rows);
+            *best_rows = rows;
+            return BL_OK;
+        }
+    }
+    if (!theta || !xhat) return c->err = "null theta or xhat", BL_E_ARG;
+    if (iters < 1 || iters > 100000) return c->err = "iters outside [1, 100000]", BL_E_ARG;
+    const TuneLayout T = tune_layout(P, s);
+    if (!wsp) return c->err = "null workspace", BL_E_WORKSPACE;
+    if (ws_bytes < T.total) return c->err = "workspace smaller than bl_autotune_workspace_bytes()", BL_E_WORKSPACE;
+    if ((uintptr_t)wsp % ALIGN) return c->err = "workspace must be 256-byte aligned", BL_E_WORKSPACE;
+    double us[3] = {0.0, 0.0, 0.0};
+    TRY(autotune_time(c, P, theta, xhat, s, iters, (char*)wsp, T, us));
+    const int heights[3] = {QTY, 2 * QTY, 4 * QTY};
     int best = 0;
     for (int k = 1; k < 3; ++k)
         if (us[k] < us[best]) best = k;
@@ -531,6 +596,61 @@ bl_status bl_autotune_tiles(bl_ctx* c, const bl_problem* P, const double* theta,
     *best_rows = heights[best];
     if (us_per_iter)
         for (int k = 0; k < 3; ++k) us_per_iter[k] = us[k];
+    if (cache_path && !tile_cache_store(cache_path, P, heights[best], us, c->err)) return BL_E_ARG;
+    return BL_OK;
+}
+
+bl_status bl_tile_cache_load(const char* cache_path, int* entries) {
+    if (!cache_path) return BL_E_ARG;
+    int k = 0;
+    std::string err;
+    if (!tile_cache_load_all(cache_path, k, err)) return BL_E_ARG;
+    if (entries) *entries = k;
+    return BL_OK;
+}
+
+// ---------------------------------------------------------------------------- recycle storage
+namespace {
+struct RecLayout {
+    size_t U, C, Z, mu, V, total;
+};
+RecLayout rec_layout(const bl_problem* P, int s_max, int v_cap) {
+    const size_t n = (size_t)P->h * P->w;
+    RecLayout R{};
+    R.U = 0;
+    R.C = al(n * s_max * 8);
+    R.Z = R.C + al(n * s_max * 8);
+    R.mu = R.Z + al(n * s_max * 8);
+    R.V = R.mu + al((size_t)s_max * 8);
+    R.total = R.V + al(n * v_cap * 8);
+    return R;
+}
+bool rec_shape_ok(const bl_problem* P, int s_max, int v_cap) {
+    bl_ctx tmp;
+    return P && check_problem(&tmp, P) == BL_OK && s_max >= 0 && s_max <= S_MAX && v_cap >= 0 && s_max + v_cap <= 256;
+}
+}  // namespace
+
+size_t bl_recycle_bytes(const bl_problem* P, int s_max, int v_cap) {
+    return rec_shape_ok(P, s_max, v_cap) ? rec_layout(P, s_max, v_cap).total : 0;
+}
+
+bl_status bl_recycle_init(const bl_problem* P, int s_max, int v_cap, void* base, size_t bytes, bl_recycle* rs) {
+    if (!rs || !base) return BL_E_ARG;
+    if (!rec_shape_ok(P, s_max, v_cap)) return BL_E_SHAPE;
+    const RecLayout R = rec_layout(P, s_max, v_cap);
+    if (bytes < R.total) return BL_E_WORKSPACE;
+    if ((uintptr_t)base % ALIGN) return BL_E_WORKSPACE;
+    char* b = (char*)base;
+    rs->U = (double*)(b + R.U);
+    rs->C = (double*)(b + R.C);
+    rs->Z = (double*)(b + R.Z);
+    rs->mu = (double*)(b + R.mu);
+    rs->V = v_cap > 0 ? (double*)(b + R.V) : nullptr;
+    rs->s_max = s_max;
+    rs->s_cur = 0;
+    rs->v_cap = v_cap;
+    rs->v_cur = 0;
     return BL_OK;
 }
 

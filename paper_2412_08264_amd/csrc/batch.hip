@@ -45,7 +45,9 @@ __global__ void __launch_bounds__(NT) k_b_init(const Slot* __restrict__ slots, B
 // the test of iteration j + 1 evaluates the error estimate).
 // REC: some slot of the launch has a recycle space; without one (plain CG only) no registers
 // hold columns of C or Z.  A slot with s = 0 computes the same values either way.
-template <bool REC>
+// WIDE: the records are reduced with all of a thread's loads in flight at once (a single
+// memory round trip; costs registers): for launches of few blocks, where latency decides.
+template <bool REC, bool WIDE>
 __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, StepRef sr) {
     constexpr int UPRE = REC ? 24 : 1;
     __shared__ double tot[NT];
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     const double rho = uni(st->rho2[j & 1]);
     const bool acc_mine = m.y == 0 && (int)threadIdx.x < s;
     const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
-    reduce_partials(rec, nb, 1 + s, tot);
+    reduce_partials<WIDE ? 32 : 8>(rec, nb, 1 + s, tot);
     if (sdone) return;
     const double sigma = tot[0];
     if (!(sigma > 0.0)) {
@@ -266,10 +268,14 @@ hipError_t launch_b_init(const Slot* slots, const BatchMap& M, hipStream_t strea
 }
 hipError_t launch_b_update(const Slot* slots, const BatchMap& M, StepRef sr, bool rec, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
-    if (rec)
-        hipLaunchKernelGGL(k_b_update<true>, map_grid(M), dim3(NT), 0, stream, slots, M, sr);
+    // a grid of at most 16 blocks per compute unit waits on memory latency, not bandwidth
+    const bool wide = rec && map_grid(M).x <= 16 * 256;
+    if (wide)
+        hipLaunchKernelGGL((k_b_update<true, true>), map_grid(M), dim3(NT), 0, stream, slots, M, sr);
+    else if (rec)
+        hipLaunchKernelGGL((k_b_update<true, false>), map_grid(M), dim3(NT), 0, stream, slots, M, sr);
     else
-        hipLaunchKernelGGL(k_b_update<false>, map_grid(M), dim3(NT), 0, stream, slots, M, sr);
+        hipLaunchKernelGGL((k_b_update<false, false>), map_grid(M), dim3(NT), 0, stream, slots, M, sr);
     return hipGetLastError();
 }
 hipError_t launch_b_replace(const Slot* slots, const BatchMap& M, int periodic, StepRef sr, hipStream_t stream) {

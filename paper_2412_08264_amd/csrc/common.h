@@ -201,13 +201,16 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
 
 // out[k] = sum over blocks of part[b*nv + k], k < nv (nv <= NT), into LDS `out` (all threads).
 // G threads share value k (G the largest power of two with G * nv <= NT): thread (k, j) sums
-// blocks j, j+G, ... (eight loads in flight), then the G partial sums are combined by a group
-// sum (within a wave; across the waves of a group in wave order).  The order depends
-// only on (nblocks, nv), so every block that reduces the same records obtains bit-identical
-// values, and no thread adds more than nblocks / G + log2(G) terms in sequence.
+// blocks j, j+G, ..., all of its first U loads issued before the first addition (one memory
+// round trip for up to U * G records: the records come from other compute units' caches, so
+// each dependent round costs a full miss; U = 32 covers the 256 tiles of a 256 x 256 image
+// with a 20-column recycle record, at the price of 64 registers), then the G partial sums are
+// combined by a group sum (within a wave; across the waves of a group in wave order).  The
+// order depends only on (U, nblocks, nv), so every block that reduces the same records with
+// the same U obtains bit-identical values.
+template <int U = 8>
 __device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv, double* out) {
     __shared__ double wsum[NWAVE];
-    constexpr int U = 8;
     int G = 1;
     while (G * 2 * nv <= NT) G *= 2;
     const int k = threadIdx.x / G, j = threadIdx.x & (G - 1);
@@ -215,15 +218,18 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
     if (k < nv) {
         double a[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = 0.0;
-        int b = j;
-        for (; b + (U - 1) * G < nblocks; b += U * G) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) a[u] += part[(size_t)(b + u * G) * nv + k];
+        for (int u = 0; u < U; ++u) {
+            const int b = j + u * G;
+            a[u] = b < nblocks ? part[(size_t)b * nv + k] : 0.0;
         }
+        // beyond U * G records (unfolded large record arrays): further rounds of 8 loads
+        for (int b = j + U * G; b < nblocks; b += 8 * G) {
+            double c[8];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (b + u * G < nblocks) a[u] += part[(size_t)(b + u * G) * nv + k];
+            for (int u = 0; u < 8; ++u) c[u] = b + u * G < nblocks ? part[(size_t)(b + u * G) * nv + k] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += c[u];
+        }
 #pragma unroll
         for (int w2 = U / 2; w2 > 0; w2 >>= 1)
 #pragma unroll

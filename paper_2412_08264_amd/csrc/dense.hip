@@ -621,15 +621,16 @@ __device__ void solve_cols(int t, const double* L, double* X, int ncols, size_t 
 // mu (s_eff), info = {s_eff, rank_G, status}.  Scratch: sc (gsvd_scratch_doubles).
 // Route: Cholesky M = L L^T;  S = G M^{-1};
 //   p >= t: eigen of S^T S = V_H diag(mu^2) V_H^T; right vectors X ~ M^{-1} V_H;
-//   p <  t: eigen of S S^T (p x p) gives mu and V_H = S^T u / mu; null(G) from the Householder
-//           QR G^T = Q R: the remaining slots take the smallest Ritz pairs of N^T M N with
-//           N = Q[:, p:], formed as the trailing block of Q^T M Q (Ritz-S).
+//   p <  t: eigen of S S^T (p x p) gives mu and V_H = S^T u / mu; null(G) from a Householder
+//           QR of the rank_G columns G^T u_k (u_k the eigenvectors of G G^T with non-zero
+//           eigenvalues) = Q R: the remaining slots take the smallest Ritz pairs of N^T M N with
+//           N = Q[:, rank_G:], formed as the trailing block of Q^T M Q (Ritz-S).
 __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int size, const double* __restrict__ Min,
                                                        const double* __restrict__ G, double* sc, double* Xs,
                                                        double* VHs, double* mu, int* info, int ldsd) {
     extern __shared__ double dyn_lds[];
     __shared__ int s_rank;
-    __shared__ double s_beta[64];
+    __shared__ double s_beta[EIG_MAX];   // Householder factors of the QR of G^T (p < t <= EIG_MAX)
     __shared__ double red[SD_NT / 64];
     __shared__ double vv[EIG_MAX], pw[EIG_MAX];
     const int s_eff = s < t ? s : t;
@@ -778,7 +779,7 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
         }
         __syncthreads();
         double* lamg = lamv + t;
-        eig_range(p, GG, 0, 0, lamg, GV, esc, ldsd);   // singular values of G (squared)
+        eig_range(p, GG, 0, p, lamg, GV, esc, ldsd);   // G G^T = U diag(sigma^2) U^T, ascending
         eig_range(p, K, 0, p, lamv, Vv, esc, ldsd);    // S S^T: all pairs, ascending
         if (threadIdx.x == 0) {
             const double mx2 = fmax(lamg[p - 1], 0.0);
@@ -819,12 +820,22 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
         __syncthreads();
         solve_cols(t, L, Xs, kg, t, 1, ldsd);
         const int nfill = s_eff - kg;
-        if (nfill > 0 && p <= 64) {
-            const int nn = t - p;
-            if (threadIdx.x == 0) {   // Householder QR of G^T (t x p), reflectors in Hv
-                for (int j = 0; j < p; ++j)
-                    for (int i = 0; i < t; ++i) Hv[(size_t)j * t + i] = G[(size_t)i * p + j];
-                for (int j = 0; j < p; ++j) {
+        if (nfill > 0) {
+            // null(G) is the orthogonal complement of range(G^T) = span{G^T u_k}, u_k the
+            // eigenvectors of G G^T with non-zero eigenvalues (rankG of them, mutually
+            // orthogonal): a Householder QR of those rankG columns gives N = Q[:, rankG:],
+            // also where G has fewer independent rows than p
+            const int r = rankG, nn = t - r;
+            for (int idx = threadIdx.x; idx < r * t; idx += blockDim.x) {
+                const int j = idx / t, i = idx - j * t;
+                const double* u = GV + (size_t)(p - 1 - j) * p;
+                double v = 0.0;
+                for (int k = 0; k < p; ++k) v += G[(size_t)i * p + k] * u[k];
+                Hv[(size_t)j * t + i] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {   // Householder QR of the t x r columns, reflectors in Hv
+                for (int j = 0; j < r; ++j) {
                     double* v = Hv + (size_t)j * t;
                     double nrm = 0.0;
                     for (int i = j; i < t; ++i) nrm += v[i] * v[i];
@@ -836,7 +847,7 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
                     const double beta = vn > 0.0 ? 2.0 / vn : 0.0;
                     s_beta[j] = beta;
                     for (int i = 0; i < j; ++i) v[i] = 0.0;
-                    for (int jj = j + 1; jj < p; ++jj) {
+                    for (int jj = j + 1; jj < r; ++jj) {
                         double* u = Hv + (size_t)jj * t;
                         double d = 0.0;
                         for (int i = j; i < t; ++i) d += v[i] * u[i];
@@ -845,7 +856,7 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
                 }
             }
             __syncthreads();
-            // Q^T M Q = H_{p-1} ... H_0 M H_0 ... H_{p-1}; its trailing block is N^T M N
+            // Q^T M Q = H_{r-1} ... H_0 M H_0 ... H_{r-1}; its trailing block is N^T M N
             {
                 const bool in_lds = (int)T2 <= ldsd;
                 double* MM = in_lds ? dyn_lds : Ms;   // row-major (M symmetric)
@@ -854,7 +865,7 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
                     __syncthreads();
                 }
                 const int tid = threadIdx.x, bs = blockDim.x;
-                for (int j = 0; j < p; ++j) {
+                for (int j = 0; j < r; ++j) {
                     const double beta = s_beta[j];
                     if (beta == 0.0) continue;
                     for (int i = tid; i < t; i += bs) vv[i] = Hv[(size_t)j * t + i];
@@ -880,23 +891,23 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
                 }
                 // B = trailing nn x nn block, into K (row-major)
                 for (int idx = threadIdx.x; idx < nn * nn; idx += blockDim.x) {
-                    const int r = idx / nn, c = idx - r * nn;
-                    K[idx] = MM[(size_t)(p + r) * t + (p + c)];
+                    const int rr = idx / nn, c = idx - rr * nn;
+                    K[idx] = MM[(size_t)(r + rr) * t + (r + c)];
                 }
                 __syncthreads();
             }
             eig_range(nn, K, 0, nfill, lamv, BV, esc, ldsd);   // the nfill smallest Ritz pairs
-            // fill vectors x = N y = Q [0; y]: apply H_{p-1}, ..., H_0 to [0; y] (element-parallel;
+            // fill vectors x = N y = Q [0; y]: apply H_{r-1}, ..., H_0 to [0; y] (element-parallel;
             // the dot v_j . x_f of each reflection is one wave's sum, kept in pw[f])
             for (int f = threadIdx.x; f < nfill; f += blockDim.x) mu[kg + f] = 0.0;
             for (int idx = threadIdx.x; idx < nfill * t; idx += blockDim.x) {
                 const int f = idx / t, i = idx - f * t;
-                Xs[(size_t)(kg + f) * t + i] = i < p ? 0.0 : BV[(size_t)f * nn + (i - p)];
+                Xs[(size_t)(kg + f) * t + i] = i < r ? 0.0 : BV[(size_t)f * nn + (i - r)];
                 VHs[(size_t)(kg + f) * t + i] = 0.0;
             }
             __syncthreads();
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-            for (int j = p - 1; j >= 0; --j) {
+            for (int j = r - 1; j >= 0; --j) {
                 const double* v = Hv + (size_t)j * t;
                 for (int f = wave; f < nfill; f += nwave) {
                     const double* x = Xs + (size_t)(kg + f) * t;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -146,6 +147,100 @@ void set_tile_rows(const bl_problem* P, int rows) {
     std::lock_guard<std::mutex> lk(tile_mu);
     if (rows == 0) tile_table.erase(tile_key(P));
     else tile_table[tile_key(P)] = rows;
+}
+
+// Tile cache file: one line per entry, "reg radius n_filters filter_size prec log2n rows us8 us16
+// us32" (the key of the table, the chosen height and the timings that chose it); '#' starts a
+// comment line.  The whole file is parsed before it is used or rewritten, so a malformed file is
+// reported instead of being overwritten.
+namespace {
+struct CacheLine {
+    int rows;
+    double us[3];
+};
+bool read_tile_cache(const char* path, std::map<TileKey, CacheLine>& out, bool& exists, std::string& err) {
+    out.clear();
+    FILE* f = std::fopen(path, "r");
+    exists = f != nullptr;
+    if (!f) return true;
+    char line[512];
+    int lineno = 0;
+    bool ok = true;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        const char* q = line;
+        while (*q == ' ' || *q == '\t') ++q;
+        if (*q == '#' || *q == '\n' || *q == '\0') continue;
+        int k[7];
+        double us[3];
+        if (std::sscanf(q, "%d %d %d %d %d %d %d %lf %lf %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &us[0],
+                        &us[1], &us[2]) != 10 ||
+            !valid_rows(k[6])) {
+            err = std::string("malformed tile cache line ") + std::to_string(lineno) + " in " + path;
+            ok = false;
+            break;
+        }
+        out[TileKey(k[0], k[1], k[2], k[3], k[4], k[5])] = CacheLine{k[6], {us[0], us[1], us[2]}};
+    }
+    std::fclose(f);
+    return ok;
+}
+}  // namespace
+
+bool tile_cache_lookup(const char* path, const bl_problem* P, int& rows, bool& found, std::string& err) {
+    std::map<TileKey, CacheLine> m;
+    bool exists = false;
+    found = false;
+    if (!read_tile_cache(path, m, exists, err)) return false;
+    const auto it = m.find(tile_key(P));
+    if (it != m.end()) {
+        found = true;
+        rows = it->second.rows;
+    }
+    return true;
+}
+
+bool tile_cache_load_all(const char* path, int& entries, std::string& err) {
+    std::map<TileKey, CacheLine> m;
+    bool exists = false;
+    entries = 0;
+    if (!read_tile_cache(path, m, exists, err)) return false;
+    if (!exists) {
+        err = std::string("cannot read ") + path;
+        return false;
+    }
+    std::lock_guard<std::mutex> lk(tile_mu);
+    for (const auto& kv : m) tile_table[kv.first] = kv.second.rows;
+    entries = (int)m.size();
+    return true;
+}
+
+bool tile_cache_store(const char* path, const bl_problem* P, int rows, const double us[3], std::string& err) {
+    std::map<TileKey, CacheLine> m;
+    bool exists = false;
+    if (!read_tile_cache(path, m, exists, err)) return false;
+    m[tile_key(P)] = CacheLine{rows, {us[0], us[1], us[2]}};
+    // written next to the target and renamed over it: readers see the old or the new file whole
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) {
+        err = std::string("cannot write ") + tmp;
+        return false;
+    }
+    std::fprintf(f, "# bilevel tile cache: reg radius n_filters filter_size prec log2n rows us8 us16 us32\n");
+    for (const auto& kv : m) {
+        const TileKey& k = kv.first;
+        std::fprintf(f, "%d %d %d %d %d %d %d %.3f %.3f %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                     std::get<3>(k), std::get<4>(k), std::get<5>(k), kv.second.rows, kv.second.us[0], kv.second.us[1],
+                     kv.second.us[2]);
+    }
+    const bool wrote = std::fclose(f) == 0;
+    if (!wrote || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        err = std::string("cannot replace ") + path;
+        return false;
+    }
+    return true;
 }
 
 // Records are sized for the shortest tiles (the most tiles), whatever height a solve uses.

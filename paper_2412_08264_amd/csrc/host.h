@@ -77,6 +77,14 @@ bool valid_rows(int rows);
 int default_rows(const bl_problem* P);
 int tile_rows(const bl_problem* P);
 void set_tile_rows(const bl_problem* P, int rows);
+// Tile cache file (persisted autotuner results): the stored height of P's class and size class
+// (found = false without an entry or file), and an entry stored or replaced.  False with err set
+// when the file is malformed or cannot be written.
+bool tile_cache_lookup(const char* path, const bl_problem* P, int& rows, bool& found, std::string& err);
+bool tile_cache_store(const char* path, const bl_problem* P, int rows, const double us[3], std::string& err);
+// Every entry of a cache file into the table (false with err: missing or malformed file, and
+// then nothing is loaded).
+bool tile_cache_load_all(const char* path, int& entries, std::string& err);
 
 // Device scratch of one solve.
 struct SlotBuffers {

@@ -287,8 +287,9 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
 
 // ------------------------------------------------------------------ update, step k
 // `zr` values of Z^T r_{k-1} go into this launch's record (0 or nz); `fold`: the apply records
-// were folded.
-template <bool REC>
+// were folded.  WIDE: the records are reduced with all of a thread's loads in flight at once
+// (for grids of few blocks, where latency decides; costs registers).
+template <bool REC, bool WIDE>
 __global__ void __launch_bounds__(NT) k_m_update(MinresArgs a, int k, int zr, int fold) {
     constexpr int MPRE = REC ? 24 : 1;
     __shared__ double tot[NT];
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(NT) k_m_update(MinresArgs a, int k, int zr, in
     const double e_km = mine ? st->e[km & 3][threadIdx.x] : 0.0;
     const double mh1 = mine ? st->mh[(km - 1) & 3][threadIdx.x] : 0.0;
     const double mh2 = mine ? st->mh[(km - 2) & 3][threadIdx.x] : 0.0;
-    reduce_partials(fold ? a.fold : a.rec_app, fold ? FOLD_BLOCKS : a.ntiles, 1 + s, tot);
+    reduce_partials<WIDE ? 32 : 8>(fold ? a.fold : a.rec_app, fold ? FOLD_BLOCKS : a.ntiles, 1 + s, tot);
     if (sdone) return;
     const double alpha = tot[0];
     const double* e = tot + 1;
@@ -424,8 +425,12 @@ hipError_t launch_m_apply(const Stencil& S, const MinresArgs& a, int k, int nvb,
 }
 
 hipError_t launch_m_update(const MinresArgs& a, int k, int zr, bool fold, hipStream_t stream) {
-    if (a.s > 0) hipLaunchKernelGGL(k_m_update<true>, dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
-    else hipLaunchKernelGGL(k_m_update<false>, dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
+    if (a.s > 0 && a.npix <= 16 * 256)
+        hipLaunchKernelGGL((k_m_update<true, true>), dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
+    else if (a.s > 0)
+        hipLaunchKernelGGL((k_m_update<true, false>), dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
+    else
+        hipLaunchKernelGGL((k_m_update<false, false>), dim3(a.npix), dim3(NT), 0, stream, a, k, zr, (int)fold);
     return hipGetLastError();
 }
 

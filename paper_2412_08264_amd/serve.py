@@ -33,7 +33,7 @@ class Sample:
         self.xhats = xhats         # per outer step (device tensors)
         self.xstar = xstar
         self.s = s
-        self.rec = B.Recycle(P.h * P.w, s, v_cap, device)
+        self.rec = B.Recycle(P.h * P.w, s, v_cap, device, P)
         self.w = xstar.new_zeros(xstar.shape)
         self.step = 0              # next outer step to serve
         self.prev_hg = None

@@ -127,4 +127,61 @@ def test_tile_height_table_without_gpu():
     assert B.bl_tile_rows(P) == 8
     assert B.lib.bl_tile_rows(None) == 0
     nul = C.c_int()
-    assert B.lib.bl_autotune_tiles(None, C.byref(P), None, None, 0, 10, None, C.byref(nul)) == B.BL_E_ARG
+    assert B.lib.bl_autotune(None, C.byref(P), None, None, 0, 10, None, None, 0, C.byref(nul), None) == B.BL_E_ARG
+    assert B.lib.bl_autotune_workspace_bytes(C.byref(P), 20) >= B.bl_workspace_bytes(P, 20, 0) + (2 + 3 * 20) * 8 * 65536
+    assert B.lib.bl_autotune_workspace_bytes(C.byref(P), 65) == 0
+
+
+def test_tile_cache_file_without_gpu(tmp_path):
+    """bl_tile_cache_load: entries of the autotuner's cache file go into the tile table by
+    operator class and size class; a malformed or missing file is refused and loads nothing."""
+    from paper_2412_08264_amd import bilevel as B
+    P = B.bl_problem(256, 256, 4, 2.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)          # TV r=4 FP64, log2 n = 16
+    Pf = B.bl_problem(512, 512, 5, 3.0, B.BL_REG_FILTERS, 8, 7, 1e-6, 0, 1)   # filters 8x7x7 mixed, 18
+    good = tmp_path / "tiles.txt"
+    good.write_text("# reg radius n_filters filter_size prec log2n rows us8 us16 us32\n"
+                    "0 4 0 0 0 16 32 30.0 28.0 25.0\n"
+                    "1 5 8 7 1 18 16 900.0 850.0 870.0\n")
+    try:
+        assert B.bl_tile_cache_load(str(good)) == 2
+        assert B.bl_tile_rows(P) == 32 and B.bl_tile_rows(Pf) == 16
+        B.bl_tile_rows_set(P, 0)
+        B.bl_tile_rows_set(Pf, 0)
+        bad = tmp_path / "bad.txt"
+        bad.write_text("0 4 0 0 0 16 32 30.0 28.0 25.0\n1 5 8 7 1 18 12 1 2 3\n")   # 12 rows: invalid
+        with pytest.raises(B.BLError):
+            B.bl_tile_cache_load(str(bad))
+        assert B.bl_tile_rows(P) == 8                # nothing from the bad file was loaded
+        with pytest.raises(B.BLError):
+            B.bl_tile_cache_load(str(tmp_path / "missing.txt"))
+        assert B.lib.bl_tile_cache_load(None, None) == B.BL_E_ARG
+    finally:
+        B.bl_tile_rows_set(P, 0)
+        B.bl_tile_rows_set(Pf, 0)
+
+
+def test_recycle_storage_layout_without_gpu():
+    """bl_recycle_bytes / bl_recycle_init: U, C, Z (n x s_max), mu (s_max), V (n x v_cap), in that
+    order, each on a 256-byte boundary, carved from one caller buffer (host only: the addresses
+    are never dereferenced, so a fake aligned base serves)."""
+    from paper_2412_08264_amd import bilevel as B
+    al = lambda b: -(-b // 256) * 256
+    P = B.bl_problem(96, 80, 2, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)
+    n, s, v = 96 * 80, 10, 50
+    want = 3 * al(8 * n * s) + al(8 * s) + al(8 * n * v)
+    assert B.lib.bl_recycle_bytes(C.byref(P), s, v) == want
+    assert B.lib.bl_recycle_bytes(C.byref(P), 65, 0) == 0 and B.lib.bl_recycle_bytes(C.byref(P), 20, 237) == 0
+    assert B.lib.bl_recycle_bytes(None, 4, 4) == 0
+    base = 1 << 40
+    rs = B.bl_recycle()
+    assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base), want, C.byref(rs)) == B.BL_OK
+    assert (rs.U, rs.C, rs.Z, rs.mu, rs.V) == (base, base + al(8 * n * s), base + 2 * al(8 * n * s),
+                                               base + 3 * al(8 * n * s), base + 3 * al(8 * n * s) + al(8 * s))
+    assert (rs.s_max, rs.s_cur, rs.v_cap, rs.v_cur) == (s, 0, v, 0)
+    assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base), want - 1, C.byref(rs)) == B.BL_E_WORKSPACE
+    assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base + 8), want, C.byref(rs)) == B.BL_E_WORKSPACE
+    assert B.lib.bl_recycle_init(C.byref(P), 65, v, C.c_void_p(base), want, C.byref(rs)) == B.BL_E_SHAPE
+    assert B.lib.bl_recycle_init(C.byref(P), s, v, None, want, C.byref(rs)) == B.BL_E_ARG
+    rs0 = B.bl_recycle()
+    assert B.lib.bl_recycle_init(C.byref(P), 4, 0, C.c_void_p(base), want, C.byref(rs0)) == B.BL_OK
+    assert rs0.V is None and rs0.v_cap == 0
