@@ -146,7 +146,8 @@ size_t bl_workspace_bytes(const bl_problem* P, int s_max, int v_cap);
 
 /* Recycle storage of one training sample (the U, C = H U of Section 2.2.2 with Z, mu and the
  * stored basis V of Section 3.1) as one caller-owned device buffer: bl_recycle_bytes gives its
- * size for capacities s_max (0..64) and v_cap (s_max + v_cap <= 256), 0 for an invalid shape;
+ * size for capacities s_max (0..64) and v_cap (s_max + v_cap <= 256), at least 256 bytes, and 0
+ * for an invalid shape;
  * bl_recycle_init carves base (256-byte aligned, at least that many bytes) into U, C, Z
  * (n x s_max each), mu (s_max doubles) and V (n x v_cap; NULL when v_cap = 0), in that order,
  * each array starting on a 256-byte boundary, and sets s_cur = v_cur = 0.  Host-only: no device

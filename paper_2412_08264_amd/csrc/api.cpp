@@ -622,7 +622,7 @@ RecLayout rec_layout(const bl_problem* P, int s_max, int v_cap) {
     R.Z = R.C + al(n * s_max * 8);
     R.mu = R.Z + al(n * s_max * 8);
     R.V = R.mu + al((size_t)s_max * 8);
-    R.total = R.V + al(n * v_cap * 8);
+    R.total = std::max(R.V + al(n * v_cap * 8), ALIGN);   // never 0 for a valid shape (0 reports an invalid one)
     return R;
 }
 bool rec_shape_ok(const bl_problem* P, int s_max, int v_cap) {

@@ -172,6 +172,7 @@ def test_recycle_storage_layout_without_gpu():
     assert B.lib.bl_recycle_bytes(C.byref(P), s, v) == want
     assert B.lib.bl_recycle_bytes(C.byref(P), 65, 0) == 0 and B.lib.bl_recycle_bytes(C.byref(P), 20, 237) == 0
     assert B.lib.bl_recycle_bytes(None, 4, 4) == 0
+    assert B.lib.bl_recycle_bytes(C.byref(P), 0, 0) == 256     # empty storage: still a valid shape
     base = 1 << 40
     rs = B.bl_recycle()
     assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base), want, C.byref(rs)) == B.BL_OK
