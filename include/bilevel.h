@@ -186,6 +186,22 @@ bl_status bl_hessian_solve(bl_ctx* ctx, const bl_problem* P, const double* theta
                            const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
                            void* ws, size_t ws_bytes, bl_stats* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): bl_hessian_solve with the same arguments and results
+ * minus the workspace.  Its scratch is a static device array of BL_NOALLOC_SCRATCH_BYTES bytes,
+ * one per GPU, held from the library's first use on that GPU until the process ends (its address
+ * is looked up once per device, on the calling thread's current device, which must be the
+ * device of the context's stream).  A problem whose solve needs more scratch (TV up to about
+ * 1024 x 1024 fits; filters up to about 512 x 512) is refused with BL_E_WORKSPACE before any
+ * launch.  The call allocates nothing and launches directly (no graph capture).  All calls on
+ * one GPU share its array: calls that overlap on one GPU (other streams, other threads) race and
+ * must be serialised by the caller; a call leaves the array holding its own data, and every
+ * value a solve reads from it is written by that solve first. */
+#define BL_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+bl_status bl_hessian_solve_noalloc(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                                   const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
+                                   bl_stats* out);
+
 /* Hessian solve H w = g by RMINRES (Section 2.2.2, Algorithm 3): the correction V_k y + U z
  * minimising ||g - H w|| over w0 + range(U) + K_k((I - C C^T) H, r0) (eq. coupled), with the
  * Lanczos vectors kept orthogonal to C = H U (eq. arnoldi_aug_matrix).  H may be indefinite.

@@ -72,6 +72,8 @@ _SIGS = {
                                     _P(bl_recycle_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hessian_solve": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
                                    _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
+    "bl_hessian_solve_noalloc": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
+                                           _P(bl_solve_opts), _P(bl_stats)]),
     "bl_hessian_solve_rminres": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
                                            _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hypergradient": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _P(C.c_double), C.c_int,

@@ -341,6 +341,30 @@ bl_status solve_args(bl_ctx* c, const bl_problem* P, const double* xhat, const d
     return BL_OK;
 }
 
+// Scratch of bl_hessian_solve_noalloc: one array per device that loads the library, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, never the device array:
+// its device address comes from hipGetSymbolAddress, once per device, and only that address is
+// handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = BL_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex scratch_mu;
+void* scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+bl_status scratch_address(bl_ctx* c, void*& ptr) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return c->err = "device index above the scratch table", BL_E_ARG;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return c->err = "no device address for the scratch array", BL_E_HIP;
+        scratch_ptr[dev] = p;
+    }
+    ptr = scratch_ptr[dev];
+    return BL_OK;
+}
 }  // namespace
 
 bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat, const double* g,
@@ -350,6 +374,28 @@ bl_status bl_hessian_solve(bl_ctx* c, const bl_problem* P, const double* theta, 
     WS ws;
     TRY(check_ws(c, layout(P, rs ? rs->s_max : 0, rs ? rs->v_cap : 0), wsp, ws_bytes, ws));
     return solve_in(c, P, theta, xhat, g, w, rs, o, ws, out);
+}
+
+bl_status bl_hessian_solve_noalloc(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat,
+                                   const double* g, double* w, bl_recycle* rs, const bl_solve_opts* o,
+                                   bl_stats* out) {
+    TRY(solve_args(c, P, xhat, g, w, rs, o));
+    const Layout L = layout(P, 0, 0, true);
+    if (L.total > NOALLOC_SCRATCH_BYTES)
+        return c->err = "problem needs " + std::to_string(L.total) + " scratch bytes, above the " +
+                        std::to_string(NOALLOC_SCRATCH_BYTES) + " of the static array",
+               BL_E_WORKSPACE;
+    void* ptr = nullptr;
+    TRY(scratch_address(c, ptr));
+    WS ws;
+    ws.L = L;
+    ws.base = (char*)ptr;
+    // direct launches only: capturing and instantiating graphs could allocate
+    const int graphs = c->graphs;
+    c->graphs = 0;
+    const bl_status st = solve_in(c, P, theta, xhat, g, w, rs, o, ws, out);
+    c->graphs = graphs;
+    return st;
 }
 
 // ------------------------------------------------------------------------------ RMINRES
