@@ -95,7 +95,8 @@ def solve_sequence(prob, thetas, xhats, xstar, s: int, tol: float = 1e-10, stop:
                                  stop="hgerr" if use_hg else "resid",
                                  hg_tol=hg_rel * prev_hg if use_hg else 0.0, max_iter=max_iter, v_cap=v_cap)
         hg = jac(res["w"])
-        out.append({"w": res["w"], "iters": res["iters"], "status": res["status"], "hg": hg, "t": rs["t"]})
+        out.append({"w": res["w"], "iters": res["iters"], "status": res["status"], "hg": hg, "t": rs["t"],
+                    "w0": w_prev, "rs": rs})
         U, V = rs["U"], res["V"]
         w_prev = res["w"]
         prev_hg = float(np.linalg.norm(hg))

@@ -84,3 +84,43 @@ def test_hvp_filters_1024(B):
             out = torch.empty(prob.n, dtype=torch.float64, device=DEV)
             S.hvp(th, dev(xh), dev(v), out)
             assert rel(host(out), ref) <= tol, prec
+
+
+def test_mixed_precision_converged_solve_filters_256(B):
+    """Mixed precision (FP32 filter stencils, FP64 dots, projections and residual replacement)
+    converged on a 256 x 256 filter problem (two 7 x 7 filters, the filter family's 11 x 11 blur):
+    w and the hypergradient within 1e-6 of the oracle's FP64 reference solve (plain CG to 1e-13
+    with true-residual replacement), with and without a recycle space.  The reconstruction is a
+    stand-in point with small filter responses (|K_j x| < 1, so phi'' > 0 and H is SPD) and
+    the filter weights are e^0 = 1; the oracle needs about 260 products (17 s)."""
+    import math
+    wl = synth.custom("f", 256, "filters", 8, n_filters=2, filter_size=7, seed=3101)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    th = inst["theta0"].copy()
+    for j in range(2):
+        th[j * 50] = math.log(1.0)
+    xh = 0.2 * inst["xstar"].ravel() + 0.01 * synth.unit_noise(prob.n, 3102)
+    assert max(np.abs(k).max() for k in prob.responses(xh, th)[2]) < 1.0
+    g = xh - inst["xstar"].ravel()
+    hvp = lambda v: prob.hvp(xh, th, v)
+    wref, _ = krylov.reference_solve(hvp, g)
+    hgref = prob.jac_apply(xh, th, wref)
+    # a recycle space: s random directions, C = H U orthonormalised by QR (oracle products)
+    rng = np.random.default_rng(3103)
+    s = 4
+    Ut = rng.standard_normal((prob.n, s))
+    Cq, Rc = np.linalg.qr(np.stack([hvp(Ut[:, j]) for j in range(s)], axis=1))
+    U = np.linalg.solve(Rc.T, Ut.T).T
+    with B.Session(B.problem_from(wl, prec="mixed"), s_max=s, v_cap=8) as S:
+        for recycled in (False, True):
+            if recycled:
+                S.U[:s] = dev(U.T)
+                S.Cm[:s] = dev(Cq.T)
+                S.rs.s_cur = s
+            w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+            st = S.solve(th, dev(xh), dev(g), w, tol=1e-10, rr_every=25, store_basis=False, recycle=recycled,
+                         max_iter=5000)
+            assert st.status == 0
+            assert rel(host(w), wref) <= 1e-6, (recycled, rel(host(w), wref))
+            assert rel(S.hypergradient(th, dev(xh), w), hgref) <= 1e-6

@@ -464,6 +464,76 @@ def test_sequence_tv32(B):
             assert rel(hg, ref[i]["hg"]) <= 1e-8
 
 
+@pytest.fixture(scope="module")
+def tv32_sequence():
+    """The 32x32 TV recipe's 20-step frozen trajectory and the oracle's recycled solve sequence
+    on it (refresh, warm-started recycled CG to 1e-10, hypergradient), all on the CPU."""
+    from oracle import upper
+    wl = synth.WORKLOADS["tv32"]
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    thetas, xhats = upper.trajectory(prob, inst["xstar"], inst["theta0"], wl.outer)
+    xs = inst["xstar"].ravel()
+    ref = upper.solve_sequence(prob, thetas, xhats, xs, s=wl.s, tol=wl.tol)
+    return wl, prob, thetas, xhats, xs, ref
+
+
+def test_sequence_tv32_all_steps(B, tv32_sequence):
+    """The GPU's own pipeline (its refreshes, warm starts and stop decisions) over all 20 steps
+    of the 32x32 recipe: per step, the iteration count within 1 of the oracle's and the
+    hypergradient within 1e-9 of the oracle's (both solves stop at relative residual 1e-10 from
+    recycle spaces and warm starts each built by its own side, so they agree to the accuracy of
+    the solve rather than of rounding)."""
+    wl, prob, thetas, xhats, xs, ref = tv32_sequence
+    assert len(ref) == 20
+    errs = []
+    with B.Session(B.problem_from(wl), s_max=wl.s, v_cap=64) as S:
+        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+        for i, (t, x) in enumerate(zip(thetas, xhats)):
+            xd, gd = dev(x), dev(x - xs)
+            if i:
+                S.refresh(t, xd, s=wl.s)
+            st = S.solve(t, xd, gd, w, tol=wl.tol)
+            hg = S.hypergradient(t, xd, w)
+            errs.append((i, st.iters - ref[i]["iters"], rel(hg, ref[i]["hg"])))
+            assert abs(st.iters - ref[i]["iters"]) <= 1, errs[-1]
+            assert rel(hg, ref[i]["hg"]) <= 1e-9, errs[-1]
+    print("step, iteration difference, hypergradient difference:", errs)
+
+
+def test_sequence_tv32_at_oracle_stop(B, tv32_sequence):
+    """Each of the 20 systems solved from the oracle's own inputs (its recycle space U, C, Z, mu
+    and warm start) for exactly the oracle's iteration count (180-265): w and the hypergradient
+    within 1e-10 of the oracle's (measured worst: 3.3e-12 and 3.4e-11).  The oracle's own
+    one-ulp sensitivity (the same solve from g with every entry moved by one ulp) is printed
+    beside each step: the GPU's differences are of the same size."""
+    wl, prob, thetas, xhats, xs, ref = tv32_sequence
+    worst = []
+    with B.Session(B.problem_from(wl), s_max=wl.s, v_cap=64) as S:
+        for i, (t, x) in enumerate(zip(thetas, xhats)):
+            r = ref[i]
+            rs = r["rs"]
+            hvp = lambda v, x=x, t=t: prob.hvp(x, t, v)
+            g = x - xs
+            # the oracle's one-ulp spread at its own stopping iteration
+            pert = krylov.recycled_cg(hvp, np.nextafter(g, np.inf), r["w0"], rs["U"], rs["C"], tol=0.0,
+                                      max_iter=r["iters"], v_cap=0)
+            spread_w = rel(pert["w"], r["w"])
+            spread_hg = rel(prob.jac_apply(x, t, pert["w"]), r["hg"])
+            if rs["U"] is not None:
+                upload_recycle(S, rs)
+            else:
+                S.rs.s_cur = 0
+            w = dev(r["w0"]) if r["w0"] is not None else torch.zeros(prob.n, dtype=torch.float64, device=DEV)
+            st = S.solve(t, dev(x), dev(g), w, tol=0.0, max_iter=r["iters"], store_basis=False,
+                         recycle=rs["U"] is not None, allow=(B.BL_E_NOT_CONVERGED, B.BL_OK))
+            assert st.iters == r["iters"]
+            ew, ehg = rel(host(w), r["w"]), rel(S.hypergradient(t, dev(x), w), r["hg"])
+            worst.append((i, ew, ehg, spread_w, spread_hg))
+            assert ew <= 1e-10 and ehg <= 1e-10, worst[-1]
+    print("step, |dw|, |dhg|, one-ulp spread w, hg:", worst)
+
+
 @pytest.mark.parametrize("h,w", [(24, 24), (40, 52)])
 def test_lower_solve(B, h, w):
     """L-BFGS on the GPU against the oracle's: 576 pixels (three vector blocks, the last a
