@@ -18,6 +18,10 @@ Stop tests (Section 4):
   * hypergradient-error estimate (eq. hg-err-stop-lowrank): with Z = W V_H and mu the
     selected Ritz generalized singular values, ||mu . (Z^T r_j)|| <= hg_tol.
 The first test at j = 0 allows zero iterations.
+
+The solver also returns the CG coefficients alpha_j and rho_j = r_j . r_j of the iterations whose
+normalised residual went into V (what the inner refresh of recycle.py reads through the
+CG form of the Lanczos relation).
 """
 from __future__ import annotations
 
@@ -44,6 +48,7 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
     rho = float(r @ r)
     zacc = np.zeros(s)
     V = []
+    alphas, rhos = [], []       # CG coefficients of the iterations whose residual went into V
     hist_res, hist_nsc = [], []
 
     def nsc(rv):
@@ -68,8 +73,10 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
     done = met(r, rho, 0)
     while not done and iters < max_iter:
         # V: basis of the generated Krylov space, one normalised residual per iteration run
-        if len(V) < v_cap:
+        stored = len(V) < v_cap
+        if stored:
             V.append(r / np.sqrt(rho))
+            rhos.append(rho)
         q = hvp(p)
         e = C.T @ q if s else np.zeros(0)
         sigma = float(p @ q)
@@ -77,6 +84,8 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
             status = INDEFINITE
             break
         alpha = rho / sigma
+        if stored:
+            alphas.append(alpha)
         if recurrence == "single":
             rq, qq, ee = float(r @ q), float(q @ q), float(e @ e)
         w += alpha * p
@@ -100,7 +109,8 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
         w = w + U @ zacc
     return {"w": w, "iters": iters, "status": status, "res_norm": float(np.sqrt(max(rho, 0.0))),
             "g_norm": gnorm, "V": np.stack(V, axis=1) if V else np.zeros((n, 0)),
-            "hist_res": hist_res, "hist_nsc": hist_nsc, "r": r, "zacc": zacc}
+            "hist_res": hist_res, "hist_nsc": hist_nsc, "r": r, "zacc": zacc,
+            "alpha": np.array(alphas), "rho": np.array(rhos)}
 
 
 def cg(hvp, g, w0=None, tol: float = 1e-10, max_iter: int = 10000, v_cap: int = 64, record: bool = False):

@@ -2,6 +2,9 @@
 
 Outer variant (eq. subtle-new): the space for system i is extracted from
 W = [U^{(i-1)}, V^{(i-1)}] using the *new* Hessian H^{(i)} and adjoint Jacobian J^{(i)}.
+Inner variant (eq. subtle-old): the projected matrix uses the previous Hessian H^{(i-1)}
+(what the previous solve's Lanczos relation already holds); only the s chosen vectors are
+multiplied by H^{(i)}.
 
 Readings taken where the paper is silent:
   * W is orthonormalised before projecting (the paper's W is only "full rank";
@@ -205,10 +208,11 @@ def select(G, M, YtY, s: int, rule: str) -> dict:
     raise ValueError(f"unknown selection {rule}")
 
 
-def build_from_selection(W: np.ndarray, Y: np.ndarray, sel: dict) -> dict:
-    """U~ = W X~, C~ = Y X~ (= H U~), thin QR C~ = C R, U = U~ R^{-1}, Z = W V_H~."""
+def build_from_selection(W: np.ndarray, Y: np.ndarray, sel: dict, Ut=None) -> dict:
+    """U~ = W X~, C~ = Y X~ (= H U~), thin QR C~ = C R, U = U~ R^{-1}, Z = W V_H~.  With Ut
+    given, U~ = Ut and Y already holds H U~ (X~ = I)."""
     X = sel["X"] / np.linalg.norm(sel["X"], axis=0, keepdims=True)
-    Ut = W @ X
+    Ut = W @ X if Ut is None else Ut
     Ct = Y @ X
     Qc, Rc = np.linalg.qr(Ct)
     sgn = np.sign(np.diag(Rc))
@@ -219,25 +223,63 @@ def build_from_selection(W: np.ndarray, Y: np.ndarray, sel: dict) -> dict:
     return {"U": U, "C": Qc, "Z": W @ sel["V_H"], "mu": sel["mu"].copy()}
 
 
-def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL, select_rule: str = "rgen-l-r") -> dict:
-    """Outer refresh (RGen-L(R) by default; any rule of SELECTIONS).  ``hvp(v)``/``jac_apply(v)``
-    use the new (x_hat, theta).  Selections other than RGen leave mu = 0 and Z = 0: the
-    error-estimate test is then undefined and solves use the residual test."""
+def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL, select_rule: str = "rgen-l-r",
+            hvp_old=None) -> dict:
+    """Recycle-space refresh (RGen-L(R) by default; any rule of SELECTIONS).  ``hvp(v)`` and
+    ``jac_apply(v)`` use the new (x_hat, theta).
+
+    Outer variant (``hvp_old`` None, eq. subtle-new): the projected matrix is W^T H^{(i)} W.
+    Inner variant (``hvp_old`` the previous system's product, eq. subtle-old): it is
+    W^T H^{(i-1)} W, and only the s selected vectors meet the new Hessian (C~ = H^{(i)} U~).
+    The paper changes only the Hessian between the two (Section 3.1; Section 5.1, "Inner versus
+    outer recycling strategies"); reading: J stays the new J^{(i)} in both.
+
+    Selections other than RGen leave mu = 0 and Z = 0: the error-estimate test is then undefined
+    and solves use the residual test."""
     blocks = [B for B in (U_prev, V_prev) if B is not None and B.shape[1] > 0]
     if not blocks or s <= 0:
         return {"U": None, "C": None, "Z": None, "mu": None, "t": 0, "rank_G": 0}
     W, kept = orthonormalize(np.concatenate(blocks, axis=1), rank_tol)
     t = W.shape[1]
-    Y = np.stack([hvp(W[:, c]) for c in range(t)], axis=1)
+    proj = hvp if hvp_old is None else hvp_old
+    Y = np.stack([proj(W[:, c]) for c in range(t)], axis=1)
     M = 0.5 * (W.T @ Y + Y.T @ W)
     rgen = select_rule.startswith("rgen")
     G = np.stack([jac_apply(W[:, c]) for c in range(t)], axis=1) if rgen else None
     YtY = Y.T @ Y if select_rule.startswith("hritz") else None
     sel = select(G, M, YtY, s, select_rule)
-    out = build_from_selection(W, Y, sel)
+    if hvp_old is None:
+        out = build_from_selection(W, Y, sel)
+    else:
+        # C~ = H^{(i)} U~ by s products with the new Hessian
+        X = sel["X"] / np.linalg.norm(sel["X"], axis=0, keepdims=True)
+        Ynew = np.stack([hvp(W @ X[:, c]) for c in range(X.shape[1])], axis=1)
+        out = build_from_selection(W, Ynew, dict(sel, X=np.eye(X.shape[1])), Ut=W @ X)
     out.update({"t": t, "rank_G": sel["rank_G"], "W": W, "M": M, "G": G, "Y": Y, "sel": sel,
                 "dropped": len(np.concatenate(blocks, axis=1).T) - len(kept)})
     return out
+
+
+def cg_lanczos_matrix(alpha: np.ndarray, rho: np.ndarray) -> np.ndarray:
+    """V^T A V for the normalised CG residuals v_j = r_j / sqrt(rho_j), j < k, from the CG
+    coefficients alone (the Lanczos relation eq. arnoldi-matrix-id written for CG; with the
+    recycle space it is eq. arnoldi_aug_matrix, A = (I - C C^T) H on range(C)^perp, and
+    V^T H V = V^T A V there since V is orthogonal to C).
+
+    From A p_j = (r_j - r_{j+1}) / alpha_j and p_j = r_j + beta_{j-1} p_{j-1}
+    (beta_{j-1} = rho_j / rho_{j-1}):
+        A r_j = (1/alpha_j + beta_{j-1}/alpha_{j-1}) r_j - r_{j+1}/alpha_j - (beta_{j-1}/alpha_{j-1}) r_{j-1},
+    and the residuals are orthogonal, so T is tridiagonal with
+        T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}   (no second term for j = 0),
+        T_{j,j+1} = T_{j+1,j} = -sqrt(rho_{j+1}/rho_j) / alpha_j.
+    In floating point it equals V^T H V while the stored residuals stay orthogonal."""
+    k = len(rho)
+    T = np.zeros((k, k))
+    for j in range(k):
+        T[j, j] = 1.0 / alpha[j] + ((rho[j] / rho[j - 1]) / alpha[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            T[j, j + 1] = T[j + 1, j] = -np.sqrt(rho[j + 1] / rho[j]) / alpha[j]
+    return T
 
 
 def principal_angles(A: np.ndarray, B: np.ndarray) -> np.ndarray:

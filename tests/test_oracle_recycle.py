@@ -168,3 +168,99 @@ def test_rgen_large_picks_largest_quotient_singular_values(p, t, s):
     Vtop = Vt[:s].T
     assert recycle.principal_angles(sel["V_H"], Vtop).max() < 1e-8
     assert recycle.principal_angles(sel["X"], np.linalg.solve(M, Vtop)).max() < 1e-8
+
+
+# ------------------------------------------------------------------ inner refresh (eq. subtle-old)
+def _tv_pair(seed=131):
+    """A 20 x 18 TV problem at two nearby (x_hat, theta): the systems i-1 and i of a sequence."""
+    wl = synth.custom("t", 20, "tv", 4, width=18, blur_radius=2, blur_sigma=1.5, rect_min=2, rect_max=5, seed=seed)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xs = inst["xstar"].ravel()
+    x0 = xs + 0.05 * synth.unit_noise(prob.n, seed + 1)
+    x1 = x0 + 0.01 * synth.unit_noise(prob.n, seed + 2)
+    t0 = np.array(inst["theta0"])
+    t1 = t0 + np.array([0.05, -0.03])
+    return prob, xs, (x0, t0), (x1, t1)
+
+
+def test_cg_lanczos_matrix_is_projected_hessian():
+    """The CG form of the Lanczos relation: V^T H V of the stored normalised residuals equals
+    the tridiagonal matrix built from the CG coefficients alone, with and without a recycle
+    space (then V is also orthogonal to C, so U^T H V = C^T V = 0)."""
+    prob, xs, (x0, t0), _ = _tv_pair()
+    hvp = lambda v: prob.hvp(x0, t0, v)
+    g = x0 - xs
+    first = krylov.cg(hvp, g, tol=1e-12, v_cap=14)
+    V = first["V"]
+    assert V.shape[1] == 14 and len(first["alpha"]) == 14 and len(first["rho"]) == 14
+    HV = np.stack([hvp(V[:, j]) for j in range(14)], axis=1)
+    T = recycle.cg_lanczos_matrix(first["alpha"], first["rho"])
+    assert np.abs(T - V.T @ HV).max() <= 1e-9 * np.abs(T).max()    # rounding: the residuals lose orthogonality
+    assert np.count_nonzero(np.triu(T, 2)) == 0
+    # recycled: CG on (I - C C^T) H with C = H U from an outer refresh of the first basis
+    rs = recycle.refresh(hvp, lambda v: prob.jac_apply(x0, t0, v), None, V, s=4)
+    second = krylov.recycled_cg(hvp, g + 0.1 * synth.unit_noise(prob.n, 7), None, rs["U"], rs["C"], tol=1e-12,
+                                v_cap=10)
+    V2 = second["V"]
+    HV2 = np.stack([hvp(V2[:, j]) for j in range(V2.shape[1])], axis=1)
+    T2 = recycle.cg_lanczos_matrix(second["alpha"], second["rho"])
+    assert np.abs(T2 - V2.T @ HV2).max() <= 1e-9 * np.abs(T2).max()
+    UtHV = rs["U"].T @ HV2
+    assert np.abs(UtHV).max() <= 1e-10 * np.abs(T2).max()
+    assert np.abs(rs["C"].T @ V2).max() <= 1e-12
+
+
+def test_inner_refresh_from_lanczos_relation():
+    """Inner refresh (eq. subtle-old): its projected matrix W^T H^{(i-1)} W, formed by the
+    oracle from products with the previous Hessian, equals X^T blockdiag(U^T C, T) X assembled
+    from the previous solve's relation (U^T H^{(i-1)} U = U^T C, U^T H^{(i-1)} V = 0, V^T H^{(i-1)} V
+    = T from the CG coefficients), W = [U, V] X; only the s selected vectors meet H^{(i)}."""
+    prob, xs, (x0, t0), (x1, t1) = _tv_pair(141)
+    h0 = lambda v: prob.hvp(x0, t0, v)
+    h1 = lambda v: prob.hvp(x1, t1, v)
+    jac1 = lambda v: prob.jac_apply(x1, t1, v)
+    first = krylov.cg(h0, x0 - xs, tol=1e-12, v_cap=12)
+    rs0 = recycle.refresh(h0, lambda v: prob.jac_apply(x0, t0, v), None, first["V"], s=4)
+    prev = krylov.recycled_cg(h0, x0 - xs, first["w"], rs0["U"], rs0["C"], tol=1e-13, v_cap=10)
+    U, C, V = rs0["U"], rs0["C"], prev["V"]
+    assert V.shape[1] == 10
+    calls = {"old": 0, "new": 0}
+
+    def count(h, key):
+        def f(v):
+            calls[key] += 1
+            return h(v)
+        return f
+
+    ref = recycle.refresh(count(h1, "new"), jac1, U, V, s=4, hvp_old=count(h0, "old"))
+    assert calls == {"old": ref["t"], "new": 4}
+    W = ref["W"]
+    X = np.linalg.lstsq(np.concatenate([U, V], axis=1), W, rcond=None)[0]
+    M0 = np.zeros((14, 14))
+    M0[:4, :4] = 0.5 * (U.T @ C + C.T @ U)
+    M0[4:, 4:] = recycle.cg_lanczos_matrix(prev["alpha"], prev["rho"])
+    M_rel = X.T @ M0 @ X
+    assert np.abs(M_rel - ref["M"]).max() <= 1e-9 * np.abs(ref["M"]).max()
+    # the recycle space it returns satisfies the invariants of the new system
+    HU = np.stack([h1(ref["U"][:, j]) for j in range(ref["U"].shape[1])], axis=1)
+    assert np.linalg.norm(HU - ref["C"]) <= 1e-12 * np.linalg.norm(ref["C"])
+    assert np.abs(ref["C"].T @ ref["C"] - np.eye(ref["C"].shape[1])).max() <= 1e-13
+    # and differs from the outer variant's, which projects with the new Hessian
+    out = recycle.refresh(h1, jac1, U, V, s=4)
+    assert np.abs(out["M"] - ref["M"]).max() > 1e-6 * np.abs(ref["M"]).max()
+
+
+def test_inner_equals_outer_for_an_unchanged_hessian():
+    """With H^{(i)} = H^{(i-1)} the two variants are one definition: same mu, same spaces."""
+    prob, xs, (x0, t0), _ = _tv_pair(151)
+    h0 = lambda v: prob.hvp(x0, t0, v)
+    jac = lambda v: prob.jac_apply(x0, t0, v)
+    first = krylov.cg(h0, x0 - xs, tol=1e-10, v_cap=16)
+    a = recycle.refresh(h0, jac, None, first["V"], s=5)
+    b = recycle.refresh(h0, jac, None, first["V"], s=5, hvp_old=h0)
+    assert np.abs(a["M"] - b["M"]).max() == 0.0
+    assert np.abs(a["mu"] - b["mu"]).max() <= 1e-12 * a["mu"].max()
+    assert recycle.principal_angles(a["U"], b["U"]).max() <= 1e-9
+    assert recycle.principal_angles(a["C"], b["C"]).max() <= 1e-9
+    assert recycle.principal_angles(a["Z"][:, :2], b["Z"][:, :2]).max() <= 1e-9
