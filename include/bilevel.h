@@ -79,6 +79,10 @@ typedef struct {
     double* V;               /* first v_cap normalised CG residuals of the last solve         */
     int s_max, s_cur;        /* capacity / valid columns of U, C, Z, mu (s_cur = 0: none)     */
     int v_cap, v_cur;        /* capacity / valid columns of V                                 */
+    double* lz;              /* 2 v_cap doubles or NULL: CG coefficients alpha_j (at 2j) and  */
+                             /* rho_j = r_j.r_j (at 2j+1) of the stored residuals, written by */
+                             /* CG solves with store_basis; read by the inner refresh          */
+    int v_lz;                /* leading columns of V the coefficients describe (0: none)      */
 } bl_recycle;
 
 typedef struct {
@@ -118,6 +122,7 @@ typedef struct {
     int s;                   /* requested recycle dimension (<= rs->s_max)                    */
     double rank_tol;         /* relative column-norm drop threshold for orthonormalising W   */
     int select;              /* bl_select (0: RGen-L(R))                                       */
+    int inner;               /* 0: outer variant (eq. subtle-new), 1: inner (eq. subtle-old)  */
 } bl_recycle_opts;
 
 typedef struct {
@@ -149,8 +154,9 @@ size_t bl_workspace_bytes(const bl_problem* P, int s_max, int v_cap);
  * size for capacities s_max (0..64) and v_cap (s_max + v_cap <= 256), at least 256 bytes, and 0
  * for an invalid shape;
  * bl_recycle_init carves base (256-byte aligned, at least that many bytes) into U, C, Z
- * (n x s_max each), mu (s_max doubles) and V (n x v_cap; NULL when v_cap = 0), in that order,
- * each array starting on a 256-byte boundary, and sets s_cur = v_cur = 0.  Host-only: no device
+ * (n x s_max each), mu (s_max doubles), V (n x v_cap) and lz (2 v_cap doubles; V and lz NULL
+ * when v_cap = 0), in that order, each array starting on a 256-byte boundary, and sets
+ * s_cur = v_cur = v_lz = 0.  Host-only: no device
  * access, the buffer's contents are not touched.  BL_E_ARG (null pointer), BL_E_SHAPE (bad
  * capacities or problem), BL_E_WORKSPACE (buffer too small or misaligned). */
 size_t bl_recycle_bytes(const bl_problem* P, int s_max, int v_cap);

@@ -32,7 +32,8 @@ class bl_problem(C.Structure):
 
 class bl_recycle(C.Structure):
     _fields_ = [("U", C.c_void_p), ("C", C.c_void_p), ("Z", C.c_void_p), ("mu", C.c_void_p), ("V", C.c_void_p),
-                ("s_max", C.c_int), ("s_cur", C.c_int), ("v_cap", C.c_int), ("v_cur", C.c_int)]
+                ("s_max", C.c_int), ("s_cur", C.c_int), ("v_cap", C.c_int), ("v_cur", C.c_int),
+                ("lz", C.c_void_p), ("v_lz", C.c_int)]
 
 
 class bl_solve_opts(C.Structure):
@@ -41,7 +42,7 @@ class bl_solve_opts(C.Structure):
 
 
 class bl_recycle_opts(C.Structure):
-    _fields_ = [("s", C.c_int), ("rank_tol", C.c_double), ("select", C.c_int)]
+    _fields_ = [("s", C.c_int), ("rank_tol", C.c_double), ("select", C.c_int), ("inner", C.c_int)]
 
 
 # selection rules of bl_select, by name
@@ -286,9 +287,10 @@ class Context:
                "bl_lower_solve", ok=(BL_OK, BL_E_NOT_CONVERGED))
         return st
 
-    def refresh_p(self, P, rec, theta, xhat, s: int, rank_tol: float = 1e-8, select: str = "rgen-l-r") -> bl_stats:
+    def refresh_p(self, P, rec, theta, xhat, s: int, rank_tol: float = 1e-8, select: str = "rgen-l-r",
+                  inner: bool = False) -> bl_stats:
         st = bl_stats()
-        o = bl_recycle_opts(s, rank_tol, SELECTIONS[select])
+        o = bl_recycle_opts(s, rank_tol, SELECTIONS[select], 1 if inner else 0)
         _check(self.ctx, lib.bl_recycle_update(self.ctx, C.byref(P), _theta(theta), _ptr(xhat),
                                                C.byref(rec.rs), C.byref(o), self.ws_ptr, self.ws_bytes,
                                                C.byref(st)), "bl_recycle_update", ok=(BL_OK, BL_E_RANK))
@@ -335,11 +337,13 @@ class Session(Context):
         self.p = bl_num_params(P)
         self.rec = Recycle(self.n, s_max, v_cap, self.device, P)
         self.U, self.Cm, self.Z, self.mu, self.V = self.rec.U, self.rec.Cm, self.rec.Z, self.rec.mu, self.rec.V
+        self.lz = self.rec.lz
         self.rs = self.rec.rs
 
     def reset(self):
         self.rs.s_cur = 0
         self.rs.v_cur = 0
+        self.rs.v_lz = 0
 
     def forward(self, x, e, noise, y):
         self.forward_p(self.P, x, e, noise, y)
@@ -353,8 +357,9 @@ class Session(Context):
     def lower_solve(self, theta, y, x, gtol=1e-8, max_iter=20000, m=10) -> bl_stats:
         return self.lower_solve_p(self.P, theta, y, x, gtol, max_iter, m)
 
-    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8, select: str = "rgen-l-r") -> bl_stats:
-        return self.refresh_p(self.P, self.rec, theta, xhat, s, rank_tol, select)
+    def refresh(self, theta, xhat, s: int, rank_tol: float = 1e-8, select: str = "rgen-l-r",
+                inner: bool = False) -> bl_stats:
+        return self.refresh_p(self.P, self.rec, theta, xhat, s, rank_tol, select, inner)
 
     def solve(self, theta, xhat, g, w, **kw) -> bl_stats:
         return self.solve_p(self.P, self.rec, theta, xhat, g, w, **kw)
@@ -393,6 +398,8 @@ class Recycle:
         self.Z = view(self.rs.Z, s_max)
         self.mu = self.buf[off(self.rs.mu):off(self.rs.mu) + 8 * s_max].view(torch.float64)
         self.V = view(self.rs.V, v_cap) if v_cap > 0 else self.buf[:0].view(torch.float64).view(0, n)
+        self.lz = (self.buf[off(self.rs.lz):off(self.rs.lz) + 16 * v_cap].view(torch.float64) if v_cap > 0
+                   else self.buf[:0].view(torch.float64))
         self._nbytes = nbytes
 
     def nbytes(self) -> int:
@@ -509,7 +516,7 @@ def hessian_solve_batched(problems, thetas, xhats, gs, ws_, recs, opts: bl_solve
         ga = (_vp * k)(*[_ptr(t) for t in gs])
         wa = (_vp * k)(*[_ptr(t) for t in ws_])
         any_rec = any(r is not None for r in recs)
-        empty = bl_recycle(None, None, None, None, None, 0, 0, 0, 0)
+        empty = bl_recycle(None, None, None, None, None, 0, 0, 0, 0, None, 0)
         rsarr = (bl_recycle * k)(*[(r.rs if r is not None else empty) for r in recs]) if any_rec else None
         out = (bl_stats * k)()
         code = lib.bl_hessian_solve_batched(ctx, k, Parr, tharr, xa, ga, wa, rsarr, C.byref(opts), wsp, nbytes, out)
@@ -519,6 +526,7 @@ def hessian_solve_batched(problems, thetas, xhats, gs, ws_, recs, opts: bl_solve
             for r, rr in zip(recs, rsarr):
                 if r is not None:
                     r.rs.v_cur = rr.v_cur
+                    r.rs.v_lz = rr.v_lz
         return code, list(out)
     finally:
         if own:

@@ -66,7 +66,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap, bool solve_only = false
     L.Ct = o;       o += al((size_t)L.n * std::max(s_max, 1) * sizeof(double));
     const size_t T2 = (size_t)L.t_max * L.t_max;
     L.small = o;
-    o += al((6 * T2 + (size_t)L.p * L.t_max + 2 * (size_t)L.t_max * std::max(s_max, 1) + 256 +
+    o += al((9 * T2 + (size_t)L.p * L.t_max + 2 * (size_t)L.t_max * std::max(s_max, 1) + 256 +
              gsvd_scratch_doubles(L.t_max, L.p)) * sizeof(double) + 4 * L.t_max * sizeof(int));
     L.lb = o;       o += al(((size_t)2 * (LBFGS_MMAX + 1) * L.n + (size_t)(LBFGS_MMAX + 6) * 1024 + 64) * sizeof(double));
     L.total = o;
@@ -495,7 +495,10 @@ bl_status bl_hessian_solve_rminres(bl_ctx* c, const bl_problem* P, const double*
     HIPCHK(hipStreamSynchronize(c->stream));
     MinresState hs;
     std::memcpy(&hs, c->h_buf, sizeof(MinresState));
-    if (store) rs->v_cur = std::min(hs.iters, v_cap);
+    if (store) {
+        rs->v_cur = std::min(hs.iters, v_cap);
+        rs->v_lz = 0;   // Lanczos vectors: no CG coefficients for an inner refresh
+    }
     if (out) {
         *out = bl_stats{};
         out->iters = hs.iters;
@@ -658,7 +661,7 @@ bl_status bl_tile_cache_load(const char* cache_path, int* entries) {
 // ---------------------------------------------------------------------------- recycle storage
 namespace {
 struct RecLayout {
-    size_t U, C, Z, mu, V, total;
+    size_t U, C, Z, mu, V, lz, total;
 };
 RecLayout rec_layout(const bl_problem* P, int s_max, int v_cap) {
     const size_t n = (size_t)P->h * P->w;
@@ -668,7 +671,8 @@ RecLayout rec_layout(const bl_problem* P, int s_max, int v_cap) {
     R.Z = R.C + al(n * s_max * 8);
     R.mu = R.Z + al(n * s_max * 8);
     R.V = R.mu + al((size_t)s_max * 8);
-    R.total = std::max(R.V + al(n * v_cap * 8), ALIGN);   // never 0 for a valid shape (0 reports an invalid one)
+    R.lz = R.V + al(n * v_cap * 8);
+    R.total = std::max(R.lz + al((size_t)2 * v_cap * 8), ALIGN);   // never 0 for a valid shape (0: invalid)
     return R;
 }
 bool rec_shape_ok(const bl_problem* P, int s_max, int v_cap) {
@@ -693,10 +697,12 @@ bl_status bl_recycle_init(const bl_problem* P, int s_max, int v_cap, void* base,
     rs->Z = (double*)(b + R.Z);
     rs->mu = (double*)(b + R.mu);
     rs->V = v_cap > 0 ? (double*)(b + R.V) : nullptr;
+    rs->lz = v_cap > 0 ? (double*)(b + R.lz) : nullptr;
     rs->s_max = s_max;
     rs->s_cur = 0;
     rs->v_cap = v_cap;
     rs->v_cur = 0;
+    rs->v_lz = 0;
     return BL_OK;
 }
 
@@ -735,6 +741,15 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     if (!rs->U || !rs->C || !rs->Z || !rs->mu || (rs->v_cap > 0 && !rs->V))
         return c->err = "null recycle arrays", BL_E_ARG;
     if (!(o->rank_tol > 0.0 && o->rank_tol < 1.0)) return c->err = "rank_tol outside (0, 1)", BL_E_ARG;
+    if (o->inner != 0 && o->inner != 1) return c->err = "inner must be 0 or 1", BL_E_ARG;
+    const bool inner = o->inner == 1;
+    if (inner) {
+        if (o->select >= BL_SEL_HRITZ_S && o->select <= BL_SEL_HRITZ_M)
+            return c->err = "the inner refresh has no (H W)^T (H W): harmonic Ritz selections are outer only", BL_E_ARG;
+        if (rs->v_lz < 0 || rs->v_lz > rs->v_cur) return c->err = "v_lz outside [0, v_cur]", BL_E_SHAPE;
+        if (rs->v_cur > 0 && (rs->v_lz == 0 || !rs->lz))
+            return c->err = "inner refresh: no CG coefficients for the stored basis (store it with a CG solve)", BL_E_ARG;
+    }
     if (o->select < BL_SEL_RGEN_L_R || o->select > BL_SEL_RGEN_M_M) return c->err = "unknown selection", BL_E_ARG;
     const bool rgen = o->select <= BL_SEL_RGEN_L_M || o->select >= BL_SEL_RGEN_S_R;
     // RGen: size 0 / 1 / 2 (largest / smallest / both ends), side 0 / 1 / 2 (right / left / sum)
@@ -749,7 +764,10 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     WS ws;
     TRY(check_ws(c, layout(P, rs->s_max, rs->v_cap), wsp, ws_bytes, ws));
     const int n = P->h * P->w, p = nparams(P);
-    const int t0 = rs->s_cur + rs->v_cur;
+    // inner: the stored residuals the CG coefficients describe (all of them, unless a residual
+    // replacement of a mixed-precision solve cut the relation short)
+    const int v_use = inner ? rs->v_lz : rs->v_cur;
+    const int t0 = rs->s_cur + v_use;
     if (out) std::memset(out, 0, sizeof(*out));
     if (t0 == 0 || o->s == 0) {
         rs->s_cur = 0;
@@ -770,7 +788,11 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     double* VHs = Xs + (size_t)tm * std::max(rs->s_max, 1);
     double* mu_tmp = VHs + (size_t)tm * std::max(rs->s_max, 1);
     double* gsc = mu_tmp + 256;
-    int* ibuf = (int*)(gsc + gsvd_scratch_doubles(tm, p));
+    double* X1c = gsc + gsvd_scratch_doubles(tm, p);   // inner: first-pass factor, X = X1 X2, Y = M0 X
+    double* Xp = X1c + T2;
+    double* Yp = Xp + T2;
+    double* UtC = Xinv;                                  // inner: U^T C of the previous system (s0 x s0)
+    int* ibuf = (int*)(Yp + T2);
     int* kept = ibuf;
     int* tk_dev = ibuf + tm;
     int* info = ibuf + tm + 4;
@@ -779,8 +801,8 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     double* W1 = ws.W1();
     if (rs->s_cur)
         HIPCHK(hipMemcpyAsync(W0, rs->U, (size_t)rs->s_cur * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if (rs->v_cur)
-        HIPCHK(hipMemcpyAsync(W0 + (size_t)rs->s_cur * n, rs->V, (size_t)rs->v_cur * n * sizeof(double),
+    if (v_use)
+        HIPCHK(hipMemcpyAsync(W0 + (size_t)rs->s_cur * n, rs->V, (size_t)v_use * n * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
     // two passes of Cholesky QR with column drop: W = [U, V] X1 X2
     HIPCHK(launch_gram(n, t0, t0, W0, W0, ws.part(), Gram, c->stream));
@@ -793,6 +815,7 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
         return BL_E_RANK;
     }
     HIPCHK(launch_gemm_tall(n, t0, t1, W0, Xinv, t0, W1, c->stream));
+    if (inner) HIPCHK(hipMemcpyAsync(X1c, Xinv, (size_t)t0 * t1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(launch_gram(n, t1, t1, W1, W1, ws.part(), Gram, c->stream));
     HIPCHK(launch_chol_drop(t1, Gram, 1e-12, Achol, kept, tk_dev, Xinv, t1, c->stream));
     HIPCHK(hipMemcpyAsync(c->h_info, tk_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -800,10 +823,20 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     const int t = c->h_info[0];
     HIPCHK(launch_gemm_tall(n, t1, t, W1, Xinv, t1, W0, c->stream));   // W (orthonormal) in W0
     mark(c, 1);
-    // Y = H W (FP64), M = W^T Y, G = J W
-    // t columns give any tile height enough blocks: the tallest (measured fastest for this product)
-    HIPCHK(launch_hvp(S, false, xhat, W0, W1, t, 4 * QTY, c->stream));
-    HIPCHK(launch_gram(n, t, t, W0, W1, ws.part(), M, c->stream));
+    if (!inner) {
+        // Y = H W (FP64), M = W^T Y
+        // t columns give any tile height enough blocks: the tallest (measured fastest for this product)
+        HIPCHK(launch_hvp(S, false, xhat, W0, W1, t, 4 * QTY, c->stream));
+        HIPCHK(launch_gram(n, t, t, W0, W1, ws.part(), M, c->stream));
+    } else {
+        // M = W^T H_old W without products: W = [U, V] X with X = X1 X2, and [U, V]^T H_old [U, V]
+        // = blockdiag(sym(U^T C), T) (U^T H_old V = C^T V = 0; T from the CG coefficients)
+        const int s0 = rs->s_cur;
+        HIPCHK(launch_small_gemm(t0, t1, t, false, X1c, t0, Xinv, t1, Xp, t0, c->stream));
+        if (s0) HIPCHK(launch_gram(n, s0, s0, rs->U, rs->C, ws.part(), UtC, c->stream));
+        HIPCHK(launch_inner_y(s0, v_use, t, UtC, rs->lz, Xp, Yp, c->stream));
+        HIPCHK(launch_small_gemm(t, t0, t, true, Xp, t0, Yp, t0, M, t, c->stream));
+    }
     if (rgen) HIPCHK(launch_jac(S, xhat, W0, t, ws.d1(), ws.d2(), ws.part(), Gj, 1, c->stream));
     mark(c, 2);
     if (rgen) {
@@ -829,9 +862,10 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
                       : "(H W)^T (H W) is not positive definite";
         return (bl_status)gst;
     }
-    // U~ = W X~, C~ = Y X~, Z = W V_H~
+    // U~ = W X~, C~ = Y X~ (inner: s products with the new Hessian), Z = W V_H~
     HIPCHK(launch_gemm_tall(n, t, s_eff, W0, Xs, t, ws.Ut(), c->stream));
-    HIPCHK(launch_gemm_tall(n, t, s_eff, W1, Xs, t, ws.Ct(), c->stream));
+    if (!inner) HIPCHK(launch_gemm_tall(n, t, s_eff, W1, Xs, t, ws.Ct(), c->stream));
+    else HIPCHK(launch_hvp(S, false, xhat, ws.Ut(), ws.Ct(), s_eff, 4 * QTY, c->stream));
     HIPCHK(launch_gemm_tall(n, t, s_eff, W0, VHs, t, rs->Z, c->stream));
     HIPCHK(hipMemcpyAsync(rs->mu, mu_tmp, s_eff * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     // C~ = C R (two passes of Cholesky QR), U = U~ R^{-1}

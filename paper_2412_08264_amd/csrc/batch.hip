@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     // scalars of earlier launches, read before the reduction: rho_j (the apply of this
     // iteration) and, in block 0, the recycle coefficient accumulated so far
     const double rho = uni(st->rho2[j & 1]);
+    const bool keep_lz = m.y == 0 && sl.lz && uni(st->store_basis) && j < uni(st->v_cap);
     const bool acc_mine = m.y == 0 && (int)threadIdx.x < s;
     const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
     reduce_partials<WIDE ? 32 : 8>(rec, nb, 1 + s, tot);
@@ -91,6 +92,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     const double* e = tot + 1;
     if (acc_mine) st->zacc[threadIdx.x] = zacc0 - alpha * e[threadIdx.x];
     if (m.y == 0 && threadIdx.x == 0) st->alpha = alpha;
+    if (keep_lz && threadIdx.x == 0) sl.lz[2 * j] = alpha;
     double ce = 0.0;
 #pragma unroll
     for (int k = 0; k < UPRE; ++k)

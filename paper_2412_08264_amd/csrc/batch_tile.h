@@ -201,6 +201,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
         for (int k = threadIdx.x; k < zw; k += NT) st->zr[k] = tot[1 + k];
         if (threadIdx.x == 0) {
             st->rho2[j & 1] = rho;
+            if (store_basis && sl.lz) sl.lz[2 * j + 1] = rho;
             if (zw) st->est = dec.est;
             st->iters = j;
             if (j == 0) st->res0 = sqrt(rho);

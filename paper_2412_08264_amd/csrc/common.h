@@ -82,6 +82,7 @@ struct Slot {
     const double* C;
     const double* Z;
     double* V;
+    double* lz;                           // CG coefficients of the stored residuals: alpha_j at 2j, rho_j at 2j+1
     SolveState* st;
     double* rec_res;                      // records: residual (tiles), apply (tiles), update (pixel blocks)
     double* rec_app;

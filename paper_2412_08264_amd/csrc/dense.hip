@@ -1081,6 +1081,70 @@ __global__ void __launch_bounds__(SD_NT) k_rgen_side(int t, int side, const doub
     }
 }
 
+// ------------------------------------------------------------------ inner refresh (eq. subtle-old)
+// C = op(A) B for small dense matrices (column-major; op(A) = A, m x k at lda, or A^T with A
+// k x m at lda), one output element per thread.
+__global__ void __launch_bounds__(NT) k_small_gemm(int m, int k, int ncols, int trans_a, const double* __restrict__ A,
+                                                   int lda, const double* __restrict__ Bm, int ldb, double* __restrict__ Cm,
+                                                   int ldc) {
+    const int idx = blockIdx.x * NT + threadIdx.x;
+    if (idx >= m * ncols) return;
+    const int i = idx % m, j = idx / m;
+    double acc = 0.0;
+    if (trans_a)
+        for (int q = 0; q < k; ++q) acc += A[(size_t)i * lda + q] * Bm[(size_t)j * ldb + q];
+    else
+        for (int q = 0; q < k; ++q) acc += A[(size_t)q * lda + i] * Bm[(size_t)j * ldb + q];
+    Cm[(size_t)j * ldc + i] = acc;
+}
+
+// Y = M0 X for the previous solve's projected Hessian in the basis [U, V] (t0 = s0 + v columns):
+// M0 = blockdiag(sym(U^T C), T), T the tridiagonal matrix of the CG coefficients of the stored
+// residuals (alpha_j = lz[2j], rho_j = lz[2j+1]):
+//   T_aa = 1/alpha_a + (rho_a / rho_{a-1}) / alpha_{a-1},  T_{a,a+1} = -sqrt(rho_{a+1} / rho_a) / alpha_a.
+// X: t0 x t (ld t0), Y likewise; UtC: s0 x s0 (column-major).
+__global__ void __launch_bounds__(NT) k_inner_y(int s0, int v, int t, const double* __restrict__ UtC,
+                                                const double* __restrict__ lz, const double* __restrict__ X,
+                                                double* __restrict__ Y) {
+    const int t0 = s0 + v;
+    const int idx = blockIdx.x * NT + threadIdx.x;
+    if (idx >= t0 * t) return;
+    const int i = idx % t0, c = idx / t0;
+    const double* x = X + (size_t)c * t0;
+    double acc = 0.0;
+    if (i < s0) {
+        for (int q = 0; q < s0; ++q) acc += 0.5 * (UtC[(size_t)q * s0 + i] + UtC[(size_t)i * s0 + q]) * x[q];
+    } else {
+        const int a = i - s0;
+        const double al = lz[2 * a], rh = lz[2 * a + 1];
+        double d = 1.0 / al;
+        if (a > 0) {
+            const double alm = lz[2 * a - 2], rhm = lz[2 * a - 1];
+            d += (rh / rhm) / alm;
+            acc += -sqrt(rh / rhm) / alm * x[i - 1];
+        }
+        acc += d * x[i];
+        if (a + 1 < v) acc += -sqrt(lz[2 * a + 3] / rh) / al * x[i + 1];
+    }
+    Y[(size_t)c * t0 + i] = acc;
+}
+
+hipError_t launch_small_gemm(int m, int k, int ncols, bool trans_a, const double* A, int lda, const double* B, int ldb,
+                             double* C, int ldc, hipStream_t stream) {
+    if (m <= 0 || ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_small_gemm, dim3((m * ncols + NT - 1) / NT), dim3(NT), 0, stream, m, k, ncols,
+                       trans_a ? 1 : 0, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner_y(int s0, int v, int t, const double* UtC, const double* lz, const double* X, double* Y,
+                          hipStream_t stream) {
+    const int tot = (s0 + v) * t;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inner_y, dim3((tot + NT - 1) / NT), dim3(NT), 0, stream, s0, v, t, UtC, lz, X, Y);
+    return hipGetLastError();
+}
+
 size_t gsvd_scratch_doubles(int t, int p) {
     const size_t T2 = (size_t)t * t, P2 = (size_t)p * p, PT = (size_t)p * t, KM = T2 > P2 ? T2 : P2;
     const size_t m = t > p ? t : p;

@@ -428,6 +428,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.C = s ? rs->C : nullptr;
     v.Z = hg ? rs->Z : nullptr;
     v.V = store ? rs->V : nullptr;
+    v.lz = store ? rs->lz : nullptr;
     v.st = B.st;
     v.rec_res = B.rec_res;
     v.rec_app = B.rec_app;
@@ -750,6 +751,12 @@ void Batch::stats(int idx, bl_stats* out) const {
     if (h.rs && h.store_basis) {
         const int nv = h.hdr.iters + (out->status == BL_E_INDEFINITE ? 1 : 0);
         h.rs->v_cur = std::min(nv, h.v_cap);
+        // the CG coefficients describe the stored residuals up to the first residual replacement
+        // after the set-up (mixed precision): the relation of the later ones to them is broken
+        int vl = h.rs->lz ? std::min(h.rs->v_cur, h.hdr.iters) : 0;
+        for (int j : h.rr_js)
+            if (j > 0 && j < vl) vl = j;
+        h.rs->v_lz = vl;
     }
 }
 

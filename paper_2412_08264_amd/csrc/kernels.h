@@ -151,6 +151,12 @@ hipError_t launch_gsvd_select(int t, int p, int s, int size, const double* M, co
 // gsvd_scratch_doubles.
 hipError_t launch_ritz_select(int t, int s, int kind, int size, const double* M, const double* YtY, double* sc,
                               double* Xs, double* VHs, double* mu, int* info, hipStream_t stream);
+// Inner refresh: C = op(A) B for small column-major matrices, and Y = M0 X with M0 the previous
+// solve's projected Hessian in the basis [U, V] (blockdiag(sym(U^T C), T of the CG coefficients lz)).
+hipError_t launch_small_gemm(int m, int k, int ncols, bool trans_a, const double* A, int lda, const double* B, int ldb,
+                             double* C, int ldc, hipStream_t stream);
+hipError_t launch_inner_y(int s0, int v, int t, const double* UtC, const double* lz, const double* X, double* Y,
+                          hipStream_t stream);
 // Left (side 1) or mixed (side 2) RGen vectors from the right ones in Xs.
 hipError_t launch_rgen_side(int t, int side, const double* M, double* Xs, const int* info, hipStream_t stream);
 

@@ -168,7 +168,7 @@ def test_recycle_storage_layout_without_gpu():
     al = lambda b: -(-b // 256) * 256
     P = B.bl_problem(96, 80, 2, 1.5, B.BL_REG_TV, 0, 0, 0.0, 0, 0)
     n, s, v = 96 * 80, 10, 50
-    want = 3 * al(8 * n * s) + al(8 * s) + al(8 * n * v)
+    want = 3 * al(8 * n * s) + al(8 * s) + al(8 * n * v) + al(16 * v)
     assert B.lib.bl_recycle_bytes(C.byref(P), s, v) == want
     assert B.lib.bl_recycle_bytes(C.byref(P), 65, 0) == 0 and B.lib.bl_recycle_bytes(C.byref(P), 20, 237) == 0
     assert B.lib.bl_recycle_bytes(None, 4, 4) == 0
@@ -178,11 +178,12 @@ def test_recycle_storage_layout_without_gpu():
     assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base), want, C.byref(rs)) == B.BL_OK
     assert (rs.U, rs.C, rs.Z, rs.mu, rs.V) == (base, base + al(8 * n * s), base + 2 * al(8 * n * s),
                                                base + 3 * al(8 * n * s), base + 3 * al(8 * n * s) + al(8 * s))
-    assert (rs.s_max, rs.s_cur, rs.v_cap, rs.v_cur) == (s, 0, v, 0)
+    assert rs.lz == rs.V + al(8 * n * v)
+    assert (rs.s_max, rs.s_cur, rs.v_cap, rs.v_cur, rs.v_lz) == (s, 0, v, 0, 0)
     assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base), want - 1, C.byref(rs)) == B.BL_E_WORKSPACE
     assert B.lib.bl_recycle_init(C.byref(P), s, v, C.c_void_p(base + 8), want, C.byref(rs)) == B.BL_E_WORKSPACE
     assert B.lib.bl_recycle_init(C.byref(P), 65, v, C.c_void_p(base), want, C.byref(rs)) == B.BL_E_SHAPE
     assert B.lib.bl_recycle_init(C.byref(P), s, v, None, want, C.byref(rs)) == B.BL_E_ARG
     rs0 = B.bl_recycle()
     assert B.lib.bl_recycle_init(C.byref(P), 4, 0, C.c_void_p(base), want, C.byref(rs0)) == B.BL_OK
-    assert rs0.V is None and rs0.v_cap == 0
+    assert rs0.V is None and rs0.lz is None and rs0.v_cap == 0
