@@ -21,7 +21,9 @@ Other workloads (``--workload``):
   selections  the tv256 sequence refreshed by every selection rule of Table 2 (Ritz, harmonic
            Ritz, sides of RGen-L), recycled CG with the residual stop;
   train    tv256 trained end to end (not a frozen sequence) with recycled CG, RMINRES and plain
-           CG hypergradients; wall time per outer iteration and its split.
+           CG hypergradients; wall time per outer iteration and its split;
+  sweep    tv256 over recycle dimensions s and stored-basis capacities v_cap, outer and inner
+           refreshes, with plain CG beside them.
 """
 from __future__ import annotations
 
@@ -184,12 +186,13 @@ def make_trajectory(ctx, P, B, wl, torch, y, xs, theta0, outer, gtol=1e-8):
 
 
 def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID_TOL, rr_every=50,
-                 first_tol=RESID_TOL, check_every=1):
+                 first_tol=RESID_TOL, check_every=1, inner=False):
     """One pass over the sequence.  mode: 'rgen_hg' | 'rgen_res' | 'plain' (recycled CG, or CG)
     | 'rminres_hg' | 'minres' (RMINRES with the error-estimate stop, or MINRES); thr: the stopping
     threshold (residual tolerance, or the error-estimate threshold relative to the previous
     hypergradient norm); first_tol: residual tolerance of the error-estimate variant's first
-    system, which has no recycle space yet (the threshold of the variant without recycling).
+    system, which has no recycle space yet (the threshold of the variant without recycling);
+    inner: refreshes by the inner variant (eq. subtle-old) instead of the outer one.
     Returns per-solve records."""
     method = "rminres" if mode in ("rminres_hg", "minres") else "cg"
     kind = {"rminres_hg": "rgen_hg", "minres": "plain"}.get(mode, mode)
@@ -201,7 +204,7 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
         t0 = time.perf_counter()
         g = x - xs
         if kind != "plain" and i > 0:
-            S.refresh(th, x, s=S.rs.s_max)
+            S.refresh(th, x, s=S.rs.s_max, inner=inner)
         if kind == "rgen_hg" and S.rs.s_cur > 0 and prev_hg is not None:
             st = S.solve(th, x, g, w, stop="hgerr", hg_tol=thr * prev_hg, tol=RESID_TOL, store_basis=True,
                          rr_every=rr_every, check_every=check_every, method=method)
@@ -215,25 +218,26 @@ def run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat=None, thr=RESID
         if lat is not None:
             lat.append((t1 - t0) * 1e3)
         prev_hg = float(np.linalg.norm(hg))
-        recs.append({"iters": st.iters, "err": rel_err(hg, refs[i]), "status": st.status})
+        recs.append({"iters": st.iters, "err": rel_err(hg, refs[i]), "status": st.status, "hg": hg})
     return recs
 
 
-def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep, first_tol=RESID_TOL, check_every=1):
+def choose_threshold(S, B, torch, thetas, xhats, xs, mode, refs, sweep, first_tol=RESID_TOL, check_every=1,
+                     inner=False):
     for thr in sweep:
         rr = run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, thr=thr, first_tol=first_tol,
-                          check_every=check_every)
+                          check_every=check_every, inner=inner)
         if all(r["err"] <= 1e-6 and r["status"] == 0 for r in rr):
             return thr
     return sweep[-1]
 
 
 def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=None, first_tol=RESID_TOL,
-                 check_every=1):
+                 check_every=1, inner=False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [run_sequence(S, B, torch, thetas, xhats, xs, mode, refs, lat, thr=thr, first_tol=first_tol,
-                         check_every=check_every) for _ in range(steps)]
+                         check_every=check_every, inner=inner) for _ in range(steps)]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
@@ -241,40 +245,120 @@ def timed_passes(S, B, torch, thetas, xhats, xs, mode, refs, thr, steps, lat=Non
     return recs, el, ok, total
 
 
-def cpu_baseline_sequence(wl, seconds_budget=25.0):
-    """The CPU oracle timed on a bounded sample of the same workload (consecutive systems).
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The oracle takes no input from the GPU path, so the sample uses stand-in points
-    x_hat = x* + 0.05 e' (e' a separate seeded normal field) and a theta path stepping
-    away from the initial value; each system is refreshed, solved by recycled CG
-    (residual stop 1e-10) and mapped to its hypergradient, as on the GPU.
-    """
-    import synth
+
+def cpu_baseline_sequence(wl, thetas, xhats, xs_t, ftol, thr, check_every, gpu_iters_per_solve, budget_s=12.0):
+    """The CPU oracle on the benchmark's own systems with the headline's stop rules, over a bounded
+    sample scaled to solves/s.
+
+    One tv256 system takes the oracle longer than the sample's budget, so the sample is: the
+    first system's solve (plain CG, residual stop ftol) cut at the iteration count that fits the
+    budget, timed per iteration; the refresh of the second system from that run's basis (outer
+    RGen-L(R): t products, projected GSVD, U, C, Z) and one hypergradient, timed once.  The
+    oracle's time per solve is then refresh + hypergradient + (the GPU headline's mean
+    iterations per solve) x (time per iteration).  Run twice: with the BLAS threads of every
+    affinity core, and with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     from oracle import krylov, problem, recycle
+    import synth
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    xs = xs_t.detach().cpu().numpy()
+    th0, x0 = thetas[0], xhats[0].detach().cpu().numpy()
+    th1, x1 = thetas[1], xhats[1].detach().cpu().numpy()
+
+    def one(limit):
+        with threadpool_limits(limits=limit):
+            hvp0 = lambda v: prob.hvp(x0, th0, v)
+            t0 = time.perf_counter()
+            for _ in range(5):
+                hvp0(x0)
+            per = (time.perf_counter() - t0) / 5
+            k = max(10, int(0.7 * budget_s / per))
+            t0 = time.perf_counter()
+            res = krylov.recycled_cg(hvp0, x0 - xs, None, tol=ftol, max_iter=k, v_cap=V_CAP)
+            t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
+            t0 = time.perf_counter()
+            rs = recycle.refresh(lambda v: prob.hvp(x1, th1, v), lambda v: prob.jac_apply(x1, th1, v), None, res["V"],
+                                 wl.s)
+            t_ref = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            prob.jac_apply(x1, th1, res["w"])
+            t_hg = time.perf_counter() - t0
+            per_solve = t_ref + t_hg + gpu_iters_per_solve * t_it
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+            return 1.0 / per_solve, res["iters"], t_it, t_ref, t_hg, threads
+
+    v_all, it_all, tit_all, tref_all, thg_all, thr_all = one(None)
+    v_one, _, tit_one, tref_one, _, _ = one(1)
+    ncores = len(os.sched_getaffinity(0))
+    return {"value": v_all, "unit": "solves/s", "cores": ncores, "kind": "oracle",
+            "sample": (f"oracle on the bench's own {wl.h}x{wl.w} systems: {it_all} CG iterations of system 0 "
+                       f"({tit_all * 1e3:.1f} ms each), the outer RGen-L(R) refresh of system 1 ({tref_all:.2f} s) "
+                       f"and a hypergradient ({thg_all * 1e3:.0f} ms), scaled to one solve of the headline's mean "
+                       f"{gpu_iters_per_solve:.0f} iterations (the threshold rule {thr:g} x previous |grad| "
+                       f"decides those on the GPU); NumPy FP64"),
+            "blas_threads": int(thr_all), "cpu_model": cpu_model(),
+            "value_1thread": v_one, "ms_per_iter_1thread": tit_one * 1e3, "refresh_s_1thread": tref_one}
+
+
+def oracle_reference_worker(inp: str, outp: str) -> None:
+    """Child process of the benchmark: the oracle's reference hypergradients (plain CG to relative
+    residual 1e-13 with true-residual replacement, Section 5's reference) for the listed systems."""
+    import synth
+    from oracle import krylov, problem
+    d = np.load(inp, allow_pickle=False)
+    wl = synth.WORKLOADS[str(d["workload"])]
     inst = synth.instance(wl)
     prob = problem.make_problem(wl, inst["xstar"], inst["e"])
     xs = inst["xstar"].ravel()
-    xh = xs + 0.05 * synth.unit_noise(prob.n, wl.seed + 77)
-    path = synth.theta_drift(wl, 3, wl.seed + 78, scale=0.01)
-    U = V = None
-    w = None
-    done = 0
-    t0 = time.perf_counter()
-    for th in path:
-        hvp = lambda v, th=th: prob.hvp(xh, th, v)
-        jac = lambda v, th=th: prob.jac_apply(xh, th, v)
-        rs = recycle.refresh(hvp, jac, U, V, wl.s) if (U is not None or V is not None) else {"U": None, "C": None}
-        res = krylov.recycled_cg(hvp, xh - xs, w, rs["U"], rs["C"], tol=RESID_TOL, v_cap=V_CAP)
-        jac(res["w"])
-        U, V, w = rs["U"], res["V"], res["w"]
-        done += 1
-        if time.perf_counter() - t0 > seconds_budget:
-            break
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "solves/s", "cores": int(threads_used()), "kind": "oracle",
-            "sample": f"{done} consecutive {wl.h}x{wl.w} {wl.reg} systems (refresh + recycled CG 1e-10 + "
-                      f"hypergradient) at stand-in points x*+0.05e', numpy FP64, {el:.1f} s; host "
-                      f"{len(os.sched_getaffinity(0))} affinity cores"}
+    hgs, its = [], []
+    for th, xh in zip(d["thetas"], d["xhats"]):
+        w, it = krylov.reference_solve(lambda v: prob.hvp(xh, th, v), xh - xs, tol=1e-13)
+        hgs.append(prob.jac_apply(xh, th, w))
+        its.append(it)
+    np.savez(outp, hg=np.stack(hgs), iters=np.array(its))
+
+
+def start_oracle_gate(wl, thetas, xhats, idx):
+    import subprocess
+    import tempfile
+    d = tempfile.mkdtemp(prefix="bench_oracle_")
+    inp, outp = os.path.join(d, "in.npz"), os.path.join(d, "out.npz")
+    np.savez(inp, workload=np.array(wl.name), thetas=np.stack([thetas[i] for i in idx]),
+             xhats=np.stack([xhats[i].detach().cpu().numpy() for i in idx]))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-ref", inp, outp],
+                            stdout=subprocess.DEVNULL, stderr=subprocess.PIPE, env=env)
+    return {"proc": proc, "out": outp, "idx": list(idx), "t0": time.perf_counter()}
+
+
+def finish_oracle_gate(gate, hgs_by_variant, timeout_s=300.0):
+    """Relative error of each listed variant's hypergradients against the oracle's references."""
+    try:
+        gate["proc"].wait(timeout=max(1.0, timeout_s - (time.perf_counter() - gate["t0"])))
+    except Exception:
+        gate["proc"].kill()
+        return {"systems": gate["idx"], "error": "oracle reference timed out"}
+    if gate["proc"].returncode != 0 or not os.path.exists(gate["out"]):
+        err = gate["proc"].stderr.read().decode()[-400:] if gate["proc"].stderr else ""
+        return {"systems": gate["idx"], "error": f"oracle reference failed: {err}"}
+    d = np.load(gate["out"], allow_pickle=False)
+    out = {"systems": gate["idx"], "oracle_cg_iters": [int(v) for v in d["iters"]],
+           "seconds": round(time.perf_counter() - gate["t0"], 1)}
+    for name, hgs in hgs_by_variant.items():
+        out[f"{name}_vs_oracle"] = [rel_err(np.asarray(h), o) for h, o in zip(hgs, d["hg"])]
+    return out
 
 
 def bench_selections(args, B, torch, synth):
@@ -348,6 +432,86 @@ def bench_selections(args, B, torch, synth):
                      selections=out_rules)
 
 
+SWEEP_GRID = ((20, 64), (10, 64), (50, 64), (20, 128), (20, 236), (10, 246), (50, 206))
+
+
+def bench_sweep(args, B, torch, synth):
+    """tv256: recycled CG with RGen-L(R) and the error-estimate stop (Section 5.1, "Dimension of the
+    recycle space") at recycle dimensions s and stored-basis capacities v_cap (s + v_cap <= 256, the
+    refresh's limit), outer and inner refreshes, each at the loosest threshold of SWEEP_HG that
+    keeps every hypergradient within 1e-6; plain CG beside them.  Reports iterations per pass,
+    solves/s and the mean refresh time of each setting."""
+    wl = synth.WORKLOADS["tv256"]
+    outer = args.outer or wl.outer
+    dev = torch.device("cuda:0")
+    inst = synth.instance(wl)
+    P64 = B.problem_from(wl, prec="fp64")
+    S0 = B.Session(P64, s_max=wl.s, v_cap=V_CAP, device=dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1)
+    xs, e = t(inst["xstar"]), t(inst["e"])
+    y = torch.empty_like(xs)
+    S0.forward(xs, e, wl.noise, y)
+    thetas, xhats = make_trajectory(S0, P64, B, wl, torch, y, xs, inst["theta0"], outer)
+    refs = []
+    w = torch.zeros_like(xs)
+    for th, x in zip(thetas, xhats):
+        w.zero_()
+        S0.solve(th, x, x - xs, w, tol=1e-13, store_basis=False, recycle=False, max_iter=100000,
+                 allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+        refs.append(S0.hypergradient(th, x, w))
+    tiles = autotune_tiles(S0, B, [(S0.P, thetas[0], xhats[0], wl.s)])
+    ftol = choose_threshold(S0, B, torch, thetas, xhats, xs, "plain", refs, SWEEP_RESID)
+    rr, el, ok, tot = timed_passes(S0, B, torch, thetas, xhats, xs, "plain", refs, ftol, args.steps)
+    rows = [{"s": 0, "v_cap": 0, "refresh": "-", "threshold": ftol, "iters_per_sequence": sum(r["iters"] for r in rr[0]),
+             "solves_per_s": ok / el, "passing": f"{ok}/{tot}"}]
+    log(f"[bench] sweep plain: {rows[-1]}")
+    S0.close()
+    for s_, vc in SWEEP_GRID:
+        S = B.Session(P64, s_max=s_, v_cap=vc, device=dev)
+        for inner in (False, True):
+            thr = choose_threshold(S, B, torch, thetas, xhats, xs, "rgen_hg", refs, SWEEP_HG, first_tol=ftol,
+                                   check_every=args.check_every, inner=inner)
+            S.set_timing(1)
+            ref_ms = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs = []
+            for _ in range(args.steps):
+                S.reset()
+                wv = torch.zeros_like(xs)
+                prev_hg = None
+                rec = []
+                for i, (th, x) in enumerate(zip(thetas, xhats)):
+                    if i > 0:
+                        st = S.refresh(th, x, s=s_, inner=inner)
+                        ref_ms.append(st.ms[3])
+                    if S.rs.s_cur > 0 and prev_hg is not None:
+                        st = S.solve(th, x, x - xs, wv, stop="hgerr", hg_tol=thr * prev_hg, tol=RESID_TOL,
+                                     check_every=args.check_every)
+                    else:
+                        st = S.solve(th, x, x - xs, wv, tol=ftol)
+                    hg = S.hypergradient(th, x, wv)
+                    prev_hg = float(np.linalg.norm(hg))
+                    rec.append({"iters": st.iters, "err": rel_err(hg, refs[i]), "status": st.status})
+                recs.append(rec)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            S.set_timing(0)
+            ok = sum(1 for rr in recs for r in rr if r["err"] <= 1e-6 and r["status"] == 0)
+            tot = sum(len(rr) for rr in recs)
+            rows.append({"s": s_, "v_cap": vc, "refresh": "inner" if inner else "outer", "threshold": thr,
+                         "iters_per_sequence": sum(r["iters"] for r in recs[0]), "solves_per_s": ok / el,
+                         "passing": f"{ok}/{tot}", "refresh_ms": float(np.mean(ref_ms)) if ref_ms else 0.0})
+            log(f"[bench] sweep: {rows[-1]}")
+        S.close()
+    best = max(rows[1:], key=lambda r: r["solves_per_s"])
+    desc = (f"sweep: tv256 ({wl.h}x{wl.w} smoothed-TV, {outer} frozen outer steps), recycled CG with RGen-L(R) and "
+            f"the error-estimate stop over recycle dimension s and stored-basis capacity v_cap, outer and inner "
+            f"refreshes; plain CG beside them")
+    return base_line(args, best["solves_per_s"], 0.0, "f64", {"workload": desc, "outer_steps": outer, "tiles": tiles},
+                     sweep=rows, best=best, plain_cg=rows[0])
+
+
 def bench_train(args, B, torch, synth):
     """tv256 trained end to end (Algorithm 2 with Algorithm 1's backtracking, `outer` steps from
     theta0): hypergradients by recycled CG with RGen-L(R) and the error-estimate stop, by RMINRES
@@ -399,13 +563,17 @@ def bench_sequence(args, B, torch, synth):
     tt = time.perf_counter()
     thetas, xhats = make_trajectory(S, P64, B, wl, torch, y, xs, inst["theta0"], outer)
     log(f"[bench] trajectory built in {time.perf_counter() - tt:.1f} s; reference hypergradients")
-    refs = []
+    refs, ref_ok = [], 0
     w = torch.zeros_like(xs)
     for th, x in zip(thetas, xhats):
         w.zero_()
-        S.solve(th, x, x - xs, w, tol=1e-13, store_basis=False, recycle=False, max_iter=100000,
-                allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+        st = S.solve(th, x, x - xs, w, tol=1e-13, store_basis=False, recycle=False, max_iter=100000,
+                     allow=(B.BL_OK, B.BL_E_NOT_CONVERGED))
+        ref_ok += st.status == B.BL_OK
         refs.append(S.hypergradient(th, x, w))
+    if ref_ok < len(refs):
+        log(f"[bench] WARNING: {len(refs) - ref_ok} reference solves stopped at the iteration limit "
+            "before relative residual 1e-13: the run is marked failed")
     mixed = wl.prec == "mixed"
     Sh = B.Session(B.problem_from(wl, prec="mixed"), s_max=wl.s, v_cap=V_CAP, device=dev) if mixed else S
     if args.rows:   # a fixed tile height (profiling runs repeat the height a timed run chose)
@@ -415,7 +583,8 @@ def bench_sequence(args, B, torch, synth):
     else:
         tiles = autotune_tiles(S, B, [(Sh.P, thetas[0], xhats[0], wl.s), (S.P, thetas[0], xhats[0], wl.s)])
     # threshold selection (untimed): loosest setting with every hypergradient within 1e-6
-    variants = [("rgen_hg", Sh, SWEEP_HG), ("rgen_res", Sh, SWEEP_RESID), ("plain", S, SWEEP_RESID)]
+    variants = [("rgen_hg", Sh, SWEEP_HG), ("rgen_res", Sh, SWEEP_RESID), ("plain", S, SWEEP_RESID),
+                ("rgen_hg_inner", Sh, SWEEP_HG)]
     if mixed:
         variants.append(("rgen_hg_fp64", S, SWEEP_HG))
     # the paper's own solver (FP64): RMINRES with the error-estimate stop, and MINRES
@@ -426,9 +595,11 @@ def bench_sequence(args, B, torch, synth):
     first_of = lambda name: chosen.get("minres" if name == "rminres_hg" else "plain", RESID_TOL)
     order = [v for v in variants if v[0] in ("plain", "minres")] + [v for v in variants
                                                                     if v[0] not in ("plain", "minres")]
+    mode_of = lambda name: name.replace("_fp64", "").replace("_inner", "")
     for name, SS, sweep in order:
-        chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, name.replace("_fp64", ""), refs, sweep,
-                                        first_tol=first_of(name), check_every=args.check_every)
+        chosen[name] = choose_threshold(SS, B, torch, thetas, xhats, xs, mode_of(name), refs, sweep,
+                                        first_tol=first_of(name), check_every=args.check_every,
+                                        inner=name.endswith("_inner"))
         log(f"[bench] {name}: threshold {chosen[name]:g}")
     ftol = chosen["plain"]
     for _ in range(args.warmup):
@@ -443,16 +614,17 @@ def bench_sequence(args, B, torch, synth):
     kt = Sh.kernel_times(reset=True)
     Sh.set_timing(0)
     value = ok / el
-    extra = {}
+    extra, hg_of = {}, {}
     for name, SS, _ in variants[1:]:
-        mode = name.replace("_fp64", "")
+        mode, inner = mode_of(name), name.endswith("_inner")
         run_sequence(SS, B, torch, thetas, xhats, xs, mode, refs, thr=chosen[name], first_tol=first_of(name),
-                     check_every=args.check_every)
+                     check_every=args.check_every, inner=inner)
         rr, elm, okm, totm = timed_passes(SS, B, torch, thetas, xhats, xs, mode, refs, chosen[name], args.steps,
-                                          first_tol=first_of(name), check_every=args.check_every)
+                                          first_tol=first_of(name), check_every=args.check_every, inner=inner)
         extra[name] = {"solves_per_s": okm / elm, "threshold": chosen[name],
                        "iters_per_sequence": sum(r["iters"] for r in rr[0]),
                        "max_rel_err": max(r["err"] for r in rr[0]), "passing": f"{okm}/{totm}"}
+        hg_of[name] = rr[0]
     head = recs[0]
     iters_seq = sum(r["iters"] for r in head)
     prec = "mixed" if mixed else "fp64"
@@ -472,8 +644,11 @@ def bench_sequence(args, B, torch, synth):
                     iters_per_sequence={"rgen_hg": iters_seq, **{k: v["iters_per_sequence"] for k, v in extra.items()}},
                     max_rel_err=max(r["err"] for r in head),
                     speedup_vs_plain_cg=value / extra["plain"]["solves_per_s"],
-                    plain_cg=extra["plain"], rgen_resid=extra["rgen_res"],
+                    reference_converged=f"{ref_ok}/{len(refs)}",
+                    plain_cg=extra["plain"], rgen_resid=extra["rgen_res"], rgen_inner=extra["rgen_hg_inner"],
                     roofline=roofline(kname, bpp * wl.n, kt, args.workload))
+    if ref_ok < len(refs):
+        out["status"] = "failed: reference solves did not converge"
     if mixed:
         out["rgen_hg_fp64"] = extra["rgen_hg_fp64"]
     out["rminres"] = extra["rminres_hg"]
@@ -482,8 +657,19 @@ def bench_sequence(args, B, torch, synth):
         log("[bench] HBM microbenchmark (4096 x 4096)")
         out["hbm_micro"] = hbm_micro(args, B, torch, synth)
     if not args.no_cpu:
+        # the CPU leg, after every GPU timing (host work beside the timed GPU runs would slow their
+        # launches): the oracle timed on the same systems, and its reference hypergradients of the
+        # first and last systems (in a child process) as a gate on the GPU's own references and on
+        # the headline's results
         log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline_sequence(wl)
+        out["cpu_baseline"] = cpu_baseline_sequence(wl, thetas, xhats, xs, ftol, chosen["rgen_hg"], args.check_every,
+                                                    iters_seq / len(thetas))
+        log("[bench] the oracle's reference hypergradients of the first and last systems")
+        gate = start_oracle_gate(wl, thetas, xhats, [0, len(thetas) - 1])
+        idx = gate["idx"]
+        pick = lambda recs: [recs[i]["hg"] for i in idx]
+        out["cpu_baseline"]["oracle_gate"] = finish_oracle_gate(
+            gate, {"reference": [refs[i] for i in idx], "headline": pick(head), "plain_cg": pick(hg_of["plain"])})
     S.close()
     if Sh is not S:
         Sh.close()
@@ -1009,7 +1195,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve", "selections", "train"))
+    ap.add_argument("--workload", default="tv256", choices=("tv256", "tv32", "foe512", "batch64", "serve", "selections", "train",
+                                                      "sweep"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", dest="no_micro", action="store_true",
                     help="skip the 4096 x 4096 HBM microbenchmark of the default workload")
@@ -1035,10 +1222,15 @@ def main():
                     help="iterations between error-estimate tests (Z^T r is formed on tested iterations only)")
     ap.add_argument("--rows", type=int, default=0, choices=(0, 8, 16, 32),
                     help="tile height of the solves (0: autotune; kernels-only batch64: 0 means 32)")
+    ap.add_argument("--oracle-ref", dest="oracle_ref", nargs=2, metavar=("IN", "OUT"),
+                    help="internal: the oracle's reference hypergradients for the systems in IN (host only)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: a few recycled-CG iterations on the workload's shape at stand-in points "
                          "x* + 0.05 e' (no trajectory) plus a 64 MiB device copy for counter calibration")
     args = ap.parse_args()
+    if args.oracle_ref:
+        oracle_reference_worker(*args.oracle_ref)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-sample solves are "
               "independent: several GPUs would each hold and solve their own samples.", file=sys.stderr)
@@ -1063,6 +1255,8 @@ def main():
         out = bench_selections(args, B, torch, synth)
     elif args.workload == "train":
         out = bench_train(args, B, torch, synth)
+    elif args.workload == "sweep":
+        out = bench_sweep(args, B, torch, synth)
     else:
         out = bench_sequence(args, B, torch, synth)
     print(json.dumps(out), flush=True)

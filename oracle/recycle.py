@@ -4,7 +4,8 @@ Outer variant (eq. subtle-new): the space for system i is extracted from
 W = [U^{(i-1)}, V^{(i-1)}] using the *new* Hessian H^{(i)} and adjoint Jacobian J^{(i)}.
 Inner variant (eq. subtle-old): the projected matrix uses the previous Hessian H^{(i-1)}
 (what the previous solve's Lanczos relation already holds); only the s chosen vectors are
-multiplied by H^{(i)}.
+multiplied by H^{(i)}.  It takes the semi-orthogonal leading part of the stored basis
+(:func:`semiorthogonal_prefix`).
 
 Readings taken where the paper is silent:
   * W is orthonormalised before projecting (the paper's W is only "full rank";
@@ -236,9 +237,13 @@ def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL, 
 
     Selections other than RGen leave mu = 0 and Z = 0: the error-estimate test is then undefined
     and solves use the residual test."""
+    v_used = 0 if V_prev is None else V_prev.shape[1]
+    if hvp_old is not None and V_prev is not None:
+        v_used = semiorthogonal_prefix(V_prev)
+        V_prev = V_prev[:, :v_used]
     blocks = [B for B in (U_prev, V_prev) if B is not None and B.shape[1] > 0]
     if not blocks or s <= 0:
-        return {"U": None, "C": None, "Z": None, "mu": None, "t": 0, "rank_G": 0}
+        return {"U": None, "C": None, "Z": None, "mu": None, "t": 0, "rank_G": 0, "v_used": v_used}
     W, kept = orthonormalize(np.concatenate(blocks, axis=1), rank_tol)
     t = W.shape[1]
     proj = hvp if hvp_old is None else hvp_old
@@ -256,8 +261,26 @@ def refresh(hvp, jac_apply, U_prev, V_prev, s: int, rank_tol: float = RANK_TOL, 
         Ynew = np.stack([hvp(W @ X[:, c]) for c in range(X.shape[1])], axis=1)
         out = build_from_selection(W, Ynew, dict(sel, X=np.eye(X.shape[1])), Ut=W @ X)
     out.update({"t": t, "rank_G": sel["rank_G"], "W": W, "M": M, "G": G, "Y": Y, "sel": sel,
-                "dropped": len(np.concatenate(blocks, axis=1).T) - len(kept)})
+                "dropped": len(np.concatenate(blocks, axis=1).T) - len(kept), "v_used": v_used})
     return out
+
+
+SEMIORTH_TOL = 2.0 ** -26    # sqrt of the FP64 unit roundoff
+
+
+def semiorthogonal_prefix(V: np.ndarray, tol: float = SEMIORTH_TOL) -> int:
+    """Number of leading columns of a stored Krylov basis that are semi-orthogonal: every pair
+    |v_i . v_j| and every |v_j . v_j - 1| within sqrt(eps).  Reading for the inner refresh: the
+    previous solve's relation V^T H V = T (eq. arnoldi_aug_matrix in CG form) holds to working
+    precision only while the computed basis keeps this property (Simon's semi-orthogonality
+    condition for the Lanczos process); the residuals after the first column that breaks it are
+    not used.  Applied by the oracle's inner refresh so that both sides project the same basis."""
+    Gm = V.T @ V
+    k = V.shape[1]
+    for j in range(k):
+        if abs(Gm[j, j] - 1.0) > tol or (j > 0 and np.abs(Gm[:j, j]).max() > tol):
+            return j
+    return k
 
 
 def cg_lanczos_matrix(alpha: np.ndarray, rho: np.ndarray) -> np.ndarray:

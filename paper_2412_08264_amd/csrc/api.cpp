@@ -766,8 +766,8 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
     const int n = P->h * P->w, p = nparams(P);
     // inner: the stored residuals the CG coefficients describe (all of them, unless a residual
     // replacement of a mixed-precision solve cut the relation short)
-    const int v_use = inner ? rs->v_lz : rs->v_cur;
-    const int t0 = rs->s_cur + v_use;
+    int v_use = inner ? rs->v_lz : rs->v_cur;
+    int t0 = rs->s_cur + v_use;
     if (out) std::memset(out, 0, sizeof(*out));
     if (t0 == 0 || o->s == 0) {
         rs->s_cur = 0;
@@ -806,6 +806,22 @@ bl_status bl_recycle_update(bl_ctx* c, const bl_problem* P, const double* theta,
                               hipMemcpyDeviceToDevice, c->stream));
     // two passes of Cholesky QR with column drop: W = [U, V] X1 X2
     HIPCHK(launch_gram(n, t0, t0, W0, W0, ws.part(), Gram, c->stream));
+    if (inner && v_use > 0) {
+        // the previous solve's relation V^T H V = T holds to working precision only over the
+        // semi-orthogonal leading part of its stored residuals (Simon's condition): keep that part
+        HIPCHK(launch_semiorth_prefix(t0, rs->s_cur, Gram, 0x1p-26, tk_dev + 1, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_info, tk_dev + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->h_info[0] < v_use) {
+            v_use = c->h_info[0];
+            t0 = rs->s_cur + v_use;
+            if (t0 == 0) {
+                rs->s_cur = 0;
+                return c->err = "inner refresh: no semi-orthogonal stored residual", BL_E_RANK;
+            }
+            HIPCHK(launch_gram(n, t0, t0, W0, W0, ws.part(), Gram, c->stream));
+        }
+    }
     HIPCHK(launch_chol_drop(t0, Gram, o->rank_tol, Achol, kept, tk_dev, Xinv, t0, c->stream));
     HIPCHK(hipMemcpyAsync(c->h_info, tk_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -1129,6 +1129,30 @@ __global__ void __launch_bounds__(NT) k_inner_y(int s0, int v, int t, const doub
     Y[(size_t)c * t0 + i] = acc;
 }
 
+// Leading columns of a stored basis that are semi-orthogonal, from the Gram matrix of [U, V]
+// (t0 x t0, V in columns s0 ..): column j of V qualifies while |G_jj - 1| and every |G_ij| with
+// i < j in the V block are within tol; out[0] = the first column that breaks it (or all of V).
+__global__ void __launch_bounds__(SD_NT) k_semiorth_prefix(int t0, int s0, const double* __restrict__ G, double tol,
+                                                           int* __restrict__ out) {
+    __shared__ int first;
+    const int v = t0 - s0;
+    if (threadIdx.x == 0) first = v;
+    __syncthreads();
+    for (int j = threadIdx.x; j < v; j += blockDim.x) {
+        const double* col = G + (size_t)(s0 + j) * t0;
+        bool bad = fabs(col[s0 + j] - 1.0) > tol;
+        for (int i = 0; i < j && !bad; ++i) bad = fabs(col[s0 + i]) > tol;
+        if (bad) atomicMin(&first, j);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = first;
+}
+
+hipError_t launch_semiorth_prefix(int t0, int s0, const double* G, double tol, int* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_semiorth_prefix, dim3(1), dim3(SD_NT), 0, stream, t0, s0, G, tol, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_small_gemm(int m, int k, int ncols, bool trans_a, const double* A, int lda, const double* B, int ldb,
                              double* C, int ldc, hipStream_t stream) {
     if (m <= 0 || ncols <= 0) return hipSuccess;

@@ -155,6 +155,7 @@ hipError_t launch_ritz_select(int t, int s, int kind, int size, const double* M,
 // solve's projected Hessian in the basis [U, V] (blockdiag(sym(U^T C), T of the CG coefficients lz)).
 hipError_t launch_small_gemm(int m, int k, int ncols, bool trans_a, const double* A, int lda, const double* B, int ldb,
                              double* C, int ldc, hipStream_t stream);
+hipError_t launch_semiorth_prefix(int t0, int s0, const double* G, double tol, int* out, hipStream_t stream);
 hipError_t launch_inner_y(int s0, int v, int t, const double* UtC, const double* lz, const double* X, double* Y,
                           hipStream_t stream);
 // Left (side 1) or mixed (side 2) RGen vectors from the right ones in Xs.

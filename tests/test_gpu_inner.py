@@ -129,3 +129,28 @@ def test_solve_records_cg_coefficients(B):
         assert S.rs.v_lz == 0 and S.rs.v_cur > 0
         with pytest.raises(B.BLError):
             S.refresh(t1, dev(x1), s=6, inner=True)
+
+
+def test_inner_refresh_long_basis_takes_semiorthogonal_prefix(B):
+    """A stored basis of 120 residuals from a long solve has lost orthogonality: both sides keep
+    its semi-orthogonal leading part (the oracle from V^T V, the GPU from its Gram matrix), and
+    the refreshes agree."""
+    wl, prob, xs, (x0, t0), (x1, t1) = pair("tv", 40, 52, 191)
+    h0 = lambda v: prob.hvp(x0, t0, v)
+    h1 = lambda v: prob.hvp(x1, t1, v)
+    prev = krylov.cg(h0, x0 - xs, tol=1e-13, v_cap=120)
+    assert prev["V"].shape[1] == 120
+    k = recycle.semiorthogonal_prefix(prev["V"])
+    assert 6 < k < 120
+    ref = recycle.refresh(h1, lambda v: prob.jac_apply(x1, t1, v), None, prev["V"], s=6, hvp_old=h0)
+    assert ref["v_used"] == k and ref["t"] == k
+    with B.Session(B.problem_from(wl, prec="fp64"), s_max=6, v_cap=120) as S:
+        S.V[:120] = dev(prev["V"].T)
+        S.lz[:240] = dev(lz_of(prev))
+        S.rs.v_cur = S.rs.v_lz = 120
+        st = S.refresh(t1, dev(x1), s=6, inner=True)
+        assert st.t == k and S.rs.s_cur == 6
+        U = host(S.U[:6]).T
+        assert recycle.principal_angles(U, ref["U"]).max() <= 1e-6
+        mu = host(S.mu[:2])
+        assert np.abs(mu - ref["mu"][:2]).max() <= 1e-8 * ref["mu"][0]

@@ -264,3 +264,25 @@ def test_inner_equals_outer_for_an_unchanged_hessian():
     assert recycle.principal_angles(a["U"], b["U"]).max() <= 1e-9
     assert recycle.principal_angles(a["C"], b["C"]).max() <= 1e-9
     assert recycle.principal_angles(a["Z"][:, :2], b["Z"][:, :2]).max() <= 1e-9
+
+
+def test_semiorthogonal_prefix():
+    """Leading columns with pairwise products and norms within sqrt(eps) of orthonormal; a
+    column breaking it ends the prefix, whatever follows."""
+    rng = np.random.default_rng(5)
+    Q = np.linalg.qr(rng.standard_normal((60, 12)))[0]
+    assert recycle.semiorthogonal_prefix(Q) == 12
+    Qb = Q.copy()
+    Qb[:, 7] += 1e-6 * Qb[:, 2]
+    Qb[:, 7] /= np.linalg.norm(Qb[:, 7])
+    assert recycle.semiorthogonal_prefix(Qb) == 7
+    Qn = Q.copy()
+    Qn[:, 4] *= 1.0 + 1e-7
+    assert recycle.semiorthogonal_prefix(Qn) == 4
+    # CG residuals of a long solve lose orthogonality: the prefix stops before the end
+    prob, xs, (x0, t0), _ = _tv_pair(161)
+    res = krylov.cg(lambda v: prob.hvp(x0, t0, v), x0 - xs, tol=1e-14, v_cap=200)
+    k = recycle.semiorthogonal_prefix(res["V"])
+    assert 10 < k < res["V"].shape[1]
+    Vk = res["V"][:, :k]
+    assert np.abs(Vk.T @ Vk - np.eye(k)).max() <= recycle.SEMIORTH_TOL
