@@ -12,6 +12,14 @@ system solved by recycled CG or RMINRES (refresh of U, C, Z, mu from the previou
 space and Krylov basis, warm start from the previous solution) instead of the reference solve;
 the hypergradient-error stop uses ``hg_rel`` times the previous hypergradient norm.
 
+Batch training with Adam (Section 5.2 trains on a batch of images with Adam): the upper loss
+is the sum over the images of 1/2 ||x_hat_k - x*_k||^2 (the config's batch loss is a sum), so
+its hypergradient is the sum of the images' J_k w_k, each from its own recycled solve (own
+recycle space, own warm start).  Adam (Kingma and Ba, 2015): m = b1 m + (1 - b1) g,
+v = b2 v + (1 - b2) g^2, step = lr m_hat / (sqrt(v_hat) + eps) with the bias corrections
+m_hat = m / (1 - b1^t), v_hat = v / (1 - b2^t); theta -= step.  Filter regularisers: each
+filter's tap block of the step is projected onto zero mean, so the filters stay zero-mean.
+
 Solve sequence (Section 5's fixed-sequence protocol).  Given the frozen
 {theta_i, x_hat_i}, solve every H^{(i)} w = g^{(i)} with recycled CG, warm started
 from w^{(i-1)}, refreshing U, C, Z, mu between systems (outer RGen-L(R)).
@@ -169,4 +177,77 @@ def train(prob, xstar, theta0, outer: int, s: int = 0, solver: str = "cg", stop:
         hist["tau"].append(tau_acc)
     hist["theta"].append(theta.copy())
     hist["loss"].append(c1)
+    return hist
+
+
+def adam_step(theta, grad, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8,
+              zero_mean_blocks=None):
+    """One Adam update (t >= 1); zero_mean_blocks = (n_filters, fsize) projects each filter's tap
+    block of the step onto zero mean.  Returns (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    step = lr * (m / (1.0 - b1 ** t)) / (np.sqrt(v / (1.0 - b2 ** t)) + eps)
+    if zero_mean_blocks is not None:
+        nf, fs = zero_mean_blocks
+        f2 = fs * fs
+        step = step.reshape(nf, 1 + f2).copy()
+        step[:, 1:] -= step[:, 1:].mean(axis=1, keepdims=True)
+        step = step.ravel()
+    return theta - step, m, v
+
+
+def train_adam(probs, xstars, theta0, steps: int, lr: float = 1e-2, s: int = 0, stop: str = "resid",
+               tol: float = 1e-10, hg_rel: float = 1e-8, v_cap: int = 64, gtol: float = 1e-8,
+               lbfgs_iters: int = 20000, max_iter: int = 20000, zero_mean_blocks=None):
+    """Adam on the summed upper loss of a batch of images (problems ``probs`` with ground truths
+    ``xstars``), ``steps`` updates from theta0.  Per step and image: lower-level L-BFGS solve at
+    the current theta warm started from that image's previous reconstruction; refresh of the
+    image's recycle space (s > 0; from the previous step's); recycled CG on H_k w_k = x_hat_k - x*_k
+    warm started from the image's previous w_k (the error-estimate stop at hg_rel times the image's
+    previous hypergradient norm, when it has a recycle space); J_k w_k summed into the gradient.
+    Returns per-step records: theta (steps + 1), loss (steps + 1: the summed upper loss at each
+    theta), gradient norms, Hessian-solve iterations per image."""
+    theta = np.array(theta0, dtype=np.float64)
+    xs = [np.asarray(x).ravel() for x in xstars]
+    K = len(probs)
+
+    def lower(k, th, xinit):
+        x, _ = lbfgs.lbfgs(lambda v: probs[k].phi(v, th), lambda v: probs[k].grad(v, th), xinit, gtol=gtol,
+                           max_iter=lbfgs_iters)
+        return x
+
+    xh = [lower(k, theta, probs[k].y.ravel()) for k in range(K)]
+    U = [None] * K
+    V = [None] * K
+    w = [np.zeros_like(x) for x in xs]
+    prev_hg = [None] * K
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    hist = {"theta": [theta.copy()], "loss": [sum(upper_loss(xh[k], xs[k]) for k in range(K))], "grad_norm": [],
+            "iters": []}
+    for t in range(1, steps + 1):
+        grad = np.zeros_like(theta)
+        its = []
+        for k in range(K):
+            hvp = lambda q, k=k: probs[k].hvp(xh[k], theta, q)
+            jac = lambda q, k=k: probs[k].jac_apply(xh[k], theta, q)
+            rs = {"U": None, "C": None, "Z": None, "mu": None}
+            if s and (U[k] is not None or V[k] is not None):
+                rs = recycle.refresh(hvp, jac, U[k], V[k], s)
+            use_hg = stop == "hgerr" and rs["U"] is not None and prev_hg[k] is not None
+            res = krylov.recycled_cg(hvp, xh[k] - xs[k], w[k], rs["U"], rs["C"], rs["Z"], rs["mu"], tol=tol,
+                                     stop="hgerr" if use_hg else "resid",
+                                     hg_tol=hg_rel * prev_hg[k] if use_hg else 0.0, max_iter=max_iter,
+                                     v_cap=v_cap if s else 0)
+            U[k], V[k], w[k] = rs["U"], res["V"], res["w"]
+            hg = jac(w[k])
+            prev_hg[k] = float(np.linalg.norm(hg))
+            grad += hg
+            its.append(res["iters"])
+        theta, m, v = adam_step(theta, grad, m, v, t, lr, zero_mean_blocks=zero_mean_blocks)
+        xh = [lower(k, theta, xh[k]) for k in range(K)]
+        hist["theta"].append(theta.copy())
+        hist["loss"].append(sum(upper_loss(xh[k], xs[k]) for k in range(K)))
+        hist["grad_norm"].append(float(np.linalg.norm(grad)))
+        hist["iters"].append(its)
     return hist

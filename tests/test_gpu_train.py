@@ -40,3 +40,33 @@ def test_training_matches_oracle(B, solver, stop, s):
         assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
     assert np.allclose(hist["loss"], ref["loss"], rtol=1e-6)
     assert all(b < a for a, b in zip(hist["loss"], hist["loss"][1:]))
+
+
+@pytest.mark.parametrize("s,stop", [(0, "resid"), (4, "hgerr")])
+def test_adam_batch_matches_oracle(B, s, stop):
+    """Batch training with Adam (Section 5.2): three TV images of different sizes sharing theta,
+    every step's Hessian solves advanced together by the batch engine, against the oracle's Adam
+    loop: parameters and summed losses to 1e-6 relative after 3 steps."""
+    from oracle import upper
+    from paper_2412_08264_amd import train
+    cases = []
+    for k, (h, w) in enumerate([(16, 14), (12, 18), (20, 20)]):
+        wl = synth.custom(f"b{k}", h, "tv", 4, width=w, blur_radius=2, blur_sigma=1.5, rect_min=2, rect_max=5,
+                          seed=41 + k)
+        inst = synth.instance(wl)
+        cases.append((wl, inst, problem.make_problem(wl, inst["xstar"], inst["e"])))
+    th0 = cases[0][1]["theta0"]
+    kw = dict(lr=2e-2, s=s, stop=stop, tol=1e-10, hg_rel=1e-9)
+    ref = upper.train_adam([c[2] for c in cases], [c[1]["xstar"] for c in cases], th0, 3, **kw)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).ravel(), device=DEV)
+    Ps = [B.problem_from(c[0]) for c in cases]
+    with B.Context(Ps, s_max=4, v_cap=64) as ctx:
+        hist = train.train_adam(ctx, Ps, [t(c[2].y) for c in cases], [t(c[1]["xstar"]) for c in cases], th0, 3,
+                                v_cap=64, **kw)
+    for a, b in zip(hist["theta"], ref["theta"]):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), (a, b)
+    assert np.allclose(hist["loss"], ref["loss"], rtol=1e-6)
+    assert np.allclose(hist["grad_norm"], ref["grad_norm"], rtol=1e-6)
+    if s == 0:
+        assert [list(i) for i in hist["iters"]] == [list(i) for i in ref["iters"]] or all(
+            abs(a - b) <= 1 for x, y in zip(hist["iters"], ref["iters"]) for a, b in zip(x, y))
