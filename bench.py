@@ -680,6 +680,7 @@ def bench_sequence(args, B, torch, synth):
 def bench_batch(args, B, torch, synth):
     """64 filter images, shared theta: per outer step a refresh of every image's recycle space,
     one engine advancing all 64 recycled solves together, and the summed hypergradient."""
+    from paper_2412_08264_amd import train as train_mod
     wls = synth.batch_set(args.batch, 4000, s=20)
     T = args.outer or 4
     dev = torch.device("cuda:0")
@@ -719,13 +720,7 @@ def bench_batch(args, B, torch, synth):
         hgs = [ctx.hypergradient_p(P, theta, x, w) for P, x, w in zip(P64, xcur, wref)]
         refs.append(hgs)
         grad = np.sum(hgs, axis=0)
-        m = 0.9 * m + 0.1 * grad
-        v = 0.999 * v + 0.001 * grad * grad
-        step = 1e-2 * (m / (1 - 0.9 ** (i + 1))) / (np.sqrt(v / (1 - 0.999 ** (i + 1))) + 1e-8)
-        for j in range(nf):
-            blk = step[j * (1 + f2) + 1:(j + 1) * (1 + f2)]
-            blk -= blk.mean()
-        theta = theta - step
+        theta, m, v = train_mod.adam_update(theta, grad, m, v, i + 1, 1e-2, zero_mean_blocks=(nf, wls[0].filter_size))
         log(f"  step {i + 1}/{T}: L-BFGS iterations max {max(its)} mean {np.mean(its):.0f}, "
             f"|grad| {np.linalg.norm(grad):.3e} ({time.perf_counter() - tt:.1f} s)")
     recs = [B.Recycle(w.n, 20, V_CAP, dev) for w in wls]
