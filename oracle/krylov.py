@@ -113,6 +113,80 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
             "alpha": np.array(alphas), "rho": np.array(rhos)}
 
 
+def deflated_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1e-10, stop: str = "resid",
+                hg_tol: float = 0.0, max_iter: int = 10000, v_cap: int = 64, check_every: int = 1,
+                record: bool = False):
+    """Deflated CG of Saad, Yeung, Erhel and Guyomarc'h (2000): the reading of the recycled
+    solver that the paper leaves open beside the Galerkin form above (Section 2.2.2 defines only
+    RMINRES), with the recycle space U and C = H U of the refresh as the deflation space.  With
+    E = U^T C (= U^T H U, symmetric positive definite):
+      1. r = g - H w0;  w = w0 + U E^{-1} U^T r;  r -= C E^{-1} U^T r      (so U^T r = 0)
+      2. mu = E^{-1} C^T r;  p = r - U mu
+      3. per iteration: q = H p;  alpha = rho / (p . q);  w += alpha p;  r -= alpha q;
+         rho' = r . r;  stop test;  beta = rho' / rho;  mu = E^{-1} C^T r;  p = r + beta p - U mu.
+    The residuals stay orthogonal to U and the directions H-conjugate to it (C^T p = 0); the
+    iterate minimises the energy-norm error over w0 + range(U) + the directions.  Same stop tests
+    and returned keys as recycled_cg; V holds the normalised residuals."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    n = g.size
+    w = np.zeros(n) if w0 is None else np.array(w0, dtype=np.float64).ravel().copy()
+    s = 0 if U is None else U.shape[1]
+    r = g - hvp(w)
+    if s:
+        E = 0.5 * (U.T @ C + C.T @ U)
+        c = np.linalg.solve(E, U.T @ r)
+        w = w + U @ c
+        r = r - C @ c
+    gnorm = float(np.linalg.norm(g))
+    rho = float(r @ r)
+    p = r - U @ np.linalg.solve(E, C.T @ r) if s else r.copy()
+    V, hist_res, hist_nsc, P = [], [], [], []
+
+    def met(rv, rho_v, j):
+        res = np.sqrt(max(rho_v, 0.0))
+        est = float(np.linalg.norm(mu * (Z.T @ rv))) if (Z is not None and mu is not None and len(mu)) else np.nan
+        if record:
+            hist_res.append(res)
+            hist_nsc.append(est)
+        if rho_v == 0.0:
+            return True
+        if j % check_every:
+            return False
+        if stop == "hgerr":
+            return est <= hg_tol
+        return res <= tol * gnorm
+
+    status, iters = OK, 0
+    done = met(r, rho, 0)
+    while not done and iters < max_iter:
+        if len(V) < v_cap:
+            V.append(r / np.sqrt(rho))
+        if record:
+            P.append(p.copy())
+        q = hvp(p)
+        sigma = float(p @ q)
+        if sigma <= 0.0:
+            status = INDEFINITE
+            break
+        alpha = rho / sigma
+        w += alpha * p
+        r -= alpha * q
+        rho_new = float(r @ r)
+        iters += 1
+        done = met(r, rho_new, iters)
+        if done:
+            rho = rho_new
+            break
+        beta = rho_new / rho
+        p = r + beta * p - (U @ np.linalg.solve(E, C.T @ r) if s else 0.0)
+        rho = rho_new
+    if not done and status == OK:
+        status = NOT_CONVERGED
+    return {"w": w, "iters": iters, "status": status, "res_norm": float(np.sqrt(max(rho, 0.0))),
+            "g_norm": gnorm, "V": np.stack(V, axis=1) if V else np.zeros((n, 0)),
+            "hist_res": hist_res, "hist_nsc": hist_nsc, "r": r, "P": P}
+
+
 def cg(hvp, g, w0=None, tol: float = 1e-10, max_iter: int = 10000, v_cap: int = 64, record: bool = False):
     """Plain CG: the recycled solver with an empty recycle space."""
     return recycled_cg(hvp, g, w0, tol=tol, max_iter=max_iter, v_cap=v_cap, record=record)

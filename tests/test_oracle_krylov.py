@@ -159,3 +159,50 @@ def test_reference_solve_tight():
     g = np.random.default_rng(22).standard_normal(40)
     w, _ = krylov.reference_solve(lambda v: H @ v, g)
     assert np.linalg.norm(H @ w - g) <= 1e-12 * np.linalg.norm(g)
+
+
+# ------------------------------------------------------------------ deflated CG (the O5 alternative)
+@pytest.mark.parametrize("s", [3, 8])
+def test_deflated_cg_minimises_energy_error_over_augmented_space(s):
+    """Deflated CG (Saad et al. 2000): after j iterations the iterate is the energy-norm best
+    approximation of w* over w0 + span(U, p_0, ..., p_{j-1}) (brute force: the Galerkin system
+    of that basis); its residuals stay orthogonal to U and its directions H-conjugate to U."""
+    H = spd(50, 3e3, 11 + s)
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal(50)
+    w0 = rng.standard_normal(50)
+    U, C = recycle_pair(H, s, 13)
+    wstar = np.linalg.solve(H, g)
+    for j in (1, 4, 9):
+        res = krylov.deflated_cg(lambda v: H @ v, g, w0, U, C, tol=0.0, max_iter=j, record=True)
+        Bm = np.concatenate([U, np.stack(res["P"], axis=1)], axis=1)
+        c = np.linalg.solve(Bm.T @ H @ Bm, Bm.T @ (g - H @ w0))
+        best = w0 + Bm @ c
+        assert np.linalg.norm(res["w"] - best) <= 1e-9 * np.linalg.norm(wstar)
+        assert np.abs(U.T @ res["r"]).max() <= 1e-10 * np.linalg.norm(g)
+        for p in res["P"]:
+            assert np.abs(C.T @ p).max() <= 1e-10 * np.linalg.norm(p)
+        # the recursive residual is the true residual
+        assert np.linalg.norm(res["r"] - (g - H @ res["w"])) <= 1e-10 * np.linalg.norm(g)
+
+
+def test_deflated_cg_special_cases():
+    """No deflation space: textbook CG, bit for bit the same arithmetic as plain CG; w* - w0 in
+    range(U): the set-up alone gives w* (zero iterations); converges to the dense solution."""
+    H = spd(40, 1e3, 21)
+    rng = np.random.default_rng(22)
+    g = rng.standard_normal(40)
+    a = krylov.deflated_cg(lambda v: H @ v, g, tol=1e-10)
+    b = krylov.cg(lambda v: H @ v, g, tol=1e-10)
+    assert a["iters"] == b["iters"] and np.array_equal(a["w"], b["w"])
+    wstar = np.linalg.solve(H, g)
+    w0 = rng.standard_normal(40)
+    Ut = np.concatenate([(wstar - w0)[:, None], rng.standard_normal((40, 2))], axis=1)
+    Qc, Rc = np.linalg.qr(H @ Ut)
+    U = Ut @ np.linalg.inv(Rc)
+    one = krylov.deflated_cg(lambda v: H @ v, g, w0, U, Qc, tol=1e-9)
+    assert one["iters"] == 0 and np.linalg.norm(one["w"] - wstar) <= 1e-10 * np.linalg.norm(wstar)
+    U, C = recycle_pair(H, 5, 23)
+    full = krylov.deflated_cg(lambda v: H @ v, g, w0, U, C, tol=1e-12)
+    assert full["status"] == krylov.OK
+    assert np.linalg.norm(full["w"] - wstar) <= 1e-8 * np.linalg.norm(wstar)
