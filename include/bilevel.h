@@ -230,6 +230,22 @@ bl_status bl_hessian_solve_rminres(bl_ctx* ctx, const bl_problem* P, const doubl
                                    const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
                                    void* ws, size_t ws_bytes, bl_stats* out);
 
+/* Hessian solve H w = g by deflated CG (Saad, Yeung, Erhel and Guyomarc'h 2000), the other
+ * reading of a recycled CG beside bl_hessian_solve's Galerkin form (Section 2.2.2 defines only
+ * RMINRES), with U and C = H U of the recycle state as the deflation space: with
+ * E = U^T C (= U^T H U), the set-up w = w0 + U E^{-1} U^T r0, r0 -= C E^{-1} U^T r0 makes
+ * U^T r = 0, and each direction p = r + beta p_prev - U E^{-1} C^T r is H-conjugate to U.  Same
+ * arguments, stop tests and statistics as bl_hessian_solve; differences:
+ *   * FP64 only (prec = BL_PREC_MIXED is refused with BL_E_ARG; rr_every is ignored);
+ *   * BL_E_INDEFINITE before any iteration if U^T C is not positive definite;
+ *   * with store_basis the normalised residuals go to rs->V (rs->v_lz = 0: no CG coefficients
+ *     of the Galerkin form, so the inner refresh refuses this basis);
+ *   * tiles of 32 x 8 pixels, no graph replay: two launches per step from the host with a
+ *     double-buffered poll of the stop flag every 8 steps. */
+bl_status bl_hessian_solve_deflated(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
+                                    const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
+                                    void* ws, size_t ws_bytes, bl_stats* out);
+
 /* Hypergradient J w = -(D_theta grad_x Phi)^T w (eq. hypgrad) into grad_host (p doubles).
  * Filters: each filter's tap block is projected onto zero mean when project_zero_mean. */
 bl_status bl_hypergradient(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,

@@ -75,6 +75,8 @@ _SIGS = {
                                    _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hessian_solve_noalloc": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
                                            _P(bl_solve_opts), _P(bl_stats)]),
+    "bl_hessian_solve_deflated": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
+                                            _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hessian_solve_rminres": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _vp, _P(bl_recycle),
                                            _P(bl_solve_opts), _vp, C.c_size_t, _P(bl_stats)]),
     "bl_hypergradient": (C.c_int, [_vp, _P(bl_problem), _P(C.c_double), _vp, _vp, _P(C.c_double), C.c_int,
@@ -299,11 +301,14 @@ class Context:
     def solve_p(self, P, rec, theta, xhat, g, w, tol=1e-10, stop: str = "resid", hg_tol: float = 0.0,
                 max_iter: int = 20000, check_every: int = 1, rr_every: int = 50, store_basis: bool = True,
                 recycle: bool = True, allow=(BL_OK,), method: str = "cg") -> bl_stats:
-        """Hessian solve by recycled CG (``method="cg"``) or RMINRES (``method="rminres"``)."""
-        if method not in ("cg", "rminres"):
+        """Hessian solve by recycled CG (``method="cg"``), RMINRES (``method="rminres"``) or
+        deflated CG (``method="deflated"``)."""
+        fns = {"cg": (lib.bl_hessian_solve, "bl_hessian_solve"),
+               "rminres": (lib.bl_hessian_solve_rminres, "bl_hessian_solve_rminres"),
+               "deflated": (lib.bl_hessian_solve_deflated, "bl_hessian_solve_deflated")}
+        if method not in fns:
             raise ValueError(f"unknown method {method!r}")
-        fn, name = ((lib.bl_hessian_solve, "bl_hessian_solve") if method == "cg"
-                    else (lib.bl_hessian_solve_rminres, "bl_hessian_solve_rminres"))
+        fn, name = fns[method]
         st = bl_stats()
         o = bl_solve_opts(BL_STOP_HGERR if stop == "hgerr" else BL_STOP_RESID, tol, hg_tol, max_iter, check_every,
                           rr_every, 1 if store_basis else 0)

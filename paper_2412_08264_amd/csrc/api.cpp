@@ -515,6 +515,130 @@ bl_status bl_hessian_solve_rminres(bl_ctx* c, const bl_problem* P, const double*
     return (bl_status)hs.status;
 }
 
+// ------------------------------------------------------------------------------ deflated CG
+// One solve, launched step by step: the set-up, then an apply and an update launch per step,
+// with a record fold before a consumer whenever the records exceed REC_LIMIT values, and a poll
+// of the stop flag every POLL steps (double-buffered, as for RMINRES).  The test of iterate j
+// runs in the apply launch of step j, so at most max_iter + 1 steps are launched.
+bl_status bl_hessian_solve_deflated(bl_ctx* c, const bl_problem* P, const double* theta, const double* xhat,
+                                    const double* g, double* w, bl_recycle* rs, const bl_solve_opts* o, void* wsp,
+                                    size_t ws_bytes, bl_stats* out) {
+    if (!c) return BL_E_ARG;
+    TRY(check_problem(c, P));
+    if (!xhat || !g || !w) return c->err = "null argument", BL_E_ARG;
+    TRY(check_solve_opts(c, o));
+    if (P->prec != BL_PREC_FP64) return c->err = "deflated CG runs in FP64 only", BL_E_ARG;
+    const int s = rs ? rs->s_cur : 0, s_max = rs ? rs->s_max : 0, v_cap = rs ? rs->v_cap : 0;
+    if (s_max < 0 || s_max > S_MAX || v_cap < 0) return c->err = "s_max outside [0, 64] or v_cap < 0", BL_E_SHAPE;
+    if (rs) {
+        if (s < 0 || s > s_max) return c->err = "s_cur outside [0, s_max]", BL_E_SHAPE;
+        if (s > 0 && (!rs->U || !rs->C || !rs->mu)) return c->err = "null recycle arrays", BL_E_ARG;
+        if (o->store_basis && (!rs->V || v_cap < 1)) return c->err = "store_basis needs V", BL_E_ARG;
+    }
+    WS ws;
+    TRY(check_ws(c, layout(P, s_max, v_cap), wsp, ws_bytes, ws));
+    mark(c, 0);
+    Stencil S;
+    TRY(make_stencil(c, P, theta, ws, S));
+    TRY(filter_state(c, S, xhat, ws));
+    const bool hg = o->stop == BL_STOP_HGERR && s > 0 && rs->Z;
+    const bool store = o->store_basis && rs;
+    const int n = P->h * P->w;
+    const size_t T2 = (size_t)ws.L.t_max * ws.L.t_max;
+    DeflArgs a{};
+    a.xhat = xhat;
+    a.g = g;
+    a.w = w;
+    a.r = ws.vec(0);
+    a.p[0] = ws.vec(1);
+    a.p[1] = ws.vec(2);
+    a.q = ws.vec(3);
+    a.U = s ? rs->U : nullptr;
+    a.C = s ? rs->C : nullptr;
+    a.Z = hg ? rs->Z : nullptr;
+    a.mu = s ? rs->mu : nullptr;
+    a.Einv = ws.small(0);
+    a.V = store ? rs->V : nullptr;
+    a.st = ws.st();
+    a.rec_res = ws.part_res();
+    a.rec_app = ws.part_app();
+    a.rec_upd = ws.part_upd();
+    a.fold = ws.part_fold(0);
+    a.n = n;
+    a.ntiles = ((P->w + QW - 1) / QW) * ((P->h + QTY - 1) / QTY);
+    a.npix = (n + NT - 1) / NT;
+    a.s = s;
+    a.nz = hg ? s : 0;
+    if (s) {   // E^{-1} = (U^T C)^{-1}: the deflation space's projected Hessian (E = U^T H U)
+        int* info = ws.ctr();
+        HIPCHK(launch_gram(n, s, s, rs->U, rs->C, ws.part(), ws.small(2 * T2), c->stream));
+        HIPCHK(launch_d_einv(s, ws.small(2 * T2), ws.small(T2), ws.small(0), info, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_info, info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->h_info[0] != BL_OK) return c->err = "U^T C is not positive definite", BL_E_INDEFINITE;
+    }
+    const StateInit in{o->tol, o->hg_tol, o->max_iter, o->check_every, o->stop, s, store ? v_cap : 0,
+                       store ? 1 : 0, hg ? 1 : 0};
+    HIPCHK(launch_d_residual(S, a, c->stream));
+    const bool fold_res = (long)a.ntiles * (1 + s) > REC_LIMIT;
+    if (fold_res) HIPCHK(launch_m_fold(a.rec_res, a.ntiles, 1 + s, a.fold, c->stream));
+    HIPCHK(launch_d_init(a, in, fold_res, c->stream));
+    mark(c, 1);
+    const bool fold_app = (long)a.ntiles > REC_LIMIT;
+    const auto zw_of = [&](long j) { return (a.nz > 0 && j % o->check_every == 0) ? a.nz : 0; };
+    bool decided = false;
+    const long jmax = (long)o->max_iter;
+    int pending = -1, npoll = 0;
+    for (long j = 0; j <= jmax && !decided; ++j) {
+        const int zw = zw_of(j);
+        const bool fold_upd = (long)a.npix * (1 + s + zw) > REC_LIMIT;
+        if (fold_upd) HIPCHK(launch_m_fold(a.rec_upd, a.npix, 1 + s + zw, a.fold, c->stream));
+        HIPCHK(launch_d_apply(S, a, (int)j, zw, fold_upd, c->stream));
+        if (j < jmax) {
+            if (fold_app) HIPCHK(launch_m_fold(a.rec_app, a.ntiles, 1, a.fold, c->stream));
+            HIPCHK(launch_d_update(a, (int)j, zw_of(j + 1), fold_app, c->stream));
+        }
+        if ((j + 1) % POLL == 0 || j == jmax) {
+            const int buf = npoll++ & 1;
+            HIPCHK(hipMemcpyAsync(c->h_hdr + (size_t)buf * HDR_BYTES, a.st, HDR_BYTES, hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipEventRecord(c->poll_ev[buf], c->stream));
+            if (pending >= 0) {
+                HIPCHK(hipEventSynchronize(c->poll_ev[pending]));
+                decided = reinterpret_cast<const SolveState*>(c->h_hdr + (size_t)pending * HDR_BYTES)->done != 0;
+            }
+            pending = buf;
+        }
+    }
+    if (!decided && pending >= 0) {
+        HIPCHK(hipEventSynchronize(c->poll_ev[pending]));
+        decided = reinterpret_cast<const SolveState*>(c->h_hdr + (size_t)pending * HDR_BYTES)->done != 0;
+    }
+    if (!decided) return c->err = "deflated CG ended without a stop decision", BL_E_HIP;
+    mark(c, 2);
+    HIPCHK(hipMemcpyAsync(c->h_state, a.st, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const SolveState hs = *c->h_state;
+    if (store) {
+        rs->v_cur = std::min(hs.iters + (hs.status == BL_E_INDEFINITE ? 1 : 0), v_cap);
+        rs->v_lz = 0;   // no CG coefficients of the Galerkin form: the inner refresh refuses this basis
+    }
+    if (out) {
+        *out = bl_stats{};
+        out->iters = hs.iters;
+        out->status = hs.status;
+        out->s_cur = s;
+        out->res_norm = std::sqrt(std::max(hs.rho2[hs.iters & 1], 0.0));
+        out->res0_norm = hs.res0;
+        out->g_norm = hs.gnorm;
+        out->est = hs.est;
+        out->ms[0] = elapsed(c, 0, 1);
+        out->ms[1] = elapsed(c, 1, 2);
+        out->ms[3] = elapsed(c, 0, 2);
+    }
+    return (bl_status)hs.status;
+}
+
 // ------------------------------------------------------------------------------ tile heights
 bl_status bl_tile_rows_set(const bl_problem* P, int rows) {
     bl_ctx tmp;

@@ -134,6 +134,33 @@ hipError_t launch_m_update(const MinresArgs& a, int k, int nvb, bool fold, hipSt
 hipError_t launch_m_finish(const MinresArgs& a, hipStream_t stream);
 hipError_t launch_m_fold(const double* rec, int nb, int nv, double* out, hipStream_t stream);
 
+// deflated.hip: deflated CG on 32 x 8 tiles, FP64, one solve (scalars in a SolveState).
+struct DeflArgs {
+    const double* xhat;
+    const double* g;
+    double* w;
+    double* r;
+    double* p[2];             // p_j in p[j & 1]
+    double* q;
+    const double* U;
+    const double* C;
+    const double* Z;
+    const double* mu;         // selected generalized singular values (s, device; may be null)
+    const double* Einv;       // (U^T C)^{-1}, s x s
+    double* V;                // stored normalised residuals (store_basis)
+    SolveState* st;
+    double* rec_res;          // records: residual (tiles x (1 + s)), apply (tiles x 1),
+    double* rec_app;          // set-up and update (pixel blocks x (1 + s + nz))
+    double* rec_upd;
+    double* fold;             // FOLD_BLOCKS folded records
+    int n, ntiles, npix, s, nz;
+};
+hipError_t launch_d_residual(const Stencil& S, const DeflArgs& a, hipStream_t stream);
+hipError_t launch_d_einv(int s, const double* UtC, double* Lscr, double* Einv, int* info, hipStream_t stream);
+hipError_t launch_d_init(const DeflArgs& a, const StateInit& in, bool fold, hipStream_t stream);
+hipError_t launch_d_apply(const Stencil& S, const DeflArgs& a, int j, int zw, bool fold, hipStream_t stream);
+hipError_t launch_d_update(const DeflArgs& a, int j, int zw, bool fold, hipStream_t stream);
+
 // dense.hip
 int gram_chunks(int n);
 hipError_t launch_gram(int n, int t1, int t2, const double* A, const double* B, double* part, double* out,
