@@ -91,16 +91,18 @@ def recycled_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
         w += alpha * p
         zacc -= alpha * e
         r -= alpha * (q - C @ e) if s else alpha * q
-        if recurrence == "single":
-            rho_new = rho - 2.0 * alpha * rq + alpha * alpha * (qq - ee)
-        else:
-            rho_new = float(r @ r)
+        rho_new = float(r @ r)
         iters += 1
         done = met(r, rho_new, iters)
         if done:
             rho = rho_new
             break
-        beta = rho_new / rho
+        if recurrence == "single":
+            # Chronopoulos-Gear: beta from the recurrence of the projected residual's norm
+            # (C^T r = 0, C^T C = I), anchored on the explicit r.r of the previous iterate
+            beta = (rho - 2.0 * alpha * rq + alpha * alpha * (qq - ee)) / rho
+        else:
+            beta = rho_new / rho
         p = r + beta * p
         rho = rho_new
     if not done and status == OK:
@@ -187,9 +189,10 @@ def deflated_cg(hvp, g, w0=None, U=None, C=None, Z=None, mu=None, tol: float = 1
             "hist_res": hist_res, "hist_nsc": hist_nsc, "r": r, "P": P}
 
 
-def cg(hvp, g, w0=None, tol: float = 1e-10, max_iter: int = 10000, v_cap: int = 64, record: bool = False):
+def cg(hvp, g, w0=None, tol: float = 1e-10, max_iter: int = 10000, v_cap: int = 64, record: bool = False,
+       recurrence: str = "textbook"):
     """Plain CG: the recycled solver with an empty recycle space."""
-    return recycled_cg(hvp, g, w0, tol=tol, max_iter=max_iter, v_cap=v_cap, record=record)
+    return recycled_cg(hvp, g, w0, tol=tol, max_iter=max_iter, v_cap=v_cap, record=record, recurrence=recurrence)
 
 
 def reference_solve(hvp, g, tol: float = 1e-13, max_iter: int = 100000, replace_every: int = 50):

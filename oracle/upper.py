@@ -84,8 +84,9 @@ def trajectory(prob, xstar, theta0, outer: int, gtol: float = 1e-8, x0=None, eta
 
 def solve_sequence(prob, thetas, xhats, xstar, s: int, tol: float = 1e-10, stop: str = "resid",
                    hg_rel: float = 1e-7, v_cap: int = 64, max_iter: int = 10000, recycle_on: bool = True,
-                   warm: bool = True):
-    """Solve the frozen sequence with recycled CG; returns per-system records."""
+                   warm: bool = True, recurrence: str = "textbook"):
+    """Solve the frozen sequence with recycled CG; returns per-system records.  recurrence:
+    the CG form (recycled_cg's option)."""
     xs = np.asarray(xstar).ravel()
     U = V = None
     w_prev = None
@@ -101,7 +102,8 @@ def solve_sequence(prob, thetas, xhats, xstar, s: int, tol: float = 1e-10, stop:
         use_hg = stop == "hgerr" and rs["U"] is not None and prev_hg is not None
         res = krylov.recycled_cg(hvp, g, w_prev if warm else None, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=tol,
                                  stop="hgerr" if use_hg else "resid",
-                                 hg_tol=hg_rel * prev_hg if use_hg else 0.0, max_iter=max_iter, v_cap=v_cap)
+                                 hg_tol=hg_rel * prev_hg if use_hg else 0.0, max_iter=max_iter, v_cap=v_cap,
+                                 recurrence=recurrence)
         hg = jac(res["w"])
         out.append({"w": res["w"], "iters": res["iters"], "status": res["status"], "hg": hg, "t": rs["t"],
                     "w0": w_prev, "rs": rs})
@@ -198,7 +200,7 @@ def adam_step(theta, grad, m, v, t: int, lr: float, b1: float = 0.9, b2: float =
 
 def train_adam(probs, xstars, theta0, steps: int, lr: float = 1e-2, s: int = 0, stop: str = "resid",
                tol: float = 1e-10, hg_rel: float = 1e-8, v_cap: int = 64, gtol: float = 1e-8,
-               lbfgs_iters: int = 20000, max_iter: int = 20000, zero_mean_blocks=None):
+               lbfgs_iters: int = 20000, max_iter: int = 20000, zero_mean_blocks=None, recurrence: str = "textbook"):
     """Adam on the summed upper loss of a batch of images (problems ``probs`` with ground truths
     ``xstars``), ``steps`` updates from theta0.  Per step and image: lower-level L-BFGS solve at
     the current theta warm started from that image's previous reconstruction; refresh of the
@@ -206,7 +208,8 @@ def train_adam(probs, xstars, theta0, steps: int, lr: float = 1e-2, s: int = 0, 
     warm started from the image's previous w_k (the error-estimate stop at hg_rel times the image's
     previous hypergradient norm, when it has a recycle space); J_k w_k summed into the gradient.
     Returns per-step records: theta (steps + 1), loss (steps + 1: the summed upper loss at each
-    theta), gradient norms, Hessian-solve iterations per image."""
+    theta), gradient norms, Hessian-solve iterations per image.  recurrence: the CG form
+    (recycled_cg's option)."""
     theta = np.array(theta0, dtype=np.float64)
     xs = [np.asarray(x).ravel() for x in xstars]
     K = len(probs)
@@ -238,7 +241,7 @@ def train_adam(probs, xstars, theta0, steps: int, lr: float = 1e-2, s: int = 0, 
             res = krylov.recycled_cg(hvp, xh[k] - xs[k], w[k], rs["U"], rs["C"], rs["Z"], rs["mu"], tol=tol,
                                      stop="hgerr" if use_hg else "resid",
                                      hg_tol=hg_rel * prev_hg[k] if use_hg else 0.0, max_iter=max_iter,
-                                     v_cap=v_cap if s else 0)
+                                     v_cap=v_cap if s else 0, recurrence=recurrence)
             U[k], V[k], w[k] = rs["U"], res["V"], res["w"]
             hg = jac(w[k])
             prev_hg[k] = float(np.linalg.norm(hg))

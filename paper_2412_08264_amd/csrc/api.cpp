@@ -51,12 +51,13 @@ Layout layout(const bl_problem* P, int s_max, int v_cap, bool solve_only = false
     L.hdr = o;      o += al(HDR_BYTES);
     L.ctr = o;      o += al(sizeof(int));
     L.fold = o;     o += al((size_t)3 * FOLD_BLOCKS * NV_RED * sizeof(double));
-    L.part = o;     o += al(3 * pd * sizeof(double));   // records: residual / apply / update (and general)
+    L.part = o;     o += al(4 * pd * sizeof(double));   // records: residual / apply / update / apply of odd fused steps
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
     L.taps = o;     o += al(TAPS_BYTES);
-    if (solve_only) {
-        L.W0 = L.W1 = L.Ut = L.Ct = L.small = L.lb = o;
+    if (solve_only) {   // the solve's H C (n x s_max) in the place of the refresh's U~
+        L.W0 = L.W1 = L.Ct = L.small = L.lb = L.Ut = o;
+        o += al((size_t)L.n * std::max(s_max, 1) * sizeof(double));
         L.total = o;
         return L;
     }
@@ -85,6 +86,7 @@ struct WS {
     double* part_res() const { return part(); }
     double* part_app() const { return part() + L.part_doubles; }
     double* part_upd() const { return part() + 2 * L.part_doubles; }
+    double* part_app2() const { return part() + 3 * L.part_doubles; }
     double* part_fold(int k) const { return (double*)(base + L.fold) + (size_t)k * FOLD_BLOCKS * NV_RED; }
     double* vec(int k) const { return (double*)(base + L.vec) + (size_t)k * L.n; }
     double* d1() const { return (double*)(base + L.maps); }
@@ -303,6 +305,9 @@ bl_status solve_in(bl_ctx* c, const bl_problem* P, const double* theta, const do
     buf.p0 = ws.vec(1);
     buf.p1 = ws.vec(2);
     buf.q = ws.vec(3);
+    buf.r2 = ws.vec(4);
+    buf.q2 = ws.vec(5);
+    buf.HC = ws.Ut();
     buf.d1 = ws.d1();
     buf.d2 = ws.d2();
     buf.d2f = ws.d2f();
@@ -310,6 +315,7 @@ bl_status solve_in(bl_ctx* c, const bl_problem* P, const double* theta, const do
     buf.rec_res = ws.part_res();
     buf.rec_app = ws.part_app();
     buf.rec_upd = ws.part_upd();
+    buf.rec_app2 = ws.part_app2();
     buf.fold = ws.part_fold(0);
     buf.st = ws.st();
     const SolveSpec sp{P, theta, xhat, g, w, rs, o};
@@ -380,7 +386,7 @@ bl_status bl_hessian_solve_noalloc(bl_ctx* c, const bl_problem* P, const double*
                                    const double* g, double* w, bl_recycle* rs, const bl_solve_opts* o,
                                    bl_stats* out) {
     TRY(solve_args(c, P, xhat, g, w, rs, o));
-    const Layout L = layout(P, 0, 0, true);
+    const Layout L = layout(P, rs ? rs->s_max : 0, 0, true);
     if (L.total > NOALLOC_SCRATCH_BYTES)
         return c->err = "problem needs " + std::to_string(L.total) + " scratch bytes, above the " +
                         std::to_string(NOALLOC_SCRATCH_BYTES) + " of the static array",

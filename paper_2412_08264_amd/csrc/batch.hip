@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(NT) k_b_finish(const Slot* __restrict__ slots,
 }
 
 // Fold the records of kind `which` (0 residual, 1 apply, 2 update, read by the test of step
-// sr): FOLD_BLOCKS blocks per listed slot; block f reduces the records f * nb / FOLD_BLOCKS ..
+// sr; 3: the input of a fused step, the set-up's records at its step 0 and the previous step's
+// after): FOLD_BLOCKS blocks per listed slot; block f reduces the records f * nb / FOLD_BLOCKS ..
 // (f + 1) * nb / FOLD_BLOCKS - 1 (in order) into folded record f, and consumers then reduce the
 // FOLD_BLOCKS folded records (two levels, fixed order: deterministic).
 __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which, StepRef sr) {
@@ -180,7 +181,22 @@ __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, B
     const int f = blockIdx.x % FOLD_BLOCKS;
     int nb, nv;
     const double* rec;
-    if (which == 0) {
+    if (which == 3) {
+        const int j = step_of(sr) - sl.j0;
+        if (j == 0) {
+            if (!sl.fold_upd) return;
+            which = 2;
+            nb = sl.npix;
+            nv = 1 + zr_width(sl.st, sl.nz, 0);
+            rec = sl.rec_upd;
+        } else {
+            if (!sl.fold_app) return;
+            which = 1;
+            nb = sl.ntiles;
+            nv = 4 + sl.s + (j >= 2 ? zr_width(sl.st, sl.nz, j - 1) : 0);
+            rec = ((j - 1) & 1) ? sl.rec_app2 : sl.rec_app;
+        }
+    } else if (which == 0) {
         nb = sl.ntiles;
         nv = 1 + sl.s;
         rec = sl.rec_res;
@@ -259,6 +275,17 @@ hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, co
         case QTY * 1: return launch_b_apply_q<1>(base, rec, fp32, slots, M, sr, stream);
         case QTY * 2: return launch_b_apply_q<2>(base, rec, fp32, slots, M, sr, stream);
         case QTY * 4: return launch_b_apply_q<4>(base, rec, fp32, slots, M, sr, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_f_step(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
+                         hipStream_t stream) {
+    if (M.ns == 0) return hipSuccess;
+    switch (rows) {
+        case QTY * 1: return launch_f_step_q<1>(base, rec, slots, M, sr, stream);
+        case QTY * 2: return launch_f_step_q<2>(base, rec, slots, M, sr, stream);
+        case QTY * 4: return launch_f_step_q<4>(base, rec, slots, M, sr, stream);
         default: return hipErrorInvalidValue;
     }
 }

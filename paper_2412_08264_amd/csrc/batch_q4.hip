@@ -1,4 +1,4 @@
-// Batched residual and apply kernels, and the stand-alone Hessian-vector product, on tiles of
+// Batched residual, apply and fused-step kernels, and the stand-alone Hessian-vector product, on tiles of
 // 32 x 32 pixels.
 #include "batch_tile.h"
 
@@ -7,6 +7,7 @@ namespace bl {
 template hipError_t launch_b_residual_q<4>(const Stencil&, bool, const Slot*, const BatchMap&, int, hipStream_t);
 template hipError_t launch_b_apply_q<4>(const Stencil&, bool, bool, const Slot*, const BatchMap&, StepRef,
                                              hipStream_t);
+template hipError_t launch_f_step_q<4>(const Stencil&, bool, const Slot*, const BatchMap&, StepRef, hipStream_t);
 template hipError_t launch_hvp_q<4>(const Stencil&, bool, const double*, const double*, double*, int,
                                           hipStream_t);
 

@@ -274,6 +274,228 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
         m.y);
 }
 
+// ------------------------------------------------------------------ fused FP64 step
+// One launch per iteration of the recycled CG of an FP64 solve (Chronopoulos and Gear's
+// single-reduction form of CG, with the residual norm recomputed each step).  Launch j:
+//   j = 0   the set-up's records [r_0.r_0, Z^T r_0]: the test of iterate 0; p_0 = r_0, q_0 = H p_0.
+//   j >= 1  the records of launch j - 1 [sigma, rho, r.q, q.q, e = C^T q, Z^T r] (all of iterate
+//           j - 1): the test of iterate j - 1 (from j = 2; launch 0 tested iterate 0), then
+//           alpha = rho / sigma, the projected residual's norm from the recurrence
+//           rho^ = rho - 2 alpha (r.q) + alpha^2 (q.q - e.e)   (C^T r = 0, C^T C = I),
+//           beta = rho^ / rho; on the own pixels r_j = r - alpha (q - C e), w += alpha p,
+//           p_j = r_j + beta p; the stencil input y = r - alpha q + beta p on the tile and its
+//           halo (p_j = y + alpha C e, so H p_j = H y + alpha (H C) e with H C formed once per
+//           solve: no column of C is read on the halo), q_j = H y + alpha (H C e) on the own pixels.
+//   record  [p_j.q_j, r_j.r_j, r_j.q_j, q_j.q_j, C^T q_j, Z^T r_j when iterate j is tested], in the
+//           record buffer of j's parity: launch j + 1 reads them while writing the other.
+// alpha uses the explicit r.r of the previous launch, and so does every test: the recurrence
+// only enters beta.  r, q and p alternate between two buffers by iteration parity; stored
+// basis columns and CG coefficients of iterate j - 1 are written by launch j.
+template <int R, int CLS, int Q, bool REC>
+__global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restrict__ slots, BatchMap M,
+                                               StepRef sr) {
+    using L = QLayout<double, R, CLS, Q>;
+    using G = QGeo<R, CLS, Q>;
+    constexpr int QR = Q;
+    constexpr bool EARLY = CLS == TC_TV && Q < 4;
+    constexpr int CP = c_prefetch<CLS, Q, REC>();
+    constexpr int NST = EARLY ? (G::N_V + NT - 1) / NT : 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    __shared__ double tot[NT];
+    __shared__ int sdone;
+    const int2 m = map_block(M, blockIdx.x);
+    const Slot& sl = slots[m.x];
+    if (m.y >= sl.ntiles) return;
+    SolveState* st = sl.st;
+    const int j = step_of(sr) - sl.j0;
+    if (threadIdx.x == 0) sdone = st->done;
+    const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
+    const int h = sl.h, w = sl.width, n = sl.n;
+    const bool first = j == 0;
+    const double* __restrict__ r0b = (j & 1) ? sl.r : sl.r2;   // iterate j - 1 (j >= 1)
+    const double* __restrict__ q0b = (j & 1) ? sl.q : sl.q2;
+    const double* __restrict__ p0b = sl.p[(j + 1) & 1];
+    double* __restrict__ r1b = (j & 1) ? sl.r2 : sl.r;          // iterate j
+    double* __restrict__ q1b = (j & 1) ? sl.q2 : sl.q;
+    double* __restrict__ p1b = sl.p[j & 1];
+    const double* __restrict__ rin = first ? sl.r : r0b;
+    int r0, c0;
+    slot_tile<Q>(sl, m.y, r0, c0);
+    const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
+    double ri[QR], qi[QR], pi[QR], wi[QR], cpre[CP][QR], hr[NST], hq[NST], hp[NST];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        ri[k] = o.in[k] ? rin[o.g[k]] : 0.0;
+        qi[k] = (o.in[k] && !first) ? q0b[o.g[k]] : 0.0;
+        pi[k] = (o.in[k] && !first) ? p0b[o.g[k]] : 0.0;
+        wi[k] = (o.in[k] && !first) ? sl.w[o.g[k]] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+#pragma unroll
+        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * n + o.g[k]] : 0.0;
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            hr[u] = hq[u] = hp[u] = 0.0;
+            if (idx < G::N_V) {
+                const int rr = idx / G::RW, cc = idx - rr * G::RW;
+                const int gi = r0 - G::E + rr, gj = c0 - G::E + cc;
+                if (gi >= 0 && gi < h && gj >= 0 && gj < w) {
+                    hr[u] = rin[gi * w + gj];
+                    if (!first) {
+                        hq[u] = q0b[gi * w + gj];
+                        hp[u] = p0b[gi * w + gj];
+                    }
+                }
+            }
+        }
+        q_stage_xhat<double, Q>(lds + L::o_x, h, w, sl.xhat, r0, c0);
+    }
+    // records of the previous launch (set-up records for launch 0) and the settings of the test
+    // records of launch j - 1 are in the buffer of its parity (or folded); launch j writes the other
+    int nb;
+    const double* rec = slot_rec(sl, first ? 2 : 1, nb);
+    if (!first && !sl.fold_app && ((j - 1) & 1)) rec = sl.rec_app2;
+    double* rec_out = (j & 1) ? sl.rec_app2 : sl.rec_app;
+    const int zin = first ? zr_width(st, nz, 0) : (j >= 2 ? zr_width(st, nz, j - 1) : 0);
+    const int nin = first ? 1 + zin : 4 + s + zin;
+    const TestSettings ts = test_settings(st);
+    const bool keep = j >= 1 && uni(st->store_basis) && j - 1 < uni(st->v_cap);
+    const bool acc_mine = m.y == 0 && j >= 1 && (int)threadIdx.x < s;
+    const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
+    reduce_partials(rec, nb, nin, tot);
+    if (sdone) return;
+    double alpha = 0.0, beta = 0.0, rho_prev = 0.0;
+    const double* e = tot + 4;
+    bool stop = false;
+    if (first || j >= 2) {   // test of iterate 0 (launch 0) or of iterate j - 1
+        const int it = first ? 0 : j - 1;
+        const double rho_t = first ? tot[0] : tot[1];
+        const Decision dec = decide(st, ts, it, rho_t, first ? tot + 1 : tot + 4 + s, zin > 0);
+        if (m.y == 0 && threadIdx.x == 0) {
+            st->rho2[it & 1] = rho_t;
+            if (zin) st->est = dec.est;
+            st->iters = it;
+            if (first) st->res0 = sqrt(rho_t);
+            if (dec.done) {
+                st->status = dec.status;
+                st->done = 1;
+            }
+        }
+        stop = dec.done;
+    }
+    if (!first && !stop) {
+        const double sigma = tot[0];
+        rho_prev = tot[1];
+        if (!(sigma > 0.0)) {
+            if (m.y == 0 && threadIdx.x == 0) {
+                st->status = (sigma != sigma || fabs(sigma) == INFINITY) ? BL_E_NONFINITE : BL_E_INDEFINITE;
+                st->iters = j - 1;
+                st->done = 1;
+            }
+            stop = true;
+        } else {
+            alpha = rho_prev / sigma;
+            double ee = 0.0;
+            for (int k = 0; k < s; ++k) ee += e[k] * e[k];
+            const double rho_hat = rho_prev - 2.0 * alpha * tot[2] + alpha * alpha * (tot[3] - ee);
+            beta = rho_hat / rho_prev;
+        }
+    }
+    if (stop) return;
+    if (m.y == 0 && j >= 1) {
+        if (acc_mine) st->zacc[threadIdx.x] = zacc0 - alpha * e[threadIdx.x];
+        if (threadIdx.x == 0 && keep && sl.lz) {
+            sl.lz[2 * (j - 1)] = alpha;
+            sl.lz[2 * (j - 1) + 1] = rho_prev;
+        }
+    }
+    Stencil S = base;
+    slot_stencil(S, sl);
+    auto yof = [&](double rv, double qv, double pv) { return first ? rv : rv - alpha * qv + beta * pv; };
+    if constexpr (EARLY) {
+        double* v = lds + L::o_v;
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            if (idx < G::N_V) v[idx] = yof(hr[u], hq[u], hp[u]);
+        }
+    } else {
+        if (first)
+            q_stage<double, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0, [&](int g) { return rin[g]; });
+        else
+            q_stage<double, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0,
+                                       [&](int g) { return rin[g] - alpha * q0b[g] + beta * p0b[g]; });
+        if constexpr (CLS == TC_TV) q_stage_xhat<double, Q>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
+    }
+    __syncthreads();
+    double hv[QR];
+    q_hvp<double, R, CLS, Q>(lds, S, r0, c0, hv);
+    // own pixels: C e and (H C) e of the previous step's e, the new vectors
+    double rn[QR], pn[QR], qn[QR];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        double ce = 0.0, hce = 0.0;
+        if (!first && o.in[k]) {
+#pragma unroll
+            for (int c = 0; c < CP; ++c)
+                if (c < s) ce += cpre[c][k] * e[c];
+            for (int c = CP; c < s; ++c) ce += sl.C[(size_t)c * n + o.g[k]] * e[c];
+            for (int c = 0; c < s; ++c) hce += sl.HC[(size_t)c * n + o.g[k]] * e[c];
+        }
+        const double y = yof(ri[k], qi[k], pi[k]);
+        rn[k] = o.in[k] ? (first ? ri[k] : ri[k] - alpha * qi[k] + alpha * ce) : 0.0;
+        pn[k] = o.in[k] ? y + alpha * ce : 0.0;
+        qn[k] = o.in[k] ? hv[k] + alpha * hce : 0.0;
+        if (o.in[k]) {
+            if (!first) {
+                r1b[o.g[k]] = rn[k];
+                sl.w[o.g[k]] = wi[k] + alpha * pi[k];
+                if (keep) sl.V[(size_t)(j - 1) * n + o.g[k]] = ri[k] / sqrt(rho_prev);
+            }
+            p1b[o.g[k]] = pn[k];
+            q1b[o.g[k]] = qn[k];
+        }
+    }
+    const int zw = j >= 1 ? zr_width(st, nz, j) : 0;
+    block_partials(
+        rec_out, 4 + s + zw,
+        [&](int k) {
+            double acc = 0.0;
+            if (k < 4) {
+#pragma unroll
+                for (int u = 0; u < QR; ++u)
+                    acc += k == 0 ? pn[u] * qn[u] : (k == 1 ? rn[u] * rn[u] : (k == 2 ? rn[u] * qn[u] : qn[u] * qn[u]));
+                return acc;
+            }
+            const int c = k - 4;
+            if (c < s) {
+                if (c < CP) {
+#pragma unroll
+                    for (int cc = 0; cc < CP; ++cc)
+                        if (cc == c) {
+#pragma unroll
+                            for (int u = 0; u < QR; ++u) acc += cpre[cc][u] * qn[u];
+                        }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < QR; ++u)
+                        if (o.in[u]) acc += sl.C[(size_t)c * S.n + o.g[u]] * qn[u];
+                }
+                return acc;
+            }
+            const int z = c - s;
+#pragma unroll
+            for (int u = 0; u < QR; ++u)
+                if (o.in[u]) acc += sl.Z[(size_t)z * S.n + o.g[u]] * rn[u];
+            return acc;
+        },
+        m.y);
+}
+
 // ------------------------------------------------------------------ out[:, c] = H v[:, c]
 // One 32 x 8Q tile of one column per block (grid: tiles x columns): the refresh's Y = H W and
 // the stand-alone product of the ABI.
@@ -342,6 +564,22 @@ hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot
             if (rec) go(k_b_apply<double, RR, CC, Q, true>, l64);
             else go(k_b_apply<double, RR, CC, Q, false>, l64);
         }
+    });
+    return hipGetLastError();
+}
+
+template <int Q>
+hipError_t launch_f_step_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
+                           hipStream_t stream) {
+    q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
+        constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
+        const size_t lds = QLayout<double, RR, CC, Q>::bytes;
+        auto go = [&](auto kern) {
+            allow_lds_b(kern, lds);
+            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, sr);
+        };
+        if (rec) go(k_f_step<RR, CC, Q, true>);
+        else go(k_f_step<RR, CC, Q, false>);
     });
     return hipGetLastError();
 }

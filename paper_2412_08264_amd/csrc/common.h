@@ -17,7 +17,7 @@ constexpr int MAX_R = 8;        // largest blur radius
 constexpr int MAX_NF = 8;       // largest number of filters
 constexpr int MAX_FS = 7;       // largest filter size
 constexpr int RED_BLOCKS = 512; // blocks of 1-D reduction kernels
-constexpr int NV_RED = 2 + 2 * S_MAX;   // widest per-block partial record
+constexpr int NV_RED = 4 + 2 * S_MAX;   // widest per-block partial record
 constexpr int FOLD_BLOCKS = 128;        // blocks (and folded records) per slot of a record fold
 
 // Stencil description passed by value to kernels.
@@ -78,6 +78,10 @@ struct Slot {
     double* r;
     double* p[2];
     double* q;
+    double* r2;                           // fused FP64 steps: r_j, q_j alternate between r / r2, q / q2
+    double* q2;
+    const double* HC;                     // fused FP64 steps with a recycle space: H C (n x s)
+    int fused;                            // one launch per iteration (FP64 solves)
     const double* U;
     const double* C;
     const double* Z;
@@ -87,6 +91,8 @@ struct Slot {
     double* rec_res;                      // records: residual (tiles), apply (tiles), update (pixel blocks)
     double* rec_app;
     double* rec_upd;
+    double* rec_app2;                     // fused steps: records of odd iterations (a launch reads the
+                                          // records of the previous one while writing its own)
     double* fold;                         // folded records: 3 kinds x FOLD_BLOCKS records of NV_RED values
 };
 

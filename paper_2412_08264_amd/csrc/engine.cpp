@@ -248,8 +248,9 @@ size_t slot_bytes(const bl_problem* P, int s) {
     const size_t n = (size_t)P->h * P->w;
     const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
     const size_t nt = ntiles_of(P->h, P->w, QTY), np = npix_of((long)n);
-    return 4 * al(n * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al(TAPS_BYTES) +
-           2 * al(nt * (1 + s) * 8) + al(np * (1 + s) * 8) + al((size_t)3 * FOLD_BLOCKS * NV_RED * 8);
+    return 6 * al(n * 8) + al(n * s * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al(TAPS_BYTES) +
+           al(nt * (1 + s) * 8) + 2 * al(nt * (4 + 2 * s) * 8) + al(np * (1 + s) * 8) +
+           al((size_t)3 * FOLD_BLOCKS * NV_RED * 8);
 }
 
 SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
@@ -267,13 +268,17 @@ SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
     B.p0 = (double*)take(n * 8);
     B.p1 = (double*)take(n * 8);
     B.q = (double*)take(n * 8);
+    B.r2 = (double*)take(n * 8);
+    B.q2 = (double*)take(n * 8);
+    B.HC = (double*)take(n * s * 8);
     B.d1 = nf ? (double*)take(nf * n * 8) : nullptr;
     B.d2 = nf ? (double*)take(nf * n * 8) : nullptr;
     B.d2f = nf ? (float*)take(nf * n * 4) : nullptr;
     B.taps = (double*)take(TAPS_BYTES);
     B.rec_res = (double*)take(nt * (1 + s) * 8);
-    B.rec_app = (double*)take(nt * (1 + s) * 8);
+    B.rec_app = (double*)take(nt * (4 + 2 * s) * 8);
     B.rec_upd = (double*)take(np * (1 + s) * 8);
+    B.rec_app2 = (double*)take(nt * (4 + 2 * s) * 8);
     B.fold = (double*)take((size_t)3 * FOLD_BLOCKS * NV_RED * 8);
     B.st = nullptr;
     return B;
@@ -347,10 +352,18 @@ bl_status Batch::rebuild() {
             if (S[i].group == gi) mine.push_back(i);
         groups[gi].tmap = make_map(S, mine, true);
     }
-    pmap = make_map(S, run_list, false);
+    std::vector<int> two;
+    for (int i : run_list)
+        if (!S[i].d.fused) two.push_back(i);
+    pmap = make_map(S, two, false);
     fold_app = BatchMap{};
     fold_upd = BatchMap{};
+    fold_fused = BatchMap{};
     for (int i : run_list) {
+        if (S[i].d.fused) {
+            if (S[i].d.fold_app || S[i].d.fold_upd) fold_fused.slot[fold_fused.ns++] = i;
+            continue;
+        }
         if (S[i].d.fold_app) fold_app.slot[fold_app.ns++] = i;
         if (S[i].d.fold_upd) fold_upd.slot[fold_upd.ns++] = i;
     }
@@ -412,8 +425,9 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.j0 = step;
     v.s = s;
     v.nz = hg ? s : 0;
+    v.fused = grp.fp32 ? 0 : 1;
     v.fold_res = (long)v.ntiles * (1 + s) > REC_LIMIT;
-    v.fold_app = v.fold_res;
+    v.fold_app = v.fused ? (long)v.ntiles * (4 + s + v.nz) > REC_LIMIT : v.fold_res;
     v.fold_upd = (long)v.npix * (1 + v.nz) > REC_LIMIT;
     v.lam = lam;
     v.gam2 = gam2;
@@ -424,6 +438,9 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.p[0] = B.p0;
     v.p[1] = B.p1;
     v.q = B.q;
+    v.r2 = B.r2;
+    v.q2 = B.q2;
+    v.HC = (v.fused && s) ? B.HC : nullptr;
     v.U = s ? rs->U : nullptr;
     v.C = s ? rs->C : nullptr;
     v.Z = hg ? rs->Z : nullptr;
@@ -433,6 +450,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.rec_res = B.rec_res;
     v.rec_app = B.rec_app;
     v.rec_upd = B.rec_upd;
+    v.rec_app2 = B.rec_app2;
     v.fold = B.fold;
     if (P->reg == BL_REG_FILTERS) {
         const int nf = P->n_filters, f2 = P->filter_size * P->filter_size;
@@ -455,6 +473,22 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         Sx.d2 = v.d2;
         Sx.d2f = v.d2f;
         HIPCHK(launch_filter_state(Sx, sp.xhat, B.d1, B.d2, B.d2f, c->stream));
+    }
+    if (v.fused && s) {   // H C for the fused steps: s FP64 products at (xhat, theta)
+        Stencil Sx = base;
+        Sx.h = P->h;
+        Sx.w = P->w;
+        Sx.n = n;
+        Sx.tiles_x = v.tiles_x;
+        Sx.tiles_y = (P->h + TH - 1) / TH;
+        Sx.lam = lam;
+        Sx.gam2 = gam2;
+        Sx.taps = v.taps;
+        Sx.tapsf = v.tapsf;
+        Sx.lamj = v.lamj;
+        Sx.d2 = v.d2;
+        Sx.d2f = v.d2f;
+        HIPCHK(launch_hvp(Sx, false, sp.xhat, rs->C, B.HC, s, 4 * QTY, c->stream));
     }
     StateInit init{o->tol, o->hg_tol, o->max_iter, o->check_every, o->stop, s, store ? v_cap : 0, store ? 1 : 0,
                    hg ? 1 : 0};
@@ -520,12 +554,13 @@ bl_status Batch::finish(int idx) {
 bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipStream_t ls,
                               bool time_all) {
     bool any_rec = false;
-    for (const Group& grp : groups) any_rec |= grp.rec && grp.tmap.ns > 0;
+    for (const Group& grp : groups) any_rec |= grp.rec && !grp.fused() && grp.tmap.ns > 0;
     for (int k = 0; k < nsteps; ++k) {
         const StepRef sr{d_ctr, k};
         const bool ktime = c->timing == 2 && (time_all || (!c->graphs && (step + k) % KT_SAMPLE == 0));
         if (!rr[k].empty()) TRY(replace_residual(rr[k], 1, k, ls));
         if (fold_upd.ns) HIPCHK(launch_b_fold(d_slots, fold_upd, 2, sr, ls));
+        if (fold_fused.ns) HIPCHK(launch_b_fold(d_slots, fold_fused, 3, sr, ls));
         int ev = 0;
         if (ktime) {
             ev = 3 * (int)timed.size();
@@ -536,8 +571,11 @@ bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector
             }
             HIPCHK(hipEventRecord(c->kev[ev], ls));
         }
-        for (const Group& grp : groups)
-            if (grp.tmap.ns) HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, sr, ls));
+        for (const Group& grp : groups) {
+            if (!grp.tmap.ns) continue;
+            if (grp.fused()) HIPCHK(launch_f_step(grp.base, grp.rows, grp.rec, d_slots, grp.tmap, sr, ls));
+            else HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, sr, ls));
+        }
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], ls));
         if (fold_app.ns) HIPCHK(launch_b_fold(d_slots, fold_app, 1, sr, ls));
         HIPCHK(launch_b_update(d_slots, pmap, sr, any_rec, ls));
@@ -749,7 +787,7 @@ void Batch::stats(int idx, bl_stats* out) const {
     out->g_norm = h.hdr.gnorm;
     out->est = h.hdr.est;
     if (h.rs && h.store_basis) {
-        const int nv = h.hdr.iters + (out->status == BL_E_INDEFINITE ? 1 : 0);
+        const int nv = h.hdr.iters + (out->status == BL_E_INDEFINITE && !h.d.fused ? 1 : 0);
         h.rs->v_cur = std::min(nv, h.v_cap);
         // the CG coefficients describe the stored residuals up to the first residual replacement
         // after the set-up (mixed precision): the relation of the later ones to them is broken

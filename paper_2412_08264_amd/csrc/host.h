@@ -89,10 +89,11 @@ bool tile_cache_load_all(const char* path, int& entries, std::string& err);
 // Device scratch of one solve.
 struct SlotBuffers {
     double *r, *p0, *p1, *q;
+    double *r2, *q2, *HC;     // fused FP64 steps: second r and q buffers, H C (n x s)
     double *d1, *d2;
     float* d2f;
     double* taps;
-    double *rec_res, *rec_app, *rec_upd, *fold;
+    double *rec_res, *rec_app, *rec_upd, *rec_app2, *fold;
     bl::SolveState* st;
 };
 // Bytes of SlotBuffers (without st) for an h x w problem of this class with s recycle columns,
@@ -129,11 +130,14 @@ public:
     hipEvent_t poll_ev[2] = {};
 
     struct Group {                 // operator class, tile height, recycling: stencil template, precision
+                                   // (FP64 groups run the fused one-launch step, FP32-stencil ones the
+                                   // apply + update pair with residual replacement)
         bl_problem cls{};
         bl::Stencil base{};
         bool fp32 = false;
         int rows = 0;
         bool rec = false;          // solves with a recycle space (projection code) or plain CG
+        bool fused() const { return !fp32; }
         int users = 0;             // slots in use
         bl::BatchMap tmap{};       // tile map of its running slots
     };
@@ -174,7 +178,7 @@ public:
 
 private:
     bool dirty = true;
-    bl::BatchMap pmap{}, fold_app{}, fold_upd{};
+    bl::BatchMap pmap{}, fold_app{}, fold_upd{}, fold_fused{};   // pmap / fold_*: two-launch slots only
     std::vector<int> run_list;
     struct Timed {
         int ev;                    // first of 3 events

@@ -55,6 +55,12 @@ hipError_t launch_b_residual(const Stencil& base, int rows, bool rec, const Slot
                              int periodic, hipStream_t stream);
 hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
                           StepRef sr, hipStream_t stream);
+// Fused FP64 step of the recycled CG (one launch per iteration), on tiles of `rows` rows.
+hipError_t launch_f_step(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
+                         hipStream_t stream);
+template <int Q>
+hipError_t launch_f_step_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
+                           hipStream_t stream);
 template <int Q>
 hipError_t launch_b_residual_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, int periodic,
                                hipStream_t stream);
@@ -65,7 +71,9 @@ hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot
     extern template hipError_t launch_b_residual_q<Q>(const Stencil&, bool, const Slot*, const BatchMap&, int,    \
                                                       hipStream_t);                                               \
     extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, bool, const Slot*, const BatchMap&,      \
-                                                   StepRef, hipStream_t);
+                                                   StepRef, hipStream_t);                                         \
+    extern template hipError_t launch_f_step_q<Q>(const Stencil&, bool, const Slot*, const BatchMap&, StepRef,    \
+                                                  hipStream_t);
 #define BL_HVP_EXTERN(Q)                                                                                   \
     extern template hipError_t launch_hvp_q<Q>(const Stencil&, bool, const double*, const double*, double*, int, \
                                                hipStream_t);

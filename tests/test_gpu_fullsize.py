@@ -55,7 +55,7 @@ def test_recycled_cg_1024_tv(B):
     mu = np.geomspace(1.0, 1e-2, s)
     k = 6
     ref = krylov.recycled_cg(hvp, g, None, U, Cq, Z, mu, tol=0.0, max_iter=k, stop="hgerr", hg_tol=0.0,
-                             record=True)
+                             record=True, recurrence="single")   # the GPU's FP64 single-reduction form
     with B.Session(B.problem_from(wl), s_max=s, v_cap=4) as S:
         S.U[:s] = dev(U.T)
         S.Cm[:s] = dev(Cq.T)

@@ -107,7 +107,8 @@ def test_solve_records_cg_coefficients(B):
     first = krylov.cg(h0, x0 - xs, tol=1e-10, v_cap=20)
     rs0 = recycle.refresh(h0, lambda v: prob.jac_apply(x0, t0, v), None, first["V"], s=6)
     g = x0 - xs
-    ref = krylov.recycled_cg(h0, g, None, rs0["U"], rs0["C"], tol=0.0, max_iter=30, v_cap=24)
+    ref = krylov.recycled_cg(h0, g, None, rs0["U"], rs0["C"], tol=0.0, max_iter=30, v_cap=24,
+                             recurrence="single")   # the GPU's FP64 single-reduction form
     with B.Session(B.problem_from(wl, prec="fp64"), s_max=6, v_cap=24) as S:
         S.U[:6] = dev(rs0["U"].T)
         S.Cm[:6] = dev(rs0["C"].T)

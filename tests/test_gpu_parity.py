@@ -13,6 +13,10 @@ from oracle import krylov, lbfgs, problem, recycle
 
 pytestmark = pytest.mark.gpu
 
+# FP64 solves run the fused single-reduction step on the GPU: the oracle's references take the
+# same CG form (recycled_cg's recurrence option), so iterates compare like with like
+SINGLE = "single"
+
 torch = pytest.importorskip("torch")
 
 
@@ -187,9 +191,9 @@ def test_plain_cg_fixed_iterations_and_basis(B):
     w0 = 0.1 * synth.unit_noise(prob.n, 8)
     hvp = lambda v: prob.hvp(xh, th, v)
     for k in (1, 10, 25, 40):
-        ref = krylov.cg(hvp, g, w0, tol=0.0, max_iter=k, v_cap=16)
+        ref = krylov.cg(hvp, g, w0, tol=0.0, max_iter=k, v_cap=16, recurrence=SINGLE)
         bound = 1e-10 if k <= 25 else max(1e-10, 100 * oracle_sensitivity(
-            lambda gg: krylov.cg(hvp, gg, w0, tol=0.0, max_iter=k)["w"], g))
+            lambda gg: krylov.cg(hvp, gg, w0, tol=0.0, max_iter=k, recurrence=SINGLE)["w"], g))
         with B.Session(B.problem_from(wl), s_max=4, v_cap=16) as S:
             w = dev(w0)
             st = S.solve(th, dev(xh), dev(g), w, tol=0.0, max_iter=k, allow=(B.BL_E_NOT_CONVERGED,))
@@ -207,7 +211,7 @@ def test_plain_cg_converged(B):
     th = inst["theta0"]
     g = xh - inst["xstar"].ravel()
     hvp = lambda v: prob.hvp(xh, th, v)
-    ref = krylov.cg(hvp, g, tol=1e-10)
+    ref = krylov.cg(hvp, g, tol=1e-10, recurrence=SINGLE)
     with B.Session(B.problem_from(wl), s_max=4, v_cap=16) as S:
         w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
         st = S.solve(th, dev(xh), dev(g), w, tol=1e-10)
@@ -241,7 +245,8 @@ def test_recycled_cg_parity(B, stop):
     w0 = first["w"]
     hg_tol = 1e-7 * np.linalg.norm(jac(first["w"]))
     for k in (1, 7, 25):   # fixed iteration counts
-        ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k)
+        ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
+                                 recurrence=SINGLE)
         with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
             upload_recycle(S, rs)
             w = dev(w0)
@@ -251,7 +256,7 @@ def test_recycled_cg_parity(B, stop):
         if stop == "hgerr":
             # the error estimate after k iterations
             ref_e = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
-                                       stop="hgerr", hg_tol=0.0, record=True)
+                                       stop="hgerr", hg_tol=0.0, record=True, recurrence=SINGLE)
             with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
                 upload_recycle(S, rs)
                 st = S.solve(th2, dev(xh), dev(g), dev(w0), tol=0.0, max_iter=k, stop="hgerr", hg_tol=0.0,
@@ -260,9 +265,10 @@ def test_recycled_cg_parity(B, stop):
     # converged: the stopping iteration of the estimate test is itself rounding-sensitive
     # (the estimate is far from monotone), so the GPU must stop inside the spread of the
     # oracle's own stopping iterations under one-ulp perturbations of g, and meet the test.
-    ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)
+    ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol,
+                             recurrence=SINGLE)
     runs = [krylov.recycled_cg(hvp2, g * (1 + 2.0 ** -52 * synth.unit_noise(prob.n, 200 + k)), w0, rs["U"],
-                               rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol)
+                               rs["C"], rs["Z"], rs["mu"], tol=1e-10, stop=stop, hg_tol=hg_tol, recurrence=SINGLE)
             for k in range(4)] + [ref]
     spread = [r_["iters"] for r_ in runs]
     wstar, _ = krylov.reference_solve(hvp2, g)
@@ -299,7 +305,7 @@ def test_error_estimate_on_tested_iterations_only(B):
     w0 = first["w"]
     for k in (8, 10, 13):
         ref = krylov.recycled_cg(hvp2, g, w0, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
-                                 stop="hgerr", hg_tol=0.0, record=True)
+                                 stop="hgerr", hg_tol=0.0, record=True, recurrence=SINGLE)
         with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
             upload_recycle(S, rs)
             w = dev(w0)
@@ -310,7 +316,8 @@ def test_error_estimate_on_tested_iterations_only(B):
             assert rel(host(w), ref["w"]) <= 1e-10
     hg_tol = 1e-7 * np.linalg.norm(jac(first["w"]))
     runs = [krylov.recycled_cg(hvp2, g * (1 + 2.0 ** -52 * synth.unit_noise(prob.n, 300 + k)), w0, rs["U"], rs["C"],
-                               rs["Z"], rs["mu"], tol=1e-10, stop="hgerr", hg_tol=hg_tol, check_every=4)
+                               rs["Z"], rs["mu"], tol=1e-10, stop="hgerr", hg_tol=hg_tol, check_every=4,
+                               recurrence=SINGLE)
             for k in range(4)]
     spread = [r_["iters"] for r_ in runs]
     with B.Session(B.problem_from(wl), s_max=8, v_cap=30) as S:
@@ -335,7 +342,7 @@ def test_recycled_cg_folded_records(B):
     s_eff = rs["U"].shape[1]
     k = 9
     ref = krylov.recycled_cg(hvp, g, None, rs["U"], rs["C"], rs["Z"], rs["mu"], tol=0.0, max_iter=k,
-                             stop="hgerr", hg_tol=0.0, record=True)
+                             stop="hgerr", hg_tol=0.0, record=True, recurrence=SINGLE)
     P = B.problem_from(wl)
     try:
         B.bl_tile_rows_set(P, 8)
@@ -365,7 +372,8 @@ def test_recycled_cg_every_tile_height(B, kind, prec):
     rs = recycle.refresh(hvp, lambda v: prob.jac_apply(xh, th, v), None, first["V"], s=6)
     P = B.problem_from(wl, prec=prec)
     k = 12
-    ref = krylov.recycled_cg(hvp, g, None, rs["U"], rs["C"], tol=0.0, max_iter=k)
+    ref = krylov.recycled_cg(hvp, g, None, rs["U"], rs["C"], tol=0.0, max_iter=k,
+                             recurrence=SINGLE if prec == "fp64" else "textbook")
     wstar, _ = krylov.reference_solve(hvp, g)
     try:
         for rows in (8, 16, 32):
@@ -441,29 +449,6 @@ def test_refresh_parity_filters(B):
         assert recycle.principal_angles(U, ref["U"]).max() <= 1e-8
 
 
-def test_sequence_tv32(B):
-    """Full GPU pipeline (refresh + recycled solve + hypergradient) on the 32x32 TV trajectory."""
-    from oracle import upper
-    wl = synth.WORKLOADS["tv32"]
-    inst = synth.instance(wl)
-    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
-    thetas, xhats = upper.trajectory(prob, inst["xstar"], inst["theta0"], 6)
-    xs = inst["xstar"].ravel()
-    ref = upper.solve_sequence(prob, thetas, xhats, xs, s=wl.s, tol=wl.tol)
-    refs = [upper.hypergradient(prob, x, t, xs)[0] for t, x in zip(thetas, xhats)]
-    with B.Session(B.problem_from(wl), s_max=wl.s, v_cap=64) as S:
-        w = torch.zeros(prob.n, dtype=torch.float64, device=DEV)
-        for i, (t, x) in enumerate(zip(thetas, xhats)):
-            xd, gd = dev(x), dev(x - xs)
-            if i:
-                S.refresh(t, xd, s=wl.s)
-            st = S.solve(t, xd, gd, w, tol=wl.tol)
-            hg = S.hypergradient(t, xd, w)
-            assert abs(st.iters - ref[i]["iters"]) <= 2
-            assert rel(hg, refs[i]) <= 1e-8
-            assert rel(hg, ref[i]["hg"]) <= 1e-8
-
-
 @pytest.fixture(scope="module")
 def tv32_sequence():
     """The 32x32 TV recipe's 20-step frozen trajectory and the oracle's recycled solve sequence
@@ -474,7 +459,8 @@ def tv32_sequence():
     prob = problem.make_problem(wl, inst["xstar"], inst["e"])
     thetas, xhats = upper.trajectory(prob, inst["xstar"], inst["theta0"], wl.outer)
     xs = inst["xstar"].ravel()
-    ref = upper.solve_sequence(prob, thetas, xhats, xs, s=wl.s, tol=wl.tol)
+    # the GPU's FP64 solves take the single-reduction form: the oracle runs the same form
+    ref = upper.solve_sequence(prob, thetas, xhats, xs, s=wl.s, tol=wl.tol, recurrence="single")
     return wl, prob, thetas, xhats, xs, ref
 
 
@@ -517,7 +503,7 @@ def test_sequence_tv32_at_oracle_stop(B, tv32_sequence):
             g = x - xs
             # the oracle's one-ulp spread at its own stopping iteration
             pert = krylov.recycled_cg(hvp, np.nextafter(g, np.inf), r["w0"], rs["U"], rs["C"], tol=0.0,
-                                      max_iter=r["iters"], v_cap=0)
+                                      max_iter=r["iters"], v_cap=0, recurrence="single")
             spread_w = rel(pert["w"], r["w"])
             spread_hg = rel(prob.jac_apply(x, t, pert["w"]), r["hg"])
             if rs["U"] is not None:

@@ -112,18 +112,22 @@ def test_one_step_exactness():
 
 
 def test_single_reduction_recurrence():
-    """The rho-recurrence agrees with the textbook form early on but loses accuracy as the
-    residual falls (cancellation in rho - 2 alpha r.q + alpha^2 |q - Ce|^2), so it is an
-    oracle option only and never the default."""
+    """Single-reduction form (the GPU's fused FP64 step): beta from the recurrence
+    rho - 2 alpha r.q + alpha^2 (q.q - e.e) anchored on the explicit r.r of the previous iterate,
+    alpha and every stop test from the explicit r.r.  It reaches the same true residual as the
+    textbook form within a few iterations (rounding changes CG's path over ~180 iterations),
+    and agrees with it to rounding at small counts; the recurrence really enters (the iterates
+    differ in the last bits)."""
     n, s = 70, 4
     H = spd(n, 300.0, 13)
     g = np.random.default_rng(14).standard_normal(n)
     U, C = recycle_pair(H, s, 15)
     a = krylov.recycled_cg(lambda v: H @ v, g, None, U, C, tol=1e-11)
     b = krylov.recycled_cg(lambda v: H @ v, g, None, U, C, tol=1e-11, recurrence="single")
-    true_b = np.linalg.norm(g - H @ b["w"]) / np.linalg.norm(g)
     assert np.linalg.norm(g - H @ a["w"]) / np.linalg.norm(g) <= 1e-10
-    assert true_b > 1e-11          # stopped on an under-estimated residual
+    assert np.linalg.norm(g - H @ b["w"]) / np.linalg.norm(g) <= 1e-10
+    assert abs(a["iters"] - b["iters"]) <= 3
+    assert not np.array_equal(a["w"], b["w"])
     # at a fixed small iteration count the two recurrences agree to rounding
     a5 = krylov.recycled_cg(lambda v: H @ v, g, None, U, C, tol=0.0, max_iter=5)
     b5 = krylov.recycled_cg(lambda v: H @ v, g, None, U, C, tol=0.0, max_iter=5, recurrence="single")
