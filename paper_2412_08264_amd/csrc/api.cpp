@@ -23,7 +23,7 @@ constexpr int LBFGS_MMAX = 20;
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, mstate, slots, hdr, ctr, fold, part, vec, maps, taps, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, mstate, slots, hdr, ctr, fold, part, vec, maps, taps, mhc, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -55,6 +55,7 @@ Layout layout(const bl_problem* P, int s_max, int v_cap, bool solve_only = false
     L.vec = o;      o += al(((size_t)8 * L.n + 2 * L.p) * sizeof(double));   // 8 vectors + a p-vector
     L.maps = o;     o += al((size_t)L.nf * L.n * (2 * sizeof(double) + sizeof(float)));
     L.taps = o;     o += al(TAPS_BYTES);
+    L.mhc = o;      o += al((size_t)s_max * s_max * sizeof(double));   // the solve's C^T H C
     if (solve_only) {   // the solve's H C (n x s_max) in the place of the refresh's U~
         L.W0 = L.W1 = L.Ct = L.small = L.lb = L.Ut = o;
         o += al((size_t)L.n * std::max(s_max, 1) * sizeof(double));
@@ -93,6 +94,7 @@ struct WS {
     double* d2() const { return d1() + (size_t)L.nf * L.n; }
     float* d2f() const { return (float*)(d2() + (size_t)L.nf * L.n); }
     double* taps() const { return (double*)(base + L.taps); }
+    double* mhc() const { return (double*)(base + L.mhc); }
     double* W0() const { return (double*)(base + L.W0); }
     double* W1() const { return (double*)(base + L.W1); }
     double* Ut() const { return (double*)(base + L.Ut); }
@@ -308,6 +310,8 @@ bl_status solve_in(bl_ctx* c, const bl_problem* P, const double* theta, const do
     buf.r2 = ws.vec(4);
     buf.q2 = ws.vec(5);
     buf.HC = ws.Ut();
+    buf.M = ws.mhc();
+    buf.mpart = ws.vec(1);   // vectors 1-4, free until the set-up
     buf.d1 = ws.d1();
     buf.d2 = ws.d2();
     buf.d2f = ws.d2f();

@@ -88,17 +88,17 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
 #pragma unroll
     for (int k = 0; k < QR; ++k) gv[k] = o.in[k] ? sl.g[o.g[k]] : 0.0;
     q_stage<double, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return sl.w[gi]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<double, Q>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
+    const TvX<Q> X = tv_x<CLS, Q>(S.h, S.w, sl.xhat, r0, c0);
     __syncthreads();
     double hv[QR];
-    q_hvp<double, R, CLS, Q>(lds, S, r0, c0, hv);
+    q_hvp<double, R, CLS, Q>(lds, S, r0, c0, hv, X);
     double ov[QR];
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
         ov[k] = o.in[k] ? gv[k] - hv[k] : 0.0;
         if (o.in[k]) sl.r[o.g[k]] = ov[k];
     }
-    block_partials(
+    block_partials_in(reinterpret_cast<double*>(smem_raw),
         sl.rec_res, REC ? 1 + sl.s : 1,
         [&](int k) {
             double acc = 0.0;
@@ -158,6 +158,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
     // p_old is read whatever the iteration and selected away below when the direction restarts
     double ri[QR], pr[QR], cpre[CP][QR], hr[NST], hp[NST];
+    TvX<Q> X{};
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
         ri[k] = o.in[k] ? r[o.g[k]] : 0.0;
@@ -181,7 +182,6 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
                 }
             }
         }
-        q_stage_xhat<T, Q>(lds + L::o_x, h, w, sl.xhat, r0, c0);
     }
     int nb;
     const double* rec = slot_rec(sl, 2, nb);
@@ -212,6 +212,8 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
         }
     }
     if (dec.done) return;
+    // x_hat for the flux blocks: read after the decision, held through the first pass only
+    if constexpr (EARLY) X = tv_xload<Q>(h, w, sl.xhat, r0, c0);
     Stencil S = base;
     slot_stencil(S, sl);
     const bool first = (j == 0) || restart;
@@ -229,11 +231,11 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     } else {
         q_stage<T, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0,
                               [&](int g) { return first ? r[g] : r[g] + beta * p_old[g]; });
-        if constexpr (CLS == TC_TV) q_stage_xhat<T, Q>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
+        if constexpr (CLS == TC_TV) X = tv_xload<Q>(h, w, sl.xhat, r0, c0);
     }
     __syncthreads();
     T hv[QR];
-    q_hvp<T, R, CLS, Q>(lds, S, r0, c0, hv);
+    q_hvp<T, R, CLS, Q>(lds, S, r0, c0, hv, X);
     double pv[QR], qq[QR];
     const double inv = store_basis ? 1.0 / sqrt(rho) : 0.0;
 #pragma unroll
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
             if (store_basis) sl.V[(size_t)j * S.n + o.g[k]] = ri[k] * inv;
         }
     }
-    block_partials(
+    block_partials_in(reinterpret_cast<double*>(smem_raw),
         sl.rec_app, 1 + s,
         [&](int k) {
             double acc = 0.0;
@@ -288,9 +290,18 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
 //           solve: no column of C is read on the halo), q_j = H y + alpha (H C e) on the own pixels.
 //   record  [p_j.q_j, r_j.r_j, r_j.q_j, q_j.q_j, C^T q_j, Z^T r_j when iterate j is tested], in the
 //           record buffer of j's parity: launch j + 1 reads them while writing the other.
+// C^T q_j = C^T (H y) + alpha (C^T H C) e: the blocks reduce C^T (H y) from the stencil output, and
+// block 0 adds alpha M e with M = C^T H C (s x s, formed with H C), so each column of C and of
+// H C is read once per launch, in rounds of a few columns (no column is held in registers
+// across the stencil, except the first few, loaded before the record reduction on 8-row tiles).
 // alpha uses the explicit r.r of the previous launch, and so does every test: the recurrence
 // only enters beta.  r, q and p alternate between two buffers by iteration parity; stored
 // basis columns and CG coefficients of iterate j - 1 are written by launch j.
+template <int CLS, int Q>
+__host__ __device__ constexpr int f_prefetch() {
+    return Q == 1 ? (CLS == TC_TV ? 16 : 8) : 0;
+}
+
 template <int R, int CLS, int Q, bool REC>
 __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restrict__ slots, BatchMap M,
                                                StepRef sr) {
@@ -298,7 +309,9 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     using G = QGeo<R, CLS, Q>;
     constexpr int QR = Q;
     constexpr bool EARLY = CLS == TC_TV && Q < 4;
-    constexpr int CP = c_prefetch<CLS, Q, REC>();
+    constexpr int PF = REC ? f_prefetch<CLS, Q>() : 0;   // columns of C and H C loaded up front
+    constexpr int PFA = PF > 0 ? PF : 1;
+    constexpr int CH = Q == 1 ? 8 : (Q == 2 ? 4 : 2);      // columns per later round of loads
     constexpr int NST = EARLY ? (G::N_V + NT - 1) / NT : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
@@ -323,7 +336,8 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     int r0, c0;
     slot_tile<Q>(sl, m.y, r0, c0);
     const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
-    double ri[QR], qi[QR], pi[QR], wi[QR], cpre[CP][QR], hr[NST], hq[NST], hp[NST];
+    double ri[QR], qi[QR], pi[QR], wi[QR], cpre[PFA][QR], hpre[PFA][QR], hr[NST], hq[NST], hp[NST];
+    TvX<Q> X{};
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
         ri[k] = o.in[k] ? rin[o.g[k]] : 0.0;
@@ -332,9 +346,13 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         wi[k] = (o.in[k] && !first) ? sl.w[o.g[k]] : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < CP; ++c)
+    for (int c = 0; c < PFA; ++c)
 #pragma unroll
-        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * n + o.g[k]] : 0.0;
+        for (int k = 0; k < QR; ++k) {
+            const bool ld = PF > 0 && o.in[k] && c < s;
+            cpre[c][k] = ld ? sl.C[(size_t)c * n + o.g[k]] : 0.0;
+            hpre[c][k] = (ld && !first) ? sl.HC[(size_t)c * n + o.g[k]] : 0.0;
+        }
     if constexpr (EARLY) {
 #pragma unroll
         for (int u = 0; u < NST; ++u) {
@@ -352,9 +370,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
                 }
             }
         }
-        q_stage_xhat<double, Q>(lds + L::o_x, h, w, sl.xhat, r0, c0);
     }
-    // records of the previous launch (set-up records for launch 0) and the settings of the test
     // records of launch j - 1 are in the buffer of its parity (or folded); launch j writes the other
     int nb;
     const double* rec = slot_rec(sl, first ? 2 : 1, nb);
@@ -366,7 +382,9 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     const bool keep = j >= 1 && uni(st->store_basis) && j - 1 < uni(st->v_cap);
     const bool acc_mine = m.y == 0 && j >= 1 && (int)threadIdx.x < s;
     const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
-    reduce_partials(rec, nb, nin, tot);
+    // recycled steps on 8-row tiles (small images, latency-bound): 32 loads in flight per thread
+    // cover the records of a 256 x 256 image in one round
+    reduce_partials<(REC && Q == 1) ? 32 : 8>(rec, nb, nin, tot);
     if (sdone) return;
     double alpha = 0.0, beta = 0.0, rho_prev = 0.0;
     const double* e = tot + 4;
@@ -406,6 +424,17 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         }
     }
     if (stop) return;
+    if constexpr (EARLY) X = tv_xload<Q>(h, w, sl.xhat, r0, c0);
+    // block 0, thread 4 + k: alpha (M e)_k, the part of record value 4 + k that no pixel carries
+    double corr = 0.0;
+    if constexpr (REC) {
+        const int k = (int)threadIdx.x - 4;
+        if (m.y == 0 && !first && k >= 0 && k < s) {
+            double acc = 0.0;
+            for (int l = 0; l < s; ++l) acc += sl.M[(size_t)l * s + k] * e[l];
+            corr = alpha * acc;
+        }
+    }
     if (m.y == 0 && j >= 1) {
         if (acc_mine) st->zacc[threadIdx.x] = zacc0 - alpha * e[threadIdx.x];
         if (threadIdx.x == 0 && keep && sl.lz) {
@@ -429,27 +458,61 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         else
             q_stage<double, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0,
                                        [&](int g) { return rin[g] - alpha * q0b[g] + beta * p0b[g]; });
-        if constexpr (CLS == TC_TV) q_stage_xhat<double, Q>(lds + L::o_x, S.h, S.w, sl.xhat, r0, c0);
+        if constexpr (CLS == TC_TV) X = tv_xload<Q>(h, w, sl.xhat, r0, c0);
     }
     __syncthreads();
     double hv[QR];
-    q_hvp<double, R, CLS, Q>(lds, S, r0, c0, hv);
-    // own pixels: C e and (H C) e of the previous step's e, the new vectors
+    q_hvp<double, R, CLS, Q>(lds, S, r0, c0, hv, X);
+    // per-wave record sums in the tile's LDS (free once the product is in registers)
+    double* wred = lds;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto put = [&](int k, double v) {
+        const double t = wave_sum(v);
+        if (lane == 0) wred[wave * NV_RED + k] = t;
+    };
+    // columns of C and H C: C e and (H C) e of the previous step's e at the own pixels, and the
+    // record values C^T (H y)
+    double ce[QR], hce[QR];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) ce[k] = hce[k] = 0.0;
+    if constexpr (REC) {
+        auto column = [&](int c, const double* cv, const double* hcv) {
+            const double ec = first ? 0.0 : e[c];
+            double d = 0.0;
+#pragma unroll
+            for (int k = 0; k < QR; ++k) {
+                ce[k] += cv[k] * ec;
+                hce[k] += hcv[k] * ec;
+                d += cv[k] * hv[k];
+            }
+            put(4 + c, d);
+        };
+#pragma unroll
+        for (int c = 0; c < PF; ++c)
+            if (c < s) column(c, cpre[c], hpre[c]);
+        for (int c0r = PF; c0r < s; c0r += CH) {
+            double cv[CH][QR], hcv[CH][QR];
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+#pragma unroll
+                for (int k = 0; k < QR; ++k) {
+                    const bool ld = o.in[k] && c0r + i < s;
+                    cv[i][k] = ld ? sl.C[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
+                    hcv[i][k] = (ld && !first) ? sl.HC[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
+                }
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (c0r + i < s) column(c0r + i, cv[i], hcv[i]);
+        }
+    }
+    // own pixels: the new vectors
     double rn[QR], pn[QR], qn[QR];
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
-        double ce = 0.0, hce = 0.0;
-        if (!first && o.in[k]) {
-#pragma unroll
-            for (int c = 0; c < CP; ++c)
-                if (c < s) ce += cpre[c][k] * e[c];
-            for (int c = CP; c < s; ++c) ce += sl.C[(size_t)c * n + o.g[k]] * e[c];
-            for (int c = 0; c < s; ++c) hce += sl.HC[(size_t)c * n + o.g[k]] * e[c];
-        }
         const double y = yof(ri[k], qi[k], pi[k]);
-        rn[k] = o.in[k] ? (first ? ri[k] : ri[k] - alpha * qi[k] + alpha * ce) : 0.0;
-        pn[k] = o.in[k] ? y + alpha * ce : 0.0;
-        qn[k] = o.in[k] ? hv[k] + alpha * hce : 0.0;
+        rn[k] = o.in[k] ? (first ? ri[k] : ri[k] - alpha * qi[k] + alpha * ce[k]) : 0.0;
+        pn[k] = o.in[k] ? y + alpha * ce[k] : 0.0;
+        qn[k] = o.in[k] ? hv[k] + alpha * hce[k] : 0.0;
         if (o.in[k]) {
             if (!first) {
                 r1b[o.g[k]] = rn[k];
@@ -460,40 +523,49 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
             q1b[o.g[k]] = qn[k];
         }
     }
+    {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int k = 0; k < QR; ++k) {
+            a0 += pn[k] * qn[k];
+            a1 += rn[k] * rn[k];
+            a2 += rn[k] * qn[k];
+            a3 += qn[k] * qn[k];
+        }
+        put(0, a0);
+        put(1, a1);
+        put(2, a2);
+        put(3, a3);
+    }
+    // Z^T r_j when iterate j is tested (launch j + 1 tests it)
     const int zw = j >= 1 ? zr_width(st, nz, j) : 0;
-    block_partials(
-        rec_out, 4 + s + zw,
-        [&](int k) {
-            double acc = 0.0;
-            if (k < 4) {
+    if constexpr (REC) {
+        for (int z0 = 0; z0 < zw; z0 += CH) {
+            double zv[CH][QR];
 #pragma unroll
-                for (int u = 0; u < QR; ++u)
-                    acc += k == 0 ? pn[u] * qn[u] : (k == 1 ? rn[u] * rn[u] : (k == 2 ? rn[u] * qn[u] : qn[u] * qn[u]));
-                return acc;
+            for (int i = 0; i < CH; ++i)
+#pragma unroll
+                for (int k = 0; k < QR; ++k)
+                    zv[i][k] = (o.in[k] && z0 + i < zw) ? sl.Z[(size_t)(z0 + i) * n + o.g[k]] : 0.0;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                if (z0 + i >= zw) break;
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < QR; ++k) d += zv[i][k] * rn[k];
+                put(4 + s + z0 + i, d);
             }
-            const int c = k - 4;
-            if (c < s) {
-                if (c < CP) {
+        }
+    }
+    __syncthreads();
+    const int nv = 4 + s + zw;
+    for (int k = threadIdx.x; k < nv; k += NT) {
+        double sum = 0.0;
 #pragma unroll
-                    for (int cc = 0; cc < CP; ++cc)
-                        if (cc == c) {
-#pragma unroll
-                            for (int u = 0; u < QR; ++u) acc += cpre[cc][u] * qn[u];
-                        }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < QR; ++u)
-                        if (o.in[u]) acc += sl.C[(size_t)c * S.n + o.g[u]] * qn[u];
-                }
-                return acc;
-            }
-            const int z = c - s;
-#pragma unroll
-            for (int u = 0; u < QR; ++u)
-                if (o.in[u]) acc += sl.Z[(size_t)z * S.n + o.g[u]] * rn[u];
-            return acc;
-        },
-        m.y);
+        for (int wv = 0; wv < NWAVE; ++wv) sum += wred[wv * NV_RED + k];
+        if (k == (int)threadIdx.x) sum += corr;
+        rec_out[(size_t)m.y * nv + k] = sum;
+    }
 }
 
 // ------------------------------------------------------------------ out[:, c] = H v[:, c]
@@ -511,10 +583,10 @@ __global__ void __launch_bounds__(NT) k_hvp(Stencil S, const double* __restrict_
     const int r0 = (t / qtx) * QH, c0 = (t % qtx) * QW;
     const double* vc = v + (size_t)blockIdx.y * S.n;
     q_stage<T, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0, [&](int i) { return vc[i]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<T, Q>(lds + L::o_x, S.h, S.w, xhat, r0, c0);
+    const TvX<Q> X = tv_x<CLS, Q>(S.h, S.w, xhat, r0, c0);
     __syncthreads();
     T hv[Q];
-    q_hvp<T, R, CLS, Q>(lds, S, r0, c0, hv);
+    q_hvp<T, R, CLS, Q>(lds, S, r0, c0, hv, X);
     double* oc = out + (size_t)blockIdx.y * S.n;
     const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW, gj = c0 + tx;
 #pragma unroll

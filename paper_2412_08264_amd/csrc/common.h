@@ -81,6 +81,7 @@ struct Slot {
     double* r2;                           // fused FP64 steps: r_j, q_j alternate between r / r2, q / q2
     double* q2;
     const double* HC;                     // fused FP64 steps with a recycle space: H C (n x s)
+    const double* M;                      // and C^T H C (s x s, column-major)
     int fused;                            // one launch per iteration (FP64 solves)
     const double* U;
     const double* C;
@@ -179,9 +180,10 @@ __device__ __forceinline__ double block_sum(double val, double* red) {
 // Block partial record of nv values (nv <= NV_RED): value k of this thread is val(k).
 // Each wavefront reduces with shuffles, one barrier, then threads k < nv add the NWAVE
 // wave sums in fixed order and write part[blockIdx.x * nv + k].
+// block_partials_in takes the NWAVE x NV_RED doubles of LDS for the wave sums from the caller
+// (a tile kernel passes its tile region, free once the product is in registers).
 template <typename Val>
-__device__ __forceinline__ void block_partials(double* part, int nv, Val val, int rec_index = -1) {
-    __shared__ double wred[NWAVE][NV_RED];
+__device__ __forceinline__ void block_partials_in(double* wred, double* part, int nv, Val val, int rec_index = -1) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k0 = 0; k0 < nv; k0 += 8) {
         // the values of a group of 8 (typically loads of 8 columns) are all in flight
@@ -193,7 +195,7 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
         for (int u = 0; u < 8; ++u) {
             if (k0 + u >= nv) break;   // uniform: no reduction of the padding values
             const double sum = wave_sum(v[u]);
-            if (lane == 0) wred[wave][k0 + u] = sum;
+            if (lane == 0) wred[wave * NV_RED + k0 + u] = sum;
         }
     }
     __syncthreads();
@@ -201,9 +203,14 @@ __device__ __forceinline__ void block_partials(double* part, int nv, Val val, in
     for (int k = threadIdx.x; k < nv; k += NT) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < NWAVE; ++w) s += wred[w][k];
+        for (int w = 0; w < NWAVE; ++w) s += wred[w * NV_RED + k];
         part[rec * nv + k] = s;
     }
+}
+template <typename Val>
+__device__ __forceinline__ void block_partials(double* part, int nv, Val val, int rec_index = -1) {
+    __shared__ double wred[NWAVE * NV_RED];
+    block_partials_in(wred, part, nv, val, rec_index);
 }
 
 // out[k] = sum over blocks of part[b*nv + k], k < nv (nv <= NT), into LDS `out` (all threads).

@@ -35,10 +35,10 @@ __global__ void __launch_bounds__(NT) k_d_residual(Stencil S, DeflArgs a) {
     const Own<1> o = own_pixels<1>(S.h, S.w, r0, c0);
     const double gv = o.in[0] ? a.g[o.g[0]] : 0.0;
     q_stage<double, R, CLS, 1>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return a.w[gi]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+    const TvX<1> X = tv_x<CLS, 1>(S.h, S.w, a.xhat, r0, c0);
     __syncthreads();
     double hv[1];
-    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv);
+    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv, X);
     const double rv = o.in[0] ? gv - hv[0] : 0.0;
     if (o.in[0]) a.r[o.g[0]] = rv;
     block_partials(a.rec_res, 1 + a.s, [&](int k) -> double {
@@ -181,12 +181,12 @@ __global__ void __launch_bounds__(NT) k_d_apply(Stencil S, DeflArgs a, int j, in
     }
     q_stage<double, R, CLS, 1>(lds + L::o_v, S.h, S.w, r0, c0,
                                [&](int gi) { return j == 0 ? a.r[gi] : a.r[gi] + beta * p_old[gi]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+    const TvX<1> X = tv_x<CLS, 1>(S.h, S.w, a.xhat, r0, c0);
     __syncthreads();
     const double yi = o.in[0] ? (j == 0 ? a.r[o.g[0]] : a.r[o.g[0]] + beta * p_old[o.g[0]]) : 0.0;
     const double ri = o.in[0] ? a.r[o.g[0]] : 0.0;
     double hv[1];
-    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv);
+    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv, X);
     double pi = 0.0, qi = 0.0;
     if (o.in[0]) {
         pi = yi - combo(a.U, n, o.g[0], mus, s);

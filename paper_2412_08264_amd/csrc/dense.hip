@@ -86,7 +86,11 @@ int gram_chunks(int n) {
 
 hipError_t launch_gram(int n, int t1, int t2, const double* A, const double* B, double* part, double* out,
                        hipStream_t stream) {
-    const int nch = gram_chunks(n);
+    return launch_gram_n(n, t1, t2, A, B, gram_chunks(n), part, out, stream);
+}
+
+hipError_t launch_gram_n(int n, int t1, int t2, const double* A, const double* B, int nch, double* part,
+                         double* out, hipStream_t stream) {
     const int chunk_rows = (n + nch - 1) / nch;
     dim3 grid(nch, (t1 + GRAM_T - 1) / GRAM_T, (t2 + GRAM_T - 1) / GRAM_T);
     hipLaunchKernelGGL(k_gram, grid, dim3(NT), 0, stream, n, t1, t2, A, B, chunk_rows, part);

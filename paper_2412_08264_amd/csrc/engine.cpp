@@ -248,7 +248,8 @@ size_t slot_bytes(const bl_problem* P, int s) {
     const size_t n = (size_t)P->h * P->w;
     const size_t nf = P->reg == BL_REG_FILTERS ? P->n_filters : 0;
     const size_t nt = ntiles_of(P->h, P->w, QTY), np = npix_of((long)n);
-    return 6 * al(n * 8) + al(n * s * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) + al(TAPS_BYTES) +
+    return 6 * al(n * 8) + al(n * s * 8) + al((size_t)s * s * 8) + 2 * al(nf * n * 8) + al(nf * n * 4) +
+           al(TAPS_BYTES) +
            al(nt * (1 + s) * 8) + 2 * al(nt * (4 + 2 * s) * 8) + al(np * (1 + s) * 8) +
            al((size_t)3 * FOLD_BLOCKS * NV_RED * 8);
 }
@@ -271,6 +272,8 @@ SlotBuffers carve_slot(char* base, const bl_problem* P, int s) {
     B.r2 = (double*)take(n * 8);
     B.q2 = (double*)take(n * 8);
     B.HC = (double*)take(n * s * 8);
+    B.M = (double*)take((size_t)s * s * 8);
+    B.mpart = B.p0;   // p0, p1, q, r2: consecutive, free until the set-up
     B.d1 = nf ? (double*)take(nf * n * 8) : nullptr;
     B.d2 = nf ? (double*)take(nf * n * 8) : nullptr;
     B.d2f = nf ? (float*)take(nf * n * 4) : nullptr;
@@ -441,6 +444,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.r2 = B.r2;
     v.q2 = B.q2;
     v.HC = (v.fused && s) ? B.HC : nullptr;
+    v.M = (v.fused && s) ? B.M : nullptr;
     v.U = s ? rs->U : nullptr;
     v.C = s ? rs->C : nullptr;
     v.Z = hg ? rs->Z : nullptr;
@@ -474,7 +478,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         Sx.d2f = v.d2f;
         HIPCHK(launch_filter_state(Sx, sp.xhat, B.d1, B.d2, B.d2f, c->stream));
     }
-    if (v.fused && s) {   // H C for the fused steps: s FP64 products at (xhat, theta)
+    if (v.fused && s) {   // H C and C^T H C for the fused steps: s FP64 products at (xhat, theta)
         Stencil Sx = base;
         Sx.h = P->h;
         Sx.w = P->w;
@@ -489,6 +493,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
         Sx.d2 = v.d2;
         Sx.d2f = v.d2f;
         HIPCHK(launch_hvp(Sx, false, sp.xhat, rs->C, B.HC, s, 4 * QTY, c->stream));
+        HIPCHK(launch_gram_n(n, s, s, rs->C, B.HC, mhc_chunks(n, s), B.mpart, B.M, c->stream));
     }
     StateInit init{o->tol, o->hg_tol, o->max_iter, o->check_every, o->stop, s, store ? v_cap : 0, store ? 1 : 0,
                    hg ? 1 : 0};
@@ -642,7 +647,7 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
     slots = run_list;
     id = chunk_id++;
     const int buf = (int)(id & 1);
-    const int nsteps = std::min(POLL, max_steps - steps_done);
+    const int nsteps = std::min(CHUNK, max_steps - steps_done);
     // scheduled replacements (mixed precision): before the test of every rr_every-th iteration
     std::vector<std::vector<int>> rr(nsteps);
     for (int k = 0; k < nsteps; ++k)

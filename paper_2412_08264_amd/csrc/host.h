@@ -48,6 +48,7 @@ struct bl_ctx {
 namespace blh {
 
 constexpr int POLL = 8;              // iterations launched between host polls of the stop flags
+constexpr int CHUNK = 16;            // batch engine: iterations per chunk (one graph, one header poll)
 constexpr int KT_SAMPLE = 8;         // timing mode 2: kernel events on every KT_SAMPLE-th step
 // Consumer kernels re-reduce the producer's per-block records in every block; above this many
 // record values a fold kernel (FOLD_BLOCKS blocks per solve) first reduces them to FOLD_BLOCKS
@@ -90,6 +91,7 @@ bool tile_cache_load_all(const char* path, int& entries, std::string& err);
 struct SlotBuffers {
     double *r, *p0, *p1, *q;
     double *r2, *q2, *HC;     // fused FP64 steps: second r and q buffers, H C (n x s)
+    double *M, *mpart;        // C^T H C (s x s) and the partial sums that form it
     double *d1, *d2;
     float* d2f;
     double* taps;
@@ -112,10 +114,10 @@ struct SolveSpec {
 };
 
 // Recycled CG over up to `cap` concurrent solves in up to MAX_GROUPS groups (operator class,
-// tile height, with or without a recycle space).  Each iteration is one apply launch per group
-// with running solves and one update launch over all
-// running solves; the host enqueues chunks of POLL iterations and reads the solves' stop flags
-// one chunk behind, so the device never waits for the host.  A solve's arithmetic and
+// tile height, with or without a recycle space).  Each iteration is one launch per group with
+// running solves (FP64: the fused step) and, for the mixed-precision groups, one update launch
+// over their solves; the host enqueues chunks of CHUNK iterations and reads the solves' stop
+// flags one chunk behind, so the device never waits for the host.  A solve's arithmetic and
 // decisions do not depend on the others.
 constexpr int MAX_GROUPS = 16;
 

