@@ -63,16 +63,28 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def apply_bytes_per_pixel(reg: str, prec: str, s: int, nf: int) -> int:
-    """Algorithmic HBM bytes per pixel of one fused apply step (H p with p.q and C^T q): read
-    r and p, write p and q (FP64), read the s columns of C, and the Hessian state: x_hat for TV,
-    the nf phi'' maps for filters (FP32 in mixed precision)."""
-    b = 8 * 4 + 8 * s
-    if reg == "tv":
-        b += 8
-    else:
-        b += (4 if prec == "mixed" else 8) * nf
+def step_bytes_per_pixel(reg: str, prec: str, s: int, nf: int, z_cols: float = 0.0) -> float:
+    """Algorithmic HBM bytes per pixel of the launch the library times in each Krylov step.
+    FP64 (one fused launch per iteration): read r, q, p, w and write r, p, q, w (FP64), read the s
+    columns of C and of H C, z_cols columns of Z on average (the error-estimate test reads all of
+    Z on the iterations it runs), and the Hessian state: x_hat for TV, the nf phi'' maps for
+    filters.  Mixed precision (the apply launch of the two-launch step): read r and p, write p and
+    q (FP64), read the s columns of C and the state (FP32 phi'' maps)."""
+    if prec == "mixed":
+        b = 8 * 4 + 8 * s
+        b += 8 if reg == "tv" else 4 * nf
+        return b
+    b = 8 * 8 + 16 * s + 8 * z_cols
+    b += 8 if reg == "tv" else 8 * nf
     return b
+
+
+def step_kernel(prec: str, radius: int, reg: str, rows: int, rec: bool = True) -> str:
+    """Name of the timed launch's kernel (the template arguments as rocprofv3 prints them)."""
+    cls = 0 if reg == "tv" else 1
+    if prec == "mixed":
+        return f"k_b_apply<float, {radius}, {cls}, {rows // 8}, {'true' if rec else 'false'}>"
+    return f"k_f_step<{radius}, {cls}, {rows // 8}, {'true' if rec else 'false'}>"
 
 
 def source_hash() -> str:
@@ -628,9 +640,9 @@ def bench_sequence(args, B, torch, synth):
     head = recs[0]
     iters_seq = sum(r["iters"] for r in head)
     prec = "mixed" if mixed else "fp64"
-    bpp = apply_bytes_per_pixel(wl.reg, prec, wl.s, wl.n_filters)
-    kname = (f"k_b_apply<{'float' if mixed else 'double'}, {wl.blur_radius}, {0 if wl.reg == 'tv' else 1}, "
-             f"{B.bl_tile_rows(Sh.P) // 8}, true>")
+    # the error-estimate test reads the s columns of Z on one iteration in check_every
+    bpp = step_bytes_per_pixel(wl.reg, prec, wl.s, wl.n_filters, z_cols=wl.s / args.check_every)
+    kname = step_kernel(prec, wl.blur_radius, wl.reg, B.bl_tile_rows(Sh.P))
     desc = (f"{args.workload}: {wl.h}x{wl.w} {'smoothed-TV' if wl.reg == 'tv' else '8 x 7x7 filter'} deblurring, "
             f"blur r={wl.blur_radius} sigma={wl.blur_sigma}, noise {wl.noise}, {outer} frozen outer steps, "
             f"RGen-L(R) s={wl.s}, error-estimate stop {chosen['rgen_hg']:g} x previous |grad| tested every "
@@ -821,7 +833,8 @@ def bench_batch(args, B, torch, synth):
     ctx.set_timing(0)
     ok = sum(1 for e in allerr if e <= 1e-6)
     value = ok / el
-    total_bytes = sum(apply_bytes_per_pixel("filters", prec, 20, nf) * wls[k].n * it for k, it in stats)
+    total_bytes = sum(step_bytes_per_pixel("filters", prec, 20, nf, z_cols=20 / args.check_every) * wls[k].n * it
+                      for k, it in stats)
     launches = max(kt[1] * KT_SAMPLE, 1.0)   # apply launches of the timed passes (sampled 1 in 8)
     one_pass("plain", chosen["plain"])
     torch.cuda.synchronize()
@@ -834,7 +847,7 @@ def bench_batch(args, B, torch, synth):
     torch.cuda.synchronize()
     elp = time.perf_counter() - tp
     okp = sum(1 for e in perr if e <= 1e-6)
-    kname = f"k_b_apply<{'float' if prec == 'mixed' else 'double'}, 5, 1, {best_rows // 8}, true>"
+    kname = step_kernel(prec, 5, "filters", best_rows)
     out = base_line(args, value, el, "f32+f64" if prec == "mixed" else "f64",
                     {"workload": f"batch{len(wls)}: {len(wls)} filter images (8 x 7x7, blur r=5 sigma=3, noise 0.02), "
                                  f"sides {sorted(set(w.h for w in wls))}, sum n = {sum(w.n for w in wls)}, shared theta, "
@@ -979,8 +992,8 @@ def bench_serve(args, B, torch, synth):
         stages = {"queue": stage("t_arrival", "t_start"), "refresh": stage("t_start", "t_ready"),
                   "wait_engine": stage("t_ready", "t_admit"), "solve": stage("t_admit", "t_solved"),
                   "hypergradient": stage("t_solved", "t_done")}
-        bpp = lambda smp: apply_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec, smp.s,
-                                                smp.P.n_filters)
+        bpp = lambda smp: step_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec, smp.s,
+                                               smp.P.n_filters, z_cols=smp.s / args.check_every)
         total_bytes = sum(bpp(r.sample) * r.sample.P.h * r.sample.P.w * r.stats.iters for r in srv.completed)
         launches = max(kt[1] * KT_SAMPLE, 1.0)
         key = prec if rate == args.rate else f"{prec}_at_{rate:g}_per_s"
@@ -993,7 +1006,8 @@ def bench_serve(args, B, torch, synth):
                        "max_rel_err": max(errs) if errs else None,
                        "mean_iters": float(np.mean([r.stats.iters for r in win])) if win else None,
                        "mean_stage_ms": {k: (round(v, 2) if v is not None else None) for k, v in stages.items()},
-                       "roofline": roofline("k_b_apply<*> (all classes)", total_bytes / launches, kt, "serve")}
+                       "roofline": roofline("k_b_apply<float, *> (all classes)" if prec == "mixed" else
+                                            "k_f_step<*> (all classes)", total_bytes / launches, kt, "serve")}
         log(f"[bench] serve {key}: {modes[key]['solves_per_s']:.1f} solves/s, p50 "
             f"{modes[key]['latency_ms']['p50']} ms, p99 {modes[key]['latency_ms']['p99']} ms, backlog {backlog}")
         srv.close()
@@ -1051,11 +1065,11 @@ def cpu_baseline_serve(wls, data_steps, seconds_budget=25.0):
 
 
 # =============================================================================== HBM microbenchmark
-def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=64):
+def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=63):
     """HBM rate of the iteration kernels where the working set is far above the 256 MB Infinity
     Cache: a 4096 x 4096 TV problem (16.8 M pixels, FP64) solved for a fixed number of iterations
     (stop test off) with s recycle columns that are zero (plain-CG arithmetic with every projection
-    read and written as in a recycled solve), then without a recycle space.  Apply and update
+    read and written as in a recycled solve), then without a recycle space.  The fused step's
     durations come from the library's sampled HIP events; rates use algorithmic bytes."""
     wl = synth.custom("tv4096", side, "tv", s, blur_radius=4, blur_sigma=2.5, rect_min=8, rect_max=20, seed=6001)
     inst = synth.instance(wl)
@@ -1079,7 +1093,9 @@ def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=64):
     for name, sc in (("recycled", s), ("plain", 0)):
         S.rs.s_cur = sc
         w = torch.zeros_like(xs)
-        S.solve(th, xh, g, w, tol=0.0, max_iter=16, store_basis=False, recycle=sc > 0, allow=(B.BL_E_NOT_CONVERGED,))
+        # iteration counts of whole chunks (the launch of iteration k tests iterate k - 1: k + 1
+        # launches), so that no launch of a stopped solve enters the kernel statistics
+        S.solve(th, xh, g, w, tol=0.0, max_iter=15, store_basis=False, recycle=sc > 0, allow=(B.BL_E_NOT_CONVERGED,))
         S.set_timing(2)
         S.kernel_times(reset=True)
         w.zero_()
@@ -1088,16 +1104,11 @@ def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=64):
         kt = S.kernel_times(reset=True)
         S.set_timing(0)
         a_us = kt[0] / max(kt[1], 1.0) * 1e3
-        u_us = kt[2] / max(kt[3], 1.0) * 1e3
-        a_bytes = 8 * (5 + sc) * n
-        u_bytes = 8 * (6 + sc) * n
-        out[name] = {"apply": {"kernel": f"k_b_apply<double, 4, 0, {B.bl_tile_rows(P) // 8}, {'true' if sc else 'false'}>",
-                               "avg_us": round(a_us, 2), "algorithmic_bytes": a_bytes,
-                               "GBps": round(a_bytes / (a_us * 1e3), 1),
-                               "frac": round(a_bytes / (a_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[1])},
-                     "update": {"kernel": f"k_b_update<{'true, false' if sc else 'false, false'}>", "avg_us": round(u_us, 2), "algorithmic_bytes": u_bytes,
-                                "GBps": round(u_bytes / (u_us * 1e3), 1),
-                                "frac": round(u_bytes / (u_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[3])}}
+        a_bytes = int(step_bytes_per_pixel("tv", "fp64", sc, 0) * n)
+        out[name] = {"step": {"kernel": step_kernel("fp64", 4, "tv", B.bl_tile_rows(P), sc > 0),
+                              "avg_us": round(a_us, 2), "algorithmic_bytes": a_bytes,
+                              "GBps": round(a_bytes / (a_us * 1e3), 1),
+                              "frac": round(a_bytes / (a_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[1])}}
     S.close()
     torch.cuda.empty_cache()
     return out

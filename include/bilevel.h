@@ -364,13 +364,15 @@ size_t bl_autotune_workspace_bytes(const bl_problem* P, int s);
  *   cache_path != NULL and the file holds an entry for P's operator class and size class: the
  *     stored height goes into the table and *best_rows; nothing is timed, no device work,
  *     theta_host, xhat, iters and ws may be NULL / 0; us_per_iter (may be NULL) gets zeros.
- *   otherwise: times `iters` (1..100000) iterations of a recycled-CG solve of P at
- *     (theta_host, xhat) with s recycle columns at each height (8, 16, 32 rows), stores the
- *     fastest in the table, returns it in *best_rows and the mean microseconds per iteration in
- *     us_per_iter[0..2]; with cache_path the entry is then added to (or replaced in) the file,
- *     which is rewritten whole through a temporary file next to it and a rename.  The recycle
- *     columns are zero (the arithmetic of plain CG with every projection still read) and the
- *     stop test is off, so each height runs exactly `iters` iterations.  Scratch: the caller's
+ *   otherwise: times recycled-CG solves of P at (theta_host, xhat) with s recycle columns at
+ *     each height (8, 16, 32 rows): one of 16 iterations and one of 16 + 16 max(1, iters / 16)
+ *     (iters in 1..100000), whose difference is the cost of the extra iterations without the
+ *     per-solve set-up; stores the fastest height in the table, returns it in *best_rows and
+ *     the microseconds per iteration in us_per_iter[0..2]; with cache_path the entry is then
+ *     added to (or replaced in) the file, which is rewritten whole through a temporary file
+ *     next to it and a rename.  The recycle columns are zero (the arithmetic of plain CG with
+ *     every projection still read) and the stop test is off, so each solve runs exactly its
+ *     iteration count.  Scratch: the caller's
  *     ws of bl_autotune_workspace_bytes(P, s) bytes (256-byte aligned); synchronous on the
  *     context's stream.
  * Cache file: text, one entry per line "reg radius n_filters filter_size prec log2n rows us8

@@ -709,24 +709,31 @@ bl_status autotune_time(bl_ctx* c, const bl_problem* P, const double* theta, con
         o.tol = 0.0;
         o.check_every = 1;
         o.rr_every = 50;
+        // per tile height: a warm-up solve of a iterations, then timed solves of a and b: the
+        // difference is the cost of b - a iterations, free of the per-solve set-up (the residual,
+        // H C and C^T H C of a recycled solve); a and b are whole chunks of the batch engine
+        const int a = CHUNK, b = CHUNK + CHUNK * std::max(1, iters / CHUNK);
         for (int k = 0; k < 3; ++k) {
             c->force_rows = heights[k];
-            for (int pass = 0; pass < 2; ++pass) {
-                o.max_iter = pass == 0 ? std::min(iters, 16) : iters;
+            float ms[2] = {0.f, 0.f};
+            int its[2] = {0, 0};
+            for (int pass = 0; pass < 3; ++pass) {
+                o.max_iter = pass == 2 ? b : a;
                 HIPCHK(hipMemsetAsync(mem + T.w, 0, n * 8, c->stream));
-                if (pass == 1) HIPCHK(hipEventRecord(e0, c->stream));
+                if (pass > 0) HIPCHK(hipEventRecord(e0, c->stream));
                 bl_stats st{};
                 const bl_status r = bl_hessian_solve(c, P, theta, xhat, (const double*)(mem + T.g),
                                                      (double*)(mem + T.w), s ? &rs : nullptr, &o, mem, T.solve, &st);
                 if (r == BL_E_HIP || r == BL_E_ARG || r == BL_E_SHAPE || r == BL_E_WORKSPACE) return r;
-                if (pass == 1) {
+                if (pass > 0) {
                     HIPCHK(hipEventRecord(e1, c->stream));
                     HIPCHK(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    us[k] = 1e3 * ms / std::max(st.iters, 1);
+                    HIPCHK(hipEventElapsedTime(&ms[pass - 1], e0, e1));
+                    its[pass - 1] = st.iters;
                 }
             }
+            us[k] = its[1] > its[0] ? 1e3 * (ms[1] - ms[0]) / (its[1] - its[0])
+                                    : 1e3 * ms[1] / std::max(its[1], 1);   // (a solve that stopped early)
         }
         return BL_OK;
     };

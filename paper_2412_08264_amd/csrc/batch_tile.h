@@ -326,13 +326,15 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     const int h = sl.h, w = sl.width, n = sl.n;
     const bool first = j == 0;
-    const double* __restrict__ r0b = (j & 1) ? sl.r : sl.r2;   // iterate j - 1 (j >= 1)
-    const double* __restrict__ q0b = (j & 1) ? sl.q : sl.q2;
-    const double* __restrict__ p0b = sl.p[(j + 1) & 1];
-    double* __restrict__ r1b = (j & 1) ? sl.r2 : sl.r;          // iterate j
-    double* __restrict__ q1b = (j & 1) ? sl.q2 : sl.q;
-    double* __restrict__ p1b = sl.p[j & 1];
-    const double* __restrict__ rin = first ? sl.r : r0b;
+    const gbl_t<const double> __restrict__ r0b = gbl((j & 1) ? sl.r : sl.r2);   // iterate j - 1 (j >= 1)
+    const gbl_t<const double> __restrict__ q0b = gbl((j & 1) ? sl.q : sl.q2);
+    const gbl_t<const double> __restrict__ p0b = gbl(sl.p[(j + 1) & 1]);
+    const gbl_t<double> __restrict__ r1b = gbl((j & 1) ? sl.r2 : sl.r);          // iterate j
+    const gbl_t<double> __restrict__ q1b = gbl((j & 1) ? sl.q2 : sl.q);
+    const gbl_t<double> __restrict__ p1b = gbl(sl.p[j & 1]);
+    const gbl_t<const double> __restrict__ rin = first ? gbl(sl.r) : r0b;
+    const gbl_t<const double> gC = gbl(sl.C), gHC = gbl(sl.HC), gM = gbl(sl.M), gZ = gbl(sl.Z);
+    const gbl_t<double> gW = gbl(sl.w), gV = gbl(sl.V), gLZ = gbl(sl.lz);
     int r0, c0;
     slot_tile<Q>(sl, m.y, r0, c0);
     const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
@@ -343,15 +345,15 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         ri[k] = o.in[k] ? rin[o.g[k]] : 0.0;
         qi[k] = (o.in[k] && !first) ? q0b[o.g[k]] : 0.0;
         pi[k] = (o.in[k] && !first) ? p0b[o.g[k]] : 0.0;
-        wi[k] = (o.in[k] && !first) ? sl.w[o.g[k]] : 0.0;
+        wi[k] = (o.in[k] && !first) ? gW[o.g[k]] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < PFA; ++c)
 #pragma unroll
         for (int k = 0; k < QR; ++k) {
             const bool ld = PF > 0 && o.in[k] && c < s;
-            cpre[c][k] = ld ? sl.C[(size_t)c * n + o.g[k]] : 0.0;
-            hpre[c][k] = (ld && !first) ? sl.HC[(size_t)c * n + o.g[k]] : 0.0;
+            cpre[c][k] = ld ? gC[(size_t)c * n + o.g[k]] : 0.0;
+            hpre[c][k] = (ld && !first) ? gHC[(size_t)c * n + o.g[k]] : 0.0;
         }
     if constexpr (EARLY) {
 #pragma unroll
@@ -424,22 +426,40 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         }
     }
     if (stop) return;
-    if constexpr (EARLY) X = tv_xload<Q>(h, w, sl.xhat, r0, c0);
-    // block 0, thread 4 + k: alpha (M e)_k, the part of record value 4 + k that no pixel carries
-    double corr = 0.0;
+    // block 0: corrs[k] = alpha (M e)_k, the part of record value 4 + k that no pixel carries.
+    // G lanes share row k of M (all of their loads in one round), summed by a group sum.
+    __shared__ double corrs[S_MAX];
     if constexpr (REC) {
-        const int k = (int)threadIdx.x - 4;
-        if (m.y == 0 && !first && k >= 0 && k < s) {
-            double acc = 0.0;
-            for (int l = 0; l < s; ++l) acc += sl.M[(size_t)l * s + k] * e[l];
-            corr = alpha * acc;
+        if (m.y == 0 && !first) {
+            const int G = s <= 32 ? 8 : 4;
+            const int k = (int)threadIdx.x / G, jl = (int)threadIdx.x & (G - 1);
+            double part = 0.0;
+            if (k < s) {
+#pragma unroll 1
+                for (int u0 = 0; u0 < 16; u0 += 8) {   // (one round for s <= 32)
+                    if (jl + u0 * G >= s) break;
+                    double mv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int l = jl + (u0 + u) * G;
+                        mv[u] = l < s ? gM[(size_t)l * s + k] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int l = jl + (u0 + u) * G;
+                        if (l < s) part += mv[u] * e[l];
+                    }
+                }
+            }
+            part = group_sum(part, G);
+            if (k < s && jl == 0) corrs[k] = alpha * part;
         }
     }
     if (m.y == 0 && j >= 1) {
         if (acc_mine) st->zacc[threadIdx.x] = zacc0 - alpha * e[threadIdx.x];
         if (threadIdx.x == 0 && keep && sl.lz) {
-            sl.lz[2 * (j - 1)] = alpha;
-            sl.lz[2 * (j - 1) + 1] = rho_prev;
+            gLZ[2 * (j - 1)] = alpha;
+            gLZ[2 * (j - 1) + 1] = rho_prev;
         }
     }
     Stencil S = base;
@@ -452,6 +472,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
             const int idx = threadIdx.x + u * NT;
             if (idx < G::N_V) v[idx] = yof(hr[u], hq[u], hp[u]);
         }
+        X = tv_xload<Q>(h, w, sl.xhat, r0, c0);
     } else {
         if (first)
             q_stage<double, R, CLS, Q>(lds + L::o_v, S.h, S.w, r0, c0, [&](int g) { return rin[g]; });
@@ -467,7 +488,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     double* wred = lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     auto put = [&](int k, double v) {
-        const double t = wave_sum(v);
+        const double t = wave_total(v);
         if (lane == 0) wred[wave * NV_RED + k] = t;
     };
     // columns of C and H C: C e and (H C) e of the previous step's e at the own pixels, and the
@@ -497,8 +518,8 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
 #pragma unroll
                 for (int k = 0; k < QR; ++k) {
                     const bool ld = o.in[k] && c0r + i < s;
-                    cv[i][k] = ld ? sl.C[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
-                    hcv[i][k] = (ld && !first) ? sl.HC[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
+                    cv[i][k] = ld ? gC[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
+                    hcv[i][k] = (ld && !first) ? gHC[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
                 }
 #pragma unroll
             for (int i = 0; i < CH; ++i)
@@ -516,8 +537,8 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         if (o.in[k]) {
             if (!first) {
                 r1b[o.g[k]] = rn[k];
-                sl.w[o.g[k]] = wi[k] + alpha * pi[k];
-                if (keep) sl.V[(size_t)(j - 1) * n + o.g[k]] = ri[k] / sqrt(rho_prev);
+                gW[o.g[k]] = wi[k] + alpha * pi[k];
+                if (keep) gV[(size_t)(j - 1) * n + o.g[k]] = ri[k] / sqrt(rho_prev);
             }
             p1b[o.g[k]] = pn[k];
             q1b[o.g[k]] = qn[k];
@@ -546,7 +567,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
             for (int i = 0; i < CH; ++i)
 #pragma unroll
                 for (int k = 0; k < QR; ++k)
-                    zv[i][k] = (o.in[k] && z0 + i < zw) ? sl.Z[(size_t)(z0 + i) * n + o.g[k]] : 0.0;
+                    zv[i][k] = (o.in[k] && z0 + i < zw) ? gZ[(size_t)(z0 + i) * n + o.g[k]] : 0.0;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 if (z0 + i >= zw) break;
@@ -563,8 +584,8 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         double sum = 0.0;
 #pragma unroll
         for (int wv = 0; wv < NWAVE; ++wv) sum += wred[wv * NV_RED + k];
-        if (k == (int)threadIdx.x) sum += corr;
-        rec_out[(size_t)m.y * nv + k] = sum;
+        if (REC && m.y == 0 && !first && k >= 4 && k < 4 + s) sum += corrs[k - 4];
+        gbl(rec_out)[(size_t)m.y * nv + k] = sum;
     }
 }
 

@@ -164,6 +164,38 @@ __device__ __forceinline__ double group_sum(double v, int G) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum(v, 64); }
 
+// DPP move whose lanes outside the rows of ROWS keep zero.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64_rows(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sums over aligned groups of 32 or 64 lanes without LDS permutes: the row sums of group_sum,
+// then DPP row broadcasts (row_bcast:15 adds row 0 into row 1 and row 2 into row 3; for 64,
+// row_bcast:31 then adds rows 0-1 into rows 2-3), so the last lane of each group holds its sum
+// (lanes 31 and 63; the other lanes hold partial sums).  A fixed pattern: deterministic.
+__device__ __forceinline__ double group_sum_last(double v, int G) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    v += dpp_f64_rows<0x142, 0xA>(v);                // row_bcast:15 into rows 1 and 3
+    if (G >= 64) v += dpp_f64_rows<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// The wave's sum as a uniform value (lane 63 of group_sum_last, read into scalar registers).
+__device__ __forceinline__ double wave_total(double v) {
+    v = group_sum_last(v, 64);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Sum `val` over the block; result valid in every thread.  `red` has NWAVE doubles.
 __device__ __forceinline__ double block_sum(double val, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -175,6 +207,16 @@ __device__ __forceinline__ double block_sum(double val, double* red) {
 #pragma unroll
     for (int k = 0; k < NWAVE; ++k) s += red[k];
     return s;
+}
+
+// Global-memory views of generic pointers: accesses through them compile to global (not flat)
+// memory instructions, which do not count against the LDS wait counter (a flat load in flight
+// would hold up every later LDS wait) and take a uniform base address in scalar registers.
+template <typename T>
+using gbl_t = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gbl_t<T> gbl(T* p) {
+    return (gbl_t<T>)p;
 }
 
 // Block partial record of nv values (nv <= NV_RED): value k of this thread is val(k).
@@ -194,7 +236,7 @@ __device__ __forceinline__ void block_partials_in(double* wred, double* part, in
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (k0 + u >= nv) break;   // uniform: no reduction of the padding values
-            const double sum = wave_sum(v[u]);
+            const double sum = wave_total(v[u]);
             if (lane == 0) wred[wave * NV_RED + k0 + u] = sum;
         }
     }
@@ -204,7 +246,7 @@ __device__ __forceinline__ void block_partials_in(double* wred, double* part, in
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NWAVE; ++w) s += wred[w * NV_RED + k];
-        part[rec * nv + k] = s;
+        gbl(part)[rec * nv + k] = s;
     }
 }
 template <typename Val>
@@ -228,19 +270,20 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
     int G = 1;
     while (G * 2 * nv <= NT) G *= 2;
     const int k = threadIdx.x / G, j = threadIdx.x & (G - 1);
+    const gbl_t<const double> gp = gbl(part);
     double acc = 0.0;
     if (k < nv) {
         double a[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int b = j + u * G;
-            a[u] = b < nblocks ? part[(size_t)b * nv + k] : 0.0;
+            a[u] = b < nblocks ? gp[(size_t)b * nv + k] : 0.0;
         }
         // beyond U * G records (unfolded large record arrays): further rounds of 8 loads
         for (int b = j + U * G; b < nblocks; b += 8 * G) {
             double c[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) c[u] = b + u * G < nblocks ? part[(size_t)(b + u * G) * nv + k] : 0.0;
+            for (int u = 0; u < 8; ++u) c[u] = b + u * G < nblocks ? gp[(size_t)(b + u * G) * nv + k] : 0.0;
 #pragma unroll
             for (int u = 0; u < 8; ++u) a[u] += c[u];
         }
@@ -250,11 +293,13 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
             for (int u = 0; u < w2; ++u) a[u] += a[u + w2];
         acc = a[0];
     }
-    acc = group_sum(acc, G < 64 ? G : 64);
+    // groups of 32 or more lanes: the sum in the group's last lane (no LDS permutes)
+    const int Gw = G < 64 ? G : 64;
+    acc = Gw >= 32 ? group_sum_last(acc, Gw) : group_sum(acc, Gw);
     if (G <= 64) {
-        if (j == 0 && k < nv) out[k] = acc;
+        if (j == (Gw >= 32 ? G - 1 : 0) && k < nv) out[k] = acc;
     } else {
-        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+        if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = acc;
         __syncthreads();
         if ((int)threadIdx.x < nv) {
             const int wpg = G / 64;

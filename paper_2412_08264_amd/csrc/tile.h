@@ -122,7 +122,8 @@ template <int Q>
 __device__ __forceinline__ TvX<Q> tv_xload(int h, int w, const double* __restrict__ xhat, int r0, int c0) {
     const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW;
     const int i0 = r0 + Q * ty, j = c0 + tx;
-    auto at = [&](int i, int jj) { return (i >= 0 && i < h && jj >= 0 && jj < w) ? xhat[i * w + jj] : 0.0; };
+    const gbl_t<const double> gx = gbl(xhat);
+    auto at = [&](int i, int jj) { return (i >= 0 && i < h && jj >= 0 && jj < w) ? gx[i * w + jj] : 0.0; };
     TvX<Q> X;
 #pragma unroll
     for (int m = 0; m < Q + 2; ++m) X.c[m] = at(i0 - 1 + m, j);
@@ -150,34 +151,6 @@ __device__ __forceinline__ void tv_block(double xc, double xr, double xd, bool i
     c11 = (in && !last_col) ? (b * b + gam2) * s3 : T(0);
     c12 = in ? -(a * b) * s3 : T(0);
     c22 = (in && !last_row) ? (a * a + gam2) * s3 : T(0);
-}
-
-// Flux blocks a thread needs for the divergence at its Q pixels (i0 + k, j): its own points,
-// the points to their left (x flux only) and the point above the first (y flux only).
-template <typename T, int Q>
-struct TvCoef {
-    T c11[Q], c12[Q], c22[Q];
-    T l11[Q], l12[Q];
-    T u12, u22;
-};
-template <typename T, int Q>
-__device__ __forceinline__ TvCoef<T, Q> tv_coef(const TvX<Q>& X, int h, int w, int r0, int c0, double gam2) {
-    const int tx = threadIdx.x & (QW - 1), ty = threadIdx.x / QW;
-    const int i0 = r0 + Q * ty, j = c0 + tx;
-    const T g2 = (T)gam2;
-    TvCoef<T, Q> C;
-    T unused;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        const int i = i0 + k;
-        tv_block<T>(X.c[k + 1], X.r[k + 1], X.c[k + 2], i < h && j < w, j == w - 1, i == h - 1, g2, C.c11[k],
-                    C.c12[k], C.c22[k]);
-        tv_block<T>(X.l[k], X.c[k + 1], X.l[k + 1], i < h && j >= 1 && j - 1 < w, j - 1 == w - 1, i == h - 1, g2,
-                    C.l11[k], C.l12[k], unused);
-    }
-    tv_block<T>(X.c[0], X.r[0], X.c[1], i0 >= 1 && i0 - 1 < h && j < w, j == w - 1, i0 - 1 == h - 1, g2, unused,
-                C.u12, C.u22);
-    return C;
 }
 
 // x_hat around the thread's pixels for a TV tile (nothing is loaded for the filter classes).
@@ -254,26 +227,29 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
     for (int a = 0; a <= 2 * R; ++a) g[a] = (T)S.g[a];
 
     // TV: the divergence D^T B D v at the own pixels, from the staged v (x_hat is not needed
-    // after this)
+    // after this).  Each flux block is formed where it is used.
     T div[QR];
     if constexpr (CLS == TC_TV) {
-        const TvCoef<T, Q> cf = tv_coef<T, Q>(X, h, w, r0, c0, S.gam2);
+        const int i0 = r0 + QR * ty, j = c0 + tx;
+        const T g2 = (T)S.gam2;
         const T* vc = v + (QR * ty + G::E) * G::RW + (tx + G::E);   // the thread's first pixel
-        T cn[QR + 2], rt[QR + 1], lf[QR + 1];
-#pragma unroll
-        for (int m = 0; m < QR + 2; ++m) cn[m] = vc[(m - 1) * G::RW];
-#pragma unroll
-        for (int m = 0; m < QR + 1; ++m) {
-            rt[m] = vc[(m - 1) * G::RW + 1];
-            lf[m] = vc[m * G::RW - 1];
-        }
-        T fy_up = cf.u12 * (rt[0] - cn[0]) + cf.u22 * (cn[1] - cn[0]);
+        T b11, b12, b22;
+        // y flux at (i0 - 1, j)
+        tv_block<T>(X.c[0], X.r[0], X.c[1], i0 >= 1 && i0 - 1 < h && j < w, j == w - 1, i0 - 1 == h - 1, g2, b11,
+                    b12, b22);
+        T fy_up = b12 * (vc[1 - G::RW] - vc[-G::RW]) + b22 * (vc[0] - vc[-G::RW]);
 #pragma unroll
         for (int k = 0; k < QR; ++k) {
-            const T da = rt[k + 1] - cn[k + 1], db = cn[k + 2] - cn[k + 1];
-            const T fx = cf.c11[k] * da + cf.c12[k] * db;
-            const T fy = cf.c12[k] * da + cf.c22[k] * db;
-            const T fx_left = cf.l11[k] * (cn[k + 1] - lf[k]) + cf.l12[k] * (lf[k + 1] - lf[k]);
+            const int i = i0 + k;
+            const T* p = vc + k * G::RW;
+            const T da = p[1] - p[0], db = p[G::RW] - p[0];
+            tv_block<T>(X.c[k + 1], X.r[k + 1], X.c[k + 2], i < h && j < w, j == w - 1, i == h - 1, g2, b11, b12,
+                        b22);
+            const T fx = b11 * da + b12 * db;
+            const T fy = b12 * da + b22 * db;
+            tv_block<T>(X.l[k], X.c[k + 1], X.l[k + 1], i < h && j >= 1 && j - 1 < w, j - 1 == w - 1, i == h - 1, g2,
+                        b11, b12, b22);
+            const T fx_left = b11 * (p[0] - p[-1]) + b12 * (p[G::RW - 1] - p[-1]);
             div[k] = -fx + fx_left - fy + fy_up;
             fy_up = fy;
         }
