@@ -647,7 +647,9 @@ bl_status Batch::enqueue_chunk(int max_steps, int& steps_done, long& id, std::ve
     slots = run_list;
     id = chunk_id++;
     const int buf = (int)(id & 1);
-    const int nsteps = std::min(CHUNK, max_steps - steps_done);
+    // a lone solve takes long chunks (fewer polls and graph launches); in a batch a stopped slot
+    // idles until the chunk ends and retires a chunk later, so its chunks are shorter
+    const int nsteps = std::min(run_list.size() > 1 ? CHUNK_MANY : CHUNK, max_steps - steps_done);
     // scheduled replacements (mixed precision): before the test of every rr_every-th iteration
     std::vector<std::vector<int>> rr(nsteps);
     for (int k = 0; k < nsteps; ++k)

@@ -48,7 +48,8 @@ struct bl_ctx {
 namespace blh {
 
 constexpr int POLL = 8;              // iterations launched between host polls of the stop flags
-constexpr int CHUNK = 16;            // batch engine: iterations per chunk (one graph, one header poll)
+constexpr int CHUNK = 16;            // batch engine: iterations per chunk of a lone solve (one graph, one poll)
+constexpr int CHUNK_MANY = 8;        // ... and of a batch, whose slots stop at different steps
 constexpr int KT_SAMPLE = 8;         // timing mode 2: kernel events on every KT_SAMPLE-th step
 // Consumer kernels re-reduce the producer's per-block records in every block; above this many
 // record values a fold kernel (FOLD_BLOCKS blocks per solve) first reduces them to FOLD_BLOCKS
@@ -116,7 +117,7 @@ struct SolveSpec {
 // Recycled CG over up to `cap` concurrent solves in up to MAX_GROUPS groups (operator class,
 // tile height, with or without a recycle space).  Each iteration is one launch per group with
 // running solves (FP64: the fused step) and, for the mixed-precision groups, one update launch
-// over their solves; the host enqueues chunks of CHUNK iterations and reads the solves' stop
+// over their solves; the host enqueues chunks of CHUNK (one solve) or CHUNK_MANY iterations and reads the solves' stop
 // flags one chunk behind, so the device never waits for the host.  A solve's arithmetic and
 // decisions do not depend on the others.
 constexpr int MAX_GROUPS = 16;
