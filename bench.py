@@ -935,15 +935,19 @@ def bench_serve(args, B, torch, synth):
     tiles = {}
     # the offered rate in both precisions, then (mixed) a rate below the measured capacity, where
     # latency is service time rather than queueing
-    runs = [("mixed", args.rate), ("fp64", args.rate)] + ([("mixed", args.rate2)] if args.rate2 > 0 else [])
-    for prec, rate in runs:
+    # last: plain warm-started FP64 CG on the same stream (no recycle space, no refresh; every
+    # solve on the residual test at --serve-tol), the baseline of the recycled forms
+    runs = ([("mixed", args.rate), ("fp64", args.rate)] + ([("mixed", args.rate2)] if args.rate2 > 0 else [])
+            + [("fp64_plain", args.rate)])
+    for mode, rate in runs:
+        prec = "fp64" if mode == "fp64_plain" else mode
         arrivals = synth.poisson_arrivals(rate, args.warm_s + args.duration, len(wls), seed=5001)
         Ps = [B.problem_from(wl, prec=prec) for wl in wls]
         tiles.update(autotune_tiles(ctx, B, [(P, data[k][0][0], data[k][1][0], wl.s)
                                              for k, (P, wl) in enumerate(zip(Ps, wls))]))
         arena = sum(B.Engine.slot_bytes(P, wl.s) for P, wl in zip(Ps, wls))
         srv = serve.Server(ctx, cap=64, arena_bytes=arena, hg_rel=args.hg_rel, tol=args.serve_tol, pool=pool,
-                           check_every=args.check_every)
+                           check_every=args.check_every, recycle=mode != "fp64_plain")
         for k, (wl, P) in enumerate(zip(wls, Ps)):
             path, xhats, xs = data[k]
             srv.add_sample(serve.Sample(k, P, path, xhats, xs, wl.s, args.v_cap, dev))
@@ -992,11 +996,13 @@ def bench_serve(args, B, torch, synth):
         stages = {"queue": stage("t_arrival", "t_start"), "refresh": stage("t_start", "t_ready"),
                   "wait_engine": stage("t_ready", "t_admit"), "solve": stage("t_admit", "t_solved"),
                   "hypergradient": stage("t_solved", "t_done")}
-        bpp = lambda smp: step_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec, smp.s,
-                                               smp.P.n_filters, z_cols=smp.s / args.check_every)
+        sc = 0 if mode == "fp64_plain" else None   # plain CG reads no recycle columns
+        bpp = lambda smp: step_bytes_per_pixel("tv" if smp.P.reg == B.BL_REG_TV else "filters", prec,
+                                               smp.s if sc is None else sc, smp.P.n_filters,
+                                               z_cols=smp.s / args.check_every if sc is None else 0.0)
         total_bytes = sum(bpp(r.sample) * r.sample.P.h * r.sample.P.w * r.stats.iters for r in srv.completed)
         launches = max(kt[1] * KT_SAMPLE, 1.0)
-        key = prec if rate == args.rate else f"{prec}_at_{rate:g}_per_s"
+        key = mode if rate == args.rate else f"{mode}_at_{rate:g}_per_s"
         modes[key] = {"rate_per_s": rate, "solves_per_s": ok / args.duration, "completed": len(win),
                        "passing": f"{ok}/{len(win)}",
                        "arrived": sum(1 for a in arrivals if args.warm_s <= a[0] < end),
@@ -1018,12 +1024,18 @@ def bench_serve(args, B, torch, synth):
                                  f"Poisson arrivals {args.rate:g}/s, {args.duration:g} s window after {args.warm_s:g} s, "
                                  f"continuous batching (engine cap 64), error-estimate stop {args.hg_rel:g} x previous "
                                  f"|grad| tested every {args.check_every} iterations, residual stop {args.serve_tol:g} "
-                                 f"without a recycle space, mixed precision; FP64 beside it",
+                                 f"without a recycle space, mixed precision; recycled FP64 and plain warm-started "
+                                 f"FP64 CG (residual stop {args.serve_tol:g}, no refresh) on the same stream beside it",
                      "samples": len(wls), "rate_per_s": args.rate, "window_s": args.duration, "tiles": tiles},
                     latency_ms=head["latency_ms"], passing=head["passing"], mixed=head, fp64=modes["fp64"],
                     roofline=head["roofline"], **{k: v for k, v in modes.items() if k not in ("mixed", "fp64")})
     out["steps"] = 1
     out["ms_per_step"] = args.duration * 1e3
+    plain = modes["fp64_plain"]
+    out["vs_plain_fp64_cg"] = {
+        "solves_per_s": [head["solves_per_s"], plain["solves_per_s"]],
+        "p99_ms": [head["latency_ms"]["p99"], plain["latency_ms"]["p99"]],
+        "ratio": head["solves_per_s"] / max(plain["solves_per_s"], 1e-30)}
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline_serve(wls, data_steps=T)

@@ -67,8 +67,11 @@ class Server:
 
     def __init__(self, ctx: B.Context, cap: int, arena_bytes: int, hg_rel: float = 1e-9, tol: float = 1e-10,
                  rr_every: int = 50, iters_per_turn: int = 16, clock=time.perf_counter, pool=None,
-                 check_every: int = 1):
+                 check_every: int = 1, recycle: bool = True):
+        """recycle=False serves plain warm-started CG: no refresh, every solve on the residual
+        test at `tol` (the baseline the recycled form is compared with)."""
         self.ctx = ctx
+        self.recycle = recycle
         self.engine = B.Engine(cap=cap, arena_bytes=arena_bytes, device=ctx.device, ctx=ctx.ctx)
         self.hg_rel = hg_rel
         self.tol = tol
@@ -113,7 +116,7 @@ class Server:
             smp.prev_hg = None
             smp.w.zero_()
         req.t_start = self.clock()
-        if step > 0:
+        if step > 0 and self.recycle:
             req.fut = self._run(lambda c, P, rec, th, xh, s: c.refresh_p(P, rec, th, xh, s=s),
                                 smp.P64, smp.rec, smp.thetas[step], smp.xhats[step], smp.s)
 
@@ -121,7 +124,7 @@ class Server:
         smp = req.sample
         use_hg = smp.rec.rs.s_cur > 0 and smp.prev_hg is not None
         opts = B.solve_opts(stop="hgerr" if use_hg else "resid", hg_tol=self.hg_rel * smp.prev_hg if use_hg else 0.0,
-                            tol=self.tol, store_basis=True, rr_every=self.rr_every,
+                            tol=self.tol, store_basis=self.recycle, rr_every=self.rr_every,
                             check_every=self.check_every if use_hg else 1)
         xh = smp.xhats[req.step]
         req.g = xh - smp.xstar
