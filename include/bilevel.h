@@ -187,7 +187,12 @@ bl_status bl_recycle_update(bl_ctx* ctx, const bl_problem* P, const double* thet
 /* Hessian solve H w = g (eq. hess_sys) by recycled CG (Galerkin counterpart of RMINRES,
  * Section 2.2.2) with the residual or hypergradient-error test (Section 4, eq.
  * hg-err-stop-lowrank).  rs == NULL or rs->s_cur == 0: plain CG.  w_inout: warm start in,
- * solution out.  With opts->store_basis the normalised residuals go to rs->V. */
+ * solution out.  With opts->store_basis the normalised residuals go to rs->V and the CG
+ * coefficients (alpha_j, r_j.r_j) of those iterations to rs->lz (rs->v_lz of them), which the
+ * inner refresh reads.  FP64 problems run one fused launch per iteration (Chronopoulos and
+ * Gear's single-reduction form: beta from the recurrence of the projected residual's norm,
+ * alpha and every test from the explicitly reduced r.r); mixed-precision problems run an apply
+ * and an update launch per iteration with FP64 residual replacement every opts->rr_every. */
 bl_status bl_hessian_solve(bl_ctx* ctx, const bl_problem* P, const double* theta_host, const double* xhat,
                            const double* g, double* w_inout, bl_recycle* rs, const bl_solve_opts* opts,
                            void* ws, size_t ws_bytes, bl_stats* out);
@@ -273,24 +278,27 @@ bl_status bl_set_graphs(bl_ctx* ctx, int enable);
 bl_status bl_graph_counts(const bl_ctx* ctx, long long* captured, long long* replayed);
 
 /* Time the phases of subsequent calls with HIP events (stats->ms), 0/1.  With 2, also record
- * HIP events around the apply and update launches of every eighth Krylov step (see
- * bl_kernel_times; with graph replay on, every step of every eighth chunk, which then runs
- * directly); sampling keeps the events' own cost out of the run they measure. */
+ * HIP events around the step launches (FP64: the fused step; mixed: the apply) and the update
+ * launch of every eighth Krylov step (see bl_kernel_times; with graph replay on, every step of
+ * every eighth chunk, which then runs directly); sampling keeps the events' own cost out of the
+ * run they measure. */
 bl_status bl_set_timing(bl_ctx* ctx, int enable);
 
 /* Per-kernel durations accumulated over solves since the last reset, iterations that ran
- * only, over the sampled steps: out4[0] = total ms of the apply launches (H p fused with p.q
- * and C^T q), out4[1] = their count, out4[2] / out4[3] = the same for the update kernel.
- * reset != 0 clears the totals after reading. */
+ * only, over the sampled steps: out4[0] = total ms of the step launches (the fused FP64 step,
+ * or the mixed-precision apply: H p fused with p.q and C^T q), out4[1] = their count,
+ * out4[2] / out4[3] = the same for the mixed-precision update launch (FP64 solves launch no
+ * update: their pair of events brackets nothing and measures the events' own cost).  reset != 0
+ * clears the totals after reading. */
 bl_status bl_kernel_times(bl_ctx* ctx, double* out4, int reset);
 
 /* ------------------------------------------------------------------------------------------
  * Batched and served Hessian solves.  An engine runs up to `cap` (<= 64) recycled-CG solves
- * side by side: each iteration is one launch of the fused apply kernel (H p with p.q and
- * C^T q) per group of solves with the same operator class (problems equal in every
- * bl_problem field but h, w), tile height (bl_tile_rows) and recycling (s_cur > 0 or not; at
- * most 16 groups at a time), and
- * one launch of the update kernel over all running solves, whatever their sizes, recycle
+ * side by side: each iteration is one launch per group of solves with the same operator class
+ * (problems equal in every bl_problem field but h, w), tile height (bl_tile_rows) and recycling
+ * (s_cur > 0 or not; at most 16 groups at a time): the fused step for FP64 groups, the apply
+ * kernel (H p with p.q and C^T q) for mixed-precision groups, followed by one launch of the
+ * update kernel over the running mixed-precision solves, whatever their sizes, recycle
  * dimensions and iteration indices.  Every solve reduces only its own records in a fixed
  * order, so its iterates, iteration count and status are bitwise those of the same solve
  * run alone (bl_hessian_solve, which is a one-solve engine) with the same tile height.  Solves are admitted and retired

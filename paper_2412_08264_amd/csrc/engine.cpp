@@ -551,9 +551,10 @@ bl_status Batch::finish(int idx) {
 }
 
 // The launches of one chunk of nsteps iterations on stream ls: scheduled replacements, record
-// folds, one apply launch per group and one update launch per iteration, then the header
-// gather (which advances the step counter) and its copy to pinned buffer buf.  With time_all
-// (timing mode 2) HIP events bracket the apply and update launches of every iteration; without
+// folds, one launch per group (the fused step of an FP64 group, the apply of a mixed one) and
+// one update launch over the mixed-precision slots per iteration, then the header gather
+// (which advances the step counter) and its copy to pinned buffer buf.  With time_all (timing
+// mode 2) HIP events bracket the group launches and the update of every iteration; without
 // graphs, those of every KT_SAMPLE-th step.  No host-side state changes here, so the same
 // sequence can be captured.
 bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector<int>>& rr, hipStream_t ls,
