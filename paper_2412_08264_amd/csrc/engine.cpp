@@ -430,7 +430,7 @@ bl_status Batch::admit(int idx, const SolveSpec& sp, const SlotBuffers& B, doubl
     v.nz = hg ? s : 0;
     v.fused = grp.fp32 ? 0 : 1;
     v.fold_res = (long)v.ntiles * (1 + s) > REC_LIMIT;
-    v.fold_app = v.fused ? (long)v.ntiles * (4 + s + v.nz) > REC_LIMIT : v.fold_res;
+    v.fold_app = v.fused ? fused_fold(v.ntiles, rows, s, v.nz) : v.fold_res;
     v.fold_upd = (long)v.npix * (1 + v.nz) > REC_LIMIT;
     v.lam = lam;
     v.gam2 = gam2;

@@ -55,6 +55,17 @@ constexpr int KT_SAMPLE = 8;         // timing mode 2: kernel events on every KT
 // record values a fold kernel (FOLD_BLOCKS blocks per solve) first reduces them to FOLD_BLOCKS
 // records, so the consumers' re-reads stay bounded whatever the image size.
 constexpr long REC_LIMIT = 8192;
+// The fused FP64 step reduces the previous launch's records in every block, G threads per
+// value (G the largest power of two with 2 G nv <= 256) with U loads in flight each (32 on
+// recycled 8-row tiles, else 8): records are folded first (one more launch) only when that
+// reduction would take more than two dependent rounds of loads.
+inline bool fused_fold(int ntiles, int rows, int s, int nz) {
+    const int nv = 4 + s + nz;
+    int G = 1;
+    while (G * 2 * nv <= 256) G *= 2;
+    const int U = (s > 0 && rows == 8) ? 32 : 8;
+    return ntiles > 2 * U * G;
+}
 constexpr size_t ALIGN = 256;
 constexpr int TAPS_MAX = bl::MAX_NF * bl::MAX_FS * bl::MAX_FS + bl::MAX_NF;
 // Device and pinned staging layout of a problem's taps: TAPS_MAX doubles, then TAPS_MAX floats.

@@ -331,8 +331,9 @@ def test_error_estimate_on_tested_iterations_only(B):
 
 def test_recycled_cg_folded_records(B):
     """A 384 x 384 solve with s = 20 has more record values per kernel than the consumers reduce
-    directly (576 tiles x 21 values), so every record kind goes through the multi-block fold:
-    iterates and the error estimate against the oracle after a fixed number of iterations."""
+    directly (576 tiles x 21 values for the set-up; the fused step's 576 x 44 take more than two
+    rounds of loads), so every record kind goes through the multi-block fold: iterates and the
+    error estimate against the oracle after a fixed number of iterations."""
     wl, inst, prob, xh = tv_case(384, 384, seed=58)
     th = inst["theta0"]
     g = xh - inst["xstar"].ravel()
