@@ -484,12 +484,34 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     __syncthreads();
     double hv[QR];
     q_hvp<double, R, CLS, Q>(lds, S, r0, c0, hv, X);
-    // per-wave record sums in the tile's LDS (free once the product is in registers)
+    // The record.  Taller tiles (Q >= 2): per-wave sums by DPP (wave_total) into the tile's LDS.
+    // 8-row tiles (one pixel per thread, one wave per SIMD at 256 x 256, where every dependent
+    // instruction shows): the values go through LDS eight at a time, transposed, so each is
+    // summed by 32 lanes over 8 entries and one 32-lane DPP sum instead of a full wave sum per
+    // value; two alternating buffers of 8 x 256 values, one barrier per round.
+    constexpr bool LDS_RED = Q == 1;
+    __shared__ double recv[NV_RED];
     double* wred = lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     auto put = [&](int k, double v) {
         const double t = wave_total(v);
         if (lane == 0) wred[wave * NV_RED + k] = t;
+    };
+    int rbuf = 0;
+    auto sum8 = [&](const double (&v)[8], int nval, int base) {
+        double* buf = lds + rbuf * 8 * NT;
+        rbuf ^= 1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) buf[k * NT + threadIdx.x] = v[k];
+        __syncthreads();
+        const int k = threadIdx.x >> 5, jl = threadIdx.x & 31;
+        double acc = 0.0;
+        if (k < nval) {
+            const double* b = buf + k * NT + jl;
+            acc = ((b[0] + b[32]) + (b[64] + b[96])) + ((b[128] + b[160]) + (b[192] + b[224]));
+        }
+        acc = group_sum_last(acc, 32);
+        if (jl == 31 && k < nval) recv[base + k] = acc;
     };
     // columns of C and H C: C e and (H C) e of the previous step's e at the own pixels, and the
     // record values C^T (H y)
@@ -506,11 +528,23 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
                 hce[k] += hcv[k] * ec;
                 d += cv[k] * hv[k];
             }
-            put(4 + c, d);
+            return d;
         };
+        if constexpr (LDS_RED) {
+            static_assert(PF % 8 == 0 && CH == 8, "rounds of 8 columns");
 #pragma unroll
-        for (int c = 0; c < PF; ++c)
-            if (c < s) column(c, cpre[c], hpre[c]);
+            for (int r = 0; r < PF / 8; ++r) {
+                if (8 * r >= s) break;
+                double v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = 8 * r + i < s ? column(8 * r + i, cpre[8 * r + i], hpre[8 * r + i]) : 0.0;
+                sum8(v, s - 8 * r < 8 ? s - 8 * r : 8, 4 + 8 * r);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < PF; ++c)
+                if (c < s) put(4 + c, column(c, cpre[c], hpre[c]));
+        }
         for (int c0r = PF; c0r < s; c0r += CH) {
             double cv[CH][QR], hcv[CH][QR];
 #pragma unroll
@@ -521,9 +555,16 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
                     cv[i][k] = ld ? gC[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
                     hcv[i][k] = (ld && !first) ? gHC[(size_t)(c0r + i) * n + o.g[k]] : 0.0;
                 }
+            if constexpr (LDS_RED) {
+                double v[8];
 #pragma unroll
-            for (int i = 0; i < CH; ++i)
-                if (c0r + i < s) column(c0r + i, cv[i], hcv[i]);
+                for (int i = 0; i < 8; ++i) v[i] = c0r + i < s ? column(c0r + i, cv[i], hcv[i]) : 0.0;
+                sum8(v, s - c0r < 8 ? s - c0r : 8, 4 + c0r);
+            } else {
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    if (c0r + i < s) put(4 + c0r + i, column(c0r + i, cv[i], hcv[i]));
+            }
         }
     }
     // own pixels: the new vectors
@@ -553,10 +594,15 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
             a2 += rn[k] * qn[k];
             a3 += qn[k] * qn[k];
         }
-        put(0, a0);
-        put(1, a1);
-        put(2, a2);
-        put(3, a3);
+        if constexpr (LDS_RED) {
+            const double v[8] = {a0, a1, a2, a3, 0.0, 0.0, 0.0, 0.0};
+            sum8(v, 4, 0);
+        } else {
+            put(0, a0);
+            put(1, a1);
+            put(2, a2);
+            put(3, a3);
+        }
     }
     // Z^T r_j when iterate j is tested (launch j + 1 tests it)
     const int zw = j >= 1 ? zr_width(st, nz, j) : 0;
@@ -568,22 +614,39 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
 #pragma unroll
                 for (int k = 0; k < QR; ++k)
                     zv[i][k] = (o.in[k] && z0 + i < zw) ? gZ[(size_t)(z0 + i) * n + o.g[k]] : 0.0;
+            if constexpr (LDS_RED) {
+                double v[8];
 #pragma unroll
-            for (int i = 0; i < CH; ++i) {
-                if (z0 + i >= zw) break;
-                double d = 0.0;
+                for (int i = 0; i < 8; ++i) {
+                    double d = 0.0;
 #pragma unroll
-                for (int k = 0; k < QR; ++k) d += zv[i][k] * rn[k];
-                put(4 + s + z0 + i, d);
+                    for (int k = 0; k < QR; ++k) d += zv[i][k] * rn[k];
+                    v[i] = z0 + i < zw ? d : 0.0;
+                }
+                sum8(v, zw - z0 < 8 ? zw - z0 : 8, 4 + s + z0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    if (z0 + i >= zw) break;
+                    double d = 0.0;
+#pragma unroll
+                    for (int k = 0; k < QR; ++k) d += zv[i][k] * rn[k];
+                    put(4 + s + z0 + i, d);
+                }
             }
         }
     }
     __syncthreads();
     const int nv = 4 + s + zw;
     for (int k = threadIdx.x; k < nv; k += NT) {
-        double sum = 0.0;
+        double sum;
+        if constexpr (LDS_RED) {
+            sum = recv[k];
+        } else {
+            sum = 0.0;
 #pragma unroll
-        for (int wv = 0; wv < NWAVE; ++wv) sum += wred[wv * NV_RED + k];
+            for (int wv = 0; wv < NWAVE; ++wv) sum += wred[wv * NV_RED + k];
+        }
         if (REC && m.y == 0 && !first && k >= 4 && k < 4 + s) sum += corrs[k - 4];
         gbl(rec_out)[(size_t)m.y * nv + k] = sum;
     }
@@ -666,7 +729,9 @@ hipError_t launch_f_step_q(const Stencil& base, bool rec, const Slot* slots, con
                            hipStream_t stream) {
     q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
-        const size_t lds = QLayout<double, RR, CC, Q>::bytes;
+        // 8-row tiles reduce their record through two buffers of 8 x NT doubles in the tile's LDS
+        constexpr size_t tile = QLayout<double, RR, CC, Q>::bytes, red = Q == 1 ? 2 * 8 * NT * sizeof(double) : 0;
+        const size_t lds = tile > red ? tile : red;
         auto go = [&](auto kern) {
             allow_lds_b(kern, lds);
             hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, sr);
