@@ -584,7 +584,33 @@ __device__ void solve_cols(int t, const double* L, double* X, int ncols, size_t 
         }
         __syncthreads();
         const int c = threadIdx.x;
-        if (c < gn) {
+        if (gn <= 8) {
+            // few columns: one thread per column would run t^2 dependent steps alone, so wave 0
+            // sweeps instead: at step j every lane updates its rows of the remaining part with
+            // x_j / L_jj.  One wave needs no barrier between steps: its LDS accesses complete in
+            // program order (the wave barrier only keeps the compiler from moving them).
+            if (threadIdx.x < 64) {
+                const int lane = threadIdx.x;
+                for (int j = 0; j < t; ++j) {   // L y = x, column by column of L
+                    const double dj = LL[(size_t)j * t + j];
+                    for (int cc = 0; cc < gn; ++cc) {
+                        const double xj = xs[j * gn + cc] / dj;
+                        for (int i = j + 1 + lane; i < t; i += 64) xs[i * gn + cc] -= LL[(size_t)j * t + i] * xj;
+                        if (lane == 0) xs[j * gn + cc] = xj;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                for (int i = t - 1; i >= 0; --i) {   // L^T x = y, column by column of L^T
+                    const double di = LL[(size_t)i * t + i];
+                    for (int cc = 0; cc < gn; ++cc) {
+                        const double xi = xs[i * gn + cc] / di;
+                        for (int k = lane; k < i; k += 64) xs[k * gn + cc] -= LL[(size_t)k * t + i] * xi;
+                        if (lane == 0) xs[i * gn + cc] = xi;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+        } else if (c < gn) {
             for (int i = 0; i < t; ++i) {   // L y = x
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 int k = 0;
