@@ -51,13 +51,12 @@ template <bool REC, bool WIDE>
 __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots, BatchMap M, StepRef sr) {
     constexpr int UPRE = REC ? 24 : 1;
     __shared__ double tot[NT];
-    __shared__ int sdone;
     const int2 m = map_block(M, blockIdx.x);
     const Slot& sl = slots[m.x];
     if (m.y >= sl.npix) return;
     SolveState* st = sl.st;
-    const int j = step_of(sr) - sl.j0;
-    if (threadIdx.x == 0) sdone = st->done;
+    const int mark = stop_mark(st);
+    const int step = step_of(sr), j = step - sl.j0;
     const int s = REC ? sl.s : 0, n = sl.n;
     const int i = m.y * NT + threadIdx.x;
     const bool in = i < n;
@@ -66,6 +65,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     double cpre[UPRE], zpre[UPRE];
 #pragma unroll
     for (int k = 0; k < UPRE; ++k) cpre[k] = (in && k < s) ? sl.C[(size_t)k * n + i] : 0.0;
+    const gbl_t<const SolveState> sg = gbl((const SolveState*)st);
     const int zw = REC ? zr_width(st, sl.nz, j + 1) : 0;
 #pragma unroll
     for (int k = 0; k < UPRE; ++k) zpre[k] = (in && k < zw) ? sl.Z[(size_t)k * n + i] : 0.0;
@@ -73,18 +73,20 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     const double* rec = slot_rec(sl, 1, nb);
     // scalars of earlier launches, read before the reduction: rho_j (the apply of this
     // iteration) and, in block 0, the recycle coefficient accumulated so far
-    const double rho = uni(st->rho2[j & 1]);
-    const bool keep_lz = m.y == 0 && sl.lz && uni(st->store_basis) && j < uni(st->v_cap);
+    const double rho = uni(sg->rho2[j & 1]);
+    const bool keep_lz = m.y == 0 && sl.lz && uni(sg->store_basis) && j < uni(sg->v_cap);
     const bool acc_mine = m.y == 0 && (int)threadIdx.x < s;
-    const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
+    const double zacc0 = acc_mine ? sg->zacc[threadIdx.x] : 0.0;
+    // the apply launch of this step runs first: a stop it decided counts too
+    if (stopped_before(mark, step + 1)) return;
     reduce_partials<WIDE ? 32 : 8>(rec, nb, 1 + s, tot);
-    if (sdone) return;
     const double sigma = tot[0];
     if (!(sigma > 0.0)) {
         if (m.y == 0 && threadIdx.x == 0) {
             st->status = (sigma != sigma || fabs(sigma) == INFINITY) ? BL_E_NONFINITE : BL_E_INDEFINITE;
             st->iters = j;
             st->done = 1;
+            st->stop_at = step + 1;
         }
         return;
     }
@@ -137,6 +139,7 @@ __global__ void __launch_bounds__(NT) k_b_replace(const Slot* __restrict__ slots
         for (int k = threadIdx.x; k < s; k += NT) sl.st->zacc[k] = c[k];
         if (threadIdx.x == 0) {
             sl.st->done = 0;
+            sl.st->stop_at = 0;
             sl.st->status = BL_OK;
             sl.st->rr_j = step_of(sr) - sl.j0;
         }
@@ -178,6 +181,9 @@ __global__ void __launch_bounds__(NT) k_b_finish(const Slot* __restrict__ slots,
 __global__ void __launch_bounds__(NT) k_b_fold(const Slot* __restrict__ slots, BatchMap M, int which, StepRef sr) {
     __shared__ double tot[NT];
     const Slot& sl = slots[M.slot[blockIdx.x / FOLD_BLOCKS]];
+    // the records of a step (kinds 1 to 3) are read by no one once the slot has stopped (kind 1
+    // follows the apply launch of its own step)
+    if (which != 0 && stopped_before(stop_mark(sl.st), step_of(sr) + (which == 1 ? 1 : 0))) return;
     const int f = blockIdx.x % FOLD_BLOCKS;
     int nb, nv;
     const double* rec;

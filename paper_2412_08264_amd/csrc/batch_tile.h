@@ -115,9 +115,8 @@ __global__ void __launch_bounds__(NT) k_b_residual(Stencil base, const Slot* __r
 // previous recursive one the direction restarts (p = r): keeping it would let the stale
 // direction dominate (beta = rho_true / rho_rec >> 1) and stall at the accuracy of the FP32
 // operator; restarting turns the replacement into a step of iterative refinement.
-// A stopped slot's blocks leave after the record reduction (its flag is read by one thread
-// and published by the reduction's barrier: uniform per block; a flag set by block 0 during
-// this launch follows from the same decision every block of the slot takes).
+// A slot stopped by an earlier launch leaves before its record reduction (stopped_before);
+// one stopped by this launch's decision leaves after it, as every block takes that decision.
 // TV on short tiles (8 or 16 rows, the small images, where latency decides): the loads that
 // do not depend on the scalars of this iteration (the thread's r, p and columns of C, the halo
 // of r and p, x_hat) are issued before the record reduction, so their latency overlaps it; the
@@ -141,13 +140,12 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     __shared__ double tot[NT];
-    __shared__ int sdone;
     const int2 m = map_block(M, blockIdx.x);
     const Slot& sl = slots[m.x];
     if (m.y >= sl.ntiles) return;
     SolveState* st = sl.st;
-    const int j = step_of(sr) - sl.j0;
-    if (threadIdx.x == 0) sdone = st->done;
+    const int mark = stop_mark(st);
+    const int step = step_of(sr), j = step - sl.j0;
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     const int h = sl.h, w = sl.width, n = sl.n;
     const double* __restrict__ r = sl.r;
@@ -185,18 +183,20 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     }
     int nb;
     const double* rec = slot_rec(sl, 2, nb);
-    const int zw = REC ? zr_width(st, nz, j) : 0;
     // scalars written by earlier launches, read before the reduction so that nothing after it
     // waits on them
+    const gbl_t<const SolveState> sg = gbl((const SolveState*)st);
     const TestSettings ts = test_settings(st);
-    const double rho_prev = j > 0 ? uni(st->rho2[(j - 1) & 1]) : 1.0;
-    const bool store_basis = uni(st->store_basis) && j >= 0 && j < uni(st->v_cap);
-    const int rr_j = uni(st->rr_j);
+    const int zw = REC ? zr_width(ts.check_every, nz, j) : 0;
+    const double rho_prev = j > 0 ? uni(sg->rho2[(j - 1) & 1]) : 1.0;
+    const bool store_basis = uni(sg->store_basis) && j >= 0 && j < uni(sg->v_cap);
+    const int rr_j = uni(sg->rr_j);
+    const double mu_lane = REC ? mu_of_lane(st, ts.s) : 0.0;
+    if (stopped_before(mark, step)) return;
     reduce_partials(rec, nb, 1 + zw, tot);
-    if (sdone) return;
     const double rho = tot[0];
     const bool restart = j > 0 && rr_j == j && rho > rho_prev;
-    const Decision dec = decide(st, ts, j, rho, tot + 1, zw > 0);
+    const Decision dec = decide(ts, j, rho, tot + 1, zw > 0, mu_lane);
     if (m.y == 0) {
         for (int k = threadIdx.x; k < zw; k += NT) st->zr[k] = tot[1 + k];
         if (threadIdx.x == 0) {
@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
             if (dec.done) {
                 st->status = dec.status;
                 st->done = 1;
+                st->stop_at = step + 1;
             }
         }
     }
@@ -316,13 +317,12 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
     __shared__ double tot[NT];
-    __shared__ int sdone;
     const int2 m = map_block(M, blockIdx.x);
     const Slot& sl = slots[m.x];
     if (m.y >= sl.ntiles) return;
     SolveState* st = sl.st;
-    const int j = step_of(sr) - sl.j0;
-    if (threadIdx.x == 0) sdone = st->done;
+    const int mark = stop_mark(st);
+    const int step = step_of(sr), j = step - sl.j0;
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     const int h = sl.h, w = sl.width, n = sl.n;
     const bool first = j == 0;
@@ -378,23 +378,25 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     const double* rec = slot_rec(sl, first ? 2 : 1, nb);
     if (!first && !sl.fold_app && ((j - 1) & 1)) rec = sl.rec_app2;
     double* rec_out = (j & 1) ? sl.rec_app2 : sl.rec_app;
-    const int zin = first ? zr_width(st, nz, 0) : (j >= 2 ? zr_width(st, nz, j - 1) : 0);
-    const int nin = first ? 1 + zin : 4 + s + zin;
+    const gbl_t<const SolveState> sg = gbl((const SolveState*)st);
     const TestSettings ts = test_settings(st);
-    const bool keep = j >= 1 && uni(st->store_basis) && j - 1 < uni(st->v_cap);
+    const int zin = first ? zr_width(ts.check_every, nz, 0) : (j >= 2 ? zr_width(ts.check_every, nz, j - 1) : 0);
+    const int nin = first ? 1 + zin : 4 + s + zin;
+    const bool keep = j >= 1 && uni(sg->store_basis) && j - 1 < uni(sg->v_cap);
     const bool acc_mine = m.y == 0 && j >= 1 && (int)threadIdx.x < s;
-    const double zacc0 = acc_mine ? st->zacc[threadIdx.x] : 0.0;
+    const double zacc0 = acc_mine ? sg->zacc[threadIdx.x] : 0.0;
+    const double mu_lane = REC ? mu_of_lane(st, ts.s) : 0.0;
     // recycled steps on 8-row tiles (small images, latency-bound): 32 loads in flight per thread
     // cover the records of a 256 x 256 image in one round
+    if (stopped_before(mark, step)) return;
     reduce_partials<(REC && Q == 1) ? 32 : 8>(rec, nb, nin, tot);
-    if (sdone) return;
     double alpha = 0.0, beta = 0.0, rho_prev = 0.0;
     const double* e = tot + 4;
     bool stop = false;
     if (first || j >= 2) {   // test of iterate 0 (launch 0) or of iterate j - 1
         const int it = first ? 0 : j - 1;
         const double rho_t = first ? tot[0] : tot[1];
-        const Decision dec = decide(st, ts, it, rho_t, first ? tot + 1 : tot + 4 + s, zin > 0);
+        const Decision dec = decide(ts, it, rho_t, first ? tot + 1 : tot + 4 + s, zin > 0, mu_lane);
         if (m.y == 0 && threadIdx.x == 0) {
             st->rho2[it & 1] = rho_t;
             if (zin) st->est = dec.est;
@@ -403,6 +405,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
             if (dec.done) {
                 st->status = dec.status;
                 st->done = 1;
+                st->stop_at = step + 1;
             }
         }
         stop = dec.done;
@@ -415,6 +418,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
                 st->status = (sigma != sigma || fabs(sigma) == INFINITY) ? BL_E_NONFINITE : BL_E_INDEFINITE;
                 st->iters = j - 1;
                 st->done = 1;
+                st->stop_at = step + 1;
             }
             stop = true;
         } else {
@@ -605,7 +609,7 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         }
     }
     // Z^T r_j when iterate j is tested (launch j + 1 tests it)
-    const int zw = j >= 1 ? zr_width(st, nz, j) : 0;
+    const int zw = j >= 1 ? zr_width(ts.check_every, nz, j) : 0;
     if constexpr (REC) {
         for (int z0 = 0; z0 < zw; z0 += CH) {
             double zv[CH][QR];

@@ -49,6 +49,7 @@ struct SolveState {
     double alpha, gnorm, tol, hg_tol, res0, est, pad0[3];
     int iters, done, status, max_iter, check_every, stop, s, v_cap, v_cur, store_basis, hgerr_on;
     int rr_j;             // iteration whose test follows the last residual replacement (-1: none)
+    int stop_at;          // 1 + the step index of the launch that stopped the solve (0: running)
     double e[S_MAX];      // C^T q of the current iteration
     double zr[S_MAX];     // Z^T r
     double zacc[S_MAX];   // coefficient of U accumulated over the iterations
@@ -314,8 +315,14 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nblocks,
 // Width of the residual record that the test of iteration j reads: r.r, and Z^T r (nz values)
 // only when that test evaluates the error estimate (every check_every-th iteration), so the
 // columns of Z are read on tested iterations only.
+// Loads of the solve state go through global-address-space pointers: before a kernel's first
+// store they are uniform and unclobbered, so they become scalar loads that no vector load waits
+// behind (a flat load waits for every vector load issued before it).
+__device__ __forceinline__ int zr_width(int check_every, int nz, int j) {
+    return (nz > 0 && j % check_every == 0) ? nz : 0;
+}
 __device__ __forceinline__ int zr_width(const SolveState* st, int nz, int j) {
-    return (nz > 0 && j % st->check_every == 0) ? nz : 0;
+    return zr_width(gbl(st)->check_every, nz, j);
 }
 
 // Stop decision after j completed iterations from the reduced residual record (r.r and,
@@ -338,6 +345,18 @@ __device__ __forceinline__ double uni(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A solve stopped by an earlier launch: its blocks have nothing to do and leave before their
+// record reduction.  stop_at is written once, by block 0 of the stopping launch (step S writes
+// S + 1), so the blocks of that launch read 0 or S + 1 and carry on to the decision they share,
+// and every later launch reads the same value in every wave: the test is uniform per block
+// without a barrier.  The mark is loaded first and tested later (stop_mark, then
+// stopped_before), so that no wave waits for it before issuing its other loads.
+__device__ __forceinline__ int stop_mark(const SolveState* st) { return *gbl(&st->stop_at); }
+__device__ __forceinline__ bool stopped_before(int mark, int step) {
+    const int a = uni(mark);
+    return a != 0 && a <= step;
+}
+
 // The settings the test reads, loaded once: a kernel can issue these loads before its record
 // reduction, so the decision does not wait on them afterwards.
 struct TestSettings {
@@ -345,17 +364,32 @@ struct TestSettings {
     int check_every, stop, hgerr_on, s, max_iter;
 };
 __device__ __forceinline__ TestSettings test_settings(const SolveState* st) {
-    return TestSettings{uni(st->tol),         uni(st->hg_tol), uni(st->gnorm), uni(st->check_every),
-                        uni(st->stop),        uni(st->hgerr_on), uni(st->s),   uni(st->max_iter)};
+    const gbl_t<const SolveState> g = gbl(st);
+    return TestSettings{uni(g->tol),  uni(g->hg_tol),   uni(g->gnorm), uni(g->check_every),
+                        uni(g->stop), uni(g->hgerr_on), uni(g->s),     uni(g->max_iter)};
 }
 
-__device__ __forceinline__ Decision decide(const SolveState* st, const TestSettings& ts, int j, double rho,
-                                           const double* zr, bool have_zr) {
+// Lane k of the wave holds mu[k] (k < s <= 64, s the solve state's count): one load per lane, issued with the kernel's
+// other early loads, instead of s dependent loads inside the test.
+__device__ __forceinline__ double mu_of_lane(const SolveState* st, int s) {
+    const int k = (int)(threadIdx.x & 63);
+    return k < s ? gbl(st->mu)[k] : 0.0;
+}
+
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ Decision decide(const TestSettings& ts, int j, double rho, const double* zr, bool have_zr,
+                                           double mu_lane) {
     Decision d{false, BL_OK, NAN};
     if (ts.hgerr_on && have_zr) {
         double acc = 0.0;
         for (int k = 0; k < ts.s; ++k) {
-            const double t = st->mu[k] * zr[k];
+            const double t = lane_value(mu_lane, k) * zr[k];
             acc += t * t;
         }
         d.est = sqrt(acc);

@@ -158,10 +158,11 @@ __global__ void __launch_bounds__(NT) k_d_apply(Stencil S, DeflArgs a, int j, in
     double* __restrict__ p_new = a.p[j & 1];
     const TestSettings ts = test_settings(st);
     const double rho_prev = j > 0 ? uni(st->rho2[(j - 1) & 1]) : 1.0;
+    const double mu_lane = mu_of_lane(st, ts.s);
     reduce_partials(fold ? a.fold : a.rec_upd, fold ? FOLD_BLOCKS : a.npix, 1 + s + zw, tot);
     if (sdone) return;
     const double rho = tot[0];
-    const Decision dec = decide(st, ts, j, rho, tot + 1 + s, zw > 0);
+    const Decision dec = decide(ts, j, rho, tot + 1 + s, zw > 0, mu_lane);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->rho2[j & 1] = rho;
         if (zw) st->est = dec.est;
