@@ -60,15 +60,17 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
     const int s = REC ? sl.s : 0, n = sl.n;
     const int i = m.y * NT + threadIdx.x;
     const bool in = i < n;
-    const double* p = sl.p[(j + 1) & 1];
-    const double wi = in ? sl.w[i] : 0.0, pi = in ? p[i] : 0.0, ri0 = in ? sl.r[i] : 0.0, qi = in ? sl.q[i] : 0.0;
+    const gbl_t<const double> p = gbl((const double*)sl.p[(j + 1) & 1]), gq = gbl((const double*)sl.q);
+    const gbl_t<const double> gC = gbl(sl.C), gZ = gbl(sl.Z);
+    const gbl_t<double> gw = gbl(sl.w), gr = gbl(sl.r);
+    const double wi = in ? gw[i] : 0.0, pi = in ? p[i] : 0.0, ri0 = in ? gr[i] : 0.0, qi = in ? gq[i] : 0.0;
     double cpre[UPRE], zpre[UPRE];
 #pragma unroll
-    for (int k = 0; k < UPRE; ++k) cpre[k] = (in && k < s) ? sl.C[(size_t)k * n + i] : 0.0;
+    for (int k = 0; k < UPRE; ++k) cpre[k] = (in && k < s) ? gC[(size_t)k * n + i] : 0.0;
     const gbl_t<const SolveState> sg = gbl((const SolveState*)st);
     const int zw = REC ? zr_width(st, sl.nz, j + 1) : 0;
 #pragma unroll
-    for (int k = 0; k < UPRE; ++k) zpre[k] = (in && k < zw) ? sl.Z[(size_t)k * n + i] : 0.0;
+    for (int k = 0; k < UPRE; ++k) zpre[k] = (in && k < zw) ? gZ[(size_t)k * n + i] : 0.0;
     int nb;
     const double* rec = slot_rec(sl, 1, nb);
     // scalars of earlier launches, read before the reduction: rho_j (the apply of this
@@ -99,11 +101,11 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
 #pragma unroll
     for (int k = 0; k < UPRE; ++k)
         if (k < s) ce += cpre[k] * e[k];
-    for (int k = UPRE; k < s; ++k) ce += (in ? sl.C[(size_t)k * n + i] : 0.0) * e[k];
+    for (int k = UPRE; k < s; ++k) ce += (in ? gC[(size_t)k * n + i] : 0.0) * e[k];
     const double ri = ri0 - alpha * (qi - ce);
     if (in) {
-        sl.w[i] = wi + alpha * pi;
-        sl.r[i] = ri;
+        gw[i] = wi + alpha * pi;
+        gr[i] = ri;
     }
     block_partials(
         sl.rec_upd, 1 + zw,
@@ -115,7 +117,7 @@ __global__ void __launch_bounds__(NT) k_b_update(const Slot* __restrict__ slots,
 #pragma unroll
             for (int u = 0; u < UPRE; ++u)
                 if (u == c) zv = zpre[u];
-            if (c >= UPRE) zv = sl.Z[(size_t)c * n + i];
+            if (c >= UPRE) zv = gZ[(size_t)c * n + i];
             return zv * ri;
         },
         m.y);

@@ -148,9 +148,10 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
     const int step = step_of(sr), j = step - sl.j0;
     const int s = REC ? sl.s : 0, nz = REC ? sl.nz : 0;
     const int h = sl.h, w = sl.width, n = sl.n;
-    const double* __restrict__ r = sl.r;
-    const double* __restrict__ p_old = sl.p[j & 1];
-    double* __restrict__ p_new = sl.p[(j + 1) & 1];
+    const gbl_t<const double> __restrict__ r = gbl((const double*)sl.r);
+    const gbl_t<const double> __restrict__ p_old = gbl((const double*)sl.p[j & 1]);
+    const gbl_t<double> __restrict__ p_new = gbl(sl.p[(j + 1) & 1]);
+    const gbl_t<const double> gC = gbl(sl.C);
     int r0, c0;
     slot_tile<Q>(sl, m.y, r0, c0);
     const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
 #pragma unroll
     for (int c = 0; c < CP; ++c)
 #pragma unroll
-        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? sl.C[(size_t)c * n + o.g[k]] : 0.0;
+        for (int k = 0; k < QR; ++k) cpre[c][k] = (o.in[k] && c < s) ? gC[(size_t)c * n + o.g[k]] : 0.0;
     if constexpr (EARLY) {
 #pragma unroll
         for (int u = 0; u < NST; ++u) {
@@ -246,8 +247,8 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
         pv[k] = o.in[k] ? pn : 0.0;
         if (o.in[k]) {
             p_new[o.g[k]] = pn;
-            sl.q[o.g[k]] = qq[k];
-            if (store_basis) sl.V[(size_t)j * S.n + o.g[k]] = ri[k] * inv;
+            gbl(sl.q)[o.g[k]] = qq[k];
+            if (store_basis) gbl(sl.V)[(size_t)j * S.n + o.g[k]] = ri[k] * inv;
         }
     }
     block_partials_in(reinterpret_cast<double*>(smem_raw),
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(NT) k_b_apply(Stencil base, const Slot* __rest
             } else {
 #pragma unroll
                 for (int u = 0; u < QR; ++u)
-                    if (o.in[u]) acc += sl.C[(size_t)c * S.n + o.g[u]] * qq[u];
+                    if (o.in[u]) acc += gC[(size_t)c * S.n + o.g[u]] * qq[u];
             }
             return acc;
         },

@@ -162,19 +162,21 @@ __device__ __forceinline__ TvX<Q> tv_x(int h, int w, const double* __restrict__ 
 }
 
 // Filter taps and weights of filter j in precision T: k_j (fs*fs) then lambda_j at nf*fs*fs + j.
+// Read through global pointers: uniform tap loads become scalar loads, and the phi'' loads
+// global ones, so that neither waits behind LDS traffic (as flat loads would).
 template <typename T>
-__device__ __forceinline__ const T* taps_of(const Stencil& S);
+__device__ __forceinline__ gbl_t<const T> taps_of(const Stencil& S);
 template <>
-__device__ __forceinline__ const double* taps_of<double>(const Stencil& S) { return S.taps; }
+__device__ __forceinline__ gbl_t<const double> taps_of<double>(const Stencil& S) { return gbl(S.taps); }
 template <>
-__device__ __forceinline__ const float* taps_of<float>(const Stencil& S) { return S.tapsf; }
+__device__ __forceinline__ gbl_t<const float> taps_of<float>(const Stencil& S) { return gbl(S.tapsf); }
 
 template <typename T>
 __device__ __forceinline__ T d2_at(const Stencil& S, size_t gidx);
 template <>
-__device__ __forceinline__ double d2_at<double>(const Stencil& S, size_t gidx) { return S.d2[gidx]; }
+__device__ __forceinline__ double d2_at<double>(const Stencil& S, size_t gidx) { return gbl(S.d2)[gidx]; }
 template <>
-__device__ __forceinline__ float d2_at<float>(const Stencil& S, size_t gidx) { return S.d2f[gidx]; }
+__device__ __forceinline__ float d2_at<float>(const Stencil& S, size_t gidx) { return gbl(S.d2f)[gidx]; }
 
 // Horizontal pass of the separable blur: dst[r][c] = sum_b g[b] src[r][c + b] for r < NR,
 // c < NC (src rows hold NC + 2R values).  A thread computes SEG consecutive outputs of one row
@@ -306,7 +308,7 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
 #pragma unroll
         for (int k = 0; k < QR; ++k) out[k] += eps * v[(QR * ty + k + G::E) * G::RW + tx + G::E];
         const int nf = S.nf;
-        const T* __restrict__ tp = taps_of<T>(S);
+        const gbl_t<const T> __restrict__ tp = taps_of<T>(S);
         constexpr int NFG = L::NFG;
         T* __restrict__ tb = lds + L::o_tb;
         if constexpr (CLS == TC_F7) {
@@ -352,7 +354,7 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
 #pragma unroll
                     for (int jj = 0; jj < NFG; ++jj) {
                         if (j0 + jj >= nf) break;
-                        const T* kj = tp + (j0 + jj) * F2;
+                        const gbl_t<const T> kj = tp + (j0 + jj) * F2;
                         T acc0 = T(0), acc1 = T(0);
 #pragma unroll
                         for (int a = 0; a < FS; ++a)
@@ -373,7 +375,7 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
 #pragma unroll 1
                 for (int jj = 0; jj < NFG; ++jj) {
                     if (j0 + jj >= nf) break;
-                    const T* kj = tp + (j0 + jj) * F2;
+                    const gbl_t<const T> kj = tp + (j0 + jj) * F2;
                     const T* tj = tb + jj * G::THF * G::TWF;
                     T win[QR + FS - 1][FS];
 #pragma unroll
@@ -404,7 +406,7 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
                     for (int jj = 0; jj < NFG && j0 + jj < nf; ++jj) {
                         T val = T(0);
                         if (in) {
-                            const T* kj = tp + (j0 + jj) * f2;
+                            const gbl_t<const T> kj = tp + (j0 + jj) * f2;
                             const T* src = v + (rr + G::E - G::F - F) * G::RW + (cc + G::E - G::F - F);
                             T acc = T(0);
                             for (int a = 0; a < fs; ++a)
@@ -416,7 +418,7 @@ __device__ __forceinline__ void q_hvp(T* lds, const Stencil& S, int r0, int c0, 
                 }
                 __syncthreads();
                 for (int jj = 0; jj < NFG && j0 + jj < nf; ++jj) {
-                    const T* kj = tp + (j0 + jj) * f2;
+                    const gbl_t<const T> kj = tp + (j0 + jj) * f2;
                     const T* tj = tb + jj * G::THF * G::TWF;
                     for (int k = 0; k < QR; ++k) {
                         const int rr = QR * ty + k + G::F, cc = tx + G::F;   // own pixel in tb coordinates
