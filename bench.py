@@ -1096,13 +1096,14 @@ def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=63):
     th = inst["theta0"]
     if args.rows:
         B.bl_tile_rows_set(P, args.rows)
-        tuned = None
-    else:
-        tuned = S.autotune_tiles(P, th, xh, s, 24)[1]
     out = {"workload": f"{side}x{side} smoothed-TV (r=4), FP64, {iters} iterations, s={s} zero recycle columns "
-                       f"(recycled) or none (plain), residual stop off; tile height {B.bl_tile_rows(P)} rows",
-           "n": n, "autotune_us_per_iter": [round(u, 1) for u in tuned] if tuned else None}
+                       f"(recycled) or none (plain), residual stop off; tile height "
+                       + (f"{args.rows} rows" if args.rows else "tuned per variant"),
+           "n": n}
     for name, sc in (("recycled", s), ("plain", 0)):
+        # each variant at the tile height its own autotune picks (the plain step has a fraction
+        # of the recycled one's registers, so the two need not agree)
+        tuned = None if args.rows else S.autotune_tiles(P, th, xh, sc, 24)[1]
         S.rs.s_cur = sc
         w = torch.zeros_like(xs)
         # iteration counts of whole chunks (the launch of iteration k tests iterate k - 1: k + 1
@@ -1120,7 +1121,9 @@ def hbm_micro(args, B, torch, synth, side=4096, s=20, iters=63):
         out[name] = {"step": {"kernel": step_kernel("fp64", 4, "tv", B.bl_tile_rows(P), sc > 0),
                               "avg_us": round(a_us, 2), "algorithmic_bytes": a_bytes,
                               "GBps": round(a_bytes / (a_us * 1e3), 1),
-                              "frac": round(a_bytes / (a_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[1])}}
+                              "frac": round(a_bytes / (a_us * 1e3) / HBM_PEAK, 3), "launches": int(kt[1])},
+                     "tile_rows": B.bl_tile_rows(P),
+                     "autotune_us_per_iter": [round(u, 1) for u in tuned] if tuned else None}
     S.close()
     torch.cuda.empty_cache()
     return out

@@ -181,16 +181,21 @@ constexpr int SD_NT = 512;
 // column order: the pivot of column j is its diagonal after the updates from the kept
 // columns before it (= squared norm of column j after projection); j is dropped when
 // pivot_j <= tol^2 Gm_jj.  Writes Xinv (t x tk, ld ldx) with W Xinv = orthonormal basis of
-// the kept columns (rows of dropped columns zero) and *tk_out = tk.  Scratch: A (t*t); X (t*t,
-// optional, in LDS) holds Xinv while its columns are solved, so that the solve's reads of
-// values it has just written stay on chip.  Gm's diagonal is staged in LDS once: the serial
-// pivot test of every column reads it.
-__device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, double* A, double* X, int* tk_out,
-                          double* Xinv, int ldx) {
+// the kept columns (rows of dropped columns zero) and *tk_out = tk.  A (t*t) is the working
+// matrix; with XL the inverse factor is solved into X (t*t, in LDS) and then copied to Xinv,
+// so that the solve's accesses stay on chip.  Gm's diagonal is staged in LDS once: the serial
+// pivot test of every column reads it.  Instantiated with A and X either in LDS or in global
+// memory, never a pointer that may be either (which would make every access a flat one).
+template <bool XL, typename AP>
+__device__ __forceinline__ void chol_drop(int t, const double* __restrict__ Gm, double tol, AP A, double* X,
+                                          int* tk_out, double* Xinv, int ldx) {
+    constexpr int NU = 4;   // rows per lane in the inverse (t <= 256)
+    constexpr int GC = 4;   // columns of the inverse one wave solves together
     __shared__ int s_tk, s_keep;
     __shared__ double s_d;
     __shared__ int kept[256];
-    __shared__ double gdiag[256];
+    __shared__ double gdiag[256], rdiag[256];
+    const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63), nwv = (int)(blockDim.x >> 6);
     if (threadIdx.x == 0) s_tk = 0;
     for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) A[idx] = Gm[idx];
     for (int j = threadIdx.x; j < t; j += blockDim.x) gdiag[j] = Gm[(size_t)j * t + j];
@@ -213,31 +218,76 @@ __device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, doub
         // row j of R: R[j][i] = A[j][i] / d for i > j (A symmetric: use column j)
         for (int i = j + 1 + threadIdx.x; i < t; i += blockDim.x) A[(size_t)i * t + j] /= d;
         __syncthreads();
+        // trailing update, one column per wave at a time (no index division)
         const int m = t - j - 1;
-        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-            const int kk = idx / m, ii = idx - kk * m;
-            const int k = j + 1 + kk, i = j + 1 + ii;
-            A[(size_t)k * t + i] -= A[(size_t)i * t + j] * A[(size_t)k * t + j];
+        for (int kk = wv; kk < m; kk += nwv) {
+            const int k = j + 1 + kk;
+            const double akj = A[(size_t)k * t + j];
+            for (int ii = ln; ii < m; ii += 64) {
+                const int i = j + 1 + ii;
+                A[(size_t)k * t + i] -= A[(size_t)i * t + j] * akj;
+            }
         }
         __syncthreads();
     }
     const int tk = s_tk;
-    double* xb = X ? X : Xinv;
-    const int ldb = X ? t : ldx;
+    double* xb = XL ? X : Xinv;
+    const int ldb = XL ? t : ldx;
     for (int idx = threadIdx.x; idx < t * tk; idx += blockDim.x) xb[(size_t)(idx / t) * ldb + idx % t] = 0.0;
+    for (int k = threadIdx.x; k < tk; k += blockDim.x) rdiag[k] = 1.0 / A[(size_t)kept[k] * t + kept[k]];
     __syncthreads();
-    // R (kept rows/cols) upper triangular: Rk[k][l] = A[kept_l * t + kept_k] (k < l), diag A[kept_k*t+kept_k]
-    for (int mcol = threadIdx.x; mcol < tk; mcol += blockDim.x) {
-        double* x = xb + (size_t)mcol * ldb;
-        for (int k = mcol; k >= 0; --k) {
-            const int ck = kept[k];
-            double v = (k == mcol) ? 1.0 : 0.0;
-            for (int l = k + 1; l <= mcol; ++l) v -= A[(size_t)kept[l] * t + ck] * x[kept[l]];
-            x[ck] = v / A[(size_t)ck * t + ck];
+    // R^{-1} (kept rows and columns; R[k][l] = A[kept_l * t + kept_k] for k < l): a wave solves GC
+    // columns together, sweeping l downwards; lane ln holds rows ln + 64 u of the right-hand
+    // sides, and at step l every lane updates its rows k < l with x_l = b_l / R_ll.
+    int kk_row[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = ln + 64 * u;
+        kk_row[u] = k < tk ? kept[k] : 0;
+    }
+    for (int g0 = wv * GC; g0 < tk; g0 += nwv * GC) {
+        double b[GC][NU];
+#pragma unroll
+        for (int c = 0; c < GC; ++c)
+#pragma unroll
+            for (int u = 0; u < NU; ++u) b[c][u] = (ln + 64 * u == g0 + c) ? 1.0 : 0.0;
+        const int top = min(g0 + GC, tk) - 1;
+        for (int l = top; l >= 0; --l) {
+            const int kl = kept[l];
+            const double rl = rdiag[l];
+            const int ul = l >> 6, lanel = l & 63;
+            double x[GC];
+#pragma unroll
+            for (int c = 0; c < GC; ++c) {
+                double bl = 0.0;
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+                    if (u == ul) bl = b[c][u];
+                const long long bb = __double_as_longlong(bl);
+                const int lo = __builtin_amdgcn_readlane((int)bb, lanel);
+                const int hi = __builtin_amdgcn_readlane((int)(bb >> 32), lanel);
+                x[c] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo) * rl;
+            }
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = ln + 64 * u;
+                if (k < l) {
+                    const double rkl = A[(size_t)kl * t + kk_row[u]];
+#pragma unroll
+                    for (int c = 0; c < GC; ++c) b[c][u] -= rkl * x[c];
+                }
+            }
+            if (ln < GC && g0 + ln < tk && l <= g0 + ln) {
+                double xv = 0.0;
+#pragma unroll
+                for (int c = 0; c < GC; ++c)
+                    if (c == ln) xv = x[c];
+                xb[(size_t)(g0 + ln) * ldb + kl] = xv;
+            }
         }
     }
     __syncthreads();
-    if (X) {
+    if constexpr (XL) {
         for (int idx = threadIdx.x; idx < t * tk; idx += blockDim.x) Xinv[(size_t)(idx / t) * ldx + idx % t] = X[idx];
         __syncthreads();
     }
@@ -249,7 +299,9 @@ __device__ void chol_drop(int t, const double* __restrict__ Gm, double tol, doub
 __global__ void __launch_bounds__(SD_NT) k_chol_drop(int t, const double* Gm, double tol, double* R, int* tk_out,
                                                      double* Xinv, int ldx, int lds) {
     extern __shared__ double dyn_lds[];
-    chol_drop(t, Gm, tol, lds ? dyn_lds : R, lds == 2 ? dyn_lds + (size_t)t * t : nullptr, tk_out, Xinv, ldx);
+    if (lds == 2) chol_drop<true>(t, Gm, tol, dyn_lds, dyn_lds + (size_t)t * t, tk_out, Xinv, ldx);
+    else if (lds == 1) chol_drop<false>(t, Gm, tol, dyn_lds, nullptr, tk_out, Xinv, ldx);
+    else chol_drop<false>(t, Gm, tol, gbl(R), nullptr, tk_out, Xinv, ldx);
 }
 
 // ------------------------------------------------------------------ symmetric eigensolver
