@@ -395,16 +395,30 @@ __device__ void tridiag(int m, double* A, double* d, double* e, double* tau, dou
     __syncthreads();
 }
 
-// Eigenvalues of the symmetric tridiagonal (d, e), e2[i] = e[i]^2, by bisection on Sturm
+// Eigenvalues of the symmetric tridiagonal (d, e), e2[i] = e[i]^2, by multisection on Sturm
 // counts (the number of negative pivots of the LDL^T factorisation of T - x I equals the
-// number of eigenvalues below x), one thread per eigenvalue: lam[k] = k-th smallest.
+// number of eigenvalues below x): lam[k] = k-th smallest.  A group of G lanes of one wave
+// (G a power of two, as many as the block has for m eigenvalues) brackets one eigenvalue: per
+// round each lane evaluates the count at one of G equally spaced interior points, and the first
+// point whose count exceeds k (a ballot over the group) gives the next bracket, G + 1 times
+// narrower.  Rounds end when the bracket's midpoint is no longer strictly inside (adjacent
+// doubles).  The bracket invariant count(lo) <= k < count(hi) holds whatever the rounding of
+// the counts: the new ends are two neighbouring points on either side of the first crossing.
 __device__ void tri_bisect(int m, const double* d, const double* e2, double glo, double ghi, double pivmin,
                            double* lam) {
-    for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    int G = 64;
+    while (G > 1 && G * m > (int)blockDim.x) G >>= 1;
+    const int lane = (int)(threadIdx.x & 63);
+    const int gi = lane & (G - 1), gbase = lane - gi;
+    const unsigned long long gmask = G == 64 ? ~0ull : (((1ull << G) - 1) << gbase);
+    const double inv = 1.0 / (double)(G + 1);
+    const int ngrp = (int)blockDim.x / G;
+    for (int k = (int)threadIdx.x / G; k < m; k += ngrp) {   // uniform within a group
         double lo = glo, hi = ghi;
-        for (int it = 0; it < 96; ++it) {
-            const double x = 0.5 * (lo + hi);
-            if (!(x > lo && x < hi)) break;   // adjacent doubles: converged
+        for (int round = 0; round < 96; ++round) {
+            const double mid = 0.5 * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;   // adjacent doubles: converged
+            const double x = lo + (hi - lo) * ((double)(gi + 1) * inv);
             int cnt = 0;
             double q = d[0] - x;
             for (int i = 0;;) {
@@ -413,10 +427,14 @@ __device__ void tri_bisect(int m, const double* d, const double* e2, double glo,
                 if (++i >= m) break;
                 q = (d[i] - x) - e2[i - 1] * fast_rcp(q);
             }
-            if (cnt > k) hi = x;
-            else lo = x;
+            const unsigned long long above = __ballot(cnt > k) & gmask;
+            const int first = above ? (int)__builtin_ctzll(above) - gbase : G;
+            const double xl = first == 0 ? lo : lo + (hi - lo) * ((double)first * inv);
+            const double xh = first == G ? hi : lo + (hi - lo) * ((double)(first + 1) * inv);
+            lo = xl;
+            hi = xh;
         }
-        lam[k] = 0.5 * (lo + hi);
+        if (gi == 0) lam[k] = 0.5 * (lo + hi);
     }
 }
 
@@ -554,25 +572,24 @@ __device__ void eig_range(int m, double* A, int lo, int hi, double* lam, double*
                       pv + k + j, nw, lo + k + j);
     }
     __syncthreads();
-    // back to the original basis: z <- H_0 H_1 ... H_{m-3} z
-    for (int k = threadIdx.x; k < nw; k += blockDim.x) {
-        double* z = zs + k;
-        for (int r = m - 3; r >= 0; --r) {
-            const double tr = tau[r];
-            if (tr == 0.0) continue;
-            const double* hv = LA + (size_t)(r + 1) * m + r;   // v_r[i] at hv[i * m]
-            const int len = m - r - 1;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int i = 0;
-            for (; i + 3 < len; i += 4) {
-                a0 += hv[(size_t)i * m] * z[(size_t)(r + 1 + i) * nw];
-                a1 += hv[(size_t)(i + 1) * m] * z[(size_t)(r + 2 + i) * nw];
-                a2 += hv[(size_t)(i + 2) * m] * z[(size_t)(r + 3 + i) * nw];
-                a3 += hv[(size_t)(i + 3) * m] * z[(size_t)(r + 4 + i) * nw];
+    // back to the original basis: z <- H_0 H_1 ... H_{m-3} z, one wave per vector (the lanes
+    // split each reflection's dot product and update; a block-scope fence orders a lane's
+    // update before another lane's read in the next reflection)
+    {
+        const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6), nwave = (int)(blockDim.x >> 6);
+        for (int k = wave; k < nw; k += nwave) {
+            double* z = zs + k;
+            for (int r = m - 3; r >= 0; --r) {
+                const double tr = tau[r];
+                if (tr == 0.0) continue;
+                const double* hv = LA + (size_t)(r + 1) * m + r;   // v_r[i] at hv[i * m]
+                const int len = m - r - 1;
+                double a = 0.0;
+                for (int i = lane; i < len; i += 64) a += hv[(size_t)i * m] * z[(size_t)(r + 1 + i) * nw];
+                const double dt = tr * wave_sum(a);
+                for (int i = lane; i < len; i += 64) z[(size_t)(r + 1 + i) * nw] -= dt * hv[(size_t)i * m];
+                __threadfence_block();
             }
-            for (; i < len; ++i) a0 += hv[(size_t)i * m] * z[(size_t)(r + 1 + i) * nw];
-            const double dt = tr * ((a0 + a1) + (a2 + a3));
-            for (i = 0; i < len; ++i) z[(size_t)(r + 1 + i) * nw] -= dt * hv[(size_t)i * m];
         }
     }
     __syncthreads();
