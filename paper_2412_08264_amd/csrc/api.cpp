@@ -23,7 +23,7 @@ constexpr int LBFGS_MMAX = 20;
 
 // Workspace layout (all offsets in bytes from the workspace base).
 struct Layout {
-    size_t state, mstate, slots, hdr, ctr, fold, part, vec, maps, taps, mhc, W0, W1, Ut, Ct, small, lb, total;
+    size_t state, mstate, slots, ctr, fold, part, vec, maps, taps, mhc, W0, W1, Ut, Ct, small, lb, total;
     size_t part_doubles;
     int n, p, s_max, v_cap, t_max, nf;
 };
@@ -48,7 +48,6 @@ Layout layout(const bl_problem* P, int s_max, int v_cap, bool solve_only = false
     L.state = o;    o += al(sizeof(SolveState));
     L.mstate = o;   o += al(sizeof(MinresState));
     L.slots = o;    o += al(sizeof(Slot));
-    L.hdr = o;      o += al(HDR_BYTES);
     L.ctr = o;      o += al(sizeof(int));
     L.fold = o;     o += al((size_t)3 * FOLD_BLOCKS * NV_RED * sizeof(double));
     L.part = o;     o += al(4 * pd * sizeof(double));   // records: residual / apply / update / apply of odd fused steps
@@ -81,7 +80,6 @@ struct WS {
     SolveState* st() const { return (SolveState*)(base + L.state); }
     MinresState* mst() const { return (MinresState*)(base + L.mstate); }
     Slot* slots() const { return (Slot*)(base + L.slots); }
-    int* hdr() const { return (int*)(base + L.hdr); }
     int* ctr() const { return (int*)(base + L.ctr); }
     double* part() const { return (double*)(base + L.part); }
     double* part_res() const { return part(); }
@@ -301,7 +299,7 @@ bl_status solve_in(bl_ctx* c, const bl_problem* P, const double* theta, const do
                    double* w, bl_recycle* rs, const bl_solve_opts* o, const WS& ws, bl_stats* out) {
     mark(c, 0);
     Batch B;
-    TRY(B.init(c, 1, ws.slots(), ws.hdr(), ws.ctr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
+    TRY(B.init(c, 1, ws.slots(), ws.ctr(), c->h_hdr, c->poll_ev[0], c->poll_ev[1]));
     SlotBuffers buf{};
     buf.r = ws.vec(0);
     buf.p0 = ws.vec(1);

@@ -252,8 +252,9 @@ __global__ void k_b_set_j0(Slot* __restrict__ slots, int idx, int j0) {
     if (threadIdx.x == 0) slots[idx].j0 = j0;
 }
 
-// Scalar headers of the listed slots into out[slot index * HDR_BYTES] (4-byte words), and the
-// step counter advanced past the chunk (adv steps; no other block of this kernel reads it).
+// Scalar headers of the listed slots into out[slot index * HDR_BYTES] (4-byte words; out is
+// pinned host memory that the host reads after the chunk's poll event), and the step counter
+// advanced past the chunk (adv steps; no other block of this kernel reads it).
 __global__ void __launch_bounds__(NT) k_b_headers(const Slot* __restrict__ slots, BatchMap M, int* __restrict__ out,
                                                   int* __restrict__ ctr, int adv) {
     constexpr int WPS = HDR_BYTES / 4;

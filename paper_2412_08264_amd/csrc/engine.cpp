@@ -295,13 +295,12 @@ Batch::~Batch() {
     for (hipGraphExec_t ex : retired) (void)hipGraphExecDestroy(ex);
 }
 
-bl_status Batch::init(bl_ctx* ctx, int capacity, Slot* slots, int* hdr_dev, int* ctr_dev, char* hdr_pinned,
+bl_status Batch::init(bl_ctx* ctx, int capacity, Slot* slots, int* ctr_dev, char* hdr_pinned,
                       hipEvent_t ev0, hipEvent_t ev1) {
     c = ctx;
     groups.clear();
     cap = capacity;
     d_slots = slots;
-    d_hdr = hdr_dev;
     d_ctr = ctr_dev;
     HIPCHK(hipMemsetAsync(d_ctr, 0, sizeof(int), c->stream));
     h_hdr = hdr_pinned;
@@ -596,9 +595,10 @@ bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector
     BatchMap all{};
     all.ns = (int)run_list.size();
     for (int k = 0; k < all.ns; ++k) all.slot[k] = run_list[k];
-    HIPCHK(launch_b_headers(d_slots, all, d_hdr, d_ctr, nsteps, ls));
-    HIPCHK(hipMemcpyAsync(h_hdr + (size_t)buf * cap * HDR_BYTES, d_hdr, (size_t)cap * HDR_BYTES, hipMemcpyDeviceToHost,
-                          ls));
+    // the header kernel writes the snapshot straight into pinned host memory (the poll event
+    // after it orders those writes before the host's read): no copy launch per chunk
+    HIPCHK(launch_b_headers(d_slots, all, reinterpret_cast<int*>(h_hdr + (size_t)buf * cap * HDR_BYTES), d_ctr,
+                            nsteps, ls));
     return BL_OK;
 }
 
@@ -861,14 +861,13 @@ struct bl_engine {
 namespace {
 
 struct EngineLayout {
-    size_t slots, hdr, ctr, states, arena, total;
+    size_t slots, ctr, states, arena, total;
 };
 
 EngineLayout engine_layout(int cap, size_t arena_bytes) {
     EngineLayout L{};
     size_t o = 0;
     L.slots = o;   o += al((size_t)cap * sizeof(Slot));
-    L.hdr = o;     o += al((size_t)cap * HDR_BYTES);
     L.ctr = o;     o += al(sizeof(int));
     L.states = o;  o += al((size_t)cap * sizeof(SolveState));
     L.arena = o;   o += al(arena_bytes);
@@ -920,7 +919,7 @@ bl_status bl_engine_create(bl_ctx* c, int cap, void* ws, size_t ws_bytes, bl_eng
         delete e;
         return BL_E_HIP;
     }
-    if (e->B.init(c, cap, (Slot*)(base + L0.slots), (int*)(base + L0.hdr), (int*)(base + L0.ctr), e->h_hdr, e->ev[0],
+    if (e->B.init(c, cap, (Slot*)(base + L0.slots), (int*)(base + L0.ctr), e->h_hdr, e->ev[0],
                   e->ev[1]) != BL_OK) {
         hipHostFree(e->h_taps);
         hipHostFree(e->h_hdr);

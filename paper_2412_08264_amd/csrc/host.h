@@ -138,9 +138,8 @@ public:
     bl_ctx* c = nullptr;
     int cap = 0;
     bl::Slot* d_slots = nullptr;   // device [cap]
-    int* d_hdr = nullptr;          // device [cap * HDR_BYTES / 4]: gathered headers
     int* d_ctr = nullptr;          // device step counter (equals `step` at chunk boundaries)
-    char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES]
+    char* h_hdr = nullptr;         // pinned [2][cap * HDR_BYTES], written by the header kernel
     hipEvent_t poll_ev[2] = {};
 
     struct Group {                 // operator class, tile height, recycling: stencil template, precision
@@ -177,7 +176,7 @@ public:
     Batch(const Batch&) = delete;
     Batch& operator=(const Batch&) = delete;
     ~Batch();
-    bl_status init(bl_ctx* ctx, int capacity, bl::Slot* slots, int* hdr_dev, int* ctr_dev, char* hdr_pinned,
+    bl_status init(bl_ctx* ctx, int capacity, bl::Slot* slots, int* ctr_dev, char* hdr_pinned,
                    hipEvent_t ev0, hipEvent_t ev1);
     // Validate and start solve `sp` in free slot idx with device scratch B; taps_stage is
     // pinned host memory of TAPS_MAX doubles that stays untouched until the slot retires.
