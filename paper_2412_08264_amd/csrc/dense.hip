@@ -601,8 +601,11 @@ __device__ void eig_range(int m, double* A, int lo, int hi, double* lam, double*
 }
 
 // Cholesky M = L L^T in place (lower, column-major ld t).  Returns false if not SPD.
-__device__ bool chol_inplace(int t, double* L) {
+// (Instantiated for L in LDS or in global memory, never a pointer that may be either.)
+template <typename PL>
+__device__ __forceinline__ bool chol_inplace(int t, PL L) {
     __shared__ int s_ok;
+    const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63), nwv = (int)(blockDim.x >> 6);
     if (threadIdx.x == 0) s_ok = 1;
     __syncthreads();
     for (int j = 0; j < t; ++j) {
@@ -616,12 +619,10 @@ __device__ bool chol_inplace(int t, double* L) {
         const double dj = L[(size_t)j * t + j];
         for (int i = j + 1 + threadIdx.x; i < t; i += blockDim.x) L[(size_t)j * t + i] /= dj;
         __syncthreads();
-        // trailing update: L[i][k] -= L[i][j] L[k][j], j < k <= i
-        const int m = t - j - 1;
-        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-            const int kk = idx / m, ii = idx - kk * m;
-            const int k = j + 1 + kk, i = j + 1 + ii;
-            if (i >= k) L[(size_t)k * t + i] -= L[(size_t)j * t + i] * L[(size_t)j * t + k];
+        // trailing update: L[i][k] -= L[i][j] L[k][j], j < k <= i; one column k per wave
+        for (int k = j + 1 + wv; k < t; k += nwv) {
+            const double lkj = L[(size_t)j * t + k];
+            for (int i = k + ln; i < t; i += 64) L[(size_t)k * t + i] -= L[(size_t)j * t + i] * lkj;
         }
         __syncthreads();
     }
@@ -754,14 +755,13 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
     __syncthreads();
     {
         const bool in_lds = (int)T2 <= ldsd;
-        double* LL = in_lds ? dyn_lds : L;
         if (in_lds) {
-            for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) LL[idx] = L[idx];
+            for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) dyn_lds[idx] = L[idx];
             __syncthreads();
         }
-        const bool spd = chol_inplace(t, LL);
+        const bool spd = in_lds ? chol_inplace(t, dyn_lds) : chol_inplace(t, gbl(L));
         if (in_lds) {
-            for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) L[idx] = LL[idx];
+            for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) L[idx] = dyn_lds[idx];
             __syncthreads();
         }
         if (!spd) {
@@ -1024,12 +1024,15 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
             }
         }
     }
-    for (int c = threadIdx.x; c < s_eff; c += blockDim.x) {   // unit columns of X~
-        double* x = Xs + (size_t)c * t;
-        double nrm = 0.0;
-        for (int i = 0; i < t; ++i) nrm += x[i] * x[i];
-        nrm = sqrt(nrm);
-        for (int i = 0; i < t; ++i) x[i] /= nrm;
+    {   // unit columns of X~, one wave per column
+        const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6), nwave = (int)(blockDim.x >> 6);
+        for (int c = wave; c < s_eff; c += nwave) {
+            double* x = Xs + (size_t)c * t;
+            double part = 0.0;
+            for (int i = lane; i < t; i += 64) part += x[i] * x[i];
+            const double nrm = sqrt(wave_sum(part));
+            for (int i = lane; i < t; i += 64) x[i] /= nrm;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1068,7 +1071,7 @@ __global__ void __launch_bounds__(SD_NT) k_ritz_select(int t, int s, int kind, i
     }
     __syncthreads();
     if (kind == 1) {
-        if (!chol_inplace(t, L)) {
+        if (!chol_inplace(t, gbl(L))) {
             if (threadIdx.x == 0) {
                 info[0] = 0;
                 info[1] = 0;
