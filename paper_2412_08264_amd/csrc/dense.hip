@@ -629,89 +629,118 @@ __device__ __forceinline__ bool chol_inplace(int t, PL L) {
     return true;
 }
 
-// X[:, c] <- M^{-1} X[:, c], c < ncols, with M = L L^T (L lower, column-major ld t); column c
-// starts at X + c * ldc with element stride incx.  L is staged in LDS when it fits; the
-// columns are solved in groups held in LDS (element i of group column c at xs[i * gn + c]),
-// one column per thread.
+// One wave's group of GC columns of X through L y = b, then L^T x = y (L lower, element (i, j)
+// at LL[j * ld + i]).  Lane l holds rows l + 64 u of the group in registers; at step j every
+// lane updates its rows with x_j, read from the lane that owns row j (readlane), scaled by the
+// reciprocal diagonal.  No barrier: the columns and their registers are the wave's own.
+template <int GC, typename PL>
+__device__ __forceinline__ void solve_group(int t, PL LL, int ld, const double* rdg, double* X, int c0, int gn,
+                                            size_t ldc, size_t incx) {
+    constexpr int NU = EIG_MAX / 64;
+    const int lane = (int)(threadIdx.x & 63);
+    const int nu = (t + 63) >> 6;
+    double x[GC][NU];
+#pragma unroll
+    for (int cc = 0; cc < GC; ++cc)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int r = lane + 64 * u;
+            x[cc][u] = (cc < gn && r < t) ? X[(size_t)(c0 + cc) * ldc + (size_t)r * incx] : 0.0;
+        }
+    auto bcast = [&](int row, double (&out)[GC]) {
+        const int ur = row >> 6, lr = row & 63;
+#pragma unroll
+        for (int cc = 0; cc < GC; ++cc) {
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+                if (u == ur) v = x[cc][u];
+            const long long b = __double_as_longlong(v);
+            const int lo = __builtin_amdgcn_readlane((int)b, lr);
+            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lr);
+            out[cc] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo) * rdg[row];
+        }
+    };
+    auto settle = [&](int row, const double (&val)[GC]) {   // row takes its solved value
+        const int ur = row >> 6, lr = row & 63;
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (u == ur && lane == lr) {
+#pragma unroll
+                for (int cc = 0; cc < GC; ++cc) x[cc][u] = val[cc];
+            }
+    };
+    for (int jj = 0; jj < t; ++jj) {   // L y = b, column jj of L
+        double y[GC];
+        bcast(jj, y);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int r = lane + 64 * u;
+            if (u < nu && r > jj && r < t) {
+                const double l = LL[(size_t)jj * ld + r];
+#pragma unroll
+                for (int cc = 0; cc < GC; ++cc) x[cc][u] -= l * y[cc];
+            }
+        }
+        settle(jj, y);
+    }
+    for (int ii = t - 1; ii >= 0; --ii) {   // L^T x = y, row ii of L
+        double z[GC];
+        bcast(ii, z);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int r = lane + 64 * u;
+            if (u < nu && r < ii) {
+                const double l = LL[(size_t)r * ld + ii];
+#pragma unroll
+                for (int cc = 0; cc < GC; ++cc) x[cc][u] -= l * z[cc];
+            }
+        }
+        settle(ii, z);
+    }
+#pragma unroll
+    for (int cc = 0; cc < GC; ++cc)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int r = lane + 64 * u;
+            if (cc < gn && r < t) X[(size_t)(c0 + cc) * ldc + (size_t)r * incx] = x[cc][u];
+        }
+}
+
+template <typename PL>
+__device__ __forceinline__ void solve_cols_waves(int t, PL LL, int ld, const double* rdg, double* X, int ncols,
+                                                 size_t ldc, size_t incx) {
+    const int wave = (int)(threadIdx.x >> 6), nwave = (int)(blockDim.x >> 6);
+    const int want = (ncols + nwave - 1) / nwave;   // columns per wave in one pass, at most 8
+    const int per = want <= 1 ? 1 : (want <= 2 ? 2 : (want <= 4 ? 4 : 8));
+    for (int c0 = wave * per; c0 < ncols; c0 += nwave * per) {
+        const int gn = ncols - c0 < per ? ncols - c0 : per;
+        if (per == 1) solve_group<1>(t, LL, ld, rdg, X, c0, gn, ldc, incx);
+        else if (per == 2) solve_group<2>(t, LL, ld, rdg, X, c0, gn, ldc, incx);
+        else if (per == 4) solve_group<4>(t, LL, ld, rdg, X, c0, gn, ldc, incx);
+        else solve_group<8>(t, LL, ld, rdg, X, c0, gn, ldc, incx);
+    }
+}
+
+// X[:, c] <- M^{-1} X[:, c], c < ncols, with M = L L^T (L lower, column-major ld t, t <= 256);
+// column c starts at X + c * ldc with element stride incx.  L is staged in LDS when it fits,
+// with an odd leading dimension so that the backward sweep's row reads (stride ld) spread over
+// the banks.  The columns are dealt to the waves in groups of 1, 2, 4 or 8 (solve_group).
 __device__ void solve_cols(int t, const double* L, double* X, int ncols, size_t ldc, size_t incx, int ldsd) {
     extern __shared__ double dyn_lds[];
-    const bool l_in = t * t + t <= ldsd;
-    const double* LL = L;
-    if (l_in) {
-        for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) dyn_lds[idx] = L[idx];
-        LL = dyn_lds;
-    }
-    double* xs = l_in ? dyn_lds + (size_t)t * t : dyn_lds;
-    const int avail = ldsd - (l_in ? t * t : 0);
-    int group = avail / t;
-    if (group > (int)blockDim.x) group = blockDim.x;
-    for (int c0 = 0; c0 < ncols; c0 += group) {
-        const int gn = (ncols - c0) < group ? (ncols - c0) : group;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < gn * t; idx += blockDim.x) {
-            const int c = idx / t, i = idx - c * t;
-            xs[i * gn + c] = X[(size_t)(c0 + c) * ldc + (size_t)i * incx];
+    __shared__ double rdg[EIG_MAX];   // reciprocal diagonal of L
+    const int ldl = t | 1;
+    const bool l_in = ldl * t <= ldsd;
+    __syncthreads();   // earlier users of the dynamic LDS are done
+    if (l_in)
+        for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+            const int jc = idx / t, ir = idx - jc * t;
+            dyn_lds[(size_t)jc * ldl + ir] = L[idx];
         }
-        __syncthreads();
-        const int c = threadIdx.x;
-        if (gn <= 8) {
-            // few columns: one thread per column would run t^2 dependent steps alone, so wave 0
-            // sweeps instead: at step j every lane updates its rows of the remaining part with
-            // x_j / L_jj.  One wave needs no barrier between steps: its LDS accesses complete in
-            // program order (the wave barrier only keeps the compiler from moving them).
-            if (threadIdx.x < 64) {
-                const int lane = threadIdx.x;
-                for (int j = 0; j < t; ++j) {   // L y = x, column by column of L
-                    const double dj = LL[(size_t)j * t + j];
-                    for (int cc = 0; cc < gn; ++cc) {
-                        const double xj = xs[j * gn + cc] / dj;
-                        for (int i = j + 1 + lane; i < t; i += 64) xs[i * gn + cc] -= LL[(size_t)j * t + i] * xj;
-                        if (lane == 0) xs[j * gn + cc] = xj;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                }
-                for (int i = t - 1; i >= 0; --i) {   // L^T x = y, column by column of L^T
-                    const double di = LL[(size_t)i * t + i];
-                    for (int cc = 0; cc < gn; ++cc) {
-                        const double xi = xs[i * gn + cc] / di;
-                        for (int k = lane; k < i; k += 64) xs[k * gn + cc] -= LL[(size_t)k * t + i] * xi;
-                        if (lane == 0) xs[i * gn + cc] = xi;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
-        } else if (c < gn) {
-            for (int i = 0; i < t; ++i) {   // L y = x
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int k = 0;
-                for (; k + 3 < i; k += 4) {
-                    a0 += LL[(size_t)k * t + i] * xs[k * gn + c];
-                    a1 += LL[(size_t)(k + 1) * t + i] * xs[(k + 1) * gn + c];
-                    a2 += LL[(size_t)(k + 2) * t + i] * xs[(k + 2) * gn + c];
-                    a3 += LL[(size_t)(k + 3) * t + i] * xs[(k + 3) * gn + c];
-                }
-                for (; k < i; ++k) a0 += LL[(size_t)k * t + i] * xs[k * gn + c];
-                xs[i * gn + c] = (xs[i * gn + c] - ((a0 + a1) + (a2 + a3))) / LL[(size_t)i * t + i];
-            }
-            for (int i = t - 1; i >= 0; --i) {   // L^T x = y
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int k = i + 1;
-                for (; k + 3 < t; k += 4) {
-                    a0 += LL[(size_t)i * t + k] * xs[k * gn + c];
-                    a1 += LL[(size_t)i * t + k + 1] * xs[(k + 1) * gn + c];
-                    a2 += LL[(size_t)i * t + k + 2] * xs[(k + 2) * gn + c];
-                    a3 += LL[(size_t)i * t + k + 3] * xs[(k + 3) * gn + c];
-                }
-                for (; k < t; ++k) a0 += LL[(size_t)i * t + k] * xs[k * gn + c];
-                xs[i * gn + c] = (xs[i * gn + c] - ((a0 + a1) + (a2 + a3))) / LL[(size_t)i * t + i];
-            }
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < gn * t; idx += blockDim.x) {
-            const int cc = idx / t, i = idx - cc * t;
-            X[(size_t)(c0 + cc) * ldc + (size_t)i * incx] = xs[i * gn + cc];
-        }
-    }
+    for (int i = threadIdx.x; i < t; i += blockDim.x) rdg[i] = 1.0 / L[(size_t)i * t + i];
+    __syncthreads();
+    if (l_in) solve_cols_waves(t, (const double*)dyn_lds, ldl, rdg, X, ncols, ldc, incx);
+    else solve_cols_waves(t, gbl(L), t, rdg, X, ncols, ldc, incx);
     __syncthreads();
 }
 
