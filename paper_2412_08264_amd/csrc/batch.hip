@@ -289,12 +289,12 @@ hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, co
 }
 
 hipError_t launch_f_step(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
-                         hipStream_t stream) {
+                         const Slot* one, hipStream_t stream) {
     if (M.ns == 0) return hipSuccess;
     switch (rows) {
-        case QTY * 1: return launch_f_step_q<1>(base, rec, slots, M, sr, stream);
-        case QTY * 2: return launch_f_step_q<2>(base, rec, slots, M, sr, stream);
-        case QTY * 4: return launch_f_step_q<4>(base, rec, slots, M, sr, stream);
+        case QTY * 1: return launch_f_step_q<1>(base, rec, slots, M, sr, one, stream);
+        case QTY * 2: return launch_f_step_q<2>(base, rec, slots, M, sr, one, stream);
+        case QTY * 4: return launch_f_step_q<4>(base, rec, slots, M, sr, one, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -7,7 +7,8 @@ namespace bl {
 template hipError_t launch_b_residual_q<2>(const Stencil&, bool, const Slot*, const BatchMap&, int, hipStream_t);
 template hipError_t launch_b_apply_q<2>(const Stencil&, bool, bool, const Slot*, const BatchMap&, StepRef,
                                              hipStream_t);
-template hipError_t launch_f_step_q<2>(const Stencil&, bool, const Slot*, const BatchMap&, StepRef, hipStream_t);
+template hipError_t launch_f_step_q<2>(const Stencil&, bool, const Slot*, const BatchMap&, StepRef, const Slot*,
+                                       hipStream_t);
 template hipError_t launch_hvp_q<2>(const Stencil&, bool, const double*, const double*, double*, int,
                                           hipStream_t);
 

@@ -304,9 +304,11 @@ __host__ __device__ constexpr int f_prefetch() {
     return Q == 1 ? (CLS == TC_TV ? 16 : 8) : 0;
 }
 
-template <int R, int CLS, int Q, bool REC>
+// ONE: a launch of a single solve, whose descriptor comes by value with the kernel arguments
+// (loaded with them, instead of from the descriptor array after the block's slot is known).
+template <int R, int CLS, int Q, bool REC, bool ONE>
 __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restrict__ slots, BatchMap M,
-                                               StepRef sr) {
+                                               StepRef sr, Slot one) {
     using L = QLayout<double, R, CLS, Q>;
     using G = QGeo<R, CLS, Q>;
     constexpr int QR = Q;
@@ -318,8 +320,8 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
     __shared__ double tot[NT];
-    const int2 m = map_block(M, blockIdx.x);
-    const Slot& sl = slots[m.x];
+    const int2 m = ONE ? make_int2(M.slot[0], (int)blockIdx.x) : map_block(M, blockIdx.x);
+    const Slot& sl = ONE ? one : slots[m.x];
     if (m.y >= sl.ntiles) return;
     SolveState* st = sl.st;
     const int mark = stop_mark(st);
@@ -731,18 +733,20 @@ hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot
 
 template <int Q>
 hipError_t launch_f_step_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
-                           hipStream_t stream) {
+                           const Slot* one, hipStream_t stream) {
     q_dispatch(base.R, tile_class(base.reg, base.fs), [&](auto rc, auto cc) {
         constexpr int RR = decltype(rc)::value, CC = decltype(cc)::value;
         // 8-row tiles reduce their record through two buffers of 8 x NT doubles in the tile's LDS
         constexpr size_t tile = QLayout<double, RR, CC, Q>::bytes, red = Q == 1 ? 2 * 8 * NT * sizeof(double) : 0;
         const size_t lds = tile > red ? tile : red;
+        const bool single = one && M.ns == 1;
+        const Slot arg = single ? *one : Slot{};
         auto go = [&](auto kern) {
             allow_lds_b(kern, lds);
-            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, sr);
+            hipLaunchKernelGGL(kern, map_grid(M), dim3(NT), lds, stream, base, slots, M, sr, arg);
         };
-        if (rec) go(k_f_step<RR, CC, Q, true>);
-        else go(k_f_step<RR, CC, Q, false>);
+        if (rec) single ? go(k_f_step<RR, CC, Q, true, true>) : go(k_f_step<RR, CC, Q, true, false>);
+        else single ? go(k_f_step<RR, CC, Q, false, true>) : go(k_f_step<RR, CC, Q, false, false>);
     });
     return hipGetLastError();
 }

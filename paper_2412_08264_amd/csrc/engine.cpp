@@ -578,7 +578,12 @@ bl_status Batch::launch_chunk(int nsteps, int buf, const std::vector<std::vector
         }
         for (const Group& grp : groups) {
             if (!grp.tmap.ns) continue;
-            if (grp.fused()) HIPCHK(launch_f_step(grp.base, grp.rows, grp.rec, d_slots, grp.tmap, sr, ls));
+            if (grp.fused()) {
+                // a group of one solve passes its descriptor by value (a fused slot's descriptor
+                // does not change between admission and retirement, so a captured graph stays valid)
+                const Slot* one = grp.tmap.ns == 1 ? &S[grp.tmap.slot[0]].d : nullptr;
+                HIPCHK(launch_f_step(grp.base, grp.rows, grp.rec, d_slots, grp.tmap, sr, one, ls));
+            }
             else HIPCHK(launch_b_apply(grp.base, grp.rows, grp.rec, grp.fp32, d_slots, grp.tmap, sr, ls));
         }
         if (ktime) HIPCHK(hipEventRecord(c->kev[ev + 1], ls));

@@ -55,12 +55,14 @@ hipError_t launch_b_residual(const Stencil& base, int rows, bool rec, const Slot
                              int periodic, hipStream_t stream);
 hipError_t launch_b_apply(const Stencil& base, int rows, bool rec, bool fp32, const Slot* slots, const BatchMap& M,
                           StepRef sr, hipStream_t stream);
-// Fused FP64 step of the recycled CG (one launch per iteration), on tiles of `rows` rows.
+// Fused FP64 step of the recycled CG (one launch per iteration), on tiles of `rows` rows.  `one`
+// (host memory, may be null): the descriptor of the launch's only slot, passed by value with the
+// kernel arguments when the map holds one slot; it must equal slots[M.slot[0]].
 hipError_t launch_f_step(const Stencil& base, int rows, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
-                         hipStream_t stream);
+                         const Slot* one, hipStream_t stream);
 template <int Q>
 hipError_t launch_f_step_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, StepRef sr,
-                           hipStream_t stream);
+                           const Slot* one, hipStream_t stream);
 template <int Q>
 hipError_t launch_b_residual_q(const Stencil& base, bool rec, const Slot* slots, const BatchMap& M, int periodic,
                                hipStream_t stream);
@@ -73,7 +75,7 @@ hipError_t launch_b_apply_q(const Stencil& base, bool rec, bool fp32, const Slot
     extern template hipError_t launch_b_apply_q<Q>(const Stencil&, bool, bool, const Slot*, const BatchMap&,      \
                                                    StepRef, hipStream_t);                                         \
     extern template hipError_t launch_f_step_q<Q>(const Stencil&, bool, const Slot*, const BatchMap&, StepRef,    \
-                                                  hipStream_t);
+                                                  const Slot*, hipStream_t);
 #define BL_HVP_EXTERN(Q)                                                                                   \
     extern template hipError_t launch_hvp_q<Q>(const Stencil&, bool, const double*, const double*, double*, int, \
                                                hipStream_t);
