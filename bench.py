@@ -79,12 +79,13 @@ def step_bytes_per_pixel(reg: str, prec: str, s: int, nf: int, z_cols: float = 0
     return b
 
 
-def step_kernel(prec: str, radius: int, reg: str, rows: int, rec: bool = True) -> str:
-    """Name of the timed launch's kernel (the template arguments as rocprofv3 prints them)."""
+def step_kernel(prec: str, radius: int, reg: str, rows: int, rec: bool = True, single: bool = True) -> str:
+    """Name of the timed launch's kernel (the template arguments as rocprofv3 prints them); `single`:
+    the FP64 step of a launch that holds one solve (its descriptor passed by value)."""
     cls = 0 if reg == "tv" else 1
     if prec == "mixed":
         return f"k_b_apply<float, {radius}, {cls}, {rows // 8}, {'true' if rec else 'false'}>"
-    return f"k_f_step<{radius}, {cls}, {rows // 8}, {'true' if rec else 'false'}>"
+    return f"k_f_step<{radius}, {cls}, {rows // 8}, {'true' if rec else 'false'}, {'true' if single else 'false'}>"
 
 
 def source_hash() -> str:
