@@ -343,6 +343,16 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
     const Own<Q> o = own_pixels<Q>(h, w, r0, c0);
     double ri[QR], qi[QR], pi[QR], wi[QR], cpre[PFA][QR], hpre[PFA][QR], hr[NST], hq[NST], hp[NST];
     TvX<Q> X{};
+    // the columns of C and H C do not depend on the step index: issued first, they need not wait
+    // for the step counter (H C enters only through alpha e, zero at j = 0)
+#pragma unroll
+    for (int c = 0; c < PFA; ++c)
+#pragma unroll
+        for (int k = 0; k < QR; ++k) {
+            const bool ld = PF > 0 && o.in[k] && c < s;
+            cpre[c][k] = ld ? gC[(size_t)c * n + o.g[k]] : 0.0;
+            hpre[c][k] = ld ? gHC[(size_t)c * n + o.g[k]] : 0.0;
+        }
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
         ri[k] = o.in[k] ? rin[o.g[k]] : 0.0;
@@ -350,14 +360,6 @@ __global__ void __launch_bounds__(NT) k_f_step(Stencil base, const Slot* __restr
         pi[k] = (o.in[k] && !first) ? p0b[o.g[k]] : 0.0;
         wi[k] = (o.in[k] && !first) ? gW[o.g[k]] : 0.0;
     }
-#pragma unroll
-    for (int c = 0; c < PFA; ++c)
-#pragma unroll
-        for (int k = 0; k < QR; ++k) {
-            const bool ld = PF > 0 && o.in[k] && c < s;
-            cpre[c][k] = ld ? gC[(size_t)c * n + o.g[k]] : 0.0;
-            hpre[c][k] = (ld && !first) ? gHC[(size_t)c * n + o.g[k]] : 0.0;
-        }
     if constexpr (EARLY) {
 #pragma unroll
         for (int u = 0; u < NST; ++u) {
