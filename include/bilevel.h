@@ -267,8 +267,8 @@ bl_status bl_lower_grad(bl_ctx* ctx, const bl_problem* P, const double* theta_ho
                         const double* x, double* grad, double* phi_host, void* ws, size_t ws_bytes);
 
 /* Graph replay of the Krylov iterations, 1 (default) / 0.  The iterations of a solve run in
- * chunks of 8 (apply and update launches, scheduled residual replacements, the gather of the
- * stop flags).  A chunk whose launch sequence has occurred before since the set of running
+ * chunks of 16 for a lone solve and 8 for a batch (the step launches, scheduled residual
+ * replacements, the header snapshot written into pinned host memory).  A chunk whose launch sequence has occurred before since the set of running
  * solves last changed is captured once (on a private stream of the context) and replayed with
  * hipGraphLaunch on the context's stream; the kernels take their iteration index from a device
  * counter, so the replays need no new arguments.  Results are bitwise those of direct launches.

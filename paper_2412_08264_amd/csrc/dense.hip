@@ -1,6 +1,6 @@
 // Dense kernels of the recycle-space refresh: tall-skinny Gram products, tall x small
 // products, and single-workgroup small dense algebra (Cholesky with column drop, a
-// symmetric eigensolver (Householder tridiagonalisation, bisection, inverse iteration),
+// symmetric eigensolver (Householder tridiagonalisation, multisection, inverse iteration),
 // projected GSVD and Ritz-GSV selection).
 #include <algorithm>
 
@@ -515,9 +515,10 @@ __device__ void tri_invit(int m, const double* d, const double* e, double lam, d
 // Symmetric eigenproblem of the m x m matrix A (row-major, destroyed): all eigenvalues in
 // ascending order to lam, the eigenvectors of eigenvalues lo .. hi-1 to the columns of Z
 // (Z[(k - lo) * m + i] = component i).  Householder tridiagonalisation (in LDS when m^2
-// doubles fit), eigenvalues by parallel bisection, vectors by inverse iteration (eigenvalues
-// closer than 1e-7 of the spectrum's width are treated as a cluster, their vectors computed
-// in sequence and orthogonalised), and the reflectors applied to the few vectors wanted.
+// doubles fit), eigenvalues by multisection (tri_bisect), vectors by inverse iteration
+// (eigenvalues closer than 1e-7 of the spectrum's width are treated as a cluster, their vectors
+// computed in sequence and orthogonalised), and the reflectors applied to the few vectors
+// wanted, one wave per vector.
 // scr: (hi - lo) * 4 m + m doubles of scratch.
 __device__ void eig_range(int m, double* A, int lo, int hi, double* lam, double* Z, double* scr, int ldsd) {
     __shared__ double d[EIG_MAX], e[EIG_MAX], e2[EIG_MAX], tau[EIG_MAX], vv[EIG_MAX], pw[EIG_MAX],
