@@ -35,7 +35,7 @@ from __future__ import annotations
 import numpy as np
 
 RANK_TOL = 1e-8       # relative column-norm drop threshold of the orthonormalisation
-G_RANK_TOL = 1e-8     # singular values of G below this times the largest count as zero
+G_RANK_TOL = 1e-6     # singular values of G below this times the largest count as zero
 
 
 def orthonormalize(W: np.ndarray, rank_tol: float = RANK_TOL):

@@ -914,7 +914,9 @@ __global__ void __launch_bounds__(SD_NT) k_gsvd_select(int t, int p, int s, int 
             const double mx2 = fmax(lamg[p - 1], 0.0);
             int r = 0;
             for (int i = 0; i < p; ++i)
-                if (lamg[i] > 1e-16 * mx2) ++r;   // singular values of G above 1e-8 of the largest
+                // singular values of G above 1e-6 of the largest: G G^T's rounding (about p eps
+                // of its largest eigenvalue) stays far below the cutoff squared
+                if (lamg[i] > 1e-12 * mx2) ++r;
             s_rank = r;
         }
         __syncthreads();

@@ -450,6 +450,44 @@ def test_refresh_parity_filters(B):
         assert recycle.principal_angles(U, ref["U"]).max() <= 1e-8
 
 
+def test_refresh_fill_many_params(B):
+    """RGen-L(R) with more than 64 parameters, fewer parameters than stored vectors (p < t) and
+    rank(J W) < s, so that the GSVD fills the slots beyond rank(J W) from null(J W): two
+    identical 7x7 filters (p = 100, rank(J W) at most 50) and s = 60.  mu against the oracle,
+    the same rank on both sides, and the selected subspace (1e-6 rad: the fill's Ritz vectors
+    sit in a denser part of the spectrum than the RGen vectors)."""
+    wl = synth.custom("f2", 40, "filters", 60, width=44, n_filters=2, rect_min=2, rect_max=6, seed=73)
+    inst = synth.instance(wl)
+    prob = problem.make_problem(wl, inst["xstar"], inst["e"])
+    th = inst["theta0"].copy()
+    th[50:100] = th[0:50]   # filter 2 = filter 1 (weight and taps): rows of J W repeat
+    xh = inst["xstar"].ravel() + 0.02 * synth.unit_noise(prob.n, 74)
+    hvp = lambda v: prob.hvp(xh, th, v)
+    jac = lambda v: prob.jac_apply(xh, th, v)
+    # a well-conditioned stored basis of 120 > p vectors (unit Gaussian columns), so that both
+    # sides keep all of them (t = 120) and the GSVD takes its p < t route
+    m = 120
+    V = synth.unit_noise((prob.n, m), 76)
+    V /= np.linalg.norm(V, axis=0)
+    ref = recycle.refresh(hvp, jac, None, V, s=60)
+    assert ref["t"] == m
+    rk = ref["rank_G"]
+    assert 0 < rk <= 50, rk
+    with B.Session(B.problem_from(wl, prec="fp64"), s_max=60, v_cap=120) as S:
+        S.V[:m] = dev(V.T)
+        S.rs.v_cur = m
+        st = S.refresh(th, dev(xh), s=60)
+        assert st.t == m, st.t
+        assert st.iters == rk, (st.iters, rk)   # rank of J W
+        assert S.rs.s_cur == 60
+        mu = host(S.mu[:60])
+        assert np.abs(mu - ref["mu"]).max() <= 1e-10 * ref["mu"][0]
+        assert np.all(mu[rk:] == 0.0)
+        U = host(S.U[:60]).T
+        assert np.isfinite(U).all()
+        assert recycle.principal_angles(U, ref["U"]).max() <= 1e-6
+
+
 @pytest.fixture(scope="module")
 def tv32_sequence():
     """The 32x32 TV recipe's 20-step frozen trajectory and the oracle's recycled solve sequence
